@@ -1,0 +1,580 @@
+"""FP64 CPU oracle for the continuous relaxations of a dense CRF.
+
+TEST INFRASTRUCTURE. Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU
+baseline leg of ``bench.py`` may import this module. It shares no code with the
+GPU library (``paper_1608_06192_amd``); the only inputs both sides share are
+the seeded arrays of ``paper_1608_06192_amd.synth``, which hold no arithmetic
+of the method.
+
+Everything here follows Desmaison, Bunel, Kohli, Torr and Kumar, "Efficient
+Continuous Relaxations for Dense CRF" (ECCV 2016), in FP64, step by step in
+the paper's order and notation, with no blocking or fusion:
+
+* the model: energy (Sec. 3, eq. labelling-energy), Gaussian pairwise
+  potentials (eq. pairwise, eq. gaussiankernel, App. G), the QP matrices
+  Psi = mu (x) (sum_m w_m K_m - I) and d (eq. pairwise-matrix, eq. RL-diagonal);
+* the pairwise filter in two forms: the exact O(N^2) Gaussian sum (eq. fb) and
+  a reference permutohedral lattice (``dcrf_oracle.c``);
+* Frank-Wolfe on the convex QP (Sec. 4, Alg. fw, eq. LRQP-grad, eq. LRQP-lp,
+  App. B eq. alpha-opt and the filter-reuse recurrence);
+* the generic DC relaxation by CCCP (Sec. 5.1, Alg. cccp, eq. cccp-qp);
+* the LP relaxation (Sec. 6, eq. potts-lp, eq. simple_S, eq. grad_lp), its
+  subgradient by brute force and by divide and conquer (App. E), projected
+  subgradient descent (Alg. lp_subgrad) with a simplex projection;
+* the reverse-mode derivative of unrolled Frank-Wolfe.
+
+Readings of the paper where it is silent or ambiguous are listed in the design doc
+of the repository; the ones that change numbers are repeated next to the code.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path):
+            raise RuntimeError("oracle library not built: run "
+                               "__graft_entry__.build() first")
+        lib = ctypes.CDLL(path)
+        P = ctypes.c_void_p
+        I = ctypes.c_int
+        lib.or_gauss_exact.argtypes = [I, P, I, P, I, I, P, P, I]
+        lib.or_gauss_exact.restype = None
+        lib.or_elevate.argtypes = [I, P, P]
+        lib.or_simplex.argtypes = [I, P, P, P]
+        lib.or_lattice_build.argtypes = [I, I, P]
+        lib.or_lattice_build.restype = P
+        lib.or_lattice_free.argtypes = [P]
+        lib.or_lattice_nv.argtypes = [P]
+        lib.or_lattice_nv.restype = I
+        lib.or_lattice_points.argtypes = [P, P, P]
+        lib.or_lattice_keys.argtypes = [P, P]
+        lib.or_lattice_neighbours.argtypes = [P, P]
+        lib.or_lattice_splat.argtypes = [P, I, P, P]
+        lib.or_lattice_blur.argtypes = [P, I, P, I]
+        lib.or_lattice_slice.argtypes = [P, I, P, P]
+        lib.or_lattice_filter.argtypes = [P, I, P, P, I]
+        lib.or_lattice_gamma.argtypes = [I]
+        lib.or_lattice_gamma.restype = ctypes.c_double
+        _LIB = lib
+    return _LIB
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# The model (Sec. 3; App. G)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Kernel:
+    """One Gaussian kernel of the pixel compatibility (eq. pairwise, App. G).
+
+    Features are positions divided by ``theta_pos`` and, when ``use_rgb``,
+    colours divided by ``theta_rgb``: k(a, b) = exp(-|f_a - f_b|^2 / 2) is then
+    exp(-|p_a - p_b|^2 / (2 theta_pos^2) - |I_a - I_b|^2 / (2 theta_rgb^2)),
+    App. G's form with sigma = 2 theta^2.
+    """
+    use_rgb: int
+    theta_pos: float
+    theta_rgb: float
+    weight: float
+
+
+def features(H: int, W: int, rgb: np.ndarray, k: Kernel) -> np.ndarray:
+    """Feature vectors (x, y[, R, G, B]) of the N = H*W pixels, x = column."""
+    a = np.arange(H * W)
+    cols = (a % W).astype(np.float64)
+    rows = (a // W).astype(np.float64)
+    f = [cols / k.theta_pos, rows / k.theta_pos]
+    if k.use_rgb:
+        c = np.asarray(rgb, dtype=np.float64).reshape(-1, 3)
+        f += [c[:, 0] / k.theta_rgb, c[:, 1] / k.theta_rgb,
+              c[:, 2] / k.theta_rgb]
+    return np.ascontiguousarray(np.stack(f, axis=1))
+
+
+def gauss_exact(fa: np.ndarray, fb: np.ndarray, vb: np.ndarray,
+                exclude_same_index: bool) -> np.ndarray:
+    """sum_b exp(-|fa_a - fb_b|^2 / 2) vb_b  (eq. fb), O(na nb C)."""
+    fa, fb, vb = _f64(fa), _f64(fb), _f64(vb)
+    vb2 = vb.reshape(vb.shape[0], -1)
+    out = np.empty((fa.shape[0], vb2.shape[1]))
+    _lib().or_gauss_exact(fa.shape[0], _p(fa), fb.shape[0], _p(fb),
+                          fa.shape[1], vb2.shape[1], _p(vb2), _p(out),
+                          int(exclude_same_index))
+    return out.reshape((fa.shape[0],) + vb.shape[1:])
+
+
+class Lattice:
+    """Reference permutohedral lattice over n points of dimension d."""
+
+    def __init__(self, f: np.ndarray):
+        self.f = _f64(f)
+        self.n, self.d = self.f.shape
+        self._h = _lib().or_lattice_build(self.n, self.d, _p(self.f))
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _lib().or_lattice_free(self._h)
+            self._h = None
+
+    @property
+    def nv(self) -> int:
+        return _lib().or_lattice_nv(self._h)
+
+    @property
+    def gamma(self) -> float:
+        return _lib().or_lattice_gamma(self.d)
+
+    def points(self):
+        vid = np.empty((self.n, self.d + 1), dtype=np.int32)
+        w = np.empty((self.n, self.d + 1))
+        _lib().or_lattice_points(self._h, _p(vid), _p(w))
+        return vid, w
+
+    def keys(self) -> np.ndarray:
+        k = np.empty((self.nv, self.d), dtype=np.int32)
+        _lib().or_lattice_keys(self._h, _p(k))
+        return k
+
+    def neighbours(self) -> np.ndarray:
+        nb = np.empty((self.nv, self.d + 1, 2), dtype=np.int32)
+        _lib().or_lattice_neighbours(self._h, _p(nb))
+        return nb
+
+    def splat(self, Y: np.ndarray) -> np.ndarray:
+        Y = _f64(Y).reshape(self.n, -1)
+        V = np.empty((self.nv, Y.shape[1]))
+        _lib().or_lattice_splat(self._h, Y.shape[1], _p(Y), _p(V))
+        return V
+
+    def blur(self, V: np.ndarray, reverse: bool = False) -> np.ndarray:
+        V = np.array(V, dtype=np.float64, order="C", copy=True)
+        _lib().or_lattice_blur(self._h, V.shape[1], _p(V), int(reverse))
+        return V
+
+    def slice(self, V: np.ndarray) -> np.ndarray:
+        V = _f64(V)
+        out = np.empty((self.n, V.shape[1]))
+        _lib().or_lattice_slice(self._h, V.shape[1], _p(V), _p(out))
+        return out
+
+    def filter(self, Y: np.ndarray, reverse: bool = False) -> np.ndarray:
+        """gamma_d * slice(blur(splat(Y))); ``reverse`` gives the adjoint."""
+        Y = _f64(Y)
+        Y2 = Y.reshape(self.n, -1)
+        out = np.empty_like(Y2)
+        _lib().or_lattice_filter(self._h, Y2.shape[1], _p(Y2), _p(out),
+                                 int(reverse))
+        return out.reshape(Y.shape)
+
+
+def elevate(f: np.ndarray) -> np.ndarray:
+    f = _f64(f)
+    x = np.empty(f.shape[0] + 1)
+    _lib().or_elevate(f.shape[0], _p(f), _p(x))
+    return x
+
+
+def simplex(x: np.ndarray):
+    """Vertices ((d+1) x (d+1) integer coordinates) and barycentric weights of
+    the lattice simplex that contains the elevated point x."""
+    x = _f64(x)
+    d = x.shape[0] - 1
+    vert = np.empty((d + 1, d + 1), dtype=np.int32)
+    b = np.empty(d + 1)
+    _lib().or_simplex(d, _p(x), _p(vert), _p(b))
+    return vert, b
+
+
+class Model:
+    """Pixel compatibility sum_m w_m k_m over an H x W image (eq. pairwise).
+
+    ``Kp(Y)`` applies K' = sum_m w_m K_m - (sum_m w_m) I, i.e.
+    (K'Y)_a = sum_{b != a} Kbar_ab Y_b: the restriction b != a of
+    eq. labelling-energy and the "- I_N" of eq. pairwise-matrix, with the
+    weights w_m inside the sum as in Sec. 6's K_ab (reading: eq.
+    pairwise-matrix leaves the weights implicit).
+
+    mode "exact": the O(N^2) sum. mode "lattice": each K_m replaced by its
+    permutohedral approximation; the self term subtracted is still the exact
+    (sum_m w_m) Y_a.
+    """
+
+    def __init__(self, H: int, W: int, rgb: np.ndarray, kernels, mode="lattice"):
+        self.H, self.W, self.N = H, W, H * W
+        self.kernels = [k if isinstance(k, Kernel) else Kernel(**k)
+                        for k in kernels]
+        self.feats = [features(H, W, rgb, k) for k in self.kernels]
+        self.w = np.array([k.weight for k in self.kernels], dtype=np.float64)
+        self.mode = mode
+        self.lattices = ([Lattice(f) for f in self.feats]
+                         if mode == "lattice" else None)
+
+    def with_weights(self, w) -> "Model":
+        m = object.__new__(Model)
+        m.__dict__.update(self.__dict__)
+        m.w = np.asarray(w, dtype=np.float64).copy()
+        return m
+
+    def Km(self, m: int, Y: np.ndarray, reverse: bool = False) -> np.ndarray:
+        """K_m Y including the diagonal term (exact or lattice)."""
+        if self.mode == "exact":
+            f = self.feats[m]
+            return gauss_exact(f, f, Y, exclude_same_index=False)
+        return self.lattices[m].filter(Y, reverse=reverse)
+
+    def Kp(self, Y: np.ndarray, reverse: bool = False) -> np.ndarray:
+        Y = _f64(Y)
+        if self.mode == "exact":
+            out = np.zeros_like(Y)
+            for m, f in enumerate(self.feats):
+                out += self.w[m] * gauss_exact(f, f, Y, exclude_same_index=True)
+            return out
+        out = -self.w.sum() * Y
+        for m in range(len(self.feats)):
+            out = out + self.w[m] * self.lattices[m].filter(Y, reverse=reverse)
+        return out
+
+    def dense_K(self) -> np.ndarray:
+        """Kbar with a zero diagonal, N x N (tiny N only)."""
+        K = np.zeros((self.N, self.N))
+        for m, f in enumerate(self.feats):
+            r2 = ((f[:, None, :] - f[None, :, :]) ** 2).sum(-1)
+            K += self.w[m] * np.exp(-0.5 * r2)
+        np.fill_diagonal(K, 0.0)
+        return K
+
+
+def onehot(labels: np.ndarray, L: int) -> np.ndarray:
+    s = np.zeros((labels.shape[0], L))
+    s[np.arange(labels.shape[0]), labels] = 1.0
+    return s
+
+
+def energy(model: Model, phi: np.ndarray, mu: np.ndarray,
+           labels: np.ndarray) -> float:
+    """E(x) = sum_a phi_a(x_a) + sum_a sum_{b != a} mu(x_a, x_b) Kbar_ab
+    (eq. labelling-energy with eq. pairwise), evaluated through K'."""
+    L = phi.shape[1]
+    S = onehot(labels, L)
+    KS = model.Kp(S)                       # (K'S)_a(j) = sum_{b!=a, x_b=j} Kbar
+    a = np.arange(labels.shape[0])
+    pair = (mu[labels, :] * KS).sum()      # sum_a sum_j mu(x_a, j) (K'S)_a(j)
+    return float(phi[a, labels].sum() + pair)
+
+
+def energy_dense(K: np.ndarray, phi: np.ndarray, mu: np.ndarray,
+                 labels: np.ndarray) -> float:
+    """The same energy from an explicit N x N Kbar (zero diagonal)."""
+    a = np.arange(labels.shape[0])
+    return float(phi[a, labels].sum() + (mu[labels][:, labels] * K).sum())
+
+
+def brute_force_min(K: np.ndarray, phi: np.ndarray, mu: np.ndarray):
+    """min_x E(x) by enumerating all L^N labellings (eq. map-pb), tiny N."""
+    N, L = phi.shape
+    best, best_x = math.inf, None
+    x = np.zeros(N, dtype=np.int64)
+    for code in range(L ** N):
+        c = code
+        for a in range(N):
+            x[a] = c % L
+            c //= L
+        e = energy_dense(K, phi, mu, x)
+        if e < best:
+            best, best_x = e, x.copy()
+    return best, best_x
+
+
+# ---------------------------------------------------------------------------
+# QP relaxation (Sec. 4) and Frank-Wolfe (Alg. fw, App. B)
+# ---------------------------------------------------------------------------
+
+class QP:
+    """The matrices of the QP relaxation for a model, unaries and mu.
+
+    (Psi y)_a(i) = sum_j mu_ij (K'Y)_a(j)        eq. pairwise-matrix
+    d_a(i) = sum_{b != a} sum_j |psi_ab(i, j)|    eq. RL-diagonal
+           = (sum_j |mu_ij|) (K'1)_a
+    Q y = (Psi + D) y.
+    """
+
+    def __init__(self, model: Model, phi: np.ndarray, mu: np.ndarray):
+        self.model, self.phi, self.mu = model, _f64(phi), _f64(mu)
+        self.N, self.L = self.phi.shape
+        self.r = model.Kp(np.ones((self.N, 1)))[:, 0]
+        self.d = self.r[:, None] * np.abs(self.mu).sum(axis=1)[None, :]
+        self.filter_calls = 0
+
+    def Psi(self, Y: np.ndarray) -> np.ndarray:
+        self.filter_calls += 1
+        return self.model.Kp(Y) @ self.mu.T
+
+    def Q(self, Y: np.ndarray) -> np.ndarray:
+        return self.Psi(Y) + self.d * Y
+
+    def S(self, y: np.ndarray) -> float:
+        """Non-convex QP objective phi^T y + y^T Psi y (eq. matrix-ilp)."""
+        return float((self.phi * y).sum() + (y * self.Psi(y)).sum())
+
+    def S_cvx(self, y: np.ndarray) -> float:
+        """(phi - d)^T y + y^T (Psi + D) y (eq. cvx-qp-min)."""
+        return float(((self.phi - self.d) * y).sum() + (y * self.Q(y)).sum())
+
+
+def softmax_neg(phi: np.ndarray) -> np.ndarray:
+    """y0 = softmax(-phi) per pixel: a point of M (reading: Alg. fw leaves
+    y0 unspecified)."""
+    z = -phi
+    z = z - z.max(axis=1, keepdims=True)
+    e = np.exp(z)
+    return e / e.sum(axis=1, keepdims=True)
+
+
+@dataclass
+class FWState:
+    y: np.ndarray
+    Py: np.ndarray
+    trace: list = field(default_factory=list)
+    s_hist: list = field(default_factory=list)
+    alphas: list = field(default_factory=list)
+
+
+def fw_step_size(c, y, s, Py, Ps):
+    """Exact minimiser over [0, 1] of f(y + alpha (s - y)) for
+    f(z) = c^T z + z^T Q z, with P_y = Q y and P_s = Q s (App. B,
+    eq. second-order-polynomial and eq. alpha-opt).
+
+    f(y + alpha D) = f(y) + alpha b1 + alpha^2 a2 with
+      b1 = c^T D + y^T Q D + D^T Q y,   a2 = D^T Q D,   D = s - y,
+    written with the four products <y,Py>, <y,Ps>, <s,Py>, <s,Ps> so that it
+    stays exact when the approximate Q is not symmetric. When a2 <= 0 the
+    minimum is at an endpoint.
+    """
+    A = (y * Py).sum()
+    B = (y * Ps).sum()
+    C = (s * Py).sum()
+    Dp = (s * Ps).sum()
+    cy = (c * y).sum()
+    cs = (c * s).sum()
+    b1 = cs - cy + B + C - 2.0 * A
+    a2 = Dp - B - C + A
+    if a2 > 0:
+        alpha = min(max(-b1 / (2.0 * a2), 0.0), 1.0)
+    else:
+        alpha = 1.0 if a2 + b1 < 0 else 0.0
+    return float(alpha), float(a2), float(b1)
+
+
+def frank_wolfe(qp: QP, y0: np.ndarray, iters: int, c: np.ndarray | None = None,
+                Py: np.ndarray | None = None) -> FWState:
+    """Frank-Wolfe on f(y) = c^T y + y^T (Psi + D) y over M (Alg. fw).
+
+    c defaults to phi - d (the convex QP, eq. cvx-qp-min). Per iteration:
+      gradient g = c + 2 P_y                        (eq. LRQP-grad)
+      conditional gradient s = one-hot argmin_i g   (eq. LRQP-lp; ties go to
+                                                     the lowest label)
+      P_s = (Psi + D) s                             (the one filter call)
+      optimal step alpha                            (App. B, eq. alpha-opt)
+      y <- y + alpha (s - y)                        (eq. conditional-upd-rule)
+      P_y <- (1 - alpha) P_y + alpha P_s            (App. B recurrence)
+    Reading: App. B's update y + alpha (s - y) is used (Alg. fw writes alpha
+    on y instead; the two are the same step with alpha <-> 1 - alpha).
+    Trace per iteration: (f(y_t), gap_t = <g, y_t - s_t>, alpha_t).
+    """
+    if c is None:
+        c = qp.phi - qp.d
+    y = _f64(y0).copy()
+    Py = qp.Q(y) if Py is None else Py.copy()
+    st = FWState(y=y, Py=Py)
+    L = qp.L
+    for _ in range(iters):
+        g = c + 2.0 * st.Py
+        s_lab = np.argmin(g, axis=1)
+        s = onehot(s_lab, L)
+        Ps = qp.Q(s)
+        alpha, _, _ = fw_step_size(c, st.y, s, st.Py, Ps)
+        obj = float((c * st.y).sum() + (st.y * st.Py).sum())
+        gap = float((g * (st.y - s)).sum())
+        st.trace.append((obj, gap, alpha))
+        st.s_hist.append(s_lab.astype(np.int32))
+        st.alphas.append(alpha)
+        st.y = st.y + alpha * (s - st.y)
+        st.Py = (1.0 - alpha) * st.Py + alpha * Ps
+    return st
+
+
+def round_argmax(y: np.ndarray) -> np.ndarray:
+    """Labelling from marginals: argmax per pixel, lowest label on ties
+    (reading: the paper does not fix a rounding for the QP and DC solvers)."""
+    return np.argmax(y, axis=1).astype(np.int32)
+
+
+def dc_gen(qp: QP, y0: np.ndarray, outer: int, inner: int):
+    """CCCP on the generic DC decomposition (Sec. 5.1, Alg. cccp, eq. cccp-qp).
+
+    p(y) = phi^T y + y^T (Psi + D) y,  q(y) = y^T D y.
+    Step k: g = grad q(y^k) = 2 d * y^k, then minimise the convex
+    p(y) - g^T y over M with ``inner`` Frank-Wolfe iterations warm-started at
+    y^k (App. C: decreasing the convex surrogate is enough for CCCP's
+    monotone decrease). Returns y and the objective S(y^k) after each step.
+    """
+    y = _f64(y0).copy()
+    Py = qp.Q(y)
+    hist = [qp.S(y)]
+    for _ in range(outer):
+        c = qp.phi - 2.0 * qp.d * y
+        st = frank_wolfe(qp, y, inner, c=c, Py=Py)
+        y, Py = st.y, st.Py
+        hist.append(qp.S(y))
+    return y, hist
+
+
+# ---------------------------------------------------------------------------
+# LP relaxation (Sec. 6; App. D, E) -- Potts model
+# ---------------------------------------------------------------------------
+
+def sorted_order(col: np.ndarray) -> np.ndarray:
+    """Pixels by y_a(i) descending; equal values keep ascending pixel index
+    (reading: ties are not discussed; any order gives a valid subgradient)."""
+    return np.argsort(-col, kind="stable")
+
+
+def lp_pair_sums_brute(K: np.ndarray, order: np.ndarray):
+    """U_c = sum_{a after c} Kbar_ac and Lo_c = sum_{a before c} Kbar_ac in the
+    given order (the two sums of eq. grad_lp), O(N^2), from a dense Kbar."""
+    N = order.shape[0]
+    U = np.zeros(N)
+    Lo = np.zeros(N)
+    for p in range(N):
+        c = order[p]
+        U[c] = K[order[p + 1:], c].sum()
+        Lo[c] = K[order[:p], c].sum()
+    return U, Lo
+
+
+def dnc_nodes(N: int):
+    """Nodes of the divide and conquer of App. E, level by level.
+
+    App. E splits a range of N positions at h = N/2 and recurses on both
+    halves; "the odd case is very similar". Reading: at level l the node
+    boundaries are b_n = floor(n N / 2^l), n = 0..2^l, so node n = [b_n, b_{n+1})
+    splits at floor((2n+1) N / 2^(l+1)); the top split is N/2 for even N (the
+    3|3 blocks of the N = 6 example of Sec. 6) and after ceil(log2 N) levels
+    every node holds at most one position. Yields (lo, mid, hi) for every node
+    whose two halves are both non-empty.
+    """
+    levels = int(math.ceil(math.log2(N))) if N > 1 else 0
+    for l in range(levels):
+        for n in range(1 << l):
+            lo = (n * N) >> l
+            hi = ((n + 1) * N) >> l
+            mid = ((2 * n + 1) * N) >> (l + 1)
+            if lo < mid < hi:
+                yield lo, mid, hi
+
+
+def lp_pair_sums_dnc(model: Model, order: np.ndarray, inner: str):
+    """U and Lo of eq. grad_lp by the divide-and-conquer of App. E.
+
+    For each node, the block between its halves is one filter call: the
+    indicator of the right half filtered over the node's points and read at
+    the left half adds to U; the indicator of the left half read at the right
+    half adds to Lo. ``inner`` = "exact" uses the O(n^2) Gaussian sum,
+    "lattice" a permutohedral lattice built on the node's points only.
+    """
+    N = order.shape[0]
+    U = np.zeros(N)
+    Lo = np.zeros(N)
+    for lo, mid, hi in dnc_nodes(N):
+        left = order[lo:mid]
+        right = order[mid:hi]
+        if inner == "exact":
+            for m, f in enumerate(model.feats):
+                ones_r = np.ones((right.shape[0], 1))
+                ones_l = np.ones((left.shape[0], 1))
+                U[left] += model.w[m] * gauss_exact(f[left], f[right], ones_r,
+                                                    False)[:, 0]
+                Lo[right] += model.w[m] * gauss_exact(f[right], f[left], ones_l,
+                                                      False)[:, 0]
+        else:
+            pts = order[lo:hi]
+            ind = np.zeros((pts.shape[0], 2))
+            ind[: mid - lo, 0] = 1.0          # channel 0: left indicator
+            ind[mid - lo:, 1] = 1.0           # channel 1: right indicator
+            acc = np.zeros((pts.shape[0], 2))
+            for m, f in enumerate(model.feats):
+                acc += model.w[m] * Lattice(f[pts]).filter(ind)
+            U[left] += acc[: mid - lo, 1]
+            Lo[right] += acc[mid - lo:, 0]
+    return U, Lo
+
+
+def lp_subgradient(phi: np.ndarray, y: np.ndarray, pair_sums):
+    """g_c(k) = phi_c(k) + sum_{a>c} K_ac - sum_{a<c} K_ac   (eq. grad_lp)
+    with the order of label k's marginals; S_LP(y) = <g, y> (eq. simple_S)."""
+    N, L = phi.shape
+    g = np.array(phi, dtype=np.float64, copy=True)
+    for i in range(L):
+        U, Lo = pair_sums(sorted_order(y[:, i]))
+        g[:, i] += U - Lo
+    return g, float((g * y).sum())
+
+
+def S_LP_dense(K: np.ndarray, phi: np.ndarray, y: np.ndarray) -> float:
+    """eq. potts-lp evaluated directly from a dense Kbar (tiny N)."""
+    pair = 0.0
+    for i in range(y.shape[1]):
+        pair += (K * np.abs(y[:, None, i] - y[None, :, i])).sum() / 2.0
+    return float((phi * y).sum() + pair)
+
+
+def project_simplex(V: np.ndarray) -> np.ndarray:
+    """Euclidean projection of every row onto {y >= 0, sum y = 1}: the sort
+    based method (Held, Wolfe and Crowder; Duchi et al.). Condat's algorithm,
+    which the paper uses, returns the same unique point."""
+    V = _f64(V)
+    u = -np.sort(-V, axis=1)
+    css = np.cumsum(u, axis=1)
+    j = np.arange(1, V.shape[1] + 1)[None, :]
+    cond = u - (css - 1.0) / j > 0
+    rho = V.shape[1] - np.argmax(cond[:, ::-1], axis=1)      # last true, 1-based
+    tau = (css[np.arange(V.shape[0]), rho - 1] - 1.0) / rho
+    return np.maximum(V - tau[:, None], 0.0)
+
+
+def lp_descent(phi: np.ndarray, y0: np.ndarray, steps: int, beta0: float,
+               pair_sums):
+    """Projected subgradient descent on S_LP (Alg. lp_subgrad) with
+    beta_t = beta0 / (1 + t), t = 0, 1, ... (reading: the paper's example
+    sequence 1/(1+t) with an explicit scale). Returns the last y, the best
+    (S_LP, y) seen and the S_LP history."""
+    y = _f64(y0).copy()
+    best, best_y, hist = math.inf, y.copy(), []
+    for t in range(steps):
+        g, S = lp_subgradient(phi, y, pair_sums)
+        hist.append(S)
+        if S < best:
+            best, best_y = S, y.copy()
+        y = project_simplex(y - beta0 / (1.0 + t) * g)
+    return y, best, best_y, hist

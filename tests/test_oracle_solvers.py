@@ -1,0 +1,289 @@
+"""Pins of the oracle's solvers: Frank-Wolfe on the convex QP, CCCP on the
+generic DC relaxation, the LP subgradient (brute force and divide and
+conquer), projected subgradient descent and the simplex projection.
+
+The pins are brute-force minima, an independent LP solver (scipy's HiGHS on
+the standard-form LP with one extra variable per pair), independent line
+searches and projections, and identities the paper states.
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1608_06192_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def tiny_problem(N=6, L=3, seed=0, w=(4.0, 1.5)):
+    """A tiny dense CRF on a 2 x (N/2) image, exact filter."""
+    rng = np.random.default_rng(seed)
+    H, W = 2, N // 2
+    rgb = rng.uniform(0, 255, size=(N, 3)).astype(np.float32)
+    kern = [O.Kernel(1, 2.0, 60.0, w[0]), O.Kernel(0, 1.0, 0.0, w[1])]
+    model = O.Model(H, W, rgb, kern, mode="exact")
+    phi = rng.normal(0, 3.0, size=(N, L))
+    return model, phi
+
+
+def test_energy_two_pixels_by_hand():
+    # N = 2, Kbar_12 = w/2: E(x) = phi_1(x_1) + phi_2(x_2) + 2 mu(x_1,x_2) w/2,
+    # because eq. labelling-energy sums ordered pairs a != b.
+    t = math.sqrt(2 * math.log(2))        # pixel distance giving k = 1/2
+    model = O.Model(1, 2, np.zeros((2, 3), np.float32),
+                    [O.Kernel(0, 1.0 / t, 0.0, 3.0)], mode="exact")
+    phi = np.array([[0.5, 2.0], [1.0, 0.25]])
+    mu = synth.potts(2)
+    expect = {(0, 0): 1.5, (1, 1): 2.25, (0, 1): 0.75 + 3.0, (1, 0): 3.0 + 3.0}
+    for x, e in expect.items():
+        assert abs(O.energy(model, phi, mu, np.array(x)) - e) < 1e-14
+
+
+def test_qp_equals_energy_at_integral_points():
+    # eq. energy-ip: the objective equals E at integral y; S_cvx adds
+    # sum d (y^2 - y), which vanishes there (eq. cvx-qp-min).
+    model, phi = tiny_problem()
+    mu = synth.potts(3)
+    qp = O.QP(model, phi, mu)
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        x = rng.integers(0, 3, size=6)
+        y = O.onehot(x, 3)
+        E = O.energy(model, phi, mu, x)
+        assert abs(qp.S(y) - E) < 1e-12 * max(1, abs(E))
+        assert abs(qp.S_cvx(y) - E) < 1e-12 * max(1, abs(E))
+    # on M, S_cvx <= S since d >= 0 and y^2 <= y
+    for _ in range(20):
+        y = synth.random_simplex_points(6, 3, int(rng.integers(1 << 30)))
+        assert qp.S_cvx(y) <= qp.S(y) + 1e-12
+
+
+def test_rl_diagonal_is_row_sum_of_abs_psi():
+    # eq. RL-diagonal with an explicit Psi built from the dense Kbar
+    model, phi = tiny_problem()
+    mu = np.array([[0.0, 1.0, 2.0], [1.0, 0.0, -0.5], [2.0, -0.5, 0.0]])
+    qp = O.QP(model, phi, mu)
+    K = model.dense_K()
+    N, L = phi.shape
+    for a in range(N):
+        for i in range(L):
+            dd = sum(abs(mu[i, j] * K[a, b]) for b in range(N) if b != a
+                     for j in range(L))
+            assert abs(qp.d[a, i] - dd) < 1e-12
+
+
+def test_fw_step_is_exact_line_minimum():
+    # App. B: alpha* minimises S_cvx on the segment; compare with a 10001-point
+    # grid of fresh evaluations of S_cvx
+    model, phi = tiny_problem(seed=2)
+    qp = O.QP(model, phi, synth.potts(3))
+    y = O.softmax_neg(phi)
+    c = qp.phi - qp.d
+    for _ in range(4):
+        Py = qp.Q(y)
+        s = O.onehot(np.argmin(c + 2 * Py, axis=1), 3)
+        alpha, _, _ = O.fw_step_size(c, y, s, Py, qp.Q(s))
+        grid = np.linspace(0, 1, 10001)
+        vals = np.array([qp.S_cvx(y + t * (s - y)) for t in grid])
+        assert qp.S_cvx(y + alpha * (s - y)) <= vals.min() + 1e-9
+        assert abs(alpha - grid[vals.argmin()]) <= 2e-4 or alpha in (0.0, 1.0)
+        y = y + alpha * (s - y)
+
+
+def test_fw_invariants_and_bounds():
+    # gap >= 0; f non-increasing; recurrence P_y == fresh Q y; the best dual
+    # bound max_t (f_t - gap_t) <= min over M of S_cvx <= E_min (Sec. 4:
+    # S_cvx is a relaxation; Ravikumar-Lafferty tightness of the QP)
+    model, phi = tiny_problem(seed=4)
+    mu = synth.potts(3)
+    qp = O.QP(model, phi, mu)
+    st = O.frank_wolfe(qp, O.softmax_neg(phi), 200)
+    f = np.array([t[0] for t in st.trace])
+    gap = np.array([t[1] for t in st.trace])
+    assert (gap >= -1e-9).all()
+    assert (np.diff(f) <= 1e-9).all()
+    assert np.abs(st.Py - qp.Q(st.y)).max() < 1e-9
+    Emin, xmin = O.brute_force_min(model.dense_K(), phi, mu)
+    lower = (f - gap).max()
+    assert lower <= qp.S_cvx(st.y) + 1e-9
+    assert lower <= Emin + 1e-9
+    assert qp.S_cvx(st.y) <= Emin + 1e-9
+    assert abs(O.energy(model, phi, mu, xmin) - Emin) < 1e-12
+
+
+def test_fw_matches_projected_gradient_minimum():
+    # an independent solver of the same convex QP: projected gradient with
+    # the textbook simplex projection and step 1/Lipschitz
+    model, phi = tiny_problem(seed=6)
+    qp = O.QP(model, phi, synth.potts(3))
+    st = O.frank_wolfe(qp, O.softmax_neg(phi), 2000)
+    Qd = np.stack([qp.Q(e.reshape(6, 3)).ravel() for e in np.eye(18)], 1)
+    lip = 2 * np.linalg.eigvalsh(0.5 * (Qd + Qd.T)).max()
+    y = O.softmax_neg(phi)
+    c = qp.phi - qp.d
+    for _ in range(20000):
+        y = O.project_simplex(y - (c + 2 * qp.Q(y)) / lip)
+    f = np.array([t[0] for t in st.trace])
+    gap = np.array([t[1] for t in st.trace])
+    pg = qp.S_cvx(y)
+    # FW's duality bound and value bracket the independent minimum
+    assert (f - gap).max() <= pg + 1e-9
+    assert pg <= qp.S_cvx(st.y) + 1e-9
+    assert qp.S_cvx(st.y) - pg < 1e-4 * abs(pg)
+
+
+def test_fw_zero_weights_is_unary_argmin():
+    # w = 0: d = 0 and the objective is linear; one step reaches argmin phi
+    model, phi = tiny_problem(seed=7, w=(0.0, 0.0))
+    qp = O.QP(model, phi, synth.potts(3))
+    st = O.frank_wolfe(qp, O.softmax_neg(phi), 1)
+    assert st.alphas[0] == 1.0
+    assert (O.round_argmax(st.y) == np.argmin(phi, axis=1)).all()
+
+
+def test_dc_gen_monotone_and_above_minimum():
+    # Alg. cccp: S(y^{k+1}) <= S(y^k) (Sec. 5.1; App. C: an inexact convex
+    # step that decreases the surrogate is enough); S >= E_min on M
+    model, phi = tiny_problem(seed=8)
+    mu = synth.potts(3)
+    qp = O.QP(model, phi, mu)
+    st = O.frank_wolfe(qp, O.softmax_neg(phi), 30)
+    y, hist = O.dc_gen(qp, st.y, outer=8, inner=10)
+    assert (np.diff(hist) <= 1e-9).all()
+    Emin, _ = O.brute_force_min(model.dense_K(), phi, mu)
+    assert min(hist) >= Emin - 1e-9
+    # the surrogate's linear term at y = 1/2 everywhere equals S_cvx's: 2 d/2 = d
+    assert np.allclose(qp.phi - 2 * qp.d * 0.5, qp.phi - qp.d)
+
+
+# ----------------------------------------------------------------------- LP
+
+def test_dnc_nodes_golden_example():
+    rows = [tuple(int(v) for v in line.split())
+            for line in open(os.path.join(GOLDEN, "dnc_n6_example.txt"))
+            if line.strip() and not line.startswith("#")]
+    got = list(O.dnc_nodes(6))
+    assert [(lo, mid, hi) for (_, lo, mid, hi) in rows] == got
+
+
+@pytest.mark.parametrize("N", list(range(1, 40)) + [64, 100, 187])
+def test_dnc_blocks_cover_upper_triangle_once(N):
+    cover = np.zeros((N, N), dtype=int)
+    for lo, mid, hi in O.dnc_nodes(N):
+        cover[lo:mid, mid:hi] += 1
+    assert (cover == np.triu(np.ones((N, N), dtype=int), 1)).all()
+
+
+def test_lp_dnc_exact_equals_brute_force():
+    model, phi = tiny_problem(N=12, L=3, seed=9)
+    K = model.dense_K()
+    rng = np.random.default_rng(0)
+    for sp in (0.0, 0.5):
+        y = synth.random_simplex_points(12, 3, int(rng.integers(99)), sp)
+        g1, S1 = O.lp_subgradient(phi, y, lambda o: O.lp_pair_sums_brute(K, o))
+        g2, S2 = O.lp_subgradient(
+            phi, y, lambda o: O.lp_pair_sums_dnc(model, o, "exact"))
+        assert np.abs(g1 - g2).max() < 1e-12
+        assert abs(S1 - S2) < 1e-11
+
+
+def test_lp_reformulation_and_integral_energy():
+    # eq. simple_S: <g(y), y> equals eq. potts-lp's |.| form; at integral y
+    # S_LP = E (Sec. 6)
+    model, phi = tiny_problem(N=10, L=3, seed=10)
+    K = model.dense_K()
+    mu = synth.potts(3)
+    rng = np.random.default_rng(1)
+    brute = lambda o: O.lp_pair_sums_brute(K, o)
+    for sp in (0.0, 0.3, 0.7):
+        y = synth.random_simplex_points(10, 3, int(rng.integers(99)), sp)
+        _, S = O.lp_subgradient(phi, y, brute)
+        assert abs(S - O.S_LP_dense(K, phi, y)) < 1e-11
+    for _ in range(10):
+        x = rng.integers(0, 3, size=10)
+        _, S = O.lp_subgradient(phi, O.onehot(x, 3), brute)
+        assert abs(S - O.energy(model, phi, mu, x)) < 1e-11
+
+
+def test_lp_subgradient_inequality():
+    # S_LP is convex and g(y) is a subgradient: S_LP(z) >= S_LP(y) + <g, z - y>
+    model, phi = tiny_problem(N=10, L=4, seed=11)
+    K = model.dense_K()
+    rng = np.random.default_rng(2)
+    for _ in range(30):
+        y = synth.random_simplex_points(10, 4, int(rng.integers(1 << 20)), 0.3)
+        g, S = O.lp_subgradient(phi, y, lambda o: O.lp_pair_sums_brute(K, o))
+        for _ in range(5):
+            z = synth.random_simplex_points(10, 4, int(rng.integers(1 << 20)))
+            assert O.S_LP_dense(K, phi, z) >= S + (g * (z - y)).sum() - 1e-10
+
+
+def _lp_optimum_highs(K, phi):
+    """min phi^T y + sum_{a<b} K_ab sum_i t_ab(i), t >= |y_a(i) - y_b(i)|,
+    y in M: the LP of Kleinberg and Tardos with one variable per pair."""
+    from scipy.optimize import linprog
+    N, L = phi.shape
+    pairs = [(a, b) for a in range(N) for b in range(a + 1, N)]
+    ny, nt = N * L, len(pairs) * L
+    cost = np.concatenate([phi.ravel(),
+                           np.repeat([K[a, b] for a, b in pairs], L)])
+    A, rhs = [], []
+    for p, (a, b) in enumerate(pairs):
+        for i in range(L):
+            for sgn in (1, -1):
+                row = np.zeros(ny + nt)
+                row[a * L + i] = sgn
+                row[b * L + i] = -sgn
+                row[ny + p * L + i] = -1
+                A.append(row)
+                rhs.append(0.0)
+    Aeq = np.zeros((N, ny + nt))
+    for a in range(N):
+        Aeq[a, a * L:(a + 1) * L] = 1
+    res = linprog(cost, A_ub=np.array(A), b_ub=rhs, A_eq=Aeq, b_eq=np.ones(N),
+                  bounds=[(0, None)] * (ny + nt), method="highs")
+    assert res.status == 0
+    return res.fun
+
+
+def test_lp_descent_approaches_lp_optimum_and_two_label_tightness():
+    # Alg. lp_subgrad converges to the LP optimum (checked against HiGHS);
+    # with two labels the LP is tight: its optimum equals E_min (Sec. 8)
+    for L, seed, beta0 in ((2, 12, 0.2), (3, 13, 2.0)):
+        model, phi = tiny_problem(N=6, L=L, seed=seed)
+        K = model.dense_K()
+        opt = _lp_optimum_highs(K, phi)
+        Emin, _ = O.brute_force_min(K, phi, synth.potts(L))
+        assert opt <= Emin + 1e-9
+        if L == 2:
+            assert abs(opt - Emin) < 1e-8
+        y0 = O.softmax_neg(phi)
+        _, best, best_y, hist = O.lp_descent(
+            phi, y0, 3000, beta0, lambda o: O.lp_pair_sums_brute(K, o))
+        assert best >= opt - 1e-9
+        assert best - opt < 2e-2 * max(1.0, abs(opt))
+
+
+def test_simplex_projection_kkt_and_bisection():
+    rng = np.random.default_rng(14)
+    V = rng.normal(0, 2, size=(200, 21))
+    V[:20, :5] = 0.3                        # ties
+    P = O.project_simplex(V)
+    assert (P >= 0).all() and np.allclose(P.sum(1), 1, atol=1e-13)
+    for v, p in zip(V, P):
+        lo, hi = v.min() - 1, v.max()
+        for _ in range(200):                 # bisection on sum max(v-t,0) = 1
+            mid = 0.5 * (lo + hi)
+            if np.maximum(v - mid, 0).sum() > 1:
+                lo = mid
+            else:
+                hi = mid
+        assert np.abs(p - np.maximum(v - 0.5 * (lo + hi), 0)).max() < 1e-12
+        # nearest point: no feasible random point is closer
+        for _ in range(10):
+            z = rng.dirichlet(np.ones(21))
+            assert np.linalg.norm(v - p) <= np.linalg.norm(v - z) + 1e-12
