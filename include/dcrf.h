@@ -1,0 +1,177 @@
+/*
+ * dcrf.h -- C ABI of the MI355X (gfx950) library for energy minimisation in
+ * dense CRFs with Gaussian pairwise potentials by continuous relaxations
+ * (Desmaison, Bunel, Kohli, Torr, Kumar, "Efficient Continuous Relaxations
+ * for Dense CRF", ECCV 2016).
+ *
+ * Problem (Sec. 3): N = H*W pixels, L labels, unaries phi (N x L), a label
+ * compatibility mu (L x L) and a pixel compatibility that is a mixture of
+ * Gaussian kernels sum_m w_m exp(-|f_a^m - f_b^m|^2 / 2) (eq. pairwise,
+ * eq. gaussiankernel). Kernel m's features are the pixel position divided by
+ * theta_pos and, when use_rgb, the RGB colour divided by theta_rgb (App. G):
+ * f = (x/theta_pos, y/theta_pos[, R/theta_rgb, G/theta_rgb, B/theta_rgb]),
+ * x = column, y = row.
+ *
+ * Conventions for every call below:
+ *  - Layout: pixel-major. Pixel a = row*W + col. An N x C array holds
+ *    element (a, c) at [a*C + c]. mu is row-major L x L. rgb is float32
+ *    N x 3 with values in [0, 255].
+ *  - Memory: every array argument marked (dev) is DEVICE memory on the
+ *    context's device, owned by the caller, contiguous, in the context's
+ *    floating type (float for DCRF_F32, double for DCRF_F64) unless stated.
+ *    Arguments marked (host) are host memory. The library keeps its own
+ *    device workspace (lattice tables, solver state) inside the context and
+ *    never frees caller memory.
+ *  - Streams: all device work is enqueued on the context's stream. Calls
+ *    that return host values (energies, traces, objective values) wait for
+ *    the stream; the others are asynchronous.
+ *  - Errors: every call returns a dcrf_status. It never aborts or exits. On
+ *    failure dcrf_last_error() returns a message; the context stays usable.
+ */
+#ifndef DCRF_H
+#define DCRF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dcrf_ctx dcrf_ctx;
+
+typedef enum {
+    DCRF_OK = 0,
+    DCRF_EINVAL = -1,        /* bad argument (null, size, value)            */
+    DCRF_ENOMEM = -2,        /* device allocation failed                    */
+    DCRF_ERANGE = -3,        /* lattice coordinates exceed the key range    */
+    DCRF_ECAPACITY = -4,     /* hash table overflow                          */
+    DCRF_EHIP = -5,          /* a HIP runtime call failed                    */
+    DCRF_EUNSUPPORTED = -6,  /* unsupported size or combination             */
+    DCRF_ESTATE = -7         /* call out of order (e.g. no image set)       */
+} dcrf_status;
+
+typedef enum { DCRF_F32 = 0, DCRF_F64 = 1 } dcrf_dtype;
+
+/* How the solvers apply the pixel compatibility. */
+typedef enum {
+    DCRF_FILTER_LATTICE = 0, /* permutohedral lattice, O(N) (Sec. 3, App. A) */
+    DCRF_FILTER_EXACT = 1    /* exact O(N^2) Gaussian sum (eq. fb)           */
+} dcrf_filter_mode;
+
+/* Flags of dcrf_filter. */
+#define DCRF_ADJOINT 1u      /* apply the transpose (blur directions reversed) */
+#define DCRF_EXACT 2u        /* use the exact O(N^2) sum for this call        */
+
+/* One Gaussian kernel of the pixel compatibility (eq. pairwise, App. G). */
+typedef struct {
+    int use_rgb;             /* 1: features (x, y, R, G, B); 0: (x, y)       */
+    double theta_pos;        /* > 0, in pixels                               */
+    double theta_rgb;        /* > 0 when use_rgb, in colour units             */
+    double weight;           /* w_m >= 0                                      */
+} dcrf_kernel;
+
+/* Per-iteration record of a Frank-Wolfe run (Sec. 4, Alg. fw). */
+typedef struct {
+    double objective;        /* f(y_t) = c^T y_t + y_t^T (Psi + D) y_t        */
+    double gap;              /* <g_t, y_t - s_t>, g_t = c + 2 (Psi + D) y_t   */
+    double alpha;            /* step taken from y_t                           */
+    double changed;          /* pixels whose conditional gradient changed     */
+} dcrf_iter_trace;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device`; `hip_stream` is a hipStream_t
+ * (NULL = the null stream). *out receives the context. */
+int dcrf_create(dcrf_ctx **out, int device, void *hip_stream);
+int dcrf_destroy(dcrf_ctx *ctx);
+/* Message of the last failed call on this context (never NULL). */
+const char *dcrf_last_error(const dcrf_ctx *ctx);
+/* Enqueue later work on another hipStream_t. */
+int dcrf_set_stream(dcrf_ctx *ctx, void *hip_stream);
+/* Library version string. */
+const char *dcrf_version(void);
+
+/* ---- image and lattices ------------------------------------------------ */
+
+/* Set the image and kernels (1 <= nk <= 4) and build one permutohedral
+ * lattice per kernel on the device: lattice coordinates in FP64, a device
+ * hash table of vertices, per-pixel vertex ids and barycentric weights and a
+ * neighbour table along the d+1 blur directions. Also computes the row sums
+ * r = K'1 used by d (eq. RL-diagonal). rgb: (dev) float32 N x 3.
+ * dtype: DCRF_F32 or DCRF_F64 for every later floating argument.
+ * Errors: DCRF_EINVAL (sizes, thetas), DCRF_ERANGE (coordinates too large
+ * for the 64-bit vertex key: theta too small for the image), DCRF_ENOMEM. */
+int dcrf_set_image(dcrf_ctx *ctx, int H, int W, const float *rgb,
+                   const dcrf_kernel *kernels, int nk, int dtype);
+
+/* Replace the kernel weights w_m (host, nk values) without rebuilding the
+ * lattices; recomputes r. */
+int dcrf_set_weights(dcrf_ctx *ctx, const double *w, int nk);
+
+/* Choose lattice or exact filtering for the solvers (default lattice). */
+int dcrf_set_filter_mode(dcrf_ctx *ctx, int mode);
+
+/* Lattice of kernel m: feature dimension d and number of vertices. */
+int dcrf_lattice_info(dcrf_ctx *ctx, int m, int *d, int *nvert);
+
+/* Copy lattice m to the host: keys (host, nvert x d int32) = the first d
+ * integer coordinates of each vertex in the scaled lattice (d+1)A*_d;
+ * vid (host, N x (d+1) int32) = the vertex of each pixel's simplex, -1 where
+ * the barycentric weight is 0; w (host, N x (d+1) double) = the weights.
+ * Any pointer may be NULL. For tests and inspection. */
+int dcrf_lattice_export(dcrf_ctx *ctx, int m, int32_t *keys, int32_t *vid,
+                        double *w);
+
+/* ---- the pairwise filter ----------------------------------------------- */
+
+/* out = K' in, where K' = sum_m w_m K_m - (sum_m w_m) I, i.e.
+ * out_a = sum_{b != a} sum_m w_m k_m(a, b) in_b  (eq. fb summed over the
+ * kernels without the b = a term of eq. labelling-energy). By default each
+ * K_m is its permutohedral approximation gamma_d * slice . blur . splat;
+ * DCRF_EXACT uses the O(N^2) sum, DCRF_ADJOINT the transpose.
+ * in, out: (dev) N x C, 1 <= C <= 256, not aliased. */
+int dcrf_filter(dcrf_ctx *ctx, const void *in, void *out, int C,
+                unsigned flags);
+
+/* out = (Psi + D) y = (K'Y) mu^T + d * y  (eq. pairwise-matrix,
+ * eq. RL-diagonal with d_a(i) = sum_j |mu_ij| (K'1)_a). y, out: (dev) N x L;
+ * mu: (dev) L x L. Uses the filter mode of the context. */
+int dcrf_qp_apply(dcrf_ctx *ctx, const void *y, const void *mu, int L,
+                  void *out);
+
+/* ---- solvers ------------------------------------------------------------ */
+
+/* Frank-Wolfe on the convex QP relaxation (Sec. 4, Alg. fw, App. B):
+ * minimise (phi - d)^T y + y^T (Psi + D) y over the product of simplices.
+ * unary: (dev) N x L; mu: (dev) L x L; y_inout: (dev) N x L, the starting
+ * point on input (must lie in the feasible set), the result on output.
+ * trace: (host) `iters` records or NULL. One filter call per iteration; the
+ * step size is solved on the device. */
+int dcrf_qp_frank_wolfe(dcrf_ctx *ctx, const void *unary, const void *mu,
+                        int L, void *y_inout, int iters,
+                        dcrf_iter_trace *trace);
+
+/* Generic DC relaxation by CCCP (Sec. 5.1, Alg. cccp, eq. cccp-qp): `outer`
+ * steps, each minimising phi^T y - 2 (d * y^k)^T y + y^T (Psi + D) y with
+ * `inner` warm-started Frank-Wolfe iterations. S_hist: (host) outer+1 values
+ * of S(y) = phi^T y + y^T Psi y (before the first and after each step) or
+ * NULL. */
+int dcrf_dc_gen(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
+                void *y_inout, int outer, int inner, double *S_hist);
+
+/* argmax labelling of marginals y (dev, N x L) into labels (dev int32 N),
+ * lowest label on ties. */
+int dcrf_round(dcrf_ctx *ctx, const void *y, int L, int32_t *labels);
+
+/* Energy E(x) = sum_a phi_a(x_a) + sum_a sum_{b != a} mu(x_a, x_b) Kbar_ab
+ * (eq. labelling-energy) of labels (dev int32 N, values in [0, L)), with the
+ * context's filter mode; *energy (host). */
+int dcrf_energy(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
+                const int32_t *labels, double *energy);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DCRF_H */

@@ -1,0 +1,243 @@
+// C ABI of the library (declared in include/dcrf.h): argument checks, error
+// capture and dispatch to the launchers. No call throws or aborts; failures
+// return a status and leave a message in the context.
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "dcrf_internal.h"
+
+using dcrf::Error;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+int set_err(dcrf_ctx *ctx, int code, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+template <typename F>
+int guarded(dcrf_ctx *ctx, F &&f) {
+    if (!ctx) return DCRF_EINVAL;
+    try {
+        DCRF_TRY_HIP(hipSetDevice(ctx->device));
+        f();
+        ctx->err.clear();
+        return DCRF_OK;
+    } catch (const Error &e) {
+        return set_err(ctx, e.code, e.msg);
+    } catch (const std::bad_alloc &) {
+        return set_err(ctx, DCRF_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return set_err(ctx, DCRF_EHIP, "unexpected exception");
+    }
+}
+
+#define REQUIRE(cond, msg)                                        \
+    do {                                                          \
+        if (!(cond)) dcrf::fail(DCRF_EINVAL, std::string(msg));   \
+    } while (0)
+
+void require_image(dcrf_ctx *ctx) {
+    if (!ctx->has_image)
+        dcrf::fail(DCRF_ESTATE, "no image set: call dcrf_set_image first");
+}
+
+void check_labels(int L) {
+    REQUIRE(L >= 1 && L <= 256, "L must be in [1, 256]");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dcrf_version(void) { return "dcrf 0.1 (gfx950)"; }
+
+int dcrf_create(dcrf_ctx **out, int device, void *hip_stream) {
+    if (!out) return DCRF_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+        g_create_error = "no such HIP device";
+        return DCRF_EINVAL;
+    }
+    dcrf_ctx *ctx = new (std::nothrow) dcrf_ctx();
+    if (!ctx) return DCRF_ENOMEM;
+    ctx->device = device;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    *out = ctx;
+    return DCRF_OK;
+}
+
+int dcrf_destroy(dcrf_ctx *ctx) {
+    if (!ctx) return DCRF_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto &L : ctx->lat) L.release();
+    for (dcrf::DevBuf *b :
+         {&ctx->r, &ctx->scratch, &ctx->tmpA, &ctx->tmpB, &ctx->fw_c,
+          &ctx->fw_Py, &ctx->fw_Ps, &ctx->fw_s, &ctx->fw_sprev, &ctx->fw_part,
+          &ctx->fw_scal, &ctx->fw_trace, &ctx->fw_mu})
+        b->release();
+    delete ctx;
+    return DCRF_OK;
+}
+
+const char *dcrf_last_error(const dcrf_ctx *ctx) {
+    if (!ctx) return g_create_error.c_str();
+    return ctx->err.c_str();
+}
+
+int dcrf_set_stream(dcrf_ctx *ctx, void *hip_stream) {
+    return guarded(ctx, [&] { ctx->stream = static_cast<hipStream_t>(hip_stream); });
+}
+
+int dcrf_set_image(dcrf_ctx *ctx, int H, int W, const float *rgb,
+                   const dcrf_kernel *kernels, int nk, int dtype) {
+    return guarded(ctx, [&] {
+        REQUIRE(H >= 1 && W >= 1 && (long long)H * W <= (1ll << 28),
+                "H and W must be >= 1 with H*W <= 2^28");
+        REQUIRE(rgb != nullptr, "rgb is null");
+        REQUIRE(kernels != nullptr && nk >= 1 && nk <= DCRF_MAXK,
+                "need 1 to 4 kernels");
+        REQUIRE(dtype == DCRF_F32 || dtype == DCRF_F64, "dtype must be F32 or F64");
+        for (int m = 0; m < nk; ++m) {
+            const dcrf_kernel &k = kernels[m];
+            REQUIRE(std::isfinite(k.theta_pos) && k.theta_pos > 0,
+                    "theta_pos must be > 0");
+            REQUIRE(!k.use_rgb || (std::isfinite(k.theta_rgb) && k.theta_rgb > 0),
+                    "theta_rgb must be > 0 for a colour kernel");
+            REQUIRE(std::isfinite(k.weight) && k.weight >= 0,
+                    "weights must be finite and >= 0");
+        }
+        ctx->has_image = false;
+        ctx->H = H;
+        ctx->W = W;
+        ctx->N = H * W;
+        ctx->nk = nk;
+        ctx->dtype = dtype;
+        ctx->wsum = 0;
+        for (int m = 0; m < nk; ++m) {
+            ctx->kern[m] = kernels[m];
+            ctx->kern[m].use_rgb = kernels[m].use_rgb ? 1 : 0;
+            ctx->wsum += kernels[m].weight;
+        }
+        dcrf::build_lattices(ctx, rgb);
+        ctx->has_image = true;
+        dcrf::compute_row_sums(ctx);
+    });
+}
+
+int dcrf_set_weights(dcrf_ctx *ctx, const double *w, int nk) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        REQUIRE(w != nullptr && nk == ctx->nk, "need one weight per kernel");
+        double s = 0;
+        for (int m = 0; m < nk; ++m) {
+            REQUIRE(std::isfinite(w[m]) && w[m] >= 0, "weights must be >= 0");
+            s += w[m];
+        }
+        for (int m = 0; m < nk; ++m) ctx->kern[m].weight = w[m];
+        ctx->wsum = s;
+        dcrf::compute_row_sums(ctx);
+    });
+}
+
+int dcrf_set_filter_mode(dcrf_ctx *ctx, int mode) {
+    return guarded(ctx, [&] {
+        REQUIRE(mode == DCRF_FILTER_LATTICE || mode == DCRF_FILTER_EXACT,
+                "mode must be DCRF_FILTER_LATTICE or DCRF_FILTER_EXACT");
+        const bool changed = ctx->mode != mode;
+        ctx->mode = mode;
+        if (changed && ctx->has_image) dcrf::compute_row_sums(ctx);
+    });
+}
+
+int dcrf_lattice_info(dcrf_ctx *ctx, int m, int *d, int *nvert) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        REQUIRE(m >= 0 && m < ctx->nk, "kernel index out of range");
+        if (d) *d = ctx->lat[m].d;
+        if (nvert) *nvert = ctx->lat[m].M;
+    });
+}
+
+int dcrf_lattice_export(dcrf_ctx *ctx, int m, int32_t *keys, int32_t *vid,
+                        double *w) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        REQUIRE(m >= 0 && m < ctx->nk, "kernel index out of range");
+        dcrf::lattice_export(ctx, m, keys, vid, w);
+    });
+}
+
+int dcrf_filter(dcrf_ctx *ctx, const void *in, void *out, int C,
+                unsigned flags) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        REQUIRE(in && out && in != out, "in and out must be distinct, non-null");
+        REQUIRE(C >= 1 && C <= 256, "C must be in [1, 256]");
+        REQUIRE((flags & ~(DCRF_ADJOINT | DCRF_EXACT)) == 0, "unknown flags");
+        dcrf::filter_apply(ctx, in, out, C, (flags & DCRF_ADJOINT) != 0,
+                           (flags & DCRF_EXACT) != 0);
+    });
+}
+
+int dcrf_qp_apply(dcrf_ctx *ctx, const void *y, const void *mu, int L,
+                  void *out) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        check_labels(L);
+        REQUIRE(y && mu && out && y != out, "null or aliased argument");
+        dcrf::qp_apply(ctx, y, mu, L, out);
+    });
+}
+
+int dcrf_qp_frank_wolfe(dcrf_ctx *ctx, const void *unary, const void *mu,
+                        int L, void *y_inout, int iters,
+                        dcrf_iter_trace *trace) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        check_labels(L);
+        REQUIRE(unary && mu && y_inout, "null argument");
+        REQUIRE(iters >= 0, "iters must be >= 0");
+        dcrf::frank_wolfe(ctx, unary, mu, L, y_inout, iters, trace, nullptr,
+                          false);
+    });
+}
+
+int dcrf_dc_gen(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
+                void *y_inout, int outer, int inner, double *S_hist) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        check_labels(L);
+        REQUIRE(unary && mu && y_inout, "null argument");
+        REQUIRE(outer >= 0 && inner >= 1, "outer >= 0 and inner >= 1 required");
+        dcrf::dc_gen(ctx, unary, mu, L, y_inout, outer, inner, S_hist);
+    });
+}
+
+int dcrf_round(dcrf_ctx *ctx, const void *y, int L, int32_t *labels) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        check_labels(L);
+        REQUIRE(y && labels, "null argument");
+        dcrf::round_labels(ctx, y, L, labels);
+    });
+}
+
+int dcrf_energy(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
+                const int32_t *labels, double *energy) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        check_labels(L);
+        REQUIRE(unary && mu && labels && energy, "null argument");
+        *energy = dcrf::energy(ctx, unary, mu, L, labels);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,504 @@
+// Device construction of the permutohedral lattices of an image.
+//
+// The paper computes every pairwise message with the filter of Adams et al.
+// (Sec. 3 "Filter-based Method", App. A) and gives no details of it. The
+// lattice built here: each pixel's feature vector f (dimension d) is mapped
+// onto the hyperplane sum(x) = 0 of R^{d+1} by an orthonormal basis scaled by
+// s = (d+1) sqrt(2/3); the simplex of the lattice (d+1)A*_d that contains the
+// point is found from the nearest remainder-0 point (round every coordinate
+// to a multiple of d+1, then fix the coordinate sum by moving the coordinates
+// that were rounded the farthest); its d+1 vertices and barycentric weights
+// are stored per pixel. Vertices with weight 0 are not created, so the vertex
+// set does not depend on how exact ties between coordinates are broken.
+//
+// The coordinates are computed in FP64 without contraction of multiply-adds
+// (this file is compiled with -ffp-contract=off): which vertices exist is a
+// discrete decision, and it has to be the same decision a plain IEEE
+// evaluation of the same formulas takes.
+//
+// Vertices live in an open-addressing hash table of packed 64-bit keys
+// (remainder in 3 bits, the first d coordinates divided by d+1 in the rest),
+// filled with atomicCAS. Occupied slots are compacted into dense vertex ids
+// by a block scan, and a neighbour table stores, for each vertex and blur
+// direction u_j = (d+1) e_j - 1, the ids of v + u_j and v - u_j.
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "dcrf_internal.h"
+
+namespace dcrf {
+namespace {
+
+constexpr uint64_t kEmpty = ~0ull;
+constexpr int kFlagRange = 1;
+constexpr int kFlagCapacity = 2;
+
+template <int D>
+struct Codec {
+    static constexpr int kBits = (64 - 3) / D;
+    static constexpr long long kBias = 1ll << (kBits - 1);
+    static constexpr unsigned long long kMask = (1ull << kBits) - 1;
+
+    // coords: the first D coordinates of a vertex, all congruent to rem
+    __device__ static bool encode(const int (&coord)[D], int rem,
+                                  uint64_t &key) {
+        uint64_t k = uint64_t(rem);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            long long q = (long long)(coord[i] - rem) / (D + 1) + kBias;
+            if (q < 0 || q > (long long)kMask) return false;
+            k |= uint64_t(q) << (3 + kBits * i);
+        }
+        key = k;
+        return true;
+    }
+    __device__ static void decode(uint64_t key, int (&coord)[D], int &rem) {
+        rem = int(key & 7u);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            long long q = (long long)((key >> (3 + kBits * i)) & kMask) - kBias;
+            coord[i] = int(q * (D + 1) + rem);
+        }
+    }
+};
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z ^= z >> 30;
+    z *= 0xbf58476d1ce4e5b9ull;
+    z ^= z >> 27;
+    z *= 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    return z;
+}
+
+// Elevation matrix (d+1 x d), scaled, passed by value.
+template <int D>
+struct Elev {
+    double e[D + 1][D];
+};
+
+template <int D>
+Elev<D> make_elevation() {
+    Elev<D> E;
+    const double s = double(D + 1) * std::sqrt(2.0 / 3.0);
+    for (int j = 0; j < D; ++j) {
+        const double cj = s / std::sqrt(double((j + 1) * (j + 2)));
+        for (int i = 0; i <= D; ++i)
+            E.e[i][j] = (i <= j) ? cj : (i == j + 1 ? -double(j + 1) * cj : 0.0);
+    }
+    return E;
+}
+
+// rank[i]: position of coordinate i in descending order of delta, equal
+// values ordered by lower index first
+template <int D>
+__device__ __forceinline__ void ranks(const double (&delta)[D + 1],
+                                      int (&rank)[D + 1]) {
+#pragma unroll
+    for (int i = 0; i <= D; ++i) {
+        int r = 0;
+#pragma unroll
+        for (int j = 0; j <= D; ++j)
+            r += (delta[j] > delta[i] || (delta[j] == delta[i] && j < i)) ? 1 : 0;
+        rank[i] = r;
+    }
+}
+
+// One thread per pixel: features -> elevated point -> enclosing simplex ->
+// insert the vertices with positive weight into the hash table.
+template <int D, typename T>
+__global__ void __launch_bounds__(256)
+k_lattice_points(int N, int W, const float *__restrict__ rgb, double theta_pos,
+                 double theta_rgb, Elev<D> E, uint64_t *__restrict__ hkeys,
+                 uint64_t capmask, uint32_t *__restrict__ pix_slot,
+                 T *__restrict__ pix_w, int *__restrict__ flags) {
+#pragma clang fp contract(off)
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= N) return;
+    constexpr int D1 = D + 1;
+    const int row = a / W;
+    const int col = a - row * W;
+    double f[D];
+    f[0] = double(col) / theta_pos;
+    f[1] = double(row) / theta_pos;
+    if constexpr (D == 5) {
+        f[2] = double(rgb[3 * (size_t)a + 0]) / theta_rgb;
+        f[3] = double(rgb[3 * (size_t)a + 1]) / theta_rgb;
+        f[4] = double(rgb[3 * (size_t)a + 2]) / theta_rgb;
+    }
+    double x[D1];
+#pragma unroll
+    for (int i = 0; i < D1; ++i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) acc += E.e[i][j] * f[j];
+        x[i] = acc;
+    }
+    // coordinates that are not finite or too large for the integer vertex
+    // coordinates (non-finite colours, a tiny theta) are reported, not used
+    bool finite = true;
+#pragma unroll
+    for (int i = 0; i < D1; ++i) finite = finite && (fabs(x[i]) < 1.0e9);
+    if (!finite) {
+        atomicOr(flags, kFlagRange);
+#pragma unroll
+        for (int k = 0; k < D1; ++k) {
+            pix_w[(size_t)a * D1 + k] = T(0);
+            pix_slot[(size_t)a * D1 + k] = 0xffffffffu;
+        }
+        return;
+    }
+    double c[D1], delta[D1];
+    int rank[D1];
+    int sum = 0;
+#pragma unroll
+    for (int i = 0; i < D1; ++i) {
+        c[i] = double(D1) * floor(x[i] / double(D1) + 0.5);
+        sum += int(llrint(c[i])) / D1;
+    }
+#pragma unroll
+    for (int i = 0; i < D1; ++i) delta[i] = x[i] - c[i];
+    ranks<D>(delta, rank);
+    if (sum != 0) {
+#pragma unroll
+        for (int i = 0; i < D1; ++i) {
+            if (sum > 0 && rank[i] >= D1 - sum) c[i] -= double(D1);
+            if (sum < 0 && rank[i] < -sum) c[i] += double(D1);
+        }
+#pragma unroll
+        for (int i = 0; i < D1; ++i) delta[i] = x[i] - c[i];
+        ranks<D>(delta, rank);
+    }
+    // sorted offsets y_0 >= ... >= y_D, selected without dynamic indexing
+    double y[D1];
+#pragma unroll
+    for (int p = 0; p < D1; ++p) {
+        double v = 0.0;
+#pragma unroll
+        for (int i = 0; i < D1; ++i) v = (rank[i] == p) ? delta[i] : v;
+        y[p] = v;
+    }
+    double b[D1];
+    b[0] = 1.0 - (y[0] - y[D]) / double(D1);
+#pragma unroll
+    for (int p = 0; p < D; ++p) b[D - p] = (y[p] - y[p + 1]) / double(D1);
+
+    int ci[D1];
+#pragma unroll
+    for (int i = 0; i < D1; ++i) ci[i] = int(llrint(c[i]));
+
+#pragma unroll
+    for (int k = 0; k < D1; ++k) {
+        const size_t e = (size_t)a * D1 + k;
+        pix_w[e] = T(b[k] > 0.0 ? b[k] : 0.0);
+        uint32_t slot = 0xffffffffu;
+        if (b[k] > 0.0) {
+            int coord[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+                coord[i] = ci[i] + k - (rank[i] > D - k ? D1 : 0);
+            uint64_t key;
+            if (!Codec<D>::encode(coord, k, key)) {
+                atomicOr(flags, kFlagRange);
+            } else {
+                uint64_t h = mix64(key) & capmask;
+                uint64_t probe = 0;
+                for (; probe <= capmask; ++probe) {
+                    unsigned long long prev = atomicCAS(
+                        (unsigned long long *)&hkeys[h],
+                        (unsigned long long)kEmpty, (unsigned long long)key);
+                    if (prev == kEmpty || prev == key) break;
+                    h = (h + 1) & capmask;
+                }
+                if (probe > capmask)
+                    atomicOr(flags, kFlagCapacity);
+                else
+                    slot = uint32_t(h);
+            }
+        }
+        pix_slot[e] = slot;
+    }
+}
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// exclusive scan of one int per thread within a block of kScanThreads
+__device__ int block_exclusive_scan(int v, int *lds, int &total) {
+    const int t = threadIdx.x;
+    lds[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        int add = (t >= off) ? lds[t - off] : 0;
+        __syncthreads();
+        lds[t] += add;
+        __syncthreads();
+    }
+    total = lds[kScanThreads - 1];
+    int incl = lds[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+k_count_occupied(const uint64_t *__restrict__ hkeys, size_t cap,
+                 int *__restrict__ tile_counts) {
+    __shared__ int lds[kScanThreads];
+    size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
+    int cnt = 0;
+    for (int i = 0; i < kScanItems; ++i)
+        if (base + i < cap && hkeys[base + i] != kEmpty) ++cnt;
+    int total;
+    block_exclusive_scan(cnt, lds, total);
+    if (threadIdx.x == 0) tile_counts[blockIdx.x] = total;
+}
+
+// single block: exclusive scan of the tile counts, total written at [ntiles]
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_tiles(int *__restrict__ tile_counts, int ntiles) {
+    __shared__ int lds[kScanThreads];
+    int carry = 0;
+    for (int base = 0; base < ntiles; base += kScanThreads) {
+        int i = base + threadIdx.x;
+        int v = i < ntiles ? tile_counts[i] : 0;
+        int total;
+        int ex = block_exclusive_scan(v, lds, total);
+        if (i < ntiles) tile_counts[i] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) tile_counts[ntiles] = carry;
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+k_assign_ids(const uint64_t *__restrict__ hkeys, size_t cap,
+             const int *__restrict__ tile_offsets, int *__restrict__ slot_vid,
+             uint64_t *__restrict__ vkeys) {
+    __shared__ int lds[kScanThreads];
+    size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
+    int cnt = 0;
+    for (int i = 0; i < kScanItems; ++i)
+        if (base + i < cap && hkeys[base + i] != kEmpty) ++cnt;
+    int total;
+    int id = tile_offsets[blockIdx.x] + block_exclusive_scan(cnt, lds, total);
+    for (int i = 0; i < kScanItems; ++i) {
+        size_t s = base + i;
+        if (s < cap) {
+            uint64_t k = hkeys[s];
+            if (k != kEmpty) {
+                slot_vid[s] = id;
+                vkeys[id] = k;
+                ++id;
+            } else {
+                slot_vid[s] = -1;
+            }
+        }
+    }
+}
+
+__global__ void k_pixel_ids(size_t count, const uint32_t *__restrict__ pix_slot,
+                            const int *__restrict__ slot_vid,
+                            int *__restrict__ pix_vid) {
+    size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    uint32_t s = pix_slot[e];
+    pix_vid[e] = (s == 0xffffffffu) ? -1 : slot_vid[s];
+}
+
+template <int D>
+__device__ int hash_lookup(const uint64_t *__restrict__ hkeys, uint64_t capmask,
+                           const int *__restrict__ slot_vid, uint64_t key) {
+    uint64_t h = mix64(key) & capmask;
+    for (uint64_t probe = 0; probe <= capmask; ++probe) {
+        uint64_t k = hkeys[h];
+        if (k == key) return slot_vid[h];
+        if (k == kEmpty) return -1;
+        h = (h + 1) & capmask;
+    }
+    return -1;
+}
+
+template <int D>
+__global__ void __launch_bounds__(256)
+k_neighbours(int M, const uint64_t *__restrict__ vkeys,
+             const uint64_t *__restrict__ hkeys, uint64_t capmask,
+             const int *__restrict__ slot_vid, int *__restrict__ nbr) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= M) return;
+    constexpr int D1 = D + 1;
+    int coord[D], rem;
+    Codec<D>::decode(vkeys[v], coord, rem);
+#pragma unroll
+    for (int j = 0; j < D1; ++j) {
+#pragma unroll
+        for (int sgn = 0; sgn < 2; ++sgn) {
+            const int s = sgn == 0 ? 1 : -1;
+            int cn[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) cn[i] = coord[i] + s * (i == j ? D : -1);
+            const int rn = (rem - s + D1) % D1;
+            uint64_t key;
+            int id = -1;
+            if (Codec<D>::encode(cn, rn, key))
+                id = hash_lookup<D>(hkeys, capmask, slot_vid, key);
+            nbr[((size_t)j * M + v) * 2 + sgn] = id;
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_features(int N, int W, const float *__restrict__ rgb,
+                           int use_rgb, double theta_pos, double theta_rgb,
+                           T *__restrict__ feat) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= N) return;
+    const int row = a / W;
+    const int col = a - row * W;
+    const int d = use_rgb ? 5 : 2;
+    T *f = feat + (size_t)a * d;
+    f[0] = T(double(col) / theta_pos);
+    f[1] = T(double(row) / theta_pos);
+    if (use_rgb) {
+        for (int c = 0; c < 3; ++c)
+            f[2 + c] = T(double(rgb[3 * (size_t)a + c]) / theta_rgb);
+    }
+}
+
+template <int D, typename T>
+void build_one(dcrf_ctx *ctx, int m, const float *rgb, int *flags_dev) {
+    Lattice &L = ctx->lat[m];
+    const dcrf_kernel &k = ctx->kern[m];
+    const hipStream_t s = ctx->stream;
+    const int N = ctx->N;
+    constexpr int D1 = D + 1;
+    L.d = D;
+    L.gamma = std::pow(4.0 * M_PI / 3.0, 0.5 * D) * std::sqrt(double(D1));
+    size_t cap = 1024;
+    while (cap < 2 * (size_t)N * D1) cap <<= 1;
+    L.cap = cap;
+    L.hkeys.ensure(cap * 8, s);
+    L.slot_vid.ensure(cap * 4, s);
+    L.pix_slot.ensure((size_t)N * D1 * 4, s);
+    L.pix_vid.ensure((size_t)N * D1 * 4, s);
+    L.pix_w.ensure((size_t)N * D1 * sizeof(T), s);
+    DCRF_TRY_HIP(hipMemsetAsync(L.hkeys.p, 0xff, cap * 8, s));
+
+    hipLaunchKernelGGL((k_lattice_points<D, T>), dim3(ceil_div(N, 256)),
+                       dim3(256), 0, s, N, ctx->W, rgb, k.theta_pos,
+                       k.theta_rgb, make_elevation<D>(), L.hkeys.as<uint64_t>(),
+                       uint64_t(cap - 1), L.pix_slot.as<uint32_t>(),
+                       L.pix_w.as<T>(), flags_dev);
+    DCRF_CHECK_LAUNCH();
+
+    // the caller sized the scratch for the largest lattice (see build_all)
+    const int ntiles = ceil_div((long long)cap, kScanTile);
+    int *tiles = reinterpret_cast<int *>(ctx->scratch.as<char>() + 64);
+    hipLaunchKernelGGL(k_count_occupied, dim3(ntiles), dim3(kScanThreads), 0,
+                       s, L.hkeys.as<uint64_t>(), cap, tiles);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, tiles,
+                       ntiles);
+    int M = 0;
+    DCRF_TRY_HIP(hipMemcpyAsync(&M, tiles + ntiles, 4, hipMemcpyDeviceToHost, s));
+    DCRF_TRY_HIP(hipStreamSynchronize(s));
+    L.M = M;
+    L.vkeys.ensure((size_t)(M > 0 ? M : 1) * 8, s);
+    hipLaunchKernelGGL(k_assign_ids, dim3(ntiles), dim3(kScanThreads), 0, s,
+                       L.hkeys.as<uint64_t>(), cap, tiles,
+                       L.slot_vid.as<int>(), L.vkeys.as<uint64_t>());
+    const size_t cnt = (size_t)N * D1;
+    hipLaunchKernelGGL(k_pixel_ids, dim3(ceil_div((long long)cnt, 256)),
+                       dim3(256), 0, s, cnt, L.pix_slot.as<uint32_t>(),
+                       L.slot_vid.as<int>(), L.pix_vid.as<int>());
+    L.nbr.ensure((size_t)D1 * (M > 0 ? M : 1) * 2 * 4, s);
+    if (M > 0)
+        hipLaunchKernelGGL((k_neighbours<D>), dim3(ceil_div(M, 256)), dim3(256),
+                           0, s, M, L.vkeys.as<uint64_t>(),
+                           L.hkeys.as<uint64_t>(), uint64_t(cap - 1),
+                           L.slot_vid.as<int>(), L.nbr.as<int>());
+    L.feat.ensure((size_t)N * D * sizeof(T), s);
+    hipLaunchKernelGGL((k_features<T>), dim3(ceil_div(N, 256)), dim3(256), 0,
+                       s, N, ctx->W, rgb, k.use_rgb, k.theta_pos, k.theta_rgb,
+                       L.feat.as<T>());
+    DCRF_CHECK_LAUNCH();
+}
+
+template <typename T>
+void build_all(dcrf_ctx *ctx, const float *rgb) {
+    const hipStream_t s = ctx->stream;
+    // scratch: 64 bytes of flags, then the tile counts of the compaction scan
+    // of the largest hash table; sized once so no pointer into it goes stale
+    size_t maxcap = 1024;
+    for (int m = 0; m < ctx->nk; ++m) {
+        const int D1 = (ctx->kern[m].use_rgb ? 5 : 2) + 1;
+        size_t cap = 1024;
+        while (cap < 2 * (size_t)ctx->N * D1) cap <<= 1;
+        maxcap = std::max(maxcap, cap);
+    }
+    ctx->scratch.ensure(64 + (size_t)(ceil_div((long long)maxcap, kScanTile) + 1) * 4,
+                        s);
+    int *flags = ctx->scratch.as<int>();
+    DCRF_TRY_HIP(hipMemsetAsync(flags, 0, 4, s));
+    for (int m = 0; m < ctx->nk; ++m) {
+        if (ctx->kern[m].use_rgb)
+            build_one<5, T>(ctx, m, rgb, flags);
+        else
+            build_one<2, T>(ctx, m, rgb, flags);
+    }
+    int hflags = 0;
+    DCRF_TRY_HIP(hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, s));
+    DCRF_TRY_HIP(hipStreamSynchronize(s));
+    if (hflags & kFlagRange)
+        fail(DCRF_ERANGE,
+             "lattice coordinates exceed the 64-bit vertex key range "
+             "(theta too small for the image extent)");
+    if (hflags & kFlagCapacity) fail(DCRF_ECAPACITY, "lattice hash table full");
+}
+
+}  // namespace
+
+void build_lattices(dcrf_ctx *ctx, const float *rgb) {
+    if (ctx->dtype == DCRF_F64)
+        build_all<double>(ctx, rgb);
+    else
+        build_all<float>(ctx, rgb);
+}
+
+void lattice_export(dcrf_ctx *ctx, int m, int32_t *keys, int32_t *vid,
+                    double *w) {
+    Lattice &L = ctx->lat[m];
+    const hipStream_t s = ctx->stream;
+    const int D = L.d, D1 = L.d + 1;
+    const size_t cnt = (size_t)ctx->N * D1;
+    DCRF_TRY_HIP(hipStreamSynchronize(s));
+    if (keys) {
+        std::vector<uint64_t> k(L.M);
+        DCRF_TRY_HIP(hipMemcpy(k.data(), L.vkeys.p, (size_t)L.M * 8,
+                               hipMemcpyDeviceToHost));
+        const int bits = (64 - 3) / D;
+        const long long bias = 1ll << (bits - 1);
+        const unsigned long long mask = (1ull << bits) - 1;
+        for (int v = 0; v < L.M; ++v) {
+            const int rem = int(k[v] & 7u);
+            for (int i = 0; i < D; ++i) {
+                long long q = (long long)((k[v] >> (3 + bits * i)) & mask) - bias;
+                keys[(size_t)v * D + i] = int32_t(q * D1 + rem);
+            }
+        }
+    }
+    if (vid)
+        DCRF_TRY_HIP(hipMemcpy(vid, L.pix_vid.p, cnt * 4, hipMemcpyDeviceToHost));
+    if (w) {
+        if (ctx->dtype == DCRF_F64) {
+            DCRF_TRY_HIP(hipMemcpy(w, L.pix_w.p, cnt * 8, hipMemcpyDeviceToHost));
+        } else {
+            std::vector<float> wf(cnt);
+            DCRF_TRY_HIP(hipMemcpy(wf.data(), L.pix_w.p, cnt * 4,
+                                   hipMemcpyDeviceToHost));
+            for (size_t i = 0; i < cnt; ++i) w[i] = wf[i];
+        }
+    }
+}
+
+}  // namespace dcrf

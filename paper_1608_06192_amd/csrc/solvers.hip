@@ -1,0 +1,743 @@
+// Solvers on top of the pairwise filter.
+//
+// Frank-Wolfe on the convex QP relaxation (Sec. 4, Alg. fw, App. B):
+//   f(y) = c^T y + y^T (Psi + D) y over the product of simplices,
+//   c = phi - d (eq. cvx-qp-min) or, inside CCCP, phi - 2 d * y^k
+//   (eq. cccp-qp), with (Psi y)_a(i) = sum_j mu_ij (K'Y)_a(j) and
+//   d_a(i) = (sum_j |mu_ij|) (K'1)_a (eq. pairwise-matrix, eq. RL-diagonal).
+// One iteration is three kinds of launch, with no host synchronisation:
+//   1. k_fw_lmo: apply the previous step (y <- y + alpha (s - y) and
+//      P_y <- (1 - alpha) P_y + alpha P_s, App. B's recurrence), form the
+//      gradient g = c + 2 P_y (eq. LRQP-grad), take the conditional gradient
+//      s_a = argmin_i g_a(i) (eq. LRQP-lp, lowest label on ties), splat the
+//      one-hot s into the lattices, and reduce <y,P_y>, <s,P_y>, <c,y>,
+//      <c,s>, <g,y>, <g,s> per block;
+//   2. the blur passes;
+//   3. k_fw_slice: slice, apply mu and the diagonal, P_s = (Psi + D) s,
+//      reduce <y,P_s> and <s,P_s>; the last block to finish reduces every
+//      block's partial sums in a fixed order and solves the step size on the
+//      device (App. B, eq. alpha-opt, written with the four products so that
+//      it is exact for a non-symmetric approximate Psi; endpoints when the
+//      quadratic is not convex).
+// Dot products accumulate in FP64.
+
+#include <algorithm>
+#include <vector>
+
+#include "dcrf_internal.h"
+#include "kernels_common.h"
+
+namespace dcrf {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxGrid = 2048;
+constexpr int kP1 = 8;   // partial sums written by k_fw_lmo
+constexpr int kP2 = 2;   // partial sums written by k_fw_slice
+
+// scalar slots in fw_scal (doubles)
+constexpr int kAlpha = 0;
+constexpr int kCounter = 1;   // used as an unsigned int
+
+template <int NV>
+__device__ void block_reduce(double (&v)[NV], double *lds /* NV*kThreads */) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) lds[i * kThreads + t] = v[i];
+    __syncthreads();
+    for (int off = kThreads / 2; off > 0; off >>= 1) {
+        if (t < off)
+#pragma unroll
+            for (int i = 0; i < NV; ++i)
+                lds[i * kThreads + t] += lds[i * kThreads + t + off];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = lds[i * kThreads];
+    __syncthreads();
+}
+
+template <typename T>
+__global__ void k_fill(T *p, size_t n, T v) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_i32(int32_t *p, size_t n, int32_t v) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// mabs[i] = sum_j |mu_ij|
+template <typename T>
+__global__ void k_mu_abs(int L, const T *__restrict__ mu, T *__restrict__ mabs) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L) return;
+    T s = T(0);
+    for (int j = 0; j < L; ++j) s += fabs(mu[(size_t)i * L + j]);
+    mabs[i] = s;
+}
+
+// c = phi - scale * d * z, d_a(i) = mabs_i r_a; z = 1 when y == nullptr
+template <typename T>
+__global__ void k_linear_term(int N, int L, const T *__restrict__ phi,
+                              const T *__restrict__ r, const T *__restrict__ mabs,
+                              const T *__restrict__ y, T scale, T *__restrict__ c) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)N * L) return;
+    const int a = int(e / L);
+    const int i = int(e - (size_t)a * L);
+    const T z = y ? y[e] : T(1);
+    c[e] = phi[e] - scale * mabs[i] * r[a] * z;
+}
+
+// (Psi + D) Y for a dense Y (or its K'Y given in `pre`), whole pixels per block
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_slice_qp(int N, int L, const T *__restrict__ Y, const T *__restrict__ pre,
+           LatSet<T> ls, T wsum, const T *__restrict__ mu,
+           const T *__restrict__ mabs, const T *__restrict__ r,
+           T *__restrict__ out) {
+    __shared__ T sq[kThreads];
+    const int ppb = kThreads / L;
+    const int t = threadIdx.x;
+    const int lp = t / L;
+    const int l = t - lp * L;
+    for (int g = blockIdx.x; (long long)g * ppb < N; g += gridDim.x) {
+        const int a = g * ppb + lp;
+        const bool act = lp < ppb && a < N;
+        const size_t e = (size_t)a * L + l;
+        T yv = T(0);
+        if (act) {
+            yv = Y[e];
+            T q;
+            if (pre) {
+                q = pre[e];
+            } else {
+                q = T(0);
+                for (int m = 0; m < ls.nk; ++m) {
+                    const LatView<T> &Lt = ls.l[m];
+                    const int D1 = Lt.d + 1;
+                    T s = T(0);
+                    for (int k = 0; k < D1; ++k) {
+                        const int id = Lt.vid[(size_t)a * D1 + k];
+                        if (id >= 0)
+                            s += Lt.w[(size_t)a * D1 + k] * Lt.Vf[(size_t)id * L + l];
+                    }
+                    q += Lt.wg * s;
+                }
+                q -= wsum * yv;
+            }
+            sq[t] = q;
+        }
+        __syncthreads();
+        if (act) {
+            T p = T(0);
+            const T *qrow = sq + lp * L;
+            for (int j = 0; j < L; ++j) p += mu[(size_t)l * L + j] * qrow[j];
+            out[e] = p + mabs[l] * r[a] * yv;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+struct FWArgs {
+    int N, L;
+    T *y, *Py;
+    const T *Ps, *c;
+    int32_t *s;
+    const int32_t *sprev;
+    double *scal, *part;
+    int first;
+};
+
+// Step 1 of an iteration (see the file comment).
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_fw_lmo(FWArgs<T> A, LatSet<T> ls) {
+    __shared__ T sg[kThreads];
+    __shared__ int sarg[kThreads];
+    __shared__ double red[kP1 * kThreads];
+    const int L = A.L;
+    const int ppb = kThreads / L;
+    const int t = threadIdx.x;
+    const int lp = t / L;
+    const int l = t - lp * L;
+    const double alpha = A.first ? 0.0 : A.scal[kAlpha];
+    const T al = T(alpha);
+    double acc[kP1];
+#pragma unroll
+    for (int i = 0; i < kP1; ++i) acc[i] = 0.0;
+    int nvt = 0;
+    for (int m = 0; m < ls.nk; ++m) nvt += ls.l[m].d + 1;
+
+    for (int g = blockIdx.x; (long long)g * ppb < A.N; g += gridDim.x) {
+        const int a = g * ppb + lp;
+        const bool act = lp < ppb && a < A.N;
+        const size_t e = (size_t)a * L + l;
+        T yv = T(0), pyv = T(0), cv = T(0), gv = T(0);
+        int sp = -1;
+        if (act) {
+            yv = A.y[e];
+            pyv = A.Py[e];
+            sp = A.sprev[a];
+            if (!A.first) {
+                yv = yv + al * (T(l == sp ? 1 : 0) - yv);
+                pyv = (T(1) - al) * pyv + al * A.Ps[e];
+                A.y[e] = yv;
+                A.Py[e] = pyv;
+            }
+            cv = A.c[e];
+            gv = cv + T(2) * pyv;
+            sg[t] = gv;
+        }
+        __syncthreads();
+        if (act && l == 0) {
+            int best = 0;
+            T bv = sg[t];
+            for (int j = 1; j < L; ++j) {
+                const T v = sg[t + j];
+                if (v < bv) {
+                    bv = v;
+                    best = j;
+                }
+            }
+            sarg[lp] = best;
+            A.s[a] = best;
+            acc[6] += (best != sp) ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        if (act) {
+            const int sl = sarg[lp];
+            acc[0] += double(yv) * double(pyv);
+            acc[2] += double(cv) * double(yv);
+            acc[4] += double(gv) * double(yv);
+            if (l == sl) {
+                acc[1] += double(pyv);
+                acc[3] += double(cv);
+                acc[5] += double(gv);
+            }
+            // splat the one-hot s: lanes of the pixel share its vertices
+            for (int q = l; q < nvt; q += L) {
+                int m = 0, k = q;
+                while (k > ls.l[m].d) {
+                    k -= ls.l[m].d + 1;
+                    ++m;
+                }
+                const LatView<T> &Lt = ls.l[m];
+                const int D1 = Lt.d + 1;
+                const int id = Lt.vid[(size_t)a * D1 + k];
+                if (id >= 0)
+                    atomic_add(&Lt.V0[(size_t)id * L + sl], Lt.w[(size_t)a * D1 + k]);
+            }
+        }
+        __syncthreads();
+    }
+    block_reduce<kP1>(acc, red);
+    if (t < kP1) A.part[(size_t)blockIdx.x * kP1 + t] = acc[t];
+}
+
+template <typename T>
+struct FWSliceArgs {
+    int N, L;
+    const T *y;
+    const int32_t *s;
+    T *Ps;
+    const T *mu, *mabs, *r, *pre;
+    T wsum;
+    double *scal, *part1, *part2;
+    int G1;
+    double *trace;   // 4 doubles per iteration
+    int it;
+};
+
+// Step 3 of an iteration (see the file comment).
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_fw_slice(FWSliceArgs<T> A, LatSet<T> ls) {
+    __shared__ T sq[kThreads];
+    __shared__ double red[kP1 * kThreads];
+    __shared__ bool last;
+    const int L = A.L;
+    const int ppb = kThreads / L;
+    const int t = threadIdx.x;
+    const int lp = t / L;
+    const int l = t - lp * L;
+    double acc[kP2] = {0.0, 0.0};
+    for (int g = blockIdx.x; (long long)g * ppb < A.N; g += gridDim.x) {
+        const int a = g * ppb + lp;
+        const bool act = lp < ppb && a < A.N;
+        const size_t e = (size_t)a * L + l;
+        int sa = 0;
+        if (act) {
+            sa = A.s[a];
+            T q;
+            if (A.pre) {
+                q = A.pre[e];
+            } else {
+                q = T(0);
+                for (int m = 0; m < ls.nk; ++m) {
+                    const LatView<T> &Lt = ls.l[m];
+                    const int D1 = Lt.d + 1;
+                    T sum = T(0);
+                    for (int k = 0; k < D1; ++k) {
+                        const int id = Lt.vid[(size_t)a * D1 + k];
+                        if (id >= 0)
+                            sum += Lt.w[(size_t)a * D1 + k] * Lt.Vf[(size_t)id * L + l];
+                    }
+                    q += Lt.wg * sum;
+                }
+                if (l == sa) q -= A.wsum;
+            }
+            sq[t] = q;
+        }
+        __syncthreads();
+        if (act) {
+            T p = T(0);
+            const T *qrow = sq + lp * L;
+            for (int j = 0; j < L; ++j) p += A.mu[(size_t)l * L + j] * qrow[j];
+            if (l == sa) p += A.mabs[l] * A.r[a];
+            A.Ps[e] = p;
+            acc[0] += double(A.y[e]) * double(p);
+            if (l == sa) acc[1] += double(p);
+        }
+        __syncthreads();
+    }
+    double v[kP2] = {acc[0], acc[1]};
+    block_reduce<kP2>(v, red);
+    if (t < kP2) A.part2[(size_t)blockIdx.x * kP2 + t] = v[t];
+    __threadfence();
+    __syncthreads();
+    if (t == 0) {
+        unsigned int *ctr = reinterpret_cast<unsigned int *>(A.scal + kCounter);
+        unsigned int ticket = atomicAdd(ctr, 1u);
+        last = (ticket == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // last block: fixed-order reduction of every block's partial sums
+    double tot[kP1 + kP2];
+#pragma unroll
+    for (int i = 0; i < kP1 + kP2; ++i) tot[i] = 0.0;
+    for (int b = t; b < A.G1; b += kThreads)
+#pragma unroll
+        for (int i = 0; i < kP1; ++i) tot[i] += A.part1[(size_t)b * kP1 + i];
+    for (int b = t; b < (int)gridDim.x; b += kThreads)
+#pragma unroll
+        for (int i = 0; i < kP2; ++i) tot[kP1 + i] += A.part2[(size_t)b * kP2 + i];
+    __shared__ double red2[(kP1 + kP2) * kThreads];
+    block_reduce<kP1 + kP2>(tot, red2);
+    if (t == 0) {
+        const double Ayy = tot[0], Csy = tot[1], cy = tot[2], cs = tot[3];
+        const double gy = tot[4], gs = tot[5], changed = tot[6];
+        const double Bys = tot[kP1 + 0], Dss = tot[kP1 + 1];
+        const double b1 = cs - cy + Bys + Csy - 2.0 * Ayy;
+        const double a2 = Dss - Bys - Csy + Ayy;
+        double alpha;
+        if (a2 > 0.0)
+            alpha = fmin(fmax(-b1 / (2.0 * a2), 0.0), 1.0);
+        else
+            alpha = (a2 + b1 < 0.0) ? 1.0 : 0.0;
+        A.scal[kAlpha] = alpha;
+        double *tr = A.trace + (size_t)A.it * 4;
+        tr[0] = cy + Ayy;        // f(y_t)
+        tr[1] = gy - gs;         // <g, y_t - s_t>
+        tr[2] = alpha;
+        tr[3] = changed;
+        *reinterpret_cast<unsigned int *>(A.scal + kCounter) = 0u;
+    }
+}
+
+// y <- y + alpha (s - y), P_y <- (1 - alpha) P_y + alpha P_s
+template <typename T>
+__global__ void k_fw_final(int N, int L, T *__restrict__ y, T *__restrict__ Py,
+                           const T *__restrict__ Ps, const int32_t *__restrict__ s,
+                           const double *__restrict__ scal) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)N * L) return;
+    const int a = int(e / L);
+    const int l = int(e - (size_t)a * L);
+    const T al = T(scal[kAlpha]);
+    y[e] = y[e] + al * (T(l == s[a] ? 1 : 0) - y[e]);
+    Py[e] = (T(1) - al) * Py[e] + al * Ps[e];
+}
+
+template <typename T>
+__global__ void k_onehot(int N, int L, const int32_t *__restrict__ s,
+                         T *__restrict__ out) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)N * L) return;
+    const int a = int(e / L);
+    out[e] = T(int(e - (size_t)a * L) == s[a] ? 1 : 0);
+}
+
+__global__ void k_check_labels(int N, int L, const int32_t *__restrict__ x,
+                               int *__restrict__ bad) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < N && (x[a] < 0 || x[a] >= L)) atomicOr(bad, 1);
+}
+
+template <typename T>
+__global__ void k_round(int N, int L, const T *__restrict__ y,
+                        int32_t *__restrict__ labels) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= N) return;
+    int best = 0;
+    T bv = y[(size_t)a * L];
+    for (int j = 1; j < L; ++j) {
+        const T v = y[(size_t)a * L + j];
+        if (v > bv) {
+            bv = v;
+            best = j;
+        }
+    }
+    labels[a] = best;
+}
+
+// per-block partial sums of the energy of labels x (the pairwise part reads
+// the sliced one-hot filter, or its K'S in `pre`)
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_energy(int N, int L, const T *__restrict__ phi, const int32_t *__restrict__ x,
+         const T *__restrict__ pre, LatSet<T> ls, T wsum,
+         const T *__restrict__ mu, double *__restrict__ part) {
+    __shared__ double red[kThreads];
+    const int ppb = kThreads / L;
+    const int t = threadIdx.x;
+    const int lp = t / L;
+    const int l = t - lp * L;
+    double acc[1] = {0.0};
+    for (int g = blockIdx.x; (long long)g * ppb < N; g += gridDim.x) {
+        const int a = g * ppb + lp;
+        if (lp < ppb && a < N) {
+            const size_t e = (size_t)a * L + l;
+            const int xa = x[a];
+            if (xa < 0 || xa >= L) continue;   // rejected by k_check_labels
+            T q;
+            if (pre) {
+                q = pre[e];
+            } else {
+                q = T(0);
+                for (int m = 0; m < ls.nk; ++m) {
+                    const LatView<T> &Lt = ls.l[m];
+                    const int D1 = Lt.d + 1;
+                    T sum = T(0);
+                    for (int k = 0; k < D1; ++k) {
+                        const int id = Lt.vid[(size_t)a * D1 + k];
+                        if (id >= 0)
+                            sum += Lt.w[(size_t)a * D1 + k] * Lt.Vf[(size_t)id * L + l];
+                    }
+                    q += Lt.wg * sum;
+                }
+                if (l == xa) q -= wsum;
+            }
+            acc[0] += double(mu[(size_t)xa * L + l]) * double(q);
+            if (l == xa) acc[0] += double(phi[e]);
+        }
+    }
+    block_reduce<1>(acc, red);
+    if (t == 0) part[blockIdx.x] = acc[0];
+}
+
+// per-block partial sums of S(y) = phi^T y + y^T Psi y with Psi y = P_y - d*y
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_S_value(int N, int L, const T *__restrict__ phi, const T *__restrict__ y,
+          const T *__restrict__ Py, const T *__restrict__ mabs,
+          const T *__restrict__ r, double *__restrict__ part) {
+    __shared__ double red[kThreads];
+    double acc[1] = {0.0};
+    for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < (size_t)N * L;
+         e += (size_t)gridDim.x * kThreads) {
+        const int a = int(e / L);
+        const int i = int(e - (size_t)a * L);
+        const double yv = y[e];
+        acc[0] += double(phi[e]) * yv + yv * double(Py[e]) -
+                  double(mabs[i]) * double(r[a]) * yv * yv;
+    }
+    block_reduce<1>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+}
+
+int grid_for(int N, int L) {
+    const int ppb = kThreads / L;
+    return std::max(1, std::min(kMaxGrid, ceil_div(N, ppb)));
+}
+
+double sum_partials(dcrf_ctx *ctx, const double *dpart, int n) {
+    std::vector<double> h(n);
+    DCRF_TRY_HIP(hipMemcpyAsync(h.data(), dpart, n * sizeof(double),
+                                hipMemcpyDeviceToHost, ctx->stream));
+    DCRF_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += h[i];
+    return s;
+}
+
+template <typename T>
+struct Work {
+    T *c, *Py, *Ps, *mabs, *mu;
+    int32_t *s, *sprev;
+    double *part1, *part2, *scal, *trace;
+};
+
+template <typename T>
+Work<T> fw_workspace(dcrf_ctx *ctx, int L, int iters) {
+    const hipStream_t st = ctx->stream;
+    const size_t NL = (size_t)ctx->N * L;
+    ctx->fw_c.ensure(NL * sizeof(T), st);
+    ctx->fw_Py.ensure(NL * sizeof(T), st);
+    ctx->fw_Ps.ensure(NL * sizeof(T), st);
+    ctx->fw_s.ensure((size_t)ctx->N * 4, st);
+    ctx->fw_sprev.ensure((size_t)ctx->N * 4, st);
+    ctx->fw_part.ensure((size_t)kMaxGrid * (kP1 + kP2) * 8, st);
+    ctx->fw_scal.ensure(64, st);
+    ctx->fw_trace.ensure((size_t)std::max(iters, 1) * 4 * 8, st);
+    ctx->fw_mu.ensure((size_t)L * sizeof(T), st);
+    Work<T> w;
+    w.c = ctx->fw_c.as<T>();
+    w.Py = ctx->fw_Py.as<T>();
+    w.Ps = ctx->fw_Ps.as<T>();
+    w.mabs = ctx->fw_mu.as<T>();
+    w.s = ctx->fw_s.as<int32_t>();
+    w.sprev = ctx->fw_sprev.as<int32_t>();
+    w.part1 = ctx->fw_part.as<double>();
+    w.part2 = w.part1 + (size_t)kMaxGrid * kP1;
+    w.scal = ctx->fw_scal.as<double>();
+    w.trace = ctx->fw_trace.as<double>();
+    return w;
+}
+
+template <typename T>
+void qp_apply_t(dcrf_ctx *ctx, const T *y, const T *mu, int L, const T *mabs,
+                T *out) {
+    const hipStream_t st = ctx->stream;
+    const int N = ctx->N;
+    const T *pre = nullptr;
+    LatSet<T> ls{};
+    if (ctx->mode == DCRF_FILTER_EXACT) {
+        ctx->tmpA.ensure((size_t)N * L * sizeof(T), st);
+        filter_apply(ctx, y, ctx->tmpA.p, L, false, true);
+        pre = ctx->tmpA.as<T>();
+    } else {
+        splat_dense(ctx, y, L);
+        blur_all(ctx, L, false);
+        ls = make_lat_set<T>(ctx, L);
+    }
+    hipLaunchKernelGGL((k_slice_qp<T>), dim3(grid_for(N, L)), dim3(kThreads), 0,
+                       st, N, L, y, pre, ls, T(ctx->wsum), mu, mabs,
+                       ctx->r.as<T>(), out);
+    DCRF_CHECK_LAUNCH();
+}
+
+template <typename T>
+void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
+                   int iters, dcrf_iter_trace *trace, int cmode, bool have_Py) {
+    const hipStream_t st = ctx->stream;
+    const int N = ctx->N;
+    const size_t NL = (size_t)N * L;
+    Work<T> w = fw_workspace<T>(ctx, L, iters);
+    const int gE = ceil_div((long long)NL, 256);
+    hipLaunchKernelGGL((k_mu_abs<T>), dim3(1), dim3(256), 0, st, L, mu, w.mabs);
+    // linear term: c = phi - d (convex QP) or phi - 2 d * y (CCCP step)
+    hipLaunchKernelGGL((k_linear_term<T>), dim3(gE), dim3(256), 0, st, N, L,
+                       phi, ctx->r.as<T>(), w.mabs, cmode == 1 ? y : nullptr,
+                       T(cmode == 1 ? 2 : 1), w.c);
+    if (!have_Py) qp_apply_t<T>(ctx, y, mu, L, w.mabs, w.Py);
+    hipLaunchKernelGGL(k_fill_i32, dim3(ceil_div(N, 256)), dim3(256), 0, st,
+                       w.sprev, (size_t)N, -1);
+    DCRF_TRY_HIP(hipMemsetAsync(w.scal, 0, 64, st));
+    DCRF_CHECK_LAUNCH();
+
+    const bool exact = ctx->mode == DCRF_FILTER_EXACT;
+    if (!exact) ensure_vertex_buffers(ctx, L);
+    if (exact) ctx->tmpA.ensure(NL * sizeof(T), st), ctx->tmpB.ensure(NL * sizeof(T), st);
+    const int G = grid_for(N, L);
+    for (int it = 0; it < iters; ++it) {
+        FWArgs<T> a{N, L, y, w.Py, w.Ps, w.c, w.s, w.sprev, w.scal, w.part1,
+                    it == 0 ? 1 : 0};
+        LatSet<T> ls = exact ? LatSet<T>{} : make_lat_set<T>(ctx, L);
+        hipLaunchKernelGGL((k_fw_lmo<T>), dim3(G), dim3(kThreads), 0, st, a, ls);
+        const T *pre = nullptr;
+        if (exact) {
+            hipLaunchKernelGGL((k_onehot<T>), dim3(gE), dim3(256), 0, st, N, L,
+                               w.s, ctx->tmpB.as<T>());
+            filter_apply(ctx, ctx->tmpB.p, ctx->tmpA.p, L, false, true);
+            pre = ctx->tmpA.as<T>();
+        } else {
+            blur_all(ctx, L, false);
+        }
+        FWSliceArgs<T> b{N, L, y, w.s, w.Ps, mu, w.mabs, ctx->r.as<T>(), pre,
+                         T(ctx->wsum), w.scal, w.part1, w.part2, G, w.trace, it};
+        hipLaunchKernelGGL((k_fw_slice<T>), dim3(G), dim3(kThreads), 0, st, b, ls);
+        DCRF_CHECK_LAUNCH();
+        std::swap(w.s, w.sprev);
+    }
+    // the last conditional gradient is in sprev after the swap
+    if (iters > 0) {
+        hipLaunchKernelGGL((k_fw_final<T>), dim3(gE), dim3(256), 0, st, N, L, y,
+                           w.Py, w.Ps, w.sprev, w.scal);
+        DCRF_CHECK_LAUNCH();
+    }
+    // keep the buffer roles stable for the next call (s / sprev swapped)
+    if (iters % 2 == 1) {
+        void *p = ctx->fw_s.p;
+        ctx->fw_s.p = ctx->fw_sprev.p;
+        ctx->fw_sprev.p = p;
+    }
+    if (trace && iters > 0) {
+        std::vector<double> h((size_t)iters * 4);
+        DCRF_TRY_HIP(hipMemcpyAsync(h.data(), w.trace, h.size() * 8,
+                                    hipMemcpyDeviceToHost, st));
+        DCRF_TRY_HIP(hipStreamSynchronize(st));
+        for (int i = 0; i < iters; ++i)
+            trace[i] = dcrf_iter_trace{h[i * 4 + 0], h[i * 4 + 1], h[i * 4 + 2],
+                                       h[i * 4 + 3]};
+    }
+}
+
+template <typename T>
+double S_value_t(dcrf_ctx *ctx, const T *phi, const T *y, int L) {
+    const int G = std::min(kMaxGrid, ceil_div((long long)ctx->N * L, kThreads));
+    hipLaunchKernelGGL((k_S_value<T>), dim3(G), dim3(kThreads), 0, ctx->stream,
+                       ctx->N, L, phi, y, ctx->fw_Py.as<T>(), ctx->fw_mu.as<T>(),
+                       ctx->r.as<T>(), ctx->fw_part.as<double>());
+    DCRF_CHECK_LAUNCH();
+    return sum_partials(ctx, ctx->fw_part.as<double>(), G);
+}
+
+template <typename T>
+void dc_gen_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y, int outer,
+              int inner, double *S_hist) {
+    // P_y = (Psi + D) y for the starting point
+    Work<T> w = fw_workspace<T>(ctx, L, inner);
+    hipLaunchKernelGGL((k_mu_abs<T>), dim3(1), dim3(256), 0, ctx->stream, L, mu,
+                       w.mabs);
+    qp_apply_t<T>(ctx, y, mu, L, w.mabs, w.Py);
+    if (S_hist) S_hist[0] = S_value_t<T>(ctx, phi, y, L);
+    for (int k = 0; k < outer; ++k) {
+        frank_wolfe_t<T>(ctx, phi, mu, L, y, inner, nullptr, 1, true);
+        if (S_hist) S_hist[k + 1] = S_value_t<T>(ctx, phi, y, L);
+    }
+}
+
+template <typename T>
+double energy_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L,
+                const int32_t *x) {
+    const hipStream_t st = ctx->stream;
+    const int N = ctx->N;
+    {
+        ctx->scratch.ensure(64, st);
+        int *bad = ctx->scratch.as<int>() + 1;
+        DCRF_TRY_HIP(hipMemsetAsync(bad, 0, 4, st));
+        hipLaunchKernelGGL(k_check_labels, dim3(ceil_div(N, 256)), dim3(256), 0,
+                           st, N, L, x, bad);
+        int hbad = 0;
+        DCRF_TRY_HIP(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, st));
+        DCRF_TRY_HIP(hipStreamSynchronize(st));
+        if (hbad) fail(DCRF_EINVAL, "labels must lie in [0, L)");
+    }
+    const T *pre = nullptr;
+    LatSet<T> ls{};
+    if (ctx->mode == DCRF_FILTER_EXACT) {
+        ctx->tmpA.ensure((size_t)N * L * sizeof(T), st);
+        ctx->tmpB.ensure((size_t)N * L * sizeof(T), st);
+        hipLaunchKernelGGL((k_onehot<T>), dim3(ceil_div((long long)N * L, 256)),
+                           dim3(256), 0, st, N, L, x, ctx->tmpB.as<T>());
+        filter_apply(ctx, ctx->tmpB.p, ctx->tmpA.p, L, false, true);
+        pre = ctx->tmpA.as<T>();
+    } else {
+        splat_labels(ctx, x, L);
+        blur_all(ctx, L, false);
+        ls = make_lat_set<T>(ctx, L);
+    }
+    ctx->fw_part.ensure((size_t)kMaxGrid * (kP1 + kP2) * 8, st);
+    const int G = grid_for(N, L);
+    hipLaunchKernelGGL((k_energy<T>), dim3(G), dim3(kThreads), 0, st, N, L, phi,
+                       x, pre, ls, T(ctx->wsum), mu, ctx->fw_part.as<double>());
+    DCRF_CHECK_LAUNCH();
+    return sum_partials(ctx, ctx->fw_part.as<double>(), G);
+}
+
+}  // namespace
+
+void fill_ones(dcrf_ctx *ctx, void *p, size_t n) {
+    if (ctx->dtype == DCRF_F64)
+        hipLaunchKernelGGL((k_fill<double>), dim3(ceil_div((long long)n, 256)),
+                           dim3(256), 0, ctx->stream, static_cast<double *>(p), n,
+                           1.0);
+    else
+        hipLaunchKernelGGL((k_fill<float>), dim3(ceil_div((long long)n, 256)),
+                           dim3(256), 0, ctx->stream, static_cast<float *>(p), n,
+                           1.0f);
+    DCRF_CHECK_LAUNCH();
+}
+
+void qp_apply(dcrf_ctx *ctx, const void *y, const void *mu, int L, void *out) {
+    const hipStream_t st = ctx->stream;
+    ctx->fw_mu.ensure((size_t)L * ctx->elt(), st);
+    if (ctx->dtype == DCRF_F64) {
+        hipLaunchKernelGGL((k_mu_abs<double>), dim3(1), dim3(256), 0, st, L,
+                           static_cast<const double *>(mu), ctx->fw_mu.as<double>());
+        qp_apply_t<double>(ctx, static_cast<const double *>(y),
+                           static_cast<const double *>(mu), L,
+                           ctx->fw_mu.as<double>(), static_cast<double *>(out));
+    } else {
+        hipLaunchKernelGGL((k_mu_abs<float>), dim3(1), dim3(256), 0, st, L,
+                           static_cast<const float *>(mu), ctx->fw_mu.as<float>());
+        qp_apply_t<float>(ctx, static_cast<const float *>(y),
+                          static_cast<const float *>(mu), L,
+                          ctx->fw_mu.as<float>(), static_cast<float *>(out));
+    }
+}
+
+void frank_wolfe(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
+                 void *y, int iters, dcrf_iter_trace *trace, const void *,
+                 bool have_Py) {
+    if (ctx->dtype == DCRF_F64)
+        frank_wolfe_t<double>(ctx, static_cast<const double *>(unary),
+                              static_cast<const double *>(mu), L,
+                              static_cast<double *>(y), iters, trace, 0, have_Py);
+    else
+        frank_wolfe_t<float>(ctx, static_cast<const float *>(unary),
+                             static_cast<const float *>(mu), L,
+                             static_cast<float *>(y), iters, trace, 0, have_Py);
+}
+
+void dc_gen(dcrf_ctx *ctx, const void *unary, const void *mu, int L, void *y,
+            int outer, int inner, double *S_hist) {
+    if (ctx->dtype == DCRF_F64)
+        dc_gen_t<double>(ctx, static_cast<const double *>(unary),
+                         static_cast<const double *>(mu), L,
+                         static_cast<double *>(y), outer, inner, S_hist);
+    else
+        dc_gen_t<float>(ctx, static_cast<const float *>(unary),
+                        static_cast<const float *>(mu), L,
+                        static_cast<float *>(y), outer, inner, S_hist);
+}
+
+void round_labels(dcrf_ctx *ctx, const void *y, int L, int32_t *labels) {
+    if (ctx->dtype == DCRF_F64)
+        hipLaunchKernelGGL((k_round<double>), dim3(ceil_div(ctx->N, 256)),
+                           dim3(256), 0, ctx->stream, ctx->N, L,
+                           static_cast<const double *>(y), labels);
+    else
+        hipLaunchKernelGGL((k_round<float>), dim3(ceil_div(ctx->N, 256)),
+                           dim3(256), 0, ctx->stream, ctx->N, L,
+                           static_cast<const float *>(y), labels);
+    DCRF_CHECK_LAUNCH();
+}
+
+double energy(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
+              const int32_t *labels) {
+    if (ctx->dtype == DCRF_F64)
+        return energy_t<double>(ctx, static_cast<const double *>(unary),
+                                static_cast<const double *>(mu), L, labels);
+    return energy_t<float>(ctx, static_cast<const float *>(unary),
+                           static_cast<const float *>(mu), L, labels);
+}
+
+}  // namespace dcrf

@@ -1,0 +1,222 @@
+"""Python binding of the HIP library ``libdcrf.so`` (C ABI in include/dcrf.h).
+
+Argument marshalling only: every step runs in the library's kernels. Tensors
+supply device memory; calls are enqueued on torch's current stream. The
+module raises at import when the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdcrf.so")
+
+DCRF_OK = 0
+DCRF_F32, DCRF_F64 = 0, 1
+DCRF_FILTER_LATTICE, DCRF_FILTER_EXACT = 0, 1
+DCRF_ADJOINT, DCRF_EXACT = 1, 2
+
+STATUS = {0: "DCRF_OK", -1: "DCRF_EINVAL", -2: "DCRF_ENOMEM", -3: "DCRF_ERANGE",
+          -4: "DCRF_ECAPACITY", -5: "DCRF_EHIP", -6: "DCRF_EUNSUPPORTED",
+          -7: "DCRF_ESTATE"}
+
+
+class DcrfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class dcrf_kernel(ctypes.Structure):
+    _fields_ = [("use_rgb", ctypes.c_int), ("theta_pos", ctypes.c_double),
+                ("theta_rgb", ctypes.c_double), ("weight", ctypes.c_double)]
+
+
+class dcrf_iter_trace(ctypes.Structure):
+    _fields_ = [("objective", ctypes.c_double), ("gap", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("changed", ctypes.c_double)]
+
+
+# name -> (restype, argtypes); mirrors include/dcrf.h
+_P, _I, _U, _D = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint, ctypes.c_double
+_PD = ctypes.POINTER(ctypes.c_double)
+PROTOTYPES = {
+    "dcrf_create": (_I, [ctypes.POINTER(_P), _I, _P]),
+    "dcrf_destroy": (_I, [_P]),
+    "dcrf_last_error": (ctypes.c_char_p, [_P]),
+    "dcrf_set_stream": (_I, [_P, _P]),
+    "dcrf_version": (ctypes.c_char_p, []),
+    "dcrf_set_image": (_I, [_P, _I, _I, _P, ctypes.POINTER(dcrf_kernel), _I, _I]),
+    "dcrf_set_weights": (_I, [_P, _PD, _I]),
+    "dcrf_set_filter_mode": (_I, [_P, _I]),
+    "dcrf_lattice_info": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "dcrf_lattice_export": (_I, [_P, _I, _P, _P, _P]),
+    "dcrf_filter": (_I, [_P, _P, _P, _I, _U]),
+    "dcrf_qp_apply": (_I, [_P, _P, _P, _I, _P]),
+    "dcrf_qp_frank_wolfe": (_I, [_P, _P, _P, _I, _P, _I,
+                                 ctypes.POINTER(dcrf_iter_trace)]),
+    "dcrf_dc_gen": (_I, [_P, _P, _P, _I, _P, _I, _I, _PD]),
+    "dcrf_round": (_I, [_P, _P, _I, _P]),
+    "dcrf_energy": (_I, [_P, _P, _P, _I, _P, _PD]),
+}
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build it with `python __graft_entry__.py` "
+            "(hipcc --offload-arch=gfx950); there is no fallback path")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in PROTOTYPES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = load_library()
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _kernels(kernels):
+    arr = (dcrf_kernel * len(kernels))()
+    for i, k in enumerate(kernels):
+        if isinstance(k, dict):
+            k = (k["use_rgb"], k["theta_pos"], k.get("theta_rgb", 0.0),
+                 k["weight"])
+        arr[i] = dcrf_kernel(int(k[0]), float(k[1]), float(k[2]), float(k[3]))
+    return arr
+
+
+class Context:
+    """One image's lattices and solver workspace on one device."""
+
+    def __init__(self, device: int = 0):
+        self.device = torch.device("cuda", device)
+        self._h = ctypes.c_void_p()
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        self._check(_lib.dcrf_create(ctypes.byref(self._h), device,
+                                     ctypes.c_void_p(st)), create=True)
+        self.dtype = None
+        self.N = 0
+        self.nk = 0
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.dcrf_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def _check(self, status: int, create: bool = False):
+        if status != DCRF_OK:
+            msg = _lib.dcrf_last_error(None if create else self._h)
+            raise DcrfError(status, (msg or b"").decode())
+
+    def _stream(self):
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        self._check(_lib.dcrf_set_stream(self._h, ctypes.c_void_p(st)))
+
+    def _arg(self, t: torch.Tensor, dtype=None, name="argument"):
+        dtype = dtype or self.dtype
+        if t.device != self.device or t.dtype != dtype or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {dtype} tensor on "
+                             f"{self.device}")
+        return _ptr(t)
+
+    # -- image -----------------------------------------------------------
+    def set_image(self, H: int, W: int, rgb: torch.Tensor, kernels,
+                  dtype=torch.float32):
+        self._stream()
+        code = {torch.float32: DCRF_F32, torch.float64: DCRF_F64}[dtype]
+        ks = _kernels(kernels)
+        self._check(_lib.dcrf_set_image(
+            self._h, H, W, self._arg(rgb, torch.float32, "rgb"), ks, len(ks),
+            code))
+        self.dtype, self.N, self.nk, self.H, self.W = dtype, H * W, len(ks), H, W
+
+    def set_weights(self, w):
+        arr = (ctypes.c_double * len(w))(*[float(v) for v in w])
+        self._stream()
+        self._check(_lib.dcrf_set_weights(self._h, arr, len(w)))
+
+    def set_filter_mode(self, mode: str):
+        self._stream()
+        m = {"lattice": DCRF_FILTER_LATTICE, "exact": DCRF_FILTER_EXACT}[mode]
+        self._check(_lib.dcrf_set_filter_mode(self._h, m))
+
+    def lattice_info(self, m: int):
+        d, M = ctypes.c_int(), ctypes.c_int()
+        self._check(_lib.dcrf_lattice_info(self._h, m, ctypes.byref(d),
+                                           ctypes.byref(M)))
+        return d.value, M.value
+
+    def lattice_export(self, m: int):
+        import numpy as np
+        d, M = self.lattice_info(m)
+        keys = np.empty((M, d), np.int32)
+        vid = np.empty((self.N, d + 1), np.int32)
+        w = np.empty((self.N, d + 1), np.float64)
+        self._check(_lib.dcrf_lattice_export(
+            self._h, m, keys.ctypes.data_as(_P), vid.ctypes.data_as(_P),
+            w.ctypes.data_as(_P)))
+        return keys, vid, w
+
+    # -- filter ----------------------------------------------------------
+    def filter(self, x: torch.Tensor, adjoint=False, exact=False,
+               out: torch.Tensor | None = None) -> torch.Tensor:
+        C = x.shape[1] if x.dim() == 2 else 1
+        if out is None:
+            out = torch.empty_like(x)
+        flags = (DCRF_ADJOINT if adjoint else 0) | (DCRF_EXACT if exact else 0)
+        self._stream()
+        self._check(_lib.dcrf_filter(self._h, self._arg(x, name="in"),
+                                     self._arg(out, name="out"), C, flags))
+        return out
+
+    def qp_apply(self, y: torch.Tensor, mu: torch.Tensor,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+        out = torch.empty_like(y) if out is None else out
+        self._stream()
+        self._check(_lib.dcrf_qp_apply(self._h, self._arg(y), self._arg(mu),
+                                       y.shape[1], self._arg(out)))
+        return out
+
+    # -- solvers ---------------------------------------------------------
+    def qp_frank_wolfe(self, unary, mu, y, iters: int, trace: bool = True):
+        tr = (dcrf_iter_trace * max(iters, 1))() if trace else None
+        self._stream()
+        self._check(_lib.dcrf_qp_frank_wolfe(
+            self._h, self._arg(unary, name="unary"), self._arg(mu, name="mu"),
+            unary.shape[1], self._arg(y, name="y"), iters, tr))
+        if not trace:
+            return None
+        return [(t.objective, t.gap, t.alpha, t.changed) for t in tr[:iters]]
+
+    def dc_gen(self, unary, mu, y, outer: int, inner: int):
+        hist = (ctypes.c_double * (outer + 1))()
+        self._stream()
+        self._check(_lib.dcrf_dc_gen(
+            self._h, self._arg(unary), self._arg(mu), unary.shape[1],
+            self._arg(y), outer, inner, hist))
+        return list(hist)
+
+    def round(self, y: torch.Tensor) -> torch.Tensor:
+        lab = torch.empty(y.shape[0], dtype=torch.int32, device=self.device)
+        self._stream()
+        self._check(_lib.dcrf_round(self._h, self._arg(y), y.shape[1],
+                                    _ptr(lab)))
+        return lab
+
+    def energy(self, unary, mu, labels: torch.Tensor) -> float:
+        e = ctypes.c_double()
+        self._stream()
+        self._check(_lib.dcrf_energy(
+            self._h, self._arg(unary), self._arg(mu), unary.shape[1],
+            self._arg(labels, torch.int32, "labels"), ctypes.byref(e)))
+        return e.value

@@ -1,0 +1,234 @@
+"""GPU parity: the HIP library against the FP64 oracle, through the C ABI.
+
+Tolerances (written next to each check):
+* lattice vertex sets and per-pixel vertex keys: bit-exact; weights
+  bit-exact in FP64 and equal to the FP64 weight rounded once in FP32;
+* filter outputs: |gpu - oracle| <= rtol * (K~|Y| + wsum |Y|) elementwise, i.e.
+  relative to the magnitude of the summands (rtol 1e-5 in FP32, 1e-11 in FP64);
+* Frank-Wolfe marginals within 1e-4 absolute and objectives within 1e-4
+  relative; energies within 1e-5 relative (FP32) / 1e-10 (FP64).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1608_06192_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+KERNELS = [synth.BILATERAL, synth.SPATIAL]
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def gpu_ctx(im, dtype, kernels=KERNELS, mode="lattice"):
+    from paper_1608_06192_amd import dcrf
+    print(f"[case] {im.H}x{im.W} dtype={dtype} mode={mode}", flush=True)
+    ctx = dcrf.Context(0)
+    ctx.set_image(im.H, im.W, torch.from_numpy(im.rgb).to(dev()), kernels,
+                  dtype=dtype)
+    if mode != "lattice":
+        ctx.set_filter_mode(mode)
+    return ctx
+
+
+def T(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev(), dtype)
+
+
+def key_table(keys, vid, w):
+    """per pixel: sorted list of (vertex key, weight) with weight > 0"""
+    out = []
+    for a in range(vid.shape[0]):
+        out.append(sorted((tuple(keys[v]), float(w[a, k]))
+                          for k, v in enumerate(vid[a]) if v >= 0))
+    return out
+
+
+def filter_bound(model, Y, rtol):
+    Ya = np.abs(Y)
+    return rtol * (model.Kp(Ya) + 2 * model.w.sum() * Ya) + 1e-300
+
+
+@pytest.mark.parametrize("name,dtype", [("rect_32x24_L3", torch.float64),
+                                        ("voronoi_320x213_L21", torch.float32)])
+def test_vertex_sets_match_oracle(name, dtype):
+    im = synth.make(name)
+    ctx = gpu_ctx(im, dtype)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    for m, lat in enumerate(model.lattices):
+        d, M = ctx.lattice_info(m)
+        assert d == lat.d and M == lat.nv
+        gk, gv, gw = ctx.lattice_export(m)
+        ok = lat.keys()
+        assert set(map(tuple, gk)) == set(map(tuple, ok))
+        ov, ow = lat.points()
+        if dtype == torch.float32:
+            ow = ow.astype(np.float32).astype(np.float64)
+        sample = np.arange(0, im.N, max(1, im.N // 4000))
+        gt = key_table(gk, gv[sample], gw[sample])
+        ot = key_table(ok, ov[sample], ow[sample])
+        assert gt == ot
+
+
+@pytest.mark.parametrize("name,dtype,C,rtol", [
+    ("rect_32x24_L3", torch.float64, 3, 1e-11),
+    ("rect_32x24_L3", torch.float64, 1, 1e-11),
+    ("voronoi_320x213_L21", torch.float32, 21, 1e-5),
+    ("voronoi_320x213_L21", torch.float32, 5, 1e-5),
+    ("voronoi_500x375_L21", torch.float32, 21, 1e-5),
+])
+def test_filter_matches_oracle_lattice(name, dtype, C, rtol):
+    im = synth.make(name)
+    ctx = gpu_ctx(im, dtype)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    rng = np.random.default_rng(C)
+    Y = rng.uniform(-1, 1, size=(im.N, C))
+    if dtype == torch.float32:
+        Y = Y.astype(np.float32).astype(np.float64)
+    bound = filter_bound(model, Y, rtol)
+    for adjoint in (False, True):
+        g = ctx.filter(T(Y, dtype), adjoint=adjoint).cpu().numpy()
+        o = model.Kp(Y, reverse=adjoint)
+        assert (np.abs(g - o) <= bound).all(), (adjoint, np.abs(g - o).max())
+
+
+def test_filter_exact_matches_oracle_exact():
+    im = synth.make("rect_32x24_L3")
+    ctx = gpu_ctx(im, torch.float64)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS, mode="exact")
+    Y = np.random.default_rng(1).uniform(-1, 1, size=(im.N, 11))
+    g = ctx.filter(T(Y, torch.float64), exact=True).cpu().numpy()
+    assert np.abs(g - model.Kp(Y)).max() <= 1e-11 * np.abs(model.Kp(np.abs(Y))).max()
+
+
+@pytest.mark.parametrize("H,W", [(1, 1), (1, 2), (3, 5), (7, 1), (17, 13)])
+def test_filter_small_and_ragged_images(H, W):
+    im = synth.voronoi_image(H, W, 4, seed=H * 100 + W, regions=3)
+    ctx = gpu_ctx(im, torch.float64)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    Y = np.random.default_rng(2).uniform(0, 1, size=(im.N, 4))
+    g = ctx.filter(T(Y, torch.float64)).cpu().numpy()
+    assert np.abs(g - model.Kp(Y)).max() <= 1e-11 * (1 + np.abs(model.Kp(Y)).max())
+
+
+@pytest.mark.parametrize("name,dtype,rtol", [
+    ("rect_32x24_L3", torch.float64, 1e-11),
+    ("voronoi_320x213_L21", torch.float32, 1e-5)])
+def test_qp_apply_matches_oracle(name, dtype, rtol):
+    im = synth.make(name)
+    ctx = gpu_ctx(im, dtype)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    mu = synth.potts(im.L)
+    qp = O.QP(model, im.unary, mu)
+    y = O.softmax_neg(im.unary)
+    if dtype == torch.float32:
+        y = y.astype(np.float32).astype(np.float64)
+    g = ctx.qp_apply(T(y, dtype), T(mu, dtype)).cpu().numpy()
+    o = qp.Q(y)
+    scale = np.abs(qp.Q(np.abs(y))) + np.abs(qp.d) * np.abs(y)
+    assert (np.abs(g - o) <= rtol * (scale + 1e-30)).all()
+
+
+@pytest.mark.parametrize("mode", ["lattice", "exact"])
+def test_fw_fp64_matches_oracle(mode):
+    # 32x24, L = 3, FP64, 20 iterations, seed 0
+    im = synth.make("rect_32x24_L3")
+    ctx = gpu_ctx(im, torch.float64, mode=mode)
+    mu = synth.potts(im.L)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS, mode=mode)
+    qp = O.QP(model, im.unary, mu)
+    y0 = O.softmax_neg(im.unary)
+    st = O.frank_wolfe(qp, y0, 20)
+    y = T(y0, torch.float64)
+    tr = ctx.qp_frank_wolfe(T(im.unary, torch.float64), T(mu, torch.float64),
+                            y, 20)
+    yg = y.cpu().numpy()
+    assert np.abs(yg - st.y).max() < 1e-9
+    for (fo, go, ao), (fg, gg, ag, _) in zip(st.trace, tr):
+        assert abs(fg - fo) <= 1e-9 * abs(fo)
+        assert abs(ag - ao) <= 1e-8
+        assert abs(gg - go) <= 1e-9 * abs(fo)
+    lab = ctx.round(y)
+    assert (lab.cpu().numpy() == O.round_argmax(st.y)).all()
+    e = ctx.energy(T(im.unary, torch.float64), T(mu, torch.float64), lab)
+    eo = O.energy(model, im.unary, mu, O.round_argmax(st.y))
+    assert abs(e - eo) <= 1e-10 * abs(eo)
+
+
+def test_fw_fp32_matches_oracle_320x213():
+    # 320x213, L = 21, FP32 marginals, 50 iterations
+    im = synth.make("voronoi_320x213_L21")
+    ctx = gpu_ctx(im, torch.float32)
+    mu = synth.potts(im.L)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    qp = O.QP(model, im.unary, mu)
+    y0 = O.softmax_neg(im.unary).astype(np.float32).astype(np.float64)
+    st = O.frank_wolfe(qp, y0, 50)
+    y = T(y0, torch.float32)
+    tr = ctx.qp_frank_wolfe(T(im.unary, torch.float32), T(mu, torch.float32),
+                            y, 50)
+    yg = y.cpu().numpy().astype(np.float64)
+    err = np.abs(yg - st.y).max()
+    print("max |y_gpu - y_oracle| =", err)
+    assert err < 1e-4
+    fo, fg = st.trace[-1][0], tr[-1][0]
+    assert abs(fg - fo) <= 1e-4 * abs(fo)
+    lab = ctx.round(y)
+    e = ctx.energy(T(im.unary, torch.float32), T(mu, torch.float32), lab)
+    eo = O.energy(model, im.unary, mu, lab.cpu().numpy())
+    assert abs(e - eo) <= 1e-5 * abs(eo)
+
+
+def test_energy_random_labels():
+    im = synth.make("voronoi_320x213_L21")
+    ctx = gpu_ctx(im, torch.float32)
+    mu = synth.potts(im.L)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    x = np.random.default_rng(3).integers(0, im.L, size=im.N).astype(np.int32)
+    e = ctx.energy(T(im.unary, torch.float32), T(mu, torch.float32),
+                   torch.from_numpy(x).to(dev()))
+    assert abs(e - O.energy(model, im.unary, mu, x)) <= 1e-5 * abs(e)
+
+
+def test_dc_gen_fp64_matches_oracle():
+    im = synth.make("rect_32x24_L3")
+    ctx = gpu_ctx(im, torch.float64)
+    mu = synth.potts(im.L)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    qp = O.QP(model, im.unary, mu)
+    y0 = O.frank_wolfe(qp, O.softmax_neg(im.unary), 10).y
+    yo, ho = O.dc_gen(qp, y0, outer=4, inner=5)
+    y = T(y0, torch.float64)
+    hg = ctx.dc_gen(T(im.unary, torch.float64), T(mu, torch.float64), y, 4, 5)
+    assert np.abs(y.cpu().numpy() - yo).max() < 1e-9
+    assert np.allclose(hg, ho, rtol=1e-9, atol=0)
+
+
+def test_errors_are_reported_not_fatal():
+    from paper_1608_06192_amd import dcrf
+    im = synth.make("rect_32x24_L3")
+    ctx = gpu_ctx(im, torch.float64)
+    mu = T(synth.potts(3), torch.float64)
+    bad = torch.full((im.N,), 7, dtype=torch.int32, device=dev())
+    with pytest.raises(dcrf.DcrfError) as ei:
+        ctx.energy(T(im.unary, torch.float64), mu, bad)
+    assert ei.value.status == -1
+    with pytest.raises(dcrf.DcrfError) as ei:
+        ctx.set_image(im.H, im.W, torch.from_numpy(im.rgb).to(dev()),
+                      [dict(use_rgb=1, theta_pos=0.0, theta_rgb=13, weight=1)])
+    assert ei.value.status == -1
+    with pytest.raises(dcrf.DcrfError) as ei:
+        # tiny theta: coordinates beyond the vertex key range
+        ctx.set_image(im.H, im.W, torch.from_numpy(im.rgb).to(dev()),
+                      [dict(use_rgb=1, theta_pos=80, theta_rgb=0.01, weight=1)])
+    assert ei.value.status == -3
+    # the context stays usable
+    ctx.set_image(im.H, im.W, torch.from_numpy(im.rgb).to(dev()), KERNELS,
+                  dtype=torch.float64)
+    x = torch.zeros(im.N, dtype=torch.int32, device=dev())
+    ctx.energy(T(im.unary, torch.float64), mu, x)
