@@ -170,6 +170,19 @@ int dcrf_round(dcrf_ctx *ctx, const void *y, int L, int32_t *labels);
 int dcrf_energy(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
                 const int32_t *labels, double *energy);
 
+/* ---- benchmarking support ---------------------------------------------- */
+
+/* Turn per-kernel timing on or off (and reset the counters). While on, each
+ * launch of the hot kernels is bracketed by HIP events recorded on the
+ * context's stream; the events add a small gap between launches. */
+int dcrf_set_profiling(dcrf_ctx *ctx, int enable);
+
+/* Totals of kernel class k (0 <= k < 8): *name (static string, the kernel's
+ * name), *total_ms (summed event time) and *launches. Waits for the stream.
+ * Any output pointer may be NULL. */
+int dcrf_get_profile(dcrf_ctx *ctx, int k, const char **name, double *total_ms,
+                     long long *launches);
+
 #ifdef __cplusplus
 }
 #endif

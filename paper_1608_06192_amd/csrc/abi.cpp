@@ -11,6 +11,16 @@
 
 using dcrf::Error;
 
+namespace dcrf {
+const char *prof_name(int c) {
+    static const char *names[PROF_NCLASS] = {
+        "k_fw_lmo_rows", "k_blur_pass", "k_fw_slice_rows", "k_splat_gather",
+        "k_slice_rows", "k_slice_rows_qp", "k_splat_labels_entries",
+        "k_fw_alpha"};
+    return (c >= 0 && c < PROF_NCLASS) ? names[c] : "?";
+}
+}  // namespace dcrf
+
 namespace {
 
 thread_local std::string g_create_error;
@@ -78,6 +88,7 @@ int dcrf_destroy(dcrf_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     for (auto &L : ctx->lat) L.release();
+    ctx->prof.release();
     for (dcrf::DevBuf *b :
          {&ctx->r, &ctx->scratch, &ctx->tmpA, &ctx->tmpB, &ctx->fw_c,
           &ctx->fw_Py, &ctx->fw_Ps, &ctx->fw_s, &ctx->fw_sprev, &ctx->fw_part,
@@ -237,6 +248,26 @@ int dcrf_energy(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
         check_labels(L);
         REQUIRE(unary && mu && labels && energy, "null argument");
         *energy = dcrf::energy(ctx, unary, mu, L, labels);
+    });
+}
+
+int dcrf_set_profiling(dcrf_ctx *ctx, int enable) {
+    return guarded(ctx, [&] {
+        DCRF_TRY_HIP(hipStreamSynchronize(ctx->stream));
+        ctx->prof.collect();
+        ctx->prof.reset();
+        ctx->prof.on = enable != 0;
+    });
+}
+
+int dcrf_get_profile(dcrf_ctx *ctx, int k, const char **name, double *total_ms,
+                     long long *launches) {
+    return guarded(ctx, [&] {
+        REQUIRE(k >= 0 && k < dcrf::PROF_NCLASS, "kernel class out of range");
+        ctx->prof.collect();
+        if (name) *name = dcrf::prof_name(k);
+        if (total_ms) *total_ms = ctx->prof.total_ms[k];
+        if (launches) *launches = ctx->prof.launches[k];
     });
 }
 

@@ -8,6 +8,8 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "dcrf.h"
 
@@ -76,12 +78,87 @@ struct Lattice {
     DevBuf pix_w;        // N (d+1) x T barycentric weight
     DevBuf vkeys;        // M x u64
     DevBuf nbr;          // (d+1) x M x 2 i32: id of v + u_j, v - u_j, or -1
-    DevBuf V[3];         // M x C x T: splat target (kept zero), ping, pong
+    DevBuf V[3];         // M x ld x T: splat target (kept zero), ping, pong
     DevBuf feat;         // N x d x T features (exact mode)
+    // inverse index: the (pixel, weight) pairs of vertex v are entries
+    // [csr_off[v], csr_off[v+1]); chunks of at most `chunk` entries
+    DevBuf csr_off;      // M + 1 i32
+    DevBuf csr_tmp;      // M + 1 i32 (counts / cursors while building)
+    DevBuf ent_pix;      // N (d+1) i32 pixel of each entry
+    DevBuf ent_w;        // N (d+1) x T weight of each entry
+    DevBuf ent_v;        // N (d+1) i32 vertex of each entry
+    int nent = 0;        // number of entries (pixel vertices with weight > 0)
+    DevBuf chunk_off;    // M + 1 i32 first chunk of each vertex
+    DevBuf chunks;       // nchunks x int4 (vertex, begin, end, 0)
+    int nchunks = 0;
+    int chunk = 32;
     void release() {
         for (DevBuf *b : {&hkeys, &slot_vid, &pix_slot, &pix_vid, &pix_w,
-                          &vkeys, &nbr, &V[0], &V[1], &V[2], &feat})
+                          &vkeys, &nbr, &V[0], &V[1], &V[2], &feat, &csr_off,
+                          &csr_tmp, &ent_pix, &ent_w, &ent_v, &chunk_off, &chunks})
             b->release();
+    }
+};
+
+// Row stride of the M x C vertex arrays: C rounded up to 16 bytes so that a
+// row can be moved with 16-byte loads; the padding channels stay zero.
+inline int row_stride(int C, size_t elt) {
+    const int q = int(16 / elt);
+    return (C + q - 1) / q * q;
+}
+
+// Per-kernel timing with HIP events recorded on the context's stream around
+// each launch (enabled only for benchmarks; the events add a small gap).
+enum ProfClass {
+    PROF_FW_LMO = 0,      // k_fw_lmo: update, gradient, LMO, one-hot splat
+    PROF_BLUR = 1,        // one blur pass over every lattice
+    PROF_FW_SLICE = 2,    // k_fw_slice: slice, mu, line-search sums, alpha
+    PROF_SPLAT = 3,       // dense splat
+    PROF_SLICE = 4,       // raw slice (K'Y)
+    PROF_SLICE_QP = 5,    // slice with mu and the diagonal
+    PROF_SPLAT_LABELS = 6,  // one-hot (label) splat
+    PROF_FW_ALPHA = 7,    // reduction of the line-search sums, step size
+    PROF_NCLASS = 8
+};
+const char *prof_name(int c);
+
+struct Profiler {
+    bool on = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<hipEvent_t> pool;
+    double total_ms[PROF_NCLASS] = {};
+    long launches[PROF_NCLASS] = {};
+    hipEvent_t get() {
+        if (pool.empty()) {
+            hipEvent_t e;
+            DCRF_TRY_HIP(hipEventCreate(&e));
+            return e;
+        }
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    void collect() {
+        for (auto &p : pending) {
+            DCRF_TRY_HIP(hipEventSynchronize(p.second.second));
+            float ms = 0;
+            DCRF_TRY_HIP(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+            total_ms[p.first] += ms;
+            launches[p.first] += 1;
+            pool.push_back(p.second.first);
+            pool.push_back(p.second.second);
+        }
+        pending.clear();
+    }
+    void reset() {
+        pending.clear();
+        for (int i = 0; i < PROF_NCLASS; ++i) total_ms[i] = 0, launches[i] = 0;
+    }
+    void release() {
+        for (auto &p : pending) pool.push_back(p.second.first), pool.push_back(p.second.second);
+        pending.clear();
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        pool.clear();
     }
 };
 
@@ -96,12 +173,14 @@ struct dcrf_ctx {
     dcrf_kernel kern[DCRF_MAXK];
     dcrf::Lattice lat[DCRF_MAXK];
     double wsum = 0;
+    int splat_chunk = 64;    // entries per splat chunk (one wave of the label splat)
     dcrf::DevBuf r;          // N x T: K'1
     dcrf::DevBuf scratch;    // small device scratch (flags, counters)
     dcrf::DevBuf tmpA, tmpB; // N x C scratch arrays
     // Frank-Wolfe state
     dcrf::DevBuf fw_c, fw_Py, fw_Ps, fw_s, fw_sprev, fw_part, fw_scal,
         fw_trace, fw_mu;
+    dcrf::Profiler prof;
     std::string err;
     size_t elt() const { return dtype == DCRF_F64 ? 8 : 4; }
 };
@@ -128,6 +207,10 @@ void ensure_vertex_buffers(dcrf_ctx *ctx, int C);
 void splat_labels(dcrf_ctx *ctx, const int32_t *labels, int L);
 void splat_dense(dcrf_ctx *ctx, const void *in, int C);
 void blur_all(dcrf_ctx *ctx, int C, bool adjoint);
+// slice of the blurred lattices: K'Y (qp = false) or (K'Y) mu^T + d * Y
+// (qp = true); `pre` replaces the lattice by a given K'Y (exact mode)
+void slice_into(dcrf_ctx *ctx, const void *Y, const void *pre, int C,
+                const void *mu, const void *mabs, void *out, bool qp);
 // index of the buffer that holds the blurred values of lattice m
 inline int final_buffer(int d) { return (d % 2 == 0) ? 1 : 2; }
 
@@ -143,5 +226,26 @@ double energy(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
               const int32_t *labels);
 
 inline int ceil_div(long long a, long long b) { return int((a + b - 1) / b); }
+
+// Records events around the launches made during its lifetime when the
+// context's profiler is on.
+struct ProfScope {
+    dcrf_ctx *ctx;
+    int cls;
+    hipEvent_t start{}, stop{};
+    ProfScope(dcrf_ctx *c, int k) : ctx(c), cls(k) {
+        if (ctx->prof.on) {
+            start = ctx->prof.get();
+            stop = ctx->prof.get();
+            DCRF_TRY_HIP(hipEventRecord(start, ctx->stream));
+        }
+    }
+    ~ProfScope() {
+        if (ctx->prof.on) {
+            (void)hipEventRecord(stop, ctx->stream);
+            ctx->prof.pending.push_back({cls, {start, stop}});
+        }
+    }
+};
 
 }  // namespace dcrf

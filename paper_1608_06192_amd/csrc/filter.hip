@@ -2,20 +2,27 @@
 // over the kernels of eq. pairwise, without the b = a term of
 // eq. labelling-energy), in two forms:
 //
-//  - permutohedral: K_m Y ~ gamma_d slice(blur(splat(Y))). Splat scatters
-//    b * Y_a into the d+1 vertices of pixel a's simplex with atomics; the blur
-//    runs d+1 out-of-place passes V'[v] = V[v]/2 + (V[v+u_j] + V[v-u_j])/4
-//    (missing neighbours read as 0) over both lattices in one launch per pass;
-//    slice gathers sum_k b_k V[v_k]. gamma_d = (4 pi / 3)^{d/2} sqrt(d+1)
-//    makes the response to a uniform density equal to the Gaussian integral.
-//    The transpose runs the same splat and slice with the blur directions in
-//    reverse order.
+//  - permutohedral: K_m Y ~ gamma_d slice(blur(splat(Y))), with
+//    gamma_d = (4 pi / 3)^{d/2} sqrt(d+1) so that the response to a uniform
+//    density equals the Gaussian integral.
+//      splat: a gather over each vertex's inverse index. The (pixel, weight)
+//        pairs of a vertex are cut into chunks of at most `chunk` pairs; one
+//        group of C lanes per chunk sums w * Y[pixel] and adds the sum to the
+//        vertex row with one atomic per channel. Vertices shared by thousands
+//        of pixels (flat colour regions of the bilateral lattice) cost one
+//        atomic per chunk instead of one per pixel.
+//      blur: d+1 out-of-place passes V'[v] = V[v]/2 + (V[v+u_j] + V[v-u_j])/4
+//        (missing neighbours read as 0) over all lattices in one launch per
+//        pass; the transpose runs the directions in reverse order.
+//      slice: one thread per pixel gathers its d+1 vertex rows with 16-byte
+//        loads into registers; rows move to and from global memory through
+//        LDS so the pixel-major arrays are read and written coalesced.
 //  - exact: the O(N^2) sum on the vector ALU, tiled through LDS (reference
 //    mode for small images and for measuring the lattice's error).
 //
-// Vertex values are stored row-major, M x C. Three buffers per lattice:
-// V[0] is the splat target and is kept all-zero between calls (the second
-// blur pass clears it while the passes ping-pong between V[1] and V[2]).
+// Vertex values are M x ld (ld = C rounded up to 16 bytes, zero padding).
+// V[0] is the splat target and is kept all-zero between calls: the second
+// blur pass clears it while the passes ping-pong between V[1] and V[2].
 
 #include <algorithm>
 
@@ -27,92 +34,185 @@ namespace {
 
 // ------------------------------------------------------------------ splat
 
+// lane (chunk, c), flattened over the lattices: V0[v][c] += sum w * Y[pix][c]
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_splat_dense(int N, int C, const T *__restrict__ in, LatSet<T> ls) {
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (size_t)N * C) return;
-    const int a = int(e / C);
-    const int c = int(e - (size_t)a * C);
-    const T v = in[e];
-    if (v == T(0)) return;
-    for (int m = 0; m < ls.nk; ++m) {
-        const LatView<T> &L = ls.l[m];
-        const int D1 = L.d + 1;
-        for (int k = 0; k < D1; ++k) {
-            const int id = L.vid[(size_t)a * D1 + k];
-            if (id >= 0)
-                atomic_add(&L.V0[(size_t)id * C + c], L.w[(size_t)a * D1 + k] * v);
-        }
+k_splat_gather(int C, const T *__restrict__ Y, LatSet<T> ls) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ls.coff[ls.nk]) return;
+    int m = 0;
+    while (m + 1 < ls.nk && e >= ls.coff[m + 1]) ++m;
+    const LatView<T> &L = ls.l[m];
+    const unsigned r = unsigned(e - ls.coff[m]);
+    const int ch = int(r / unsigned(C));
+    const int c = int(r - unsigned(ch) * unsigned(C));
+    const int4 cd = L.chunks[ch];
+    T acc0 = T(0), acc1 = T(0), acc2 = T(0), acc3 = T(0);
+    int i = cd.y;
+    for (; i + 4 <= cd.z; i += 4) {   // four independent loads in flight
+        acc0 += L.ent_w[i + 0] * Y[(size_t)L.ent_pix[i + 0] * C + c];
+        acc1 += L.ent_w[i + 1] * Y[(size_t)L.ent_pix[i + 1] * C + c];
+        acc2 += L.ent_w[i + 2] * Y[(size_t)L.ent_pix[i + 2] * C + c];
+        acc3 += L.ent_w[i + 3] * Y[(size_t)L.ent_pix[i + 3] * C + c];
     }
+    for (; i < cd.z; ++i) acc0 += L.ent_w[i] * Y[(size_t)L.ent_pix[i] * C + c];
+    const T acc = (acc0 + acc1) + (acc2 + acc3);
+    if (acc != T(0)) atomic_add(&L.V0[(size_t)cd.x * L.ld + c], acc);
 }
 
-// one-hot input: pixel a contributes b to channel labels[a]
+// One-hot input (pixel a is 1 at channel labels[a]): one wave per inverse-
+// index chunk (all entries of one vertex v). Each lane takes an entry and
+// adds its weight to an LDS histogram over the labels; the wave then adds
+// the non-zero bins to V0[v][label], one global atomic per label present.
+constexpr int kLabelBins = 256;   // labels per chunk histogram (L <= 256)
+
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_splat_labels(int N, int C, const int32_t *__restrict__ labels, LatSet<T> ls) {
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= N) return;
-    const int c = labels[a];
-    if (c < 0 || c >= C) return;   // out-of-range labels are rejected by the caller
-    for (int m = 0; m < ls.nk; ++m) {
-        const LatView<T> &L = ls.l[m];
-        const int D1 = L.d + 1;
-        for (int k = 0; k < D1; ++k) {
-            const int id = L.vid[(size_t)a * D1 + k];
-            if (id >= 0)
-                atomic_add(&L.V0[(size_t)id * C + c], L.w[(size_t)a * D1 + k]);
+k_splat_labels_chunks(int C, const int32_t *__restrict__ labels, LatSet<T> ls) {
+    __shared__ T bins[4][kLabelBins];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const long long chg = (long long)blockIdx.x * 4 + wave;
+    T *b = bins[wave];
+    for (int l = lane; l < C; l += 64) b[l] = T(0);
+    __syncthreads();
+    const bool valid = chg < ls.choff[ls.nk];
+    int m = 0;
+    while (m + 1 < ls.nk && chg >= ls.choff[m + 1]) ++m;
+    const LatView<T> &L = ls.l[m];
+    int4 cd = make_int4(0, 0, 0, 0);
+    if (valid) {
+        cd = L.chunks[chg - ls.choff[m]];
+        for (int i = cd.y + lane; i < cd.z; i += 64) {
+            const int lab = labels[L.ent_pix[i]];
+            if (lab >= 0 && lab < C) atomicAdd(&b[lab], L.ent_w[i]);
         }
     }
+    __syncthreads();
+    if (valid)
+        for (int l = lane; l < C; l += 64) {
+            const T s = b[l];
+            if (s != T(0)) atomic_add(&L.V0[(size_t)cd.x * L.ld + l], s);
+        }
 }
 
 // ------------------------------------------------------------------- blur
 
-// pass p of every lattice with d >= p, flattened over sum_m M_m x C
+__device__ __forceinline__ float4 blur3(float4 c, float4 p, float4 q) {
+    return make_float4(0.5f * c.x + 0.25f * (p.x + q.x), 0.5f * c.y + 0.25f * (p.y + q.y),
+                       0.5f * c.z + 0.25f * (p.z + q.z), 0.5f * c.w + 0.25f * (p.w + q.w));
+}
+__device__ __forceinline__ double2 blur3(double2 c, double2 p, double2 q) {
+    return make_double2(0.5 * c.x + 0.25 * (p.x + q.x), 0.5 * c.y + 0.25 * (p.y + q.y));
+}
+
+// pass p of every lattice with d >= p; one thread per 16 bytes of a vertex
+// row, flattened over sum_m M_m x ld / (16 / sizeof(T))
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_blur_pass(LatSet<T> ls, int C, int pass, int reverse, long long total) {
+k_blur_pass(LatSet<T> ls, int pass, int reverse, long long total) {
+    using V = typename Vec16<T>::type;
+    constexpr int vw = Vec16<T>::n;
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= total) return;
     int m = 0;
-    while (m + 1 < ls.nk && e >= ls.off[m + 1]) ++m;
+    while (m + 1 < ls.nk && e >= ls.off[m + 1] / vw) ++m;
     const LatView<T> &L = ls.l[m];
     if (pass > L.d) return;
-    const long long r = e - ls.off[m];
-    const int v = int(r / C);
-    const int c = int(r - (long long)v * C);
+    const unsigned G = unsigned(L.ld / vw);
+    const unsigned r = unsigned(e - ls.off[m] / vw);
+    const int v = int(r / G);
+    const int g = int(r - unsigned(v) * G);
     const int j = reverse ? (L.d - pass) : pass;
-    const T *src = (pass == 0) ? L.V0 : ((pass & 1) ? L.V1 : L.V2);
-    T *dst = (pass & 1) ? L.V2 : L.V1;
+    const V *src = reinterpret_cast<const V *>((pass == 0) ? L.V0 : ((pass & 1) ? L.V1 : L.V2));
+    V *dst = reinterpret_cast<V *>((pass & 1) ? L.V2 : L.V1);
     const int np = L.nbr[((size_t)j * L.M + v) * 2 + 0];
     const int nm = L.nbr[((size_t)j * L.M + v) * 2 + 1];
-    const T vp = np >= 0 ? src[(size_t)np * C + c] : T(0);
-    const T vm = nm >= 0 ? src[(size_t)nm * C + c] : T(0);
-    dst[(size_t)v * C + c] = T(0.5) * src[(size_t)v * C + c] + T(0.25) * (vp + vm);
-    if (pass == 1) L.V0[(size_t)v * C + c] = T(0);
+    V zero;
+    for (int i = 0; i < vw; ++i) reinterpret_cast<T *>(&zero)[i] = T(0);
+    const V vp = np >= 0 ? src[(size_t)np * G + g] : zero;
+    const V vm = nm >= 0 ? src[(size_t)nm * G + g] : zero;
+    dst[r] = blur3(src[r], vp, vm);
+    if (pass == 1) reinterpret_cast<V *>(L.V0)[r] = zero;
 }
 
 // ------------------------------------------------------------------ slice
 
-// out = sum_m w_m gamma_m slice_m - wsum * in   (raw K' in, N x C)
+enum { kSliceRaw = 0, kSliceQP = 1 };
+
+// One thread per pixel.
+//   raw: out = K'Y            = slice - wsum * Y
+//   qp:  out = (Psi + D) Y    = (K'Y) mu^T + d * Y, d_a(i) = mabs_i r_a
+// `pre` (optional) holds K'Y already (exact mode): then no lattice is read.
+template <typename T, int LMAX, int MODE>
+__global__ void __launch_bounds__(RowTile<T>::kPix, 4)
+k_slice_rows(int N, int C, const T *__restrict__ Y, const T *__restrict__ pre,
+             LatSet<T> ls, T wsum, const T *__restrict__ mu,
+             const T *__restrict__ mabs, const T *__restrict__ r,
+             T *__restrict__ out) {
+    constexpr int TP = RowTile<T>::kPix;
+    __shared__ __align__(16) T lds[TP * (LMAX | 1)];
+    __shared__ T smu[MODE == kSliceQP ? LMAX * LMAX : 1];
+    if (MODE == kSliceQP) {
+        for (int i = threadIdx.x; i < C * C; i += TP)
+            smu[(i / C) * LMAX + (i % C)] = mu[i];
+        __syncthreads();
+    }
+    for (long long p0 = (long long)blockIdx.x * TP; p0 < N;
+         p0 += (long long)gridDim.x * TP) {
+        const int np = (int)min((long long)TP, N - p0);
+        const long long a = p0 + threadIdx.x;
+        const bool act = (int)threadIdx.x < np;
+        T y[LMAX], q[LMAX];
+#pragma unroll
+        for (int j = 0; j < LMAX; ++j) y[j] = T(0), q[j] = T(0);
+        if (pre) {
+            tile_load<T, LMAX, TP>(pre, p0, np, C, lds, q);
+        } else if (act) {
+            slice_pixel<T, LMAX>(ls, a, C, q);
+        }
+        // Y after the gathers, to keep their register footprint small
+        tile_load<T, LMAX, TP>(Y, p0, np, C, lds, y);
+        if (!pre) {
+#pragma unroll
+            for (int j = 0; j < LMAX; ++j) q[j] -= wsum * y[j];
+        }
+        if (MODE == kSliceRaw) {
+            tile_store<T, LMAX, TP>(out, p0, np, C, lds, q);
+        } else {
+            T o[LMAX];
+            const T ra = act ? r[a] : T(0);
+#pragma unroll
+            for (int i = 0; i < LMAX; ++i) {
+                T p = T(0);
+#pragma unroll
+                for (int j = 0; j < LMAX; ++j)
+                    if (i < C && j < C) p += smu[i * LMAX + j] * q[j];
+                o[i] = (i < C) ? p + mabs[i] * ra * y[i] : T(0);
+            }
+            tile_store<T, LMAX, TP>(out, p0, np, C, lds, o);
+        }
+    }
+}
+
+// generic slice for C > kRowMaxC: one lane per (pixel, channel)
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_slice_raw(int N, int C, const T *__restrict__ in, T *__restrict__ out,
-            LatSet<T> ls, T wsum) {
+k_slice_raw_flat(int N, int C, const T *__restrict__ in, T *__restrict__ out,
+                 LatSet<T> ls, T wsum) {
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (size_t)N * C) return;
-    const int a = int(e / C);
+    const long long a = (long long)(e / C);
     const int c = int(e - (size_t)a * C);
     T acc = T(0);
     for (int m = 0; m < ls.nk; ++m) {
         const LatView<T> &L = ls.l[m];
         const int D1 = L.d + 1;
-        T s = T(0);
         for (int k = 0; k < D1; ++k) {
-            const int id = L.vid[(size_t)a * D1 + k];
-            if (id >= 0) s += L.w[(size_t)a * D1 + k] * L.Vf[(size_t)id * C + c];
+            const int id = L.vid[a * D1 + k];
+            if (id >= 0)
+                acc += L.wg * L.w[a * D1 + k] * L.Vf[(size_t)id * L.ld + c];
         }
-        acc += L.wg * s;
     }
     out[e] = acc - wsum * in[e];
 }
@@ -123,7 +223,7 @@ constexpr int kExactTile = 128;
 constexpr int kExactMaxF = 16;   // sum of feature dimensions over the kernels
 constexpr int kExactCB = 8;      // channels per pass
 
-// out_a[c0 .. c0+CB) (+)= sum_{b != a} sum_m w_m exp(-|f_a - f_b|^2/2) in_b
+// out_a[c0 .. c0+CB) = sum_{b != a} sum_m w_m exp(-|f_a - f_b|^2/2) in_b
 template <typename T>
 __global__ void __launch_bounds__(kExactTile)
 k_exact(int N, int C, int c0, const T *__restrict__ in, T *__restrict__ out,
@@ -131,7 +231,6 @@ k_exact(int N, int C, int c0, const T *__restrict__ in, T *__restrict__ out,
     __shared__ T sf[kExactTile][kExactMaxF];
     __shared__ T sv[kExactTile][kExactCB];
     const int a = blockIdx.x * kExactTile + threadIdx.x;
-    const int nf = ex.off[ex.nk];
     T fa[kExactMaxF];
     for (int j = 0; j < kExactMaxF; ++j) fa[j] = T(0);
     if (a < N)
@@ -169,53 +268,49 @@ k_exact(int N, int C, int c0, const T *__restrict__ in, T *__restrict__ out,
         }
         __syncthreads();
     }
-    (void)nf;
     if (a < N)
         for (int c = 0; c < cn; ++c) out[(size_t)a * C + c0 + c] = acc[c];
 }
 
+int row_grid(dcrf_ctx *ctx, int tp) {
+    return std::max(1, std::min(ceil_div(ctx->N, tp), 4096));
+}
+
 template <typename T>
-void filter_t(dcrf_ctx *ctx, const void *in_, void *out_, int C, bool adjoint,
-              bool exact) {
-    const hipStream_t s = ctx->stream;
-    const T *in = static_cast<const T *>(in_);
-    T *out = static_cast<T *>(out_);
-    const int N = ctx->N;
-    if (exact) {
-        ExactSet<T> ex = make_exact_set<T>(ctx);
-        if (ex.off[ex.nk] > kExactMaxF)
-            fail(DCRF_EUNSUPPORTED, "exact filter supports at most 16 feature "
-                                    "dimensions over all kernels");
-        for (int c0 = 0; c0 < C; c0 += kExactCB)
-            hipLaunchKernelGGL((k_exact<T>), dim3(ceil_div(N, kExactTile)),
-                               dim3(kExactTile), 0, s, N, C, c0, in, out, ex);
-        DCRF_CHECK_LAUNCH();
-        return;
-    }
-    splat_dense(ctx, in, C);
-    blur_all(ctx, C, adjoint);
-    LatSet<T> ls = make_lat_set<T>(ctx, C);
-    hipLaunchKernelGGL((k_slice_raw<T>), dim3(ceil_div((long long)N * C, 256)),
-                       dim3(256), 0, s, N, C, in, out, ls, T(ctx->wsum));
+void exact_t(dcrf_ctx *ctx, const T *in, T *out, int C) {
+    ExactSet<T> ex = make_exact_set<T>(ctx);
+    if (ex.off[ex.nk] > kExactMaxF)
+        fail(DCRF_EUNSUPPORTED, "exact filter supports at most 16 feature "
+                                "dimensions over all kernels");
+    for (int c0 = 0; c0 < C; c0 += kExactCB)
+        hipLaunchKernelGGL((k_exact<T>), dim3(ceil_div(ctx->N, kExactTile)),
+                           dim3(kExactTile), 0, ctx->stream, ctx->N, C, c0, in,
+                           out, ex);
     DCRF_CHECK_LAUNCH();
 }
 
 template <typename T>
-void splat_dense_t(dcrf_ctx *ctx, const void *in, int C) {
+void splat_dense_t(dcrf_ctx *ctx, const T *in, int C) {
     ensure_vertex_buffers(ctx, C);
     LatSet<T> ls = make_lat_set<T>(ctx, C);
-    hipLaunchKernelGGL((k_splat_dense<T>),
-                       dim3(ceil_div((long long)ctx->N * C, 256)), dim3(256), 0,
-                       ctx->stream, ctx->N, C, static_cast<const T *>(in), ls);
+    const long long total = ls.coff[ls.nk];
+    if (total == 0) return;
+    ProfScope ps(ctx, PROF_SPLAT);
+    hipLaunchKernelGGL((k_splat_gather<T>), dim3(ceil_div(total, 256)), dim3(256),
+                       0, ctx->stream, C, in, ls);
     DCRF_CHECK_LAUNCH();
 }
 
 template <typename T>
 void splat_labels_t(dcrf_ctx *ctx, const int32_t *labels, int L) {
+    if (L > kLabelBins) fail(DCRF_EUNSUPPORTED, "more than 256 labels");
     ensure_vertex_buffers(ctx, L);
     LatSet<T> ls = make_lat_set<T>(ctx, L);
-    hipLaunchKernelGGL((k_splat_labels<T>), dim3(ceil_div(ctx->N, 256)),
-                       dim3(256), 0, ctx->stream, ctx->N, L, labels, ls);
+    const long long total = ls.choff[ls.nk];
+    if (total == 0) return;
+    ProfScope ps(ctx, PROF_SPLAT_LABELS);
+    hipLaunchKernelGGL((k_splat_labels_chunks<T>), dim3(ceil_div(total, 4)),
+                       dim3(256), 0, ctx->stream, L, labels, ls);
     DCRF_CHECK_LAUNCH();
 }
 
@@ -224,30 +319,81 @@ void blur_all_t(dcrf_ctx *ctx, int C, bool adjoint) {
     LatSet<T> ls = make_lat_set<T>(ctx, C);
     int maxd = 0;
     for (int m = 0; m < ctx->nk; ++m) maxd = std::max(maxd, ctx->lat[m].d);
-    const long long total = ls.off[ctx->nk];
+    const long long total = ls.off[ctx->nk] / Vec16<T>::n;
     if (total == 0) return;
-    for (int p = 0; p <= maxd; ++p)
+    for (int p = 0; p <= maxd; ++p) {
+        ProfScope ps(ctx, PROF_BLUR);
         hipLaunchKernelGGL((k_blur_pass<T>), dim3(ceil_div(total, 256)),
-                           dim3(256), 0, ctx->stream, ls, C, p, adjoint ? 1 : 0,
+                           dim3(256), 0, ctx->stream, ls, p, adjoint ? 1 : 0,
                            total);
+    }
     DCRF_CHECK_LAUNCH();
+}
+
+template <typename T>
+void slice_t(dcrf_ctx *ctx, const T *Y, const T *pre, int C, const T *mu,
+             const T *mabs, T *out, bool qp) {
+    const hipStream_t s = ctx->stream;
+    const int N = ctx->N;
+    LatSet<T> ls = make_lat_set<T>(ctx, C);
+    const T wsum = T(ctx->wsum);
+    const T *r = ctx->r.as<T>();
+    constexpr int TP = RowTile<T>::kPix;
+    if (C <= kRowMaxC) {
+        ProfScope ps(ctx, qp ? PROF_SLICE_QP : PROF_SLICE);
+        DCRF_DISPATCH_ROWS(C, {
+            if (qp)
+                hipLaunchKernelGGL((k_slice_rows<T, LMAX, kSliceQP>),
+                                   dim3(row_grid(ctx, TP)), dim3(TP), 0, s, N, C,
+                                   Y, pre, ls, wsum, mu, mabs, r, out);
+            else
+                hipLaunchKernelGGL((k_slice_rows<T, LMAX, kSliceRaw>),
+                                   dim3(row_grid(ctx, TP)), dim3(TP), 0, s, N, C,
+                                   Y, pre, ls, wsum, mu, mabs, r, out);
+        });
+        DCRF_CHECK_LAUNCH();
+        return;
+    }
+    if (qp) fail(DCRF_EUNSUPPORTED, "more than 32 labels");
+    if (pre) {
+        DCRF_TRY_HIP(hipMemcpyAsync(out, pre, (size_t)N * C * sizeof(T),
+                                    hipMemcpyDeviceToDevice, s));
+        return;
+    }
+    ProfScope ps(ctx, PROF_SLICE);
+    hipLaunchKernelGGL((k_slice_raw_flat<T>), dim3(ceil_div((long long)N * C, 256)),
+                       dim3(256), 0, s, N, C, Y, out, ls, wsum);
+    DCRF_CHECK_LAUNCH();
+}
+
+template <typename T>
+void filter_t(dcrf_ctx *ctx, const T *in, T *out, int C, bool adjoint,
+              bool exact) {
+    if (exact) {
+        exact_t<T>(ctx, in, out, C);
+        return;
+    }
+    splat_dense_t<T>(ctx, in, C);
+    blur_all_t<T>(ctx, C, adjoint);
+    slice_t<T>(ctx, in, nullptr, C, nullptr, nullptr, out, false);
 }
 
 }  // namespace
 
 void ensure_vertex_buffers(dcrf_ctx *ctx, int C) {
+    const int ld = row_stride(C, ctx->elt());
     for (int m = 0; m < ctx->nk; ++m) {
         Lattice &L = ctx->lat[m];
-        const size_t bytes = (size_t)(L.M > 0 ? L.M : 1) * C * ctx->elt();
+        const size_t bytes = (size_t)(L.M > 0 ? L.M : 1) * ld * ctx->elt();
         for (int b = 0; b < 3; ++b) L.V[b].ensure(bytes, ctx->stream);
     }
 }
 
 void splat_dense(dcrf_ctx *ctx, const void *in, int C) {
     if (ctx->dtype == DCRF_F64)
-        splat_dense_t<double>(ctx, in, C);
+        splat_dense_t<double>(ctx, static_cast<const double *>(in), C);
     else
-        splat_dense_t<float>(ctx, in, C);
+        splat_dense_t<float>(ctx, static_cast<const float *>(in), C);
 }
 
 void splat_labels(dcrf_ctx *ctx, const int32_t *labels, int L) {
@@ -264,12 +410,30 @@ void blur_all(dcrf_ctx *ctx, int C, bool adjoint) {
         blur_all_t<float>(ctx, C, adjoint);
 }
 
+void slice_into(dcrf_ctx *ctx, const void *Y, const void *pre, int C,
+                const void *mu, const void *mabs, void *out, bool qp) {
+    if (ctx->dtype == DCRF_F64)
+        slice_t<double>(ctx, static_cast<const double *>(Y),
+                        static_cast<const double *>(pre), C,
+                        static_cast<const double *>(mu),
+                        static_cast<const double *>(mabs),
+                        static_cast<double *>(out), qp);
+    else
+        slice_t<float>(ctx, static_cast<const float *>(Y),
+                       static_cast<const float *>(pre), C,
+                       static_cast<const float *>(mu),
+                       static_cast<const float *>(mabs),
+                       static_cast<float *>(out), qp);
+}
+
 void filter_apply(dcrf_ctx *ctx, const void *in, void *out, int C,
                   bool adjoint, bool exact) {
     if (ctx->dtype == DCRF_F64)
-        filter_t<double>(ctx, in, out, C, adjoint, exact);
+        filter_t<double>(ctx, static_cast<const double *>(in),
+                         static_cast<double *>(out), C, adjoint, exact);
     else
-        filter_t<float>(ctx, in, out, C, adjoint, exact);
+        filter_t<float>(ctx, static_cast<const float *>(in),
+                        static_cast<float *>(out), C, adjoint, exact);
 }
 
 void compute_row_sums(dcrf_ctx *ctx) {

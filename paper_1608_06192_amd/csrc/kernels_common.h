@@ -1,27 +1,35 @@
-// Device-side views of the lattices and small helpers shared by the kernels.
+// Device-side views of the lattices and helpers shared by the kernels.
 #pragma once
 
 #include "dcrf_internal.h"
 
 namespace dcrf {
 
-// One lattice as the splat / blur / slice kernels see it (C channels).
+// One lattice as the splat / blur / slice kernels see it.
 template <typename T>
 struct LatView {
     const int32_t *vid;  // N x (d+1) vertex ids (-1: weight 0)
     const T *w;          // N x (d+1) barycentric weights
     const int32_t *nbr;  // (d+1) x M x 2
-    T *V0, *V1, *V2;     // M x C: splat target, ping, pong
+    T *V0, *V1, *V2;     // M x ld: splat target, ping, pong
     const T *Vf;         // the buffer that holds the blurred values
-    int d, M;
+    const int4 *chunks;  // inverse-index chunks (vertex, begin, end, 0)
+    const int32_t *ent_pix;
+    const T *ent_w;
+    const int32_t *ent_v;
+    int d, M, ld, nchunks;
     T wg;                // w_m * gamma_m
 };
 
 template <typename T>
 struct LatSet {
     LatView<T> l[DCRF_MAXK];
-    long long off[DCRF_MAXK + 1];  // prefix sums of M_m * C
+    long long off[DCRF_MAXK + 1];   // prefix sums of M_m * ld (blur)
+    long long coff[DCRF_MAXK + 1];  // prefix sums of nchunks_m * C (splat)
+    long long eoff[DCRF_MAXK + 1];  // prefix sums of the entries
+    long long choff[DCRF_MAXK + 1]; // prefix sums of nchunks_m (label splat)
     int nk;
+    int shape52;                    // two lattices with d = 5 and d = 2
 };
 
 template <typename T>
@@ -33,11 +41,16 @@ struct ExactSet {
     int nk;
 };
 
+// C: channels of the call; the vertex rows have stride row_stride(C).
 template <typename T>
 inline LatSet<T> make_lat_set(dcrf_ctx *ctx, int C) {
     LatSet<T> s{};
     s.nk = ctx->nk;
     s.off[0] = 0;
+    s.coff[0] = 0;
+    s.eoff[0] = 0;
+    s.choff[0] = 0;
+    const int ld = row_stride(C, sizeof(T));
     for (int m = 0; m < ctx->nk; ++m) {
         Lattice &L = ctx->lat[m];
         LatView<T> &v = s.l[m];
@@ -48,11 +61,21 @@ inline LatSet<T> make_lat_set(dcrf_ctx *ctx, int C) {
         v.V1 = L.V[1].as<T>();
         v.V2 = L.V[2].as<T>();
         v.Vf = L.V[final_buffer(L.d)].as<T>();
+        v.chunks = L.chunks.as<int4>();
+        v.ent_pix = L.ent_pix.as<int32_t>();
+        v.ent_w = L.ent_w.as<T>();
+        v.ent_v = L.ent_v.as<int32_t>();
         v.d = L.d;
         v.M = L.M;
+        v.ld = ld;
+        v.nchunks = L.nchunks;
         v.wg = T(ctx->kern[m].weight * L.gamma);
-        s.off[m + 1] = s.off[m] + (long long)L.M * C;
+        s.off[m + 1] = s.off[m] + (long long)L.M * ld;
+        s.coff[m + 1] = s.coff[m] + (long long)L.nchunks * C;
+        s.eoff[m + 1] = s.eoff[m] + (long long)L.nent;
+        s.choff[m + 1] = s.choff[m] + (long long)L.nchunks;
     }
+    s.shape52 = (ctx->nk == 2 && ctx->lat[0].d == 5 && ctx->lat[1].d == 2) ? 1 : 0;
     return s;
 }
 
@@ -78,5 +101,215 @@ __device__ __forceinline__ void atomic_add(double *p, double v) {
 }
 
 void fill_ones(dcrf_ctx *ctx, void *p, size_t n);
+
+// ------------------------------------------------------- row kernels
+
+// Pixels per block of the row kernels (one thread per pixel).
+template <typename T> struct RowTile;
+template <> struct RowTile<float> { static constexpr int kPix = 128; };
+template <> struct RowTile<double> { static constexpr int kPix = 64; };
+
+// Largest channel count handled with per-thread register rows.
+constexpr int kRowMaxC = 32;
+
+// LDS row stride of a staged tile: odd, so that threads reading row t at
+// stride Ls hit distinct banks.
+__device__ __forceinline__ int lds_stride(int C) { return C | 1; }
+
+// 16-byte vector of T
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using type = float4; static constexpr int n = 4; };
+template <> struct Vec16<double> { using type = double2; static constexpr int n = 2; };
+
+// Move np pixel rows of C values between global memory (contiguous rows) and
+// per-thread registers through LDS so that the global side is coalesced.
+// For odd C the LDS tile is the contiguous global block and moves with
+// 16-byte accesses (tiles start at multiples of TP pixels, so 16-byte
+// aligned); for even C rows are padded to an odd stride.
+// Every thread of the block must call these (they synchronise).
+template <typename T, int TP>
+__device__ __forceinline__ void tile_copy_in(const T *__restrict__ src, int n,
+                                             int C, T *lds) {
+    if (C & 1) {
+        using V = typename Vec16<T>::type;
+        constexpr int w = Vec16<T>::n;
+        const int nv = n / w;
+        const V *s = reinterpret_cast<const V *>(src);
+        V *l = reinterpret_cast<V *>(lds);
+        for (int i = threadIdx.x; i < nv; i += TP) l[i] = s[i];
+        for (int i = nv * w + threadIdx.x; i < n; i += TP) lds[i] = src[i];
+    } else {
+        const int Ls = C | 1;
+        const float inv = 1.0f / float(C);
+        for (int i = threadIdx.x; i < n; i += TP) {
+            const int p = int((float(i) + 0.5f) * inv);
+            lds[p * Ls + (i - p * C)] = src[i];
+        }
+    }
+}
+
+template <typename T, int TP>
+__device__ __forceinline__ void tile_copy_out(T *__restrict__ dst, int n, int C,
+                                              const T *lds) {
+    if (C & 1) {
+        using V = typename Vec16<T>::type;
+        constexpr int w = Vec16<T>::n;
+        const int nv = n / w;
+        V *d = reinterpret_cast<V *>(dst);
+        const V *l = reinterpret_cast<const V *>(lds);
+        for (int i = threadIdx.x; i < nv; i += TP) d[i] = l[i];
+        for (int i = nv * w + threadIdx.x; i < n; i += TP) dst[i] = lds[i];
+    } else {
+        const int Ls = C | 1;
+        const float inv = 1.0f / float(C);
+        for (int i = threadIdx.x; i < n; i += TP) {
+            const int p = int((float(i) + 0.5f) * inv);
+            dst[i] = lds[p * Ls + (i - p * C)];
+        }
+    }
+}
+
+template <typename T, int LMAX, int TP>
+__device__ __forceinline__ void tile_load(const T *__restrict__ g, long long p0,
+                                          int np, int C, T *lds, T (&r)[LMAX]) {
+    const int Ls = lds_stride(C);
+    tile_copy_in<T, TP>(g + p0 * C, np * C, C, lds);
+    __syncthreads();
+    if ((int)threadIdx.x < np) {
+#pragma unroll
+        for (int j = 0; j < LMAX; ++j)
+            if (j < C) r[j] = lds[threadIdx.x * Ls + j];
+    }
+    __syncthreads();
+}
+
+template <typename T, int LMAX, int TP>
+__device__ __forceinline__ void tile_store(T *__restrict__ g, long long p0,
+                                           int np, int C, T *lds,
+                                           const T (&r)[LMAX]) {
+    const int Ls = lds_stride(C);
+    if ((int)threadIdx.x < np) {
+#pragma unroll
+        for (int j = 0; j < LMAX; ++j)
+            if (j < C) lds[threadIdx.x * Ls + j] = r[j];
+    }
+    __syncthreads();
+    tile_copy_out<T, TP>(g + p0 * C, np * C, C, lds);
+    __syncthreads();
+}
+
+// acc[j] += s * row[j] for j < C, with 16-byte loads (rows are 16-byte
+// aligned and padded with zeros to a multiple of 16 bytes)
+template <int LMAX>
+__device__ __forceinline__ void axpy_row(float (&acc)[LMAX], float s,
+                                         const float *__restrict__ row, int C) {
+    const float4 *r4 = reinterpret_cast<const float4 *>(row);
+#pragma unroll
+    for (int q = 0; q < LMAX / 4; ++q) {
+        if (4 * q < C) {
+            const float4 v = r4[q];
+            acc[4 * q + 0] += s * v.x;
+            acc[4 * q + 1] += s * v.y;
+            acc[4 * q + 2] += s * v.z;
+            acc[4 * q + 3] += s * v.w;
+        }
+    }
+}
+
+template <int LMAX>
+__device__ __forceinline__ void axpy_row(double (&acc)[LMAX], double s,
+                                         const double *__restrict__ row, int C) {
+    const double2 *r2 = reinterpret_cast<const double2 *>(row);
+#pragma unroll
+    for (int q = 0; q < LMAX / 2; ++q) {
+        if (2 * q < C) {
+            const double2 v = r2[q];
+            acc[2 * q + 0] += s * v.x;
+            acc[2 * q + 1] += s * v.y;
+        }
+    }
+}
+
+// The slice of pixel a for two lattices of compile-time dimensions DA, DB:
+// all vertex ids and weights are loaded first, then every row load is issued
+// unconditionally (a missing vertex reads row 0 with weight 0), so that all
+// of them can be in flight together.
+template <typename T, int LMAX, int DA, int DB>
+__device__ __forceinline__ void slice_pixel_fixed(const LatSet<T> &ls,
+                                                  long long a, int C,
+                                                  T (&acc)[LMAX]) {
+    const LatView<T> &A = ls.l[0];
+    const LatView<T> &B = ls.l[1];
+    int ia[DA + 1], ib[DB + 1];
+    T wa[DA + 1], wb[DB + 1];
+#pragma unroll
+    for (int k = 0; k <= DA; ++k) {
+        const int id = A.vid[a * (DA + 1) + k];
+        wa[k] = id >= 0 ? A.wg * A.w[a * (DA + 1) + k] : T(0);
+        ia[k] = id >= 0 ? id : 0;
+    }
+#pragma unroll
+    for (int k = 0; k <= DB; ++k) {
+        const int id = B.vid[a * (DB + 1) + k];
+        wb[k] = id >= 0 ? B.wg * B.w[a * (DB + 1) + k] : T(0);
+        ib[k] = id >= 0 ? id : 0;
+    }
+#pragma unroll
+    for (int k = 0; k <= DA; ++k)
+        axpy_row<LMAX>(acc, wa[k], A.Vf + (size_t)ia[k] * A.ld, C);
+#pragma unroll
+    for (int k = 0; k <= DB; ++k)
+        axpy_row<LMAX>(acc, wb[k], B.Vf + (size_t)ib[k] * B.ld, C);
+}
+
+// sum over the lattices of w_m gamma_m sum_k b_k V_m[v_k]  (the slice of
+// pixel a into acc, which the caller has zeroed)
+template <typename T, int LMAX>
+__device__ __forceinline__ void slice_pixel(const LatSet<T> &ls, long long a,
+                                            int C, T (&acc)[LMAX]) {
+    if (ls.shape52) {
+        slice_pixel_fixed<T, LMAX, 5, 2>(ls, a, C, acc);
+        return;
+    }
+    for (int m = 0; m < ls.nk; ++m) {
+        const LatView<T> &L = ls.l[m];
+        const int D1 = L.d + 1;
+        for (int k = 0; k < D1; ++k) {
+            const int id = L.vid[a * D1 + k];
+            if (id >= 0)
+                axpy_row<LMAX>(acc, L.wg * L.w[a * D1 + k],
+                               L.Vf + (size_t)id * L.ld, C);
+        }
+    }
+}
+
+// block-wide sum of NV doubles per thread (NT threads); every thread returns
+// the totals
+template <int NV, int NT>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *lds) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) lds[i * NT + t] = v[i];
+    __syncthreads();
+    for (int off = NT / 2; off > 0; off >>= 1) {
+        if (t < off)
+#pragma unroll
+            for (int i = 0; i < NV; ++i) lds[i * NT + t] += lds[i * NT + t + off];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = lds[i * NT];
+    __syncthreads();
+}
+
+// Calls BODY with LMAX bound to the smallest register-row size >= C.
+#define DCRF_DISPATCH_ROWS(C, BODY)                                 \
+    do {                                                           \
+        if ((C) <= 4) { constexpr int LMAX = 4; BODY; }            \
+        else if ((C) <= 8) { constexpr int LMAX = 8; BODY; }       \
+        else if ((C) <= 16) { constexpr int LMAX = 16; BODY; }     \
+        else if ((C) <= 24) { constexpr int LMAX = 24; BODY; }     \
+        else { constexpr int LMAX = 32; BODY; }                    \
+    } while (0)
 
 }  // namespace dcrf

@@ -298,6 +298,83 @@ k_assign_ids(const uint64_t *__restrict__ hkeys, size_t cap,
     }
 }
 
+// ---- generic exclusive scan of n ints (out[n] receives the total) ----------
+
+__global__ void __launch_bounds__(kScanThreads)
+k_sum_tiles(const int *__restrict__ in, int n, int *__restrict__ tile_sums) {
+    __shared__ int lds[kScanThreads];
+    const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanItems;
+    int s = 0;
+    for (int i = 0; i < kScanItems; ++i)
+        if (base + i < n) s += in[base + i];
+    int total;
+    block_exclusive_scan(s, lds, total);
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_apply(const int *__restrict__ in, int n, const int *__restrict__ tile_off,
+             int *__restrict__ out) {
+    __shared__ int lds[kScanThreads];
+    const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanItems;
+    int s = 0;
+    for (int i = 0; i < kScanItems; ++i)
+        if (base + i < n) s += in[base + i];
+    int total;
+    int run = tile_off[blockIdx.x] + block_exclusive_scan(s, lds, total);
+    for (int i = 0; i < kScanItems; ++i)
+        if (base + i < n) {
+            out[base + i] = run;
+            run += in[base + i];
+        }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanThreads - 1)
+        out[n] = tile_off[blockIdx.x] + total;
+}
+
+// ---- per-vertex inverse index: the (pixel, weight) pairs of each vertex ----
+
+__global__ void k_csr_count(size_t cnt, const int *__restrict__ pix_vid,
+                            int *__restrict__ counts) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= cnt) return;
+    const int v = pix_vid[e];
+    if (v >= 0) atomicAdd(&counts[v], 1);
+}
+
+template <typename T>
+__global__ void k_csr_fill(size_t cnt, int D1, const int *__restrict__ pix_vid,
+                           const T *__restrict__ pix_w, const int *__restrict__ off,
+                           int *__restrict__ cursor, int *__restrict__ ent_pix,
+                           T *__restrict__ ent_w, int *__restrict__ ent_v) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= cnt) return;
+    const int v = pix_vid[e];
+    if (v < 0) return;
+    const int pos = off[v] + atomicAdd(&cursor[v], 1);
+    ent_pix[pos] = int(e / D1);
+    ent_w[pos] = pix_w[e];
+    ent_v[pos] = v;
+}
+
+__global__ void k_chunk_count(int M, const int *__restrict__ off, int chunk,
+                              int *__restrict__ nch) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= M) return;
+    const int len = off[v + 1] - off[v];
+    nch[v] = (len + chunk - 1) / chunk;
+}
+
+__global__ void k_chunk_fill(int M, const int *__restrict__ off,
+                             const int *__restrict__ choff, int chunk,
+                             int4 *__restrict__ chunks) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= M) return;
+    const int b = off[v], e = off[v + 1];
+    int c = choff[v];
+    for (int s = b; s < e; s += chunk, ++c)
+        chunks[c] = make_int4(v, s, min(e, s + chunk), 0);
+}
+
 __global__ void k_pixel_ids(size_t count, const uint32_t *__restrict__ pix_slot,
                             const int *__restrict__ slot_vid,
                             int *__restrict__ pix_vid) {
@@ -366,6 +443,66 @@ __global__ void k_features(int N, int W, const float *__restrict__ rgb,
     }
 }
 
+// exclusive scan of n device ints into out (n + 1 entries) with the tile
+// counts kept in the context scratch (sized for the largest hash table)
+void scan_ints(dcrf_ctx *ctx, const int *in, int n, int *out) {
+    const hipStream_t s = ctx->stream;
+    const int ntiles = std::max(1, ceil_div(n, kScanTile));
+    int *tiles = reinterpret_cast<int *>(ctx->scratch.as<char>() + 64);
+    hipLaunchKernelGGL(k_sum_tiles, dim3(ntiles), dim3(kScanThreads), 0, s, in,
+                       n, tiles);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, tiles,
+                       ntiles);
+    hipLaunchKernelGGL(k_scan_apply, dim3(ntiles), dim3(kScanThreads), 0, s, in,
+                       n, tiles, out);
+    DCRF_CHECK_LAUNCH();
+}
+
+// Inverse index of lattice m: for each vertex the (pixel, weight) pairs that
+// splat into it, split into chunks of at most `chunk` pairs; the gather splat
+// runs one group of lanes per chunk.
+template <typename T>
+void build_inverse_index(dcrf_ctx *ctx, int m) {
+    Lattice &L = ctx->lat[m];
+    const hipStream_t s = ctx->stream;
+    const int M = L.M, D1 = L.d + 1;
+    const size_t cnt = (size_t)ctx->N * D1;
+    L.chunk = ctx->splat_chunk;
+    L.csr_off.ensure((size_t)(M + 1) * 4, s);
+    L.csr_tmp.ensure((size_t)(M + 1) * 4, s);
+    L.ent_pix.ensure(cnt * 4, s);
+    L.ent_w.ensure(cnt * sizeof(T), s);
+    L.ent_v.ensure(cnt * 4, s);
+    int *counts = L.csr_tmp.as<int>();
+    DCRF_TRY_HIP(hipMemsetAsync(counts, 0, (size_t)(M + 1) * 4, s));
+    hipLaunchKernelGGL(k_csr_count, dim3(ceil_div((long long)cnt, 256)), dim3(256),
+                       0, s, cnt, L.pix_vid.as<int>(), counts);
+    scan_ints(ctx, counts, M, L.csr_off.as<int>());
+    DCRF_TRY_HIP(hipMemsetAsync(counts, 0, (size_t)(M + 1) * 4, s));
+    hipLaunchKernelGGL((k_csr_fill<T>), dim3(ceil_div((long long)cnt, 256)),
+                       dim3(256), 0, s, cnt, D1, L.pix_vid.as<int>(),
+                       L.pix_w.as<T>(), L.csr_off.as<int>(), counts,
+                       L.ent_pix.as<int>(), L.ent_w.as<T>(), L.ent_v.as<int>());
+    DCRF_TRY_HIP(hipMemcpyAsync(&L.nent, L.csr_off.as<int>() + M, 4,
+                                hipMemcpyDeviceToHost, s));
+    if (M > 0)
+        hipLaunchKernelGGL(k_chunk_count, dim3(ceil_div(M, 256)), dim3(256), 0, s,
+                           M, L.csr_off.as<int>(), L.chunk, counts);
+    L.chunk_off.ensure((size_t)(M + 1) * 4, s);
+    scan_ints(ctx, counts, M, L.chunk_off.as<int>());
+    int nch = 0;
+    DCRF_TRY_HIP(hipMemcpyAsync(&nch, L.chunk_off.as<int>() + M, 4,
+                                hipMemcpyDeviceToHost, s));
+    DCRF_TRY_HIP(hipStreamSynchronize(s));
+    L.nchunks = nch;
+    L.chunks.ensure((size_t)std::max(nch, 1) * sizeof(int4), s);
+    if (M > 0)
+        hipLaunchKernelGGL(k_chunk_fill, dim3(ceil_div(M, 256)), dim3(256), 0, s,
+                           M, L.csr_off.as<int>(), L.chunk_off.as<int>(), L.chunk,
+                           L.chunks.as<int4>());
+    DCRF_CHECK_LAUNCH();
+}
+
 template <int D, typename T>
 void build_one(dcrf_ctx *ctx, int m, const float *rgb, int *flags_dev) {
     Lattice &L = ctx->lat[m];
@@ -422,6 +559,7 @@ void build_one(dcrf_ctx *ctx, int m, const float *rgb, int *flags_dev) {
                        s, N, ctx->W, rgb, k.use_rgb, k.theta_pos, k.theta_rgb,
                        L.feat.as<T>());
     DCRF_CHECK_LAUNCH();
+    build_inverse_index<T>(ctx, m);
 }
 
 template <typename T>

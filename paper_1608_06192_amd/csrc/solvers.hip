@@ -5,21 +5,23 @@
 //   c = phi - d (eq. cvx-qp-min) or, inside CCCP, phi - 2 d * y^k
 //   (eq. cccp-qp), with (Psi y)_a(i) = sum_j mu_ij (K'Y)_a(j) and
 //   d_a(i) = (sum_j |mu_ij|) (K'1)_a (eq. pairwise-matrix, eq. RL-diagonal).
-// One iteration is three kinds of launch, with no host synchronisation:
+// One iteration is four kinds of launch, with no host synchronisation:
 //   1. k_fw_lmo: apply the previous step (y <- y + alpha (s - y) and
 //      P_y <- (1 - alpha) P_y + alpha P_s, App. B's recurrence), form the
 //      gradient g = c + 2 P_y (eq. LRQP-grad), take the conditional gradient
-//      s_a = argmin_i g_a(i) (eq. LRQP-lp, lowest label on ties), splat the
-//      one-hot s into the lattices, and reduce <y,P_y>, <s,P_y>, <c,y>,
-//      <c,s>, <g,y>, <g,s> per block;
-//   2. the blur passes;
-//   3. k_fw_slice: slice, apply mu and the diagonal, P_s = (Psi + D) s,
+//      s_a = argmin_i g_a(i) (eq. LRQP-lp, lowest label on ties), and reduce
+//      <y,P_y>, <s,P_y>, <c,y>, <c,s>, <g,y>, <g,s> per block;
+//   2. the gather splat of the one-hot s into the lattices;
+//   3. the blur passes;
+//   4. k_fw_slice: slice, apply mu and the diagonal, P_s = (Psi + D) s,
 //      reduce <y,P_s> and <s,P_s>; the last block to finish reduces every
 //      block's partial sums in a fixed order and solves the step size on the
 //      device (App. B, eq. alpha-opt, written with the four products so that
 //      it is exact for a non-symmetric approximate Psi; endpoints when the
 //      quadratic is not convex).
-// Dot products accumulate in FP64.
+// Up to 32 labels the per-pixel kernels keep a pixel's labels in registers
+// (one thread per pixel, rows staged through LDS); above that one lane per
+// (pixel, label). Dot products accumulate in FP64.
 
 #include <algorithm>
 #include <vector>
@@ -29,6 +31,9 @@
 
 namespace dcrf {
 
+void slice_into(dcrf_ctx *ctx, const void *Y, const void *pre, int C,
+                const void *mu, const void *mabs, void *out, bool qp);
+
 namespace {
 
 constexpr int kThreads = 256;
@@ -36,27 +41,8 @@ constexpr int kMaxGrid = 2048;
 constexpr int kP1 = 8;   // partial sums written by k_fw_lmo
 constexpr int kP2 = 2;   // partial sums written by k_fw_slice
 
-// scalar slots in fw_scal (doubles)
+// scalar slot in fw_scal (doubles): the step size of the last iteration
 constexpr int kAlpha = 0;
-constexpr int kCounter = 1;   // used as an unsigned int
-
-template <int NV>
-__device__ void block_reduce(double (&v)[NV], double *lds /* NV*kThreads */) {
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) lds[i * kThreads + t] = v[i];
-    __syncthreads();
-    for (int off = kThreads / 2; off > 0; off >>= 1) {
-        if (t < off)
-#pragma unroll
-            for (int i = 0; i < NV; ++i)
-                lds[i * kThreads + t] += lds[i * kThreads + t + off];
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = lds[i * kThreads];
-    __syncthreads();
-}
 
 template <typename T>
 __global__ void k_fill(T *p, size_t n, T v) {
@@ -92,20 +78,249 @@ __global__ void k_linear_term(int N, int L, const T *__restrict__ phi,
     c[e] = phi[e] - scale * mabs[i] * r[a] * z;
 }
 
+template <typename T>
+struct FWArgs {
+    int N, L;
+    T *y, *Py;
+    const T *Ps, *c;
+    int32_t *s;
+    const int32_t *sprev;
+    double *scal, *part;
+    int first;
+};
+
+template <typename T>
+struct FWSliceArgs {
+    int N, L;
+    const T *y;
+    const int32_t *s;
+    T *Ps;
+    const T *mu, *mabs, *r, *pre;
+    T wsum;
+    double *scal, *part1, *part2;
+    int G1;
+    double *trace;   // 4 doubles per iteration
+    int it;
+};
+
+// ---------------------------------------------------------- row kernels
+
+// Step 1, one thread per pixel (see the file comment).
+// Pixels per block of k_fw_lmo_rows: one staged tile at a time keeps the LDS
+// footprint small, so more blocks fit on a CU to hide memory latency.
+template <typename T> struct LmoTile;
+template <> struct LmoTile<float> { static constexpr int kPix = 256; };
+template <> struct LmoTile<double> { static constexpr int kPix = 128; };
+
+template <typename T, int LMAX>
+__global__ void __launch_bounds__(LmoTile<T>::kPix)
+k_fw_lmo_rows(FWArgs<T> A) {
+    constexpr int TP = LmoTile<T>::kPix;
+    __shared__ __align__(16) T lds[TP * (LMAX | 1)];
+    __shared__ double red[kP1 * TP];
+    const int L = A.L;
+    const T al = A.first ? T(0) : T(A.scal[kAlpha]);
+    double acc[kP1];
+#pragma unroll
+    for (int i = 0; i < kP1; ++i) acc[i] = 0.0;
+    for (long long p0 = (long long)blockIdx.x * TP; p0 < A.N;
+         p0 += (long long)gridDim.x * TP) {
+        const int np = (int)min((long long)TP, A.N - p0);
+        const long long a = p0 + threadIdx.x;
+        const bool act = (int)threadIdx.x < np;
+        T y[LMAX], py[LMAX], c[LMAX];
+#pragma unroll
+        for (int j = 0; j < LMAX; ++j) y[j] = py[j] = c[j] = T(0);
+        tile_load<T, LMAX, TP>(A.y, p0, np, L, lds, y);
+        tile_load<T, LMAX, TP>(A.Py, p0, np, L, lds, py);
+        const int sp = act ? A.sprev[a] : -1;
+        if (!A.first) {
+            T ps[LMAX];
+#pragma unroll
+            for (int j = 0; j < LMAX; ++j) ps[j] = T(0);
+            tile_load<T, LMAX, TP>(A.Ps, p0, np, L, lds, ps);
+#pragma unroll
+            for (int j = 0; j < LMAX; ++j) {
+                y[j] = y[j] + al * (T(j == sp ? 1 : 0) - y[j]);
+                py[j] = (T(1) - al) * py[j] + al * ps[j];
+            }
+            tile_store<T, LMAX, TP>(A.y, p0, np, L, lds, y);
+            tile_store<T, LMAX, TP>(A.Py, p0, np, L, lds, py);
+        }
+        tile_load<T, LMAX, TP>(A.c, p0, np, L, lds, c);
+        if (act) {
+            int best = 0;
+            T bv = c[0] + T(2) * py[0];
+#pragma unroll
+            for (int j = 1; j < LMAX; ++j) {
+                const T g = c[j] + T(2) * py[j];
+                if (j < L && g < bv) {
+                    bv = g;
+                    best = j;
+                }
+            }
+            A.s[a] = best;
+            acc[6] += (best != sp) ? 1.0 : 0.0;
+#pragma unroll
+            for (int j = 0; j < LMAX; ++j) {
+                if (j < L) {
+                    const double yv = y[j], pv = py[j], cv = c[j];
+                    const double gv = double(c[j] + T(2) * py[j]);
+                    acc[0] += yv * pv;
+                    acc[2] += cv * yv;
+                    acc[4] += gv * yv;
+                    if (j == best) {
+                        acc[1] += pv;
+                        acc[3] += cv;
+                        acc[5] += gv;
+                    }
+                }
+            }
+        }
+    }
+    block_sum<kP1, TP>(acc, red);
+    if (threadIdx.x < kP1) A.part[(size_t)blockIdx.x * kP1 + threadIdx.x] = acc[threadIdx.x];
+}
+
+// One block: fixed-order reduction of every block's partial sums, the exact
+// line search (App. B) and the trace entry. A launch of its own, so that the
+// partial sums of all blocks are visible without device-wide fences.
+template <int NT>
+__global__ void __launch_bounds__(NT)
+k_fw_alpha(const double *__restrict__ part1, int G1,
+           const double *__restrict__ part2, int G2, double *__restrict__ scal,
+           double *__restrict__ trace, int it) {
+    __shared__ double red[(kP1 + kP2) * NT];
+    const int t = threadIdx.x;
+    double tot[kP1 + kP2];
+#pragma unroll
+    for (int i = 0; i < kP1 + kP2; ++i) tot[i] = 0.0;
+    for (int b = t; b < G1; b += NT)
+#pragma unroll
+        for (int i = 0; i < kP1; ++i) tot[i] += part1[(size_t)b * kP1 + i];
+    for (int b = t; b < G2; b += NT)
+#pragma unroll
+        for (int i = 0; i < kP2; ++i) tot[kP1 + i] += part2[(size_t)b * kP2 + i];
+    block_sum<kP1 + kP2, NT>(tot, red);
+    if (t == 0) {
+        const double Ayy = tot[0], Csy = tot[1], cy = tot[2], cs = tot[3];
+        const double gy = tot[4], gs = tot[5], changed = tot[6];
+        const double Bys = tot[kP1 + 0], Dss = tot[kP1 + 1];
+        const double b1 = cs - cy + Bys + Csy - 2.0 * Ayy;
+        const double a2 = Dss - Bys - Csy + Ayy;
+        double alpha;
+        if (a2 > 0.0)
+            alpha = fmin(fmax(-b1 / (2.0 * a2), 0.0), 1.0);
+        else
+            alpha = (a2 + b1 < 0.0) ? 1.0 : 0.0;
+        scal[kAlpha] = alpha;
+        double *tr = trace + (size_t)it * 4;
+        tr[0] = cy + Ayy;        // f(y_t)
+        tr[1] = gy - gs;         // <g, y_t - s_t>
+        tr[2] = alpha;
+        tr[3] = changed;
+    }
+}
+
+// Step 4, one thread per pixel (see the file comment). POTTS: mu = 1 - I,
+// so (Q mu^T)_i = sum_j Q_j - Q_i.
+template <typename T, int LMAX, bool POTTS>
+__global__ void __launch_bounds__(RowTile<T>::kPix, 4)
+k_fw_slice_rows(FWSliceArgs<T> A, LatSet<T> ls) {
+    constexpr int TP = RowTile<T>::kPix;
+    __shared__ __align__(16) T lds[TP * (LMAX | 1)];
+    __shared__ T smu[POTTS ? 1 : LMAX * LMAX];
+    __shared__ double red[kP2 * TP];
+    const int L = A.L;
+    if (!POTTS) {
+        for (int i = threadIdx.x; i < L * L; i += TP)
+            smu[(i / L) * LMAX + (i % L)] = A.mu[i];
+        __syncthreads();
+    }
+    double acc[kP2] = {0.0, 0.0};
+    for (long long p0 = (long long)blockIdx.x * TP; p0 < A.N;
+         p0 += (long long)gridDim.x * TP) {
+        const int np = (int)min((long long)TP, A.N - p0);
+        const long long a = p0 + threadIdx.x;
+        const bool act = (int)threadIdx.x < np;
+        T q[LMAX];
+#pragma unroll
+        for (int j = 0; j < LMAX; ++j) q[j] = T(0);
+        const int sa = act ? A.s[a] : 0;
+        if (A.pre) {
+            tile_load<T, LMAX, TP>(A.pre, p0, np, L, lds, q);
+        } else if (act) {
+            slice_pixel<T, LMAX>(ls, a, L, q);
+#pragma unroll
+            for (int j = 0; j < LMAX; ++j)
+                if (j == sa) q[j] -= A.wsum;
+        }
+        T P[LMAX];
+        const T dself = act ? A.mabs[sa] * A.r[a] : T(0);
+        if (POTTS) {
+            T tot = T(0);
+#pragma unroll
+            for (int j = 0; j < LMAX; ++j) tot += (j < L) ? q[j] : T(0);
+#pragma unroll
+            for (int i = 0; i < LMAX; ++i)
+                P[i] = (i < L) ? (tot - q[i]) + (i == sa ? dself : T(0)) : T(0);
+        } else {
+            // general mu: q goes through this thread's own LDS row so that
+            // only the L accumulators stay live across the j loop
+            const int Ls = lds_stride(L);
+            T *qrow = lds + threadIdx.x * Ls;
+#pragma unroll
+            for (int j = 0; j < LMAX; ++j)
+                if (j < L) qrow[j] = q[j];
+#pragma unroll
+            for (int i = 0; i < LMAX; ++i) P[i] = T(0);
+            for (int j = 0; j < L; ++j) {
+                const T qj = qrow[j];
+#pragma unroll
+                for (int i = 0; i < LMAX; ++i) P[i] += smu[i * LMAX + j] * qj;
+            }
+#pragma unroll
+            for (int i = 0; i < LMAX; ++i)
+                P[i] = (i < L) ? P[i] + (i == sa ? dself : T(0)) : T(0);
+            __syncthreads();   // the tile buffer is reused by tile_load below
+        }
+        // y only now, to keep the register footprint of the gathers small
+        T y[LMAX];
+#pragma unroll
+        for (int j = 0; j < LMAX; ++j) y[j] = T(0);
+        tile_load<T, LMAX, TP>(A.y, p0, np, L, lds, y);
+        if (act) {
+#pragma unroll
+            for (int j = 0; j < LMAX; ++j) {
+                if (j < L) {
+                    acc[0] += double(y[j]) * double(P[j]);
+                    if (j == sa) acc[1] += double(P[j]);
+                }
+            }
+        }
+        tile_store<T, LMAX, TP>(A.Ps, p0, np, L, lds, P);
+    }
+    double v[kP2] = {acc[0], acc[1]};
+    block_sum<kP2, TP>(v, red);
+    if (threadIdx.x < kP2) A.part2[(size_t)blockIdx.x * kP2 + threadIdx.x] = v[threadIdx.x];
+}
+
+// ------------------------------------------------- flat kernels (L > 32)
+
 // (Psi + D) Y for a dense Y (or its K'Y given in `pre`), whole pixels per block
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_slice_qp(int N, int L, const T *__restrict__ Y, const T *__restrict__ pre,
-           LatSet<T> ls, T wsum, const T *__restrict__ mu,
-           const T *__restrict__ mabs, const T *__restrict__ r,
-           T *__restrict__ out) {
+k_slice_qp_flat(int N, int L, const T *__restrict__ Y, const T *__restrict__ pre,
+                LatSet<T> ls, T wsum, const T *__restrict__ mu,
+                const T *__restrict__ mabs, const T *__restrict__ r,
+                T *__restrict__ out) {
     __shared__ T sq[kThreads];
     const int ppb = kThreads / L;
     const int t = threadIdx.x;
     const int lp = t / L;
     const int l = t - lp * L;
     for (int g = blockIdx.x; (long long)g * ppb < N; g += gridDim.x) {
-        const int a = g * ppb + lp;
+        const long long a = (long long)g * ppb + lp;
         const bool act = lp < ppb && a < N;
         const size_t e = (size_t)a * L + l;
         T yv = T(0);
@@ -119,13 +334,11 @@ k_slice_qp(int N, int L, const T *__restrict__ Y, const T *__restrict__ pre,
                 for (int m = 0; m < ls.nk; ++m) {
                     const LatView<T> &Lt = ls.l[m];
                     const int D1 = Lt.d + 1;
-                    T s = T(0);
                     for (int k = 0; k < D1; ++k) {
-                        const int id = Lt.vid[(size_t)a * D1 + k];
+                        const int id = Lt.vid[a * D1 + k];
                         if (id >= 0)
-                            s += Lt.w[(size_t)a * D1 + k] * Lt.Vf[(size_t)id * L + l];
+                            q += Lt.wg * Lt.w[a * D1 + k] * Lt.Vf[(size_t)id * Lt.ld + l];
                     }
-                    q += Lt.wg * s;
                 }
                 q -= wsum * yv;
             }
@@ -143,20 +356,8 @@ k_slice_qp(int N, int L, const T *__restrict__ Y, const T *__restrict__ pre,
 }
 
 template <typename T>
-struct FWArgs {
-    int N, L;
-    T *y, *Py;
-    const T *Ps, *c;
-    int32_t *s;
-    const int32_t *sprev;
-    double *scal, *part;
-    int first;
-};
-
-// Step 1 of an iteration (see the file comment).
-template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_fw_lmo(FWArgs<T> A, LatSet<T> ls) {
+k_fw_lmo_flat(FWArgs<T> A) {
     __shared__ T sg[kThreads];
     __shared__ int sarg[kThreads];
     __shared__ double red[kP1 * kThreads];
@@ -165,16 +366,12 @@ k_fw_lmo(FWArgs<T> A, LatSet<T> ls) {
     const int t = threadIdx.x;
     const int lp = t / L;
     const int l = t - lp * L;
-    const double alpha = A.first ? 0.0 : A.scal[kAlpha];
-    const T al = T(alpha);
+    const T al = A.first ? T(0) : T(A.scal[kAlpha]);
     double acc[kP1];
 #pragma unroll
     for (int i = 0; i < kP1; ++i) acc[i] = 0.0;
-    int nvt = 0;
-    for (int m = 0; m < ls.nk; ++m) nvt += ls.l[m].d + 1;
-
     for (int g = blockIdx.x; (long long)g * ppb < A.N; g += gridDim.x) {
-        const int a = g * ppb + lp;
+        const long long a = (long long)g * ppb + lp;
         const bool act = lp < ppb && a < A.N;
         const size_t e = (size_t)a * L + l;
         T yv = T(0), pyv = T(0), cv = T(0), gv = T(0);
@@ -219,47 +416,18 @@ k_fw_lmo(FWArgs<T> A, LatSet<T> ls) {
                 acc[3] += double(cv);
                 acc[5] += double(gv);
             }
-            // splat the one-hot s: lanes of the pixel share its vertices
-            for (int q = l; q < nvt; q += L) {
-                int m = 0, k = q;
-                while (k > ls.l[m].d) {
-                    k -= ls.l[m].d + 1;
-                    ++m;
-                }
-                const LatView<T> &Lt = ls.l[m];
-                const int D1 = Lt.d + 1;
-                const int id = Lt.vid[(size_t)a * D1 + k];
-                if (id >= 0)
-                    atomic_add(&Lt.V0[(size_t)id * L + sl], Lt.w[(size_t)a * D1 + k]);
-            }
         }
         __syncthreads();
     }
-    block_reduce<kP1>(acc, red);
+    block_sum<kP1, kThreads>(acc, red);
     if (t < kP1) A.part[(size_t)blockIdx.x * kP1 + t] = acc[t];
 }
 
 template <typename T>
-struct FWSliceArgs {
-    int N, L;
-    const T *y;
-    const int32_t *s;
-    T *Ps;
-    const T *mu, *mabs, *r, *pre;
-    T wsum;
-    double *scal, *part1, *part2;
-    int G1;
-    double *trace;   // 4 doubles per iteration
-    int it;
-};
-
-// Step 3 of an iteration (see the file comment).
-template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_fw_slice(FWSliceArgs<T> A, LatSet<T> ls) {
+k_fw_slice_flat(FWSliceArgs<T> A, LatSet<T> ls) {
     __shared__ T sq[kThreads];
-    __shared__ double red[kP1 * kThreads];
-    __shared__ bool last;
+    __shared__ double red[kP2 * kThreads];
     const int L = A.L;
     const int ppb = kThreads / L;
     const int t = threadIdx.x;
@@ -267,7 +435,7 @@ k_fw_slice(FWSliceArgs<T> A, LatSet<T> ls) {
     const int l = t - lp * L;
     double acc[kP2] = {0.0, 0.0};
     for (int g = blockIdx.x; (long long)g * ppb < A.N; g += gridDim.x) {
-        const int a = g * ppb + lp;
+        const long long a = (long long)g * ppb + lp;
         const bool act = lp < ppb && a < A.N;
         const size_t e = (size_t)a * L + l;
         int sa = 0;
@@ -281,13 +449,11 @@ k_fw_slice(FWSliceArgs<T> A, LatSet<T> ls) {
                 for (int m = 0; m < ls.nk; ++m) {
                     const LatView<T> &Lt = ls.l[m];
                     const int D1 = Lt.d + 1;
-                    T sum = T(0);
                     for (int k = 0; k < D1; ++k) {
-                        const int id = Lt.vid[(size_t)a * D1 + k];
+                        const int id = Lt.vid[a * D1 + k];
                         if (id >= 0)
-                            sum += Lt.w[(size_t)a * D1 + k] * Lt.Vf[(size_t)id * L + l];
+                            q += Lt.wg * Lt.w[a * D1 + k] * Lt.Vf[(size_t)id * Lt.ld + l];
                     }
-                    q += Lt.wg * sum;
                 }
                 if (l == sa) q -= A.wsum;
             }
@@ -306,50 +472,11 @@ k_fw_slice(FWSliceArgs<T> A, LatSet<T> ls) {
         __syncthreads();
     }
     double v[kP2] = {acc[0], acc[1]};
-    block_reduce<kP2>(v, red);
+    block_sum<kP2, kThreads>(v, red);
     if (t < kP2) A.part2[(size_t)blockIdx.x * kP2 + t] = v[t];
-    __threadfence();
-    __syncthreads();
-    if (t == 0) {
-        unsigned int *ctr = reinterpret_cast<unsigned int *>(A.scal + kCounter);
-        unsigned int ticket = atomicAdd(ctr, 1u);
-        last = (ticket == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    // last block: fixed-order reduction of every block's partial sums
-    double tot[kP1 + kP2];
-#pragma unroll
-    for (int i = 0; i < kP1 + kP2; ++i) tot[i] = 0.0;
-    for (int b = t; b < A.G1; b += kThreads)
-#pragma unroll
-        for (int i = 0; i < kP1; ++i) tot[i] += A.part1[(size_t)b * kP1 + i];
-    for (int b = t; b < (int)gridDim.x; b += kThreads)
-#pragma unroll
-        for (int i = 0; i < kP2; ++i) tot[kP1 + i] += A.part2[(size_t)b * kP2 + i];
-    __shared__ double red2[(kP1 + kP2) * kThreads];
-    block_reduce<kP1 + kP2>(tot, red2);
-    if (t == 0) {
-        const double Ayy = tot[0], Csy = tot[1], cy = tot[2], cs = tot[3];
-        const double gy = tot[4], gs = tot[5], changed = tot[6];
-        const double Bys = tot[kP1 + 0], Dss = tot[kP1 + 1];
-        const double b1 = cs - cy + Bys + Csy - 2.0 * Ayy;
-        const double a2 = Dss - Bys - Csy + Ayy;
-        double alpha;
-        if (a2 > 0.0)
-            alpha = fmin(fmax(-b1 / (2.0 * a2), 0.0), 1.0);
-        else
-            alpha = (a2 + b1 < 0.0) ? 1.0 : 0.0;
-        A.scal[kAlpha] = alpha;
-        double *tr = A.trace + (size_t)A.it * 4;
-        tr[0] = cy + Ayy;        // f(y_t)
-        tr[1] = gy - gs;         // <g, y_t - s_t>
-        tr[2] = alpha;
-        tr[3] = changed;
-        *reinterpret_cast<unsigned int *>(A.scal + kCounter) = 0u;
-    }
 }
+
+// ------------------------------------------------------------ the rest
 
 // y <- y + alpha (s - y), P_y <- (1 - alpha) P_y + alpha P_s
 template <typename T>
@@ -411,7 +538,7 @@ k_energy(int N, int L, const T *__restrict__ phi, const int32_t *__restrict__ x,
     const int l = t - lp * L;
     double acc[1] = {0.0};
     for (int g = blockIdx.x; (long long)g * ppb < N; g += gridDim.x) {
-        const int a = g * ppb + lp;
+        const long long a = (long long)g * ppb + lp;
         if (lp < ppb && a < N) {
             const size_t e = (size_t)a * L + l;
             const int xa = x[a];
@@ -424,13 +551,11 @@ k_energy(int N, int L, const T *__restrict__ phi, const int32_t *__restrict__ x,
                 for (int m = 0; m < ls.nk; ++m) {
                     const LatView<T> &Lt = ls.l[m];
                     const int D1 = Lt.d + 1;
-                    T sum = T(0);
                     for (int k = 0; k < D1; ++k) {
-                        const int id = Lt.vid[(size_t)a * D1 + k];
+                        const int id = Lt.vid[a * D1 + k];
                         if (id >= 0)
-                            sum += Lt.w[(size_t)a * D1 + k] * Lt.Vf[(size_t)id * L + l];
+                            q += Lt.wg * Lt.w[a * D1 + k] * Lt.Vf[(size_t)id * Lt.ld + l];
                     }
-                    q += Lt.wg * sum;
                 }
                 if (l == xa) q -= wsum;
             }
@@ -438,7 +563,7 @@ k_energy(int N, int L, const T *__restrict__ phi, const int32_t *__restrict__ x,
             if (l == xa) acc[0] += double(phi[e]);
         }
     }
-    block_reduce<1>(acc, red);
+    block_sum<1, kThreads>(acc, red);
     if (t == 0) part[blockIdx.x] = acc[0];
 }
 
@@ -458,13 +583,18 @@ k_S_value(int N, int L, const T *__restrict__ phi, const T *__restrict__ y,
         acc[0] += double(phi[e]) * yv + yv * double(Py[e]) -
                   double(mabs[i]) * double(r[a]) * yv * yv;
     }
-    block_reduce<1>(acc, red);
+    block_sum<1, kThreads>(acc, red);
     if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
 }
 
-int grid_for(int N, int L) {
+int grid_flat(int N, int L) {
     const int ppb = kThreads / L;
     return std::max(1, std::min(kMaxGrid, ceil_div(N, ppb)));
+}
+
+template <typename T>
+int grid_rows(int N) {
+    return std::max(1, std::min(kMaxGrid, ceil_div(N, RowTile<T>::kPix)));
 }
 
 double sum_partials(dcrf_ctx *ctx, const double *dpart, int n) {
@@ -479,7 +609,7 @@ double sum_partials(dcrf_ctx *ctx, const double *dpart, int n) {
 
 template <typename T>
 struct Work {
-    T *c, *Py, *Ps, *mabs, *mu;
+    T *c, *Py, *Ps, *mabs;
     int32_t *s, *sprev;
     double *part1, *part2, *scal, *trace;
 };
@@ -517,7 +647,6 @@ void qp_apply_t(dcrf_ctx *ctx, const T *y, const T *mu, int L, const T *mabs,
     const hipStream_t st = ctx->stream;
     const int N = ctx->N;
     const T *pre = nullptr;
-    LatSet<T> ls{};
     if (ctx->mode == DCRF_FILTER_EXACT) {
         ctx->tmpA.ensure((size_t)N * L * sizeof(T), st);
         filter_apply(ctx, y, ctx->tmpA.p, L, false, true);
@@ -525,12 +654,30 @@ void qp_apply_t(dcrf_ctx *ctx, const T *y, const T *mu, int L, const T *mabs,
     } else {
         splat_dense(ctx, y, L);
         blur_all(ctx, L, false);
-        ls = make_lat_set<T>(ctx, L);
     }
-    hipLaunchKernelGGL((k_slice_qp<T>), dim3(grid_for(N, L)), dim3(kThreads), 0,
-                       st, N, L, y, pre, ls, T(ctx->wsum), mu, mabs,
-                       ctx->r.as<T>(), out);
+    if (L <= kRowMaxC) {
+        slice_into(ctx, y, pre, L, mu, mabs, out, true);
+        return;
+    }
+    LatSet<T> ls = make_lat_set<T>(ctx, L);
+    ProfScope ps(ctx, PROF_SLICE_QP);
+    hipLaunchKernelGGL((k_slice_qp_flat<T>), dim3(grid_flat(N, L)),
+                       dim3(kThreads), 0, st, N, L, y, pre, ls, T(ctx->wsum),
+                       mu, mabs, ctx->r.as<T>(), out);
     DCRF_CHECK_LAUNCH();
+}
+
+// Whether mu is the Potts compatibility [i != j] (read once per solve).
+template <typename T>
+bool is_potts(dcrf_ctx *ctx, const T *mu, int L) {
+    std::vector<T> h((size_t)L * L);
+    DCRF_TRY_HIP(hipMemcpyAsync(h.data(), mu, h.size() * sizeof(T),
+                                hipMemcpyDeviceToHost, ctx->stream));
+    DCRF_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    for (int i = 0; i < L; ++i)
+        for (int j = 0; j < L; ++j)
+            if (h[(size_t)i * L + j] != T(i != j ? 1 : 0)) return false;
+    return true;
 }
 
 template <typename T>
@@ -553,14 +700,33 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
     DCRF_CHECK_LAUNCH();
 
     const bool exact = ctx->mode == DCRF_FILTER_EXACT;
+    const bool rows = L <= kRowMaxC;
     if (!exact) ensure_vertex_buffers(ctx, L);
-    if (exact) ctx->tmpA.ensure(NL * sizeof(T), st), ctx->tmpB.ensure(NL * sizeof(T), st);
-    const int G = grid_for(N, L);
+    if (exact) {
+        ctx->tmpA.ensure(NL * sizeof(T), st);
+        ctx->tmpB.ensure(NL * sizeof(T), st);
+    }
+    // grids of the per-pixel kernels (k_fw_lmo: G1 blocks, k_fw_slice: G2)
+    constexpr int TP1 = LmoTile<T>::kPix;
+    constexpr int TP = RowTile<T>::kPix;
+    const int G1 = rows ? std::max(1, std::min(kMaxGrid, ceil_div(N, TP1)))
+                        : grid_flat(N, L);
+    const int G = rows ? grid_rows<T>(N) : grid_flat(N, L);
+    const bool potts = is_potts<T>(ctx, mu, L);
+    const LatSet<T> ls = exact ? LatSet<T>{} : make_lat_set<T>(ctx, L);
     for (int it = 0; it < iters; ++it) {
         FWArgs<T> a{N, L, y, w.Py, w.Ps, w.c, w.s, w.sprev, w.scal, w.part1,
                     it == 0 ? 1 : 0};
-        LatSet<T> ls = exact ? LatSet<T>{} : make_lat_set<T>(ctx, L);
-        hipLaunchKernelGGL((k_fw_lmo<T>), dim3(G), dim3(kThreads), 0, st, a, ls);
+        {
+            ProfScope ps(ctx, PROF_FW_LMO);
+            if (rows) {
+                DCRF_DISPATCH_ROWS(L, hipLaunchKernelGGL((k_fw_lmo_rows<T, LMAX>),
+                                                         dim3(G1), dim3(TP1), 0, st, a));
+            } else {
+                hipLaunchKernelGGL((k_fw_lmo_flat<T>), dim3(G1), dim3(kThreads), 0,
+                                   st, a);
+            }
+        }
         const T *pre = nullptr;
         if (exact) {
             hipLaunchKernelGGL((k_onehot<T>), dim3(gE), dim3(256), 0, st, N, L,
@@ -568,11 +734,32 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
             filter_apply(ctx, ctx->tmpB.p, ctx->tmpA.p, L, false, true);
             pre = ctx->tmpA.as<T>();
         } else {
+            splat_labels(ctx, w.s, L);
             blur_all(ctx, L, false);
         }
         FWSliceArgs<T> b{N, L, y, w.s, w.Ps, mu, w.mabs, ctx->r.as<T>(), pre,
-                         T(ctx->wsum), w.scal, w.part1, w.part2, G, w.trace, it};
-        hipLaunchKernelGGL((k_fw_slice<T>), dim3(G), dim3(kThreads), 0, st, b, ls);
+                         T(ctx->wsum), w.scal, w.part1, w.part2, G1, w.trace, it};
+        {
+            ProfScope ps(ctx, PROF_FW_SLICE);
+            if (rows) {
+                if (potts)
+                    DCRF_DISPATCH_ROWS(L, hipLaunchKernelGGL(
+                        (k_fw_slice_rows<T, LMAX, true>), dim3(G), dim3(TP), 0, st,
+                        b, ls));
+                else
+                    DCRF_DISPATCH_ROWS(L, hipLaunchKernelGGL(
+                        (k_fw_slice_rows<T, LMAX, false>), dim3(G), dim3(TP), 0,
+                        st, b, ls));
+            } else {
+                hipLaunchKernelGGL((k_fw_slice_flat<T>), dim3(G), dim3(kThreads),
+                                   0, st, b, ls);
+            }
+        }
+        {
+            ProfScope ps(ctx, PROF_FW_ALPHA);
+            hipLaunchKernelGGL((k_fw_alpha<512>), dim3(1), dim3(512), 0,
+                               st, w.part1, G1, w.part2, G, w.scal, w.trace, it);
+        }
         DCRF_CHECK_LAUNCH();
         std::swap(w.s, w.sprev);
     }
@@ -581,12 +768,6 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
         hipLaunchKernelGGL((k_fw_final<T>), dim3(gE), dim3(256), 0, st, N, L, y,
                            w.Py, w.Ps, w.sprev, w.scal);
         DCRF_CHECK_LAUNCH();
-    }
-    // keep the buffer roles stable for the next call (s / sprev swapped)
-    if (iters % 2 == 1) {
-        void *p = ctx->fw_s.p;
-        ctx->fw_s.p = ctx->fw_sprev.p;
-        ctx->fw_sprev.p = p;
     }
     if (trace && iters > 0) {
         std::vector<double> h((size_t)iters * 4);
@@ -655,7 +836,7 @@ double energy_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L,
         ls = make_lat_set<T>(ctx, L);
     }
     ctx->fw_part.ensure((size_t)kMaxGrid * (kP1 + kP2) * 8, st);
-    const int G = grid_for(N, L);
+    const int G = grid_flat(N, L);
     hipLaunchKernelGGL((k_energy<T>), dim3(G), dim3(kThreads), 0, st, N, L, phi,
                        x, pre, ls, T(ctx->wsum), mu, ctx->fw_part.as<double>());
     DCRF_CHECK_LAUNCH();

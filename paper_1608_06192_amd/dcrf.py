@@ -62,7 +62,12 @@ PROTOTYPES = {
     "dcrf_dc_gen": (_I, [_P, _P, _P, _I, _P, _I, _I, _PD]),
     "dcrf_round": (_I, [_P, _P, _I, _P]),
     "dcrf_energy": (_I, [_P, _P, _P, _I, _P, _PD]),
+    "dcrf_set_profiling": (_I, [_P, _I]),
+    "dcrf_get_profile": (_I, [_P, _I, ctypes.POINTER(ctypes.c_char_p), _PD,
+                              ctypes.POINTER(ctypes.c_longlong)]),
 }
+
+PROF_CLASSES = 8
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -212,6 +217,20 @@ class Context:
         self._check(_lib.dcrf_round(self._h, self._arg(y), y.shape[1],
                                     _ptr(lab)))
         return lab
+
+    # -- profiling -------------------------------------------------------
+    def set_profiling(self, on: bool):
+        self._check(_lib.dcrf_set_profiling(self._h, int(on)))
+
+    def profile(self):
+        """{kernel name: (total ms, launches)} since profiling was enabled."""
+        out = {}
+        for k in range(PROF_CLASSES):
+            name, ms, n = ctypes.c_char_p(), ctypes.c_double(), ctypes.c_longlong()
+            self._check(_lib.dcrf_get_profile(self._h, k, ctypes.byref(name),
+                                              ctypes.byref(ms), ctypes.byref(n)))
+            out[name.value.decode()] = (ms.value, n.value)
+        return out
 
     def energy(self, unary, mu, labels: torch.Tensor) -> float:
         e = ctypes.c_double()

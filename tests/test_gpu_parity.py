@@ -160,8 +160,73 @@ def test_fw_fp64_matches_oracle(mode):
     assert abs(e - eo) <= 1e-10 * abs(eo)
 
 
-def test_fw_fp32_matches_oracle_320x213():
-    # 320x213, L = 21, FP32 marginals, 50 iterations
+def test_fw_fp64_matches_oracle_320x213():
+    # 320x213, L = 21, 50 iterations in FP64 on both sides: every argmin is
+    # decided in the same precision, so the whole trajectory must agree
+    im = synth.make("voronoi_320x213_L21")
+    ctx = gpu_ctx(im, torch.float64)
+    mu = synth.potts(im.L)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    qp = O.QP(model, im.unary, mu)
+    y0 = O.softmax_neg(im.unary)
+    st = O.frank_wolfe(qp, y0, 50)
+    y = T(y0, torch.float64)
+    tr = ctx.qp_frank_wolfe(T(im.unary, torch.float64), T(mu, torch.float64),
+                            y, 50)
+    err = np.abs(y.cpu().numpy() - st.y).max()
+    print("max |y_gpu - y_oracle| =", err)
+    assert err < 1e-8
+    for (fo, go, ao), (fg, gg, ag, _) in zip(st.trace, tr):
+        assert abs(fg - fo) <= 1e-9 * abs(fo)
+        assert abs(ag - ao) <= 1e-7
+
+
+def _eps_argmin_ok(g, s, rel=1e-5):
+    """s[a] is a valid conditional gradient of g up to FP32 rounding: its
+    gradient is within rel * scale of the minimum (scale = row max |g|)."""
+    gmin = g.min(axis=1)
+    scale = np.abs(g).max(axis=1)
+    return g[np.arange(g.shape[0]), s] <= gmin + rel * scale
+
+
+@pytest.mark.parametrize("t0", [0, 10, 30])
+def test_fw_fp32_step_matches_oracle_320x213(t0):
+    # one FP32 GPU iteration from the oracle's iterate y_t0 (rounded to FP32):
+    # the conditional gradient must be a valid argmin of the oracle's
+    # gradient at every pixel, and the step size must agree
+    im = synth.make("voronoi_320x213_L21")
+    ctx = gpu_ctx(im, torch.float32)
+    mu = synth.potts(im.L)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    qp = O.QP(model, im.unary, mu)
+    yt = O.frank_wolfe(qp, O.softmax_neg(im.unary), t0).y
+    yt = yt.astype(np.float32).astype(np.float64)
+    yt /= yt.sum(axis=1, keepdims=True)
+    yt = yt.astype(np.float32).astype(np.float64)
+    st = O.frank_wolfe(qp, yt, 1)
+    g = qp.phi - qp.d + 2 * qp.Q(yt)
+    y = T(yt, torch.float32)
+    tr = ctx.qp_frank_wolfe(T(im.unary, torch.float32), T(mu, torch.float32),
+                            y, 1)
+    ag = tr[0][2]
+    y1 = y.cpu().numpy().astype(np.float64)
+    s_gpu = np.argmax(y1 - (1 - ag) * yt, axis=1)
+    s_or = st.s_hist[0]
+    ok = _eps_argmin_ok(g, s_gpu)
+    print(f"t0={t0} alpha gpu={ag:.6g} oracle={st.alphas[0]:.6g} "
+          f"s differs at {(s_gpu != s_or).sum()} pixels")
+    assert ok.all()
+    assert abs(ag - st.alphas[0]) <= 1e-4 * max(1.0, abs(st.alphas[0]))
+    assert abs(tr[0][0] - st.trace[0][0]) <= 1e-5 * abs(st.trace[0][0])
+    same = s_gpu == s_or
+    assert np.abs(y1[same] - st.y[same]).max() < 1e-4
+
+
+def test_fw_fp32_trajectory_320x213():
+    # 320x213, L = 21, FP32 marginals, 50 iterations. FP32 and FP64 may take
+    # different (equally valid) conditional gradients at near-ties, so the
+    # trajectories are compared through objectives, energies and the share of
+    # marginals that agree to 1e-4.
     im = synth.make("voronoi_320x213_L21")
     ctx = gpu_ctx(im, torch.float32)
     mu = synth.potts(im.L)
@@ -173,15 +238,47 @@ def test_fw_fp32_matches_oracle_320x213():
     tr = ctx.qp_frank_wolfe(T(im.unary, torch.float32), T(mu, torch.float32),
                             y, 50)
     yg = y.cpu().numpy().astype(np.float64)
-    err = np.abs(yg - st.y).max()
-    print("max |y_gpu - y_oracle| =", err)
-    assert err < 1e-4
-    fo, fg = st.trace[-1][0], tr[-1][0]
-    assert abs(fg - fo) <= 1e-4 * abs(fo)
+    diff = np.abs(yg - st.y)
+    print(f"max |dy| = {diff.max():.3g}, share > 1e-4: {(diff > 1e-4).mean():.3g}")
+    assert (diff > 1e-4).mean() < 1e-3
+    for (fo, _, _), (fg, _, _, _) in zip(st.trace, tr):
+        assert abs(fg - fo) <= 1e-4 * abs(fo)
     lab = ctx.round(y)
     e = ctx.energy(T(im.unary, torch.float32), T(mu, torch.float32), lab)
-    eo = O.energy(model, im.unary, mu, lab.cpu().numpy())
-    assert abs(e - eo) <= 1e-5 * abs(eo)
+    eo_same = O.energy(model, im.unary, mu, lab.cpu().numpy())
+    assert abs(e - eo_same) <= 1e-5 * abs(eo_same)
+    eo = O.energy(model, im.unary, mu, O.round_argmax(st.y))
+    print(f"energy gpu {e:.8g} oracle {eo:.8g}")
+    assert abs(e - eo) <= 1e-4 * abs(eo)
+
+
+@pytest.mark.parametrize("L,general_mu", [(3, True), (32, False), (40, False),
+                                          (40, True)])
+def test_fw_fp64_label_counts_and_general_mu(L, general_mu):
+    # 32 labels: the largest per-thread register rows; 40: one lane per
+    # (pixel, label); a general (non-Potts) symmetric compatibility
+    im = synth.voronoi_image(19, 23, L, seed=40 + L, regions=5)
+    ctx = gpu_ctx(im, torch.float64)
+    rng = np.random.default_rng(L)
+    if general_mu:
+        mu = rng.uniform(0.2, 2.0, size=(L, L))
+        mu = 0.5 * (mu + mu.T)
+        np.fill_diagonal(mu, 0.0)
+    else:
+        mu = synth.potts(L)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    qp = O.QP(model, im.unary, mu)
+    y0 = O.softmax_neg(im.unary)
+    st = O.frank_wolfe(qp, y0, 8)
+    y = T(y0, torch.float64)
+    tr = ctx.qp_frank_wolfe(T(im.unary, torch.float64), T(mu, torch.float64),
+                            y, 8)
+    assert np.abs(y.cpu().numpy() - st.y).max() < 1e-9
+    for (fo, _, ao), (fg, _, ag, _) in zip(st.trace, tr):
+        assert abs(fg - fo) <= 1e-9 * abs(fo)
+        assert abs(ag - ao) <= 1e-8
+    g = ctx.filter(T(im.unary, torch.float64)).cpu().numpy()
+    assert np.abs(g - model.Kp(im.unary)).max() <= 1e-10 * np.abs(g).max()
 
 
 def test_energy_random_labels():
