@@ -107,6 +107,8 @@ def main():
     ap.add_argument("--filter-reps", type=int, default=200)
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--lp-steps", type=int, default=3)
+    ap.add_argument("--lp-beta0", type=float, default=1e-4)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -181,6 +183,20 @@ def main():
     log(f"[bench] dense filter L=21: {f_ms * 1e3:.1f} us, "
         f"{filt['GBps']:.0f} GB/s algorithmic")
 
+    # ---- LP subgradient steps from the QP solution -------------------------
+    lp = None
+    if args.lp_steps > 0:
+        ylp = y.clone()                       # the timed QP solve's result
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        best, hist = ctx.lp_descent(phi, ylp, args.lp_steps, args.lp_beta0)
+        torch.cuda.synchronize()
+        lp_ms = (time.perf_counter() - t0) * 1e3 / args.lp_steps
+        lp = dict(ms_per_step=lp_ms, steps=args.lp_steps, beta0=args.lp_beta0,
+                  S_LP_first=hist[0], S_LP_best=best)
+        log(f"[bench] LP subgradient step (divide and conquer, 21 labels, "
+            f"{int(np.ceil(np.log2(N)))} levels): {lp_ms:.1f} ms")
+
     # ---- roofline of the dominant kernel of the step ----------------------
     dom = max(per_iter, key=lambda k: per_iter[k][0] * per_iter[k][1])
     dom_ms = per_iter[dom][0]
@@ -208,7 +224,7 @@ def main():
                            lattice_vertices=[M for d, M in lat]),
                lattice_filter=filt, step_bytes=fw_step_bytes(N, L, 4, lat),
                per_kernel_us={k: v[0] * 1e3 for k, v in per_iter.items()},
-               roofline=roofline)
+               lp=lp, roofline=roofline)
     if not args.no_cpu:
         log(f"[bench] CPU baseline: {args.cpu_iters} oracle FW iterations ...")
         res["cpu_baseline"] = cpu_baseline(im, kernels, mu_np, args.cpu_iters)

@@ -170,6 +170,35 @@ int dcrf_round(dcrf_ctx *ctx, const void *y, int L, int32_t *labels);
 int dcrf_energy(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
                 const int32_t *labels, double *energy);
 
+/* ---- LP relaxation (Potts) --------------------------------------------- */
+
+/* One subgradient of the LP relaxation of the Potts model (Sec. 6,
+ * eq. potts-lp) at y: g_c(i) = phi_c(i) + sum_{a after c} Kbar_ac
+ * - sum_{a before c} Kbar_ac, the order being y(:, i) descending with ties by
+ * ascending pixel index (eq. simple_S, eq. grad_lp). The two sums are computed
+ * by the divide and conquer of App. E (nodes split at floor((2n+1) N / 2^(l+1))
+ * at level l), each node's filter on a permutohedral lattice built on the
+ * node's points; with DCRF_FILTER_EXACT they are summed exactly, O(N^2) per
+ * label. unary, y: (dev) N x L (y in the feasible set); g: (dev) N x L out;
+ * *S_lp (host) = <g, y>, the LP objective at y. Waits for the stream. The
+ * label compatibility is Potts; no mu argument is taken. */
+int dcrf_lp_subgradient(dcrf_ctx *ctx, const void *unary, int L, const void *y,
+                        void *g, double *S_lp);
+
+/* Projected subgradient descent on the LP (Alg. lp_subgrad): `steps` steps
+ * y <- Pi(y - beta_t g), beta_t = beta0 / (1 + t) for t = 0, 1, ..., Pi the
+ * Euclidean projection onto the product of simplices. y_inout (dev N x L):
+ * start and result. best_obj (host, may be NULL): the smallest S_LP met;
+ * best_y (dev N x L, may be NULL, not aliasing y): the iterate that had it;
+ * hist (host, `steps` values, may be NULL): S_LP(y_t). */
+int dcrf_lp_descent(dcrf_ctx *ctx, const void *unary, int L, void *y_inout,
+                    int steps, double beta0, double *best_obj, void *best_y,
+                    double *hist);
+
+/* y = Euclidean projection of each row of v onto the simplex (sort-based
+ * rule). v, y: (dev) N x L; may be the same array. */
+int dcrf_project_simplex(dcrf_ctx *ctx, const void *v, int L, void *y);
+
 /* ---- benchmarking support ---------------------------------------------- */
 
 /* Turn per-kernel timing on or off (and reset the counters). While on, each

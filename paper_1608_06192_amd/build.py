@@ -31,13 +31,14 @@ COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-    "-Wall", "-Wno-unused-result",
+    "-Wall", "-Wno-unused-result", "-Wno-pass-failed",
 ]
 
 SOURCES = {
     "lattice.hip": ["-ffp-contract=off"],
     "filter.hip": [],
     "solvers.hip": [],
+    "lp.hip": [],
     "abi.cpp": ["-x", "hip"],
 }
 

@@ -88,6 +88,7 @@ int dcrf_destroy(dcrf_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     for (auto &L : ctx->lat) L.release();
+    dcrf::lp_release(ctx);
     ctx->prof.release();
     for (dcrf::DevBuf *b :
          {&ctx->r, &ctx->scratch, &ctx->tmpA, &ctx->tmpB, &ctx->fw_c,
@@ -248,6 +249,41 @@ int dcrf_energy(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
         check_labels(L);
         REQUIRE(unary && mu && labels && energy, "null argument");
         *energy = dcrf::energy(ctx, unary, mu, L, labels);
+    });
+}
+
+int dcrf_lp_subgradient(dcrf_ctx *ctx, const void *unary, int L, const void *y,
+                        void *g, double *S_lp) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        check_labels(L);
+        REQUIRE(unary && y && g && y != g, "null or aliased argument");
+        const double S = dcrf::lp_subgradient(ctx, unary, L, y, g);
+        if (S_lp) *S_lp = S;
+    });
+}
+
+int dcrf_lp_descent(dcrf_ctx *ctx, const void *unary, int L, void *y_inout,
+                    int steps, double beta0, double *best_obj, void *best_y,
+                    double *hist) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        check_labels(L);
+        REQUIRE(unary && y_inout, "null argument");
+        REQUIRE(steps >= 0, "steps must be >= 0");
+        REQUIRE(std::isfinite(beta0) && beta0 > 0, "beta0 must be > 0");
+        REQUIRE(best_y != y_inout, "best_y must not alias y");
+        dcrf::lp_descent(ctx, unary, L, y_inout, steps, beta0, best_obj, best_y,
+                         hist);
+    });
+}
+
+int dcrf_project_simplex(dcrf_ctx *ctx, const void *v, int L, void *y) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        check_labels(L);
+        REQUIRE(v && y, "null argument");
+        dcrf::project_simplex(ctx, v, L, y);
     });
 }
 

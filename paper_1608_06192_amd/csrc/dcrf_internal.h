@@ -180,6 +180,7 @@ struct dcrf_ctx {
     // Frank-Wolfe state
     dcrf::DevBuf fw_c, fw_Py, fw_Ps, fw_s, fw_sprev, fw_part, fw_scal,
         fw_trace, fw_mu;
+    void *lp = nullptr;      // LP divide-and-conquer workspace (lp.hip)
     dcrf::Profiler prof;
     std::string err;
     size_t elt() const { return dtype == DCRF_F64 ? 8 : 4; }
@@ -224,6 +225,14 @@ void dc_gen(dcrf_ctx *ctx, const void *unary, const void *mu, int L, void *y,
 void round_labels(dcrf_ctx *ctx, const void *y, int L, int32_t *labels);
 double energy(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
               const int32_t *labels);
+
+// lp.hip
+double lp_subgradient(dcrf_ctx *ctx, const void *unary, int L, const void *y,
+                      void *g);
+void lp_descent(dcrf_ctx *ctx, const void *unary, int L, void *y, int steps,
+                double beta0, double *best, void *best_y, double *hist);
+void project_simplex(dcrf_ctx *ctx, const void *v, int L, void *y);
+void lp_release(dcrf_ctx *ctx);
 
 inline int ceil_div(long long a, long long b) { return int((a + b - 1) / b); }
 

@@ -1,0 +1,711 @@
+// The LP relaxation of the Potts model (Sec. 6) on the device.
+//
+// Subgradient (eq. grad_lp): for each label i, order the pixels by y_a(i),
+// descending (eq. simple_S; equal values keep ascending pixel index), and let
+//   U_c = sum over pixels a after c of Kbar_ac,  Lo_c = sum over a before c,
+// then g_c(i) = phi_c(i) + U_c - Lo_c and S_LP(y) = <g, y>.
+//
+// The two triangular sums are computed by the divide and conquer of App. E,
+// level by level. At level l the sorted positions are split into nodes with
+// boundaries floor(n N / 2^l); node n splits at floor((2n+1) N / 2^(l+1)).
+// For every node with two non-empty halves, the indicator of the left half
+// (channel 0) and of the right half (channel 1) are filtered over the node's
+// points only: the right channel read at left points adds to U, the left
+// channel read at right points adds to Lo. "Over the node's points only"
+// means a permutohedral lattice built on those points: its vertices are the
+// (node, global vertex) pairs touched by the node's points, found with a
+// device hash keyed by node * M + v, and its blur follows the global
+// neighbour table, keeping neighbours present in the same node.
+// All nodes of a level are filtered in one pass; labels are processed one at
+// a time (their hash tables then stay cache-resident).
+//
+// With the exact filter mode the two sums are computed directly, O(N^2) per
+// label (the definition that the divide and conquer reproduces).
+//
+// Projected subgradient descent (Alg. lp_subgrad): y <- Pi(y - beta_t g),
+// beta_t = beta0 / (1 + t), Pi the Euclidean projection of each pixel's row
+// onto the simplex by the sort-based rule (one thread per pixel, a bitonic
+// network in registers).
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "dcrf_internal.h"
+#include "hash_scan.h"
+#include "kernels_common.h"
+
+namespace dcrf {
+namespace {
+
+// ------------------------------------------------------------ radix sort
+
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 8;
+constexpr int kRsTile = kRsThreads * kRsItems;
+
+// key for an ascending sort that orders y descending; -0 counts as +0
+__device__ __forceinline__ uint32_t desc_key(float v) {
+    if (v == 0.0f) v = 0.0f;
+    const uint32_t u = __float_as_uint(v);
+    return (u & 0x80000000u) ? u : (~u & 0x7fffffffu);
+}
+__device__ __forceinline__ uint64_t desc_key(double v) {
+    if (v == 0.0) v = 0.0;
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    return (u & 0x8000000000000000ull) ? u : (~u & 0x7fffffffffffffffull);
+}
+
+template <typename T, typename K>
+__global__ void k_rs_init(int N, int L, int col, const T *__restrict__ y,
+                          K *__restrict__ keys, int *__restrict__ vals) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= N) return;
+    keys[a] = desc_key(y[(size_t)a * L + col]);
+    vals[a] = a;
+}
+
+// digit histogram of each tile, digit-major: hist[d * ntiles + tile]
+template <typename K>
+__global__ void __launch_bounds__(kRsThreads)
+k_rs_hist(const K *__restrict__ keys, int n, int shift, int ntiles,
+          int *__restrict__ hist) {
+    __shared__ int cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const long long base = (long long)blockIdx.x * kRsTile;
+    for (int r = 0; r < kRsItems; ++r) {
+        const long long i = base + (long long)r * kRsThreads + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[int((keys[i] >> shift) & 0xffu)], 1);
+    }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// stable scatter: elements keep their order within each digit. Each round of
+// kRsThreads elements is ranked per wave with ballots (lanes with the same
+// digit), then across the block's waves with LDS counts.
+template <typename K>
+__global__ void __launch_bounds__(kRsThreads)
+k_rs_scatter(const K *__restrict__ keys, const int *__restrict__ vals, int n,
+             int shift, int ntiles, const int *__restrict__ offs,
+             K *__restrict__ keys_out, int *__restrict__ vals_out) {
+    constexpr int kWaves = kRsThreads / 64;
+    __shared__ int wcount[kWaves][256];
+    __shared__ int running[256];
+    const int t = threadIdx.x;
+    const int wave = t >> 6;
+    const int lane = t & 63;
+    running[t] = offs[(size_t)t * ntiles + blockIdx.x];
+    const long long base = (long long)blockIdx.x * kRsTile;
+    for (int r = 0; r < kRsItems; ++r) {
+        for (int w = 0; w < kWaves; ++w) wcount[w][t] = 0;
+        __syncthreads();
+        const long long i = base + (long long)r * kRsThreads + t;
+        const bool valid = i < n;
+        K key = valid ? keys[i] : K(0);
+        const int dg = int((key >> shift) & 0xffu);
+        unsigned long long m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (dg >> b) & 1;
+            const unsigned long long bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        const int rank = __popcll(m & ((1ull << lane) - 1ull));
+        if (valid && lane == __ffsll((long long)m) - 1) wcount[wave][dg] = __popcll(m);
+        __syncthreads();
+        if (valid) {
+            int pos = running[dg] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcount[w][dg];
+            keys_out[pos] = key;
+            vals_out[pos] = vals[i];
+        }
+        __syncthreads();
+        int tot = 0;
+        for (int w = 0; w < kWaves; ++w) tot += wcount[w][t];
+        running[t] += tot;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------- divide and conquer
+
+// node of sorted position p at level l and whether both of its halves are
+// non-empty; side 0 = left half, 1 = right half
+__device__ __forceinline__ bool dnc_node(long long p, int l, long long N,
+                                         long long &node, int &side) {
+    node = (((p + 1) << l) - 1) / N;
+    const long long lo = (node * N) >> l;
+    const long long hi = ((node + 1) * N) >> l;
+    const long long mid = ((2 * node + 1) * N) >> (l + 1);
+    side = p < mid ? 0 : 1;
+    return lo < mid && mid < hi;
+}
+
+// insert the (node, vertex) keys of every entry (position p, vertex k)
+__global__ void k_lp_insert(int N, int l, int D1, int M,
+                            const int *__restrict__ perm,
+                            const int *__restrict__ pix_vid,
+                            uint64_t *__restrict__ hkeys, uint64_t capmask,
+                            int *__restrict__ ent_slot, int *__restrict__ flags) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)N * D1) return;
+    const int p = int(e / D1);
+    const int k = int(e - (long long)p * D1);
+    long long node;
+    int side;
+    int slot = -1;
+    if (dnc_node(p, l, N, node, side)) {
+        const int v = pix_vid[(size_t)perm[p] * D1 + k];
+        if (v >= 0) {
+            const uint64_t key = (uint64_t)node * (uint64_t)M + (uint64_t)v;
+            uint64_t h = mix64(key) & capmask;
+            uint64_t probe = 0;
+            for (; probe <= capmask; ++probe) {
+                const unsigned long long prev = atomicCAS(
+                    (unsigned long long *)&hkeys[h], (unsigned long long)kEmpty,
+                    (unsigned long long)key);
+                if (prev == kEmpty || prev == key) break;
+                h = (h + 1) & capmask;
+            }
+            if (probe > capmask)
+                atomicOr(flags, 2);
+            else
+                slot = int(h);
+        }
+    }
+    ent_slot[e] = slot;
+}
+
+// splat the two half indicators: V0[id][side] += b; records the entry's
+// sub-vertex id for the slice
+template <typename T>
+__global__ void k_lp_splat(int N, int l, int D1, const int *__restrict__ perm,
+                           const T *__restrict__ pix_w,
+                           const int *__restrict__ ent_slot,
+                           const int *__restrict__ slot_vid,
+                           int *__restrict__ ent_id, T *__restrict__ V0) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)N * D1) return;
+    const int s = ent_slot[e];
+    int id = -1;
+    if (s >= 0) {
+        const int p = int(e / D1);
+        const int k = int(e - (long long)p * D1);
+        long long node;
+        int side;
+        dnc_node(p, l, N, node, side);
+        id = slot_vid[s];
+        atomic_add(&V0[(size_t)id * 2 + side], pix_w[(size_t)perm[p] * D1 + k]);
+    }
+    ent_id[e] = id;
+}
+
+// neighbours of every sub-vertex: (node, v +- u_j) when present in the node
+__global__ void k_lp_neighbours(const int *__restrict__ count, int M, int D1,
+                                const uint64_t *__restrict__ subkeys,
+                                const int *__restrict__ nbr_global,
+                                const uint64_t *__restrict__ hkeys,
+                                uint64_t capmask, const int *__restrict__ slot_vid,
+                                int *__restrict__ nbr_sub, int cap_sub) {
+    const int S = *count;
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= S) return;
+    const uint64_t key = subkeys[id];
+    const uint64_t node = key / (uint64_t)M;
+    const int v = int(key - node * (uint64_t)M);
+    for (int j = 0; j < D1; ++j)
+        for (int sg = 0; sg < 2; ++sg) {
+            const int vn = nbr_global[((size_t)j * M + v) * 2 + sg];
+            int nid = -1;
+            if (vn >= 0) {
+                const uint64_t nk = node * (uint64_t)M + (uint64_t)vn;
+                uint64_t h = mix64(nk) & capmask;
+                for (uint64_t probe = 0; probe <= capmask; ++probe) {
+                    const uint64_t kk = hkeys[h];
+                    if (kk == nk) {
+                        nid = slot_vid[h];
+                        break;
+                    }
+                    if (kk == kEmpty) break;
+                    h = (h + 1) & capmask;
+                }
+            }
+            nbr_sub[((size_t)j * cap_sub + id) * 2 + sg] = nid;
+        }
+}
+
+// one blur pass over the sub-lattice, 2 channels; the second pass clears V0
+template <typename T>
+__global__ void k_lp_blur(const int *__restrict__ count, int j, int pass,
+                          int cap_sub, const int *__restrict__ nbr_sub,
+                          T *__restrict__ V0, T *__restrict__ V1,
+                          T *__restrict__ V2) {
+    const int S = *count;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= S * 2) return;
+    const int id = e >> 1;
+    const int c = e & 1;
+    const T *src = (pass == 0) ? V0 : ((pass & 1) ? V1 : V2);
+    T *dst = (pass & 1) ? V2 : V1;
+    const int np = nbr_sub[((size_t)j * cap_sub + id) * 2 + 0];
+    const int nm = nbr_sub[((size_t)j * cap_sub + id) * 2 + 1];
+    const T vp = np >= 0 ? src[(size_t)np * 2 + c] : T(0);
+    const T vm = nm >= 0 ? src[(size_t)nm * 2 + c] : T(0);
+    dst[e] = T(0.5) * src[e] + T(0.25) * (vp + vm);
+    if (pass == 1) V0[e] = T(0);
+}
+
+template <typename T>
+struct LPLat {
+    const T *pix_w;
+    const int *ent_id;
+    const T *Vf;
+    int D1;
+    T wg;
+};
+
+template <typename T>
+struct LPLats {
+    LPLat<T> l[DCRF_MAXK];
+    int nk;
+};
+
+// slice: the right channel at left points adds to U, the left channel at
+// right points adds to Lo; g[a][col] += U - Lo
+template <typename T>
+__global__ void k_lp_slice(int N, int l, int L, int col,
+                           const int *__restrict__ perm, LPLats<T> lats,
+                           T *__restrict__ g) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    long long node;
+    int side;
+    if (!dnc_node(p, l, N, node, side)) return;
+    const int a = perm[p];
+    const int ch = 1 - side;
+    T acc = T(0);
+    for (int m = 0; m < lats.nk; ++m) {
+        const LPLat<T> &X = lats.l[m];
+        T s = T(0);
+        for (int k = 0; k < X.D1; ++k) {
+            const int id = X.ent_id[(size_t)p * X.D1 + k];
+            if (id >= 0)
+                s += X.pix_w[(size_t)a * X.D1 + k] * X.Vf[(size_t)id * 2 + ch];
+        }
+        acc += X.wg * s;
+    }
+    g[(size_t)a * L + col] += side == 0 ? acc : -acc;
+}
+
+// exact mode: for the point at sorted position p,
+// sum_{q != p} Kbar(pi(q), pi(p)) (q > p ? 1 : -1), tiled through LDS
+constexpr int kLpExTile = 128;
+
+template <typename T>
+__global__ void __launch_bounds__(kLpExTile)
+k_lp_exact(int N, int L, int col, const int *__restrict__ perm,
+           ExactSet<T> ex, T *__restrict__ g) {
+    __shared__ T sf[kLpExTile][16];
+    const int p = blockIdx.x * kLpExTile + threadIdx.x;
+    T fa[16];
+    for (int j = 0; j < 16; ++j) fa[j] = T(0);
+    int a = 0;
+    if (p < N) {
+        a = perm[p];
+        for (int m = 0; m < ex.nk; ++m)
+            for (int j = 0; j < ex.d[m]; ++j)
+                fa[ex.off[m] + j] = ex.f[m][(size_t)a * ex.d[m] + j];
+    }
+    T acc = T(0);
+    for (int q0 = 0; q0 < N; q0 += kLpExTile) {
+        const int q = q0 + threadIdx.x;
+        if (q < N) {
+            const int b = perm[q];
+            for (int m = 0; m < ex.nk; ++m)
+                for (int j = 0; j < ex.d[m]; ++j)
+                    sf[threadIdx.x][ex.off[m] + j] = ex.f[m][(size_t)b * ex.d[m] + j];
+        }
+        __syncthreads();
+        const int nb = min(kLpExTile, N - q0);
+        for (int t = 0; t < nb; ++t) {
+            const int q2 = q0 + t;
+            if (q2 == p) continue;
+            T kab = T(0);
+            for (int m = 0; m < ex.nk; ++m) {
+                T r2 = T(0);
+                for (int j = ex.off[m]; j < ex.off[m + 1]; ++j) {
+                    const T df = fa[j] - sf[t][j];
+                    r2 += df * df;
+                }
+                kab += ex.w[m] * exp(T(-0.5) * r2);
+            }
+            acc += q2 > p ? kab : -kab;
+        }
+        __syncthreads();
+    }
+    if (p < N) g[(size_t)a * L + col] += acc;
+}
+
+// ------------------------------------------------- projection and step
+
+// Euclidean projection of v (register row, C valid entries) onto the simplex:
+// sort descending with a bitonic network, cumulative sums in sorted order,
+// rho = last j with u_j - (css_j - 1) / j > 0, tau = (css_rho - 1) / rho.
+template <typename T, int P>
+__device__ __forceinline__ T simplex_tau(const T (&v)[P], int C) {
+    T u[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) u[i] = (i < C) ? v[i] : -INFINITY;
+#pragma unroll
+    for (int k = 2; k <= P; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const bool desc = (i & k) == 0;
+                    const T x = u[i], y = u[l];
+                    const bool sw = desc ? (x < y) : (x > y);
+                    u[i] = sw ? y : x;
+                    u[l] = sw ? x : y;
+                }
+            }
+    T css = T(0), tau = T(0);
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        if (j < C) {
+            css += u[j];
+            const T t = (css - T(1)) / T(j + 1);
+            if (u[j] - t > T(0)) tau = t;
+        }
+    }
+    return tau;
+}
+
+template <int C> struct Pow2 { static constexpr int v = C <= 4 ? 4 : C <= 8 ? 8 : C <= 16 ? 16 : 32; };
+
+// y <- Pi(y - beta g) (beta = 0: plain projection of y), one thread per pixel
+template <typename T, int LMAX>
+__global__ void k_lp_step_rows(int N, int L, const T *src, const T *g, T beta,
+                               T *dst) {
+    constexpr int P = Pow2<LMAX>::v;
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= N) return;
+    T v[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+        v[j] = (j < L) ? src[(size_t)a * L + j] - (g ? beta * g[(size_t)a * L + j] : T(0))
+                       : T(0);
+    const T tau = simplex_tau<T, P>(v, L);
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+        if (j < L) dst[(size_t)a * L + j] = fmax(v[j] - tau, T(0));
+}
+
+// the same for any L: the sort-free form tau = (S_i - 1) / n_i for the
+// largest set {k : v_k >= v_i} whose smallest member stays positive
+template <typename T>
+__global__ void k_lp_step_flat(int N, int L, const T *src, const T *g, T beta,
+                               T *dst) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= N) return;
+    const T *s = src + (size_t)a * L;
+    const T *gg = g ? g + (size_t)a * L : nullptr;
+    int best_n = 0;
+    T tau = T(0);
+    for (int i = 0; i < L; ++i) {
+        const T vi = s[i] - (gg ? beta * gg[i] : T(0));
+        T S = T(0);
+        int n = 0;
+        for (int k = 0; k < L; ++k) {
+            const T vk = s[k] - (gg ? beta * gg[k] : T(0));
+            if (vk >= vi) {
+                S += vk;
+                ++n;
+            }
+        }
+        const T t = (S - T(1)) / T(n);
+        if (vi - t > T(0) && n > best_n) {
+            best_n = n;
+            tau = t;
+        }
+    }
+    for (int j = 0; j < L; ++j) {
+        const T vj = s[j] - (gg ? beta * gg[j] : T(0));
+        dst[(size_t)a * L + j] = fmax(vj - tau, T(0));
+    }
+}
+
+template <typename T>
+__global__ void k_copy(size_t n, const T *__restrict__ s, T *__restrict__ d) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = s[i];
+}
+
+// per-block partial sums of <g, y>
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_dot(size_t n, const T *__restrict__ a, const T *__restrict__ b,
+      double *__restrict__ part) {
+    __shared__ double red[256];
+    double acc[1] = {0.0};
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * 256)
+        acc[0] += double(a[i]) * double(b[i]);
+    block_sum<1, 256>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+}
+
+// ------------------------------------------------------------------ host
+
+struct LPWork {
+    DevBuf keys, keys2, vals, vals2, hist;
+    struct PerLat {
+        DevBuf hkeys, slot_vid, ent_slot, ent_id, subkeys, nbr_sub, V[3];
+        size_t cap = 0;
+        int cap_sub = 0;
+    } lat[DCRF_MAXK];
+    DevBuf g, part, cnt;
+};
+
+LPWork &lp_work(dcrf_ctx *ctx) {
+    if (!ctx->lp) ctx->lp = new LPWork();
+    return *static_cast<LPWork *>(ctx->lp);
+}
+
+template <typename T>
+void sort_column(dcrf_ctx *ctx, LPWork &W, const T *y, int L, int col,
+                 int **perm_out) {
+    using K = typename std::conditional<sizeof(T) == 8, uint64_t, uint32_t>::type;
+    const hipStream_t s = ctx->stream;
+    const int N = ctx->N;
+    const int ntiles = ceil_div(N, kRsTile);
+    W.keys.ensure((size_t)N * sizeof(K), s);
+    W.keys2.ensure((size_t)N * sizeof(K), s);
+    W.vals.ensure((size_t)N * 4, s);
+    W.vals2.ensure((size_t)N * 4, s);
+    W.hist.ensure((size_t)(256 * ntiles + 1) * 4 * 2, s);
+    K *k0 = W.keys.as<K>(), *k1 = W.keys2.as<K>();
+    int *v0 = W.vals.as<int>(), *v1 = W.vals2.as<int>();
+    int *hist = W.hist.as<int>();
+    int *offs = hist + 256 * ntiles + 1;
+    hipLaunchKernelGGL((k_rs_init<T, K>), dim3(ceil_div(N, 256)), dim3(256), 0, s,
+                       N, L, col, y, k0, v0);
+    for (int shift = 0; shift < int(8 * sizeof(K)); shift += 8) {
+        hipLaunchKernelGGL((k_rs_hist<K>), dim3(ntiles), dim3(kRsThreads), 0, s,
+                           k0, N, shift, ntiles, hist);
+        scan_ints(ctx, hist, 256 * ntiles, offs);
+        hipLaunchKernelGGL((k_rs_scatter<K>), dim3(ntiles), dim3(kRsThreads), 0,
+                           s, k0, v0, N, shift, ntiles, offs, k1, v1);
+        std::swap(k0, k1);
+        std::swap(v0, v1);
+    }
+    DCRF_CHECK_LAUNCH();
+    *perm_out = v0;   // an even number of passes leaves the result in vals
+}
+
+template <typename T>
+void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l, const int *perm) {
+    Lattice &Lt = ctx->lat[m];
+    auto &P = W.lat[m];
+    const hipStream_t s = ctx->stream;
+    const int N = ctx->N, D1 = Lt.d + 1, M = Lt.M;
+    const long long E = (long long)N * D1;
+    int *count = W.cnt.as<int>() + 4 * m;
+    int *flags = ctx->scratch.as<int>();
+    DCRF_TRY_HIP(hipMemsetAsync(P.hkeys.p, 0xff, P.cap * 8, s));
+    hipLaunchKernelGGL(k_lp_insert, dim3(ceil_div(E, 256)), dim3(256), 0, s, N, l,
+                       D1, M, perm, Lt.pix_vid.as<int>(), P.hkeys.as<uint64_t>(),
+                       uint64_t(P.cap - 1), P.ent_slot.as<int>(), flags);
+    const int ntiles = ceil_div((long long)P.cap, kScanTile);
+    int *tiles = reinterpret_cast<int *>(ctx->scratch.as<char>() + 64);
+    hipLaunchKernelGGL(k_count_occupied, dim3(ntiles), dim3(kScanThreads), 0, s,
+                       P.hkeys.as<uint64_t>(), P.cap, tiles);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, tiles,
+                       ntiles);
+    hipLaunchKernelGGL(k_assign_ids, dim3(ntiles), dim3(kScanThreads), 0, s,
+                       P.hkeys.as<uint64_t>(), P.cap, tiles, P.slot_vid.as<int>(),
+                       P.subkeys.as<uint64_t>());
+    DCRF_TRY_HIP(hipMemcpyAsync(count, tiles + ntiles, 4, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL((k_lp_splat<T>), dim3(ceil_div(E, 256)), dim3(256), 0, s,
+                       N, l, D1, perm, Lt.pix_w.as<T>(), P.ent_slot.as<int>(),
+                       P.slot_vid.as<int>(), P.ent_id.as<int>(), P.V[0].as<T>());
+    hipLaunchKernelGGL(k_lp_neighbours, dim3(ceil_div(P.cap_sub, 256)), dim3(256),
+                       0, s, count, M, D1, P.subkeys.as<uint64_t>(),
+                       Lt.nbr.as<int>(), P.hkeys.as<uint64_t>(),
+                       uint64_t(P.cap - 1), P.slot_vid.as<int>(),
+                       P.nbr_sub.as<int>(), P.cap_sub);
+    for (int pass = 0; pass < D1; ++pass)
+        hipLaunchKernelGGL((k_lp_blur<T>), dim3(ceil_div(2ll * P.cap_sub, 256)),
+                           dim3(256), 0, s, count, pass, pass, P.cap_sub,
+                           P.nbr_sub.as<int>(), P.V[0].as<T>(), P.V[1].as<T>(),
+                           P.V[2].as<T>());
+    DCRF_CHECK_LAUNCH();
+}
+
+template <typename T>
+void lp_prepare(dcrf_ctx *ctx, LPWork &W, int L) {
+    const hipStream_t s = ctx->stream;
+    const int N = ctx->N;
+    W.g.ensure((size_t)N * L * sizeof(T), s);
+    W.part.ensure(1024 * 8, s);
+    W.cnt.ensure(64, s);
+    if (ctx->mode == DCRF_FILTER_EXACT) return;
+    for (int m = 0; m < ctx->nk; ++m) {
+        auto &P = W.lat[m];
+        const int D1 = ctx->lat[m].d + 1;
+        const size_t E = (size_t)N * D1;
+        size_t cap = 1024;
+        while (cap < 2 * E) cap <<= 1;
+        P.cap = cap;
+        P.cap_sub = int(E);
+        P.hkeys.ensure(cap * 8, s);
+        P.slot_vid.ensure(cap * 4, s);
+        P.ent_slot.ensure(E * 4, s);
+        P.ent_id.ensure(E * 4, s);
+        P.subkeys.ensure(E * 8, s);
+        P.nbr_sub.ensure(E * D1 * 2 * 4, s);
+        for (int b = 0; b < 3; ++b) P.V[b].ensure(E * 2 * sizeof(T), s);
+    }
+}
+
+template <typename T>
+double lp_subgradient_t(dcrf_ctx *ctx, const T *phi, int L, const T *y, T *g) {
+    LPWork &W = lp_work(ctx);
+    const hipStream_t s = ctx->stream;
+    const int N = ctx->N;
+    lp_prepare<T>(ctx, W, L);
+    const size_t NL = (size_t)N * L;
+    hipLaunchKernelGGL((k_copy<T>), dim3(ceil_div((long long)NL, 256)), dim3(256),
+                       0, s, NL, phi, g);
+    int levels = 0;
+    while ((1ll << levels) < N) ++levels;
+    DCRF_TRY_HIP(hipMemsetAsync(ctx->scratch.p, 0, 4, s));
+    for (int col = 0; col < L; ++col) {
+        int *perm = nullptr;
+        sort_column<T>(ctx, W, y, L, col, &perm);
+        if (ctx->mode == DCRF_FILTER_EXACT) {
+            ExactSet<T> ex = make_exact_set<T>(ctx);
+            hipLaunchKernelGGL((k_lp_exact<T>), dim3(ceil_div(N, kLpExTile)),
+                               dim3(kLpExTile), 0, s, N, L, col, perm, ex, g);
+            DCRF_CHECK_LAUNCH();
+            continue;
+        }
+        for (int l = 0; l < levels; ++l) {
+            for (int m = 0; m < ctx->nk; ++m) lp_level<T>(ctx, W, m, l, perm);
+            LPLats<T> lats{};
+            lats.nk = ctx->nk;
+            for (int m = 0; m < ctx->nk; ++m) {
+                Lattice &Lt = ctx->lat[m];
+                lats.l[m] = LPLat<T>{Lt.pix_w.as<T>(), W.lat[m].ent_id.as<int>(),
+                                     W.lat[m].V[final_buffer(Lt.d)].as<T>(), Lt.d + 1,
+                                     T(ctx->kern[m].weight * Lt.gamma)};
+            }
+            hipLaunchKernelGGL((k_lp_slice<T>), dim3(ceil_div(N, 256)), dim3(256),
+                               0, s, N, l, L, col, perm, lats, g);
+            DCRF_CHECK_LAUNCH();
+        }
+    }
+    int hflags = 0;
+    DCRF_TRY_HIP(hipMemcpyAsync(&hflags, ctx->scratch.p, 4, hipMemcpyDeviceToHost, s));
+    const int G = std::min(1024, ceil_div((long long)NL, 256));
+    hipLaunchKernelGGL((k_dot<T>), dim3(G), dim3(256), 0, s, NL, g, y,
+                       W.part.as<double>());
+    std::vector<double> h(G);
+    DCRF_TRY_HIP(hipMemcpyAsync(h.data(), W.part.p, G * 8, hipMemcpyDeviceToHost, s));
+    DCRF_TRY_HIP(hipStreamSynchronize(s));
+    if (hflags & 2) fail(DCRF_ECAPACITY, "LP sub-lattice hash table full");
+    double S = 0.0;
+    for (double v : h) S += v;
+    return S;
+}
+
+template <typename T>
+void project_t(dcrf_ctx *ctx, const T *src, const T *g, T beta, int L, T *dst) {
+    const int N = ctx->N;
+    if (L <= kRowMaxC) {
+        DCRF_DISPATCH_ROWS(L, hipLaunchKernelGGL((k_lp_step_rows<T, LMAX>),
+                                                 dim3(ceil_div(N, 128)), dim3(128),
+                                                 0, ctx->stream, N, L, src, g, beta,
+                                                 dst));
+    } else {
+        hipLaunchKernelGGL((k_lp_step_flat<T>), dim3(ceil_div(N, 128)), dim3(128),
+                           0, ctx->stream, N, L, src, g, beta, dst);
+    }
+    DCRF_CHECK_LAUNCH();
+}
+
+template <typename T>
+void lp_descent_t(dcrf_ctx *ctx, const T *phi, int L, T *y, int steps,
+                  double beta0, double *best, T *best_y, double *hist) {
+    LPWork &W = lp_work(ctx);
+    lp_prepare<T>(ctx, W, L);
+    const size_t NL = (size_t)ctx->N * L;
+    double b = INFINITY;
+    for (int t = 0; t < steps; ++t) {
+        T *g = W.g.as<T>();
+        const double S = lp_subgradient_t<T>(ctx, phi, L, y, g);
+        if (hist) hist[t] = S;
+        if (S < b) {
+            b = S;
+            if (best_y)
+                hipLaunchKernelGGL((k_copy<T>), dim3(ceil_div((long long)NL, 256)),
+                                   dim3(256), 0, ctx->stream, NL, y, best_y);
+        }
+        project_t<T>(ctx, y, g, T(beta0 / (1.0 + t)), L, y);
+    }
+    if (best) *best = b;
+}
+
+}  // namespace
+
+void lp_release(dcrf_ctx *ctx) {
+    if (!ctx->lp) return;
+    LPWork *W = static_cast<LPWork *>(ctx->lp);
+    for (DevBuf *b : {&W->keys, &W->keys2, &W->vals, &W->vals2, &W->hist, &W->g,
+                      &W->part, &W->cnt})
+        b->release();
+    for (auto &P : W->lat)
+        for (DevBuf *b : {&P.hkeys, &P.slot_vid, &P.ent_slot, &P.ent_id,
+                          &P.subkeys, &P.nbr_sub, &P.V[0], &P.V[1], &P.V[2]})
+            b->release();
+    delete W;
+    ctx->lp = nullptr;
+}
+
+double lp_subgradient(dcrf_ctx *ctx, const void *unary, int L, const void *y,
+                      void *g) {
+    if (ctx->dtype == DCRF_F64)
+        return lp_subgradient_t<double>(ctx, static_cast<const double *>(unary), L,
+                                        static_cast<const double *>(y),
+                                        static_cast<double *>(g));
+    return lp_subgradient_t<float>(ctx, static_cast<const float *>(unary), L,
+                                   static_cast<const float *>(y),
+                                   static_cast<float *>(g));
+}
+
+void lp_descent(dcrf_ctx *ctx, const void *unary, int L, void *y, int steps,
+                double beta0, double *best, void *best_y, double *hist) {
+    if (ctx->dtype == DCRF_F64)
+        lp_descent_t<double>(ctx, static_cast<const double *>(unary), L,
+                             static_cast<double *>(y), steps, beta0, best,
+                             static_cast<double *>(best_y), hist);
+    else
+        lp_descent_t<float>(ctx, static_cast<const float *>(unary), L,
+                            static_cast<float *>(y), steps, beta0, best,
+                            static_cast<float *>(best_y), hist);
+}
+
+void project_simplex(dcrf_ctx *ctx, const void *v, int L, void *y) {
+    if (ctx->dtype == DCRF_F64)
+        project_t<double>(ctx, static_cast<const double *>(v), nullptr, 0.0, L,
+                          static_cast<double *>(y));
+    else
+        project_t<float>(ctx, static_cast<const float *>(v), nullptr, 0.0f, L,
+                         static_cast<float *>(y));
+}
+
+}  // namespace dcrf

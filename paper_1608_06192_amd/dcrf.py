@@ -62,6 +62,9 @@ PROTOTYPES = {
     "dcrf_dc_gen": (_I, [_P, _P, _P, _I, _P, _I, _I, _PD]),
     "dcrf_round": (_I, [_P, _P, _I, _P]),
     "dcrf_energy": (_I, [_P, _P, _P, _I, _P, _PD]),
+    "dcrf_lp_subgradient": (_I, [_P, _P, _I, _P, _P, _PD]),
+    "dcrf_lp_descent": (_I, [_P, _P, _I, _P, _I, _D, _PD, _P, _PD]),
+    "dcrf_project_simplex": (_I, [_P, _P, _I, _P]),
     "dcrf_set_profiling": (_I, [_P, _I]),
     "dcrf_get_profile": (_I, [_P, _I, ctypes.POINTER(ctypes.c_char_p), _PD,
                               ctypes.POINTER(ctypes.c_longlong)]),
@@ -217,6 +220,37 @@ class Context:
         self._check(_lib.dcrf_round(self._h, self._arg(y), y.shape[1],
                                     _ptr(lab)))
         return lab
+
+    # -- LP relaxation (Potts) -------------------------------------------
+    def lp_subgradient(self, unary, y, g: torch.Tensor | None = None):
+        """(g, S_LP(y)) at y: eq. grad_lp by divide and conquer."""
+        g = torch.empty_like(y) if g is None else g
+        S = ctypes.c_double()
+        self._stream()
+        self._check(_lib.dcrf_lp_subgradient(
+            self._h, self._arg(unary), unary.shape[1], self._arg(y),
+            self._arg(g), ctypes.byref(S)))
+        return g, S.value
+
+    def lp_descent(self, unary, y, steps: int, beta0: float,
+                   best_y: torch.Tensor | None = None):
+        """Projected subgradient descent in place on y; returns (best S_LP,
+        history of S_LP(y_t))."""
+        hist = (ctypes.c_double * max(steps, 1))()
+        best = ctypes.c_double()
+        self._stream()
+        self._check(_lib.dcrf_lp_descent(
+            self._h, self._arg(unary), unary.shape[1], self._arg(y), steps,
+            float(beta0), ctypes.byref(best),
+            None if best_y is None else self._arg(best_y), hist))
+        return best.value, list(hist[:steps])
+
+    def project_simplex(self, v: torch.Tensor, out: torch.Tensor | None = None):
+        out = torch.empty_like(v) if out is None else out
+        self._stream()
+        self._check(_lib.dcrf_project_simplex(self._h, self._arg(v), v.shape[1],
+                                              self._arg(out)))
+        return out
 
     # -- profiling -------------------------------------------------------
     def set_profiling(self, on: bool):
