@@ -578,3 +578,115 @@ def lp_descent(phi: np.ndarray, y0: np.ndarray, steps: int, beta0: float,
             best, best_y = S, y.copy()
         y = project_simplex(y - beta0 / (1.0 + t) * g)
     return y, best, best_y, hist
+
+
+# ---------------------------------------------------------------------------
+# Differentiation of unrolled Frank-Wolfe (reverse mode, hand derived)
+# ---------------------------------------------------------------------------
+
+def fw_tape(qp: QP, y0: np.ndarray, iters: int):
+    """Frank-Wolfe (as ``frank_wolfe``) recording, per iteration t, the
+    iterate y_t, P_t, the conditional gradient s_t, S_t = (Psi + D) s_t, the
+    step alpha_t, the quadratic's coefficients (a2, b1) and whether alpha_t
+    was the interior stationary point (only then does it depend smoothly on
+    the inputs). Returns (y_T, tape, c)."""
+    c = qp.phi - qp.d
+    y = _f64(y0).copy()
+    P = qp.Q(y)
+    tape = []
+    for _ in range(iters):
+        g = c + 2.0 * P
+        s = onehot(np.argmin(g, axis=1), qp.L)
+        S = qp.Q(s)
+        alpha, a2, b1 = fw_step_size(c, y, s, P, S)
+        interior = a2 > 0 and 0.0 < -b1 / (2.0 * a2) < 1.0
+        tape.append(dict(y=y, P=P, s=s, S=S, alpha=alpha, a2=a2, b1=b1,
+                         interior=interior))
+        y = y + alpha * (s - y)
+        P = (1.0 - alpha) * P + alpha * S
+    return y, tape, c
+
+
+def cross_entropy(y: np.ndarray, gt: np.ndarray) -> float:
+    """-(1/N) sum_a log max(y_a(gt_a), 1e-12)."""
+    p = y[np.arange(y.shape[0]), gt]
+    return float(-np.log(np.maximum(p, 1e-12)).mean())
+
+
+def cross_entropy_grad(y: np.ndarray, gt: np.ndarray) -> np.ndarray:
+    N = y.shape[0]
+    g = np.zeros_like(y)
+    p = y[np.arange(N), gt]
+    g[np.arange(N), gt] = np.where(p > 1e-12, -1.0 / (N * np.maximum(p, 1e-300)),
+                                   0.0)
+    return g
+
+
+def fw_unrolled_loss(model: Model, phi: np.ndarray, mu: np.ndarray, iters: int,
+                     gt: np.ndarray):
+    """The differentiable pipeline: y0 = softmax(-phi), ``iters`` Frank-Wolfe
+    iterations, cross entropy to gt. Returns (loss, y_T, tape, qp, c)."""
+    qp = QP(model, phi, mu)
+    yT, tape, c = fw_tape(qp, softmax_neg(phi), iters)
+    return cross_entropy(yT, gt), yT, tape, qp, c
+
+
+def fw_unrolled_backward(qp: QP, tape, c: np.ndarray, ybar: np.ndarray):
+    """Reverse sweep of ``fw_tape`` for an upstream gradient ybar = dl/dy_T.
+
+    Returns (dl/dphi, dl/dw) where w are the kernel weights of qp.model.
+    The step's adjoints follow from
+      y_{t+1} = (1 - alpha) y_t + alpha s_t,  P_{t+1} = (1 - alpha) P_t + alpha S_t,
+      alpha = -b1 / (2 a2) (interior only), b1 = cs - cy + B + C - 2A,
+      a2 = D - B - C + A with A = <y,P>, B = <y,S>, C = <s,P>, D = <s,S>,
+      cy = <c,y>, cs = <c,s>;
+    s_t is piecewise constant. The weights enter through S_t = Q s_t,
+    P_0 = Q y_0 and d in c = phi - d:
+      d<Zbar, Q X>/dw_m = <Zbar mu, (K_m - I) X> + sum_a rho_a (K_m 1 - 1)_a,
+      rho_a = sum_i Zbar_a(i) X_a(i) sum_j |mu_ij|.
+    """
+    model, mu = qp.model, qp.mu
+    mabs = np.abs(mu).sum(axis=1)
+    nk = len(model.feats)
+    ybar = _f64(ybar).copy()
+    Pbar = np.zeros_like(ybar)
+    cbar = np.zeros_like(ybar)
+    rho = np.zeros(ybar.shape[0])
+    gw = np.zeros(nk)
+    for rec in reversed(tape):
+        y, P, s, S, al = rec["y"], rec["P"], rec["s"], rec["S"], rec["alpha"]
+        abar = (ybar * (s - y)).sum() + (Pbar * (S - P)).sum()
+        if rec["interior"]:
+            b1bar = -abar / (2.0 * rec["a2"])
+            a2bar = -abar * al / rec["a2"]
+        else:
+            b1bar = a2bar = 0.0
+        Abar = -2.0 * b1bar + a2bar
+        Bbar = Cbar = b1bar - a2bar
+        Dbar = a2bar
+        csbar, cybar = b1bar, -b1bar
+        Sbar = al * Pbar + Bbar * y + Dbar * s
+        for m in range(nk):
+            gw[m] += ((Sbar @ mu) * (model.Km(m, s) - s)).sum()
+        rho += (Sbar * s * mabs[None, :]).sum(axis=1)
+        ybar, Pbar = ((1.0 - al) * ybar + Abar * P + Bbar * S + cybar * c,
+                      (1.0 - al) * Pbar + Abar * y + Cbar * s)
+        cbar += cybar * y + csbar * s
+    y0 = tape[0]["y"] if tape else None
+    if y0 is None:
+        raise ValueError("at least one iteration is needed")
+    # P_0 = Q y_0
+    ybar = ybar + model.Kp(Pbar @ mu, reverse=True) + qp.d * Pbar
+    for m in range(nk):
+        gw[m] += ((Pbar @ mu) * (model.Km(m, y0) - y0)).sum()
+    rho += (Pbar * y0 * mabs[None, :]).sum(axis=1)
+    # c = phi - d
+    phibar = cbar.copy()
+    rho -= (cbar * mabs[None, :]).sum(axis=1)
+    # d = mabs (x) r,  r = sum_m w_m K_m 1 - (sum_m w_m) 1
+    ones = np.ones((ybar.shape[0], 1))
+    for m in range(nk):
+        gw[m] += (rho * (model.Km(m, ones)[:, 0] - 1.0)).sum()
+    # y_0 = softmax(-phi)
+    phibar -= y0 * (ybar - (ybar * y0).sum(axis=1, keepdims=True))
+    return phibar, gw
