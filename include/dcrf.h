@@ -199,6 +199,37 @@ int dcrf_lp_descent(dcrf_ctx *ctx, const void *unary, int L, void *y_inout,
  * rule). v, y: (dev) N x L; may be the same array. */
 int dcrf_project_simplex(dcrf_ctx *ctx, const void *v, int L, void *y);
 
+/* ---- differentiation of unrolled Frank-Wolfe ---------------------------- */
+
+/* The pipeline y_T = FW^T(softmax(-phi)): T = `iters` >= 1 Frank-Wolfe
+ * iterations on the QP (Sec. 4, App. B) started from y_0 = softmax(-phi)
+ * row by row, made differentiable in phi and in the kernel weights w_m by a
+ * reverse sweep over checkpoints (the step size alpha_t = -b1 / (2 a2) of the
+ * exact line search is differentiated where it is interior to (0, 1); a
+ * clipped step and the conditional gradient s_t are piecewise constant).
+ * Lattice filter mode only (DCRF_EUNSUPPORTED in exact mode); L <= 256.
+ *
+ * *bytes (host) = the size of the checkpoint buffer for (L, iters) at the
+ * context's image and precision: y_t (T x N x L values), s_t (T x N int32)
+ * and four doubles per iteration, each part 256-byte aligned. */
+int dcrf_fw_saved_size(dcrf_ctx *ctx, int L, int iters, size_t *bytes);
+
+/* Forward: unary (dev N x L), mu (dev L x L); y_out (dev N x L) = y_T;
+ * saved (dev, dcrf_fw_saved_size bytes, caller-owned) receives the
+ * checkpoints that dcrf_fw_backward reads. */
+int dcrf_fw_forward(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
+                    int iters, void *y_out, void *saved);
+
+/* Backward: given dl/dy_T in grad_y (dev N x L), writes dl/dphi to
+ * grad_unary (dev N x L) and, if grad_w (host, nk doubles) is not NULL,
+ * dl/dw_m for every kernel. unary, mu, L, iters and saved must be those of
+ * the forward call, and neither the image nor the weights may have changed
+ * in between. Waits for the stream (the step adjoints are scalars reduced on
+ * the device and read back once per iteration). */
+int dcrf_fw_backward(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
+                     int iters, const void *saved, const void *grad_y,
+                     void *grad_unary, double *grad_w);
+
 /* ---- benchmarking support ---------------------------------------------- */
 
 /* Turn per-kernel timing on or off (and reset the counters). While on, each

@@ -631,7 +631,8 @@ def fw_unrolled_loss(model: Model, phi: np.ndarray, mu: np.ndarray, iters: int,
     return cross_entropy(yT, gt), yT, tape, qp, c
 
 
-def fw_unrolled_backward(qp: QP, tape, c: np.ndarray, ybar: np.ndarray):
+def fw_unrolled_backward(qp: QP, tape, c: np.ndarray, ybar: np.ndarray,
+                         scale: bool = False):
     """Reverse sweep of ``fw_tape`` for an upstream gradient ybar = dl/dy_T.
 
     Returns (dl/dphi, dl/dw) where w are the kernel weights of qp.model.
@@ -644,6 +645,9 @@ def fw_unrolled_backward(qp: QP, tape, c: np.ndarray, ybar: np.ndarray):
     P_0 = Q y_0 and d in c = phi - d:
       d<Zbar, Q X>/dw_m = <Zbar mu, (K_m - I) X> + sum_a rho_a (K_m 1 - 1)_a,
       rho_a = sum_i Zbar_a(i) X_a(i) sum_j |mu_ij|.
+    With ``scale`` it also returns, per weight, the sum of the absolute values
+    of the elementwise summands of dl/dw (the conditioning of that sum: its
+    rounding error in a precision with unit roundoff u is about u times this).
     """
     model, mu = qp.model, qp.mu
     mabs = np.abs(mu).sum(axis=1)
@@ -653,6 +657,7 @@ def fw_unrolled_backward(qp: QP, tape, c: np.ndarray, ybar: np.ndarray):
     cbar = np.zeros_like(ybar)
     rho = np.zeros(ybar.shape[0])
     gw = np.zeros(nk)
+    gw_abs = np.zeros(nk)
     for rec in reversed(tape):
         y, P, s, S, al = rec["y"], rec["P"], rec["s"], rec["S"], rec["alpha"]
         abar = (ybar * (s - y)).sum() + (Pbar * (S - P)).sum()
@@ -667,7 +672,9 @@ def fw_unrolled_backward(qp: QP, tape, c: np.ndarray, ybar: np.ndarray):
         csbar, cybar = b1bar, -b1bar
         Sbar = al * Pbar + Bbar * y + Dbar * s
         for m in range(nk):
-            gw[m] += ((Sbar @ mu) * (model.Km(m, s) - s)).sum()
+            term = (Sbar @ mu) * (model.Km(m, s) - s)
+            gw[m] += term.sum()
+            gw_abs[m] += np.abs(term).sum()
         rho += (Sbar * s * mabs[None, :]).sum(axis=1)
         ybar, Pbar = ((1.0 - al) * ybar + Abar * P + Bbar * S + cybar * c,
                       (1.0 - al) * Pbar + Abar * y + Cbar * s)
@@ -678,7 +685,9 @@ def fw_unrolled_backward(qp: QP, tape, c: np.ndarray, ybar: np.ndarray):
     # P_0 = Q y_0
     ybar = ybar + model.Kp(Pbar @ mu, reverse=True) + qp.d * Pbar
     for m in range(nk):
-        gw[m] += ((Pbar @ mu) * (model.Km(m, y0) - y0)).sum()
+        term = (Pbar @ mu) * (model.Km(m, y0) - y0)
+        gw[m] += term.sum()
+        gw_abs[m] += np.abs(term).sum()
     rho += (Pbar * y0 * mabs[None, :]).sum(axis=1)
     # c = phi - d
     phibar = cbar.copy()
@@ -686,7 +695,11 @@ def fw_unrolled_backward(qp: QP, tape, c: np.ndarray, ybar: np.ndarray):
     # d = mabs (x) r,  r = sum_m w_m K_m 1 - (sum_m w_m) 1
     ones = np.ones((ybar.shape[0], 1))
     for m in range(nk):
-        gw[m] += (rho * (model.Km(m, ones)[:, 0] - 1.0)).sum()
+        term = rho * (model.Km(m, ones)[:, 0] - 1.0)
+        gw[m] += term.sum()
+        gw_abs[m] += np.abs(term).sum()
     # y_0 = softmax(-phi)
     phibar -= y0 * (ybar - (ybar * y0).sum(axis=1, keepdims=True))
+    if scale:
+        return phibar, gw, gw_abs
     return phibar, gw

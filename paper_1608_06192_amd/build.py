@@ -39,6 +39,7 @@ SOURCES = {
     "filter.hip": [],
     "solvers.hip": [],
     "lp.hip": [],
+    "diff.hip": [],
     "abi.cpp": ["-x", "hip"],
 }
 

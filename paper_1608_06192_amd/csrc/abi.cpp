@@ -89,6 +89,7 @@ int dcrf_destroy(dcrf_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     for (auto &L : ctx->lat) L.release();
     dcrf::lp_release(ctx);
+    dcrf::diff_release(ctx);
     ctx->prof.release();
     for (dcrf::DevBuf *b :
          {&ctx->r, &ctx->scratch, &ctx->tmpA, &ctx->tmpB, &ctx->fw_c,
@@ -260,6 +261,45 @@ int dcrf_lp_subgradient(dcrf_ctx *ctx, const void *unary, int L, const void *y,
         REQUIRE(unary && y && g && y != g, "null or aliased argument");
         const double S = dcrf::lp_subgradient(ctx, unary, L, y, g);
         if (S_lp) *S_lp = S;
+    });
+}
+
+static void require_diff(dcrf_ctx *ctx, int L, int iters) {
+    require_image(ctx);
+    check_labels(L);
+    REQUIRE(iters >= 1, "iters must be >= 1");
+    if (ctx->mode != DCRF_FILTER_LATTICE)
+        throw dcrf::Error{DCRF_EUNSUPPORTED,
+                          "differentiation needs the lattice filter mode"};
+}
+
+int dcrf_fw_saved_size(dcrf_ctx *ctx, int L, int iters, size_t *bytes) {
+    return guarded(ctx, [&] {
+        require_diff(ctx, L, iters);
+        REQUIRE(bytes, "null argument");
+        *bytes = dcrf::fw_saved_bytes(ctx, L, iters);
+    });
+}
+
+int dcrf_fw_forward(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
+                    int iters, void *y_out, void *saved) {
+    return guarded(ctx, [&] {
+        require_diff(ctx, L, iters);
+        REQUIRE(unary && mu && y_out && saved, "null argument");
+        REQUIRE(y_out != unary, "y_out must not alias unary");
+        dcrf::fw_diff_forward(ctx, unary, mu, L, y_out, iters, saved);
+    });
+}
+
+int dcrf_fw_backward(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
+                     int iters, const void *saved, const void *grad_y,
+                     void *grad_unary, double *grad_w) {
+    return guarded(ctx, [&] {
+        require_diff(ctx, L, iters);
+        REQUIRE(unary && mu && saved && grad_y && grad_unary, "null argument");
+        REQUIRE(grad_unary != grad_y, "grad_unary must not alias grad_y");
+        dcrf::fw_diff_backward(ctx, unary, mu, L, iters, saved, grad_y,
+                               grad_unary, grad_w);
     });
 }
 

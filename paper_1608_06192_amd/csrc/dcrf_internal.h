@@ -181,6 +181,7 @@ struct dcrf_ctx {
     dcrf::DevBuf fw_c, fw_Py, fw_Ps, fw_s, fw_sprev, fw_part, fw_scal,
         fw_trace, fw_mu;
     void *lp = nullptr;      // LP divide-and-conquer workspace (lp.hip)
+    void *diff = nullptr;    // reverse-sweep workspace (diff.hip)
     dcrf::Profiler prof;
     std::string err;
     size_t elt() const { return dtype == DCRF_F64 ? 8 : 4; }
@@ -225,6 +226,31 @@ void dc_gen(dcrf_ctx *ctx, const void *unary, const void *mu, int L, void *y,
 void round_labels(dcrf_ctx *ctx, const void *y, int L, int32_t *labels);
 double energy(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
               const int32_t *labels);
+
+// Checkpoints of a Frank-Wolfe forward for the reverse sweep: y_t (iters x
+// N x L), s_t (iters x N labels) and per iteration kFWStats doubles
+// (alpha, a2, b1, interior).
+constexpr int kFWStats = 4;
+struct FWCheckpoint {
+    void *y;
+    int32_t *s;
+    double *stats;
+};
+void frank_wolfe_checkpointed(dcrf_ctx *ctx, const void *unary, const void *mu,
+                              int L, void *y, int iters, const FWCheckpoint &save);
+
+// diff.hip
+void fw_diff_forward(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
+                     void *y_out, int iters, void *saved);
+void fw_diff_backward(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
+                      int iters, const void *saved, const void *grad_y,
+                      void *grad_unary, double *grad_w);
+size_t fw_saved_bytes(dcrf_ctx *ctx, int L, int iters);
+void diff_release(dcrf_ctx *ctx);
+// K~_m X: the lattice approximation of kernel m alone (weight 1, with its
+// own response at a), or its transpose
+void filter_kernel(dcrf_ctx *ctx, int m, const void *in, void *out, int C,
+                   bool adjoint);
 
 // lp.hip
 double lp_subgradient(dcrf_ctx *ctx, const void *unary, int L, const void *y,

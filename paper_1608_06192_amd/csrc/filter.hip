@@ -378,7 +378,56 @@ void filter_t(dcrf_ctx *ctx, const T *in, T *out, int C, bool adjoint,
     slice_t<T>(ctx, in, nullptr, C, nullptr, nullptr, out, false);
 }
 
+// K~_m X alone: lattice m with weight 1 and no self-term subtraction
+template <typename T>
+void filter_kernel_t(dcrf_ctx *ctx, int m, const T *in, T *out, int C,
+                     bool adjoint) {
+    const hipStream_t s = ctx->stream;
+    ensure_vertex_buffers(ctx, C);
+    const LatSet<T> all = make_lat_set<T>(ctx, C);
+    LatSet<T> ls{};
+    ls.nk = 1;
+    ls.l[0] = all.l[m];
+    ls.l[0].wg = T(ctx->lat[m].gamma);
+    ls.off[1] = all.off[m + 1] - all.off[m];
+    ls.coff[1] = all.coff[m + 1] - all.coff[m];
+    ls.eoff[1] = all.eoff[m + 1] - all.eoff[m];
+    ls.choff[1] = all.choff[m + 1] - all.choff[m];
+    ls.shape52 = 0;
+    if (ls.coff[1] > 0)
+        hipLaunchKernelGGL((k_splat_gather<T>), dim3(ceil_div(ls.coff[1], 256)),
+                           dim3(256), 0, s, C, in, ls);
+    const long long total = ls.off[1] / Vec16<T>::n;
+    if (total > 0)
+        for (int p = 0; p <= ls.l[0].d; ++p)
+            hipLaunchKernelGGL((k_blur_pass<T>), dim3(ceil_div(total, 256)),
+                               dim3(256), 0, s, ls, p, adjoint ? 1 : 0, total);
+    const int N = ctx->N;
+    constexpr int TP = RowTile<T>::kPix;
+    if (C <= kRowMaxC) {
+        DCRF_DISPATCH_ROWS(C, hipLaunchKernelGGL((k_slice_rows<T, LMAX, kSliceRaw>),
+                                                 dim3(row_grid(ctx, TP)), dim3(TP),
+                                                 0, s, N, C, in, nullptr, ls, T(0),
+                                                 nullptr, nullptr, nullptr, out));
+    } else {
+        hipLaunchKernelGGL((k_slice_raw_flat<T>),
+                           dim3(ceil_div((long long)N * C, 256)), dim3(256), 0, s,
+                           N, C, in, out, ls, T(0));
+    }
+    DCRF_CHECK_LAUNCH();
+}
+
 }  // namespace
+
+void filter_kernel(dcrf_ctx *ctx, int m, const void *in, void *out, int C,
+                   bool adjoint) {
+    if (ctx->dtype == DCRF_F64)
+        filter_kernel_t<double>(ctx, m, static_cast<const double *>(in),
+                                static_cast<double *>(out), C, adjoint);
+    else
+        filter_kernel_t<float>(ctx, m, static_cast<const float *>(in),
+                               static_cast<float *>(out), C, adjoint);
+}
 
 void ensure_vertex_buffers(dcrf_ctx *ctx, int C) {
     const int ld = row_stride(C, ctx->elt());

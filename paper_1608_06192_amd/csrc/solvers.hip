@@ -43,6 +43,8 @@ constexpr int kP2 = 2;   // partial sums written by k_fw_slice
 
 // scalar slot in fw_scal (doubles): the step size of the last iteration
 constexpr int kAlpha = 0;
+// doubles per iteration in a forward checkpoint: alpha, a2, b1, interior
+constexpr int kStats = 4;
 
 template <typename T>
 __global__ void k_fill(T *p, size_t n, T v) {
@@ -189,7 +191,7 @@ template <int NT>
 __global__ void __launch_bounds__(NT)
 k_fw_alpha(const double *__restrict__ part1, int G1,
            const double *__restrict__ part2, int G2, double *__restrict__ scal,
-           double *__restrict__ trace, int it) {
+           double *__restrict__ trace, int it, double *__restrict__ stats) {
     __shared__ double red[(kP1 + kP2) * NT];
     const int t = threadIdx.x;
     double tot[kP1 + kP2];
@@ -219,6 +221,14 @@ k_fw_alpha(const double *__restrict__ part1, int G1,
         tr[1] = gy - gs;         // <g, y_t - s_t>
         tr[2] = alpha;
         tr[3] = changed;
+        if (stats) {   // checkpoint for the reverse sweep
+            double *st = stats + (size_t)it * kStats;
+            st[0] = alpha;
+            st[1] = a2;
+            st[2] = b1;
+            st[3] = (a2 > 0.0 && -b1 / (2.0 * a2) > 0.0 && -b1 / (2.0 * a2) < 1.0)
+                        ? 1.0 : 0.0;
+        }
     }
 }
 
@@ -682,7 +692,8 @@ bool is_potts(dcrf_ctx *ctx, const T *mu, int L) {
 
 template <typename T>
 void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
-                   int iters, dcrf_iter_trace *trace, int cmode, bool have_Py) {
+                   int iters, dcrf_iter_trace *trace, int cmode, bool have_Py,
+                   const FWCheckpoint *save = nullptr) {
     const hipStream_t st = ctx->stream;
     const int N = ctx->N;
     const size_t NL = (size_t)N * L;
@@ -727,6 +738,12 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
                                    st, a);
             }
         }
+        if (save) {   // y_t and s_t for the reverse sweep
+            DCRF_TRY_HIP(hipMemcpyAsync(static_cast<T *>(save->y) + (size_t)it * NL, y,
+                                        NL * sizeof(T), hipMemcpyDeviceToDevice, st));
+            DCRF_TRY_HIP(hipMemcpyAsync(save->s + (size_t)it * N, w.s, (size_t)N * 4,
+                                        hipMemcpyDeviceToDevice, st));
+        }
         const T *pre = nullptr;
         if (exact) {
             hipLaunchKernelGGL((k_onehot<T>), dim3(gE), dim3(256), 0, st, N, L,
@@ -758,7 +775,8 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
         {
             ProfScope ps(ctx, PROF_FW_ALPHA);
             hipLaunchKernelGGL((k_fw_alpha<512>), dim3(1), dim3(512), 0,
-                               st, w.part1, G1, w.part2, G, w.scal, w.trace, it);
+                               st, w.part1, G1, w.part2, G, w.scal, w.trace, it,
+                               save ? save->stats : nullptr);
         }
         DCRF_CHECK_LAUNCH();
         std::swap(w.s, w.sprev);
@@ -886,6 +904,22 @@ void frank_wolfe(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
         frank_wolfe_t<float>(ctx, static_cast<const float *>(unary),
                              static_cast<const float *>(mu), L,
                              static_cast<float *>(y), iters, trace, 0, have_Py);
+}
+
+static_assert(kStats == kFWStats, "checkpoint layout");
+
+void frank_wolfe_checkpointed(dcrf_ctx *ctx, const void *unary, const void *mu,
+                              int L, void *y, int iters, const FWCheckpoint &save) {
+    if (ctx->dtype == DCRF_F64)
+        frank_wolfe_t<double>(ctx, static_cast<const double *>(unary),
+                              static_cast<const double *>(mu), L,
+                              static_cast<double *>(y), iters, nullptr, 0, false,
+                              &save);
+    else
+        frank_wolfe_t<float>(ctx, static_cast<const float *>(unary),
+                             static_cast<const float *>(mu), L,
+                             static_cast<float *>(y), iters, nullptr, 0, false,
+                             &save);
 }
 
 void dc_gen(dcrf_ctx *ctx, const void *unary, const void *mu, int L, void *y,

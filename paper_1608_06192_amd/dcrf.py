@@ -65,6 +65,9 @@ PROTOTYPES = {
     "dcrf_lp_subgradient": (_I, [_P, _P, _I, _P, _P, _PD]),
     "dcrf_lp_descent": (_I, [_P, _P, _I, _P, _I, _D, _PD, _P, _PD]),
     "dcrf_project_simplex": (_I, [_P, _P, _I, _P]),
+    "dcrf_fw_saved_size": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_size_t)]),
+    "dcrf_fw_forward": (_I, [_P, _P, _P, _I, _I, _P, _P]),
+    "dcrf_fw_backward": (_I, [_P, _P, _P, _I, _I, _P, _P, _P, _PD]),
     "dcrf_set_profiling": (_I, [_P, _I]),
     "dcrf_get_profile": (_I, [_P, _I, ctypes.POINTER(ctypes.c_char_p), _PD,
                               ctypes.POINTER(ctypes.c_longlong)]),
@@ -251,6 +254,37 @@ class Context:
         self._check(_lib.dcrf_project_simplex(self._h, self._arg(v), v.shape[1],
                                               self._arg(out)))
         return out
+
+    # -- differentiation of unrolled Frank-Wolfe --------------------------
+    def fw_saved_size(self, L: int, iters: int) -> int:
+        n = ctypes.c_size_t()
+        self._check(_lib.dcrf_fw_saved_size(self._h, L, iters, ctypes.byref(n)))
+        return n.value
+
+    def fw_forward(self, unary, mu, iters: int):
+        """y_T of `iters` Frank-Wolfe iterations from softmax(-unary); returns
+        (y_T, saved), saved being the checkpoint buffer (uint8 tensor) that
+        fw_backward needs."""
+        L = unary.shape[1]
+        saved = torch.empty(self.fw_saved_size(L, iters), dtype=torch.uint8,
+                            device=self.device)
+        y = torch.empty_like(unary)
+        self._stream()
+        self._check(_lib.dcrf_fw_forward(
+            self._h, self._arg(unary, name="unary"), self._arg(mu, name="mu"), L,
+            iters, self._arg(y), _ptr(saved)))
+        return y, saved
+
+    def fw_backward(self, unary, mu, iters: int, saved, grad_y):
+        """(dl/dunary, dl/dw as a list of nk floats) for dl/dy_T = grad_y."""
+        gphi = torch.empty_like(unary)
+        gw = (ctypes.c_double * self.nk)()
+        self._stream()
+        self._check(_lib.dcrf_fw_backward(
+            self._h, self._arg(unary, name="unary"), self._arg(mu, name="mu"),
+            unary.shape[1], iters, _ptr(saved), self._arg(grad_y, name="grad_y"),
+            self._arg(gphi), gw))
+        return gphi, list(gw)
 
     # -- profiling -------------------------------------------------------
     def set_profiling(self, on: bool):

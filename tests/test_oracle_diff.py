@@ -67,3 +67,16 @@ def test_fw_gradient_general_mu():
     lp = O.fw_unrolled_loss(model.with_weights(model.w + dw), im.unary, mu, iters, im.gt)[0]
     lm = O.fw_unrolled_loss(model.with_weights(model.w - dw), im.unary, mu, iters, im.gt)[0]
     assert abs((lp - lm) / (2 * eps) - gw[0]) <= 1e-6 * max(1.0, abs(gw[0]))
+
+
+def test_fw_gradient_scale_bounds_the_sum():
+    """The absolute sum reported with ``scale`` bounds |dl/dw| and leaves the
+    gradients unchanged."""
+    im, model = problem("lattice", 2)
+    mu = synth.potts(im.L)
+    loss, yT, tape, qp, c = O.fw_unrolled_loss(model, im.unary, mu, 6, im.gt)
+    ybar = O.cross_entropy_grad(yT, im.gt)
+    g1, w1 = O.fw_unrolled_backward(qp, tape, c, ybar)
+    g2, w2, wabs = O.fw_unrolled_backward(qp, tape, c, ybar, scale=True)
+    assert np.array_equal(g1, g2) and np.array_equal(w1, w2)
+    assert (wabs >= np.abs(w1)).all() and (wabs > 0).all()
