@@ -112,7 +112,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU design is described in DESIGN.md, not built",
+              "a multi-GPU run is not built",
               file=sys.stderr)
         sys.exit(2)
 

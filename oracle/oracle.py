@@ -23,8 +23,8 @@ the paper's order and notation, with no blocking or fusion:
   subgradient descent (Alg. lp_subgrad) with a simplex projection;
 * the reverse-mode derivative of unrolled Frank-Wolfe.
 
-Readings of the paper where it is silent or ambiguous are listed in the design doc
-of the repository; the ones that change numbers are repeated next to the code.
+Where the paper is silent or ambiguous, the reading taken is stated next to
+the code that depends on it.
 """
 
 from __future__ import annotations
