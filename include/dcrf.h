@@ -79,6 +79,14 @@ typedef struct {
     double changed;          /* pixels whose conditional gradient changed     */
 } dcrf_iter_trace;
 
+/* Launch shapes chosen by dcrf_autotune. */
+typedef struct {
+    int splat_chunk;              /* inverse-index entries per splat chunk    */
+    int blur_vectors_per_thread;  /* 16-byte vectors per thread in the blur   */
+    int blur_block;               /* threads per block of the blur            */
+    double ms;                    /* time of the tuned filter paths, ms       */
+} dcrf_tune;
+
 /* ---- context ---------------------------------------------------------- */
 
 /* Create a context on HIP device `device`; `hip_stream` is a hipStream_t
@@ -104,6 +112,41 @@ const char *dcrf_version(void);
  * for the 64-bit vertex key: theta too small for the image), DCRF_ENOMEM. */
 int dcrf_set_image(dcrf_ctx *ctx, int H, int W, const float *rgb,
                    const dcrf_kernel *kernels, int nk, int dtype);
+
+/* A batch of B images of their own sizes in one context (the batched
+ * extension of the QP solver; the model of Sec. 3 per image). Image j has
+ * H[j] x W[j] pixels and colours rgb[j] (host array of B device pointers to
+ * float32 H[j] W[j] x 3); the kernels and dtype are shared. Each image gets
+ * its own lattices, concatenated so that one launch per filter stage covers
+ * the batch; the filter never couples two images.
+ *
+ * Layout: every N x C argument of the later calls is one packed array whose
+ * rows [seg[2j], seg[2j+1]) are image j's pixels in row-major order
+ * (dcrf_image_layout gives seg and the total row count N). Images start at
+ * multiples of 64 rows; the rows between images are ignored on input by the
+ * solvers, and their content in outputs is unspecified.
+ * Per-image results: Frank-Wolfe steps, traces (record t * B + j) and the
+ * step checkpoints are per image; dcrf_fw_backward writes B x nk weight
+ * gradients (image-major); dcrf_energy returns the sum over the images.
+ * Not available on a batch (DCRF_EUNSUPPORTED): the exact filter mode and
+ * the LP calls. B = 1 is the same as dcrf_set_image. */
+int dcrf_set_images(dcrf_ctx *ctx, int B, const int *H, const int *W,
+                    const float *const *rgb, const dcrf_kernel *kernels, int nk,
+                    int dtype);
+
+/* *nimg = images held (1 after dcrf_set_image), *rows = N, the rows of every
+ * N x C argument; seg (host, 2 nimg ints, may be NULL) = first and one past
+ * the last row of each image. Any pointer may be NULL. */
+int dcrf_image_layout(dcrf_ctx *ctx, int *nimg, int *rows, int *seg);
+
+/* Pick the launch shapes of the filter (splat chunk length of 32, 64 or 128
+ * entries; 1, 2 or 4 16-byte vectors per thread and 128 or 256 threads per
+ * block in the blur) by timing, for each candidate, `reps` (1..1000) runs of
+ * a dense L-channel filter plus the one-hot splat, blur and slice of a
+ * Frank-Wolfe iteration on the context's own lattices; keeps the fastest.
+ * *out (host, may be NULL) receives the choice. Results of every call are the
+ * same for every choice up to floating-point summation order. */
+int dcrf_autotune(dcrf_ctx *ctx, int L, int reps, dcrf_tune *out);
 
 /* Replace the kernel weights w_m (host, nk values) without rebuilding the
  * lattices; recomputes r. */
@@ -146,8 +189,9 @@ int dcrf_qp_apply(dcrf_ctx *ctx, const void *y, const void *mu, int L,
  * minimise (phi - d)^T y + y^T (Psi + D) y over the product of simplices.
  * unary: (dev) N x L; mu: (dev) L x L; y_inout: (dev) N x L, the starting
  * point on input (must lie in the feasible set), the result on output.
- * trace: (host) `iters` records or NULL. One filter call per iteration; the
- * step size is solved on the device. */
+ * trace: (host) `iters` records or NULL (iters x B for a batch, record
+ * t * B + j). One filter call per iteration; the step size is solved on the
+ * device, per image for a batch. */
 int dcrf_qp_frank_wolfe(dcrf_ctx *ctx, const void *unary, const void *mu,
                         int L, void *y_inout, int iters,
                         dcrf_iter_trace *trace);
@@ -211,7 +255,7 @@ int dcrf_project_simplex(dcrf_ctx *ctx, const void *v, int L, void *y);
  *
  * *bytes (host) = the size of the checkpoint buffer for (L, iters) at the
  * context's image and precision: y_t (T x N x L values), s_t (T x N int32)
- * and four doubles per iteration, each part 256-byte aligned. */
+ * and four doubles per iteration and image, each part 256-byte aligned. */
 int dcrf_fw_saved_size(dcrf_ctx *ctx, int L, int iters, size_t *bytes);
 
 /* Forward: unary (dev N x L), mu (dev L x L); y_out (dev N x L) = y_T;
@@ -221,7 +265,8 @@ int dcrf_fw_forward(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
                     int iters, void *y_out, void *saved);
 
 /* Backward: given dl/dy_T in grad_y (dev N x L), writes dl/dphi to
- * grad_unary (dev N x L) and, if grad_w (host, nk doubles) is not NULL,
+ * grad_unary (dev N x L) and, if grad_w (host, nk doubles; B x nk for a
+ * batch, image-major) is not NULL,
  * dl/dw_m for every kernel. unary, mu, L, iters and saved must be those of
  * the forward call, and neither the image nor the weights may have changed
  * in between. Waits for the stream (the step adjoints are scalars reduced on

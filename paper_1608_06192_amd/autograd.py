@@ -10,6 +10,11 @@ gradient's labels s_t (N int32) and four scalars; Q y_t and Q s_t are
 recomputed during the reverse sweep. With ``recompute=True`` the checkpoints
 are dropped after the forward and rebuilt by a second forward at backward
 time, so that nothing of size T x N x L stays alive between the two passes.
+
+On a context that holds a batch of images (``Context.set_images``) the
+unaries and marginals are the packed arrays of the batch, every image takes
+its own steps, and the shared weights receive the sum of the images'
+gradients.
 """
 
 from __future__ import annotations
@@ -50,6 +55,8 @@ class UnrolledFrankWolfe(torch.autograd.Function):
         gphi, gw = ctx.fw_backward(unary, mu, fctx.iters, saved,
                                    grad_y.contiguous())
         fctx.saved_ckpt = None
+        if ctx.nimg > 1:   # a batch shares the weights: sum over its images
+            gw = [sum(g[m] for g in gw) for m in range(ctx.nk)]
         gw_t = torch.tensor(gw, dtype=fctx.wdtype, device=fctx.wdevice)
         return None, gphi, gw_t, None, None, None
 

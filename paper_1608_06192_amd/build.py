@@ -40,6 +40,7 @@ SOURCES = {
     "solvers.hip": [],
     "lp.hip": [],
     "diff.hip": [],
+    "batch.hip": [],
     "abi.cpp": ["-x", "hip"],
 }
 

@@ -57,6 +57,11 @@ void require_image(dcrf_ctx *ctx) {
         dcrf::fail(DCRF_ESTATE, "no image set: call dcrf_set_image first");
 }
 
+void require_single(dcrf_ctx *ctx) {
+    if (ctx->nimg > 1)
+        dcrf::fail(DCRF_EUNSUPPORTED, "the LP relaxation of a batch is not built");
+}
+
 void check_labels(int L) {
     REQUIRE(L >= 1 && L <= 256, "L must be in [1, 256]");
 }
@@ -109,39 +114,105 @@ int dcrf_set_stream(dcrf_ctx *ctx, void *hip_stream) {
     return guarded(ctx, [&] { ctx->stream = static_cast<hipStream_t>(hip_stream); });
 }
 
+static void set_kernels(dcrf_ctx *ctx, const dcrf_kernel *kernels, int nk,
+                        int dtype) {
+    REQUIRE(kernels != nullptr && nk >= 1 && nk <= DCRF_MAXK,
+            "need 1 to 4 kernels");
+    REQUIRE(dtype == DCRF_F32 || dtype == DCRF_F64, "dtype must be F32 or F64");
+    for (int m = 0; m < nk; ++m) {
+        const dcrf_kernel &k = kernels[m];
+        REQUIRE(std::isfinite(k.theta_pos) && k.theta_pos > 0,
+                "theta_pos must be > 0");
+        REQUIRE(!k.use_rgb || (std::isfinite(k.theta_rgb) && k.theta_rgb > 0),
+                "theta_rgb must be > 0 for a colour kernel");
+        REQUIRE(std::isfinite(k.weight) && k.weight >= 0,
+                "weights must be finite and >= 0");
+    }
+    ctx->has_image = false;
+    ctx->nk = nk;
+    ctx->dtype = dtype;
+    ctx->wsum = 0;
+    for (int m = 0; m < nk; ++m) {
+        ctx->kern[m] = kernels[m];
+        ctx->kern[m].use_rgb = kernels[m].use_rgb ? 1 : 0;
+        ctx->wsum += kernels[m].weight;
+    }
+}
+
 int dcrf_set_image(dcrf_ctx *ctx, int H, int W, const float *rgb,
                    const dcrf_kernel *kernels, int nk, int dtype) {
     return guarded(ctx, [&] {
         REQUIRE(H >= 1 && W >= 1 && (long long)H * W <= (1ll << 28),
                 "H and W must be >= 1 with H*W <= 2^28");
         REQUIRE(rgb != nullptr, "rgb is null");
-        REQUIRE(kernels != nullptr && nk >= 1 && nk <= DCRF_MAXK,
-                "need 1 to 4 kernels");
-        REQUIRE(dtype == DCRF_F32 || dtype == DCRF_F64, "dtype must be F32 or F64");
-        for (int m = 0; m < nk; ++m) {
-            const dcrf_kernel &k = kernels[m];
-            REQUIRE(std::isfinite(k.theta_pos) && k.theta_pos > 0,
-                    "theta_pos must be > 0");
-            REQUIRE(!k.use_rgb || (std::isfinite(k.theta_rgb) && k.theta_rgb > 0),
-                    "theta_rgb must be > 0 for a colour kernel");
-            REQUIRE(std::isfinite(k.weight) && k.weight >= 0,
-                    "weights must be finite and >= 0");
-        }
-        ctx->has_image = false;
+        set_kernels(ctx, kernels, nk, dtype);
         ctx->H = H;
         ctx->W = W;
         ctx->N = H * W;
-        ctx->nk = nk;
-        ctx->dtype = dtype;
-        ctx->wsum = 0;
-        for (int m = 0; m < nk; ++m) {
-            ctx->kern[m] = kernels[m];
-            ctx->kern[m].use_rgb = kernels[m].use_rgb ? 1 : 0;
-            ctx->wsum += kernels[m].weight;
-        }
+        ctx->img_H.assign(1, H);
+        ctx->img_W.assign(1, W);
         dcrf::build_lattices(ctx, rgb);
+        dcrf::set_segments(ctx, {0, ctx->N});
         ctx->has_image = true;
         dcrf::compute_row_sums(ctx);
+    });
+}
+
+int dcrf_set_images(dcrf_ctx *ctx, int B, const int *H, const int *W,
+                    const float *const *rgb, const dcrf_kernel *kernels, int nk,
+                    int dtype) {
+    return guarded(ctx, [&] {
+        REQUIRE(B >= 1 && B <= 4096, "B must be in [1, 4096]");
+        REQUIRE(H && W && rgb, "null argument");
+        for (int j = 0; j < B; ++j) {
+            REQUIRE(H[j] >= 1 && W[j] >= 1 && (long long)H[j] * W[j] <= (1ll << 28),
+                    "every H and W must be >= 1 with H*W <= 2^28");
+            REQUIRE(rgb[j] != nullptr, "rgb pointer is null");
+        }
+        set_kernels(ctx, kernels, nk, dtype);
+        if (ctx->mode == DCRF_FILTER_EXACT && B > 1)
+            throw Error{DCRF_EUNSUPPORTED, "a batch needs the lattice filter mode"};
+        if (B == 1) {
+            ctx->H = H[0];
+            ctx->W = W[0];
+            ctx->N = H[0] * W[0];
+            ctx->img_H.assign(1, H[0]);
+            ctx->img_W.assign(1, W[0]);
+            dcrf::build_lattices(ctx, rgb[0]);
+            dcrf::set_segments(ctx, {0, ctx->N});
+        } else {
+            dcrf::build_batch(ctx, B, H, W, rgb);
+        }
+        ctx->has_image = true;
+        dcrf::compute_row_sums(ctx);
+    });
+}
+
+int dcrf_image_layout(dcrf_ctx *ctx, int *nimg, int *rows, int *seg) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        if (nimg) *nimg = ctx->nimg;
+        if (rows) *rows = ctx->N;
+        if (seg)
+            for (size_t i = 0; i < ctx->seg_h.size(); ++i) seg[i] = ctx->seg_h[i];
+    });
+}
+
+int dcrf_autotune(dcrf_ctx *ctx, int L, int reps, dcrf_tune *out) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        check_labels(L);
+        REQUIRE(reps >= 1 && reps <= 1000, "reps must be in [1, 1000]");
+        if (ctx->mode != DCRF_FILTER_LATTICE)
+            throw Error{DCRF_EUNSUPPORTED, "autotuning needs the lattice filter mode"};
+        double ms = 0;
+        dcrf::autotune(ctx, L, reps, &ms);
+        if (out) {
+            out->splat_chunk = ctx->splat_chunk;
+            out->blur_vectors_per_thread = ctx->blur_vpt;
+            out->blur_block = ctx->blur_block;
+            out->ms = ms;
+        }
     });
 }
 
@@ -164,6 +235,8 @@ int dcrf_set_filter_mode(dcrf_ctx *ctx, int mode) {
     return guarded(ctx, [&] {
         REQUIRE(mode == DCRF_FILTER_LATTICE || mode == DCRF_FILTER_EXACT,
                 "mode must be DCRF_FILTER_LATTICE or DCRF_FILTER_EXACT");
+        if (mode == DCRF_FILTER_EXACT && ctx->has_image && ctx->nimg > 1)
+            throw Error{DCRF_EUNSUPPORTED, "a batch needs the lattice filter mode"};
         const bool changed = ctx->mode != mode;
         ctx->mode = mode;
         if (changed && ctx->has_image) dcrf::compute_row_sums(ctx);
@@ -195,6 +268,8 @@ int dcrf_filter(dcrf_ctx *ctx, const void *in, void *out, int C,
         REQUIRE(in && out && in != out, "in and out must be distinct, non-null");
         REQUIRE(C >= 1 && C <= 256, "C must be in [1, 256]");
         REQUIRE((flags & ~(DCRF_ADJOINT | DCRF_EXACT)) == 0, "unknown flags");
+        if ((flags & DCRF_EXACT) && ctx->nimg > 1)
+            throw Error{DCRF_EUNSUPPORTED, "the exact filter of a batch is not built"};
         dcrf::filter_apply(ctx, in, out, C, (flags & DCRF_ADJOINT) != 0,
                            (flags & DCRF_EXACT) != 0);
     });
@@ -259,6 +334,7 @@ int dcrf_lp_subgradient(dcrf_ctx *ctx, const void *unary, int L, const void *y,
         require_image(ctx);
         check_labels(L);
         REQUIRE(unary && y && g && y != g, "null or aliased argument");
+        require_single(ctx);
         const double S = dcrf::lp_subgradient(ctx, unary, L, y, g);
         if (S_lp) *S_lp = S;
     });
@@ -310,6 +386,7 @@ int dcrf_lp_descent(dcrf_ctx *ctx, const void *unary, int L, void *y_inout,
         require_image(ctx);
         check_labels(L);
         REQUIRE(unary && y_inout, "null argument");
+        require_single(ctx);
         REQUIRE(steps >= 0, "steps must be >= 0");
         REQUIRE(std::isfinite(beta0) && beta0 > 0, "beta0 must be > 0");
         REQUIRE(best_y != y_inout, "best_y must not alias y");

@@ -168,6 +168,16 @@ struct dcrf_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     int H = 0, W = 0, N = 0, nk = 0, dtype = DCRF_F32;
+    // Images held by the context: image j owns pixel rows
+    // [seg[2j], seg[2j+1]); a single image is the segment [0, N). Rows
+    // between segments (alignment padding of a batch) belong to no image.
+    int nimg = 1;
+    std::vector<int> seg_h;
+    std::vector<int> img_H, img_W;
+    dcrf::DevBuf seg;
+    // launch-shape parameters chosen by dcrf_autotune
+    int blur_vpt = 1;        // 16-byte vectors per thread in the blur
+    int blur_block = 256;    // threads per block in the blur
     int mode = DCRF_FILTER_LATTICE;
     bool has_image = false;
     dcrf_kernel kern[DCRF_MAXK];
@@ -195,6 +205,8 @@ namespace dcrf {
 void build_lattices(dcrf_ctx *ctx, const float *rgb);
 void lattice_export(dcrf_ctx *ctx, int m, int32_t *keys, int32_t *vid,
                     double *w);
+// cut every lattice's inverse index into chunks of at most `chunk` entries
+void rechunk(dcrf_ctx *ctx, int chunk);
 
 // filter.hip
 // out = K' in (N x C), lattice or exact, optionally the transpose
@@ -261,6 +273,30 @@ void project_simplex(dcrf_ctx *ctx, const void *v, int L, void *y);
 void lp_release(dcrf_ctx *ctx);
 
 inline int ceil_div(long long a, long long b) { return int((a + b - 1) / b); }
+
+// Segments of the pixel range (see dcrf_ctx): set on the host and uploaded.
+void set_segments(dcrf_ctx *ctx, const std::vector<int> &seg);
+// Number of tiles of TP pixels over all images (no tile straddles two).
+inline int seg_tiles(const dcrf_ctx *ctx, int TP) {
+    long long n = 0;
+    for (int j = 0; j < ctx->nimg; ++j)
+        n += ceil_div(ctx->seg_h[2 * j + 1] - ctx->seg_h[2 * j], TP);
+    return int(n);
+}
+// First tile of each image (nimg + 1 entries) for tiles of TP pixels.
+inline std::vector<int> seg_tile_offsets(const dcrf_ctx *ctx, int TP) {
+    std::vector<int> o(ctx->nimg + 1, 0);
+    for (int j = 0; j < ctx->nimg; ++j)
+        o[j + 1] = o[j] + ceil_div(ctx->seg_h[2 * j + 1] - ctx->seg_h[2 * j], TP);
+    return o;
+}
+
+// batch.hip: the lattices of several images, concatenated (vertex ids,
+// neighbour ids and inverse-index entries renumbered), so that every filter
+// launch covers the whole batch; sets the segments.
+void build_batch(dcrf_ctx *ctx, int B, const int *H, const int *W,
+                 const float *const *rgb);
+void autotune(dcrf_ctx *ctx, int L, int reps, double *best_ms);
 
 // Records events around the launches made during its lifetime when the
 // context's profiler is on.

@@ -23,6 +23,10 @@
 //   d<Zbar, Q X>/dw_m = <Zbar mu, (K~_m - I) X> + sum_a rho_a (K~_m 1 - 1)_a,
 //   rho_a = sum_i Zbar_a(i) X_a(i) sum_j |mu_ij|,
 // with K~_m the lattice filter of kernel m alone.
+//
+// For a context that holds a batch of images every image has its own step
+// sizes, step adjoints and weight gradient: the reductions are per tile of
+// one image (whole pixels per block) and summed per image on the host.
 
 #include <algorithm>
 #include <cmath>
@@ -35,13 +39,15 @@ namespace dcrf {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kMaxGrid = 1024;
+constexpr int kGroups = 8;   // pixel groups (kThreads / L pixels) per tile
 
 template <typename T>
-__global__ void k_softmax_neg(int N, int L, const T *__restrict__ phi,
-                              T *__restrict__ y) {
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= N) return;
+__global__ void k_softmax_neg(const int *__restrict__ seg, int nimg, int L,
+                              const T *__restrict__ phi, T *__restrict__ y) {
+    int lo, hi;
+    tile_range(seg, nimg, 256, blockIdx.x, lo, hi);
+    const int a = lo + threadIdx.x;
+    if (a >= hi) return;
     const T *p = phi + (size_t)a * L;
     T mn = p[0];
     for (int i = 1; i < L; ++i) mn = fmin(mn, p[i]);
@@ -90,16 +96,25 @@ __device__ __forceinline__ void bsum(double (&v)[NV], double *lds) {
     block_sum<NV, kThreads>(v, lds);
 }
 
-// partial sums of abar = <ybar, s - y> + <Pbar, S - P>
+// Pixel rows [lo, hi) of this block's tile (kGroups groups of ppb pixels);
+// returns the image.
+__device__ __forceinline__ int diff_tile(const int *seg, int nimg, int ppb,
+                                         int &lo, int &hi) {
+    return tile_range(seg, nimg, ppb * kGroups, blockIdx.x, lo, hi);
+}
+
+// per-tile partial sums of abar = <ybar, s - y> + <Pbar, S - P>
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_abar(int N, int L, const T *__restrict__ ybar, const T *__restrict__ y,
-       const int32_t *__restrict__ s, const T *__restrict__ Pbar,
-       const T *__restrict__ S, const T *__restrict__ P, double *__restrict__ part) {
+k_abar(const int *__restrict__ seg, int nimg, int L, const T *__restrict__ ybar,
+       const T *__restrict__ y, const int32_t *__restrict__ s,
+       const T *__restrict__ Pbar, const T *__restrict__ S,
+       const T *__restrict__ P, double *__restrict__ part) {
     __shared__ double red[kThreads];
     double acc[1] = {0.0};
-    for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < (size_t)N * L;
-         e += (size_t)gridDim.x * kThreads) {
+    int lo, hi;
+    diff_tile(seg, nimg, kThreads / L, lo, hi);
+    for (size_t e = (size_t)lo * L + threadIdx.x; e < (size_t)hi * L; e += kThreads) {
         const int a = int(e / L);
         const int i = int(e - (size_t)a * L);
         const double si = (i == s[a]) ? 1.0 : 0.0;
@@ -116,15 +131,16 @@ struct StepBar {
 
 template <typename T>
 struct UpdArgs {
-    int N, L, nk;
+    const int *seg;
+    int nimg, L, nk;
     T *ybar, *Pbar, *cbar;
     const T *y, *P, *S, *c;
     const int32_t *s;
     const T *Ks[DCRF_MAXK];
     const T *mu, *mabs;
     double *rho;
-    double *part;    // per block: nk partial sums of <Sbar mu, K~_m s - s>
-    StepBar sb;
+    double *part;    // per tile: nk partial sums of <Sbar mu, K~_m s - s>
+    const StepBar *sb;   // per image
 };
 
 // One reverse step (see the file comment), whole pixels per block so that
@@ -142,10 +158,12 @@ k_diff_update(UpdArgs<T> A) {
     double acc[DCRF_MAXK];
 #pragma unroll
     for (int m = 0; m < DCRF_MAXK; ++m) acc[m] = 0.0;
-    const StepBar &b = A.sb;
-    for (int g = blockIdx.x; (long long)g * ppb < A.N; g += gridDim.x) {
-        const long long a = (long long)g * ppb + lp;
-        const bool act = lp < ppb && a < A.N;
+    int lo, hi;
+    const int img = diff_tile(A.seg, A.nimg, ppb, lo, hi);
+    const StepBar b = A.sb[img < 0 ? 0 : img];
+    for (int g0 = lo; g0 < hi; g0 += ppb) {
+        const long long a = (long long)g0 + lp;
+        const bool act = lp < ppb && a < hi;
         const size_t e = (size_t)a * L + i;
         double sbar = 0.0;
         int sa = 0;
@@ -202,13 +220,14 @@ k_rowmat(int N, int L, const T *__restrict__ X, const T *__restrict__ mu,
 
 template <typename T>
 struct FinArgs {
-    int N, L, nk;
+    const int *seg;
+    int nimg, L, nk;
     const T *ybar, *KtZ, *Z, *Pbar, *y0, *cbar, *r, *mabs;
     const T *Ky0[DCRF_MAXK];
     const T *K1[DCRF_MAXK];
     const double *rho;
     T *phibar;
-    double *part;   // per block: nk partial sums
+    double *part;   // per tile: nk partial sums
 };
 
 // The end of the sweep: P_0 = Q y_0, c = phi - d, d's dependence on w, and
@@ -227,9 +246,11 @@ k_diff_final(FinArgs<T> A) {
     double acc[DCRF_MAXK];
 #pragma unroll
     for (int m = 0; m < DCRF_MAXK; ++m) acc[m] = 0.0;
-    for (int g = blockIdx.x; (long long)g * ppb < A.N; g += gridDim.x) {
-        const long long a = (long long)g * ppb + lp;
-        const bool act = lp < ppb && a < A.N;
+    int lo, hi;
+    diff_tile(A.seg, A.nimg, ppb, lo, hi);
+    for (int g0 = lo; g0 < hi; g0 += ppb) {
+        const long long a = (long long)g0 + lp;
+        const bool act = lp < ppb && a < hi;
         const size_t e = (size_t)a * L + i;
         double yb0 = 0.0, y0 = 0.0;
         if (act) {
@@ -264,7 +285,7 @@ k_diff_final(FinArgs<T> A) {
 }
 
 struct DiffWork {
-    DevBuf ybar, Pbar, cbar, P, S, OH, c, Z, KtZ, rho, part, mabs, ones;
+    DevBuf ybar, Pbar, cbar, P, S, OH, c, Z, KtZ, rho, part, mabs, ones, sb;
     DevBuf Ks[DCRF_MAXK], Ky0[DCRF_MAXK], K1[DCRF_MAXK];
 };
 
@@ -285,31 +306,38 @@ SavedLayout saved_layout(dcrf_ctx *ctx, int L, int iters) {
     o.y = 0;
     o.s = align256(o.y + (size_t)iters * NL * ctx->elt());
     o.stats = align256(o.s + (size_t)iters * ctx->N * 4);
-    o.total = align256(o.stats + (size_t)iters * kFWStats * 8);
+    o.total = align256(o.stats + (size_t)iters * ctx->nimg * kFWStats * 8);
     return o;
 }
 
-int grid_pix(int N, int L) {
-    return std::max(1, std::min(kMaxGrid, ceil_div(N, kThreads / L)));
-}
-
-double host_sum(dcrf_ctx *ctx, const double *d, int n, int stride, int k) {
-    std::vector<double> h((size_t)n * stride);
+// Per-image sums of per-tile partials (stride doubles per tile, component k):
+// out[j] = sum over the tiles [toff[j], toff[j+1]) of image j.
+void image_sums(dcrf_ctx *ctx, const double *d, const std::vector<int> &toff,
+                int stride, int ncomp, std::vector<double> &out) {
+    const int nt = toff.back();
+    std::vector<double> h((size_t)nt * stride);
     DCRF_TRY_HIP(hipMemcpyAsync(h.data(), d, h.size() * 8, hipMemcpyDeviceToHost,
                                 ctx->stream));
     DCRF_TRY_HIP(hipStreamSynchronize(ctx->stream));
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += h[(size_t)i * stride + k];
-    return s;
+    const int nimg = int(toff.size()) - 1;
+    out.assign((size_t)nimg * ncomp, 0.0);
+    for (int j = 0; j < nimg; ++j)
+        for (int t = toff[j]; t < toff[j + 1]; ++t)
+            for (int k = 0; k < ncomp; ++k)
+                out[(size_t)j * ncomp + k] += h[(size_t)t * stride + k];
 }
 
 template <typename T>
 void backward_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, int iters,
                 const char *saved, const T *grad_y, T *grad_phi, double *grad_w) {
     const hipStream_t st = ctx->stream;
-    const int N = ctx->N, nk = ctx->nk;
+    const int N = ctx->N, nk = ctx->nk, nimg = ctx->nimg;
+    const int *seg = ctx->seg.as<int>();
     const size_t NL = (size_t)N * L;
     const size_t B = NL * sizeof(T);
+    const int TPD = (kThreads / L) * kGroups;
+    const int GD = seg_tiles(ctx, TPD);
+    const std::vector<int> toff = seg_tile_offsets(ctx, TPD);
     DiffWork &W = diff_work(ctx);
     for (DevBuf *b : {&W.ybar, &W.Pbar, &W.cbar, &W.P, &W.S, &W.OH, &W.c, &W.Z,
                       &W.KtZ})
@@ -320,13 +348,14 @@ void backward_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, int iters,
         W.K1[m].ensure((size_t)N * sizeof(T), st);
     }
     W.rho.ensure((size_t)N * 8, st);
-    W.part.ensure((size_t)kMaxGrid * DCRF_MAXK * 8, st);
+    W.part.ensure((size_t)GD * DCRF_MAXK * 8, st);
     W.mabs.ensure((size_t)L * sizeof(T), st);
     W.ones.ensure((size_t)N * sizeof(T), st);
+    W.sb.ensure((size_t)nimg * sizeof(StepBar), st);
     const SavedLayout lay = saved_layout(ctx, L, iters);
     const T *ys = reinterpret_cast<const T *>(saved + lay.y);
     const int32_t *ss = reinterpret_cast<const int32_t *>(saved + lay.s);
-    std::vector<double> stats((size_t)iters * kFWStats);
+    std::vector<double> stats((size_t)iters * nimg * kFWStats);
     DCRF_TRY_HIP(hipMemcpyAsync(stats.data(), saved + lay.stats, stats.size() * 8,
                                 hipMemcpyDeviceToHost, st));
     const int gE = ceil_div((long long)NL, 256);
@@ -339,31 +368,37 @@ void backward_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, int iters,
     hipLaunchKernelGGL((k_c<T>), dim3(gE), dim3(256), 0, st, N, L, phi,
                        ctx->r.as<T>(), W.mabs.as<T>(), W.c.as<T>());
     DCRF_CHECK_LAUNCH();
-    const int GP = grid_pix(N, L);
-    const int GA = std::min(kMaxGrid, gE);
-    std::vector<double> gw(nk, 0.0);
+    std::vector<double> gw((size_t)nimg * nk, 0.0), sums;
+    std::vector<StepBar> sb(nimg);
     for (int t = iters - 1; t >= 0; --t) {
         const T *yt = ys + (size_t)t * NL;
         const int32_t *sl = ss + (size_t)t * N;
-        const double *stt = stats.data() + (size_t)t * kFWStats;
         qp_apply(ctx, yt, mu, L, W.P.p);
         hipLaunchKernelGGL((k_onehot_d<T>), dim3(gE), dim3(256), 0, st, N, L, sl,
                            W.OH.as<T>());
         qp_apply(ctx, W.OH.p, mu, L, W.S.p);
         for (int m = 0; m < nk; ++m) filter_kernel(ctx, m, W.OH.p, W.Ks[m].p, L, false);
-        hipLaunchKernelGGL((k_abar<T>), dim3(GA), dim3(kThreads), 0, st, N, L, ybar,
-                           yt, sl, Pbar, W.S.as<T>(), W.P.as<T>(),
+        hipLaunchKernelGGL((k_abar<T>), dim3(GD), dim3(kThreads), 0, st, seg, nimg,
+                           L, ybar, yt, sl, Pbar, W.S.as<T>(), W.P.as<T>(),
                            W.part.as<double>());
         DCRF_CHECK_LAUNCH();
-        const double abar = host_sum(ctx, W.part.as<double>(), GA, 1, 0);
-        const double al = stt[0], a2 = stt[1];
-        double b1bar = 0.0, a2bar = 0.0;
-        if (stt[3] != 0.0) {
-            b1bar = -abar / (2.0 * a2);
-            a2bar = -abar * al / a2;
+        image_sums(ctx, W.part.as<double>(), toff, 1, 1, sums);
+        for (int j = 0; j < nimg; ++j) {
+            const double *stt = stats.data() + ((size_t)t * nimg + j) * kFWStats;
+            const double abar = sums[j], al = stt[0], a2 = stt[1];
+            double b1bar = 0.0, a2bar = 0.0;
+            if (stt[3] != 0.0) {
+                b1bar = -abar / (2.0 * a2);
+                a2bar = -abar * al / a2;
+            }
+            sb[j] = StepBar{al, -2.0 * b1bar + a2bar, b1bar - a2bar, b1bar - a2bar,
+                            a2bar, -b1bar, b1bar};
         }
+        DCRF_TRY_HIP(hipMemcpyAsync(W.sb.p, sb.data(), nimg * sizeof(StepBar),
+                                    hipMemcpyHostToDevice, st));
         UpdArgs<T> U{};
-        U.N = N;
+        U.seg = seg;
+        U.nimg = nimg;
         U.L = L;
         U.nk = nk;
         U.ybar = ybar;
@@ -379,17 +414,16 @@ void backward_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, int iters,
         U.mabs = W.mabs.as<T>();
         U.rho = W.rho.as<double>();
         U.part = W.part.as<double>();
-        U.sb = StepBar{al, -2.0 * b1bar + a2bar, b1bar - a2bar, b1bar - a2bar,
-                       a2bar, -b1bar, b1bar};
-        hipLaunchKernelGGL((k_diff_update<T>), dim3(GP), dim3(kThreads), 0, st, U);
+        U.sb = W.sb.as<StepBar>();
+        hipLaunchKernelGGL((k_diff_update<T>), dim3(GD), dim3(kThreads), 0, st, U);
         DCRF_CHECK_LAUNCH();
-        for (int m = 0; m < nk; ++m)
-            gw[m] += host_sum(ctx, W.part.as<double>(), GP, DCRF_MAXK, m);
+        image_sums(ctx, W.part.as<double>(), toff, DCRF_MAXK, nk, sums);
+        for (size_t i = 0; i < gw.size(); ++i) gw[i] += sums[i];
     }
     // the end of the sweep
     const T *y0 = ys;
-    hipLaunchKernelGGL((k_rowmat<T>), dim3(GP), dim3(kThreads), 0, st, N, L, Pbar,
-                       mu, W.Z.as<T>());
+    hipLaunchKernelGGL((k_rowmat<T>), dim3(std::min(4096, ceil_div(N, kThreads / L))),
+                       dim3(kThreads), 0, st, N, L, Pbar, mu, W.Z.as<T>());
     filter_apply(ctx, W.Z.p, W.KtZ.p, L, true, false);
     hipLaunchKernelGGL((k_fill_d<T>), dim3(ceil_div(N, 256)), dim3(256), 0, st,
                        (size_t)N, W.ones.as<T>(), T(1));
@@ -398,7 +432,8 @@ void backward_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, int iters,
         filter_kernel(ctx, m, W.ones.p, W.K1[m].p, 1, false);
     }
     FinArgs<T> F{};
-    F.N = N;
+    F.seg = seg;
+    F.nimg = nimg;
     F.L = L;
     F.nk = nk;
     F.ybar = ybar;
@@ -416,20 +451,20 @@ void backward_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, int iters,
     F.rho = W.rho.as<double>();
     F.phibar = grad_phi;
     F.part = W.part.as<double>();
-    hipLaunchKernelGGL((k_diff_final<T>), dim3(GP), dim3(kThreads), 0, st, F);
+    hipLaunchKernelGGL((k_diff_final<T>), dim3(GD), dim3(kThreads), 0, st, F);
     DCRF_CHECK_LAUNCH();
-    for (int m = 0; m < nk; ++m)
-        gw[m] += host_sum(ctx, W.part.as<double>(), GP, DCRF_MAXK, m);
+    image_sums(ctx, W.part.as<double>(), toff, DCRF_MAXK, nk, sums);
+    for (size_t i = 0; i < gw.size(); ++i) gw[i] += sums[i];
     if (grad_w)
-        for (int m = 0; m < nk; ++m) grad_w[m] = gw[m];
+        for (size_t i = 0; i < gw.size(); ++i) grad_w[i] = gw[i];
 }
 
 template <typename T>
 void forward_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y, int iters,
                char *saved) {
     const SavedLayout lay = saved_layout(ctx, L, iters);
-    hipLaunchKernelGGL((k_softmax_neg<T>), dim3(ceil_div(ctx->N, 256)), dim3(256),
-                       0, ctx->stream, ctx->N, L, phi, y);
+    hipLaunchKernelGGL((k_softmax_neg<T>), dim3(seg_tiles(ctx, 256)), dim3(256),
+                       0, ctx->stream, ctx->seg.as<int>(), ctx->nimg, L, phi, y);
     DCRF_CHECK_LAUNCH();
     FWCheckpoint cp{saved + lay.y, reinterpret_cast<int32_t *>(saved + lay.s),
                     reinterpret_cast<double *>(saved + lay.stats)};
@@ -477,7 +512,8 @@ void diff_release(dcrf_ctx *ctx) {
     if (!ctx->diff) return;
     DiffWork *W = static_cast<DiffWork *>(ctx->diff);
     for (DevBuf *b : {&W->ybar, &W->Pbar, &W->cbar, &W->P, &W->S, &W->OH, &W->c,
-                      &W->Z, &W->KtZ, &W->rho, &W->part, &W->mabs, &W->ones})
+                      &W->Z, &W->KtZ, &W->rho, &W->part, &W->mabs, &W->ones,
+                      &W->sb})
         b->release();
     for (int m = 0; m < DCRF_MAXK; ++m) {
         W->Ks[m].release();

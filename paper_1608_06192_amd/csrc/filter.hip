@@ -106,15 +106,15 @@ __device__ __forceinline__ double2 blur3(double2 c, double2 p, double2 q) {
     return make_double2(0.5 * c.x + 0.25 * (p.x + q.x), 0.5 * c.y + 0.25 * (p.y + q.y));
 }
 
-// pass p of every lattice with d >= p; one thread per 16 bytes of a vertex
-// row, flattened over sum_m M_m x ld / (16 / sizeof(T))
+// pass p of every lattice with d >= p, over 16-byte vectors of the vertex
+// rows flattened over sum_m M_m x ld / (16 / sizeof(T)); a block covers
+// blockDim * vpt consecutive vectors, thread t taking t, t + blockDim, ...
+// so that every access stays coalesced and vpt loads are in flight per thread
 template <typename T>
-__global__ void __launch_bounds__(256)
-k_blur_pass(LatSet<T> ls, int pass, int reverse, long long total) {
+__device__ __forceinline__ void blur_vector(const LatSet<T> &ls, int pass,
+                                            int reverse, long long e) {
     using V = typename Vec16<T>::type;
     constexpr int vw = Vec16<T>::n;
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= total) return;
     int m = 0;
     while (m + 1 < ls.nk && e >= ls.off[m + 1] / vw) ++m;
     const LatView<T> &L = ls.l[m];
@@ -134,6 +134,17 @@ k_blur_pass(LatSet<T> ls, int pass, int reverse, long long total) {
     const V vm = nm >= 0 ? src[(size_t)nm * G + g] : zero;
     dst[r] = blur3(src[r], vp, vm);
     if (pass == 1) reinterpret_cast<V *>(L.V0)[r] = zero;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_blur_pass(LatSet<T> ls, int pass, int reverse, long long total, int vpt) {
+    const long long base = (long long)blockIdx.x * blockDim.x * vpt + threadIdx.x;
+    for (int q = 0; q < vpt; ++q) {
+        const long long e = base + (long long)q * blockDim.x;
+        if (e >= total) return;
+        blur_vector<T>(ls, pass, reverse, e);
+    }
 }
 
 // ------------------------------------------------------------------ slice
@@ -321,11 +332,12 @@ void blur_all_t(dcrf_ctx *ctx, int C, bool adjoint) {
     for (int m = 0; m < ctx->nk; ++m) maxd = std::max(maxd, ctx->lat[m].d);
     const long long total = ls.off[ctx->nk] / Vec16<T>::n;
     if (total == 0) return;
+    const int bs = ctx->blur_block, vpt = ctx->blur_vpt;
     for (int p = 0; p <= maxd; ++p) {
         ProfScope ps(ctx, PROF_BLUR);
-        hipLaunchKernelGGL((k_blur_pass<T>), dim3(ceil_div(total, 256)),
-                           dim3(256), 0, ctx->stream, ls, p, adjoint ? 1 : 0,
-                           total);
+        hipLaunchKernelGGL((k_blur_pass<T>), dim3(ceil_div(total, (long long)bs * vpt)),
+                           dim3(bs), 0, ctx->stream, ls, p, adjoint ? 1 : 0,
+                           total, vpt);
     }
     DCRF_CHECK_LAUNCH();
 }
@@ -400,8 +412,11 @@ void filter_kernel_t(dcrf_ctx *ctx, int m, const T *in, T *out, int C,
     const long long total = ls.off[1] / Vec16<T>::n;
     if (total > 0)
         for (int p = 0; p <= ls.l[0].d; ++p)
-            hipLaunchKernelGGL((k_blur_pass<T>), dim3(ceil_div(total, 256)),
-                               dim3(256), 0, s, ls, p, adjoint ? 1 : 0, total);
+            hipLaunchKernelGGL((k_blur_pass<T>),
+                               dim3(ceil_div(total, (long long)ctx->blur_block *
+                                                        ctx->blur_vpt)),
+                               dim3(ctx->blur_block), 0, s, ls, p, adjoint ? 1 : 0,
+                               total, ctx->blur_vpt);
     const int N = ctx->N;
     constexpr int TP = RowTile<T>::kPix;
     if (C <= kRowMaxC) {

@@ -109,6 +109,27 @@ template <typename T> struct RowTile;
 template <> struct RowTile<float> { static constexpr int kPix = 128; };
 template <> struct RowTile<double> { static constexpr int kPix = 64; };
 
+// Tile `tile` of the per-image tilings of TP pixels, images taken in order
+// (see dcrf_ctx::seg): returns the image and sets [lo, hi), its pixel rows.
+// Images start at multiples of 64 pixels, so a tile's rows start 16-byte
+// aligned like those of a single image.
+__device__ __forceinline__ int tile_range(const int *__restrict__ seg, int nimg,
+                                          int TP, int tile, int &lo, int &hi) {
+    int t = tile;
+    for (int j = 0; j < nimg; ++j) {
+        const int s = seg[2 * j], e = seg[2 * j + 1];
+        const int nt = (e - s + TP - 1) / TP;
+        if (t < nt) {
+            lo = s + t * TP;
+            hi = min(lo + TP, e);
+            return j;
+        }
+        t -= nt;
+    }
+    lo = hi = 0;
+    return -1;
+}
+
 // Largest channel count handled with per-thread register rows.
 constexpr int kRowMaxC = 32;
 

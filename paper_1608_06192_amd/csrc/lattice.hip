@@ -329,6 +329,8 @@ __global__ void k_features(int N, int W, const float *__restrict__ rgb,
 // Inverse index of lattice m: for each vertex the (pixel, weight) pairs that
 // splat into it, split into chunks of at most `chunk` pairs; the gather splat
 // runs one group of lanes per chunk.
+void chunk_index(dcrf_ctx *ctx, int m);
+
 template <typename T>
 void build_inverse_index(dcrf_ctx *ctx, int m) {
     Lattice &L = ctx->lat[m];
@@ -353,6 +355,15 @@ void build_inverse_index(dcrf_ctx *ctx, int m) {
                        L.ent_pix.as<int>(), L.ent_w.as<T>(), L.ent_v.as<int>());
     DCRF_TRY_HIP(hipMemcpyAsync(&L.nent, L.csr_off.as<int>() + M, 4,
                                 hipMemcpyDeviceToHost, s));
+    chunk_index(ctx, m);
+}
+
+// chunk list of lattice m from its inverse index (csr_off) and L.chunk
+void chunk_index(dcrf_ctx *ctx, int m) {
+    Lattice &L = ctx->lat[m];
+    const hipStream_t s = ctx->stream;
+    const int M = L.M;
+    int *counts = L.csr_tmp.as<int>();
     if (M > 0)
         hipLaunchKernelGGL(k_chunk_count, dim3(ceil_div(M, 256)), dim3(256), 0, s,
                            M, L.csr_off.as<int>(), L.chunk, counts);
@@ -469,6 +480,19 @@ void build_lattices(dcrf_ctx *ctx, const float *rgb) {
         build_all<double>(ctx, rgb);
     else
         build_all<float>(ctx, rgb);
+}
+
+void rechunk(dcrf_ctx *ctx, int chunk) {
+    int maxM = 0;
+    for (int m = 0; m < ctx->nk; ++m) maxM = std::max(maxM, ctx->lat[m].M);
+    // flags, then the tile sums of the scan over M + 1 counts
+    ctx->scratch.ensure(64 + (size_t)(ceil_div((long long)maxM + 1, kScanTile) + 2) * 4,
+                        ctx->stream);
+    ctx->splat_chunk = chunk;
+    for (int m = 0; m < ctx->nk; ++m) {
+        ctx->lat[m].chunk = chunk;
+        chunk_index(ctx, m);
+    }
 }
 
 void lattice_export(dcrf_ctx *ctx, int m, int32_t *keys, int32_t *vid,

@@ -5,7 +5,7 @@
 //   c = phi - d (eq. cvx-qp-min) or, inside CCCP, phi - 2 d * y^k
 //   (eq. cccp-qp), with (Psi y)_a(i) = sum_j mu_ij (K'Y)_a(j) and
 //   d_a(i) = (sum_j |mu_ij|) (K'1)_a (eq. pairwise-matrix, eq. RL-diagonal).
-// One iteration is four kinds of launch, with no host synchronisation:
+// One iteration is five kinds of launch, with no host synchronisation:
 //   1. k_fw_lmo: apply the previous step (y <- y + alpha (s - y) and
 //      P_y <- (1 - alpha) P_y + alpha P_s, App. B's recurrence), form the
 //      gradient g = c + 2 P_y (eq. LRQP-grad), take the conditional gradient
@@ -14,11 +14,15 @@
 //   2. the gather splat of the one-hot s into the lattices;
 //   3. the blur passes;
 //   4. k_fw_slice: slice, apply mu and the diagonal, P_s = (Psi + D) s,
-//      reduce <y,P_s> and <s,P_s>; the last block to finish reduces every
-//      block's partial sums in a fixed order and solves the step size on the
-//      device (App. B, eq. alpha-opt, written with the four products so that
-//      it is exact for a non-symmetric approximate Psi; endpoints when the
-//      quadratic is not convex).
+//      reduce <y,P_s> and <s,P_s> per block;
+//   5. k_fw_alpha: one block per image reduces that image's partial sums in
+//      a fixed order and solves its step size on the device (App. B,
+//      eq. alpha-opt, written with the four products so that it is exact for
+//      a non-symmetric approximate Psi; endpoints when the quadratic is not
+//      convex).
+// The per-pixel kernels run one block per tile of one image, so a context
+// that holds a batch of images (concatenated lattices, see batch.hip) solves
+// every image's QP, each with its own step size, in the same launches.
 // Up to 32 labels the per-pixel kernels keep a pixel's labels in registers
 // (one thread per pixel, rows staged through LDS); above that one lane per
 // (pixel, label). Dot products accumulate in FP64.
@@ -38,11 +42,12 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kMaxGrid = 2048;
+// pixel groups per block of the flat (one lane per label) kernels
+constexpr int kFlatGroups = 8;
 constexpr int kP1 = 8;   // partial sums written by k_fw_lmo
 constexpr int kP2 = 2;   // partial sums written by k_fw_slice
 
-// scalar slot in fw_scal (doubles): the step size of the last iteration
-constexpr int kAlpha = 0;
+// fw_scal holds one double per image: the step size of its last iteration
 // doubles per iteration in a forward checkpoint: alpha, a2, b1, interior
 constexpr int kStats = 4;
 
@@ -89,6 +94,8 @@ struct FWArgs {
     const int32_t *sprev;
     double *scal, *part;
     int first;
+    const int *seg;   // image segments, one block per tile of an image
+    int nimg;
 };
 
 template <typename T>
@@ -103,6 +110,8 @@ struct FWSliceArgs {
     int G1;
     double *trace;   // 4 doubles per iteration
     int it;
+    const int *seg;
+    int nimg;
 };
 
 // ---------------------------------------------------------- row kernels
@@ -121,13 +130,15 @@ k_fw_lmo_rows(FWArgs<T> A) {
     __shared__ __align__(16) T lds[TP * (LMAX | 1)];
     __shared__ double red[kP1 * TP];
     const int L = A.L;
-    const T al = A.first ? T(0) : T(A.scal[kAlpha]);
+    int lo, hi;
+    const int img = tile_range(A.seg, A.nimg, TP, blockIdx.x, lo, hi);
+    const T al = (A.first || img < 0) ? T(0) : T(A.scal[img]);
     double acc[kP1];
 #pragma unroll
     for (int i = 0; i < kP1; ++i) acc[i] = 0.0;
-    for (long long p0 = (long long)blockIdx.x * TP; p0 < A.N;
-         p0 += (long long)gridDim.x * TP) {
-        const int np = (int)min((long long)TP, A.N - p0);
+    {
+        const long long p0 = lo;
+        const int np = hi - lo;
         const long long a = p0 + threadIdx.x;
         const bool act = (int)threadIdx.x < np;
         T y[LMAX], py[LMAX], c[LMAX];
@@ -187,20 +198,32 @@ k_fw_lmo_rows(FWArgs<T> A) {
 // One block: fixed-order reduction of every block's partial sums, the exact
 // line search (App. B) and the trace entry. A launch of its own, so that the
 // partial sums of all blocks are visible without device-wide fences.
+// One block per image: its tiles are [t1a, t1b) of the k_fw_lmo tiling (TP1
+// pixels) and [t2a, t2b) of the k_fw_slice tiling (TP2 pixels).
 template <int NT>
 __global__ void __launch_bounds__(NT)
-k_fw_alpha(const double *__restrict__ part1, int G1,
-           const double *__restrict__ part2, int G2, double *__restrict__ scal,
-           double *__restrict__ trace, int it, double *__restrict__ stats) {
+k_fw_alpha(const double *__restrict__ part1, const double *__restrict__ part2,
+           const int *__restrict__ seg, int nimg, int TP1, int TP2,
+           double *__restrict__ scal, double *__restrict__ trace, int it,
+           double *__restrict__ stats) {
     __shared__ double red[(kP1 + kP2) * NT];
     const int t = threadIdx.x;
+    const int img = blockIdx.x;
+    int t1a = 0, t2a = 0;
+    for (int k = 0; k < img; ++k) {
+        const int n = seg[2 * k + 1] - seg[2 * k];
+        t1a += (n + TP1 - 1) / TP1;
+        t2a += (n + TP2 - 1) / TP2;
+    }
+    const int n = seg[2 * img + 1] - seg[2 * img];
+    const int t1b = t1a + (n + TP1 - 1) / TP1, t2b = t2a + (n + TP2 - 1) / TP2;
     double tot[kP1 + kP2];
 #pragma unroll
     for (int i = 0; i < kP1 + kP2; ++i) tot[i] = 0.0;
-    for (int b = t; b < G1; b += NT)
+    for (int b = t1a + t; b < t1b; b += NT)
 #pragma unroll
         for (int i = 0; i < kP1; ++i) tot[i] += part1[(size_t)b * kP1 + i];
-    for (int b = t; b < G2; b += NT)
+    for (int b = t2a + t; b < t2b; b += NT)
 #pragma unroll
         for (int i = 0; i < kP2; ++i) tot[kP1 + i] += part2[(size_t)b * kP2 + i];
     block_sum<kP1 + kP2, NT>(tot, red);
@@ -215,14 +238,14 @@ k_fw_alpha(const double *__restrict__ part1, int G1,
             alpha = fmin(fmax(-b1 / (2.0 * a2), 0.0), 1.0);
         else
             alpha = (a2 + b1 < 0.0) ? 1.0 : 0.0;
-        scal[kAlpha] = alpha;
-        double *tr = trace + (size_t)it * 4;
+        scal[img] = alpha;
+        double *tr = trace + ((size_t)it * nimg + img) * 4;
         tr[0] = cy + Ayy;        // f(y_t)
         tr[1] = gy - gs;         // <g, y_t - s_t>
         tr[2] = alpha;
         tr[3] = changed;
         if (stats) {   // checkpoint for the reverse sweep
-            double *st = stats + (size_t)it * kStats;
+            double *st = stats + ((size_t)it * nimg + img) * kStats;
             st[0] = alpha;
             st[1] = a2;
             st[2] = b1;
@@ -248,9 +271,11 @@ k_fw_slice_rows(FWSliceArgs<T> A, LatSet<T> ls) {
         __syncthreads();
     }
     double acc[kP2] = {0.0, 0.0};
-    for (long long p0 = (long long)blockIdx.x * TP; p0 < A.N;
-         p0 += (long long)gridDim.x * TP) {
-        const int np = (int)min((long long)TP, A.N - p0);
+    int lo, hi;
+    tile_range(A.seg, A.nimg, TP, blockIdx.x, lo, hi);
+    {
+        const long long p0 = lo;
+        const int np = hi - lo;
         const long long a = p0 + threadIdx.x;
         const bool act = (int)threadIdx.x < np;
         T q[LMAX];
@@ -376,13 +401,15 @@ k_fw_lmo_flat(FWArgs<T> A) {
     const int t = threadIdx.x;
     const int lp = t / L;
     const int l = t - lp * L;
-    const T al = A.first ? T(0) : T(A.scal[kAlpha]);
+    int lo, hi;
+    const int img = tile_range(A.seg, A.nimg, ppb * kFlatGroups, blockIdx.x, lo, hi);
+    const T al = (A.first || img < 0) ? T(0) : T(A.scal[img]);
     double acc[kP1];
 #pragma unroll
     for (int i = 0; i < kP1; ++i) acc[i] = 0.0;
-    for (int g = blockIdx.x; (long long)g * ppb < A.N; g += gridDim.x) {
-        const long long a = (long long)g * ppb + lp;
-        const bool act = lp < ppb && a < A.N;
+    for (int g0 = lo; g0 < hi; g0 += ppb) {
+        const long long a = (long long)g0 + lp;
+        const bool act = lp < ppb && a < hi;
         const size_t e = (size_t)a * L + l;
         T yv = T(0), pyv = T(0), cv = T(0), gv = T(0);
         int sp = -1;
@@ -444,9 +471,11 @@ k_fw_slice_flat(FWSliceArgs<T> A, LatSet<T> ls) {
     const int lp = t / L;
     const int l = t - lp * L;
     double acc[kP2] = {0.0, 0.0};
-    for (int g = blockIdx.x; (long long)g * ppb < A.N; g += gridDim.x) {
-        const long long a = (long long)g * ppb + lp;
-        const bool act = lp < ppb && a < A.N;
+    int lo, hi;
+    tile_range(A.seg, A.nimg, ppb * kFlatGroups, blockIdx.x, lo, hi);
+    for (int g0 = lo; g0 < hi; g0 += ppb) {
+        const long long a = (long long)g0 + lp;
+        const bool act = lp < ppb && a < hi;
         const size_t e = (size_t)a * L + l;
         int sa = 0;
         if (act) {
@@ -488,18 +517,23 @@ k_fw_slice_flat(FWSliceArgs<T> A, LatSet<T> ls) {
 
 // ------------------------------------------------------------ the rest
 
-// y <- y + alpha (s - y), P_y <- (1 - alpha) P_y + alpha P_s
+// y <- y + alpha (s - y), P_y <- (1 - alpha) P_y + alpha P_s with the step
+// of each image (blockIdx.y)
 template <typename T>
-__global__ void k_fw_final(int N, int L, T *__restrict__ y, T *__restrict__ Py,
-                           const T *__restrict__ Ps, const int32_t *__restrict__ s,
+__global__ void k_fw_final(int L, const int *__restrict__ seg, T *__restrict__ y,
+                           T *__restrict__ Py, const T *__restrict__ Ps,
+                           const int32_t *__restrict__ s,
                            const double *__restrict__ scal) {
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (size_t)N * L) return;
-    const int a = int(e / L);
-    const int l = int(e - (size_t)a * L);
-    const T al = T(scal[kAlpha]);
-    y[e] = y[e] + al * (T(l == s[a] ? 1 : 0) - y[e]);
-    Py[e] = (T(1) - al) * Py[e] + al * Ps[e];
+    const int img = blockIdx.y;
+    const size_t lo = (size_t)seg[2 * img] * L, hi = (size_t)seg[2 * img + 1] * L;
+    const T al = T(scal[img]);
+    for (size_t e = lo + (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < hi;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int a = int(e / L);
+        const int l = int(e - (size_t)a * L);
+        y[e] = y[e] + al * (T(l == s[a] ? 1 : 0) - y[e]);
+        Py[e] = (T(1) - al) * Py[e] + al * Ps[e];
+    }
 }
 
 template <typename T>
@@ -511,10 +545,13 @@ __global__ void k_onehot(int N, int L, const int32_t *__restrict__ s,
     out[e] = T(int(e - (size_t)a * L) == s[a] ? 1 : 0);
 }
 
-__global__ void k_check_labels(int N, int L, const int32_t *__restrict__ x,
+__global__ void k_check_labels(const int *__restrict__ seg, int nimg, int L,
+                               const int32_t *__restrict__ x,
                                int *__restrict__ bad) {
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a < N && (x[a] < 0 || x[a] >= L)) atomicOr(bad, 1);
+    int lo, hi;
+    tile_range(seg, nimg, 256, blockIdx.x, lo, hi);
+    const int a = lo + threadIdx.x;
+    if (a < hi && (x[a] < 0 || x[a] >= L)) atomicOr(bad, 1);
 }
 
 template <typename T>
@@ -538,7 +575,8 @@ __global__ void k_round(int N, int L, const T *__restrict__ y,
 // the sliced one-hot filter, or its K'S in `pre`)
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_energy(int N, int L, const T *__restrict__ phi, const int32_t *__restrict__ x,
+k_energy(const int *__restrict__ seg, int nimg, int L,
+         const T *__restrict__ phi, const int32_t *__restrict__ x,
          const T *__restrict__ pre, LatSet<T> ls, T wsum,
          const T *__restrict__ mu, double *__restrict__ part) {
     __shared__ double red[kThreads];
@@ -547,9 +585,11 @@ k_energy(int N, int L, const T *__restrict__ phi, const int32_t *__restrict__ x,
     const int lp = t / L;
     const int l = t - lp * L;
     double acc[1] = {0.0};
-    for (int g = blockIdx.x; (long long)g * ppb < N; g += gridDim.x) {
-        const long long a = (long long)g * ppb + lp;
-        if (lp < ppb && a < N) {
+    int lo, hi;
+    tile_range(seg, nimg, ppb * kFlatGroups, blockIdx.x, lo, hi);
+    for (int g0 = lo; g0 < hi; g0 += ppb) {
+        const long long a = (long long)g0 + lp;
+        if (lp < ppb && a < hi) {
             const size_t e = (size_t)a * L + l;
             const int xa = x[a];
             if (xa < 0 || xa >= L) continue;   // rejected by k_check_labels
@@ -580,13 +620,16 @@ k_energy(int N, int L, const T *__restrict__ phi, const int32_t *__restrict__ x,
 // per-block partial sums of S(y) = phi^T y + y^T Psi y with Psi y = P_y - d*y
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_S_value(int N, int L, const T *__restrict__ phi, const T *__restrict__ y,
+k_S_value(const int *__restrict__ seg, int nimg, int L,
+          const T *__restrict__ phi, const T *__restrict__ y,
           const T *__restrict__ Py, const T *__restrict__ mabs,
           const T *__restrict__ r, double *__restrict__ part) {
     __shared__ double red[kThreads];
     double acc[1] = {0.0};
-    for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < (size_t)N * L;
-         e += (size_t)gridDim.x * kThreads) {
+    int lo, hi;
+    tile_range(seg, nimg, kThreads, blockIdx.x, lo, hi);
+    for (size_t e = (size_t)lo * L + threadIdx.x; e < (size_t)hi * L;
+         e += kThreads) {
         const int a = int(e / L);
         const int i = int(e - (size_t)a * L);
         const double yv = y[e];
@@ -602,11 +645,6 @@ int grid_flat(int N, int L) {
     return std::max(1, std::min(kMaxGrid, ceil_div(N, ppb)));
 }
 
-template <typename T>
-int grid_rows(int N) {
-    return std::max(1, std::min(kMaxGrid, ceil_div(N, RowTile<T>::kPix)));
-}
-
 double sum_partials(dcrf_ctx *ctx, const double *dpart, int n) {
     std::vector<double> h(n);
     DCRF_TRY_HIP(hipMemcpyAsync(h.data(), dpart, n * sizeof(double),
@@ -617,27 +655,47 @@ double sum_partials(dcrf_ctx *ctx, const double *dpart, int n) {
     return s;
 }
 
+// Tiles (pixels per block) of the two per-pixel Frank-Wolfe kernels: the row
+// kernels for L <= 32, the flat kernels above.
+template <typename T>
+int lmo_tile(int L) {
+    return L <= kRowMaxC ? LmoTile<T>::kPix : (kThreads / L) * kFlatGroups;
+}
+template <typename T>
+int slice_tile(int L) {
+    return L <= kRowMaxC ? RowTile<T>::kPix : (kThreads / L) * kFlatGroups;
+}
+int flat_tile(int L) { return (kThreads / L) * kFlatGroups; }
+
 template <typename T>
 struct Work {
     T *c, *Py, *Ps, *mabs;
     int32_t *s, *sprev;
     double *part1, *part2, *scal, *trace;
+    int G1, G2;   // blocks (tiles) of k_fw_lmo and k_fw_slice
 };
 
 template <typename T>
 Work<T> fw_workspace(dcrf_ctx *ctx, int L, int iters) {
     const hipStream_t st = ctx->stream;
     const size_t NL = (size_t)ctx->N * L;
+    const int G1 = seg_tiles(ctx, lmo_tile<T>(L));
+    const int G2 = seg_tiles(ctx, slice_tile<T>(L));
+    // the partial sums of k_fw_lmo and k_fw_slice; also those of k_S_value
+    const size_t np = std::max<size_t>((size_t)G1 * kP1 + (size_t)G2 * kP2,
+                                       (size_t)seg_tiles(ctx, kThreads));
     ctx->fw_c.ensure(NL * sizeof(T), st);
     ctx->fw_Py.ensure(NL * sizeof(T), st);
     ctx->fw_Ps.ensure(NL * sizeof(T), st);
     ctx->fw_s.ensure((size_t)ctx->N * 4, st);
     ctx->fw_sprev.ensure((size_t)ctx->N * 4, st);
-    ctx->fw_part.ensure((size_t)kMaxGrid * (kP1 + kP2) * 8, st);
-    ctx->fw_scal.ensure(64, st);
-    ctx->fw_trace.ensure((size_t)std::max(iters, 1) * 4 * 8, st);
+    ctx->fw_part.ensure(np * 8, st);
+    ctx->fw_scal.ensure((size_t)ctx->nimg * 8, st);
+    ctx->fw_trace.ensure((size_t)std::max(iters, 1) * ctx->nimg * 4 * 8, st);
     ctx->fw_mu.ensure((size_t)L * sizeof(T), st);
     Work<T> w;
+    w.G1 = G1;
+    w.G2 = G2;
     w.c = ctx->fw_c.as<T>();
     w.Py = ctx->fw_Py.as<T>();
     w.Ps = ctx->fw_Ps.as<T>();
@@ -645,7 +703,7 @@ Work<T> fw_workspace(dcrf_ctx *ctx, int L, int iters) {
     w.s = ctx->fw_s.as<int32_t>();
     w.sprev = ctx->fw_sprev.as<int32_t>();
     w.part1 = ctx->fw_part.as<double>();
-    w.part2 = w.part1 + (size_t)kMaxGrid * kP1;
+    w.part2 = w.part1 + (size_t)G1 * kP1;
     w.scal = ctx->fw_scal.as<double>();
     w.trace = ctx->fw_trace.as<double>();
     return w;
@@ -707,7 +765,7 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
     if (!have_Py) qp_apply_t<T>(ctx, y, mu, L, w.mabs, w.Py);
     hipLaunchKernelGGL(k_fill_i32, dim3(ceil_div(N, 256)), dim3(256), 0, st,
                        w.sprev, (size_t)N, -1);
-    DCRF_TRY_HIP(hipMemsetAsync(w.scal, 0, 64, st));
+    DCRF_TRY_HIP(hipMemsetAsync(w.scal, 0, (size_t)ctx->nimg * 8, st));
     DCRF_CHECK_LAUNCH();
 
     const bool exact = ctx->mode == DCRF_FILTER_EXACT;
@@ -717,22 +775,23 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
         ctx->tmpA.ensure(NL * sizeof(T), st);
         ctx->tmpB.ensure(NL * sizeof(T), st);
     }
-    // grids of the per-pixel kernels (k_fw_lmo: G1 blocks, k_fw_slice: G2)
-    constexpr int TP1 = LmoTile<T>::kPix;
-    constexpr int TP = RowTile<T>::kPix;
-    const int G1 = rows ? std::max(1, std::min(kMaxGrid, ceil_div(N, TP1)))
-                        : grid_flat(N, L);
-    const int G = rows ? grid_rows<T>(N) : grid_flat(N, L);
+    // one block per tile of an image (k_fw_lmo: G1 tiles of TP1 pixels,
+    // k_fw_slice: G tiles of TP pixels)
+    const int TP1 = lmo_tile<T>(L), TP = slice_tile<T>(L);
+    const int G1 = w.G1, G = w.G2;
+    const int nimg = ctx->nimg;
+    const int *seg = ctx->seg.as<int>();
     const bool potts = is_potts<T>(ctx, mu, L);
     const LatSet<T> ls = exact ? LatSet<T>{} : make_lat_set<T>(ctx, L);
     for (int it = 0; it < iters; ++it) {
         FWArgs<T> a{N, L, y, w.Py, w.Ps, w.c, w.s, w.sprev, w.scal, w.part1,
-                    it == 0 ? 1 : 0};
+                    it == 0 ? 1 : 0, seg, nimg};
         {
             ProfScope ps(ctx, PROF_FW_LMO);
             if (rows) {
                 DCRF_DISPATCH_ROWS(L, hipLaunchKernelGGL((k_fw_lmo_rows<T, LMAX>),
-                                                         dim3(G1), dim3(TP1), 0, st, a));
+                                                         dim3(G1), dim3(LmoTile<T>::kPix),
+                                                         0, st, a));
             } else {
                 hipLaunchKernelGGL((k_fw_lmo_flat<T>), dim3(G1), dim3(kThreads), 0,
                                    st, a);
@@ -755,18 +814,19 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
             blur_all(ctx, L, false);
         }
         FWSliceArgs<T> b{N, L, y, w.s, w.Ps, mu, w.mabs, ctx->r.as<T>(), pre,
-                         T(ctx->wsum), w.scal, w.part1, w.part2, G1, w.trace, it};
+                         T(ctx->wsum), w.scal, w.part1, w.part2, G1, w.trace, it,
+                         seg, nimg};
         {
             ProfScope ps(ctx, PROF_FW_SLICE);
             if (rows) {
                 if (potts)
                     DCRF_DISPATCH_ROWS(L, hipLaunchKernelGGL(
-                        (k_fw_slice_rows<T, LMAX, true>), dim3(G), dim3(TP), 0, st,
-                        b, ls));
+                        (k_fw_slice_rows<T, LMAX, true>), dim3(G),
+                        dim3(RowTile<T>::kPix), 0, st, b, ls));
                 else
                     DCRF_DISPATCH_ROWS(L, hipLaunchKernelGGL(
-                        (k_fw_slice_rows<T, LMAX, false>), dim3(G), dim3(TP), 0,
-                        st, b, ls));
+                        (k_fw_slice_rows<T, LMAX, false>), dim3(G),
+                        dim3(RowTile<T>::kPix), 0, st, b, ls));
             } else {
                 hipLaunchKernelGGL((k_fw_slice_flat<T>), dim3(G), dim3(kThreads),
                                    0, st, b, ls);
@@ -774,25 +834,30 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
         }
         {
             ProfScope ps(ctx, PROF_FW_ALPHA);
-            hipLaunchKernelGGL((k_fw_alpha<512>), dim3(1), dim3(512), 0,
-                               st, w.part1, G1, w.part2, G, w.scal, w.trace, it,
-                               save ? save->stats : nullptr);
+            hipLaunchKernelGGL((k_fw_alpha<512>), dim3(nimg), dim3(512), 0,
+                               st, w.part1, w.part2, seg, nimg, TP1, TP, w.scal,
+                               w.trace, it, save ? save->stats : nullptr);
         }
         DCRF_CHECK_LAUNCH();
         std::swap(w.s, w.sprev);
     }
     // the last conditional gradient is in sprev after the swap
     if (iters > 0) {
-        hipLaunchKernelGGL((k_fw_final<T>), dim3(gE), dim3(256), 0, st, N, L, y,
-                           w.Py, w.Ps, w.sprev, w.scal);
+        int maxn = 1;
+        for (int j = 0; j < nimg; ++j)
+            maxn = std::max(maxn, ctx->seg_h[2 * j + 1] - ctx->seg_h[2 * j]);
+        const int gx = std::min(4096, ceil_div((long long)maxn * L, 256));
+        hipLaunchKernelGGL((k_fw_final<T>), dim3(gx, nimg), dim3(256), 0, st, L,
+                           seg, y, w.Py, w.Ps, w.sprev, w.scal);
         DCRF_CHECK_LAUNCH();
     }
-    if (trace && iters > 0) {
-        std::vector<double> h((size_t)iters * 4);
+    if (trace && iters > 0) {   // record it * nimg + image
+        const size_t nrec = (size_t)iters * nimg;
+        std::vector<double> h(nrec * 4);
         DCRF_TRY_HIP(hipMemcpyAsync(h.data(), w.trace, h.size() * 8,
                                     hipMemcpyDeviceToHost, st));
         DCRF_TRY_HIP(hipStreamSynchronize(st));
-        for (int i = 0; i < iters; ++i)
+        for (size_t i = 0; i < nrec; ++i)
             trace[i] = dcrf_iter_trace{h[i * 4 + 0], h[i * 4 + 1], h[i * 4 + 2],
                                        h[i * 4 + 3]};
     }
@@ -800,10 +865,10 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
 
 template <typename T>
 double S_value_t(dcrf_ctx *ctx, const T *phi, const T *y, int L) {
-    const int G = std::min(kMaxGrid, ceil_div((long long)ctx->N * L, kThreads));
+    const int G = seg_tiles(ctx, kThreads);
     hipLaunchKernelGGL((k_S_value<T>), dim3(G), dim3(kThreads), 0, ctx->stream,
-                       ctx->N, L, phi, y, ctx->fw_Py.as<T>(), ctx->fw_mu.as<T>(),
-                       ctx->r.as<T>(), ctx->fw_part.as<double>());
+                       ctx->seg.as<int>(), ctx->nimg, L, phi, y, ctx->fw_Py.as<T>(),
+                       ctx->fw_mu.as<T>(), ctx->r.as<T>(), ctx->fw_part.as<double>());
     DCRF_CHECK_LAUNCH();
     return sum_partials(ctx, ctx->fw_part.as<double>(), G);
 }
@@ -832,8 +897,8 @@ double energy_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L,
         ctx->scratch.ensure(64, st);
         int *bad = ctx->scratch.as<int>() + 1;
         DCRF_TRY_HIP(hipMemsetAsync(bad, 0, 4, st));
-        hipLaunchKernelGGL(k_check_labels, dim3(ceil_div(N, 256)), dim3(256), 0,
-                           st, N, L, x, bad);
+        hipLaunchKernelGGL(k_check_labels, dim3(seg_tiles(ctx, 256)), dim3(256), 0,
+                           st, ctx->seg.as<int>(), ctx->nimg, L, x, bad);
         int hbad = 0;
         DCRF_TRY_HIP(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, st));
         DCRF_TRY_HIP(hipStreamSynchronize(st));
@@ -853,10 +918,11 @@ double energy_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L,
         blur_all(ctx, L, false);
         ls = make_lat_set<T>(ctx, L);
     }
-    ctx->fw_part.ensure((size_t)kMaxGrid * (kP1 + kP2) * 8, st);
-    const int G = grid_flat(N, L);
-    hipLaunchKernelGGL((k_energy<T>), dim3(G), dim3(kThreads), 0, st, N, L, phi,
-                       x, pre, ls, T(ctx->wsum), mu, ctx->fw_part.as<double>());
+    const int G = seg_tiles(ctx, flat_tile(L));
+    ctx->fw_part.ensure((size_t)G * 8, st);
+    hipLaunchKernelGGL((k_energy<T>), dim3(G), dim3(kThreads), 0, st,
+                       ctx->seg.as<int>(), ctx->nimg, L, phi, x, pre, ls,
+                       T(ctx->wsum), mu, ctx->fw_part.as<double>());
     DCRF_CHECK_LAUNCH();
     return sum_partials(ctx, ctx->fw_part.as<double>(), G);
 }

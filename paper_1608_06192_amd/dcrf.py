@@ -41,6 +41,12 @@ class dcrf_iter_trace(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("changed", ctypes.c_double)]
 
 
+class dcrf_tune(ctypes.Structure):
+    _fields_ = [("splat_chunk", ctypes.c_int),
+                ("blur_vectors_per_thread", ctypes.c_int),
+                ("blur_block", ctypes.c_int), ("ms", ctypes.c_double)]
+
+
 # name -> (restype, argtypes); mirrors include/dcrf.h
 _P, _I, _U, _D = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint, ctypes.c_double
 _PD = ctypes.POINTER(ctypes.c_double)
@@ -51,6 +57,12 @@ PROTOTYPES = {
     "dcrf_set_stream": (_I, [_P, _P]),
     "dcrf_version": (ctypes.c_char_p, []),
     "dcrf_set_image": (_I, [_P, _I, _I, _P, ctypes.POINTER(dcrf_kernel), _I, _I]),
+    "dcrf_set_images": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
+                             ctypes.POINTER(_P), ctypes.POINTER(dcrf_kernel), _I,
+                             _I]),
+    "dcrf_image_layout": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I),
+                               ctypes.POINTER(_I)]),
+    "dcrf_autotune": (_I, [_P, _I, _I, ctypes.POINTER(dcrf_tune)]),
     "dcrf_set_weights": (_I, [_P, _PD, _I]),
     "dcrf_set_filter_mode": (_I, [_P, _I]),
     "dcrf_lattice_info": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
@@ -118,6 +130,7 @@ class Context:
         self.dtype = None
         self.N = 0
         self.nk = 0
+        self.nimg, self.seg = 1, []
 
     def __del__(self):
         if getattr(self, "_h", None) and self._h.value:
@@ -150,6 +163,50 @@ class Context:
             self._h, H, W, self._arg(rgb, torch.float32, "rgb"), ks, len(ks),
             code))
         self.dtype, self.N, self.nk, self.H, self.W = dtype, H * W, len(ks), H, W
+        self.nimg, self.seg = 1, [(0, H * W)]
+
+    def set_images(self, sizes, rgbs, kernels, dtype=torch.float32):
+        """A batch: sizes = [(H, W), ...], rgbs = float32 (H*W, 3) tensors on
+        the device. Afterwards every N x C argument is one packed array in
+        the layout of `seg` (rows seg[j][0]:seg[j][1] are image j)."""
+        B = len(sizes)
+        self._stream()
+        code = {torch.float32: DCRF_F32, torch.float64: DCRF_F64}[dtype]
+        ks = _kernels(kernels)
+        Hs = (ctypes.c_int * B)(*[int(h) for h, _ in sizes])
+        Ws = (ctypes.c_int * B)(*[int(w) for _, w in sizes])
+        ptrs = (ctypes.c_void_p * B)(*[self._arg(r, torch.float32, "rgb").value
+                                      for r in rgbs])
+        self._check(_lib.dcrf_set_images(self._h, B, Hs, Ws, ptrs, ks, len(ks),
+                                         code))
+        self.dtype, self.nk = dtype, len(ks)
+        self.H = self.W = None
+        nimg, rows = ctypes.c_int(), ctypes.c_int()
+        seg = (ctypes.c_int * (2 * B))()
+        self._check(_lib.dcrf_image_layout(self._h, ctypes.byref(nimg),
+                                           ctypes.byref(rows), seg))
+        self.nimg, self.N = nimg.value, rows.value
+        self.seg = [(seg[2 * j], seg[2 * j + 1]) for j in range(self.nimg)]
+
+    def pack(self, arrays, C: int):
+        """Per-image (N_j x C) tensors -> one packed (N x C) tensor; the rows
+        between images are zero."""
+        out = torch.zeros(self.N, C, dtype=self.dtype, device=self.device)
+        for (a, b), x in zip(self.seg, arrays):
+            out[a:b].copy_(x.reshape(b - a, C))
+        return out
+
+    def unpack(self, packed):
+        """One packed (N x C) tensor -> per-image views."""
+        return [packed[a:b] for a, b in self.seg]
+
+    def autotune(self, L: int, reps: int = 5):
+        t = dcrf_tune()
+        self._stream()
+        self._check(_lib.dcrf_autotune(self._h, L, reps, ctypes.byref(t)))
+        return dict(splat_chunk=t.splat_chunk,
+                    blur_vectors_per_thread=t.blur_vectors_per_thread,
+                    blur_block=t.blur_block, ms=t.ms)
 
     def set_weights(self, w):
         arr = (ctypes.c_double * len(w))(*[float(v) for v in w])
@@ -200,14 +257,18 @@ class Context:
 
     # -- solvers ---------------------------------------------------------
     def qp_frank_wolfe(self, unary, mu, y, iters: int, trace: bool = True):
-        tr = (dcrf_iter_trace * max(iters, 1))() if trace else None
+        tr = (dcrf_iter_trace * max(iters * self.nimg, 1))() if trace else None
         self._stream()
         self._check(_lib.dcrf_qp_frank_wolfe(
             self._h, self._arg(unary, name="unary"), self._arg(mu, name="mu"),
             unary.shape[1], self._arg(y, name="y"), iters, tr))
         if not trace:
             return None
-        return [(t.objective, t.gap, t.alpha, t.changed) for t in tr[:iters]]
+        rec = [(t.objective, t.gap, t.alpha, t.changed)
+               for t in tr[:iters * self.nimg]]
+        if self.nimg == 1:
+            return rec
+        return [rec[j::self.nimg] for j in range(self.nimg)]
 
     def dc_gen(self, unary, mu, y, outer: int, inner: int):
         hist = (ctypes.c_double * (outer + 1))()
@@ -276,15 +337,19 @@ class Context:
         return y, saved
 
     def fw_backward(self, unary, mu, iters: int, saved, grad_y):
-        """(dl/dunary, dl/dw as a list of nk floats) for dl/dy_T = grad_y."""
+        """(dl/dunary, dl/dw) for dl/dy_T = grad_y; dl/dw is a list of nk
+        floats, or for a batch a list of nimg such lists."""
         gphi = torch.empty_like(unary)
-        gw = (ctypes.c_double * self.nk)()
+        gw = (ctypes.c_double * (self.nk * self.nimg))()
         self._stream()
         self._check(_lib.dcrf_fw_backward(
             self._h, self._arg(unary, name="unary"), self._arg(mu, name="mu"),
             unary.shape[1], iters, _ptr(saved), self._arg(grad_y, name="grad_y"),
             self._arg(gphi), gw))
-        return gphi, list(gw)
+        if self.nimg == 1:
+            return gphi, list(gw)
+        return gphi, [list(gw[j * self.nk:(j + 1) * self.nk])
+                      for j in range(self.nimg)]
 
     # -- profiling -------------------------------------------------------
     def set_profiling(self, on: bool):
