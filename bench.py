@@ -17,7 +17,15 @@ Beside it the JSON line reports:
   over its average launch time (HIP events on the library's stream), against
   the 8 TB/s HBM peak;
 * cpu_baseline: the FP64 oracle's Frank-Wolfe iterations on the host, one
-  thread, over a bounded sample of iterations of the same workload.
+  thread, over a bounded sample of iterations of the same workload;
+* diff: 10 unrolled Frank-Wolfe iterations at 500x375, L=21, FP32 (seed 3):
+  forward with checkpoints, reverse sweep, and the plain forward beside them;
+* batch: 16 Voronoi images of sizes U{240..500}^2, L=21, FP32, 10 Frank-
+  Wolfe iterations each: the batched forward and forward+backward (one launch
+  per stage over the concatenated lattices, autotuned launch shapes) against
+  16 sequential single-image forwards and forward+backwards;
+* lattice_error: the lattice filter against the exact O(N^2) sum at 320x213
+  (ratio of means, cosine and relative 2-norm error of K'Y for a random Y).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -99,6 +107,149 @@ def cpu_baseline(im, kernels, mu, iters):
                        f"500x375 L=21 image, {dt:.1f} s")
 
 
+def _timed(torch, fn, reps=1):
+    """milliseconds per call of fn on the current stream (HIP events)"""
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def extensions(torch, dcrf, synth, dev, kernels):
+    f32, f64 = torch.float32, torch.float64
+    out = {}
+
+    # -- differentiation: 10 unrolled iterations at 500x375 ------------------
+    im = synth.make("voronoi_500x375_L21_diff")
+    iters = synth.WORKLOADS["voronoi_500x375_L21_diff"]["iters"]
+    ctx = dcrf.Context(0)
+    ctx.set_image(im.H, im.W, torch.from_numpy(im.rgb).to(dev), kernels, dtype=f32)
+    phi = torch.from_numpy(im.unary).to(dev, f32)
+    mu = torch.from_numpy(synth.potts(im.L)).to(dev, f32)
+    gt = torch.from_numpy(im.gt.astype(np.int64)).to(dev)
+    holder = {}
+
+    def fwd():
+        holder["y"], holder["saved"] = ctx.fw_forward(phi, mu, iters)
+
+    def bwd():
+        y = holder["y"]
+        idx = torch.arange(im.N, device=dev)
+        g = torch.zeros_like(y)
+        g[idx, gt] = -1.0 / (im.N * y[idx, gt].clamp_min(1e-12))
+        ctx.fw_backward(phi, mu, iters, holder["saved"], g)
+
+    holder_y0 = torch.softmax(-phi, dim=1)   # start point, set up once
+
+    def plain():
+        y = holder_y0.clone()
+        ctx.qp_frank_wolfe(phi, mu, y, iters, trace=False)
+
+    t_f = _timed(torch, fwd, 5)
+    t_b = _timed(torch, bwd, 3)
+    t_p = _timed(torch, plain, 5)
+    out["diff"] = dict(workload="voronoi 500x375 L=21 FP32, 10 unrolled FW "
+                                "iterations, cross-entropy to the region labels",
+                       forward_ms=t_f, backward_ms=t_b, fwd_bwd_ms=t_f + t_b,
+                       plain_forward_ms=t_p,
+                       fwd_bwd_over_plain=(t_f + t_b) / t_p,
+                       checkpoint_MB=ctx.fw_saved_size(im.L, iters) / 1e6)
+    log(f"[bench] diff: forward {t_f:.2f} ms, backward {t_b:.2f} ms, "
+        f"plain forward {t_p:.2f} ms")
+    del ctx, holder
+
+    # -- batch: 16 uneven images -------------------------------------------
+    ims = synth.make_batch()
+    iters = synth.WORKLOADS["voronoi_batch16_L21"]["iters"]
+    L = ims[0].L
+    mu = torch.from_numpy(synth.potts(L)).to(dev, f32)
+    bctx = dcrf.Context(0)
+    bctx.set_images([(x.H, x.W) for x in ims],
+                    [torch.from_numpy(x.rgb).to(dev) for x in ims], kernels,
+                    dtype=f32)
+    tune = bctx.autotune(L, reps=3)
+    bphi = bctx.pack([torch.from_numpy(x.unary).to(dev, f32) for x in ims], L)
+    bgt = bctx.pack([torch.from_numpy(x.gt.astype(np.float32)).to(dev, f32)[:, None]
+                     for x in ims], 1)[:, 0].long()
+    segs = bctx.seg
+    w_img = torch.zeros(bctx.N, device=dev, dtype=f32)
+    for a, b in segs:
+        w_img[a:b] = 1.0 / (b - a)
+    bh = {}
+
+    def bfwd():
+        bh["y"], bh["saved"] = bctx.fw_forward(bphi, mu, iters)
+
+    def bfwdbwd():
+        bfwd()
+        y = bh["y"]
+        idx = torch.arange(bctx.N, device=dev)
+        g = torch.zeros_like(y)
+        g[idx, bgt] = -w_img / y[idx, bgt].clamp_min(1e-12)
+        bctx.fw_backward(bphi, mu, iters, bh["saved"], g)
+
+    sctx = []
+    for x in ims:
+        c = dcrf.Context(0)
+        c.set_image(x.H, x.W, torch.from_numpy(x.rgb).to(dev), kernels, dtype=f32)
+        sctx.append((c, torch.from_numpy(x.unary).to(dev, f32),
+                     torch.from_numpy(x.gt.astype(np.int64)).to(dev), x.N))
+
+    def seq_fwd():
+        for c, p, _, _ in sctx:
+            bh[id(c)] = c.fw_forward(p, mu, iters)
+
+    def seq_fwdbwd():
+        for c, p, g_t, n in sctx:
+            y, saved = c.fw_forward(p, mu, iters)
+            idx = torch.arange(n, device=dev)
+            g = torch.zeros_like(y)
+            g[idx, g_t] = -1.0 / (n * y[idx, g_t].clamp_min(1e-12))
+            c.fw_backward(p, mu, iters, saved, g)
+
+    t_bf = _timed(torch, bfwd, 3)
+    t_bfb = _timed(torch, bfwdbwd, 2)
+    t_sf = _timed(torch, seq_fwd, 2)
+    t_sfb = _timed(torch, seq_fwdbwd, 1)
+    npx = sum(x.N for x in ims)
+    out["batch"] = dict(workload="16 Voronoi images, H and W ~ U{240..500}, "
+                                 "L=21, FP32, 10 FW iterations each",
+                        pixels=npx, autotune=tune,
+                        batched_forward_ms=t_bf, batched_fwd_bwd_ms=t_bfb,
+                        sequential_plain_forward_ms=t_sf,
+                        sequential_fwd_bwd_ms=t_sfb,
+                        batched_fwd_bwd_over_sequential_forward=t_bfb / t_sf,
+                        forward_speedup=t_sf / t_bf,
+                        fwd_bwd_speedup=t_sfb / t_bfb)
+    log(f"[bench] batch of 16 ({npx} px): batched fwd {t_bf:.2f} ms, fwd+bwd "
+        f"{t_bfb:.2f} ms; sequential fwd {t_sf:.2f} ms, fwd+bwd {t_sfb:.2f} ms; "
+        f"tune {tune}")
+    del bctx, sctx, bh
+
+    # -- lattice against the exact sum at 320x213 ----------------------------
+    im = synth.make("voronoi_320x213_L21")
+    ctx = dcrf.Context(0)
+    ctx.set_image(im.H, im.W, torch.from_numpy(im.rgb).to(dev), kernels, dtype=f64)
+    g = torch.Generator(device="cpu").manual_seed(7)
+    Y = torch.rand(im.N, 4, generator=g, dtype=f64).to(dev)
+    lat = ctx.filter(Y)
+    exact = ctx.filter(Y, exact=True)
+    num = float((lat * exact).sum())
+    cos = num / float(lat.norm() * exact.norm())
+    out["lattice_error"] = dict(
+        workload="voronoi 320x213, both kernels, K'Y for Y ~ U[0,1]^(N x 4), FP64",
+        ratio_of_means=float(lat.mean() / exact.mean()), cosine=cos,
+        rel_l2_error=float((lat - exact).norm() / exact.norm()))
+    log(f"[bench] lattice vs exact: {out['lattice_error']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +260,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--lp-steps", type=int, default=3)
     ap.add_argument("--lp-beta0", type=float, default=1e-4)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 256 MiB copy kernel (reference for "
+                         "the HBM byte counters of a profiler run)")
+    ap.add_argument("--no-ext", action="store_true",
+                    help="skip the diff, batch and lattice-error measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -197,6 +353,15 @@ def main():
         log(f"[bench] LP subgradient step (divide and conquer, 21 labels, "
             f"{int(np.ceil(np.log2(N)))} levels): {lp_ms:.1f} ms")
 
+    ext = {} if args.no_ext else extensions(torch, dcrf, synth, dev, kernels)
+    if args.calib_copy:
+        a = torch.ones(64 << 20, device=dev, dtype=f32)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            torch.mul(a, 1.0, out=b)   # reads 256 MiB, writes 256 MiB
+        torch.cuda.synchronize()
+        del a, b
+
     # ---- roofline of the dominant kernel of the step ----------------------
     dom = max(per_iter, key=lambda k: per_iter[k][0] * per_iter[k][1])
     dom_ms = per_iter[dom][0]
@@ -224,7 +389,7 @@ def main():
                            lattice_vertices=[M for d, M in lat]),
                lattice_filter=filt, step_bytes=fw_step_bytes(N, L, 4, lat),
                per_kernel_us={k: v[0] * 1e3 for k, v in per_iter.items()},
-               lp=lp, roofline=roofline)
+               lp=lp, roofline=roofline, **ext)
     if not args.no_cpu:
         log(f"[bench] CPU baseline: {args.cpu_iters} oracle FW iterations ...")
         res["cpu_baseline"] = cpu_baseline(im, kernels, mu_np, args.cpu_iters)
