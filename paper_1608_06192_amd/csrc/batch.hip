@@ -12,9 +12,9 @@
 // images have no vertices and are not solver variables.
 //
 // The launch shapes that have a choice (inverse-index chunk length of the
-// splats, 16-byte vectors per thread and threads per block of the blur) are
-// picked by a small autotuner that times the filter paths of the context's
-// own lattices for each candidate.
+// splats; blur directions per launch, 16-byte vectors per thread and threads
+// per block of the blur) are picked by a small autotuner that times the
+// filter paths of the context's own lattices for each candidate.
 
 #include <algorithm>
 #include <vector>
@@ -243,12 +243,13 @@ void autotune(dcrf_ctx *ctx, int L, int reps, double *best_ms) {
     hipEvent_t e0, e1;
     DCRF_TRY_HIP(hipEventCreate(&e0));
     DCRF_TRY_HIP(hipEventCreate(&e1));
-    struct Cand { int chunk, vpt, block; };
+    struct Cand { int chunk, vpt, block, group; };
     std::vector<Cand> cands;
     for (int chunk : {32, 64, 128})
-        for (int vpt : {1, 2, 4})
-            for (int block : {128, 256}) cands.push_back({chunk, vpt, block});
-    Cand best = {ctx->splat_chunk, ctx->blur_vpt, ctx->blur_block};
+        for (int vpt : {1, 2})
+            for (int block : {128, 256})
+                for (int group : {1, 2, 3}) cands.push_back({chunk, vpt, block, group});
+    Cand best = {ctx->splat_chunk, ctx->blur_vpt, ctx->blur_block, ctx->blur_group};
     double best_t = 1e300;
     auto run = [&] {
         // the dense filter and the one-hot path of a Frank-Wolfe iteration
@@ -263,6 +264,7 @@ void autotune(dcrf_ctx *ctx, int L, int reps, double *best_ms) {
             if (c.chunk != ctx->splat_chunk) rechunk(ctx, c.chunk);
             ctx->blur_vpt = c.vpt;
             ctx->blur_block = c.block;
+            ctx->blur_group = c.group;
             run();
             DCRF_TRY_HIP(hipEventRecord(e0, s));
             for (int r = 0; r < reps; ++r) run();
@@ -288,6 +290,7 @@ void autotune(dcrf_ctx *ctx, int L, int reps, double *best_ms) {
     if (best.chunk != ctx->splat_chunk) rechunk(ctx, best.chunk);
     ctx->blur_vpt = best.vpt;
     ctx->blur_block = best.block;
+    ctx->blur_group = best.group;
     if (best_ms) *best_ms = best_t;
 }
 

@@ -88,15 +88,22 @@ struct Lattice {
     DevBuf ent_w;        // N (d+1) x T weight of each entry
     DevBuf ent_v;        // N (d+1) i32 vertex of each entry
     int nent = 0;        // number of entries (pixel vertices with weight > 0)
-    DevBuf chunk_off;    // M + 1 i32 first chunk of each vertex
-    DevBuf chunks;       // nchunks x int4 (vertex, begin, end, 0)
+    DevBuf chunk_off;    // M + 1 i32 chunk counts scanned (build only)
+    DevBuf chunks;       // nchunks x int4 (vertex, begin, end, 0), ordered by first pixel
     int nchunks = 0;
     int chunk = 32;
+    // grouped blur: for blur directions taken G at a time, per group and
+    // vertex the 3^G vertices reached by the paths of the group (-1 where a
+    // path leaves the lattice); [0] forward order, [1] the transpose's order
+    DevBuf gtab[2];
+    int gtab_G[2] = {0, 0};
     void release() {
         for (DevBuf *b : {&hkeys, &slot_vid, &pix_slot, &pix_vid, &pix_w,
                           &vkeys, &nbr, &V[0], &V[1], &V[2], &feat, &csr_off,
-                          &csr_tmp, &ent_pix, &ent_w, &ent_v, &chunk_off, &chunks})
+                          &csr_tmp, &ent_pix, &ent_w, &ent_v, &chunk_off, &chunks,
+                          &gtab[0], &gtab[1]})
             b->release();
+        gtab_G[0] = gtab_G[1] = 0;
     }
 };
 
@@ -178,6 +185,7 @@ struct dcrf_ctx {
     // launch-shape parameters chosen by dcrf_autotune
     int blur_vpt = 1;        // 16-byte vectors per thread in the blur
     int blur_block = 256;    // threads per block in the blur
+    int blur_group = 2;      // blur directions applied per launch (1..3)
     int mode = DCRF_FILTER_LATTICE;
     bool has_image = false;
     dcrf_kernel kern[DCRF_MAXK];
@@ -225,8 +233,14 @@ void blur_all(dcrf_ctx *ctx, int C, bool adjoint);
 // (qp = true); `pre` replaces the lattice by a given K'Y (exact mode)
 void slice_into(dcrf_ctx *ctx, const void *Y, const void *pre, int C,
                 const void *mu, const void *mabs, void *out, bool qp);
-// index of the buffer that holds the blurred values of lattice m
-inline int final_buffer(int d) { return (d % 2 == 0) ? 1 : 2; }
+// index of the buffer that holds the blurred values of a lattice whose blur
+// took n launches (the first reads V[0] and writes V[1], then V[1] and V[2]
+// alternate)
+inline int final_buffer_after(int n) { return (n % 2 == 1) ? 1 : 2; }
+// launches of the blur of a d-dimensional lattice, G directions per launch
+inline int blur_launches(int d, int G) { return (d + 1 + G - 1) / G; }
+// one pass per launch
+inline int final_buffer(int d) { return final_buffer_after(d + 1); }
 
 // solvers.hip
 void qp_apply(dcrf_ctx *ctx, const void *y, const void *mu, int L, void *out);

@@ -38,7 +38,8 @@ namespace {
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_splat_gather(int C, const T *__restrict__ Y, LatSet<T> ls) {
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long e =
+        (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (e >= ls.coff[ls.nk]) return;
     int m = 0;
     while (m + 1 < ls.nk && e >= ls.coff[m + 1]) ++m;
@@ -72,7 +73,7 @@ k_splat_labels_chunks(int C, const int32_t *__restrict__ labels, LatSet<T> ls) {
     __shared__ T bins[4][kLabelBins];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const long long chg = (long long)blockIdx.x * 4 + wave;
+    const long long chg = (long long)xcd_block(blockIdx.x, gridDim.x) * 4 + wave;
     T *b = bins[wave];
     for (int l = lane; l < C; l += 64) b[l] = T(0);
     __syncthreads();
@@ -118,9 +119,14 @@ __device__ __forceinline__ void blur_vector(const LatSet<T> &ls, int pass,
     int m = 0;
     while (m + 1 < ls.nk && e >= ls.off[m + 1] / vw) ++m;
     const LatView<T> &L = ls.l[m];
-    if (pass > L.d) return;
     const unsigned G = unsigned(L.ld / vw);
     const unsigned r = unsigned(e - ls.off[m] / vw);
+    V zero;
+    for (int i = 0; i < vw; ++i) reinterpret_cast<T *>(&zero)[i] = T(0);
+    if (pass > L.d) {
+        if (pass == 1) reinterpret_cast<V *>(L.V0)[r] = zero;
+        return;
+    }
     const int v = int(r / G);
     const int g = int(r - unsigned(v) * G);
     const int j = reverse ? (L.d - pass) : pass;
@@ -128,8 +134,6 @@ __device__ __forceinline__ void blur_vector(const LatSet<T> &ls, int pass,
     V *dst = reinterpret_cast<V *>((pass & 1) ? L.V2 : L.V1);
     const int np = L.nbr[((size_t)j * L.M + v) * 2 + 0];
     const int nm = L.nbr[((size_t)j * L.M + v) * 2 + 1];
-    V zero;
-    for (int i = 0; i < vw; ++i) reinterpret_cast<T *>(&zero)[i] = T(0);
     const V vp = np >= 0 ? src[(size_t)np * G + g] : zero;
     const V vm = nm >= 0 ? src[(size_t)nm * G + g] : zero;
     dst[r] = blur3(src[r], vp, vm);
@@ -145,6 +149,127 @@ k_blur_pass(LatSet<T> ls, int pass, int reverse, long long total, int vpt) {
         if (e >= total) return;
         blur_vector<T>(ls, pass, reverse, e);
     }
+}
+
+// Grouped blur: G consecutive directions in one launch. For the directions
+// j_1..j_G of a group (in the order they are applied) the output is
+//   out[v] = sum over a in {0, +1, -1}^G of prod_k c(a_k) V[x_0],
+//   x_G = v, x_{k-1} = x_k + a_k u_{j_k},  c(0) = 1/2, c(+-1) = 1/4,
+// over the paths whose points x_k all exist: exactly the G sequential passes
+// (a point missing in between reads as 0 there). The endpoints x_0 of the 3^G
+// paths of every vertex are tabulated once per lattice (k_group_table); a
+// group of the last launch that has fewer than G directions tabulates only
+// the staying path for the missing ones, and the launch rescales by 2 per
+// missing direction.
+template <int G> struct Pow3 { static constexpr int v = 3 * Pow3<G - 1>::v; };
+template <> struct Pow3<0> { static constexpr int v = 1; };
+
+__global__ void k_group_table(int M, const int32_t *__restrict__ nbr, int G,
+                              int j1, int j2, int j3, int npass,
+                              int32_t *__restrict__ out) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= M) return;
+    int P = 1;
+    for (int k = 0; k < G; ++k) P *= 3;
+    const int js[3] = {j1, j2, j3};
+    for (int path = 0; path < P; ++path) {
+        int x = v, code = path, pw = P / 3;
+        bool ok = true;
+        // digit k (k = G..1, most significant first) is the step along j_k
+        for (int k = G; k >= 1 && ok; --k) {
+            const int a = code / pw;
+            code -= a * pw;
+            pw /= 3;
+            if (a == 0) continue;
+            if (k > npass) {
+                ok = false;
+                break;
+            }
+            x = nbr[((size_t)js[k - 1] * M + x) * 2 + (a - 1)];
+            ok = x >= 0;
+        }
+        out[(size_t)v * P + path] = ok ? x : -1;
+    }
+}
+
+template <typename T, int G>
+__device__ __forceinline__ void blur_group_vector(const LatSet<T> &ls, int grp,
+                                                  long long e) {
+    using V = typename Vec16<T>::type;
+    constexpr int vw = Vec16<T>::n;
+    constexpr int P = Pow3<G>::v;
+    int m = 0;
+    while (m + 1 < ls.nk && e >= ls.off[m + 1] / vw) ++m;
+    const LatView<T> &L = ls.l[m];
+    const unsigned Gv = unsigned(L.ld / vw);
+    const unsigned r = unsigned(e - ls.off[m] / vw);
+    V zero;
+    for (int i = 0; i < vw; ++i) reinterpret_cast<T *>(&zero)[i] = T(0);
+    if (grp >= L.ngrp) {
+        if (grp == 1) reinterpret_cast<V *>(L.V0)[r] = zero;
+        return;
+    }
+    const int v = int(r / Gv);
+    const int g = int(r - unsigned(v) * Gv);
+    const V *src = reinterpret_cast<const V *>((grp == 0) ? L.V0 : ((grp & 1) ? L.V1 : L.V2));
+    V *dst = reinterpret_cast<V *>((grp & 1) ? L.V2 : L.V1);
+    const int32_t *ids = L.gt + ((size_t)grp * L.M + v) * P;
+    int id[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) id[p] = ids[p];
+    T acc[vw];
+#pragma unroll
+    for (int i = 0; i < vw; ++i) acc[i] = T(0);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        // coefficient: 1/2 per staying step, 1/4 per move (digits of p)
+        T c = T(1);
+        int code = p;
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            c *= (code % 3 == 0) ? T(0.5) : T(0.25);
+            code /= 3;
+        }
+        const V x = src[(size_t)(id[p] >= 0 ? id[p] : 0) * Gv + g];
+        if (id[p] < 0) c = T(0);
+#pragma unroll
+        for (int i = 0; i < vw; ++i) acc[i] += c * reinterpret_cast<const T *>(&x)[i];
+    }
+    if (grp == L.ngrp - 1) {
+        const int missing = L.ngrp * G - (L.d + 1);
+        const T sc = T(1 << missing);
+#pragma unroll
+        for (int i = 0; i < vw; ++i) acc[i] *= sc;
+    }
+    V o;
+#pragma unroll
+    for (int i = 0; i < vw; ++i) reinterpret_cast<T *>(&o)[i] = acc[i];
+    dst[r] = o;
+    if (grp == 1) reinterpret_cast<V *>(L.V0)[r] = zero;
+}
+
+template <typename T, int G>
+__global__ void __launch_bounds__(256)
+k_blur_group(LatSet<T> ls, int grp, long long total, int vpt) {
+    const long long base = (long long)blockIdx.x * blockDim.x * vpt + threadIdx.x;
+    for (int q = 0; q < vpt; ++q) {
+        const long long e = base + (long long)q * blockDim.x;
+        if (e >= total) return;
+        blur_group_vector<T, G>(ls, grp, e);
+    }
+}
+
+template <typename T>
+__global__ void k_zero_rows(LatSet<T> ls, long long total) {
+    using V = typename Vec16<T>::type;
+    constexpr int vw = Vec16<T>::n;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    int m = 0;
+    while (m + 1 < ls.nk && e >= ls.off[m + 1] / vw) ++m;
+    V zero;
+    for (int i = 0; i < vw; ++i) reinterpret_cast<T *>(&zero)[i] = T(0);
+    reinterpret_cast<V *>(ls.l[m].V0)[e - ls.off[m] / vw] = zero;
 }
 
 // ------------------------------------------------------------------ slice
@@ -169,7 +294,7 @@ k_slice_rows(int N, int C, const T *__restrict__ Y, const T *__restrict__ pre,
             smu[(i / C) * LMAX + (i % C)] = mu[i];
         __syncthreads();
     }
-    for (long long p0 = (long long)blockIdx.x * TP; p0 < N;
+    for (long long p0 = (long long)xcd_block(blockIdx.x, gridDim.x) * TP; p0 < N;
          p0 += (long long)gridDim.x * TP) {
         const int np = (int)min((long long)TP, N - p0);
         const long long a = p0 + threadIdx.x;
@@ -325,21 +450,76 @@ void splat_labels_t(dcrf_ctx *ctx, const int32_t *labels, int L) {
     DCRF_CHECK_LAUNCH();
 }
 
+// path tables of the grouped blur for the context's group size
+void ensure_group_tables(dcrf_ctx *ctx, int G, bool adjoint) {
+    const int dir = adjoint ? 1 : 0;
+    for (int m = 0; m < ctx->nk; ++m) {
+        Lattice &L = ctx->lat[m];
+        if (L.gtab_G[dir] == G || L.M == 0) continue;
+        int P = 1;
+        for (int k = 0; k < G; ++k) P *= 3;
+        const int ng = blur_launches(L.d, G);
+        L.gtab[dir].ensure((size_t)ng * L.M * P * 4, ctx->stream);
+        for (int grp = 0; grp < ng; ++grp) {
+            int js[3] = {0, 0, 0};
+            int np = 0;
+            for (int k = 0; k < G; ++k) {
+                const int pass = grp * G + k;   // position in the blur order
+                if (pass > L.d) break;
+                js[k] = adjoint ? (L.d - pass) : pass;
+                ++np;
+            }
+            hipLaunchKernelGGL(k_group_table, dim3(ceil_div(L.M, 256)), dim3(256), 0,
+                               ctx->stream, L.M, L.nbr.as<int32_t>(), G, js[0], js[1],
+                               js[2], np,
+                               L.gtab[dir].as<int32_t>() + (size_t)grp * L.M * P);
+        }
+        DCRF_CHECK_LAUNCH();
+        L.gtab_G[dir] = G;
+    }
+}
+
+// The blur of every lattice of `ls` (its views index the context's lattices
+// lat[first], lat[first+1], ...), one launch per direction or per group of
+// ctx->blur_group directions.
+template <typename T>
+void blur_launch(dcrf_ctx *ctx, LatSet<T> &ls, int first, bool adjoint) {
+    const long long total = ls.off[ls.nk] / Vec16<T>::n;
+    if (total == 0) return;
+    const int bs = ctx->blur_block, vpt = ctx->blur_vpt, G = ctx->blur_group;
+    const dim3 grid(ceil_div(total, (long long)bs * vpt));
+    int nl = 0;
+    for (int m = 0; m < ls.nk; ++m) nl = std::max(nl, ls.l[m].ngrp);
+    if (G == 1) {
+        for (int p = 0; p < nl; ++p) {
+            ProfScope ps(ctx, PROF_BLUR);
+            hipLaunchKernelGGL((k_blur_pass<T>), grid, dim3(bs), 0, ctx->stream, ls, p,
+                               adjoint ? 1 : 0, total, vpt);
+        }
+    } else {
+        ensure_group_tables(ctx, G, adjoint);
+        for (int m = 0; m < ls.nk; ++m)
+            ls.l[m].gt = ctx->lat[first + m].gtab[adjoint ? 1 : 0].as<int32_t>();
+        for (int grp = 0; grp < nl; ++grp) {
+            ProfScope ps(ctx, PROF_BLUR);
+            if (G == 2)
+                hipLaunchKernelGGL((k_blur_group<T, 2>), grid, dim3(bs), 0, ctx->stream,
+                                   ls, grp, total, vpt);
+            else
+                hipLaunchKernelGGL((k_blur_group<T, 3>), grid, dim3(bs), 0, ctx->stream,
+                                   ls, grp, total, vpt);
+        }
+    }
+    if (nl == 1)   // no second launch cleared the splat target
+        hipLaunchKernelGGL((k_zero_rows<T>), dim3(ceil_div(total, 256)), dim3(256), 0,
+                           ctx->stream, ls, total);
+    DCRF_CHECK_LAUNCH();
+}
+
 template <typename T>
 void blur_all_t(dcrf_ctx *ctx, int C, bool adjoint) {
     LatSet<T> ls = make_lat_set<T>(ctx, C);
-    int maxd = 0;
-    for (int m = 0; m < ctx->nk; ++m) maxd = std::max(maxd, ctx->lat[m].d);
-    const long long total = ls.off[ctx->nk] / Vec16<T>::n;
-    if (total == 0) return;
-    const int bs = ctx->blur_block, vpt = ctx->blur_vpt;
-    for (int p = 0; p <= maxd; ++p) {
-        ProfScope ps(ctx, PROF_BLUR);
-        hipLaunchKernelGGL((k_blur_pass<T>), dim3(ceil_div(total, (long long)bs * vpt)),
-                           dim3(bs), 0, ctx->stream, ls, p, adjoint ? 1 : 0,
-                           total, vpt);
-    }
-    DCRF_CHECK_LAUNCH();
+    blur_launch<T>(ctx, ls, 0, adjoint);
 }
 
 template <typename T>
@@ -409,14 +589,7 @@ void filter_kernel_t(dcrf_ctx *ctx, int m, const T *in, T *out, int C,
     if (ls.coff[1] > 0)
         hipLaunchKernelGGL((k_splat_gather<T>), dim3(ceil_div(ls.coff[1], 256)),
                            dim3(256), 0, s, C, in, ls);
-    const long long total = ls.off[1] / Vec16<T>::n;
-    if (total > 0)
-        for (int p = 0; p <= ls.l[0].d; ++p)
-            hipLaunchKernelGGL((k_blur_pass<T>),
-                               dim3(ceil_div(total, (long long)ctx->blur_block *
-                                                        ctx->blur_vpt)),
-                               dim3(ctx->blur_block), 0, s, ls, p, adjoint ? 1 : 0,
-                               total, ctx->blur_vpt);
+    blur_launch<T>(ctx, ls, m, adjoint);
     const int N = ctx->N;
     constexpr int TP = RowTile<T>::kPix;
     if (C <= kRowMaxC) {

@@ -19,6 +19,8 @@ struct LatView {
     const int32_t *ent_v;
     int d, M, ld, nchunks;
     T wg;                // w_m * gamma_m
+    const int32_t *gt;   // grouped-blur path table of the direction in use
+    int ngrp;            // blur launches of this lattice
 };
 
 template <typename T>
@@ -60,7 +62,10 @@ inline LatSet<T> make_lat_set(dcrf_ctx *ctx, int C) {
         v.V0 = L.V[0].as<T>();
         v.V1 = L.V[1].as<T>();
         v.V2 = L.V[2].as<T>();
-        v.Vf = L.V[final_buffer(L.d)].as<T>();
+        const int nl = blur_launches(L.d, ctx->blur_group);
+        v.ngrp = nl;
+        v.Vf = L.V[final_buffer_after(nl)].as<T>();
+        v.gt = nullptr;
         v.chunks = L.chunks.as<int4>();
         v.ent_pix = L.ent_pix.as<int32_t>();
         v.ent_w = L.ent_w.as<T>();
@@ -108,6 +113,18 @@ void fill_ones(dcrf_ctx *ctx, void *p, size_t n);
 template <typename T> struct RowTile;
 template <> struct RowTile<float> { static constexpr int kPix = 128; };
 template <> struct RowTile<double> { static constexpr int kPix = 64; };
+
+// The workgroups of a launch are dealt to the chip's 8 XCDs round-robin
+// (block b runs on XCD b % 8, each XCD with its own L2). This maps the
+// hardware block index to a logical one such that every XCD receives one
+// contiguous range of logical blocks: neighbouring work (adjacent pixel
+// tiles, inverse-index chunks ordered by pixel) then shares an L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    constexpr int X = 8;
+    const int q = nb / X, r = nb - q * X;
+    const int x = b % X, i = b / X;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
 
 // Tile `tile` of the per-image tilings of TP pixels, images taken in order
 // (see dcrf_ctx::seg): returns the image and sets [lo, hi), its pixel rows.

@@ -26,6 +26,8 @@
 #include <cmath>
 #include <vector>
 
+#include <hipcub/hipcub.hpp>
+
 #include "dcrf_internal.h"
 #include "hash_scan.h"
 
@@ -224,19 +226,65 @@ __global__ void k_csr_count(size_t cnt, const int *__restrict__ pix_vid,
     if (v >= 0) atomicAdd(&counts[v], 1);
 }
 
-template <typename T>
-__global__ void k_csr_fill(size_t cnt, int D1, const int *__restrict__ pix_vid,
-                           const T *__restrict__ pix_w, const int *__restrict__ off,
-                           int *__restrict__ cursor, int *__restrict__ ent_pix,
-                           T *__restrict__ ent_w, int *__restrict__ ent_v) {
+// sort keys of the pixel-vertex pairs: the vertex id, or the largest key of
+// `bits` bits where the weight is 0 (those sort last and are dropped)
+__global__ void k_ref_keys(size_t cnt, const int *__restrict__ pix_vid,
+                           uint32_t none, uint32_t *__restrict__ keys,
+                           uint32_t *__restrict__ refs) {
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= cnt) return;
     const int v = pix_vid[e];
-    if (v < 0) return;
-    const int pos = off[v] + atomicAdd(&cursor[v], 1);
-    ent_pix[pos] = int(e / D1);
-    ent_w[pos] = pix_w[e];
-    ent_v[pos] = v;
+    keys[e] = v >= 0 ? uint32_t(v) : none;
+    refs[e] = uint32_t(e);
+}
+
+// entries from the pairs sorted by vertex (stable, so each vertex's pixels
+// stay in raster order)
+template <typename T>
+__global__ void k_entries(int nent, int D1, const uint32_t *__restrict__ keys,
+                          const uint32_t *__restrict__ refs,
+                          const T *__restrict__ pix_w, int *__restrict__ ent_pix,
+                          T *__restrict__ ent_w, int *__restrict__ ent_v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nent) return;
+    const uint32_t ref = refs[i];
+    ent_pix[i] = int(ref / uint32_t(D1));
+    ent_w[i] = pix_w[ref];
+    ent_v[i] = int(keys[i]);
+}
+
+__global__ void k_chunk_keys(int n, const int4 *__restrict__ chunks,
+                             const int *__restrict__ ent_pix,
+                             uint32_t *__restrict__ keys, uint32_t *__restrict__ idx) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = uint32_t(ent_pix[chunks[i].y]);
+    idx[i] = uint32_t(i);
+}
+
+__global__ void k_chunk_permute(int n, const uint32_t *__restrict__ idx,
+                                const int4 *__restrict__ in, int4 *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[idx[i]];
+}
+
+int key_bits(unsigned long long maxval) {
+    int b = 1;
+    while (b < 32 && (1ull << b) <= maxval) ++b;
+    return b;
+}
+
+// stable LSD radix sort of (key, value) pairs of u32 on the stream, keys
+// using their low `bits` bits
+void sort_pairs(dcrf_ctx *ctx, const uint32_t *kin, uint32_t *kout,
+                const uint32_t *vin, uint32_t *vout, int n, int bits,
+                DevBuf &temp) {
+    size_t bytes = 0;
+    DCRF_TRY_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, kin, kout, vin,
+                                                   vout, n, 0, bits, ctx->stream));
+    temp.ensure(bytes, ctx->stream);
+    DCRF_TRY_HIP(hipcub::DeviceRadixSort::SortPairs(temp.p, bytes, kin, kout, vin,
+                                                   vout, n, 0, bits, ctx->stream));
 }
 
 __global__ void k_chunk_count(int M, const int *__restrict__ off, int chunk,
@@ -348,14 +396,30 @@ void build_inverse_index(dcrf_ctx *ctx, int m) {
     hipLaunchKernelGGL(k_csr_count, dim3(ceil_div((long long)cnt, 256)), dim3(256),
                        0, s, cnt, L.pix_vid.as<int>(), counts);
     scan_ints(ctx, counts, M, L.csr_off.as<int>());
-    DCRF_TRY_HIP(hipMemsetAsync(counts, 0, (size_t)(M + 1) * 4, s));
-    hipLaunchKernelGGL((k_csr_fill<T>), dim3(ceil_div((long long)cnt, 256)),
-                       dim3(256), 0, s, cnt, D1, L.pix_vid.as<int>(),
-                       L.pix_w.as<T>(), L.csr_off.as<int>(), counts,
-                       L.ent_pix.as<int>(), L.ent_w.as<T>(), L.ent_v.as<int>());
     DCRF_TRY_HIP(hipMemcpyAsync(&L.nent, L.csr_off.as<int>() + M, 4,
                                 hipMemcpyDeviceToHost, s));
+    // entries: the pixel-vertex pairs stably sorted by vertex
+    DevBuf k0, k1, v0, v1, temp;
+    struct Free {
+        DevBuf *b[5];
+        ~Free() { for (DevBuf *x : b) x->release(); }
+    } fr{{&k0, &k1, &v0, &v1, &temp}};
+    for (DevBuf *b : {&k0, &k1, &v0, &v1}) b->ensure(cnt * 4, s);
+    const int bits = key_bits((unsigned long long)M);
+    hipLaunchKernelGGL(k_ref_keys, dim3(ceil_div((long long)cnt, 256)), dim3(256), 0,
+                       s, cnt, L.pix_vid.as<int>(), uint32_t((1ull << bits) - 1),
+                       k0.as<uint32_t>(), v0.as<uint32_t>());
+    sort_pairs(ctx, k0.as<uint32_t>(), k1.as<uint32_t>(), v0.as<uint32_t>(),
+               v1.as<uint32_t>(), int(cnt), bits, temp);
+    DCRF_TRY_HIP(hipStreamSynchronize(s));
+    if (L.nent > 0)
+        hipLaunchKernelGGL((k_entries<T>), dim3(ceil_div(L.nent, 256)), dim3(256), 0,
+                           s, L.nent, D1, k1.as<uint32_t>(), v1.as<uint32_t>(),
+                           L.pix_w.as<T>(), L.ent_pix.as<int>(), L.ent_w.as<T>(),
+                           L.ent_v.as<int>());
+    DCRF_CHECK_LAUNCH();
     chunk_index(ctx, m);
+    DCRF_TRY_HIP(hipStreamSynchronize(s));
 }
 
 // chunk list of lattice m from its inverse index (csr_off) and L.chunk
@@ -380,6 +444,28 @@ void chunk_index(dcrf_ctx *ctx, int m) {
                            M, L.csr_off.as<int>(), L.chunk_off.as<int>(), L.chunk,
                            L.chunks.as<int4>());
     DCRF_CHECK_LAUNCH();
+    if (nch <= 1) return;
+    // order the chunks by their first pixel: the splats then walk the image
+    // roughly in raster order, and with the XCD mapping of their blocks each
+    // L2 sees one band of the image's rows
+    DevBuf k0, k1, v0, v1, temp, tmp;
+    struct Free {
+        DevBuf *b[6];
+        ~Free() { for (DevBuf *x : b) x->release(); }
+    } fr{{&k0, &k1, &v0, &v1, &temp, &tmp}};
+    for (DevBuf *b : {&k0, &k1, &v0, &v1}) b->ensure((size_t)nch * 4, s);
+    tmp.ensure((size_t)nch * sizeof(int4), s);
+    hipLaunchKernelGGL(k_chunk_keys, dim3(ceil_div(nch, 256)), dim3(256), 0, s, nch,
+                       L.chunks.as<int4>(), L.ent_pix.as<int>(), k0.as<uint32_t>(),
+                       v0.as<uint32_t>());
+    sort_pairs(ctx, k0.as<uint32_t>(), k1.as<uint32_t>(), v0.as<uint32_t>(),
+               v1.as<uint32_t>(), nch, key_bits((unsigned long long)ctx->N), temp);
+    DCRF_TRY_HIP(hipMemcpyAsync(tmp.p, L.chunks.p, (size_t)nch * sizeof(int4),
+                                hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_chunk_permute, dim3(ceil_div(nch, 256)), dim3(256), 0, s, nch,
+                       v1.as<uint32_t>(), tmp.as<int4>(), L.chunks.as<int4>());
+    DCRF_CHECK_LAUNCH();
+    DCRF_TRY_HIP(hipStreamSynchronize(s));
 }
 
 template <int D, typename T>

@@ -130,8 +130,9 @@ k_fw_lmo_rows(FWArgs<T> A) {
     __shared__ __align__(16) T lds[TP * (LMAX | 1)];
     __shared__ double red[kP1 * TP];
     const int L = A.L;
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
     int lo, hi;
-    const int img = tile_range(A.seg, A.nimg, TP, blockIdx.x, lo, hi);
+    const int img = tile_range(A.seg, A.nimg, TP, tile, lo, hi);
     const T al = (A.first || img < 0) ? T(0) : T(A.scal[img]);
     double acc[kP1];
 #pragma unroll
@@ -192,7 +193,7 @@ k_fw_lmo_rows(FWArgs<T> A) {
         }
     }
     block_sum<kP1, TP>(acc, red);
-    if (threadIdx.x < kP1) A.part[(size_t)blockIdx.x * kP1 + threadIdx.x] = acc[threadIdx.x];
+    if (threadIdx.x < kP1) A.part[(size_t)tile * kP1 + threadIdx.x] = acc[threadIdx.x];
 }
 
 // One block: fixed-order reduction of every block's partial sums, the exact
@@ -271,8 +272,9 @@ k_fw_slice_rows(FWSliceArgs<T> A, LatSet<T> ls) {
         __syncthreads();
     }
     double acc[kP2] = {0.0, 0.0};
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
     int lo, hi;
-    tile_range(A.seg, A.nimg, TP, blockIdx.x, lo, hi);
+    tile_range(A.seg, A.nimg, TP, tile, lo, hi);
     {
         const long long p0 = lo;
         const int np = hi - lo;
@@ -337,7 +339,7 @@ k_fw_slice_rows(FWSliceArgs<T> A, LatSet<T> ls) {
     }
     double v[kP2] = {acc[0], acc[1]};
     block_sum<kP2, TP>(v, red);
-    if (threadIdx.x < kP2) A.part2[(size_t)blockIdx.x * kP2 + threadIdx.x] = v[threadIdx.x];
+    if (threadIdx.x < kP2) A.part2[(size_t)tile * kP2 + threadIdx.x] = v[threadIdx.x];
 }
 
 // ------------------------------------------------- flat kernels (L > 32)

@@ -44,7 +44,8 @@ class dcrf_iter_trace(ctypes.Structure):
 class dcrf_tune(ctypes.Structure):
     _fields_ = [("splat_chunk", ctypes.c_int),
                 ("blur_vectors_per_thread", ctypes.c_int),
-                ("blur_block", ctypes.c_int), ("ms", ctypes.c_double)]
+                ("blur_block", ctypes.c_int), ("blur_group", ctypes.c_int),
+                ("ms", ctypes.c_double)]
 
 
 # name -> (restype, argtypes); mirrors include/dcrf.h
@@ -63,6 +64,7 @@ PROTOTYPES = {
     "dcrf_image_layout": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I),
                                ctypes.POINTER(_I)]),
     "dcrf_autotune": (_I, [_P, _I, _I, ctypes.POINTER(dcrf_tune)]),
+    "dcrf_set_tune": (_I, [_P, ctypes.POINTER(dcrf_tune)]),
     "dcrf_set_weights": (_I, [_P, _PD, _I]),
     "dcrf_set_filter_mode": (_I, [_P, _I]),
     "dcrf_lattice_info": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
@@ -200,13 +202,20 @@ class Context:
         """One packed (N x C) tensor -> per-image views."""
         return [packed[a:b] for a, b in self.seg]
 
+    def set_tune(self, splat_chunk=64, blur_vectors_per_thread=1,
+                 blur_block=256, blur_group=2, **_):
+        t = dcrf_tune(splat_chunk, blur_vectors_per_thread, blur_block,
+                      blur_group, 0.0)
+        self._stream()
+        self._check(_lib.dcrf_set_tune(self._h, ctypes.byref(t)))
+
     def autotune(self, L: int, reps: int = 5):
         t = dcrf_tune()
         self._stream()
         self._check(_lib.dcrf_autotune(self._h, L, reps, ctypes.byref(t)))
         return dict(splat_chunk=t.splat_chunk,
                     blur_vectors_per_thread=t.blur_vectors_per_thread,
-                    blur_block=t.blur_block, ms=t.ms)
+                    blur_block=t.blur_block, blur_group=t.blur_group, ms=t.ms)
 
     def set_weights(self, w):
         arr = (ctypes.c_double * len(w))(*[float(v) for v in w])

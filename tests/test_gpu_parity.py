@@ -329,3 +329,42 @@ def test_errors_are_reported_not_fatal():
                   dtype=torch.float64)
     x = torch.zeros(im.N, dtype=torch.int32, device=dev())
     ctx.energy(T(im.unary, torch.float64), mu, x)
+
+
+@pytest.mark.parametrize("tune", [
+    dict(splat_chunk=16, blur_vectors_per_thread=1, blur_block=64, blur_group=1),
+    dict(splat_chunk=128, blur_vectors_per_thread=2, blur_block=128, blur_group=2),
+    dict(splat_chunk=256, blur_vectors_per_thread=4, blur_block=256, blur_group=3),
+    dict(splat_chunk=32, blur_vectors_per_thread=3, blur_block=256, blur_group=3),
+])
+@pytest.mark.parametrize("name,dtype,rtol", [("rect_32x24_L3", torch.float64, 1e-11),
+                                              ("voronoi_320x213_L21", torch.float32, 1e-5)])
+def test_launch_shapes_keep_filter_parity(tune, name, dtype, rtol):
+    """Every launch shape (splat chunk length, blur directions per launch,
+    vectors per thread, block size) gives the oracle's filter, both ways."""
+    im = synth.make(name)
+    ctx = gpu_ctx(im, dtype)
+    ctx.set_tune(**tune)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    rng = np.random.default_rng(11)
+    Y = rng.uniform(-1, 1, size=(im.N, 5))
+    for adjoint in (False, True):
+        got = ctx.filter(T(Y, dtype), adjoint=adjoint).double().cpu().numpy()
+        ref = model.Kp(Y, reverse=adjoint)
+        assert (np.abs(got - ref) <= filter_bound(model, Y, rtol)).all(), adjoint
+
+
+def test_grouped_blur_fw_fp64_matches_oracle():
+    im = synth.make("rect_32x24_L3")
+    ctx = gpu_ctx(im, torch.float64)
+    ctx.set_tune(splat_chunk=32, blur_vectors_per_thread=2, blur_block=128,
+                 blur_group=3)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    mu = synth.potts(3)
+    qp = O.QP(model, im.unary, mu)
+    e = np.exp(-(im.unary - im.unary.min(axis=1, keepdims=True)))
+    y0 = e / e.sum(axis=1, keepdims=True)
+    st = O.frank_wolfe(qp, y0, 20)
+    y = T(y0, torch.float64)
+    ctx.qp_frank_wolfe(T(im.unary, torch.float64), T(mu, torch.float64), y, 20)
+    assert np.abs(y.cpu().numpy() - st.y).max() <= 1e-10
