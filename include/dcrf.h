@@ -85,6 +85,7 @@ typedef struct {
     int blur_vectors_per_thread;  /* 16-byte vectors per thread in the blur   */
     int blur_block;               /* threads per block of the blur            */
     int blur_group;               /* blur directions applied per launch       */
+    int tiles;                    /* 1: splats and slices by 16x16 pixel tiles */
     double ms;                    /* time of the tuned filter paths, ms       */
 } dcrf_tune;
 
@@ -140,10 +141,11 @@ int dcrf_set_images(dcrf_ctx *ctx, int B, const int *H, const int *W,
  * the last row of each image. Any pointer may be NULL. */
 int dcrf_image_layout(dcrf_ctx *ctx, int *nimg, int *rows, int *seg);
 
-/* Pick the launch shapes of the filter (splat chunk length of 32, 64 or 128
- * entries; in the blur 1, 2 or 3 directions per launch, 1 or 2 16-byte
- * vectors per thread and 128 or 256 threads per block) by timing, for each
- * candidate, `reps` (1..1000) runs of
+/* Pick the launch shapes of the filter (splats and slices by inverse-index
+ * chunks and pixel rows, or by 16x16 pixel tiles; splat chunk length of 32,
+ * 64 or 128 entries; in the blur 1, 2 or 3 directions per launch, 1 or 2
+ * 16-byte vectors per thread and 128 or 256 threads per block) by timing,
+ * for each candidate, `reps` (1..1000) runs of
  * a dense L-channel filter plus the one-hot splat, blur and slice of a
  * Frank-Wolfe iteration on the context's own lattices; keeps the fastest.
  * *out (host, may be NULL) receives the choice. Results of every call are the
@@ -152,8 +154,9 @@ int dcrf_autotune(dcrf_ctx *ctx, int L, int reps, dcrf_tune *out);
 
 /* Set the launch shapes directly (the `ms` field is ignored): splat_chunk in
  * {16, 32, 64, 128, 256}, blur_vectors_per_thread in 1..4, blur_block in
- * {64, 128, 256}, blur_group in 1..3; DCRF_EINVAL otherwise. Results are the
- * same for every choice up to floating-point summation order. */
+ * {64, 128, 256}, blur_group in 1..3, tiles 0 or 1; DCRF_EINVAL otherwise.
+ * Results are the same for every choice up to floating-point summation
+ * order. */
 int dcrf_set_tune(dcrf_ctx *ctx, const dcrf_tune *tune);
 
 /* Replace the kernel weights w_m (host, nk values) without rebuilding the

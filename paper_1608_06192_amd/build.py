@@ -41,6 +41,7 @@ SOURCES = {
     "lp.hip": [],
     "diff.hip": [],
     "batch.hip": [],
+    "tiles.hip": [],
     "abi.cpp": ["-x", "hip"],
 }
 

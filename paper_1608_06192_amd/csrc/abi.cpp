@@ -153,6 +153,7 @@ int dcrf_set_image(dcrf_ctx *ctx, int H, int W, const float *rgb,
         ctx->img_W.assign(1, W);
         dcrf::build_lattices(ctx, rgb);
         dcrf::set_segments(ctx, {0, ctx->N});
+        dcrf::build_tiles(ctx);
         ctx->has_image = true;
         dcrf::compute_row_sums(ctx);
     });
@@ -183,6 +184,7 @@ int dcrf_set_images(dcrf_ctx *ctx, int B, const int *H, const int *W,
         } else {
             dcrf::build_batch(ctx, B, H, W, rgb);
         }
+        dcrf::build_tiles(ctx);
         ctx->has_image = true;
         dcrf::compute_row_sums(ctx);
     });
@@ -212,6 +214,7 @@ int dcrf_autotune(dcrf_ctx *ctx, int L, int reps, dcrf_tune *out) {
             out->blur_vectors_per_thread = ctx->blur_vpt;
             out->blur_block = ctx->blur_block;
             out->blur_group = ctx->blur_group;
+            out->tiles = ctx->tile_mode;
             out->ms = ms;
         }
     });
@@ -229,10 +232,12 @@ int dcrf_set_tune(dcrf_ctx *ctx, const dcrf_tune *t) {
         REQUIRE(t->blur_block == 64 || t->blur_block == 128 || t->blur_block == 256,
                 "blur_block must be 64, 128 or 256");
         REQUIRE(t->blur_group >= 1 && t->blur_group <= 3, "blur_group must be in 1..3");
+        REQUIRE(t->tiles == 0 || t->tiles == 1, "tiles must be 0 or 1");
         if (c != ctx->splat_chunk) dcrf::rechunk(ctx, c);
         ctx->blur_vpt = t->blur_vectors_per_thread;
         ctx->blur_block = t->blur_block;
         ctx->blur_group = t->blur_group;
+        ctx->tile_mode = t->tiles;
     });
 }
 

@@ -243,13 +243,18 @@ void autotune(dcrf_ctx *ctx, int L, int reps, double *best_ms) {
     hipEvent_t e0, e1;
     DCRF_TRY_HIP(hipEventCreate(&e0));
     DCRF_TRY_HIP(hipEventCreate(&e1));
-    struct Cand { int chunk, vpt, block, group; };
+    struct Cand { int chunk, vpt, block, group, tiles; };
     std::vector<Cand> cands;
-    for (int chunk : {32, 64, 128})
-        for (int vpt : {1, 2})
-            for (int block : {128, 256})
-                for (int group : {1, 2, 3}) cands.push_back({chunk, vpt, block, group});
-    Cand best = {ctx->splat_chunk, ctx->blur_vpt, ctx->blur_block, ctx->blur_group};
+    for (int tiles : {0, 1})
+        for (int chunk : {32, 64, 128})
+            for (int vpt : {1, 2})
+                for (int block : {128, 256})
+                    for (int group : {1, 2, 3}) {
+                        if (tiles && chunk != 64) continue;   // chunks unused
+                        cands.push_back({chunk, vpt, block, group, tiles});
+                    }
+    Cand best = {ctx->splat_chunk, ctx->blur_vpt, ctx->blur_block, ctx->blur_group,
+                 ctx->tile_mode};
     double best_t = 1e300;
     auto run = [&] {
         // the dense filter and the one-hot path of a Frank-Wolfe iteration
@@ -265,6 +270,7 @@ void autotune(dcrf_ctx *ctx, int L, int reps, double *best_ms) {
             ctx->blur_vpt = c.vpt;
             ctx->blur_block = c.block;
             ctx->blur_group = c.group;
+            ctx->tile_mode = c.tiles;
             run();
             DCRF_TRY_HIP(hipEventRecord(e0, s));
             for (int r = 0; r < reps; ++r) run();
@@ -291,6 +297,7 @@ void autotune(dcrf_ctx *ctx, int L, int reps, double *best_ms) {
     ctx->blur_vpt = best.vpt;
     ctx->blur_block = best.block;
     ctx->blur_group = best.group;
+    ctx->tile_mode = best.tiles;
     if (best_ms) *best_ms = best_t;
 }
 

@@ -97,12 +97,27 @@ struct Lattice {
     // path leaves the lattice); [0] forward order, [1] the transpose's order
     DevBuf gtab[2];
     int gtab_G[2] = {0, 0};
+    // per-tile vertex slots (tiles.hip)
+    DevBuf ts_off;       // ntiles + 1 i32: slots of each pixel tile
+    DevBuf ts_vid;       // nslots i32: vertex of each slot
+    DevBuf tr_slot;      // N (d+1) u16: slot of each pixel-vertex pair in its tile
+    DevBuf sr_off;       // nslots + 1 i32: pairs of each slot
+    DevBuf sr_pix;       // nent u8: tile-local pixel of each pair, by slot
+    DevBuf sr_w;         // nent x T: weight of each pair, by slot
+    DevBuf sr_slot;      // nent u16: slot of each pair (counted from its tile's first)
+    DevBuf vs_off;       // M + 1 i32: slots of each vertex
+    DevBuf vs_slot;      // nslots i32
+    int nslots = 0, max_tile_slots = 0;
+    std::vector<int> tile_slots;
     void release() {
         for (DevBuf *b : {&hkeys, &slot_vid, &pix_slot, &pix_vid, &pix_w,
                           &vkeys, &nbr, &V[0], &V[1], &V[2], &feat, &csr_off,
                           &csr_tmp, &ent_pix, &ent_w, &ent_v, &chunk_off, &chunks,
-                          &gtab[0], &gtab[1]})
+                          &gtab[0], &gtab[1], &ts_off, &ts_vid, &tr_slot, &sr_off,
+                          &sr_pix, &sr_w, &sr_slot, &vs_off, &vs_slot})
             b->release();
+        nslots = max_tile_slots = 0;
+        tile_slots.clear();
         gtab_G[0] = gtab_G[1] = 0;
     }
 };
@@ -186,6 +201,13 @@ struct dcrf_ctx {
     int blur_vpt = 1;        // 16-byte vectors per thread in the blur
     int blur_block = 256;    // threads per block in the blur
     int blur_group = 2;      // blur directions applied per launch (1..3)
+    int tile_mode = 0;       // splats and slices through the per-tile slots
+    // 2-D pixel tiles of every image (tiles.hip)
+    int ntiles = 0;
+    dcrf::DevBuf tiles;              // ntiles x int4: first row, row stride, rows, cols
+    dcrf::DevBuf tile_img_off;       // nimg + 1 i32: first tile of each image
+    std::vector<int> tile_img_off_h;
+    dcrf::DevBuf splatP;             // partial rows of the tile splat
     int mode = DCRF_FILTER_LATTICE;
     bool has_image = false;
     dcrf_kernel kern[DCRF_MAXK];
@@ -287,6 +309,13 @@ void project_simplex(dcrf_ctx *ctx, const void *v, int L, void *y);
 void lp_release(dcrf_ctx *ctx);
 
 inline int ceil_div(long long a, long long b) { return int((a + b - 1) / b); }
+
+// 2-D pixel tiles (tiles.hip)
+constexpr int kTileH = 16, kTileW = 16, kTilePix = kTileH * kTileW;
+// largest d + 1 of a lattice served by the tile kernels (pairs of one tile
+// and lattice: at most kTilePix * (d + 1))
+constexpr int kMaxD1 = 6;
+void build_tiles(dcrf_ctx *ctx);
 
 // Segments of the pixel range (see dcrf_ctx): set on the host and uploaded.
 void set_segments(dcrf_ctx *ctx, const std::vector<int> &seg);

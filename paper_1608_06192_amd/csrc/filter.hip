@@ -408,6 +408,294 @@ k_exact(int N, int C, int c0, const T *__restrict__ in, T *__restrict__ out,
         for (int c = 0; c < cn; ++c) out[(size_t)a * C + c0 + c] = acc[c];
 }
 
+// ------------------------------------------------------- tile kernels
+
+// Splat, first pass: one block per 2-D pixel tile. The tile's input rows are
+// staged in LDS (each tile row a contiguous range, copied coalesced). Per
+// lattice, the tile's pixel-vertex pairs, grouped by slot, are cut into
+// equal runs of consecutive pairs, one per thread (so a vertex shared by the
+// whole tile is spread over many threads); a thread sums w * Y over its pairs
+// in registers and adds the sum of each slot it covers to the slot's partial
+// row in LDS (one LDS atomic per channel and slot change). The partial rows
+// are then written out, padding channels zero.
+template <typename T, int LMAX>
+__global__ void __launch_bounds__(kTilePix)
+k_tile_splat(int C, int ld, const T *__restrict__ Y, LatSet<T> ls,
+             const int4 *__restrict__ tiles, T *__restrict__ P, int cap) {
+    extern __shared__ __align__(16) unsigned char tile_smem[];
+    T *ys = reinterpret_cast<T *>(tile_smem);   // kTilePix x ld
+    T *pl = ys + kTilePix * ld;                  // cap x ld
+    const int t = xcd_block(blockIdx.x, gridDim.x);
+    const int4 td = tiles[t];
+    tile2_in<T, kTilePix>(Y, td, C, ys, ld);
+    for (int m = 0; m < ls.nk; ++m) {
+        const LatView<T> &L = ls.l[m];
+        const int s0 = L.ts_off[t], ns = L.ts_off[t + 1] - s0;
+        const int e0 = L.sr_off[s0], ne = L.sr_off[s0 + ns] - e0;
+        for (int k = threadIdx.x; k < ns * ld; k += kTilePix) pl[k] = T(0);
+        __syncthreads();
+        const int per = (ne + kTilePix - 1) / kTilePix;
+        const int rb = e0 + threadIdx.x * per, re = min(rb + per, e0 + ne);
+        T acc[LMAX];
+#pragma unroll
+        for (int c = 0; c < LMAX; ++c) acc[c] = T(0);
+        int cur = -1;
+        for (int r = rb; r < re; ++r) {
+            const int sl = L.sr_slot[r];
+            if (sl != cur) {
+                if (cur >= 0) {
+#pragma unroll
+                    for (int c = 0; c < LMAX; ++c)
+                        if (c < C) atomicAdd(&pl[cur * ld + c], acc[c]);
+                }
+#pragma unroll
+                for (int c = 0; c < LMAX; ++c) acc[c] = T(0);
+                cur = sl;
+            }
+            axpy_row<LMAX>(acc, L.sr_w[r], ys + L.sr_pix[r] * ld, C);
+        }
+        if (cur >= 0) {
+#pragma unroll
+            for (int c = 0; c < LMAX; ++c)
+                if (c < C) atomicAdd(&pl[cur * ld + c], acc[c]);
+        }
+        __syncthreads();
+        T *Pm = P + (size_t)(ls.soff[m] + s0) * ld;
+        for (int k = threadIdx.x; k < ns * ld; k += kTilePix) Pm[k] = pl[k];
+        __syncthreads();
+    }
+    (void)cap;
+}
+
+// Splat, second pass: V0[v] = sum of the partial rows of v's slots, one
+// thread per 16-byte vector of the vertex rows of every lattice.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_vertex_gather(LatSet<T> ls, const T *__restrict__ P, long long total) {
+    using V = typename Vec16<T>::type;
+    constexpr int vw = Vec16<T>::n;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    int m = 0;
+    while (m + 1 < ls.nk && e >= ls.off[m + 1] / vw) ++m;
+    const LatView<T> &L = ls.l[m];
+    const unsigned G = unsigned(L.ld / vw);
+    const unsigned r = unsigned(e - ls.off[m] / vw);
+    const int v = int(r / G);
+    const int g = int(r - unsigned(v) * G);
+    const V *Pm = reinterpret_cast<const V *>(P + (size_t)ls.soff[m] * L.ld);
+    T acc[vw];
+#pragma unroll
+    for (int i = 0; i < vw; ++i) acc[i] = T(0);
+    const int b = L.vs_off[v], en = L.vs_off[v + 1];
+    for (int i = b; i < en; ++i) {
+        const V x = Pm[(size_t)L.vs_slot[i] * G + g];
+#pragma unroll
+        for (int k = 0; k < vw; ++k) acc[k] += reinterpret_cast<const T *>(&x)[k];
+    }
+    V o;
+#pragma unroll
+    for (int k = 0; k < vw; ++k) reinterpret_cast<T *>(&o)[k] = acc[k];
+    reinterpret_cast<V *>(L.V0)[r] = o;
+}
+
+// One-hot splat: one block per tile. The tile's labels are staged in LDS;
+// per lattice the tile's pairs, grouped by slot, are cut into equal runs of
+// consecutive pairs, one per thread. A thread sums the weights of its pairs
+// per (slot, label) in registers (up to four labels per slot; further ones
+// go straight to the vertex row) and adds each sum to V0[v][label].
+template <typename T>
+__global__ void __launch_bounds__(kTilePix)
+k_tile_labels(int C, const int32_t *__restrict__ labels, LatSet<T> ls,
+              const int4 *__restrict__ tiles) {
+    __shared__ int labs[kTilePix];
+    const int t = xcd_block(blockIdx.x, gridDim.x);
+    const int4 td = tiles[t];
+    const int i = threadIdx.x / kTileW, px = threadIdx.x % kTileW;
+    labs[threadIdx.x] = (i < td.z && px < td.w)
+                            ? labels[(size_t)td.x + (size_t)i * td.y + px] : -1;
+    __syncthreads();
+    for (int m = 0; m < ls.nk; ++m) {
+        const LatView<T> &L = ls.l[m];
+        const int s0 = L.ts_off[t], ns = L.ts_off[t + 1] - s0;
+        const int e0 = L.sr_off[s0], ne = L.sr_off[s0 + ns] - e0;
+        const int per = (ne + kTilePix - 1) / kTilePix;
+        const int rb = e0 + threadIdx.x * per, re = min(rb + per, e0 + ne);
+        int cur = -1;
+        int l0 = -1, l1 = -1, l2 = -1, l3 = -1;
+        T w0 = T(0), w1 = T(0), w2 = T(0), w3 = T(0);
+        T *row = nullptr;
+        for (int r = rb; r <= re; ++r) {
+            const int sl = (r < re) ? int(L.sr_slot[r]) : -2;
+            if (sl != cur) {
+                if (cur >= 0) {
+                    if (l0 >= 0) atomic_add(&row[l0], w0);
+                    if (l1 >= 0) atomic_add(&row[l1], w1);
+                    if (l2 >= 0) atomic_add(&row[l2], w2);
+                    if (l3 >= 0) atomic_add(&row[l3], w3);
+                }
+                if (sl < 0) break;
+                cur = sl;
+                row = L.V0 + (size_t)L.ts_vid[s0 + sl] * L.ld;
+                l0 = l1 = l2 = l3 = -1;
+            }
+            const int lb = labs[L.sr_pix[r]];
+            if (lb < 0 || lb >= C) continue;
+            const T w = L.sr_w[r];
+            if (lb == l0) w0 += w;
+            else if (lb == l1) w1 += w;
+            else if (lb == l2) w2 += w;
+            else if (lb == l3) w3 += w;
+            else if (l0 < 0) { l0 = lb; w0 = w; }
+            else if (l1 < 0) { l1 = lb; w1 = w; }
+            else if (l2 < 0) { l2 = lb; w2 = w; }
+            else if (l3 < 0) { l3 = lb; w3 = w; }
+            else atomic_add(&row[lb], w);
+        }
+    }
+}
+
+// The slice of pixel a from a tile's slot rows staged in LDS, for two
+// lattices of compile-time dimensions DA and DB: the slots and weights of
+// all pairs are loaded first, then every row is read (slots beyond the
+// staged ones from global memory).
+template <typename T, int LMAX, int DA, int DB>
+__device__ __forceinline__ void tile_slice_pixel(const LatSet<T> &ls, size_t a, int C,
+                                                 const T *rows, int ld, const int *base,
+                                                 const int *nin, const int *s0,
+                                                 T (&q)[LMAX]) {
+    int sa[DA + 1], sb[DB + 1];
+    T wa[DA + 1], wb[DB + 1];
+    const LatView<T> &A = ls.l[0];
+    const LatView<T> &B = ls.l[1];
+#pragma unroll
+    for (int k = 0; k <= DA; ++k) {
+        sa[k] = A.tr_slot[a * (DA + 1) + k];
+        wa[k] = A.wg * A.w[a * (DA + 1) + k];
+    }
+#pragma unroll
+    for (int k = 0; k <= DB; ++k) {
+        sb[k] = B.tr_slot[a * (DB + 1) + k];
+        wb[k] = B.wg * B.w[a * (DB + 1) + k];
+    }
+#pragma unroll
+    for (int k = 0; k <= DA; ++k) {
+        if (sa[k] == 0xffff) continue;
+        if (sa[k] < nin[0])
+            axpy_row<LMAX>(q, wa[k], rows + (size_t)(base[0] + sa[k]) * ld, C);
+        else
+            axpy_row<LMAX>(q, wa[k], A.Vf + (size_t)A.ts_vid[s0[0] + sa[k]] * ld, C);
+    }
+#pragma unroll
+    for (int k = 0; k <= DB; ++k) {
+        if (sb[k] == 0xffff) continue;
+        if (sb[k] < nin[1])
+            axpy_row<LMAX>(q, wb[k], rows + (size_t)(base[1] + sb[k]) * ld, C);
+        else
+            axpy_row<LMAX>(q, wb[k], B.Vf + (size_t)B.ts_vid[s0[1] + sb[k]] * ld, C);
+    }
+}
+
+// Slice (raw or QP) of one tile per block, one thread per pixel. The tile's
+// slot rows of every lattice are staged in LDS first (at most `cap` rows;
+// slots beyond them are read from global memory) together with the tile's
+// rows of Y; each pixel then adds its d+1 rows per lattice from LDS, and the
+// results leave through LDS, coalesced.
+template <typename T, int LMAX, int MODE>
+__global__ void __launch_bounds__(kTilePix)
+k_tile_slice(int C, const T *__restrict__ Y, LatSet<T> ls,
+             const int4 *__restrict__ tiles, int cap, T wsum,
+             const T *__restrict__ mu, const T *__restrict__ mabs,
+             const T *__restrict__ r, T *__restrict__ out) {
+    using V = typename Vec16<T>::type;
+    constexpr int vw = Vec16<T>::n;
+    extern __shared__ __align__(16) unsigned char tile_smem[];
+    const int LS = C | 1;
+    T *py = reinterpret_cast<T *>(tile_smem);   // kTilePix x LS: Y, then out
+    T *rows = py + kTilePix * LS;                // cap x ld
+    rows = reinterpret_cast<T *>((reinterpret_cast<uintptr_t>(rows) + 15) & ~uintptr_t(15));
+    __shared__ T smu[MODE == kSliceQP ? LMAX * LMAX : 1];
+    if (MODE == kSliceQP)
+        for (int i = threadIdx.x; i < C * C; i += kTilePix)
+            smu[(i / C) * LMAX + (i % C)] = mu[i];
+    const int t = xcd_block(blockIdx.x, gridDim.x);
+    const int4 td = tiles[t];
+    const int ld = ls.l[0].ld;
+    int base[DCRF_MAXK], nin[DCRF_MAXK], s0[DCRF_MAXK];
+    int used = 0;
+    for (int m = 0; m < ls.nk; ++m) {
+        const LatView<T> &L = ls.l[m];
+        s0[m] = L.ts_off[t];
+        const int ns = L.ts_off[t + 1] - s0[m];
+        nin[m] = min(ns, cap - used);
+        base[m] = used;
+        used += nin[m];
+    }
+    {
+        const int G = ld / vw;
+        for (int m = 0; m < ls.nk; ++m) {
+            const LatView<T> &L = ls.l[m];
+            for (int idx = threadIdx.x; idx < nin[m] * G; idx += kTilePix) {
+                const int sl = idx / G, g = idx - (idx / G) * G;
+                reinterpret_cast<V *>(rows)[(size_t)(base[m] + sl) * G + g] =
+                    reinterpret_cast<const V *>(L.Vf)[(size_t)L.ts_vid[s0[m] + sl] * G + g];
+            }
+        }
+    }
+    tile2_in<T, kTilePix>(Y, td, C, py, LS);
+    __syncthreads();
+    const int i = threadIdx.x / kTileW, px = threadIdx.x % kTileW;
+    const bool act = i < td.z && px < td.w;
+    if (act) {
+        const size_t a = (size_t)td.x + (size_t)i * td.y + px;
+        T *prow = py + threadIdx.x * LS;
+        T q[LMAX];
+#pragma unroll
+        for (int j = 0; j < LMAX; ++j) q[j] = T(0);
+        if (ls.shape52) {
+            tile_slice_pixel<T, LMAX, 5, 2>(ls, a, C, rows, ld, base, nin, s0, q);
+        } else {
+            for (int m = 0; m < ls.nk; ++m) {
+                const LatView<T> &L = ls.l[m];
+                const int D1 = L.d + 1;
+                for (int k = 0; k < D1; ++k) {
+                    const int sl = L.tr_slot[a * D1 + k];
+                    if (sl == 0xffff) continue;
+                    const T w = L.wg * L.w[a * D1 + k];
+                    if (sl < nin[m])
+                        axpy_row<LMAX>(q, w, rows + (size_t)(base[m] + sl) * ld, C);
+                    else
+                        axpy_row<LMAX>(q, w, L.Vf + (size_t)L.ts_vid[s0[m] + sl] * ld, C);
+                }
+            }
+        }
+        T y[LMAX];
+#pragma unroll
+        for (int j = 0; j < LMAX; ++j) y[j] = (j < C) ? prow[j] : T(0);
+#pragma unroll
+        for (int j = 0; j < LMAX; ++j) q[j] -= wsum * y[j];
+        if (MODE == kSliceRaw) {
+#pragma unroll
+            for (int j = 0; j < LMAX; ++j)
+                if (j < C) prow[j] = q[j];
+        } else {
+            const T ra = r[a];
+#pragma unroll
+            for (int i2 = 0; i2 < LMAX; ++i2) {
+                if (i2 < C) {
+                    T p = T(0);
+#pragma unroll
+                    for (int j = 0; j < LMAX; ++j)
+                        if (j < C) p += smu[i2 * LMAX + j] * q[j];
+                    prow[i2] = p + mabs[i2] * ra * y[i2];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    tile2_out<T, kTilePix>(out, td, C, py, LS);
+}
+
 int row_grid(dcrf_ctx *ctx, int tp) {
     return std::max(1, std::min(ceil_div(ctx->N, tp), 4096));
 }
@@ -425,16 +713,69 @@ void exact_t(dcrf_ctx *ctx, const T *in, T *out, int C) {
     DCRF_CHECK_LAUNCH();
 }
 
+constexpr size_t kTileLds = 56 * 1024;   // dynamic LDS of the tile slices
+
+// LDS of k_tile_splat: the tile's values (kTilePix rows of ld), then the
+// partial rows of one lattice's slots (cap rows of ld)
+constexpr size_t kSplatLds = 60 * 1024;
+template <typename T>
+int tile_splat_cap(int C) {
+    const size_t row = (size_t)row_stride(C, sizeof(T)) * sizeof(T);
+    return int(kSplatLds / row) - kTilePix;
+}
+template <typename T>
+size_t tile_splat_lds(int C) {
+    return (size_t)(kTilePix + tile_splat_cap<T>(C)) * row_stride(C, sizeof(T)) * sizeof(T);
+}
+
+// whether the per-tile kernels serve C channels: each lattice's slots of a
+// tile must fit the splat's LDS partial rows
+template <typename T>
+bool use_tiles(const dcrf_ctx *ctx, int C) {
+    if (!(ctx->tile_mode && ctx->ntiles > 0 && C <= kRowMaxC)) return false;
+    const int cap = tile_splat_cap<T>(C);
+    for (int m = 0; m < ctx->nk; ++m)
+        if (ctx->lat[m].max_tile_slots > cap) return false;
+    // the slice stages the tile's pixel rows and at least one slot row
+    const size_t slice = (size_t)kTilePix * (C | 1) * sizeof(T) + 16 +
+                         (size_t)row_stride(C, sizeof(T)) * sizeof(T);
+    return cap > 0 && slice <= kTileLds;
+}
+
+// splat of the dense N x C input into V0 of every lattice of ls
+template <typename T>
+void splat_set(dcrf_ctx *ctx, const LatSet<T> &ls, const T *in, int C) {
+    const hipStream_t s = ctx->stream;
+    ProfScope ps(ctx, PROF_SPLAT);
+    if (use_tiles<T>(ctx, C)) {
+        const int ld = row_stride(C, sizeof(T));
+        ctx->splatP.ensure((size_t)std::max<long long>(ls.soff[ls.nk], 1) * ld * sizeof(T),
+                           s);
+        const int cap = tile_splat_cap<T>(C);
+        DCRF_DISPATCH_ROWS(C, hipLaunchKernelGGL((k_tile_splat<T, LMAX>),
+                                                 dim3(ctx->ntiles), dim3(kTilePix),
+                                                 tile_splat_lds<T>(C), s, C, ld, in, ls,
+                                                 ctx->tiles.as<int4>(),
+                                                 ctx->splatP.as<T>(), cap));
+        const long long total = ls.off[ls.nk] / Vec16<T>::n;
+        if (total > 0)
+            hipLaunchKernelGGL((k_vertex_gather<T>), dim3(ceil_div(total, 256)), dim3(256),
+                               0, s, ls, ctx->splatP.as<T>(), total);
+        DCRF_CHECK_LAUNCH();
+        return;
+    }
+    const long long total = ls.coff[ls.nk];
+    if (total == 0) return;
+    hipLaunchKernelGGL((k_splat_gather<T>), dim3(ceil_div(total, 256)), dim3(256), 0, s,
+                       C, in, ls);
+    DCRF_CHECK_LAUNCH();
+}
+
 template <typename T>
 void splat_dense_t(dcrf_ctx *ctx, const T *in, int C) {
     ensure_vertex_buffers(ctx, C);
     LatSet<T> ls = make_lat_set<T>(ctx, C);
-    const long long total = ls.coff[ls.nk];
-    if (total == 0) return;
-    ProfScope ps(ctx, PROF_SPLAT);
-    hipLaunchKernelGGL((k_splat_gather<T>), dim3(ceil_div(total, 256)), dim3(256),
-                       0, ctx->stream, C, in, ls);
-    DCRF_CHECK_LAUNCH();
+    splat_set<T>(ctx, ls, in, C);
 }
 
 template <typename T>
@@ -442,9 +783,15 @@ void splat_labels_t(dcrf_ctx *ctx, const int32_t *labels, int L) {
     if (L > kLabelBins) fail(DCRF_EUNSUPPORTED, "more than 256 labels");
     ensure_vertex_buffers(ctx, L);
     LatSet<T> ls = make_lat_set<T>(ctx, L);
+    ProfScope ps(ctx, PROF_SPLAT_LABELS);
+    if (use_tiles<T>(ctx, 1)) {
+        hipLaunchKernelGGL((k_tile_labels<T>), dim3(ctx->ntiles), dim3(kTilePix), 0,
+                           ctx->stream, L, labels, ls, ctx->tiles.as<int4>());
+        DCRF_CHECK_LAUNCH();
+        return;
+    }
     const long long total = ls.choff[ls.nk];
     if (total == 0) return;
-    ProfScope ps(ctx, PROF_SPLAT_LABELS);
     hipLaunchKernelGGL((k_splat_labels_chunks<T>), dim3(ceil_div(total, 4)),
                        dim3(256), 0, ctx->stream, L, labels, ls);
     DCRF_CHECK_LAUNCH();
@@ -522,15 +869,43 @@ void blur_all_t(dcrf_ctx *ctx, int C, bool adjoint) {
     blur_launch<T>(ctx, ls, 0, adjoint);
 }
 
+// LDS rows for the slot rows of one tile in the tile slices
 template <typename T>
-void slice_t(dcrf_ctx *ctx, const T *Y, const T *pre, int C, const T *mu,
-             const T *mabs, T *out, bool qp) {
+int tile_slice_cap(const dcrf_ctx *ctx, const LatSet<T> &ls, int first, int C) {
+    int mx = 0;
+    for (int m = 0; m < ls.nk; ++m) mx += ctx->lat[first + m].max_tile_slots;
+    const int ld = row_stride(C, sizeof(T));
+    const size_t pix = (size_t)kTilePix * (C | 1) * sizeof(T) + 16;
+    const size_t room = kTileLds > pix ? kTileLds - pix : 0;
+    return std::max(1, std::min<int>(mx, int(room / (ld * sizeof(T)))));
+}
+
+template <typename T>
+void slice_set(dcrf_ctx *ctx, const LatSet<T> &ls, int first, const T *Y,
+               const T *pre, int C, T wsum, const T *mu, const T *mabs, T *out,
+               bool qp) {
     const hipStream_t s = ctx->stream;
     const int N = ctx->N;
-    LatSet<T> ls = make_lat_set<T>(ctx, C);
-    const T wsum = T(ctx->wsum);
     const T *r = ctx->r.as<T>();
     constexpr int TP = RowTile<T>::kPix;
+    if (!pre && use_tiles<T>(ctx, C)) {
+        ProfScope ps(ctx, qp ? PROF_SLICE_QP : PROF_SLICE);
+        const int cap = tile_slice_cap<T>(ctx, ls, first, C);
+        const size_t lds = (size_t)kTilePix * (C | 1) * sizeof(T) + 16 +
+                           (size_t)cap * row_stride(C, sizeof(T)) * sizeof(T);
+        DCRF_DISPATCH_ROWS(C, {
+            if (qp)
+                hipLaunchKernelGGL((k_tile_slice<T, LMAX, kSliceQP>), dim3(ctx->ntiles),
+                                   dim3(kTilePix), lds, s, C, Y, ls,
+                                   ctx->tiles.as<int4>(), cap, wsum, mu, mabs, r, out);
+            else
+                hipLaunchKernelGGL((k_tile_slice<T, LMAX, kSliceRaw>), dim3(ctx->ntiles),
+                                   dim3(kTilePix), lds, s, C, Y, ls,
+                                   ctx->tiles.as<int4>(), cap, wsum, mu, mabs, r, out);
+        });
+        DCRF_CHECK_LAUNCH();
+        return;
+    }
     if (C <= kRowMaxC) {
         ProfScope ps(ctx, qp ? PROF_SLICE_QP : PROF_SLICE);
         DCRF_DISPATCH_ROWS(C, {
@@ -556,6 +931,13 @@ void slice_t(dcrf_ctx *ctx, const T *Y, const T *pre, int C, const T *mu,
     hipLaunchKernelGGL((k_slice_raw_flat<T>), dim3(ceil_div((long long)N * C, 256)),
                        dim3(256), 0, s, N, C, Y, out, ls, wsum);
     DCRF_CHECK_LAUNCH();
+}
+
+template <typename T>
+void slice_t(dcrf_ctx *ctx, const T *Y, const T *pre, int C, const T *mu,
+             const T *mabs, T *out, bool qp) {
+    const LatSet<T> ls = make_lat_set<T>(ctx, C);
+    slice_set<T>(ctx, ls, 0, Y, pre, C, T(ctx->wsum), mu, mabs, out, qp);
 }
 
 template <typename T>
@@ -585,24 +967,12 @@ void filter_kernel_t(dcrf_ctx *ctx, int m, const T *in, T *out, int C,
     ls.coff[1] = all.coff[m + 1] - all.coff[m];
     ls.eoff[1] = all.eoff[m + 1] - all.eoff[m];
     ls.choff[1] = all.choff[m + 1] - all.choff[m];
+    ls.soff[1] = all.soff[m + 1] - all.soff[m];
     ls.shape52 = 0;
-    if (ls.coff[1] > 0)
-        hipLaunchKernelGGL((k_splat_gather<T>), dim3(ceil_div(ls.coff[1], 256)),
-                           dim3(256), 0, s, C, in, ls);
+    (void)s;
+    splat_set<T>(ctx, ls, in, C);
     blur_launch<T>(ctx, ls, m, adjoint);
-    const int N = ctx->N;
-    constexpr int TP = RowTile<T>::kPix;
-    if (C <= kRowMaxC) {
-        DCRF_DISPATCH_ROWS(C, hipLaunchKernelGGL((k_slice_rows<T, LMAX, kSliceRaw>),
-                                                 dim3(row_grid(ctx, TP)), dim3(TP),
-                                                 0, s, N, C, in, nullptr, ls, T(0),
-                                                 nullptr, nullptr, nullptr, out));
-    } else {
-        hipLaunchKernelGGL((k_slice_raw_flat<T>),
-                           dim3(ceil_div((long long)N * C, 256)), dim3(256), 0, s,
-                           N, C, in, out, ls, T(0));
-    }
-    DCRF_CHECK_LAUNCH();
+    slice_set<T>(ctx, ls, m, in, nullptr, C, T(0), nullptr, nullptr, out, false);
 }
 
 }  // namespace

@@ -40,7 +40,7 @@ __device__ int block_exclusive_scan(int v, int *lds, int &total) {
     return incl - v;
 }
 
-__global__ void __launch_bounds__(kScanThreads)
+[[maybe_unused]] __global__ void __launch_bounds__(kScanThreads)
 k_count_occupied(const uint64_t *__restrict__ hkeys, size_t cap,
                  int *__restrict__ tile_counts) {
     __shared__ int lds[kScanThreads];
@@ -69,7 +69,7 @@ k_scan_tiles(int *__restrict__ tile_counts, int ntiles) {
     if (threadIdx.x == 0) tile_counts[ntiles] = carry;
 }
 
-__global__ void __launch_bounds__(kScanThreads)
+[[maybe_unused]] __global__ void __launch_bounds__(kScanThreads)
 k_assign_ids(const uint64_t *__restrict__ hkeys, size_t cap,
              const int *__restrict__ tile_offsets, int *__restrict__ slot_vid,
              uint64_t *__restrict__ vkeys) {
@@ -130,7 +130,7 @@ k_scan_apply(const int *__restrict__ in, int n, const int *__restrict__ tile_off
 
 // exclusive scan of n device ints into out (n + 1 entries) with the tile
 // counts kept in the context scratch (sized for the largest hash table)
-void scan_ints(dcrf_ctx *ctx, const int *in, int n, int *out) {
+[[maybe_unused]] void scan_ints(dcrf_ctx *ctx, const int *in, int n, int *out) {
     const hipStream_t s = ctx->stream;
     const int ntiles = std::max(1, ceil_div(n, kScanTile));
     int *tiles = reinterpret_cast<int *>(ctx->scratch.as<char>() + 64);

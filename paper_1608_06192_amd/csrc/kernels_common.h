@@ -21,6 +21,12 @@ struct LatView {
     T wg;                // w_m * gamma_m
     const int32_t *gt;   // grouped-blur path table of the direction in use
     int ngrp;            // blur launches of this lattice
+    // per-tile vertex slots
+    const int32_t *ts_off, *ts_vid, *sr_off, *vs_off, *vs_slot;
+    const uint16_t *tr_slot, *sr_slot;
+    const uint8_t *sr_pix;
+    const T *sr_w;
+    int nslots;
 };
 
 template <typename T>
@@ -30,6 +36,7 @@ struct LatSet {
     long long coff[DCRF_MAXK + 1];  // prefix sums of nchunks_m * C (splat)
     long long eoff[DCRF_MAXK + 1];  // prefix sums of the entries
     long long choff[DCRF_MAXK + 1]; // prefix sums of nchunks_m (label splat)
+    long long soff[DCRF_MAXK + 1];  // prefix sums of nslots_m (tile splat)
     int nk;
     int shape52;                    // two lattices with d = 5 and d = 2
 };
@@ -52,6 +59,7 @@ inline LatSet<T> make_lat_set(dcrf_ctx *ctx, int C) {
     s.coff[0] = 0;
     s.eoff[0] = 0;
     s.choff[0] = 0;
+    s.soff[0] = 0;
     const int ld = row_stride(C, sizeof(T));
     for (int m = 0; m < ctx->nk; ++m) {
         Lattice &L = ctx->lat[m];
@@ -66,6 +74,16 @@ inline LatSet<T> make_lat_set(dcrf_ctx *ctx, int C) {
         v.ngrp = nl;
         v.Vf = L.V[final_buffer_after(nl)].as<T>();
         v.gt = nullptr;
+        v.ts_off = L.ts_off.as<int32_t>();
+        v.ts_vid = L.ts_vid.as<int32_t>();
+        v.sr_off = L.sr_off.as<int32_t>();
+        v.vs_off = L.vs_off.as<int32_t>();
+        v.vs_slot = L.vs_slot.as<int32_t>();
+        v.tr_slot = L.tr_slot.as<uint16_t>();
+        v.sr_slot = L.sr_slot.as<uint16_t>();
+        v.sr_pix = L.sr_pix.as<uint8_t>();
+        v.sr_w = L.sr_w.as<T>();
+        v.nslots = L.nslots;
         v.chunks = L.chunks.as<int4>();
         v.ent_pix = L.ent_pix.as<int32_t>();
         v.ent_w = L.ent_w.as<T>();
@@ -79,6 +97,7 @@ inline LatSet<T> make_lat_set(dcrf_ctx *ctx, int C) {
         s.coff[m + 1] = s.coff[m] + (long long)L.nchunks * C;
         s.eoff[m + 1] = s.eoff[m] + (long long)L.nent;
         s.choff[m + 1] = s.choff[m] + (long long)L.nchunks;
+        s.soff[m + 1] = s.soff[m] + (long long)L.nslots;
     }
     s.shape52 = (ctx->nk == 2 && ctx->lat[0].d == 5 && ctx->lat[1].d == 2) ? 1 : 0;
     return s;
@@ -145,6 +164,42 @@ __device__ __forceinline__ int tile_range(const int *__restrict__ seg, int nimg,
     }
     lo = hi = 0;
     return -1;
+}
+
+// Copy a 2-D pixel tile of a pixel-major N x C array to or from LDS rows
+// of stride LS (pixel (i, px) of the tile at row i * kTileW + px). td holds
+// the tile's first pixel row, the image's row stride in pixels, and the
+// tile's rows and columns. Consecutive threads move consecutive elements of
+// a tile row, which is one contiguous range in global memory. Every thread
+// of the block must call these; the caller synchronises.
+template <typename T, int NT>
+__device__ __forceinline__ void tile2_in(const T *__restrict__ g, int4 td, int C,
+                                         T *lds, int LS) {
+    const int wC = td.w * C;
+    const float inv = 1.0f / float(C);
+    for (int i = 0; i < td.z; ++i) {
+        const T *src = g + ((size_t)td.x + (size_t)i * td.y) * C;
+        T *dst = lds + i * kTileW * LS;
+        for (int k = threadIdx.x; k < wC; k += NT) {
+            const int px = int((float(k) + 0.5f) * inv);
+            dst[px * LS + (k - px * C)] = src[k];
+        }
+    }
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void tile2_out(T *__restrict__ g, int4 td, int C,
+                                          const T *lds, int LS) {
+    const int wC = td.w * C;
+    const float inv = 1.0f / float(C);
+    for (int i = 0; i < td.z; ++i) {
+        T *dst = g + ((size_t)td.x + (size_t)i * td.y) * C;
+        const T *src = lds + i * kTileW * LS;
+        for (int k = threadIdx.x; k < wC; k += NT) {
+            const int px = int((float(k) + 0.5f) * inv);
+            dst[k] = src[px * LS + (k - px * C)];
+        }
+    }
 }
 
 // Largest channel count handled with per-thread register rows.

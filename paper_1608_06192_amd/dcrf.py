@@ -45,7 +45,7 @@ class dcrf_tune(ctypes.Structure):
     _fields_ = [("splat_chunk", ctypes.c_int),
                 ("blur_vectors_per_thread", ctypes.c_int),
                 ("blur_block", ctypes.c_int), ("blur_group", ctypes.c_int),
-                ("ms", ctypes.c_double)]
+                ("tiles", ctypes.c_int), ("ms", ctypes.c_double)]
 
 
 # name -> (restype, argtypes); mirrors include/dcrf.h
@@ -203,9 +203,9 @@ class Context:
         return [packed[a:b] for a, b in self.seg]
 
     def set_tune(self, splat_chunk=64, blur_vectors_per_thread=1,
-                 blur_block=256, blur_group=2, **_):
+                 blur_block=256, blur_group=2, tiles=0, **_):
         t = dcrf_tune(splat_chunk, blur_vectors_per_thread, blur_block,
-                      blur_group, 0.0)
+                      blur_group, tiles, 0.0)
         self._stream()
         self._check(_lib.dcrf_set_tune(self._h, ctypes.byref(t)))
 
@@ -215,7 +215,8 @@ class Context:
         self._check(_lib.dcrf_autotune(self._h, L, reps, ctypes.byref(t)))
         return dict(splat_chunk=t.splat_chunk,
                     blur_vectors_per_thread=t.blur_vectors_per_thread,
-                    blur_block=t.blur_block, blur_group=t.blur_group, ms=t.ms)
+                    blur_block=t.blur_block, blur_group=t.blur_group,
+                    tiles=t.tiles, ms=t.ms)
 
     def set_weights(self, w):
         arr = (ctypes.c_double * len(w))(*[float(v) for v in w])

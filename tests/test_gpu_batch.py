@@ -174,6 +174,7 @@ def test_autotune_keeps_results():
     assert tune["splat_chunk"] in (32, 64, 128)
     assert tune["blur_vectors_per_thread"] in (1, 2)
     assert tune["blur_group"] in (1, 2, 3)
+    assert tune["tiles"] in (0, 1)
     assert tune["blur_block"] in (128, 256)
     after = ctx.filter(Y).cpu().numpy()
     assert np.abs(after - before).max() <= 1e-12 * np.abs(before).max()

@@ -336,6 +336,10 @@ def test_errors_are_reported_not_fatal():
     dict(splat_chunk=128, blur_vectors_per_thread=2, blur_block=128, blur_group=2),
     dict(splat_chunk=256, blur_vectors_per_thread=4, blur_block=256, blur_group=3),
     dict(splat_chunk=32, blur_vectors_per_thread=3, blur_block=256, blur_group=3),
+    dict(splat_chunk=64, blur_vectors_per_thread=1, blur_block=256, blur_group=2,
+         tiles=1),
+    dict(splat_chunk=64, blur_vectors_per_thread=2, blur_block=128, blur_group=1,
+         tiles=1),
 ])
 @pytest.mark.parametrize("name,dtype,rtol", [("rect_32x24_L3", torch.float64, 1e-11),
                                               ("voronoi_320x213_L21", torch.float32, 1e-5)])
@@ -354,11 +358,12 @@ def test_launch_shapes_keep_filter_parity(tune, name, dtype, rtol):
         assert (np.abs(got - ref) <= filter_bound(model, Y, rtol)).all(), adjoint
 
 
-def test_grouped_blur_fw_fp64_matches_oracle():
+@pytest.mark.parametrize("tiles", [0, 1])
+def test_grouped_blur_fw_fp64_matches_oracle(tiles):
     im = synth.make("rect_32x24_L3")
     ctx = gpu_ctx(im, torch.float64)
     ctx.set_tune(splat_chunk=32, blur_vectors_per_thread=2, blur_block=128,
-                 blur_group=3)
+                 blur_group=3, tiles=tiles)
     model = O.Model(im.H, im.W, im.rgb, KERNELS)
     mu = synth.potts(3)
     qp = O.QP(model, im.unary, mu)
