@@ -262,11 +262,14 @@ int dcrf_project_simplex(dcrf_ctx *ctx, const void *v, int L, void *y);
  * reverse sweep over checkpoints (the step size alpha_t = -b1 / (2 a2) of the
  * exact line search is differentiated where it is interior to (0, 1); a
  * clipped step and the conditional gradient s_t are piecewise constant).
- * Lattice filter mode only (DCRF_EUNSUPPORTED in exact mode); L <= 256.
+ * Lattice filter mode only (DCRF_EUNSUPPORTED in exact mode); L <= 32.
  *
  * *bytes (host) = the size of the checkpoint buffer for (L, iters) at the
- * context's image and precision: y_t (T x N x L values), s_t (T x N int32)
- * and four doubles per iteration and image, each part 256-byte aligned. */
+ * context's image and precision: y_t and P_t = (Psi + D) y_t (T x N x L
+ * values each), s_t (T x N int32), per lattice the blurred vertex values of
+ * y_0 and of each one-hot s_t (T + 1 blocks of sum_m M_m x ld values, ld = L
+ * rounded up to 16 bytes), and four doubles per iteration and image, each
+ * part 256-byte aligned. L <= 32. */
 int dcrf_fw_saved_size(dcrf_ctx *ctx, int L, int iters, size_t *bytes);
 
 /* Forward: unary (dev N x L), mu (dev L x L); y_out (dev N x L) = y_T;
@@ -280,8 +283,8 @@ int dcrf_fw_forward(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
  * batch, image-major) is not NULL,
  * dl/dw_m for every kernel. unary, mu, L, iters and saved must be those of
  * the forward call, and neither the image nor the weights may have changed
- * in between. Waits for the stream (the step adjoints are scalars reduced on
- * the device and read back once per iteration). */
+ * in between. The step adjoints are formed on the device; the call waits
+ * for the stream once, at its end. */
 int dcrf_fw_backward(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
                      int iters, const void *saved, const void *grad_y,
                      void *grad_unary, double *grad_w);

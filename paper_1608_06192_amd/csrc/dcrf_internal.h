@@ -275,13 +275,18 @@ void round_labels(dcrf_ctx *ctx, const void *y, int L, int32_t *labels);
 double energy(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
               const int32_t *labels);
 
-// Checkpoints of a Frank-Wolfe forward for the reverse sweep: y_t (iters x
-// N x L), s_t (iters x N labels) and per iteration kFWStats doubles
+// Checkpoints of a Frank-Wolfe forward for the reverse sweep: y_t and
+// P_t = (Psi + D) y_t (iters x N x L each), s_t (iters x N labels), per
+// lattice the blurred vertex values of y_0 and of the one-hot s_t
+// ((iters + 1) blocks of sum_m M_m x ld values, block 0 for y_0, block t+1
+// for s_t), and per iteration and image kFWStats doubles
 // (alpha, a2, b1, interior).
 constexpr int kFWStats = 4;
 struct FWCheckpoint {
     void *y;
+    void *P;
     int32_t *s;
+    void *V;
     double *stats;
 };
 void frank_wolfe_checkpointed(dcrf_ctx *ctx, const void *unary, const void *mu,

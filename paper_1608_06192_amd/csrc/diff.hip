@@ -3,9 +3,10 @@
 // weights w_m, for an upstream gradient dl/dy_T.
 //
 // Forward: y_0 = softmax(-phi), then T iterations of the Frank-Wolfe kernels,
-// checkpointing y_t, the conditional gradient s_t and the step's quadratic
-// (alpha_t, a2, b1, interior) for every t. P_t = Q y_t and S_t = Q s_t are
-// recomputed in the reverse sweep rather than stored.
+// checkpointing y_t, P_t = Q y_t, the conditional gradient s_t, the step's
+// quadratic (alpha_t, a2, b1, interior) and, per lattice, the blurred vertex
+// values of y_0 and of every one-hot s_t (a few MB per iteration), so that
+// the reverse sweep needs no filter of its own until its last step.
 //
 // Reverse sweep, for t = T-1 .. 0 (ybar = dl/dy_{t+1}, Pbar = dl/dP_{t+1}):
 //   abar = <ybar, s - y> + <Pbar, S - P>
@@ -20,13 +21,27 @@
 // transposed lattice filter: blur directions reversed), c = phi - d gives
 // phibar = cbar, and y_0 = softmax(-phi) the softmax backward.
 // The weights enter Q (through K' and d) and c (through d):
-//   d<Zbar, Q X>/dw_m = <Zbar mu, (K~_m - I) X> + sum_a rho_a (K~_m 1 - 1)_a,
-//   rho_a = sum_i Zbar_a(i) X_a(i) sum_j |mu_ij|,
+//   d<Zbar, Q X>/dw_m = <Zbar mu, (K~_m - I) X> + sum_a rho_a kappa_m(a),
+//   rho_a = sum_i Zbar_a(i) X_a(i) sum_j |mu_ij|,  kappa_m = K~_m 1 - 1,
 // with K~_m the lattice filter of kernel m alone.
+//
+// How it runs: per iteration, k_sweep_a slices K~_m s_t of every lattice
+// from the saved vertex values, forms S_t = Q s_t, and reduces per tile the
+// pieces of abar and of the weight gradient; since Sbar is linear in
+// (alpha, Bbar, Dbar), <Sbar mu, (K~_m - I) s> and the rho terms split into
+// three scalar products each. k_step_adjoint (one block per image) turns
+// them into the step's adjoints and accumulates the weight gradient, on the
+// device; k_sweep_b updates ybar and Pbar. No host synchronisation happens
+// inside the sweep. cbar is not carried per iteration: with the recurrence
+// y_t = (1 - alpha_{t-1}) y_{t-1} + alpha_{t-1} s_{t-1},
+//   sum_t cybar_t y_t = a_0 y_0 + sum_k b_k s_k,
+//   a_0 = sum_t cybar_t prod_{u<t} (1 - alpha_u),
+//   b_k = alpha_k sum_{t>k} cybar_t prod_{k<u<t} (1 - alpha_u),
+// so the last kernel rebuilds cbar from y_0 and the saved labels.
 //
 // For a context that holds a batch of images every image has its own step
 // sizes, step adjoints and weight gradient: the reductions are per tile of
-// one image (whole pixels per block) and summed per image on the host.
+// one image.
 
 #include <algorithm>
 #include <cmath>
@@ -39,7 +54,7 @@ namespace dcrf {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kGroups = 8;   // pixel groups (kThreads / L pixels) per tile
+constexpr int kNP = 1 + 6 * DCRF_MAXK;   // partial sums per tile of k_sweep_a
 
 template <typename T>
 __global__ void k_softmax_neg(const int *__restrict__ seg, int nimg, int L,
@@ -65,133 +80,10 @@ __global__ void k_mabs(int L, const T *__restrict__ mu, T *__restrict__ mabs) {
     mabs[i] = s;
 }
 
-// c = phi - d, d_a(i) = mabs_i r_a
-template <typename T>
-__global__ void k_c(int N, int L, const T *__restrict__ phi,
-                    const T *__restrict__ r, const T *__restrict__ mabs,
-                    T *__restrict__ c) {
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (size_t)N * L) return;
-    const int a = int(e / L);
-    c[e] = phi[e] - mabs[e - (size_t)a * L] * r[a];
-}
-
-template <typename T>
-__global__ void k_onehot_d(int N, int L, const int32_t *__restrict__ s,
-                           T *__restrict__ out) {
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (size_t)N * L) return;
-    const int a = int(e / L);
-    out[e] = T(int(e - (size_t)a * L) == s[a] ? 1 : 0);
-}
-
 template <typename T>
 __global__ void k_fill_d(size_t n, T *__restrict__ p, T v) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
-}
-
-template <int NV>
-__device__ __forceinline__ void bsum(double (&v)[NV], double *lds) {
-    block_sum<NV, kThreads>(v, lds);
-}
-
-// Pixel rows [lo, hi) of this block's tile (kGroups groups of ppb pixels);
-// returns the image.
-__device__ __forceinline__ int diff_tile(const int *seg, int nimg, int ppb,
-                                         int &lo, int &hi) {
-    return tile_range(seg, nimg, ppb * kGroups, blockIdx.x, lo, hi);
-}
-
-// per-tile partial sums of abar = <ybar, s - y> + <Pbar, S - P>
-template <typename T>
-__global__ void __launch_bounds__(kThreads)
-k_abar(const int *__restrict__ seg, int nimg, int L, const T *__restrict__ ybar,
-       const T *__restrict__ y, const int32_t *__restrict__ s,
-       const T *__restrict__ Pbar, const T *__restrict__ S,
-       const T *__restrict__ P, double *__restrict__ part) {
-    __shared__ double red[kThreads];
-    double acc[1] = {0.0};
-    int lo, hi;
-    diff_tile(seg, nimg, kThreads / L, lo, hi);
-    for (size_t e = (size_t)lo * L + threadIdx.x; e < (size_t)hi * L; e += kThreads) {
-        const int a = int(e / L);
-        const int i = int(e - (size_t)a * L);
-        const double si = (i == s[a]) ? 1.0 : 0.0;
-        acc[0] += double(ybar[e]) * (si - double(y[e])) +
-                  double(Pbar[e]) * (double(S[e]) - double(P[e]));
-    }
-    bsum<1>(acc, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
-}
-
-struct StepBar {
-    double al, Abar, Bbar, Cbar, Dbar, cybar, csbar;
-};
-
-template <typename T>
-struct UpdArgs {
-    const int *seg;
-    int nimg, L, nk;
-    T *ybar, *Pbar, *cbar;
-    const T *y, *P, *S, *c;
-    const int32_t *s;
-    const T *Ks[DCRF_MAXK];
-    const T *mu, *mabs;
-    double *rho;
-    double *part;    // per tile: nk partial sums of <Sbar mu, K~_m s - s>
-    const StepBar *sb;   // per image
-};
-
-// One reverse step (see the file comment), whole pixels per block so that
-// (Sbar mu) can be formed from the pixel's row in LDS.
-template <typename T>
-__global__ void __launch_bounds__(kThreads)
-k_diff_update(UpdArgs<T> A) {
-    __shared__ double rowS[kThreads];
-    __shared__ double red[DCRF_MAXK * kThreads];
-    const int L = A.L;
-    const int ppb = kThreads / L;
-    const int t = threadIdx.x;
-    const int lp = t / L;
-    const int i = t - lp * L;
-    double acc[DCRF_MAXK];
-#pragma unroll
-    for (int m = 0; m < DCRF_MAXK; ++m) acc[m] = 0.0;
-    int lo, hi;
-    const int img = diff_tile(A.seg, A.nimg, ppb, lo, hi);
-    const StepBar b = A.sb[img < 0 ? 0 : img];
-    for (int g0 = lo; g0 < hi; g0 += ppb) {
-        const long long a = (long long)g0 + lp;
-        const bool act = lp < ppb && a < hi;
-        const size_t e = (size_t)a * L + i;
-        double sbar = 0.0;
-        int sa = 0;
-        if (act) {
-            sa = A.s[a];
-            const double si = i == sa ? 1.0 : 0.0;
-            sbar = b.al * double(A.Pbar[e]) + b.Bbar * double(A.y[e]) + b.Dbar * si;
-            rowS[t] = sbar;
-        }
-        __syncthreads();
-        if (act) {
-            const double si = i == sa ? 1.0 : 0.0;
-            double smu = 0.0;   // (Sbar mu)_a(i) = sum_k Sbar_a(k) mu_ki
-            for (int k = 0; k < L; ++k)
-                smu += rowS[lp * L + k] * double(A.mu[(size_t)k * L + i]);
-            for (int m = 0; m < A.nk; ++m)
-                acc[m] += smu * (double(A.Ks[m][e]) - si);
-            if (i == sa) A.rho[a] += sbar * double(A.mabs[i]);
-            const double yv = A.y[e], yb = A.ybar[e], pb = A.Pbar[e];
-            A.ybar[e] = T((1.0 - b.al) * yb + b.Abar * double(A.P[e]) +
-                          b.Bbar * double(A.S[e]) + b.cybar * double(A.c[e]));
-            A.Pbar[e] = T((1.0 - b.al) * pb + b.Abar * yv + b.Cbar * si);
-            A.cbar[e] = T(double(A.cbar[e]) + b.cybar * yv + b.csbar * si);
-        }
-        __syncthreads();
-    }
-    bsum<DCRF_MAXK>(acc, red);
-    if (t < DCRF_MAXK) A.part[(size_t)blockIdx.x * DCRF_MAXK + t] = acc[t];
 }
 
 // Z = X mu, row by row: Z_a(j) = sum_i X_a(i) mu_ij
@@ -218,75 +110,338 @@ k_rowmat(int N, int L, const T *__restrict__ X, const T *__restrict__ mu,
     }
 }
 
+// gamma_m times the slice of lattice m at pixel a (weight 1, no self term)
+template <typename T, int LMAX>
+__device__ __forceinline__ void slice_one(const LatView<T> &Lt, T gam, size_t a, int C,
+                                          T (&q)[LMAX]) {
+#pragma unroll
+    for (int j = 0; j < LMAX; ++j) q[j] = T(0);
+    const int D1 = Lt.d + 1;
+    for (int k = 0; k < D1; ++k) {
+        const int id = Lt.vid[a * D1 + k];
+        if (id >= 0) axpy_row<LMAX>(q, gam * Lt.w[a * D1 + k], Lt.Vf + (size_t)id * Lt.ld, C);
+    }
+}
+
+// out = mu R (out_k = sum_i mu_ki R_i); Potts: sum(R) - R_k
+template <typename T, int LMAX, bool POTTS>
+__device__ __forceinline__ void mu_apply(const T *smu, int C, const T (&R)[LMAX],
+                                         T (&out)[LMAX]) {
+    if (POTTS) {
+        T tot = T(0);
+#pragma unroll
+        for (int i = 0; i < LMAX; ++i) tot += (i < C) ? R[i] : T(0);
+#pragma unroll
+        for (int k = 0; k < LMAX; ++k) out[k] = (k < C) ? tot - R[k] : T(0);
+    } else {
+#pragma unroll
+        for (int k = 0; k < LMAX; ++k) {
+            T acc = T(0);
+#pragma unroll
+            for (int i = 0; i < LMAX; ++i)
+                if (k < C && i < C) acc += smu[k * LMAX + i] * R[i];
+            out[k] = acc;
+        }
+    }
+}
+
+// out = R mu^T (out_i = sum_j mu_ij R_j); Potts: the same as mu R
+template <typename T, int LMAX, bool POTTS>
+__device__ __forceinline__ void mu_apply_t(const T *smu, int C, const T (&R)[LMAX],
+                                           T (&out)[LMAX]) {
+    if (POTTS) {
+        mu_apply<T, LMAX, true>(smu, C, R, out);
+    } else {
+#pragma unroll
+        for (int i = 0; i < LMAX; ++i) {
+            T acc = T(0);
+#pragma unroll
+            for (int j = 0; j < LMAX; ++j)
+                if (i < C && j < C) acc += smu[i * LMAX + j] * R[j];
+            out[i] = acc;
+        }
+    }
+}
+
 template <typename T>
-struct FinArgs {
+struct SweepA {
     const int *seg;
     int nimg, L, nk;
-    const T *ybar, *KtZ, *Z, *Pbar, *y0, *cbar, *r, *mabs;
-    const T *Ky0[DCRF_MAXK];
-    const T *K1[DCRF_MAXK];
-    const double *rho;
-    T *phibar;
-    double *part;   // per tile: nk partial sums
+    const int32_t *s;
+    const T *y, *P, *ybar, *Pbar, *r, *mabs, *mu;
+    const T *kappa1[DCRF_MAXK];   // K~_m 1
+    T w[DCRF_MAXK], gam[DCRF_MAXK], wsum;
+    T *S;
+    double *part;   // per tile: abar, then per kernel X1..X3, Z1..Z3
 };
 
-// The end of the sweep: P_0 = Q y_0, c = phi - d, d's dependence on w, and
-// y_0 = softmax(-phi).
+// Per pixel of one tile: S = Q s from the saved vertex values of the
+// one-hot s, the abar terms and the six weight-gradient pieces per kernel:
+//   X1 = <Pbar mu, R_m>, X2 = <y mu, R_m>, X3 = <s mu, R_m>, R_m = K~_m s - s,
+//   Z1 = Pbar(s) |mu|_s kappa_m, Z2 = y(s) |mu|_s kappa_m, Z3 = |mu|_s kappa_m.
+template <typename T, int LMAX, bool POTTS>
+__global__ void __launch_bounds__(RowTile<T>::kPix)
+k_sweep_a(SweepA<T> A, LatSet<T> ls) {
+    constexpr int TP = RowTile<T>::kPix;
+    __shared__ __align__(16) T lds[TP * (LMAX | 1)];
+    __shared__ T smu[POTTS ? 1 : LMAX * LMAX];
+    __shared__ double red[kNP * TP];
+    const int L = A.L;
+    if (!POTTS) {
+        for (int i = threadIdx.x; i < L * L; i += TP)
+            smu[(i / L) * LMAX + (i % L)] = A.mu[i];
+        __syncthreads();
+    }
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    int lo, hi;
+    tile_range(A.seg, A.nimg, TP, tile, lo, hi);
+    const int np = hi - lo;
+    const size_t a = (size_t)lo + threadIdx.x;
+    const bool act = (int)threadIdx.x < np;
+    double acc[kNP];
+#pragma unroll
+    for (int i = 0; i < kNP; ++i) acc[i] = 0.0;
+    T y[LMAX], pb[LMAX];
+#pragma unroll
+    for (int j = 0; j < LMAX; ++j) y[j] = pb[j] = T(0);
+    tile_load<T, LMAX, TP>(A.y, lo, np, L, lds, y);
+    tile_load<T, LMAX, TP>(A.Pbar, lo, np, L, lds, pb);
+    T ks[LMAX];
+#pragma unroll
+    for (int j = 0; j < LMAX; ++j) ks[j] = T(0);
+    const int sa = act ? A.s[a] : 0;
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < LMAX; ++j)
+            if (j == sa) ks[j] = -A.wsum;
+        double pbs = 0.0, ysa = 0.0;
+#pragma unroll
+        for (int k = 0; k < LMAX; ++k)
+            if (k == sa) pbs = double(pb[k]), ysa = double(y[k]);
+        for (int m = 0; m < A.nk; ++m) {
+            T q[LMAX], t[LMAX];
+            slice_one<T, LMAX>(ls.l[m], A.gam[m], a, L, q);
+#pragma unroll
+            for (int j = 0; j < LMAX; ++j) ks[j] += A.w[m] * q[j];
+#pragma unroll
+            for (int j = 0; j < LMAX; ++j)
+                if (j == sa) q[j] -= T(1);
+            mu_apply<T, LMAX, POTTS>(smu, L, q, t);
+            double x1 = 0.0, x2 = 0.0, x3 = 0.0;
+#pragma unroll
+            for (int k = 0; k < LMAX; ++k) {
+                if (k < L) {
+                    x1 += double(pb[k]) * double(t[k]);
+                    x2 += double(y[k]) * double(t[k]);
+                    if (k == sa) x3 += double(t[k]);
+                }
+            }
+            const double mk = double(A.mabs[sa]) * (double(A.kappa1[m][a]) - 1.0);
+            acc[1 + 6 * m + 0] += x1;
+            acc[1 + 6 * m + 1] += x2;
+            acc[1 + 6 * m + 2] += x3;
+            acc[1 + 6 * m + 3] += pbs * mk;
+            acc[1 + 6 * m + 4] += ysa * mk;
+            acc[1 + 6 * m + 5] += mk;
+        }
+    }
+    // S = (K's) mu^T + d * s
+    T S[LMAX];
+    {
+        T t[LMAX];
+        mu_apply_t<T, LMAX, POTTS>(smu, L, ks, t);
+        const T dself = act ? A.mabs[sa] * A.r[a] : T(0);
+#pragma unroll
+        for (int i = 0; i < LMAX; ++i) S[i] = (i < L) ? t[i] + (i == sa ? dself : T(0)) : T(0);
+    }
+    // abar = <ybar, s - y> + <Pbar, S - P>
+    T P[LMAX], yb[LMAX];
+#pragma unroll
+    for (int j = 0; j < LMAX; ++j) P[j] = yb[j] = T(0);
+    tile_load<T, LMAX, TP>(A.P, lo, np, L, lds, P);
+    tile_load<T, LMAX, TP>(A.ybar, lo, np, L, lds, yb);
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < LMAX; ++k) {
+            if (k < L)
+                acc[0] += double(yb[k]) * ((k == sa ? 1.0 : 0.0) - double(y[k])) +
+                          double(pb[k]) * (double(S[k]) - double(P[k]));
+        }
+    }
+    tile_store<T, LMAX, TP>(A.S, lo, np, L, lds, S);
+    block_sum<kNP, TP>(acc, red);
+    if (threadIdx.x < kNP) A.part[(size_t)tile * kNP + threadIdx.x] = acc[threadIdx.x];
+}
+
+struct StepBar {
+    double al, Abar, Bbar, Cbar, Dbar, cybar, csbar;
+};
+
+// One block per image: reduce the image's tiles of k_sweep_a, form the step
+// adjoints from the checkpointed step quadratic, accumulate the weight
+// gradient and record (cybar, csbar) of the iteration.
+template <int NT>
+__global__ void __launch_bounds__(NT)
+k_step_adjoint(const double *__restrict__ part, const int *__restrict__ seg, int nimg,
+               int TP, int nk, const double *__restrict__ stats, int t,
+               StepBar *__restrict__ sb, double *__restrict__ gw,
+               double *__restrict__ coef) {
+    __shared__ double red[kNP * NT];
+    const int img = blockIdx.x;
+    int ta = 0;
+    for (int k = 0; k < img; ++k) ta += (seg[2 * k + 1] - seg[2 * k] + TP - 1) / TP;
+    const int tb = ta + (seg[2 * img + 1] - seg[2 * img] + TP - 1) / TP;
+    double tot[kNP];
+#pragma unroll
+    for (int i = 0; i < kNP; ++i) tot[i] = 0.0;
+    for (int b = ta + (int)threadIdx.x; b < tb; b += NT)
+#pragma unroll
+        for (int i = 0; i < kNP; ++i) tot[i] += part[(size_t)b * kNP + i];
+    block_sum<kNP, NT>(tot, red);
+    if (threadIdx.x != 0) return;
+    const double *st = stats + ((size_t)t * nimg + img) * kFWStats;
+    const double abar = tot[0], al = st[0], a2 = st[1];
+    double b1bar = 0.0, a2bar = 0.0;
+    if (st[3] != 0.0) {
+        b1bar = -abar / (2.0 * a2);
+        a2bar = -abar * al / a2;
+    }
+    const StepBar b{al, -2.0 * b1bar + a2bar, b1bar - a2bar, b1bar - a2bar, a2bar,
+                    -b1bar, b1bar};
+    sb[img] = b;
+    for (int m = 0; m < nk; ++m) {
+        const double *x = tot + 1 + 6 * m;
+        gw[(size_t)img * nk + m] +=
+            al * (x[0] + x[3]) + b.Bbar * (x[1] + x[4]) + b.Dbar * (x[2] + x[5]);
+    }
+    coef[((size_t)t * nimg + img) * 2 + 0] = b.cybar;
+    coef[((size_t)t * nimg + img) * 2 + 1] = b.csbar;
+}
+
+// ybar <- (1 - alpha) ybar + Abar P + Bbar S + cybar c,
+// Pbar <- (1 - alpha) Pbar + Abar y + Cbar s, with c = phi - |mu| r
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_diff_final(FinArgs<T> A) {
-    __shared__ double rowy[kThreads];
-    __shared__ double rowr[kThreads];
-    __shared__ double red[DCRF_MAXK * kThreads];
+k_sweep_b(const int *__restrict__ seg, int nimg, int L, int TPB,
+          const StepBar *__restrict__ sb, const int32_t *__restrict__ s,
+          const T *__restrict__ y, const T *__restrict__ P, const T *__restrict__ S,
+          const T *__restrict__ phi, const T *__restrict__ r, const T *__restrict__ mabs,
+          T *__restrict__ ybar, T *__restrict__ Pbar) {
+    int lo, hi;
+    const int img = tile_range(seg, nimg, TPB, xcd_block(blockIdx.x, gridDim.x), lo, hi);
+    if (img < 0) return;
+    const StepBar b = sb[img];
+    const T om = T(1.0 - b.al), Ab = T(b.Abar), Bb = T(b.Bbar), Cb = T(b.Cbar),
+            cy = T(b.cybar);
+    for (size_t e = (size_t)lo * L + threadIdx.x; e < (size_t)hi * L; e += kThreads) {
+        const size_t a = e / L;
+        const int i = int(e - a * L);
+        const T c = phi[e] - mabs[i] * r[a];
+        ybar[e] = om * ybar[e] + Ab * P[e] + Bb * S[e] + cy * c;
+        Pbar[e] = om * Pbar[e] + Ab * y[e] + (i == s[a] ? Cb : T(0));
+    }
+}
+
+template <typename T>
+struct SweepF {
+    const int *seg;
+    int nimg, L, nk, iters;
+    const T *ybar, *KtZ, *Pbar, *y0, *r, *mabs, *mu;
+    const int32_t *s;          // iters x N saved labels
+    const double *cb;          // per image: a_0, then b_k + csbar_k for k < iters
+    const T *kappa1[DCRF_MAXK];
+    T gam[DCRF_MAXK];
+    T *phibar;
+    double *part;              // per tile: nk sums
+};
+
+// The end of the sweep: P_0 = Q y_0 (ybar += K'^T (Pbar mu) + d Pbar and the
+// weight terms with X = y_0), cbar rebuilt from y_0 and the labels, c = phi -
+// d (its rho terms), and y_0 = softmax(-phi).
+template <typename T, int LMAX, bool POTTS>
+__global__ void __launch_bounds__(RowTile<T>::kPix)
+k_sweep_final(SweepF<T> A, LatSet<T> ls) {
+    constexpr int TP = RowTile<T>::kPix;
+    __shared__ __align__(16) T lds[TP * (LMAX | 1)];
+    __shared__ T smu[POTTS ? 1 : LMAX * LMAX];
+    __shared__ double red[DCRF_MAXK * TP];
     const int L = A.L;
-    const int ppb = kThreads / L;
-    const int t = threadIdx.x;
-    const int lp = t / L;
-    const int i = t - lp * L;
+    if (!POTTS) {
+        for (int i = threadIdx.x; i < L * L; i += TP)
+            smu[(i / L) * LMAX + (i % L)] = A.mu[i];
+        __syncthreads();
+    }
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    int lo, hi;
+    const int img = tile_range(A.seg, A.nimg, TP, tile, lo, hi);
+    const int np = hi - lo;
+    const size_t a = (size_t)lo + threadIdx.x;
+    const bool act = (int)threadIdx.x < np;
+    const size_t N = (size_t)A.seg[2 * A.nimg - 1];
     double acc[DCRF_MAXK];
 #pragma unroll
     for (int m = 0; m < DCRF_MAXK; ++m) acc[m] = 0.0;
-    int lo, hi;
-    diff_tile(A.seg, A.nimg, ppb, lo, hi);
-    for (int g0 = lo; g0 < hi; g0 += ppb) {
-        const long long a = (long long)g0 + lp;
-        const bool act = lp < ppb && a < hi;
-        const size_t e = (size_t)a * L + i;
-        double yb0 = 0.0, y0 = 0.0;
-        if (act) {
-            y0 = A.y0[e];
-            const double pb = A.Pbar[e];
-            const double d = double(A.mabs[i]) * double(A.r[a]);
-            yb0 = double(A.ybar[e]) + double(A.KtZ[e]) + d * pb;
-            rowy[t] = yb0 * y0;
-            // rho contributions of P_0 = Q y_0 and of c = phi - d
-            rowr[t] = pb * y0 * double(A.mabs[i]) - double(A.cbar[e]) * double(A.mabs[i]);
-            for (int m = 0; m < A.nk; ++m)
-                acc[m] += double(A.Z[e]) * (double(A.Ky0[m][e]) - y0);
+    T y0[LMAX], pb[LMAX], g[LMAX], kz[LMAX];
+#pragma unroll
+    for (int j = 0; j < LMAX; ++j) y0[j] = pb[j] = g[j] = kz[j] = T(0);
+    tile_load<T, LMAX, TP>(A.y0, lo, np, L, lds, y0);
+    tile_load<T, LMAX, TP>(A.Pbar, lo, np, L, lds, pb);
+    tile_load<T, LMAX, TP>(A.ybar, lo, np, L, lds, g);
+    tile_load<T, LMAX, TP>(A.KtZ, lo, np, L, lds, kz);
+    T out[LMAX];
+#pragma unroll
+    for (int j = 0; j < LMAX; ++j) out[j] = T(0);
+    if (act) {
+        const double *cb = A.cb + (size_t)(img < 0 ? 0 : img) * (A.iters + 1);
+        const T ra = A.r[a];
+        // cbar = a_0 y_0 + sum_k b_k s_k
+        T cbar[LMAX];
+#pragma unroll
+        for (int j = 0; j < LMAX; ++j) cbar[j] = T(cb[0]) * y0[j];
+        for (int k = 0; k < A.iters; ++k) {
+            const int sk = A.s[(size_t)k * N + a];
+            const T v = T(cb[1 + k]);
+#pragma unroll
+            for (int j = 0; j < LMAX; ++j)
+                if (j == sk) cbar[j] += v;
         }
-        __syncthreads();
-        if (act) {
-            double dot = 0.0, rr = 0.0;
-            for (int k = 0; k < L; ++k) {
-                dot += rowy[lp * L + k];
-                rr += rowr[lp * L + k];
-            }
-            A.phibar[e] = T(double(A.cbar[e]) - y0 * (yb0 - dot));
-            if (i == 0) {
-                const double rho = A.rho[a] + rr;
-                for (int m = 0; m < A.nk; ++m)
-                    acc[m] += rho * (double(A.K1[m][a]) - 1.0);
+        // ybar_0, the rho terms of P_0 = Q y_0 and of c = phi - d, the
+        // softmax backward
+        double dot = 0.0, rho = 0.0;
+#pragma unroll
+        for (int j = 0; j < LMAX; ++j) {
+            if (j < L) {
+                g[j] = g[j] + kz[j] + A.mabs[j] * ra * pb[j];
+                dot += double(g[j]) * double(y0[j]);
+                rho += (double(pb[j]) * double(y0[j]) - double(cbar[j])) * double(A.mabs[j]);
             }
         }
-        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < LMAX; ++j)
+            out[j] = (j < L) ? T(double(cbar[j]) - double(y0[j]) * (double(g[j]) - dot))
+                             : T(0);
+        for (int m = 0; m < A.nk; ++m) {
+            T q[LMAX], t[LMAX];
+            slice_one<T, LMAX>(ls.l[m], A.gam[m], a, L, q);
+#pragma unroll
+            for (int j = 0; j < LMAX; ++j) q[j] -= y0[j];
+            mu_apply<T, LMAX, POTTS>(smu, L, q, t);
+            double x = 0.0;
+#pragma unroll
+            for (int k = 0; k < LMAX; ++k)
+                if (k < L) x += double(pb[k]) * double(t[k]);
+            acc[m] += x + rho * (double(A.kappa1[m][a]) - 1.0);
+        }
     }
-    bsum<DCRF_MAXK>(acc, red);
-    if (t < DCRF_MAXK) A.part[(size_t)blockIdx.x * DCRF_MAXK + t] = acc[t];
+    tile_store<T, LMAX, TP>(A.phibar, lo, np, L, lds, out);
+    block_sum<DCRF_MAXK, TP>(acc, red);
+    if (threadIdx.x < DCRF_MAXK)
+        A.part[(size_t)tile * DCRF_MAXK + threadIdx.x] = acc[threadIdx.x];
 }
 
 struct DiffWork {
-    DevBuf ybar, Pbar, cbar, P, S, OH, c, Z, KtZ, rho, part, mabs, ones, sb;
-    DevBuf Ks[DCRF_MAXK], Ky0[DCRF_MAXK], K1[DCRF_MAXK];
+    DevBuf ybar, Pbar, S, Z, KtZ, part, mabs, ones, sb, gw, coef, cb;
+    DevBuf K1[DCRF_MAXK];
 };
 
 DiffWork &diff_work(dcrf_ctx *ctx) {
@@ -297,34 +452,50 @@ DiffWork &diff_work(dcrf_ctx *ctx) {
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 struct SavedLayout {
-    size_t y, s, stats, total;
+    size_t y, P, s, V, vblock, stats, total;
 };
 
 SavedLayout saved_layout(dcrf_ctx *ctx, int L, int iters) {
     SavedLayout o;
     const size_t NL = (size_t)ctx->N * L;
+    const size_t e = ctx->elt();
+    o.vblock = 0;
+    for (int m = 0; m < ctx->nk; ++m)
+        o.vblock += (size_t)ctx->lat[m].M * row_stride(L, e);
     o.y = 0;
-    o.s = align256(o.y + (size_t)iters * NL * ctx->elt());
-    o.stats = align256(o.s + (size_t)iters * ctx->N * 4);
+    o.P = align256(o.y + (size_t)iters * NL * e);
+    o.s = align256(o.P + (size_t)iters * NL * e);
+    o.V = align256(o.s + (size_t)iters * ctx->N * 4);
+    o.stats = align256(o.V + (size_t)(iters + 1) * o.vblock * e);
     o.total = align256(o.stats + (size_t)iters * ctx->nimg * kFWStats * 8);
     return o;
 }
 
-// Per-image sums of per-tile partials (stride doubles per tile, component k):
-// out[j] = sum over the tiles [toff[j], toff[j+1]) of image j.
-void image_sums(dcrf_ctx *ctx, const double *d, const std::vector<int> &toff,
-                int stride, int ncomp, std::vector<double> &out) {
-    const int nt = toff.back();
-    std::vector<double> h((size_t)nt * stride);
-    DCRF_TRY_HIP(hipMemcpyAsync(h.data(), d, h.size() * 8, hipMemcpyDeviceToHost,
+// the lattices of the context with their blurred values taken from a saved
+// block of vertex values
+template <typename T>
+LatSet<T> saved_lat_set(dcrf_ctx *ctx, int L, const T *block) {
+    LatSet<T> ls = make_lat_set<T>(ctx, L);
+    const T *p = block;
+    for (int m = 0; m < ctx->nk; ++m) {
+        ls.l[m].Vf = p;
+        p += (size_t)ctx->lat[m].M * ls.l[m].ld;
+    }
+    ls.shape52 = 0;
+    return ls;
+}
+
+// whether mu is the Potts compatibility (read once per call)
+template <typename T>
+bool mu_is_potts(dcrf_ctx *ctx, const T *mu, int L) {
+    std::vector<T> h((size_t)L * L);
+    DCRF_TRY_HIP(hipMemcpyAsync(h.data(), mu, h.size() * sizeof(T), hipMemcpyDeviceToHost,
                                 ctx->stream));
     DCRF_TRY_HIP(hipStreamSynchronize(ctx->stream));
-    const int nimg = int(toff.size()) - 1;
-    out.assign((size_t)nimg * ncomp, 0.0);
-    for (int j = 0; j < nimg; ++j)
-        for (int t = toff[j]; t < toff[j + 1]; ++t)
-            for (int k = 0; k < ncomp; ++k)
-                out[(size_t)j * ncomp + k] += h[(size_t)t * stride + k];
+    for (int i = 0; i < L; ++i)
+        for (int j = 0; j < L; ++j)
+            if (h[(size_t)i * L + j] != T(i != j ? 1 : 0)) return false;
+    return true;
 }
 
 template <typename T>
@@ -335,126 +506,141 @@ void backward_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, int iters,
     const int *seg = ctx->seg.as<int>();
     const size_t NL = (size_t)N * L;
     const size_t B = NL * sizeof(T);
-    const int TPD = (kThreads / L) * kGroups;
-    const int GD = seg_tiles(ctx, TPD);
-    const std::vector<int> toff = seg_tile_offsets(ctx, TPD);
+    constexpr int TP = RowTile<T>::kPix;
+    const int GA = seg_tiles(ctx, TP);
+    constexpr int TPB = 256;   // pixels per block of k_sweep_b
+    const int GB = seg_tiles(ctx, TPB);
     DiffWork &W = diff_work(ctx);
-    for (DevBuf *b : {&W.ybar, &W.Pbar, &W.cbar, &W.P, &W.S, &W.OH, &W.c, &W.Z,
-                      &W.KtZ})
-        b->ensure(B, st);
-    for (int m = 0; m < nk; ++m) {
-        W.Ks[m].ensure(B, st);
-        W.Ky0[m].ensure(B, st);
-        W.K1[m].ensure((size_t)N * sizeof(T), st);
-    }
-    W.rho.ensure((size_t)N * 8, st);
-    W.part.ensure((size_t)GD * DCRF_MAXK * 8, st);
+    for (DevBuf *b : {&W.ybar, &W.Pbar, &W.S, &W.Z, &W.KtZ}) b->ensure(B, st);
+    for (int m = 0; m < nk; ++m) W.K1[m].ensure((size_t)N * sizeof(T), st);
+    W.part.ensure((size_t)GA * kNP * 8, st);
     W.mabs.ensure((size_t)L * sizeof(T), st);
     W.ones.ensure((size_t)N * sizeof(T), st);
     W.sb.ensure((size_t)nimg * sizeof(StepBar), st);
+    W.gw.ensure((size_t)nimg * nk * 8, st);
+    W.coef.ensure((size_t)iters * nimg * 2 * 8, st);
+    W.cb.ensure((size_t)nimg * (iters + 1) * 8, st);
     const SavedLayout lay = saved_layout(ctx, L, iters);
     const T *ys = reinterpret_cast<const T *>(saved + lay.y);
+    const T *Ps = reinterpret_cast<const T *>(saved + lay.P);
     const int32_t *ss = reinterpret_cast<const int32_t *>(saved + lay.s);
-    std::vector<double> stats((size_t)iters * nimg * kFWStats);
-    DCRF_TRY_HIP(hipMemcpyAsync(stats.data(), saved + lay.stats, stats.size() * 8,
-                                hipMemcpyDeviceToHost, st));
-    const int gE = ceil_div((long long)NL, 256);
-    T *ybar = W.ybar.as<T>(), *Pbar = W.Pbar.as<T>(), *cbar = W.cbar.as<T>();
+    const T *Vs = reinterpret_cast<const T *>(saved + lay.V);
+    const double *stats = reinterpret_cast<const double *>(saved + lay.stats);
+    const bool potts = mu_is_potts<T>(ctx, mu, L);
+    T *ybar = W.ybar.as<T>(), *Pbar = W.Pbar.as<T>();
     DCRF_TRY_HIP(hipMemcpyAsync(ybar, grad_y, B, hipMemcpyDeviceToDevice, st));
-    DCRF_TRY_HIP(hipMemsetAsync(Pbar, 0, B, st));
-    DCRF_TRY_HIP(hipMemsetAsync(cbar, 0, B, st));
-    DCRF_TRY_HIP(hipMemsetAsync(W.rho.p, 0, (size_t)N * 8, st));
+    hipLaunchKernelGGL((k_fill_d<T>), dim3(ceil_div((long long)NL, 256)), dim3(256), 0, st,
+                       NL, Pbar, T(0));
+    hipLaunchKernelGGL((k_fill_d<double>), dim3(1), dim3(256), 0, st,
+                       (size_t)nimg * nk, W.gw.as<double>(), 0.0);
     hipLaunchKernelGGL((k_mabs<T>), dim3(1), dim3(256), 0, st, L, mu, W.mabs.as<T>());
-    hipLaunchKernelGGL((k_c<T>), dim3(gE), dim3(256), 0, st, N, L, phi,
-                       ctx->r.as<T>(), W.mabs.as<T>(), W.c.as<T>());
+    // kappa_m + 1 = K~_m 1
+    hipLaunchKernelGGL((k_fill_d<T>), dim3(ceil_div(N, 256)), dim3(256), 0, st,
+                       (size_t)N, W.ones.as<T>(), T(1));
+    for (int m = 0; m < nk; ++m) filter_kernel(ctx, m, W.ones.p, W.K1[m].p, 1, false);
     DCRF_CHECK_LAUNCH();
-    std::vector<double> gw((size_t)nimg * nk, 0.0), sums;
-    std::vector<StepBar> sb(nimg);
-    for (int t = iters - 1; t >= 0; --t) {
-        const T *yt = ys + (size_t)t * NL;
-        const int32_t *sl = ss + (size_t)t * N;
-        qp_apply(ctx, yt, mu, L, W.P.p);
-        hipLaunchKernelGGL((k_onehot_d<T>), dim3(gE), dim3(256), 0, st, N, L, sl,
-                           W.OH.as<T>());
-        qp_apply(ctx, W.OH.p, mu, L, W.S.p);
-        for (int m = 0; m < nk; ++m) filter_kernel(ctx, m, W.OH.p, W.Ks[m].p, L, false);
-        hipLaunchKernelGGL((k_abar<T>), dim3(GD), dim3(kThreads), 0, st, seg, nimg,
-                           L, ybar, yt, sl, Pbar, W.S.as<T>(), W.P.as<T>(),
-                           W.part.as<double>());
-        DCRF_CHECK_LAUNCH();
-        image_sums(ctx, W.part.as<double>(), toff, 1, 1, sums);
-        for (int j = 0; j < nimg; ++j) {
-            const double *stt = stats.data() + ((size_t)t * nimg + j) * kFWStats;
-            const double abar = sums[j], al = stt[0], a2 = stt[1];
-            double b1bar = 0.0, a2bar = 0.0;
-            if (stt[3] != 0.0) {
-                b1bar = -abar / (2.0 * a2);
-                a2bar = -abar * al / a2;
-            }
-            sb[j] = StepBar{al, -2.0 * b1bar + a2bar, b1bar - a2bar, b1bar - a2bar,
-                            a2bar, -b1bar, b1bar};
-        }
-        DCRF_TRY_HIP(hipMemcpyAsync(W.sb.p, sb.data(), nimg * sizeof(StepBar),
-                                    hipMemcpyHostToDevice, st));
-        UpdArgs<T> U{};
-        U.seg = seg;
-        U.nimg = nimg;
-        U.L = L;
-        U.nk = nk;
-        U.ybar = ybar;
-        U.Pbar = Pbar;
-        U.cbar = cbar;
-        U.y = yt;
-        U.P = W.P.as<T>();
-        U.S = W.S.as<T>();
-        U.c = W.c.as<T>();
-        U.s = sl;
-        for (int m = 0; m < nk; ++m) U.Ks[m] = W.Ks[m].as<T>();
-        U.mu = mu;
-        U.mabs = W.mabs.as<T>();
-        U.rho = W.rho.as<double>();
-        U.part = W.part.as<double>();
-        U.sb = W.sb.as<StepBar>();
-        hipLaunchKernelGGL((k_diff_update<T>), dim3(GD), dim3(kThreads), 0, st, U);
-        DCRF_CHECK_LAUNCH();
-        image_sums(ctx, W.part.as<double>(), toff, DCRF_MAXK, nk, sums);
-        for (size_t i = 0; i < gw.size(); ++i) gw[i] += sums[i];
+
+    SweepA<T> A{};
+    A.seg = seg;
+    A.nimg = nimg;
+    A.L = L;
+    A.nk = nk;
+    A.ybar = ybar;
+    A.Pbar = Pbar;
+    A.r = ctx->r.as<T>();
+    A.mabs = W.mabs.as<T>();
+    A.mu = mu;
+    A.wsum = T(ctx->wsum);
+    for (int m = 0; m < nk; ++m) {
+        A.kappa1[m] = W.K1[m].as<T>();
+        A.w[m] = T(ctx->kern[m].weight);
+        A.gam[m] = T(ctx->lat[m].gamma);
     }
-    // the end of the sweep
-    const T *y0 = ys;
+    A.S = W.S.as<T>();
+    A.part = W.part.as<double>();
+    for (int t = iters - 1; t >= 0; --t) {
+        A.s = ss + (size_t)t * N;
+        A.y = ys + (size_t)t * NL;
+        A.P = Ps + (size_t)t * NL;
+        const LatSet<T> ls = saved_lat_set<T>(ctx, L, Vs + (size_t)(t + 1) * lay.vblock);
+        if (potts)
+            DCRF_DISPATCH_ROWS(L, hipLaunchKernelGGL((k_sweep_a<T, LMAX, true>), dim3(GA),
+                                                     dim3(TP), 0, st, A, ls));
+        else
+            DCRF_DISPATCH_ROWS(L, hipLaunchKernelGGL((k_sweep_a<T, LMAX, false>), dim3(GA),
+                                                     dim3(TP), 0, st, A, ls));
+        hipLaunchKernelGGL((k_step_adjoint<256>), dim3(nimg), dim3(256), 0, st,
+                           W.part.as<double>(), seg, nimg, TP, nk, stats, t,
+                           W.sb.as<StepBar>(), W.gw.as<double>(), W.coef.as<double>());
+        hipLaunchKernelGGL((k_sweep_b<T>), dim3(GB), dim3(kThreads), 0, st, seg, nimg, L,
+                           TPB, W.sb.as<StepBar>(), A.s, A.y, A.P, W.S.as<T>(), phi,
+                           ctx->r.as<T>(), W.mabs.as<T>(), ybar, Pbar);
+        DCRF_CHECK_LAUNCH();
+    }
+    // coefficients of cbar = a_0 y_0 + sum_k (b_k + csbar_k) s_k, per image
+    std::vector<double> coef((size_t)iters * nimg * 2), sth((size_t)iters * nimg * kFWStats);
+    DCRF_TRY_HIP(hipMemcpyAsync(coef.data(), W.coef.p, coef.size() * 8,
+                                hipMemcpyDeviceToHost, st));
+    DCRF_TRY_HIP(hipMemcpyAsync(sth.data(), stats, sth.size() * 8, hipMemcpyDeviceToHost, st));
+    DCRF_TRY_HIP(hipStreamSynchronize(st));
+    std::vector<double> cb((size_t)nimg * (iters + 1));
+    for (int j = 0; j < nimg; ++j) {
+        auto al = [&](int t) { return sth[((size_t)t * nimg + j) * kFWStats]; };
+        auto cy = [&](int t) { return coef[((size_t)t * nimg + j) * 2 + 0]; };
+        auto cs = [&](int t) { return coef[((size_t)t * nimg + j) * 2 + 1]; };
+        // tail = sum_{t>k} cybar_t prod_{k<u<t} (1 - alpha_u), built from the
+        // last iteration backwards; at the end it is a_0
+        double tail = 0.0;
+        for (int k = iters - 1; k >= 0; --k) {
+            cb[(size_t)j * (iters + 1) + 1 + k] = al(k) * tail + cs(k);
+            tail = cy(k) + (1.0 - al(k)) * tail;
+        }
+        cb[(size_t)j * (iters + 1)] = tail;
+    }
+    DCRF_TRY_HIP(hipMemcpyAsync(W.cb.p, cb.data(), cb.size() * 8, hipMemcpyHostToDevice, st));
+    // the end of the sweep: ybar += K'^T (Pbar mu) + d Pbar and the rest
     hipLaunchKernelGGL((k_rowmat<T>), dim3(std::min(4096, ceil_div(N, kThreads / L))),
                        dim3(kThreads), 0, st, N, L, Pbar, mu, W.Z.as<T>());
     filter_apply(ctx, W.Z.p, W.KtZ.p, L, true, false);
-    hipLaunchKernelGGL((k_fill_d<T>), dim3(ceil_div(N, 256)), dim3(256), 0, st,
-                       (size_t)N, W.ones.as<T>(), T(1));
-    for (int m = 0; m < nk; ++m) {
-        filter_kernel(ctx, m, y0, W.Ky0[m].p, L, false);
-        filter_kernel(ctx, m, W.ones.p, W.K1[m].p, 1, false);
-    }
-    FinArgs<T> F{};
+    SweepF<T> F{};
     F.seg = seg;
     F.nimg = nimg;
     F.L = L;
     F.nk = nk;
+    F.iters = iters;
     F.ybar = ybar;
     F.KtZ = W.KtZ.as<T>();
-    F.Z = W.Z.as<T>();
     F.Pbar = Pbar;
-    F.y0 = y0;
-    F.cbar = cbar;
+    F.y0 = ys;
     F.r = ctx->r.as<T>();
     F.mabs = W.mabs.as<T>();
+    F.mu = mu;
+    F.s = ss;
+    F.cb = W.cb.as<double>();
     for (int m = 0; m < nk; ++m) {
-        F.Ky0[m] = W.Ky0[m].as<T>();
-        F.K1[m] = W.K1[m].as<T>();
+        F.kappa1[m] = W.K1[m].as<T>();
+        F.gam[m] = T(ctx->lat[m].gamma);
     }
-    F.rho = W.rho.as<double>();
     F.phibar = grad_phi;
     F.part = W.part.as<double>();
-    hipLaunchKernelGGL((k_diff_final<T>), dim3(GD), dim3(kThreads), 0, st, F);
+    const LatSet<T> ls0 = saved_lat_set<T>(ctx, L, Vs);
+    if (potts)
+        DCRF_DISPATCH_ROWS(L, hipLaunchKernelGGL((k_sweep_final<T, LMAX, true>), dim3(GA),
+                                                 dim3(TP), 0, st, F, ls0));
+    else
+        DCRF_DISPATCH_ROWS(L, hipLaunchKernelGGL((k_sweep_final<T, LMAX, false>), dim3(GA),
+                                                 dim3(TP), 0, st, F, ls0));
     DCRF_CHECK_LAUNCH();
-    image_sums(ctx, W.part.as<double>(), toff, DCRF_MAXK, nk, sums);
-    for (size_t i = 0; i < gw.size(); ++i) gw[i] += sums[i];
+    std::vector<double> part((size_t)GA * DCRF_MAXK), gw((size_t)nimg * nk);
+    DCRF_TRY_HIP(hipMemcpyAsync(part.data(), W.part.p, part.size() * 8,
+                                hipMemcpyDeviceToHost, st));
+    DCRF_TRY_HIP(hipMemcpyAsync(gw.data(), W.gw.p, gw.size() * 8, hipMemcpyDeviceToHost, st));
+    DCRF_TRY_HIP(hipStreamSynchronize(st));
+    const std::vector<int> toff = seg_tile_offsets(ctx, TP);
+    for (int j = 0; j < nimg; ++j)
+        for (int t = toff[j]; t < toff[j + 1]; ++t)
+            for (int m = 0; m < nk; ++m)
+                gw[(size_t)j * nk + m] += part[(size_t)t * DCRF_MAXK + m];
     if (grad_w)
         for (size_t i = 0; i < gw.size(); ++i) grad_w[i] = gw[i];
 }
@@ -466,8 +652,8 @@ void forward_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y, int iters,
     hipLaunchKernelGGL((k_softmax_neg<T>), dim3(seg_tiles(ctx, 256)), dim3(256),
                        0, ctx->stream, ctx->seg.as<int>(), ctx->nimg, L, phi, y);
     DCRF_CHECK_LAUNCH();
-    FWCheckpoint cp{saved + lay.y, reinterpret_cast<int32_t *>(saved + lay.s),
-                    reinterpret_cast<double *>(saved + lay.stats)};
+    FWCheckpoint cp{saved + lay.y, saved + lay.P, reinterpret_cast<int32_t *>(saved + lay.s),
+                    saved + lay.V, reinterpret_cast<double *>(saved + lay.stats)};
     frank_wolfe_checkpointed(ctx, phi, mu, L, y, iters, cp);
 }
 
@@ -479,6 +665,8 @@ size_t fw_saved_bytes(dcrf_ctx *ctx, int L, int iters) {
 
 void fw_diff_forward(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
                      void *y_out, int iters, void *saved) {
+    if (L > kRowMaxC)
+        fail(DCRF_EUNSUPPORTED, "differentiation serves at most 32 labels");
     if (ctx->dtype == DCRF_F64)
         forward_t<double>(ctx, static_cast<const double *>(unary),
                           static_cast<const double *>(mu), L,
@@ -494,6 +682,8 @@ void fw_diff_forward(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
 void fw_diff_backward(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
                       int iters, const void *saved, const void *grad_y,
                       void *grad_unary, double *grad_w) {
+    if (L > kRowMaxC)
+        fail(DCRF_EUNSUPPORTED, "differentiation serves at most 32 labels");
     if (ctx->dtype == DCRF_F64)
         backward_t<double>(ctx, static_cast<const double *>(unary),
                            static_cast<const double *>(mu), L, iters,
@@ -511,15 +701,10 @@ void fw_diff_backward(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
 void diff_release(dcrf_ctx *ctx) {
     if (!ctx->diff) return;
     DiffWork *W = static_cast<DiffWork *>(ctx->diff);
-    for (DevBuf *b : {&W->ybar, &W->Pbar, &W->cbar, &W->P, &W->S, &W->OH, &W->c,
-                      &W->Z, &W->KtZ, &W->rho, &W->part, &W->mabs, &W->ones,
-                      &W->sb})
+    for (DevBuf *b : {&W->ybar, &W->Pbar, &W->S, &W->Z, &W->KtZ, &W->part, &W->mabs,
+                      &W->ones, &W->sb, &W->gw, &W->coef, &W->cb})
         b->release();
-    for (int m = 0; m < DCRF_MAXK; ++m) {
-        W->Ks[m].release();
-        W->Ky0[m].release();
-        W->K1[m].release();
-    }
+    for (int m = 0; m < DCRF_MAXK; ++m) W->K1[m].release();
     delete W;
     ctx->diff = nullptr;
 }

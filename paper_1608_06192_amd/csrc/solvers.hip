@@ -765,6 +765,25 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
                        phi, ctx->r.as<T>(), w.mabs, cmode == 1 ? y : nullptr,
                        T(cmode == 1 ? 2 : 1), w.c);
     if (!have_Py) qp_apply_t<T>(ctx, y, mu, L, w.mabs, w.Py);
+    // blurred vertex values of every lattice, one block per checkpoint
+    size_t vblock = 0;
+    if (save && ctx->mode != DCRF_FILTER_EXACT)
+        for (int m = 0; m < ctx->nk; ++m)
+            vblock += (size_t)ctx->lat[m].M * row_stride(L, sizeof(T));
+    auto save_vertices = [&](int slot) {
+        const LatSet<T> cur = make_lat_set<T>(ctx, L);
+        T *dst = static_cast<T *>(save->V) + (size_t)slot * vblock;
+        for (int m = 0; m < ctx->nk; ++m) {
+            const size_t n = (size_t)ctx->lat[m].M * cur.l[m].ld;
+            DCRF_TRY_HIP(hipMemcpyAsync(dst, cur.l[m].Vf, n * sizeof(T),
+                                        hipMemcpyDeviceToDevice, st));
+            dst += n;
+        }
+    };
+    if (save && vblock) {
+        if (have_Py) fail(DCRF_EINVAL, "checkpoints need the first filter of y");
+        save_vertices(0);
+    }
     hipLaunchKernelGGL(k_fill_i32, dim3(ceil_div(N, 256)), dim3(256), 0, st,
                        w.sprev, (size_t)N, -1);
     DCRF_TRY_HIP(hipMemsetAsync(w.scal, 0, (size_t)ctx->nimg * 8, st));
@@ -799,8 +818,10 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
                                    st, a);
             }
         }
-        if (save) {   // y_t and s_t for the reverse sweep
+        if (save) {   // y_t, P_t and s_t for the reverse sweep
             DCRF_TRY_HIP(hipMemcpyAsync(static_cast<T *>(save->y) + (size_t)it * NL, y,
+                                        NL * sizeof(T), hipMemcpyDeviceToDevice, st));
+            DCRF_TRY_HIP(hipMemcpyAsync(static_cast<T *>(save->P) + (size_t)it * NL, w.Py,
                                         NL * sizeof(T), hipMemcpyDeviceToDevice, st));
             DCRF_TRY_HIP(hipMemcpyAsync(save->s + (size_t)it * N, w.s, (size_t)N * 4,
                                         hipMemcpyDeviceToDevice, st));
@@ -814,6 +835,7 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
         } else {
             splat_labels(ctx, w.s, L);
             blur_all(ctx, L, false);
+            if (save && vblock) save_vertices(it + 1);
         }
         FWSliceArgs<T> b{N, L, y, w.s, w.Ps, mu, w.mabs, ctx->r.as<T>(), pre,
                          T(ctx->wsum), w.scal, w.part1, w.part2, G1, w.trace, it,

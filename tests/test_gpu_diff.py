@@ -58,14 +58,27 @@ def _a256(b):
     return (b + 255) // 256 * 256
 
 
-def unpack_saved(saved, N, L, iters, elt):
-    """The checkpoint layout stated in the header: y_t, then s_t, then four
-    doubles (alpha, a2, b1, interior) per iteration, each 256-byte aligned."""
+def saved_offsets(ctx, N, L, iters, elt):
+    """The checkpoint layout stated in the header: y_t, P_t, s_t, the blurred
+    vertex values of every lattice ((iters + 1) blocks), then four doubles
+    (alpha, a2, b1, interior) per iteration and image, each 256-byte
+    aligned. Returns the byte offsets of s_t and of the doubles."""
+    q = 16 // elt
+    ld = (L + q - 1) // q * q
+    vblock = sum(ctx.lattice_info(m)[1] * ld for m in range(ctx.nk))
+    p_off = _a256(iters * N * L * elt)
+    s_off = _a256(p_off + iters * N * L * elt)
+    v_off = _a256(s_off + iters * N * 4)
+    st_off = _a256(v_off + (iters + 1) * vblock * elt)
+    return s_off, st_off
+
+
+def unpack_saved(ctx, saved, N, L, iters, elt):
     raw = saved.cpu().numpy()
-    s_off = _a256(iters * N * L * elt)
-    st_off = _a256(s_off + iters * N * 4)
+    s_off, st_off = saved_offsets(ctx, N, L, iters, elt)
     s = raw[s_off:s_off + iters * N * 4].view(np.int32).reshape(iters, N)
-    stats = raw[st_off:st_off + iters * 32].view(np.float64).reshape(iters, 4)
+    nst = iters * ctx.nimg * 4
+    stats = raw[st_off:st_off + nst * 8].view(np.float64).reshape(iters * ctx.nimg, 4)
     return s, stats
 
 
@@ -109,7 +122,7 @@ def test_fw_diff_fp64_matches_oracle(case):
     assert any(r["interior"] for r in ref["tape"])
     ctx = gpu_ctx(im, torch.float64)
     y, saved, gphi, gw = gpu_run(ctx, im, mu, iters, torch.float64, ref["ybar"])
-    s, stats = unpack_saved(saved, im.N, im.L, iters, 8)
+    s, stats = unpack_saved(ctx, saved, im.N, im.L, iters, 8)
     for t, r in enumerate(ref["tape"]):
         assert np.array_equal(s[t], r["s"].argmax(1)), f"s_{t}"
         assert bool(stats[t, 3]) == bool(r["interior"]), f"interior {t}"
@@ -126,7 +139,7 @@ def test_fw_diff_fp32_matches_oracle_500x375():
     ref = oracle_problem(im, iters, mu)
     ctx = gpu_ctx(im, torch.float32)
     y, saved, gphi, gw = gpu_run(ctx, im, mu, iters, torch.float32, ref["ybar"])
-    s, stats = unpack_saved(saved, im.N, im.L, iters, 4)
+    s, stats = unpack_saved(ctx, saved, im.N, im.L, iters, 4)
     differ = sum(int((s[t] != r["s"].argmax(1)).sum())
                  for t, r in enumerate(ref["tape"]))
     frac = differ / (iters * im.N)
@@ -149,9 +162,9 @@ def _gpu_loss(ctx, phi, mu, iters, gt):
     return float(-torch.log(p).mean()), saved
 
 
-def _decision_changes(sp, sm, N, L, iters):
-    sp_s, sp_st = unpack_saved(sp, N, L, iters, 8)
-    sm_s, sm_st = unpack_saved(sm, N, L, iters, 8)
+def _decision_changes(ctx, sp, sm, N, L, iters):
+    sp_s, sp_st = unpack_saved(ctx, sp, N, L, iters, 8)
+    sm_s, sm_st = unpack_saved(ctx, sm, N, L, iters, 8)
     return int((sp_s != sm_s).sum()) + int((sp_st[:, 3] != sm_st[:, 3]).sum())
 
 
@@ -162,7 +175,7 @@ def _fd_check(ctx, im, iters, directions, eps_list):
         for eps in eps_list:
             lp, sp = loss_at(eps)
             lm, sm = loss_at(-eps)
-            changes = _decision_changes(sp, sm, im.N, im.L, iters)
+            changes = _decision_changes(ctx, sp, sm, im.N, im.L, iters)
             fd = (lp - lm) / (2 * eps)
             print(f"[fd] {name} eps={eps:g}: fd={fd:.10e} analytic={analytic:.10e}"
                   f" decision changes={changes}", flush=True)
@@ -279,5 +292,5 @@ def test_fw_diff_errors():
         ctx.fw_saved_size(3, 4)
     assert dcrf.STATUS[e.value.status] == "DCRF_EUNSUPPORTED"
     ctx.set_filter_mode("lattice")
-    assert ctx.fw_saved_size(3, 4) == _a256(_a256(_a256(4 * im.N * 3 * 8) + 4 * im.N * 4)
-                                            + 4 * 32)
+    s_off, st_off = saved_offsets(ctx, im.N, 3, 4, 8)
+    assert ctx.fw_saved_size(3, 4) == _a256(st_off + 4 * 32)
