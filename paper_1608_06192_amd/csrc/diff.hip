@@ -54,21 +54,35 @@ namespace dcrf {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kNP = 1 + 6 * DCRF_MAXK;   // partial sums per tile of k_sweep_a
+constexpr int kNP = 1 + 3 * DCRF_MAXK;   // partial sums per tile of k_sweep_a
 
-template <typename T>
-__global__ void k_softmax_neg(const int *__restrict__ seg, int nimg, int L,
-                              const T *__restrict__ phi, T *__restrict__ y) {
+// y = softmax(-phi) row by row; rows move through LDS tiles (coalesced)
+template <typename T, int LMAX>
+__global__ void __launch_bounds__(RowTile<T>::kPix)
+k_softmax_neg(const int *__restrict__ seg, int nimg, int L, const T *__restrict__ phi,
+              T *__restrict__ y) {
+    constexpr int TP = RowTile<T>::kPix;
+    __shared__ __align__(16) T lds[TP * (LMAX | 1)];
     int lo, hi;
-    tile_range(seg, nimg, 256, blockIdx.x, lo, hi);
-    const int a = lo + threadIdx.x;
-    if (a >= hi) return;
-    const T *p = phi + (size_t)a * L;
+    tile_range(seg, nimg, TP, xcd_block(blockIdx.x, gridDim.x), lo, hi);
+    const int np = hi - lo;
+    T p[LMAX];
+#pragma unroll
+    for (int j = 0; j < LMAX; ++j) p[j] = T(0);
+    tile_load<T, LMAX, TP>(phi, lo, np, L, lds, p);
     T mn = p[0];
-    for (int i = 1; i < L; ++i) mn = fmin(mn, p[i]);
-    T s = T(0);
-    for (int i = 0; i < L; ++i) s += exp(mn - p[i]);
-    for (int i = 0; i < L; ++i) y[(size_t)a * L + i] = exp(mn - p[i]) / s;
+#pragma unroll
+    for (int j = 1; j < LMAX; ++j)
+        if (j < L) mn = fmin(mn, p[j]);
+    T sum = T(0);
+#pragma unroll
+    for (int j = 0; j < LMAX; ++j) {
+        p[j] = (j < L) ? exp(mn - p[j]) : T(0);
+        sum += p[j];
+    }
+#pragma unroll
+    for (int j = 0; j < LMAX; ++j) p[j] /= sum;
+    tile_store<T, LMAX, TP>(y, lo, np, L, lds, p);
 }
 
 template <typename T>
@@ -110,16 +124,41 @@ k_rowmat(int N, int L, const T *__restrict__ X, const T *__restrict__ mu,
     }
 }
 
-// gamma_m times the slice of lattice m at pixel a (weight 1, no self term)
+// gamma_m times the slice of lattice m at pixel a (weight 1, no self term).
+// For d = 5 and d = 2 the vertex ids and weights are loaded first and every
+// row load is issued unconditionally (a missing vertex reads row 0 with
+// weight 0), so that all of them are in flight together.
+template <typename T, int LMAX, int D>
+__device__ __forceinline__ void slice_fixed(const LatView<T> &Lt, T gam, size_t a, int C,
+                                            T (&q)[LMAX]) {
+    int id[D + 1];
+    T w[D + 1];
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+        const int v = Lt.vid[a * (D + 1) + k];
+        w[k] = v >= 0 ? gam * Lt.w[a * (D + 1) + k] : T(0);
+        id[k] = v >= 0 ? v : 0;
+    }
+#pragma unroll
+    for (int k = 0; k <= D; ++k) axpy_row<LMAX>(q, w[k], Lt.Vf + (size_t)id[k] * Lt.ld, C);
+}
+
 template <typename T, int LMAX>
 __device__ __forceinline__ void slice_one(const LatView<T> &Lt, T gam, size_t a, int C,
                                           T (&q)[LMAX]) {
 #pragma unroll
     for (int j = 0; j < LMAX; ++j) q[j] = T(0);
-    const int D1 = Lt.d + 1;
-    for (int k = 0; k < D1; ++k) {
-        const int id = Lt.vid[a * D1 + k];
-        if (id >= 0) axpy_row<LMAX>(q, gam * Lt.w[a * D1 + k], Lt.Vf + (size_t)id * Lt.ld, C);
+    if (Lt.d == 5) {
+        slice_fixed<T, LMAX, 5>(Lt, gam, a, C, q);
+    } else if (Lt.d == 2) {
+        slice_fixed<T, LMAX, 2>(Lt, gam, a, C, q);
+    } else {
+        const int D1 = Lt.d + 1;
+        for (int k = 0; k < D1; ++k) {
+            const int id = Lt.vid[a * D1 + k];
+            if (id >= 0)
+                axpy_row<LMAX>(q, gam * Lt.w[a * D1 + k], Lt.Vf + (size_t)id * Lt.ld, C);
+        }
     }
 }
 
@@ -166,111 +205,150 @@ __device__ __forceinline__ void mu_apply_t(const T *smu, int C, const T (&R)[LMA
 template <typename T>
 struct SweepA {
     const int *seg;
-    int nimg, L, nk;
+    int nimg, L, nk, t;
     const int32_t *s;
     const T *y, *P, *ybar, *Pbar, *r, *mabs, *mu;
+    const double *stats;          // the forward's step records
     const T *kappa1[DCRF_MAXK];   // K~_m 1
     T w[DCRF_MAXK], gam[DCRF_MAXK], wsum;
     T *S;
-    double *part;   // per tile: abar, then per kernel X1..X3, Z1..Z3
+    double *part;   // per tile: abar, then per kernel U, V, W
 };
 
 // Per pixel of one tile: S = Q s from the saved vertex values of the
-// one-hot s, the abar terms and the six weight-gradient pieces per kernel:
+// one-hot s, the abar terms, and per kernel the weight-gradient pieces
+// U = alpha (X1 + Z1), V = X2 + Z2, W = X3 + Z3 with
 //   X1 = <Pbar mu, R_m>, X2 = <y mu, R_m>, X3 = <s mu, R_m>, R_m = K~_m s - s,
-//   Z1 = Pbar(s) |mu|_s kappa_m, Z2 = y(s) |mu|_s kappa_m, Z3 = |mu|_s kappa_m.
+//   Z1 = Pbar(s) |mu|_s kappa_m, Z2 = y(s) |mu|_s kappa_m, Z3 = |mu|_s kappa_m
+// (the step's weight gradient is then U + Bbar V + Dbar W). The rows of y,
+// Pbar, ybar and P pass through three LDS tiles, so that only the slice and
+// a few sums live in registers.
 template <typename T, int LMAX, bool POTTS>
 __global__ void __launch_bounds__(RowTile<T>::kPix)
 k_sweep_a(SweepA<T> A, LatSet<T> ls) {
     constexpr int TP = RowTile<T>::kPix;
-    __shared__ __align__(16) T lds[TP * (LMAX | 1)];
+    __shared__ __align__(16) T ty[TP * (LMAX | 1)];
+    __shared__ __align__(16) T tp[TP * (LMAX | 1)];
+    __shared__ __align__(16) T tq[TP * (LMAX | 1)];
     __shared__ T smu[POTTS ? 1 : LMAX * LMAX];
-    __shared__ double red[kNP * TP];
+    __shared__ double red[kNP * (TP / 64)];
     const int L = A.L;
-    if (!POTTS) {
+    const int Ls = lds_stride(L);
+    if (!POTTS)
         for (int i = threadIdx.x; i < L * L; i += TP)
             smu[(i / L) * LMAX + (i % L)] = A.mu[i];
-        __syncthreads();
-    }
     const int tile = xcd_block(blockIdx.x, gridDim.x);
     int lo, hi;
-    tile_range(A.seg, A.nimg, TP, tile, lo, hi);
+    const int img = tile_range(A.seg, A.nimg, TP, tile, lo, hi);
     const int np = hi - lo;
     const size_t a = (size_t)lo + threadIdx.x;
     const bool act = (int)threadIdx.x < np;
+    const double al = A.stats[((size_t)A.t * A.nimg + (img < 0 ? 0 : img)) * kFWStats];
+    tile_copy_in<T, TP>(A.y + (size_t)lo * L, np * L, L, ty);
+    tile_copy_in<T, TP>(A.Pbar + (size_t)lo * L, np * L, L, tp);
+    __syncthreads();
+    const T *yr = ty + threadIdx.x * Ls;
+    const T *pr = tp + threadIdx.x * Ls;
     double acc[kNP];
 #pragma unroll
     for (int i = 0; i < kNP; ++i) acc[i] = 0.0;
-    T y[LMAX], pb[LMAX];
+    T S[LMAX];
 #pragma unroll
-    for (int j = 0; j < LMAX; ++j) y[j] = pb[j] = T(0);
-    tile_load<T, LMAX, TP>(A.y, lo, np, L, lds, y);
-    tile_load<T, LMAX, TP>(A.Pbar, lo, np, L, lds, pb);
-    T ks[LMAX];
-#pragma unroll
-    for (int j = 0; j < LMAX; ++j) ks[j] = T(0);
+    for (int j = 0; j < LMAX; ++j) S[j] = T(0);
     const int sa = act ? A.s[a] : 0;
     if (act) {
+        T ks[LMAX];
 #pragma unroll
-        for (int j = 0; j < LMAX; ++j)
-            if (j == sa) ks[j] = -A.wsum;
-        double pbs = 0.0, ysa = 0.0;
+        for (int j = 0; j < LMAX; ++j) ks[j] = (j == sa) ? -A.wsum : T(0);
+        const double pbs = pr[sa], ysa = yr[sa];
+        double sum_pb = 0.0, sum_y = 0.0;
+        if (POTTS)
+            for (int k = 0; k < L; ++k) sum_pb += pr[k], sum_y += yr[k];
+        const double ms = A.mabs[sa];
 #pragma unroll
-        for (int k = 0; k < LMAX; ++k)
-            if (k == sa) pbs = double(pb[k]), ysa = double(y[k]);
-        for (int m = 0; m < A.nk; ++m) {
-            T q[LMAX], t[LMAX];
+        for (int m = 0; m < DCRF_MAXK; ++m) {
+            if (m >= A.nk) break;
+            T q[LMAX];
             slice_one<T, LMAX>(ls.l[m], A.gam[m], a, L, q);
 #pragma unroll
             for (int j = 0; j < LMAX; ++j) ks[j] += A.w[m] * q[j];
 #pragma unroll
             for (int j = 0; j < LMAX; ++j)
                 if (j == sa) q[j] -= T(1);
-            mu_apply<T, LMAX, POTTS>(smu, L, q, t);
             double x1 = 0.0, x2 = 0.0, x3 = 0.0;
+            if (POTTS) {
+                // (v mu)_i = sum(v) - v_i
+                double totR = 0.0, pR = 0.0, yR = 0.0, Rs = 0.0;
 #pragma unroll
-            for (int k = 0; k < LMAX; ++k) {
-                if (k < L) {
-                    x1 += double(pb[k]) * double(t[k]);
-                    x2 += double(y[k]) * double(t[k]);
-                    if (k == sa) x3 += double(t[k]);
+                for (int k = 0; k < LMAX; ++k) {
+                    if (k < L) {
+                        totR += double(q[k]);
+                        pR += double(pr[k]) * double(q[k]);
+                        yR += double(yr[k]) * double(q[k]);
+                        if (k == sa) Rs = double(q[k]);
+                    }
+                }
+                x1 = totR * sum_pb - pR;
+                x2 = totR * sum_y - yR;
+                x3 = totR - Rs;
+            } else {
+#pragma unroll
+                for (int i = 0; i < LMAX; ++i) {
+                    if (i < L) {
+                        double pm = 0.0, ym = 0.0;
+                        for (int k = 0; k < L; ++k) {
+                            pm += double(pr[k]) * double(smu[k * LMAX + i]);
+                            ym += double(yr[k]) * double(smu[k * LMAX + i]);
+                        }
+                        x1 += pm * double(q[i]);
+                        x2 += ym * double(q[i]);
+                        x3 += double(smu[sa * LMAX + i]) * double(q[i]);
+                    }
                 }
             }
-            const double mk = double(A.mabs[sa]) * (double(A.kappa1[m][a]) - 1.0);
-            acc[1 + 6 * m + 0] += x1;
-            acc[1 + 6 * m + 1] += x2;
-            acc[1 + 6 * m + 2] += x3;
-            acc[1 + 6 * m + 3] += pbs * mk;
-            acc[1 + 6 * m + 4] += ysa * mk;
-            acc[1 + 6 * m + 5] += mk;
+            const double mk = ms * (double(A.kappa1[m][a]) - 1.0);
+            acc[1 + 3 * m + 0] += al * (x1 + pbs * mk);
+            acc[1 + 3 * m + 1] += x2 + ysa * mk;
+            acc[1 + 3 * m + 2] += x3 + mk;
         }
-    }
-    // S = (K's) mu^T + d * s
-    T S[LMAX];
-    {
-        T t[LMAX];
-        mu_apply_t<T, LMAX, POTTS>(smu, L, ks, t);
-        const T dself = act ? A.mabs[sa] * A.r[a] : T(0);
+        // S = (K's) mu^T + d * s
+        mu_apply_t<T, LMAX, POTTS>(smu, L, ks, S);
+        const T dself = A.mabs[sa] * A.r[a];
 #pragma unroll
-        for (int i = 0; i < LMAX; ++i) S[i] = (i < L) ? t[i] + (i == sa ? dself : T(0)) : T(0);
-    }
-    // abar = <ybar, s - y> + <Pbar, S - P>
-    T P[LMAX], yb[LMAX];
+        for (int i = 0; i < LMAX; ++i)
+            if (i == sa) S[i] += dself;
+        // <Pbar, S>
 #pragma unroll
-    for (int j = 0; j < LMAX; ++j) P[j] = yb[j] = T(0);
-    tile_load<T, LMAX, TP>(A.P, lo, np, L, lds, P);
-    tile_load<T, LMAX, TP>(A.ybar, lo, np, L, lds, yb);
+        for (int k = 0; k < LMAX; ++k)
+            if (k < L) acc[0] += double(pr[k]) * double(S[k]);
+    }
+    // <ybar, s - y>
+    __syncthreads();
+    tile_copy_in<T, TP>(A.ybar + (size_t)lo * L, np * L, L, tq);
+    __syncthreads();
     if (act) {
-#pragma unroll
-        for (int k = 0; k < LMAX; ++k) {
-            if (k < L)
-                acc[0] += double(yb[k]) * ((k == sa ? 1.0 : 0.0) - double(y[k])) +
-                          double(pb[k]) * (double(S[k]) - double(P[k]));
-        }
+        const T *br = tq + threadIdx.x * Ls;
+        double d = double(br[sa]);
+        for (int k = 0; k < L; ++k) d -= double(br[k]) * double(yr[k]);
+        acc[0] += d;
     }
-    tile_store<T, LMAX, TP>(A.S, lo, np, L, lds, S);
-    block_sum<kNP, TP>(acc, red);
-    if (threadIdx.x < kNP) A.part[(size_t)tile * kNP + threadIdx.x] = acc[threadIdx.x];
+    // -<Pbar, P>
+    __syncthreads();
+    tile_copy_in<T, TP>(A.P + (size_t)lo * L, np * L, L, ty);
+    __syncthreads();
+    if (act) {
+        double d = 0.0;
+        for (int k = 0; k < L; ++k) d += double(pr[k]) * double(ty[threadIdx.x * Ls + k]);
+        acc[0] -= d;
+        T *out = tq + threadIdx.x * Ls;
+#pragma unroll
+        for (int k = 0; k < LMAX; ++k)
+            if (k < L) out[k] = S[k];
+    }
+    __syncthreads();
+    tile_copy_out<T, TP>(A.S + (size_t)lo * L, np * L, L, tq);
+    const double tot = block_sum_waves<kNP, TP>(acc, red);
+    if ((int)threadIdx.x < kNP) A.part[(size_t)tile * kNP + threadIdx.x] = tot;
 }
 
 struct StepBar {
@@ -310,9 +388,8 @@ k_step_adjoint(const double *__restrict__ part, const int *__restrict__ seg, int
                     -b1bar, b1bar};
     sb[img] = b;
     for (int m = 0; m < nk; ++m) {
-        const double *x = tot + 1 + 6 * m;
-        gw[(size_t)img * nk + m] +=
-            al * (x[0] + x[3]) + b.Bbar * (x[1] + x[4]) + b.Dbar * (x[2] + x[5]);
+        const double *x = tot + 1 + 3 * m;
+        gw[(size_t)img * nk + m] += x[0] + b.Bbar * x[1] + b.Dbar * x[2];
     }
     coef[((size_t)t * nimg + img) * 2 + 0] = b.cybar;
     coef[((size_t)t * nimg + img) * 2 + 1] = b.csbar;
@@ -558,7 +635,9 @@ void backward_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, int iters,
     }
     A.S = W.S.as<T>();
     A.part = W.part.as<double>();
+    A.stats = stats;
     for (int t = iters - 1; t >= 0; --t) {
+        A.t = t;
         A.s = ss + (size_t)t * N;
         A.y = ys + (size_t)t * NL;
         A.P = Ps + (size_t)t * NL;
@@ -649,8 +728,11 @@ template <typename T>
 void forward_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y, int iters,
                char *saved) {
     const SavedLayout lay = saved_layout(ctx, L, iters);
-    hipLaunchKernelGGL((k_softmax_neg<T>), dim3(seg_tiles(ctx, 256)), dim3(256),
-                       0, ctx->stream, ctx->seg.as<int>(), ctx->nimg, L, phi, y);
+    constexpr int TP = RowTile<T>::kPix;
+    DCRF_DISPATCH_ROWS(L, hipLaunchKernelGGL((k_softmax_neg<T, LMAX>),
+                                             dim3(seg_tiles(ctx, TP)), dim3(TP), 0,
+                                             ctx->stream, ctx->seg.as<int>(), ctx->nimg,
+                                             L, phi, y));
     DCRF_CHECK_LAUNCH();
     FWCheckpoint cp{saved + lay.y, saved + lay.P, reinterpret_cast<int32_t *>(saved + lay.s),
                     saved + lay.V, reinterpret_cast<double *>(saved + lay.stats)};

@@ -395,6 +395,27 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds) {
     __syncthreads();
 }
 
+// Block-wide sums of NV doubles per thread: a shuffle reduction inside each
+// 64-lane wave, then the waves' sums through LDS (NV x NT/64 doubles). Thread
+// i < NV returns the total of component i (fixed summation order).
+template <int NV, int NT>
+__device__ __forceinline__ double block_sum_waves(const double (&v)[NV], double *lds) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double x = v[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        if (lane == 0) lds[i * NW + w] = x;
+    }
+    __syncthreads();
+    double s = 0.0;
+    if ((int)threadIdx.x < NV)
+        for (int k = 0; k < NW; ++k) s += lds[threadIdx.x * NW + k];
+    return s;
+}
+
 // Calls BODY with LMAX bound to the smallest register-row size >= C.
 #define DCRF_DISPATCH_ROWS(C, BODY)                                 \
     do {                                                           \

@@ -96,6 +96,8 @@ struct FWArgs {
     int first;
     const int *seg;   // image segments, one block per tile of an image
     int nimg;
+    T *ysave, *Psave;   // checkpoint slots of y_t and P_t, or null
+    int32_t *ssave;     // checkpoint slot of s_t, or null
 };
 
 template <typename T>
@@ -161,6 +163,10 @@ k_fw_lmo_rows(FWArgs<T> A) {
             tile_store<T, LMAX, TP>(A.y, p0, np, L, lds, y);
             tile_store<T, LMAX, TP>(A.Py, p0, np, L, lds, py);
         }
+        if (A.ysave) {
+            tile_store<T, LMAX, TP>(A.ysave, p0, np, L, lds, y);
+            tile_store<T, LMAX, TP>(A.Psave, p0, np, L, lds, py);
+        }
         tile_load<T, LMAX, TP>(A.c, p0, np, L, lds, c);
         if (act) {
             int best = 0;
@@ -174,6 +180,7 @@ k_fw_lmo_rows(FWArgs<T> A) {
                 }
             }
             A.s[a] = best;
+            if (A.ssave) A.ssave[a] = best;
             acc[6] += (best != sp) ? 1.0 : 0.0;
 #pragma unroll
             for (int j = 0; j < LMAX; ++j) {
@@ -805,8 +812,13 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
     const bool potts = is_potts<T>(ctx, mu, L);
     const LatSet<T> ls = exact ? LatSet<T>{} : make_lat_set<T>(ctx, L);
     for (int it = 0; it < iters; ++it) {
+        // checkpoints are written by the row kernel itself; the flat kernel
+        // (more than 32 labels) leaves them to copies below
+        T *ysv = save && rows ? static_cast<T *>(save->y) + (size_t)it * NL : nullptr;
+        T *psv = save && rows ? static_cast<T *>(save->P) + (size_t)it * NL : nullptr;
+        int32_t *ssv = save && rows ? save->s + (size_t)it * N : nullptr;
         FWArgs<T> a{N, L, y, w.Py, w.Ps, w.c, w.s, w.sprev, w.scal, w.part1,
-                    it == 0 ? 1 : 0, seg, nimg};
+                    it == 0 ? 1 : 0, seg, nimg, ysv, psv, ssv};
         {
             ProfScope ps(ctx, PROF_FW_LMO);
             if (rows) {
@@ -818,7 +830,7 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
                                    st, a);
             }
         }
-        if (save) {   // y_t, P_t and s_t for the reverse sweep
+        if (save && !rows) {   // y_t, P_t and s_t for the reverse sweep
             DCRF_TRY_HIP(hipMemcpyAsync(static_cast<T *>(save->y) + (size_t)it * NL, y,
                                         NL * sizeof(T), hipMemcpyDeviceToDevice, st));
             DCRF_TRY_HIP(hipMemcpyAsync(static_cast<T *>(save->P) + (size_t)it * NL, w.Py,
