@@ -81,7 +81,8 @@ typedef struct {
 
 /* Launch shapes chosen by dcrf_autotune. */
 typedef struct {
-    int splat_chunk;              /* inverse-index entries per splat chunk    */
+    int splat_chunk;              /* entries per chunk of the one-hot splat   */
+    int dense_chunk;              /* entries per chunk of the dense splat     */
     int blur_vectors_per_thread;  /* 16-byte vectors per thread in the blur   */
     int blur_block;               /* threads per block of the blur            */
     int blur_group;               /* blur directions applied per launch       */
@@ -142,8 +143,9 @@ int dcrf_set_images(dcrf_ctx *ctx, int B, const int *H, const int *W,
 int dcrf_image_layout(dcrf_ctx *ctx, int *nimg, int *rows, int *seg);
 
 /* Pick the launch shapes of the filter (splats and slices by inverse-index
- * chunks and pixel rows, or by 16x16 pixel tiles; splat chunk length of 32,
- * 64 or 128 entries; in the blur 1, 2 or 3 directions per launch, 1 or 2
+ * chunks and pixel rows, or by 16x16 pixel tiles; chunk length of 32, 64 or
+ * 128 entries for the one-hot splat and of 16, 32 or 64 for the dense splat;
+ * in the blur 1, 2 or 3 directions per launch, 1 or 2
  * 16-byte vectors per thread and 128 or 256 threads per block) by timing,
  * for each candidate, `reps` (1..1000) runs of
  * a dense L-channel filter plus the one-hot splat, blur and slice of a
@@ -152,8 +154,9 @@ int dcrf_image_layout(dcrf_ctx *ctx, int *nimg, int *rows, int *seg);
  * same for every choice up to floating-point summation order. */
 int dcrf_autotune(dcrf_ctx *ctx, int L, int reps, dcrf_tune *out);
 
-/* Set the launch shapes directly (the `ms` field is ignored): splat_chunk in
- * {16, 32, 64, 128, 256}, blur_vectors_per_thread in 1..4, blur_block in
+/* Set the launch shapes directly (the `ms` field is ignored): splat_chunk and
+ * dense_chunk in {16, 32, 64, 128, 256}, blur_vectors_per_thread in 1..4,
+ * blur_block in
  * {64, 128, 256}, blur_group in 1..3, tiles 0 or 1; DCRF_EINVAL otherwise.
  * Results are the same for every choice up to floating-point summation
  * order. */

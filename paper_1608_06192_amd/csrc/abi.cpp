@@ -211,6 +211,7 @@ int dcrf_autotune(dcrf_ctx *ctx, int L, int reps, dcrf_tune *out) {
         dcrf::autotune(ctx, L, reps, &ms);
         if (out) {
             out->splat_chunk = ctx->splat_chunk;
+            out->dense_chunk = ctx->dense_chunk;
             out->blur_vectors_per_thread = ctx->blur_vpt;
             out->blur_block = ctx->blur_block;
             out->blur_group = ctx->blur_group;
@@ -224,16 +225,17 @@ int dcrf_set_tune(dcrf_ctx *ctx, const dcrf_tune *t) {
     return guarded(ctx, [&] {
         require_image(ctx);
         REQUIRE(t != nullptr, "null argument");
-        const int c = t->splat_chunk;
-        REQUIRE(c == 16 || c == 32 || c == 64 || c == 128 || c == 256,
-                "splat_chunk must be 16, 32, 64, 128 or 256");
+        auto chunk_ok = [](int c) { return c == 16 || c == 32 || c == 64 || c == 128 || c == 256; };
+        REQUIRE(chunk_ok(t->splat_chunk) && chunk_ok(t->dense_chunk),
+                "splat_chunk and dense_chunk must be 16, 32, 64, 128 or 256");
         REQUIRE(t->blur_vectors_per_thread >= 1 && t->blur_vectors_per_thread <= 4,
                 "blur_vectors_per_thread must be in 1..4");
         REQUIRE(t->blur_block == 64 || t->blur_block == 128 || t->blur_block == 256,
                 "blur_block must be 64, 128 or 256");
         REQUIRE(t->blur_group >= 1 && t->blur_group <= 3, "blur_group must be in 1..3");
         REQUIRE(t->tiles == 0 || t->tiles == 1, "tiles must be 0 or 1");
-        if (c != ctx->splat_chunk) dcrf::rechunk(ctx, c);
+        if (t->splat_chunk != ctx->splat_chunk || t->dense_chunk != ctx->dense_chunk)
+            dcrf::rechunk(ctx, t->splat_chunk, t->dense_chunk);
         ctx->blur_vpt = t->blur_vectors_per_thread;
         ctx->blur_block = t->blur_block;
         ctx->blur_group = t->blur_group;

@@ -214,7 +214,7 @@ void build_batch(dcrf_ctx *ctx, int B, const int *H, const int *W,
     ctx->W = 0;
     ctx->img_H.assign(H, H + B);
     ctx->img_W.assign(W, W + B);
-    rechunk(ctx, ctx->splat_chunk);
+    rechunk(ctx, ctx->splat_chunk, ctx->dense_chunk);
     set_segments(ctx, seg);
 }
 
@@ -243,18 +243,20 @@ void autotune(dcrf_ctx *ctx, int L, int reps, double *best_ms) {
     hipEvent_t e0, e1;
     DCRF_TRY_HIP(hipEventCreate(&e0));
     DCRF_TRY_HIP(hipEventCreate(&e1));
-    struct Cand { int chunk, vpt, block, group, tiles; };
+    struct Cand { int chunk, dense, vpt, block, group, tiles; };
     std::vector<Cand> cands;
     for (int tiles : {0, 1})
         for (int chunk : {32, 64, 128})
-            for (int vpt : {1, 2})
-                for (int block : {128, 256})
-                    for (int group : {1, 2, 3}) {
-                        if (tiles && chunk != 64) continue;   // chunks unused
-                        cands.push_back({chunk, vpt, block, group, tiles});
-                    }
-    Cand best = {ctx->splat_chunk, ctx->blur_vpt, ctx->blur_block, ctx->blur_group,
-                 ctx->tile_mode};
+            for (int dense : {16, 32, 64})
+                for (int vpt : {1, 2})
+                    for (int block : {128, 256})
+                        for (int group : {1, 2, 3}) {
+                            // the tile kernels use no chunks
+                            if (tiles && (chunk != 64 || dense != 32)) continue;
+                            cands.push_back({chunk, dense, vpt, block, group, tiles});
+                        }
+    Cand best = {ctx->splat_chunk, ctx->dense_chunk, ctx->blur_vpt, ctx->blur_block,
+                 ctx->blur_group, ctx->tile_mode};
     double best_t = 1e300;
     auto run = [&] {
         // the dense filter and the one-hot path of a Frank-Wolfe iteration
@@ -266,7 +268,8 @@ void autotune(dcrf_ctx *ctx, int L, int reps, double *best_ms) {
     };
     try {
         for (const Cand &c : cands) {
-            if (c.chunk != ctx->splat_chunk) rechunk(ctx, c.chunk);
+            if (c.chunk != ctx->splat_chunk || c.dense != ctx->dense_chunk)
+                rechunk(ctx, c.chunk, c.dense);
             ctx->blur_vpt = c.vpt;
             ctx->blur_block = c.block;
             ctx->blur_group = c.group;
@@ -293,7 +296,8 @@ void autotune(dcrf_ctx *ctx, int L, int reps, double *best_ms) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ctx->prof.on = prof;
-    if (best.chunk != ctx->splat_chunk) rechunk(ctx, best.chunk);
+    if (best.chunk != ctx->splat_chunk || best.dense != ctx->dense_chunk)
+        rechunk(ctx, best.chunk, best.dense);
     ctx->blur_vpt = best.vpt;
     ctx->blur_block = best.block;
     ctx->blur_group = best.group;

@@ -92,6 +92,9 @@ struct Lattice {
     DevBuf chunks;       // nchunks x int4 (vertex, begin, end, 0), ordered by first pixel
     int nchunks = 0;
     int chunk = 32;
+    DevBuf dchunks;      // the same with at most dchunk entries (dense splat)
+    int ndchunks = 0;
+    int dchunk = 32;
     // grouped blur: for blur directions taken G at a time, per group and
     // vertex the 3^G vertices reached by the paths of the group (-1 where a
     // path leaves the lattice); [0] forward order, [1] the transpose's order
@@ -112,7 +115,7 @@ struct Lattice {
     void release() {
         for (DevBuf *b : {&hkeys, &slot_vid, &pix_slot, &pix_vid, &pix_w,
                           &vkeys, &nbr, &V[0], &V[1], &V[2], &feat, &csr_off,
-                          &csr_tmp, &ent_pix, &ent_w, &ent_v, &chunk_off, &chunks,
+                          &csr_tmp, &ent_pix, &ent_w, &ent_v, &chunk_off, &chunks, &dchunks,
                           &gtab[0], &gtab[1], &ts_off, &ts_vid, &tr_slot, &sr_off,
                           &sr_pix, &sr_w, &sr_slot, &vs_off, &vs_slot})
             b->release();
@@ -213,7 +216,8 @@ struct dcrf_ctx {
     dcrf_kernel kern[DCRF_MAXK];
     dcrf::Lattice lat[DCRF_MAXK];
     double wsum = 0;
-    int splat_chunk = 64;    // entries per splat chunk (one wave of the label splat)
+    int splat_chunk = 64;    // entries per chunk of the one-hot splat (one wave)
+    int dense_chunk = 32;    // entries per chunk of the dense splat
     dcrf::DevBuf r;          // N x T: K'1
     dcrf::DevBuf scratch;    // small device scratch (flags, counters)
     dcrf::DevBuf tmpA, tmpB; // N x C scratch arrays
@@ -236,7 +240,8 @@ void build_lattices(dcrf_ctx *ctx, const float *rgb);
 void lattice_export(dcrf_ctx *ctx, int m, int32_t *keys, int32_t *vid,
                     double *w);
 // cut every lattice's inverse index into chunks of at most `chunk` entries
-void rechunk(dcrf_ctx *ctx, int chunk);
+// (one-hot splat) and of `dense_chunk` entries (dense splat)
+void rechunk(dcrf_ctx *ctx, int chunk, int dense_chunk);
 
 // filter.hip
 // out = K' in (N x C), lattice or exact, optionally the transpose

@@ -47,7 +47,7 @@ k_splat_gather(int C, const T *__restrict__ Y, LatSet<T> ls) {
     const unsigned r = unsigned(e - ls.coff[m]);
     const int ch = int(r / unsigned(C));
     const int c = int(r - unsigned(ch) * unsigned(C));
-    const int4 cd = L.chunks[ch];
+    const int4 cd = L.dchunks[ch];
     T acc0 = T(0), acc1 = T(0), acc2 = T(0), acc3 = T(0);
     int i = cd.y;
     for (; i + 4 <= cd.z; i += 4) {   // four independent loads in flight

@@ -14,6 +14,7 @@ struct LatView {
     T *V0, *V1, *V2;     // M x ld: splat target, ping, pong
     const T *Vf;         // the buffer that holds the blurred values
     const int4 *chunks;  // inverse-index chunks (vertex, begin, end, 0)
+    const int4 *dchunks; // the chunks of the dense splat
     const int32_t *ent_pix;
     const T *ent_w;
     const int32_t *ent_v;
@@ -33,7 +34,7 @@ template <typename T>
 struct LatSet {
     LatView<T> l[DCRF_MAXK];
     long long off[DCRF_MAXK + 1];   // prefix sums of M_m * ld (blur)
-    long long coff[DCRF_MAXK + 1];  // prefix sums of nchunks_m * C (splat)
+    long long coff[DCRF_MAXK + 1];  // prefix sums of ndchunks_m * C (dense splat)
     long long eoff[DCRF_MAXK + 1];  // prefix sums of the entries
     long long choff[DCRF_MAXK + 1]; // prefix sums of nchunks_m (label splat)
     long long soff[DCRF_MAXK + 1];  // prefix sums of nslots_m (tile splat)
@@ -85,6 +86,7 @@ inline LatSet<T> make_lat_set(dcrf_ctx *ctx, int C) {
         v.sr_w = L.sr_w.as<T>();
         v.nslots = L.nslots;
         v.chunks = L.chunks.as<int4>();
+        v.dchunks = L.dchunks.as<int4>();
         v.ent_pix = L.ent_pix.as<int32_t>();
         v.ent_w = L.ent_w.as<T>();
         v.ent_v = L.ent_v.as<int32_t>();
@@ -94,7 +96,7 @@ inline LatSet<T> make_lat_set(dcrf_ctx *ctx, int C) {
         v.nchunks = L.nchunks;
         v.wg = T(ctx->kern[m].weight * L.gamma);
         s.off[m + 1] = s.off[m] + (long long)L.M * ld;
-        s.coff[m + 1] = s.coff[m] + (long long)L.nchunks * C;
+        s.coff[m + 1] = s.coff[m] + (long long)L.ndchunks * C;
         s.eoff[m + 1] = s.eoff[m] + (long long)L.nent;
         s.choff[m + 1] = s.choff[m] + (long long)L.nchunks;
         s.soff[m + 1] = s.soff[m] + (long long)L.nslots;

@@ -386,6 +386,7 @@ void build_inverse_index(dcrf_ctx *ctx, int m) {
     const int M = L.M, D1 = L.d + 1;
     const size_t cnt = (size_t)ctx->N * D1;
     L.chunk = ctx->splat_chunk;
+    L.dchunk = ctx->dense_chunk;
     L.csr_off.ensure((size_t)(M + 1) * 4, s);
     L.csr_tmp.ensure((size_t)(M + 1) * 4, s);
     L.ent_pix.ensure(cnt * 4, s);
@@ -423,31 +424,32 @@ void build_inverse_index(dcrf_ctx *ctx, int m) {
 }
 
 // chunk list of lattice m from its inverse index (csr_off) and L.chunk
-void chunk_index(dcrf_ctx *ctx, int m) {
+// a chunk list of lattice m from its inverse index (csr_off): chunks of at
+// most `len` entries, ordered by their first pixel (the splats then walk the
+// image roughly in raster order, and with the XCD mapping of their blocks
+// each L2 sees one band of the image's rows)
+void chunk_list(dcrf_ctx *ctx, int m, int len, DevBuf &out, int &count) {
     Lattice &L = ctx->lat[m];
     const hipStream_t s = ctx->stream;
     const int M = L.M;
     int *counts = L.csr_tmp.as<int>();
     if (M > 0)
         hipLaunchKernelGGL(k_chunk_count, dim3(ceil_div(M, 256)), dim3(256), 0, s,
-                           M, L.csr_off.as<int>(), L.chunk, counts);
+                           M, L.csr_off.as<int>(), len, counts);
     L.chunk_off.ensure((size_t)(M + 1) * 4, s);
     scan_ints(ctx, counts, M, L.chunk_off.as<int>());
     int nch = 0;
     DCRF_TRY_HIP(hipMemcpyAsync(&nch, L.chunk_off.as<int>() + M, 4,
                                 hipMemcpyDeviceToHost, s));
     DCRF_TRY_HIP(hipStreamSynchronize(s));
-    L.nchunks = nch;
-    L.chunks.ensure((size_t)std::max(nch, 1) * sizeof(int4), s);
+    count = nch;
+    out.ensure((size_t)std::max(nch, 1) * sizeof(int4), s);
     if (M > 0)
         hipLaunchKernelGGL(k_chunk_fill, dim3(ceil_div(M, 256)), dim3(256), 0, s,
-                           M, L.csr_off.as<int>(), L.chunk_off.as<int>(), L.chunk,
-                           L.chunks.as<int4>());
+                           M, L.csr_off.as<int>(), L.chunk_off.as<int>(), len,
+                           out.as<int4>());
     DCRF_CHECK_LAUNCH();
     if (nch <= 1) return;
-    // order the chunks by their first pixel: the splats then walk the image
-    // roughly in raster order, and with the XCD mapping of their blocks each
-    // L2 sees one band of the image's rows
     DevBuf k0, k1, v0, v1, temp, tmp;
     struct Free {
         DevBuf *b[6];
@@ -456,16 +458,24 @@ void chunk_index(dcrf_ctx *ctx, int m) {
     for (DevBuf *b : {&k0, &k1, &v0, &v1}) b->ensure((size_t)nch * 4, s);
     tmp.ensure((size_t)nch * sizeof(int4), s);
     hipLaunchKernelGGL(k_chunk_keys, dim3(ceil_div(nch, 256)), dim3(256), 0, s, nch,
-                       L.chunks.as<int4>(), L.ent_pix.as<int>(), k0.as<uint32_t>(),
+                       out.as<int4>(), L.ent_pix.as<int>(), k0.as<uint32_t>(),
                        v0.as<uint32_t>());
     sort_pairs(ctx, k0.as<uint32_t>(), k1.as<uint32_t>(), v0.as<uint32_t>(),
                v1.as<uint32_t>(), nch, key_bits((unsigned long long)ctx->N), temp);
-    DCRF_TRY_HIP(hipMemcpyAsync(tmp.p, L.chunks.p, (size_t)nch * sizeof(int4),
+    DCRF_TRY_HIP(hipMemcpyAsync(tmp.p, out.p, (size_t)nch * sizeof(int4),
                                 hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(k_chunk_permute, dim3(ceil_div(nch, 256)), dim3(256), 0, s, nch,
-                       v1.as<uint32_t>(), tmp.as<int4>(), L.chunks.as<int4>());
+                       v1.as<uint32_t>(), tmp.as<int4>(), out.as<int4>());
     DCRF_CHECK_LAUNCH();
     DCRF_TRY_HIP(hipStreamSynchronize(s));
+}
+
+// both chunk lists of lattice m: for the one-hot splat (L.chunk entries) and
+// for the dense splat (L.dchunk entries)
+void chunk_index(dcrf_ctx *ctx, int m) {
+    Lattice &L = ctx->lat[m];
+    chunk_list(ctx, m, L.chunk, L.chunks, L.nchunks);
+    chunk_list(ctx, m, L.dchunk, L.dchunks, L.ndchunks);
 }
 
 template <int D, typename T>
@@ -568,15 +578,17 @@ void build_lattices(dcrf_ctx *ctx, const float *rgb) {
         build_all<float>(ctx, rgb);
 }
 
-void rechunk(dcrf_ctx *ctx, int chunk) {
+void rechunk(dcrf_ctx *ctx, int chunk, int dense_chunk) {
     int maxM = 0;
     for (int m = 0; m < ctx->nk; ++m) maxM = std::max(maxM, ctx->lat[m].M);
     // flags, then the tile sums of the scan over M + 1 counts
     ctx->scratch.ensure(64 + (size_t)(ceil_div((long long)maxM + 1, kScanTile) + 2) * 4,
                         ctx->stream);
     ctx->splat_chunk = chunk;
+    ctx->dense_chunk = dense_chunk;
     for (int m = 0; m < ctx->nk; ++m) {
         ctx->lat[m].chunk = chunk;
+        ctx->lat[m].dchunk = dense_chunk;
         chunk_index(ctx, m);
     }
 }

@@ -42,7 +42,7 @@ class dcrf_iter_trace(ctypes.Structure):
 
 
 class dcrf_tune(ctypes.Structure):
-    _fields_ = [("splat_chunk", ctypes.c_int),
+    _fields_ = [("splat_chunk", ctypes.c_int), ("dense_chunk", ctypes.c_int),
                 ("blur_vectors_per_thread", ctypes.c_int),
                 ("blur_block", ctypes.c_int), ("blur_group", ctypes.c_int),
                 ("tiles", ctypes.c_int), ("ms", ctypes.c_double)]
@@ -135,7 +135,9 @@ class Context:
         self.nimg, self.seg = 1, []
 
     def __del__(self):
-        if getattr(self, "_h", None) and self._h.value:
+        # at interpreter exit the module globals may already be gone; the
+        # process end releases the device memory then
+        if _lib is not None and getattr(self, "_h", None) and self._h.value:
             _lib.dcrf_destroy(self._h)
             self._h = ctypes.c_void_p()
 
@@ -203,8 +205,8 @@ class Context:
         return [packed[a:b] for a, b in self.seg]
 
     def set_tune(self, splat_chunk=64, blur_vectors_per_thread=1,
-                 blur_block=256, blur_group=2, tiles=0, **_):
-        t = dcrf_tune(splat_chunk, blur_vectors_per_thread, blur_block,
+                 blur_block=256, blur_group=2, tiles=0, dense_chunk=32, **_):
+        t = dcrf_tune(splat_chunk, dense_chunk, blur_vectors_per_thread, blur_block,
                       blur_group, tiles, 0.0)
         self._stream()
         self._check(_lib.dcrf_set_tune(self._h, ctypes.byref(t)))
@@ -213,7 +215,7 @@ class Context:
         t = dcrf_tune()
         self._stream()
         self._check(_lib.dcrf_autotune(self._h, L, reps, ctypes.byref(t)))
-        return dict(splat_chunk=t.splat_chunk,
+        return dict(splat_chunk=t.splat_chunk, dense_chunk=t.dense_chunk,
                     blur_vectors_per_thread=t.blur_vectors_per_thread,
                     blur_block=t.blur_block, blur_group=t.blur_group,
                     tiles=t.tiles, ms=t.ms)

@@ -332,8 +332,12 @@ def test_errors_are_reported_not_fatal():
 
 
 @pytest.mark.parametrize("tune", [
-    dict(splat_chunk=16, blur_vectors_per_thread=1, blur_block=64, blur_group=1),
-    dict(splat_chunk=128, blur_vectors_per_thread=2, blur_block=128, blur_group=2),
+    dict(splat_chunk=16, blur_vectors_per_thread=1, blur_block=64, blur_group=1,
+         dense_chunk=16),
+    dict(splat_chunk=128, blur_vectors_per_thread=2, blur_block=128, blur_group=2,
+         dense_chunk=128),
+    dict(splat_chunk=64, blur_vectors_per_thread=1, blur_block=256, blur_group=2,
+         dense_chunk=256),
     dict(splat_chunk=256, blur_vectors_per_thread=4, blur_block=256, blur_group=3),
     dict(splat_chunk=32, blur_vectors_per_thread=3, blur_block=256, blur_group=3),
     dict(splat_chunk=64, blur_vectors_per_thread=1, blur_block=256, blur_group=2,
