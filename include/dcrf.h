@@ -83,6 +83,9 @@ typedef struct {
 typedef struct {
     int splat_chunk;              /* entries per chunk of the one-hot splat   */
     int dense_chunk;              /* entries per chunk of the dense splat     */
+    int splat_stage;              /* 1: the dense splat stages the pairs of a
+                                     block's chunks in LDS; 0: each lane
+                                     reads them from global memory          */
     int blur_vectors_per_thread;  /* 16-byte vectors per thread in the blur   */
     int blur_block;               /* threads per block of the blur            */
     int blur_group;               /* blur directions applied per launch       */
@@ -142,22 +145,22 @@ int dcrf_set_images(dcrf_ctx *ctx, int B, const int *H, const int *W,
  * the last row of each image. Any pointer may be NULL. */
 int dcrf_image_layout(dcrf_ctx *ctx, int *nimg, int *rows, int *seg);
 
-/* Pick the launch shapes of the filter (splats and slices by inverse-index
- * chunks and pixel rows, or by 16x16 pixel tiles; chunk length of 32, 64 or
- * 128 entries for the one-hot splat and of 16, 32 or 64 for the dense splat;
- * in the blur 1, 2 or 3 directions per launch, 1 or 2
- * 16-byte vectors per thread and 128 or 256 threads per block) by timing,
- * for each candidate, `reps` (1..1000) runs of
- * a dense L-channel filter plus the one-hot splat, blur and slice of a
- * Frank-Wolfe iteration on the context's own lattices; keeps the fastest.
+/* Pick the launch shapes of the filter by timing, for each candidate, `reps`
+ * (1..1000) runs of a dense L-channel filter plus the one-hot splat, blur and
+ * slice of a Frank-Wolfe iteration on the context's own lattices, in two
+ * rounds: first splats and slices by inverse-index chunks and pixel rows or
+ * by 16x16 pixel tiles, one-hot chunks of 32, 64 or 128 entries, and in the
+ * blur 1, 2 or 3 directions per launch, 1 or 2 16-byte vectors per thread and
+ * 128 or 256 threads per block; then (without tiles) dense chunks of 16, 32
+ * or 64 entries, with or without staging in LDS. Keeps the fastest.
  * *out (host, may be NULL) receives the choice. Results of every call are the
  * same for every choice up to floating-point summation order. */
 int dcrf_autotune(dcrf_ctx *ctx, int L, int reps, dcrf_tune *out);
 
 /* Set the launch shapes directly (the `ms` field is ignored): splat_chunk and
- * dense_chunk in {16, 32, 64, 128, 256}, blur_vectors_per_thread in 1..4,
- * blur_block in
- * {64, 128, 256}, blur_group in 1..3, tiles 0 or 1; DCRF_EINVAL otherwise.
+ * dense_chunk in {16, 32, 64, 128, 256}, splat_stage 0 or 1,
+ * blur_vectors_per_thread in 1..4, blur_block in {64, 128, 256}, blur_group
+ * in 1..3, tiles 0 or 1; DCRF_EINVAL otherwise.
  * Results are the same for every choice up to floating-point summation
  * order. */
 int dcrf_set_tune(dcrf_ctx *ctx, const dcrf_tune *tune);

@@ -212,6 +212,7 @@ int dcrf_autotune(dcrf_ctx *ctx, int L, int reps, dcrf_tune *out) {
         if (out) {
             out->splat_chunk = ctx->splat_chunk;
             out->dense_chunk = ctx->dense_chunk;
+            out->splat_stage = ctx->splat_lds;
             out->blur_vectors_per_thread = ctx->blur_vpt;
             out->blur_block = ctx->blur_block;
             out->blur_group = ctx->blur_group;
@@ -234,8 +235,10 @@ int dcrf_set_tune(dcrf_ctx *ctx, const dcrf_tune *t) {
                 "blur_block must be 64, 128 or 256");
         REQUIRE(t->blur_group >= 1 && t->blur_group <= 3, "blur_group must be in 1..3");
         REQUIRE(t->tiles == 0 || t->tiles == 1, "tiles must be 0 or 1");
+        REQUIRE(t->splat_stage == 0 || t->splat_stage == 1, "splat_stage must be 0 or 1");
         if (t->splat_chunk != ctx->splat_chunk || t->dense_chunk != ctx->dense_chunk)
             dcrf::rechunk(ctx, t->splat_chunk, t->dense_chunk);
+        ctx->splat_lds = t->splat_stage;
         ctx->blur_vpt = t->blur_vectors_per_thread;
         ctx->blur_block = t->blur_block;
         ctx->blur_group = t->blur_group;

@@ -243,20 +243,18 @@ void autotune(dcrf_ctx *ctx, int L, int reps, double *best_ms) {
     hipEvent_t e0, e1;
     DCRF_TRY_HIP(hipEventCreate(&e0));
     DCRF_TRY_HIP(hipEventCreate(&e1));
-    struct Cand { int chunk, dense, vpt, block, group, tiles; };
-    std::vector<Cand> cands;
-    for (int tiles : {0, 1})
-        for (int chunk : {32, 64, 128})
-            for (int dense : {16, 32, 64})
-                for (int vpt : {1, 2})
-                    for (int block : {128, 256})
-                        for (int group : {1, 2, 3}) {
-                            // the tile kernels use no chunks
-                            if (tiles && (chunk != 64 || dense != 32)) continue;
-                            cands.push_back({chunk, dense, vpt, block, group, tiles});
-                        }
-    Cand best = {ctx->splat_chunk, ctx->dense_chunk, ctx->blur_vpt, ctx->blur_block,
-                 ctx->blur_group, ctx->tile_mode};
+    struct Cand { int chunk, dense, stage, vpt, block, group, tiles; };
+    auto apply = [&](const Cand &c) {
+        if (c.chunk != ctx->splat_chunk || c.dense != ctx->dense_chunk)
+            rechunk(ctx, c.chunk, c.dense);
+        ctx->splat_lds = c.stage;
+        ctx->blur_vpt = c.vpt;
+        ctx->blur_block = c.block;
+        ctx->blur_group = c.group;
+        ctx->tile_mode = c.tiles;
+    };
+    Cand best = {ctx->splat_chunk, ctx->dense_chunk, ctx->splat_lds, ctx->blur_vpt,
+                 ctx->blur_block, ctx->blur_group, ctx->tile_mode};
     double best_t = 1e300;
     auto run = [&] {
         // the dense filter and the one-hot path of a Frank-Wolfe iteration
@@ -266,14 +264,9 @@ void autotune(dcrf_ctx *ctx, int L, int reps, double *best_ms) {
         slice_into(ctx, ctx->tmpA.p, nullptr, L, nullptr, nullptr, ctx->tmpB.p,
                    false);
     };
-    try {
+    auto measure = [&](const std::vector<Cand> &cands) {
         for (const Cand &c : cands) {
-            if (c.chunk != ctx->splat_chunk || c.dense != ctx->dense_chunk)
-                rechunk(ctx, c.chunk, c.dense);
-            ctx->blur_vpt = c.vpt;
-            ctx->blur_block = c.block;
-            ctx->blur_group = c.group;
-            ctx->tile_mode = c.tiles;
+            apply(c);
             run();
             DCRF_TRY_HIP(hipEventRecord(e0, s));
             for (int r = 0; r < reps; ++r) run();
@@ -287,6 +280,33 @@ void autotune(dcrf_ctx *ctx, int L, int reps, double *best_ms) {
                 best = c;
             }
         }
+    };
+    try {
+        // first the blur shape, the tiling and the one-hot chunks, then the
+        // dense splat's chunks and staging (which only the dense filter uses)
+        std::vector<Cand> cands;
+        for (int tiles : {0, 1})
+            for (int chunk : {32, 64, 128})
+                for (int vpt : {1, 2})
+                    for (int block : {128, 256})
+                        for (int group : {1, 2, 3}) {
+                            if (tiles && chunk != 64) continue;   // no chunks used
+                            cands.push_back({chunk, best.dense, best.stage, vpt, block,
+                                             group, tiles});
+                        }
+        measure(cands);
+        if (!best.tiles) {
+            cands.clear();
+            for (int dense : {16, 32, 64})
+                for (int stage : {0, 1}) {
+                    Cand c = best;
+                    c.dense = dense;
+                    c.stage = stage;
+                    cands.push_back(c);
+                }
+            best_t = 1e300;
+            measure(cands);
+        }
     } catch (...) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -296,12 +316,7 @@ void autotune(dcrf_ctx *ctx, int L, int reps, double *best_ms) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ctx->prof.on = prof;
-    if (best.chunk != ctx->splat_chunk || best.dense != ctx->dense_chunk)
-        rechunk(ctx, best.chunk, best.dense);
-    ctx->blur_vpt = best.vpt;
-    ctx->blur_block = best.block;
-    ctx->blur_group = best.group;
-    ctx->tile_mode = best.tiles;
+    apply(best);
     if (best_ms) *best_ms = best_t;
 }
 

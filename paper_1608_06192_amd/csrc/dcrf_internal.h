@@ -218,6 +218,7 @@ struct dcrf_ctx {
     double wsum = 0;
     int splat_chunk = 64;    // entries per chunk of the one-hot splat (one wave)
     int dense_chunk = 32;    // entries per chunk of the dense splat
+    int splat_lds = 1;       // dense splat: stage each block's pairs in LDS
     dcrf::DevBuf r;          // N x T: K'1
     dcrf::DevBuf scratch;    // small device scratch (flags, counters)
     dcrf::DevBuf tmpA, tmpB; // N x C scratch arrays

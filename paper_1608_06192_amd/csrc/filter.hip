@@ -34,19 +34,19 @@ namespace {
 
 // ------------------------------------------------------------------ splat
 
-// lane (chunk, c), flattened over the lattices: V0[v][c] += sum w * Y[pix][c]
+// lane (chunk, c): V0[v][c] += sum w * Y[pix][c]; block b of a lattice takes
+// its chunks b q .. b q + q - 1 (q = dense_splat_q: chunks of C lanes)
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_splat_gather(int C, const T *__restrict__ Y, LatSet<T> ls) {
-    const long long e =
-        (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (e >= ls.coff[ls.nk]) return;
-    int m = 0;
-    while (m + 1 < ls.nk && e >= ls.coff[m + 1]) ++m;
+k_splat_gather(int C, int q, const T *__restrict__ Y, LatSet<T> ls) {
+    const long long b0 = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x;
+    int m = 0;   // uniform: each lattice's blocks start at a multiple of 256 lanes
+    while (m + 1 < ls.nk && b0 >= ls.coff[m + 1]) ++m;
     const LatView<T> &L = ls.l[m];
-    const unsigned r = unsigned(e - ls.coff[m]);
-    const int ch = int(r / unsigned(C));
-    const int c = int(r - unsigned(ch) * unsigned(C));
+    const int k = threadIdx.x / C;
+    const int ch = int((b0 - ls.coff[m]) / 256) * q + k;
+    if (k >= q || ch >= L.ndchunks) return;
+    const int c = threadIdx.x - k * C;
     const int4 cd = L.dchunks[ch];
     T acc0 = T(0), acc1 = T(0), acc2 = T(0), acc3 = T(0);
     int i = cd.y;
@@ -57,6 +57,54 @@ k_splat_gather(int C, const T *__restrict__ Y, LatSet<T> ls) {
         acc3 += L.ent_w[i + 3] * Y[(size_t)L.ent_pix[i + 3] * C + c];
     }
     for (; i < cd.z; ++i) acc0 += L.ent_w[i] * Y[(size_t)L.ent_pix[i] * C + c];
+    const T acc = (acc0 + acc1) + (acc2 + acc3);
+    if (acc != T(0)) atomic_add(&L.V0[(size_t)cd.x * L.ld + c], acc);
+}
+
+// The same with the block's chunks staged in LDS: block b takes q <= 256 / C
+// consecutive chunks (lane = chunk * C + channel, q U <= kSplatStage). Their (pixel, weight)
+// pairs are copied to LDS with contiguous loads first, so that the only
+// per-lane global loads left are those of the input values; the C lanes of a
+// chunk would otherwise each load the same pair.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_splat_gather_lds(int C, int q, int U, const T *__restrict__ Y, LatSet<T> ls) {
+    __shared__ int spix[kSplatStage];
+    __shared__ T sw[kSplatStage];
+    __shared__ int4 scd[256];
+    const long long b0 = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x;
+    int m = 0;   // uniform: each lattice's blocks start at a multiple of 256 lanes
+    while (m + 1 < ls.nk && b0 >= ls.coff[m + 1]) ++m;
+    const LatView<T> &L = ls.l[m];
+    const int ch0 = int((b0 - ls.coff[m]) / 256) * q;
+    const int nq = min(q, L.ndchunks - ch0);
+    const int t = threadIdx.x;
+    if (t < nq) scd[t] = L.dchunks[ch0 + t];
+    __syncthreads();
+    for (int i = t; i < nq * U; i += 256) {
+        const int k = i / U, j = i - (i / U) * U;
+        const int4 cd = scd[k];
+        if (cd.y + j < cd.z) {
+            spix[i] = L.ent_pix[cd.y + j];
+            sw[i] = L.ent_w[cd.y + j];
+        }
+    }
+    __syncthreads();
+    const int k = t / C, c = t - (t / C) * C;
+    if (k >= nq) return;
+    const int4 cd = scd[k];
+    const int n = cd.z - cd.y;
+    const int *pk = spix + k * U;
+    const T *wk = sw + k * U;
+    T acc0 = T(0), acc1 = T(0), acc2 = T(0), acc3 = T(0);
+    int j = 0;
+    for (; j + 4 <= n; j += 4) {
+        acc0 += wk[j + 0] * Y[(size_t)pk[j + 0] * C + c];
+        acc1 += wk[j + 1] * Y[(size_t)pk[j + 1] * C + c];
+        acc2 += wk[j + 2] * Y[(size_t)pk[j + 2] * C + c];
+        acc3 += wk[j + 3] * Y[(size_t)pk[j + 3] * C + c];
+    }
+    for (; j < n; ++j) acc0 += wk[j] * Y[(size_t)pk[j] * C + c];
     const T acc = (acc0 + acc1) + (acc2 + acc3);
     if (acc != T(0)) atomic_add(&L.V0[(size_t)cd.x * L.ld + c], acc);
 }
@@ -766,8 +814,14 @@ void splat_set(dcrf_ctx *ctx, const LatSet<T> &ls, const T *in, int C) {
     }
     const long long total = ls.coff[ls.nk];
     if (total == 0) return;
-    hipLaunchKernelGGL((k_splat_gather<T>), dim3(ceil_div(total, 256)), dim3(256), 0, s,
-                       C, in, ls);
+    if (C > 256) fail(DCRF_EUNSUPPORTED, "the dense splat takes at most 256 channels");
+    const dim3 grid(ceil_div(total, 256));
+    const int q = dense_splat_q(ctx, C);
+    if (ctx->splat_lds)
+        hipLaunchKernelGGL((k_splat_gather_lds<T>), grid, dim3(256), 0, s, C, q,
+                           ctx->dense_chunk, in, ls);
+    else
+        hipLaunchKernelGGL((k_splat_gather<T>), grid, dim3(256), 0, s, C, q, in, ls);
     DCRF_CHECK_LAUNCH();
 }
 

@@ -18,7 +18,7 @@ struct LatView {
     const int32_t *ent_pix;
     const T *ent_w;
     const int32_t *ent_v;
-    int d, M, ld, nchunks;
+    int d, M, ld, nchunks, ndchunks;
     T wg;                // w_m * gamma_m
     const int32_t *gt;   // grouped-blur path table of the direction in use
     int ngrp;            // blur launches of this lattice
@@ -34,7 +34,8 @@ template <typename T>
 struct LatSet {
     LatView<T> l[DCRF_MAXK];
     long long off[DCRF_MAXK + 1];   // prefix sums of M_m * ld (blur)
-    long long coff[DCRF_MAXK + 1];  // prefix sums of ndchunks_m * C (dense splat)
+    long long coff[DCRF_MAXK + 1];  // dense splat: prefix sums of 256 lanes per
+                                    // block of 256 / C chunks (one lattice a block)
     long long eoff[DCRF_MAXK + 1];  // prefix sums of the entries
     long long choff[DCRF_MAXK + 1]; // prefix sums of nchunks_m (label splat)
     long long soff[DCRF_MAXK + 1];  // prefix sums of nslots_m (tile splat)
@@ -50,6 +51,17 @@ struct ExactSet {
     T w[DCRF_MAXK];
     int nk;
 };
+
+// Pairs staged in LDS per block by the staged gather splat.
+constexpr int kSplatStage = 1024;
+
+// Chunks per block of 256 lanes in the dense splat (C lanes per chunk); the
+// staged splat keeps their pairs within kSplatStage.
+inline int dense_splat_q(const dcrf_ctx *ctx, int C) {
+    int q = C <= 256 ? 256 / C : 1;
+    if (ctx->splat_lds) q = std::min(q, std::max(1, kSplatStage / ctx->dense_chunk));
+    return q;
+}
 
 // C: channels of the call; the vertex rows have stride row_stride(C).
 template <typename T>
@@ -94,9 +106,11 @@ inline LatSet<T> make_lat_set(dcrf_ctx *ctx, int C) {
         v.M = L.M;
         v.ld = ld;
         v.nchunks = L.nchunks;
+        v.ndchunks = L.ndchunks;
         v.wg = T(ctx->kern[m].weight * L.gamma);
         s.off[m + 1] = s.off[m] + (long long)L.M * ld;
-        s.coff[m + 1] = s.coff[m] + (long long)L.ndchunks * C;
+        const long long q = dense_splat_q(ctx, C);
+        s.coff[m + 1] = s.coff[m] + ((long long)L.ndchunks + q - 1) / q * 256;
         s.eoff[m + 1] = s.eoff[m] + (long long)L.nent;
         s.choff[m + 1] = s.choff[m] + (long long)L.nchunks;
         s.soff[m + 1] = s.soff[m] + (long long)L.nslots;

@@ -315,6 +315,49 @@ __global__ void k_pixel_ids(size_t count, const uint32_t *__restrict__ pix_slot,
     pix_vid[e] = (s == 0xffffffffu) ? -1 : slot_vid[s];
 }
 
+// ---- vertex order: by the first pixel-vertex pair that touches the vertex --
+//
+// Compaction numbers the vertices in hash-slot order, which scatters the
+// vertices of neighbouring pixels over the whole vertex array. Renumbering
+// them by their first pair (pixel a, simplex corner k: index a (d+1) + k,
+// unique per vertex) puts the vertices of nearby pixels at nearby ids: the
+// vertex rows gathered by a wave of neighbouring pixels share cache lines,
+// and the pixel band that one XCD works on maps to one range of rows. The
+// order does not depend on the hash table's layout.
+
+__global__ void k_first_pair(size_t cnt, const uint32_t *__restrict__ pix_slot,
+                             const int *__restrict__ slot_vid,
+                             uint32_t *__restrict__ first) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= cnt) return;
+    const uint32_t sl = pix_slot[e];
+    if (sl != 0xffffffffu) atomicMin(&first[slot_vid[sl]], uint32_t(e));
+}
+
+__global__ void k_iota_u32(int n, uint32_t *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = uint32_t(i);
+}
+
+// order[i]: old id of the vertex that becomes id i
+__global__ void k_renumber(int M, const uint32_t *__restrict__ order,
+                           const uint64_t *__restrict__ vkeys_old,
+                           uint64_t *__restrict__ vkeys_new, int *__restrict__ newid) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const uint32_t v = order[i];
+    newid[v] = i;
+    vkeys_new[i] = vkeys_old[v];
+}
+
+__global__ void k_remap_slots(size_t cap, const int *__restrict__ newid,
+                              int *__restrict__ slot_vid) {
+    const size_t sl = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (sl >= cap) return;
+    const int v = slot_vid[sl];
+    if (v >= 0) slot_vid[sl] = newid[v];
+}
+
 template <int D>
 __device__ int hash_lookup(const uint64_t *__restrict__ hkeys, uint64_t capmask,
                            const int *__restrict__ slot_vid, uint64_t key) {
@@ -520,6 +563,32 @@ void build_one(dcrf_ctx *ctx, int m, const float *rgb, int *flags_dev) {
                        L.hkeys.as<uint64_t>(), cap, tiles,
                        L.slot_vid.as<int>(), L.vkeys.as<uint64_t>());
     const size_t cnt = (size_t)N * D1;
+    if (M > 1) {
+        DevBuf first, k1, v0, v1, newid, vk, temp;
+        struct Free {
+            DevBuf *b[7];
+            ~Free() { for (DevBuf *x : b) x->release(); }
+        } fr{{&first, &k1, &v0, &v1, &newid, &vk, &temp}};
+        for (DevBuf *b : {&first, &k1, &v0, &v1, &newid}) b->ensure((size_t)M * 4, s);
+        vk.ensure((size_t)M * 8, s);
+        DCRF_TRY_HIP(hipMemsetAsync(first.p, 0xff, (size_t)M * 4, s));
+        hipLaunchKernelGGL(k_first_pair, dim3(ceil_div((long long)cnt, 256)), dim3(256),
+                           0, s, cnt, L.pix_slot.as<uint32_t>(), L.slot_vid.as<int>(),
+                           first.as<uint32_t>());
+        hipLaunchKernelGGL(k_iota_u32, dim3(ceil_div(M, 256)), dim3(256), 0, s, M,
+                           v0.as<uint32_t>());
+        DCRF_CHECK_LAUNCH();
+        sort_pairs(ctx, first.as<uint32_t>(), k1.as<uint32_t>(), v0.as<uint32_t>(),
+                   v1.as<uint32_t>(), M, key_bits((unsigned long long)cnt), temp);
+        hipLaunchKernelGGL(k_renumber, dim3(ceil_div(M, 256)), dim3(256), 0, s, M,
+                           v1.as<uint32_t>(), L.vkeys.as<uint64_t>(), vk.as<uint64_t>(),
+                           newid.as<int>());
+        hipLaunchKernelGGL(k_remap_slots, dim3(ceil_div((long long)cap, 256)), dim3(256),
+                           0, s, cap, newid.as<int>(), L.slot_vid.as<int>());
+        DCRF_CHECK_LAUNCH();
+        std::swap(L.vkeys, vk);
+        DCRF_TRY_HIP(hipStreamSynchronize(s));
+    }
     hipLaunchKernelGGL(k_pixel_ids, dim3(ceil_div((long long)cnt, 256)),
                        dim3(256), 0, s, cnt, L.pix_slot.as<uint32_t>(),
                        L.slot_vid.as<int>(), L.pix_vid.as<int>());

@@ -43,6 +43,7 @@ class dcrf_iter_trace(ctypes.Structure):
 
 class dcrf_tune(ctypes.Structure):
     _fields_ = [("splat_chunk", ctypes.c_int), ("dense_chunk", ctypes.c_int),
+                ("splat_stage", ctypes.c_int),
                 ("blur_vectors_per_thread", ctypes.c_int),
                 ("blur_block", ctypes.c_int), ("blur_group", ctypes.c_int),
                 ("tiles", ctypes.c_int), ("ms", ctypes.c_double)]
@@ -205,9 +206,10 @@ class Context:
         return [packed[a:b] for a, b in self.seg]
 
     def set_tune(self, splat_chunk=64, blur_vectors_per_thread=1,
-                 blur_block=256, blur_group=2, tiles=0, dense_chunk=32, **_):
-        t = dcrf_tune(splat_chunk, dense_chunk, blur_vectors_per_thread, blur_block,
-                      blur_group, tiles, 0.0)
+                 blur_block=256, blur_group=2, tiles=0, dense_chunk=32,
+                 splat_stage=1, **_):
+        t = dcrf_tune(splat_chunk, dense_chunk, splat_stage, blur_vectors_per_thread,
+                      blur_block, blur_group, tiles, 0.0)
         self._stream()
         self._check(_lib.dcrf_set_tune(self._h, ctypes.byref(t)))
 
@@ -216,6 +218,7 @@ class Context:
         self._stream()
         self._check(_lib.dcrf_autotune(self._h, L, reps, ctypes.byref(t)))
         return dict(splat_chunk=t.splat_chunk, dense_chunk=t.dense_chunk,
+                    splat_stage=t.splat_stage,
                     blur_vectors_per_thread=t.blur_vectors_per_thread,
                     blur_block=t.blur_block, blur_group=t.blur_group,
                     tiles=t.tiles, ms=t.ms)

@@ -173,6 +173,7 @@ def test_autotune_keeps_results():
     tune = ctx.autotune(21, reps=2)
     assert tune["splat_chunk"] in (32, 64, 128)
     assert tune["dense_chunk"] in (16, 32, 64)
+    assert tune["splat_stage"] in (0, 1)
     assert tune["blur_vectors_per_thread"] in (1, 2)
     assert tune["blur_group"] in (1, 2, 3)
     assert tune["tiles"] in (0, 1)

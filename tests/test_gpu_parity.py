@@ -338,6 +338,10 @@ def test_errors_are_reported_not_fatal():
          dense_chunk=128),
     dict(splat_chunk=64, blur_vectors_per_thread=1, blur_block=256, blur_group=2,
          dense_chunk=256),
+    dict(splat_chunk=64, blur_vectors_per_thread=1, blur_block=256, blur_group=2,
+         dense_chunk=32, splat_stage=0),
+    dict(splat_chunk=64, blur_vectors_per_thread=1, blur_block=256, blur_group=2,
+         dense_chunk=64, splat_stage=1),
     dict(splat_chunk=256, blur_vectors_per_thread=4, blur_block=256, blur_group=3),
     dict(splat_chunk=32, blur_vectors_per_thread=3, blur_block=256, blur_group=3),
     dict(splat_chunk=64, blur_vectors_per_thread=1, blur_block=256, blur_group=2,
