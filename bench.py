@@ -14,8 +14,8 @@ Beside it the JSON line reports:
 * lattice_filter: one dense L=21 lattice filter K'Y (splat, blur, slice) at
   the same shape, timed with HIP events, in algorithmic GB/s;
 * roofline: the dominant kernel of the step, its algorithmic bytes per launch
-  over its average launch time (HIP events on the library's stream), against
-  the 8 TB/s HBM peak;
+  over its average launch time (HIP events carried by the kernel dispatches
+  on the library's stream), against the 8 TB/s HBM peak;
 * cpu_baseline: the FP64 oracle's Frank-Wolfe iterations on the host, one
   thread, over a bounded sample of iterations of the same workload;
 * diff: 10 unrolled Frank-Wolfe iterations at 500x375, L=21, FP32 (seed 3):
@@ -78,14 +78,35 @@ def fw_step_bytes(N, L, e, lattices):
     return b
 
 
-def lmo_bytes(N, L, e, lattices):
-    """k_fw_lmo alone: 6 N L e (y, P_y, P_s, c in; y, P_y out), the labels,
-    the vertex ids and weights of the one-hot splat and its N (d+1) scattered
-    value updates."""
-    b = 6 * N * L * e + 2 * N * 4
-    for d, M in lattices:
-        b += N * (d + 1) * (4 + e) + N * (d + 1) * e
-    return b
+def class_bytes(name, N, L, e, lattices, group=2):
+    """Algorithmic bytes per launch of the kernel class `name` of the
+    Frank-Wolfe step (the names of the library's profiling classes):
+    * k_fw_lmo_rows: y, P_y, P_s, c in, y and P_y out (6 N L e), the previous
+      and the new labels (2 N 4);
+    * k_splat_labels_lds / _chunks: the labels (N 4), per lattice the (pixel, weight)
+      entries (N (d+1) (4 + e)) and the vertex rows written (M L e);
+    * k_fw_slice_rows: y in and P_s out (2 N L e), labels and r (N (4 + e)),
+      per lattice the per-pixel vertex ids and weights and the vertex rows
+      read;
+    * k_blur_group: per launch, over the lattices it covers, each vertex row
+      in and out (2 M L e) and the path table (M 3^G 4);
+    * k_fw_alpha: the per-tile partial sums it reduces."""
+    if name == "k_fw_lmo_rows":
+        return 6 * N * L * e + 2 * N * 4
+    if name in ("k_splat_labels_lds", "k_splat_labels_chunks"):
+        return N * 4 + sum(N * (d + 1) * (4 + e) + M * L * e for d, M in lattices)
+    if name == "k_fw_slice_rows":
+        return 2 * N * L * e + N * (4 + e) + sum(
+            N * (d + 1) * (4 + e) + M * L * e for d, M in lattices)
+    if name in ("k_blur_group", "k_blur_pass"):
+        group = 1 if name == "k_blur_pass" else group
+        groups = [-(-(d + 1) // group) for d, M in lattices]
+        tot = sum(g * (2 * M * L * e + M * 3 ** group * 4)
+                  for g, (d, M) in zip(groups, lattices))
+        return tot / max(groups)
+    if name == "k_fw_alpha":
+        return (-(-N // 256) * 7 + -(-N // 128) * 2) * 8
+    raise KeyError(name)
 
 
 def cpu_baseline(im, kernels, mu, iters):
@@ -363,15 +384,12 @@ def main():
         del a, b
 
     # ---- roofline of the dominant kernel of the step ----------------------
-    dom = max(per_iter, key=lambda k: per_iter[k][0] * per_iter[k][1])
+    step_classes = ("k_fw_lmo_rows", "k_splat_labels_lds", "k_splat_labels_chunks",
+                    "k_blur_group", "k_blur_pass", "k_fw_slice_rows", "k_fw_alpha")
+    dom = max((k for k in per_iter if k in step_classes),
+              key=lambda k: per_iter[k][0] * per_iter[k][1])
     dom_ms = per_iter[dom][0]
-    if dom == "k_fw_lmo":
-        dom_bytes = lmo_bytes(N, L, 4, lat)
-    elif dom == "k_fw_slice":
-        dom_bytes = 2 * N * L * 4 + N * 4 + sum(
-            N * (d + 1) * 8 + N * (d + 1) * L * 4 for d, M in lat)
-    else:  # one blur pass over both lattices
-        dom_bytes = sum((4 * M * L * 4 + 2 * M * 4) for d, M in lat)
+    dom_bytes = class_bytes(dom, N, L, 4, lat)
     achieved = dom_bytes / dom_ms / 1e6
     roofline = dict(bound="hbm", kernel=dom, achieved=achieved,
                     peak=HBM_PEAK_GBPS, unit="GB/s", frac=achieved / HBM_PEAK_GBPS,

@@ -297,9 +297,10 @@ int dcrf_fw_backward(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
 
 /* ---- benchmarking support ---------------------------------------------- */
 
-/* Turn per-kernel timing on or off (and reset the counters). While on, each
- * launch of the hot kernels is bracketed by HIP events recorded on the
- * context's stream; the events add a small gap between launches. */
+/* Turn per-kernel timing on or off (and reset the counters). While on, the
+ * launches of the hot kernels carry a pair of HIP events in their dispatch
+ * (hipExtLaunchKernelGGL on the context's stream), so each interval is the
+ * kernel's own execution time. */
 int dcrf_set_profiling(dcrf_ctx *ctx, int enable);
 
 /* Totals of kernel class k (0 <= k < 8): *name (static string, the kernel's

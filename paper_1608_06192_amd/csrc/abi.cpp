@@ -12,12 +12,22 @@
 using dcrf::Error;
 
 namespace dcrf {
-const char *prof_name(int c) {
-    static const char *names[PROF_NCLASS] = {
-        "k_fw_lmo_rows", "k_blur_pass", "k_fw_slice_rows", "k_splat_gather",
-        "k_slice_rows", "k_slice_rows_qp", "k_splat_labels_entries",
-        "k_fw_alpha"};
-    return (c >= 0 && c < PROF_NCLASS) ? names[c] : "?";
+// name of the kernel that class c launches under the context's launch shapes
+const char *prof_name(const dcrf_ctx *ctx, int c) {
+    const bool tiles = ctx->tile_mode != 0, staged = ctx->splat_lds != 0;
+    switch (c) {
+    case PROF_FW_LMO: return "k_fw_lmo_rows";
+    case PROF_BLUR: return ctx->blur_group > 1 ? "k_blur_group" : "k_blur_pass";
+    case PROF_FW_SLICE: return tiles ? "k_tile_slice" : "k_fw_slice_rows";
+    case PROF_SPLAT:
+        return tiles ? "k_tile_splat" : staged ? "k_splat_gather_lds" : "k_splat_gather";
+    case PROF_SLICE: return tiles ? "k_tile_slice" : "k_slice_rows";
+    case PROF_SLICE_QP: return tiles ? "k_tile_slice_qp" : "k_slice_rows_qp";
+    case PROF_SPLAT_LABELS:
+        return tiles ? "k_tile_labels" : staged ? "k_splat_labels_lds" : "k_splat_labels_chunks";
+    case PROF_FW_ALPHA: return "k_fw_alpha";
+    default: return "?";
+    }
 }
 }  // namespace dcrf
 
@@ -448,7 +458,7 @@ int dcrf_get_profile(dcrf_ctx *ctx, int k, const char **name, double *total_ms,
     return guarded(ctx, [&] {
         REQUIRE(k >= 0 && k < dcrf::PROF_NCLASS, "kernel class out of range");
         ctx->prof.collect();
-        if (name) *name = dcrf::prof_name(k);
+        if (name) *name = dcrf::prof_name(ctx, k);
         if (total_ms) *total_ms = ctx->prof.total_ms[k];
         if (launches) *launches = ctx->prof.launches[k];
     });

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdint>
 #include <cstdio>
@@ -135,17 +136,17 @@ inline int row_stride(int C, size_t elt) {
 // Per-kernel timing with HIP events recorded on the context's stream around
 // each launch (enabled only for benchmarks; the events add a small gap).
 enum ProfClass {
-    PROF_FW_LMO = 0,      // k_fw_lmo: update, gradient, LMO, one-hot splat
-    PROF_BLUR = 1,        // one blur pass over every lattice
-    PROF_FW_SLICE = 2,    // k_fw_slice: slice, mu, line-search sums, alpha
-    PROF_SPLAT = 3,       // dense splat
-    PROF_SLICE = 4,       // raw slice (K'Y)
+    PROF_FW_LMO = 0,      // k_fw_lmo_rows: update, gradient, LMO, partial sums
+    PROF_BLUR = 1,        // one blur launch over every lattice (k_blur_group,
+                          // or k_blur_pass for one direction per launch)
+    PROF_FW_SLICE = 2,    // k_fw_slice_rows: slice, mu, diagonal, partial sums
+    PROF_SPLAT = 3,       // dense splat (k_splat_gather_lds or k_splat_gather)
+    PROF_SLICE = 4,       // raw slice K'Y (k_slice_rows)
     PROF_SLICE_QP = 5,    // slice with mu and the diagonal
-    PROF_SPLAT_LABELS = 6,  // one-hot (label) splat
-    PROF_FW_ALPHA = 7,    // reduction of the line-search sums, step size
+    PROF_SPLAT_LABELS = 6,  // one-hot splat (k_splat_labels_chunks)
+    PROF_FW_ALPHA = 7,    // reduction of the partial sums, step size
     PROF_NCLASS = 8
 };
-const char *prof_name(int c);
 
 struct Profiler {
     bool on = false;
@@ -233,6 +234,9 @@ struct dcrf_ctx {
 };
 
 namespace dcrf {
+
+// name of the kernel that profiling class c launches under ctx's launch shapes
+const char *prof_name(const dcrf_ctx *ctx, int c);
 
 // ------------------------------------------------------------ launchers
 
@@ -354,23 +358,46 @@ void autotune(dcrf_ctx *ctx, int L, int reps, double *best_ms);
 
 // Records events around the launches made during its lifetime when the
 // context's profiler is on.
+// Timing of one kernel class while profiling is on: the launches of the scope
+// go through DCRF_PLAUNCH, which hands the scope's events to the dispatch
+// itself (hipExtLaunchKernelGGL), so the interval is that of the kernels and
+// no event packets are inserted between launches. The first launch of the
+// scope records the start, every launch the stop (the last one counts).
 struct ProfScope {
     dcrf_ctx *ctx;
     int cls;
     hipEvent_t start{}, stop{};
+    bool started = false;
     ProfScope(dcrf_ctx *c, int k) : ctx(c), cls(k) {
         if (ctx->prof.on) {
             start = ctx->prof.get();
             stop = ctx->prof.get();
-            DCRF_TRY_HIP(hipEventRecord(start, ctx->stream));
         }
     }
+    bool on() const { return ctx->prof.on; }
+    hipEvent_t first() {
+        if (started) return nullptr;
+        started = true;
+        return start;
+    }
     ~ProfScope() {
-        if (ctx->prof.on) {
-            (void)hipEventRecord(stop, ctx->stream);
+        if (!ctx->prof.on) return;
+        if (started) {
             ctx->prof.pending.push_back({cls, {start, stop}});
+        } else {
+            ctx->prof.pool.push_back(start);
+            ctx->prof.pool.push_back(stop);
         }
     }
 };
+
+#define DCRF_PLAUNCH(ps, kernel, grid, block, shmem, stream, ...)                   \
+    do {                                                                           \
+        if ((ps).on())                                                             \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, (ps).first(), \
+                                  (ps).stop, 0, __VA_ARGS__);                      \
+        else                                                                       \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);   \
+    } while (0)
 
 }  // namespace dcrf

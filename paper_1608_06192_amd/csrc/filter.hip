@@ -109,6 +109,53 @@ k_splat_gather_lds(int C, int q, int U, const T *__restrict__ Y, LatSet<T> ls) {
     if (acc != T(0)) atomic_add(&L.V0[(size_t)cd.x * L.ld + c], acc);
 }
 
+// One-hot input in the layout of the staged dense splat: block b takes q
+// chunks of C = L lanes (chunk, label); the labels of the chunks' pixels and
+// the weights are staged in LDS, then lane (chunk, c) adds up the weights of
+// the entries labelled c, and adds the sum to V0[v][c] if it is not zero.
+// Labels outside [0, L) add nothing.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_splat_labels_lds(int C, int q, int U, const int32_t *__restrict__ labels,
+                   LatSet<T> ls) {
+    __shared__ int slab[kSplatStage];
+    __shared__ T sw[kSplatStage];
+    __shared__ int4 scd[256];
+    const long long b0 = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x;
+    int m = 0;
+    while (m + 1 < ls.nk && b0 >= ls.coff[m + 1]) ++m;
+    const LatView<T> &L = ls.l[m];
+    const int ch0 = int((b0 - ls.coff[m]) / 256) * q;
+    const int nq = min(q, L.ndchunks - ch0);
+    const int t = threadIdx.x;
+    if (t < nq) scd[t] = L.dchunks[ch0 + t];
+    __syncthreads();
+    for (int i = t; i < nq * U; i += 256) {
+        const int k = i / U, j = i - (i / U) * U;
+        const int4 cd = scd[k];
+        if (cd.y + j < cd.z) {
+            slab[i] = labels[L.ent_pix[cd.y + j]];
+            sw[i] = L.ent_w[cd.y + j];
+        }
+    }
+    __syncthreads();
+    const int k = t / C, c = t - (t / C) * C;
+    if (k >= nq) return;
+    const int4 cd = scd[k];
+    const int n = cd.z - cd.y;
+    const int *lk = slab + k * U;
+    const T *wk = sw + k * U;
+    T acc0 = T(0), acc1 = T(0);
+    int j = 0;
+    for (; j + 2 <= n; j += 2) {
+        acc0 += lk[j + 0] == c ? wk[j + 0] : T(0);
+        acc1 += lk[j + 1] == c ? wk[j + 1] : T(0);
+    }
+    if (j < n) acc0 += lk[j] == c ? wk[j] : T(0);
+    const T acc = acc0 + acc1;
+    if (acc != T(0)) atomic_add(&L.V0[(size_t)cd.x * L.ld + c], acc);
+}
+
 // One-hot input (pixel a is 1 at channel labels[a]): one wave per inverse-
 // index chunk (all entries of one vertex v). Each lane takes an entry and
 // adds its weight to an LDS histogram over the labels; the wave then adds
@@ -800,14 +847,14 @@ void splat_set(dcrf_ctx *ctx, const LatSet<T> &ls, const T *in, int C) {
         ctx->splatP.ensure((size_t)std::max<long long>(ls.soff[ls.nk], 1) * ld * sizeof(T),
                            s);
         const int cap = tile_splat_cap<T>(C);
-        DCRF_DISPATCH_ROWS(C, hipLaunchKernelGGL((k_tile_splat<T, LMAX>),
+        DCRF_DISPATCH_ROWS(C, DCRF_PLAUNCH(ps, (k_tile_splat<T, LMAX>),
                                                  dim3(ctx->ntiles), dim3(kTilePix),
                                                  tile_splat_lds<T>(C), s, C, ld, in, ls,
                                                  ctx->tiles.as<int4>(),
                                                  ctx->splatP.as<T>(), cap));
         const long long total = ls.off[ls.nk] / Vec16<T>::n;
         if (total > 0)
-            hipLaunchKernelGGL((k_vertex_gather<T>), dim3(ceil_div(total, 256)), dim3(256),
+            DCRF_PLAUNCH(ps, (k_vertex_gather<T>), dim3(ceil_div(total, 256)), dim3(256),
                                0, s, ls, ctx->splatP.as<T>(), total);
         DCRF_CHECK_LAUNCH();
         return;
@@ -818,10 +865,10 @@ void splat_set(dcrf_ctx *ctx, const LatSet<T> &ls, const T *in, int C) {
     const dim3 grid(ceil_div(total, 256));
     const int q = dense_splat_q(ctx, C);
     if (ctx->splat_lds)
-        hipLaunchKernelGGL((k_splat_gather_lds<T>), grid, dim3(256), 0, s, C, q,
+        DCRF_PLAUNCH(ps, (k_splat_gather_lds<T>), grid, dim3(256), 0, s, C, q,
                            ctx->dense_chunk, in, ls);
     else
-        hipLaunchKernelGGL((k_splat_gather<T>), grid, dim3(256), 0, s, C, q, in, ls);
+        DCRF_PLAUNCH(ps, (k_splat_gather<T>), grid, dim3(256), 0, s, C, q, in, ls);
     DCRF_CHECK_LAUNCH();
 }
 
@@ -839,14 +886,23 @@ void splat_labels_t(dcrf_ctx *ctx, const int32_t *labels, int L) {
     LatSet<T> ls = make_lat_set<T>(ctx, L);
     ProfScope ps(ctx, PROF_SPLAT_LABELS);
     if (use_tiles<T>(ctx, 1)) {
-        hipLaunchKernelGGL((k_tile_labels<T>), dim3(ctx->ntiles), dim3(kTilePix), 0,
+        DCRF_PLAUNCH(ps, (k_tile_labels<T>), dim3(ctx->ntiles), dim3(kTilePix), 0,
                            ctx->stream, L, labels, ls, ctx->tiles.as<int4>());
+        DCRF_CHECK_LAUNCH();
+        return;
+    }
+    if (ctx->splat_lds) {
+        const long long total = ls.coff[ls.nk];
+        if (total == 0) return;
+        DCRF_PLAUNCH(ps, (k_splat_labels_lds<T>), dim3(ceil_div(total, 256)), dim3(256),
+                           0, ctx->stream, L, dense_splat_q(ctx, L), ctx->dense_chunk,
+                           labels, ls);
         DCRF_CHECK_LAUNCH();
         return;
     }
     const long long total = ls.choff[ls.nk];
     if (total == 0) return;
-    hipLaunchKernelGGL((k_splat_labels_chunks<T>), dim3(ceil_div(total, 4)),
+    DCRF_PLAUNCH(ps, (k_splat_labels_chunks<T>), dim3(ceil_div(total, 4)),
                        dim3(256), 0, ctx->stream, L, labels, ls);
     DCRF_CHECK_LAUNCH();
 }
@@ -894,7 +950,7 @@ void blur_launch(dcrf_ctx *ctx, LatSet<T> &ls, int first, bool adjoint) {
     if (G == 1) {
         for (int p = 0; p < nl; ++p) {
             ProfScope ps(ctx, PROF_BLUR);
-            hipLaunchKernelGGL((k_blur_pass<T>), grid, dim3(bs), 0, ctx->stream, ls, p,
+            DCRF_PLAUNCH(ps, (k_blur_pass<T>), grid, dim3(bs), 0, ctx->stream, ls, p,
                                adjoint ? 1 : 0, total, vpt);
         }
     } else {
@@ -904,10 +960,10 @@ void blur_launch(dcrf_ctx *ctx, LatSet<T> &ls, int first, bool adjoint) {
         for (int grp = 0; grp < nl; ++grp) {
             ProfScope ps(ctx, PROF_BLUR);
             if (G == 2)
-                hipLaunchKernelGGL((k_blur_group<T, 2>), grid, dim3(bs), 0, ctx->stream,
+                DCRF_PLAUNCH(ps, (k_blur_group<T, 2>), grid, dim3(bs), 0, ctx->stream,
                                    ls, grp, total, vpt);
             else
-                hipLaunchKernelGGL((k_blur_group<T, 3>), grid, dim3(bs), 0, ctx->stream,
+                DCRF_PLAUNCH(ps, (k_blur_group<T, 3>), grid, dim3(bs), 0, ctx->stream,
                                    ls, grp, total, vpt);
         }
     }
@@ -949,11 +1005,11 @@ void slice_set(dcrf_ctx *ctx, const LatSet<T> &ls, int first, const T *Y,
                            (size_t)cap * row_stride(C, sizeof(T)) * sizeof(T);
         DCRF_DISPATCH_ROWS(C, {
             if (qp)
-                hipLaunchKernelGGL((k_tile_slice<T, LMAX, kSliceQP>), dim3(ctx->ntiles),
+                DCRF_PLAUNCH(ps, (k_tile_slice<T, LMAX, kSliceQP>), dim3(ctx->ntiles),
                                    dim3(kTilePix), lds, s, C, Y, ls,
                                    ctx->tiles.as<int4>(), cap, wsum, mu, mabs, r, out);
             else
-                hipLaunchKernelGGL((k_tile_slice<T, LMAX, kSliceRaw>), dim3(ctx->ntiles),
+                DCRF_PLAUNCH(ps, (k_tile_slice<T, LMAX, kSliceRaw>), dim3(ctx->ntiles),
                                    dim3(kTilePix), lds, s, C, Y, ls,
                                    ctx->tiles.as<int4>(), cap, wsum, mu, mabs, r, out);
         });
@@ -964,11 +1020,11 @@ void slice_set(dcrf_ctx *ctx, const LatSet<T> &ls, int first, const T *Y,
         ProfScope ps(ctx, qp ? PROF_SLICE_QP : PROF_SLICE);
         DCRF_DISPATCH_ROWS(C, {
             if (qp)
-                hipLaunchKernelGGL((k_slice_rows<T, LMAX, kSliceQP>),
+                DCRF_PLAUNCH(ps, (k_slice_rows<T, LMAX, kSliceQP>),
                                    dim3(row_grid(ctx, TP)), dim3(TP), 0, s, N, C,
                                    Y, pre, ls, wsum, mu, mabs, r, out);
             else
-                hipLaunchKernelGGL((k_slice_rows<T, LMAX, kSliceRaw>),
+                DCRF_PLAUNCH(ps, (k_slice_rows<T, LMAX, kSliceRaw>),
                                    dim3(row_grid(ctx, TP)), dim3(TP), 0, s, N, C,
                                    Y, pre, ls, wsum, mu, mabs, r, out);
         });
@@ -982,7 +1038,7 @@ void slice_set(dcrf_ctx *ctx, const LatSet<T> &ls, int first, const T *Y,
         return;
     }
     ProfScope ps(ctx, PROF_SLICE);
-    hipLaunchKernelGGL((k_slice_raw_flat<T>), dim3(ceil_div((long long)N * C, 256)),
+    DCRF_PLAUNCH(ps, (k_slice_raw_flat<T>), dim3(ceil_div((long long)N * C, 256)),
                        dim3(256), 0, s, N, C, Y, out, ls, wsum);
     DCRF_CHECK_LAUNCH();
 }

@@ -191,15 +191,31 @@ __device__ __forceinline__ int tile_range(const int *__restrict__ seg, int nimg,
 template <typename T, int NT>
 __device__ __forceinline__ void tile2_in(const T *__restrict__ g, int4 td, int C,
                                          T *lds, int LS) {
+    // flattened elements t, t + NT, ... of the tile; each batch of kB loads is
+    // issued before any of them is stored, one round trip per batch
+    constexpr int kB = 16;
     const int wC = td.w * C;
-    const float inv = 1.0f / float(C);
-    for (int i = 0; i < td.z; ++i) {
-        const T *src = g + ((size_t)td.x + (size_t)i * td.y) * C;
-        T *dst = lds + i * kTileW * LS;
-        for (int k = threadIdx.x; k < wC; k += NT) {
-            const int px = int((float(k) + 0.5f) * inv);
-            dst[px * LS + (k - px * C)] = src[k];
+    const int E = td.z * wC;
+    const float invw = 1.0f / float(wC), invc = 1.0f / float(C);
+    for (int f0 = 0; f0 < E; f0 += NT * kB) {
+        T v[kB];
+        int dst[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            const int f = f0 + u * NT + (int)threadIdx.x;
+            dst[u] = -1;
+            v[u] = T(0);
+            if (f < E) {
+                const int i = int((float(f) + 0.5f) * invw);
+                const int k = f - i * wC;
+                const int px = int((float(k) + 0.5f) * invc);
+                v[u] = g[((size_t)td.x + (size_t)i * td.y) * C + k];
+                dst[u] = (i * kTileW + px) * LS + (k - px * C);
+            }
         }
+#pragma unroll
+        for (int u = 0; u < kB; ++u)
+            if (dst[u] >= 0) lds[dst[u]] = v[u];
     }
 }
 

@@ -738,7 +738,7 @@ void qp_apply_t(dcrf_ctx *ctx, const T *y, const T *mu, int L, const T *mabs,
     }
     LatSet<T> ls = make_lat_set<T>(ctx, L);
     ProfScope ps(ctx, PROF_SLICE_QP);
-    hipLaunchKernelGGL((k_slice_qp_flat<T>), dim3(grid_flat(N, L)),
+    DCRF_PLAUNCH(ps, (k_slice_qp_flat<T>), dim3(grid_flat(N, L)),
                        dim3(kThreads), 0, st, N, L, y, pre, ls, T(ctx->wsum),
                        mu, mabs, ctx->r.as<T>(), out);
     DCRF_CHECK_LAUNCH();
@@ -822,11 +822,11 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
         {
             ProfScope ps(ctx, PROF_FW_LMO);
             if (rows) {
-                DCRF_DISPATCH_ROWS(L, hipLaunchKernelGGL((k_fw_lmo_rows<T, LMAX>),
+                DCRF_DISPATCH_ROWS(L, DCRF_PLAUNCH(ps, (k_fw_lmo_rows<T, LMAX>),
                                                          dim3(G1), dim3(LmoTile<T>::kPix),
                                                          0, st, a));
             } else {
-                hipLaunchKernelGGL((k_fw_lmo_flat<T>), dim3(G1), dim3(kThreads), 0,
+                DCRF_PLAUNCH(ps, (k_fw_lmo_flat<T>), dim3(G1), dim3(kThreads), 0,
                                    st, a);
             }
         }
@@ -856,21 +856,21 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
             ProfScope ps(ctx, PROF_FW_SLICE);
             if (rows) {
                 if (potts)
-                    DCRF_DISPATCH_ROWS(L, hipLaunchKernelGGL(
+                    DCRF_DISPATCH_ROWS(L, DCRF_PLAUNCH(ps, 
                         (k_fw_slice_rows<T, LMAX, true>), dim3(G),
                         dim3(RowTile<T>::kPix), 0, st, b, ls));
                 else
-                    DCRF_DISPATCH_ROWS(L, hipLaunchKernelGGL(
+                    DCRF_DISPATCH_ROWS(L, DCRF_PLAUNCH(ps, 
                         (k_fw_slice_rows<T, LMAX, false>), dim3(G),
                         dim3(RowTile<T>::kPix), 0, st, b, ls));
             } else {
-                hipLaunchKernelGGL((k_fw_slice_flat<T>), dim3(G), dim3(kThreads),
+                DCRF_PLAUNCH(ps, (k_fw_slice_flat<T>), dim3(G), dim3(kThreads),
                                    0, st, b, ls);
             }
         }
         {
             ProfScope ps(ctx, PROF_FW_ALPHA);
-            hipLaunchKernelGGL((k_fw_alpha<512>), dim3(nimg), dim3(512), 0,
+            DCRF_PLAUNCH(ps, (k_fw_alpha<512>), dim3(nimg), dim3(512), 0,
                                st, w.part1, w.part2, seg, nimg, TP1, TP, w.scal,
                                w.trace, it, save ? save->stats : nullptr);
         }
