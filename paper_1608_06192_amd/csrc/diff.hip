@@ -244,8 +244,8 @@ k_sweep_a(SweepA<T> A, LatSet<T> ls) {
     const size_t a = (size_t)lo + threadIdx.x;
     const bool act = (int)threadIdx.x < np;
     const double al = A.stats[((size_t)A.t * A.nimg + (img < 0 ? 0 : img)) * kFWStats];
-    tile_copy_in<T, TP>(A.y + (size_t)lo * L, np * L, L, ty);
-    tile_copy_in<T, TP>(A.Pbar + (size_t)lo * L, np * L, L, tp);
+    tile_copy_in<T, TP, LMAX>(A.y + (size_t)lo * L, np * L, L, ty);
+    tile_copy_in<T, TP, LMAX>(A.Pbar + (size_t)lo * L, np * L, L, tp);
     __syncthreads();
     const T *yr = ty + threadIdx.x * Ls;
     const T *pr = tp + threadIdx.x * Ls;
@@ -324,7 +324,7 @@ k_sweep_a(SweepA<T> A, LatSet<T> ls) {
     }
     // <ybar, s - y>
     __syncthreads();
-    tile_copy_in<T, TP>(A.ybar + (size_t)lo * L, np * L, L, tq);
+    tile_copy_in<T, TP, LMAX>(A.ybar + (size_t)lo * L, np * L, L, tq);
     __syncthreads();
     if (act) {
         const T *br = tq + threadIdx.x * Ls;
@@ -334,7 +334,7 @@ k_sweep_a(SweepA<T> A, LatSet<T> ls) {
     }
     // -<Pbar, P>
     __syncthreads();
-    tile_copy_in<T, TP>(A.P + (size_t)lo * L, np * L, L, ty);
+    tile_copy_in<T, TP, LMAX>(A.P + (size_t)lo * L, np * L, L, ty);
     __syncthreads();
     if (act) {
         double d = 0.0;
@@ -346,7 +346,7 @@ k_sweep_a(SweepA<T> A, LatSet<T> ls) {
             if (k < L) out[k] = S[k];
     }
     __syncthreads();
-    tile_copy_out<T, TP>(A.S + (size_t)lo * L, np * L, L, tq);
+    tile_copy_out<T, TP, LMAX>(A.S + (size_t)lo * L, np * L, L, tq);
     const double tot = block_sum_waves<kNP, TP>(acc, red);
     if ((int)threadIdx.x < kNP) A.part[(size_t)tile * kNP + threadIdx.x] = tot;
 }

@@ -399,11 +399,15 @@ k_slice_rows(int N, int C, const T *__restrict__ Y, const T *__restrict__ pre,
         for (int j = 0; j < LMAX; ++j) y[j] = T(0), q[j] = T(0);
         if (pre) {
             tile_load<T, LMAX, TP>(pre, p0, np, C, lds, q);
-        } else if (act) {
-            slice_pixel<T, LMAX>(ls, a, C, q);
+            tile_load<T, LMAX, TP>(Y, p0, np, C, lds, y);
+        } else {
+            // the tile of Y goes to LDS first, while few registers are live,
+            // and its loads overlap the gathers of the slice
+            tile_copy_in<T, TP, LMAX>(Y + p0 * C, np * C, C, lds);
+            if (act) slice_pixel<T, LMAX>(ls, a, C, q);
+            __syncthreads();
+            tile_read_own<T, LMAX>(np, C, lds, y);   // each thread its own row
         }
-        // Y after the gathers, to keep their register footprint small
-        tile_load<T, LMAX, TP>(Y, p0, np, C, lds, y);
         if (!pre) {
 #pragma unroll
             for (int j = 0; j < LMAX; ++j) q[j] -= wsum * y[j];
@@ -727,13 +731,34 @@ k_tile_slice(int C, const T *__restrict__ Y, LatSet<T> ls,
         used += nin[m];
     }
     {
+        // batches of kB vectors per thread: every vertex id of a batch is
+        // loaded, then every row vector, then all are stored
+        constexpr int kB = 8;
         const int G = ld / vw;
         for (int m = 0; m < ls.nk; ++m) {
             const LatView<T> &L = ls.l[m];
-            for (int idx = threadIdx.x; idx < nin[m] * G; idx += kTilePix) {
-                const int sl = idx / G, g = idx - (idx / G) * G;
-                reinterpret_cast<V *>(rows)[(size_t)(base[m] + sl) * G + g] =
-                    reinterpret_cast<const V *>(L.Vf)[(size_t)L.ts_vid[s0[m] + sl] * G + g];
+            const int cnt = nin[m] * G;
+            for (int i0 = 0; i0 < cnt; i0 += kTilePix * kB) {
+                int vid[kB];
+#pragma unroll
+                for (int u = 0; u < kB; ++u) {
+                    const int idx = i0 + u * kTilePix + (int)threadIdx.x;
+                    vid[u] = idx < cnt ? L.ts_vid[s0[m] + idx / G] : -1;
+                }
+                V v[kB];
+#pragma unroll
+                for (int u = 0; u < kB; ++u) {
+                    const int idx = i0 + u * kTilePix + (int)threadIdx.x;
+                    if (vid[u] >= 0)
+                        v[u] = reinterpret_cast<const V *>(L.Vf)[(size_t)vid[u] * G +
+                                                                 (idx - (idx / G) * G)];
+                }
+#pragma unroll
+                for (int u = 0; u < kB; ++u) {
+                    const int idx = i0 + u * kTilePix + (int)threadIdx.x;
+                    if (vid[u] >= 0)
+                        reinterpret_cast<V *>(rows)[(size_t)base[m] * G + idx] = v[u];
+                }
             }
         }
     }

@@ -250,47 +250,102 @@ template <> struct Vec16<double> { using type = double2; static constexpr int n 
 // per-thread registers through LDS so that the global side is coalesced.
 // For odd C the LDS tile is the contiguous global block and moves with
 // 16-byte accesses (tiles start at multiples of TP pixels, so 16-byte
-// aligned); for even C rows are padded to an odd stride.
+// aligned); for even C rows are padded to an odd stride. A thread moves at
+// most ceil(CMAX / 4) vectors (np <= TP, C <= CMAX): all of its loads are
+// issued before the first store, so a copy costs one memory round trip.
 // Every thread of the block must call these (they synchronise).
-template <typename T, int TP>
+template <typename T, int TP, int CMAX>
 __device__ __forceinline__ void tile_copy_in(const T *__restrict__ src, int n,
                                              int C, T *lds) {
     if (C & 1) {
         using V = typename Vec16<T>::type;
         constexpr int w = Vec16<T>::n;
+        constexpr int K = (CMAX + w - 1) / w;
         const int nv = n / w;
         const V *s = reinterpret_cast<const V *>(src);
         V *l = reinterpret_cast<V *>(lds);
-        for (int i = threadIdx.x; i < nv; i += TP) l[i] = s[i];
-        for (int i = nv * w + threadIdx.x; i < n; i += TP) lds[i] = src[i];
+        // indices past the end repeat the last vector (loaded and stored
+        // again, same value): with no condition on a load or its store, the
+        // compiler keeps every load in flight instead of sinking each one
+        // into a branch of its own
+        if (nv > 0) {
+            V v[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                v[k] = s[min((int)threadIdx.x + k * TP, nv - 1)];
+            // an empty statement that uses every loaded vector: all of them
+            // are live at once here, so the compiler issues all the loads
+            // before the first wait instead of pairing each with its store
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int e = 0; e < w; ++e)
+                    __asm__ __volatile__("" ::"v"(reinterpret_cast<const T *>(&v[k])[e]));
+#pragma unroll
+            for (int k = 0; k < K; ++k) l[min((int)threadIdx.x + k * TP, nv - 1)] = v[k];
+        }
+        const int i = nv * w + (int)threadIdx.x;
+        if (i < n) lds[i] = src[i];
     } else {
         const int Ls = C | 1;
         const float inv = 1.0f / float(C);
-        for (int i = threadIdx.x; i < n; i += TP) {
-            const int p = int((float(i) + 0.5f) * inv);
-            lds[p * Ls + (i - p * C)] = src[i];
+        if (n > 0) {
+            T v[CMAX];
+#pragma unroll
+            for (int k = 0; k < CMAX; ++k) v[k] = src[min((int)threadIdx.x + k * TP, n - 1)];
+#pragma unroll
+            for (int k = 0; k < CMAX; ++k) __asm__ __volatile__("" ::"v"(v[k]));
+#pragma unroll
+            for (int k = 0; k < CMAX; ++k) {
+                const int i = min((int)threadIdx.x + k * TP, n - 1);
+                const int p = int((float(i) + 0.5f) * inv);
+                lds[p * Ls + (i - p * C)] = v[k];
+            }
         }
     }
 }
 
-template <typename T, int TP>
+template <typename T, int TP, int CMAX>
 __device__ __forceinline__ void tile_copy_out(T *__restrict__ dst, int n, int C,
                                               const T *lds) {
     if (C & 1) {
         using V = typename Vec16<T>::type;
         constexpr int w = Vec16<T>::n;
+        constexpr int K = (CMAX + w - 1) / w;
         const int nv = n / w;
         V *d = reinterpret_cast<V *>(dst);
         const V *l = reinterpret_cast<const V *>(lds);
-        for (int i = threadIdx.x; i < nv; i += TP) d[i] = l[i];
-        for (int i = nv * w + threadIdx.x; i < n; i += TP) dst[i] = lds[i];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = (int)threadIdx.x + k * TP;
+            if (i < nv) d[i] = l[i];
+        }
+        const int i = nv * w + (int)threadIdx.x;
+        if (i < n) dst[i] = lds[i];
     } else {
         const int Ls = C | 1;
         const float inv = 1.0f / float(C);
-        for (int i = threadIdx.x; i < n; i += TP) {
-            const int p = int((float(i) + 0.5f) * inv);
-            dst[i] = lds[p * Ls + (i - p * C)];
+#pragma unroll
+        for (int k = 0; k < CMAX; ++k) {
+            const int i = (int)threadIdx.x + k * TP;
+            if (i < n) {
+                const int p = int((float(i) + 0.5f) * inv);
+                dst[i] = lds[p * Ls + (i - p * C)];
+            }
         }
+    }
+}
+
+// Row threadIdx.x of a tile staged by tile_copy_in, into registers (no
+// synchronisation: the caller has synchronised after the copy, and a thread
+// that later overwrites only its own row needs none either).
+template <typename T, int LMAX>
+__device__ __forceinline__ void tile_read_own(int np, int C, const T *lds, T (&r)[LMAX]) {
+    const int Ls = lds_stride(C);
+    if ((int)threadIdx.x < np) {
+#pragma unroll
+        for (int j = 0; j < LMAX; ++j)
+            if (j < C) r[j] = lds[threadIdx.x * Ls + j];
     }
 }
 
@@ -298,7 +353,7 @@ template <typename T, int LMAX, int TP>
 __device__ __forceinline__ void tile_load(const T *__restrict__ g, long long p0,
                                           int np, int C, T *lds, T (&r)[LMAX]) {
     const int Ls = lds_stride(C);
-    tile_copy_in<T, TP>(g + p0 * C, np * C, C, lds);
+    tile_copy_in<T, TP, LMAX>(g + p0 * C, np * C, C, lds);
     __syncthreads();
     if ((int)threadIdx.x < np) {
 #pragma unroll
@@ -319,7 +374,7 @@ __device__ __forceinline__ void tile_store(T *__restrict__ g, long long p0,
             if (j < C) lds[threadIdx.x * Ls + j] = r[j];
     }
     __syncthreads();
-    tile_copy_out<T, TP>(g + p0 * C, np * C, C, lds);
+    tile_copy_out<T, TP, LMAX>(g + p0 * C, np * C, C, lds);
     __syncthreads();
 }
 

@@ -291,6 +291,10 @@ k_fw_slice_rows(FWSliceArgs<T> A, LatSet<T> ls) {
 #pragma unroll
         for (int j = 0; j < LMAX; ++j) q[j] = T(0);
         const int sa = act ? A.s[a] : 0;
+        // with Potts and no precomputed K'S the tile of y goes to LDS first,
+        // so that its loads overlap the gathers of the slice
+        const bool early = POTTS && !A.pre;
+        if (early) tile_copy_in<T, TP, LMAX>(A.y + p0 * L, np * L, L, lds);
         if (A.pre) {
             tile_load<T, LMAX, TP>(A.pre, p0, np, L, lds, q);
         } else if (act) {
@@ -328,11 +332,15 @@ k_fw_slice_rows(FWSliceArgs<T> A, LatSet<T> ls) {
                 P[i] = (i < L) ? P[i] + (i == sa ? dself : T(0)) : T(0);
             __syncthreads();   // the tile buffer is reused by tile_load below
         }
-        // y only now, to keep the register footprint of the gathers small
         T y[LMAX];
 #pragma unroll
         for (int j = 0; j < LMAX; ++j) y[j] = T(0);
-        tile_load<T, LMAX, TP>(A.y, p0, np, L, lds, y);
+        if (early) {
+            __syncthreads();
+            tile_read_own<T, LMAX>(np, L, lds, y);
+        } else {
+            tile_load<T, LMAX, TP>(A.y, p0, np, L, lds, y);
+        }
         if (act) {
 #pragma unroll
             for (int j = 0; j < LMAX; ++j) {
