@@ -211,7 +211,6 @@ struct dcrf_ctx {
     dcrf::DevBuf tiles;              // ntiles x int4: first row, row stride, rows, cols
     dcrf::DevBuf tile_img_off;       // nimg + 1 i32: first tile of each image
     std::vector<int> tile_img_off_h;
-    dcrf::DevBuf splatP;             // partial rows of the tile splat
     int mode = DCRF_FILTER_LATTICE;
     bool has_image = false;
     dcrf_kernel kern[DCRF_MAXK];

@@ -509,148 +509,138 @@ k_exact(int N, int C, int c0, const T *__restrict__ in, T *__restrict__ out,
 
 // ------------------------------------------------------- tile kernels
 
-// Splat, first pass: one block per 2-D pixel tile. The tile's input rows are
-// staged in LDS (each tile row a contiguous range, copied coalesced). Per
-// lattice, the tile's pixel-vertex pairs, grouped by slot, are cut into
-// equal runs of consecutive pairs, one per thread (so a vertex shared by the
-// whole tile is spread over many threads); a thread sums w * Y over its pairs
-// in registers and adds the sum of each slot it covers to the slot's partial
-// row in LDS (one LDS atomic per channel and slot change). The partial rows
-// are then written out, padding channels zero.
-template <typename T, int LMAX>
+// Tile splats: one block per 2-D pixel tile. Per lattice, the tile's
+// pixel-vertex pairs grouped by slot (each slot one distinct vertex of the
+// tile) are staged in LDS together with the slot boundaries; lane task
+// (slot, c) sums its slot's pairs from LDS and adds the sum to the vertex row
+// with one global atomic. Each input value is read from global memory once.
+
+// pairs of one lattice in one tile: at most d + 1 <= kMaxD1 per pixel
+constexpr int kTilePairs = kTilePix * kMaxD1;
+
+// Stage the pairs [e0, e0 + ne) of one lattice and its slot offsets (ns + 1,
+// relative to e0) in LDS. Loads of a thread are issued before its stores.
+template <typename T>
+__device__ __forceinline__ void tile_stage_pairs(const LatView<T> &L, int s0, int ns,
+                                                 int e0, int ne, uint8_t *spx, T *sw,
+                                                 int *sof) {
+    constexpr int K = kTilePairs / kTilePix;
+    uint8_t px[K];
+    T w[K];
+    int of[K + 1];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = (int)threadIdx.x + k * kTilePix;
+        const int ic = i < ne ? i : 0;
+        px[k] = ne > 0 ? L.sr_pix[e0 + ic] : uint8_t(0);
+        w[k] = ne > 0 ? L.sr_w[e0 + ic] : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k <= K; ++k) {
+        const int i = (int)threadIdx.x + k * kTilePix;
+        of[k] = L.sr_off[s0 + (i <= ns ? i : ns)];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = (int)threadIdx.x + k * kTilePix;
+        if (i < ne) {
+            spx[i] = px[k];
+            sw[i] = w[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k <= K; ++k) {
+        const int i = (int)threadIdx.x + k * kTilePix;
+        if (i <= ns) sof[i] = of[k] - e0;
+    }
+}
+
+// LDS of the tile splats: staged values (kTilePix rows of stride C | 1, or
+// one label per pixel), then pair weights, slot offsets and pair pixels
+template <typename T>
+size_t tile_splat_lds(int C) {
+    return (size_t)kTilePix * (C | 1) * sizeof(T) + (size_t)kTilePairs * sizeof(T) +
+           (size_t)(kTilePairs + 1) * 4 + kTilePairs;
+}
+
+template <typename T>
 __global__ void __launch_bounds__(kTilePix)
-k_tile_splat(int C, int ld, const T *__restrict__ Y, LatSet<T> ls,
-             const int4 *__restrict__ tiles, T *__restrict__ P, int cap) {
+k_tile_splat(int C, const T *__restrict__ Y, LatSet<T> ls,
+             const int4 *__restrict__ tiles) {
     extern __shared__ __align__(16) unsigned char tile_smem[];
-    T *ys = reinterpret_cast<T *>(tile_smem);   // kTilePix x ld
-    T *pl = ys + kTilePix * ld;                  // cap x ld
+    const int LS = C | 1;
+    T *ys = reinterpret_cast<T *>(tile_smem);
+    T *sw = ys + kTilePix * LS;
+    int *sof = reinterpret_cast<int *>(sw + kTilePairs);
+    uint8_t *spx = reinterpret_cast<uint8_t *>(sof + kTilePairs + 1);
     const int t = xcd_block(blockIdx.x, gridDim.x);
     const int4 td = tiles[t];
-    tile2_in<T, kTilePix>(Y, td, C, ys, ld);
+    tile2_in<T, kTilePix>(Y, td, C, ys, LS);
+    const float invC = 1.0f / float(C);
     for (int m = 0; m < ls.nk; ++m) {
         const LatView<T> &L = ls.l[m];
         const int s0 = L.ts_off[t], ns = L.ts_off[t + 1] - s0;
         const int e0 = L.sr_off[s0], ne = L.sr_off[s0 + ns] - e0;
-        for (int k = threadIdx.x; k < ns * ld; k += kTilePix) pl[k] = T(0);
+        tile_stage_pairs<T>(L, s0, ns, e0, ne, spx, sw, sof);
         __syncthreads();
-        const int per = (ne + kTilePix - 1) / kTilePix;
-        const int rb = e0 + threadIdx.x * per, re = min(rb + per, e0 + ne);
-        T acc[LMAX];
-#pragma unroll
-        for (int c = 0; c < LMAX; ++c) acc[c] = T(0);
-        int cur = -1;
-        for (int r = rb; r < re; ++r) {
-            const int sl = L.sr_slot[r];
-            if (sl != cur) {
-                if (cur >= 0) {
-#pragma unroll
-                    for (int c = 0; c < LMAX; ++c)
-                        if (c < C) atomicAdd(&pl[cur * ld + c], acc[c]);
-                }
-#pragma unroll
-                for (int c = 0; c < LMAX; ++c) acc[c] = T(0);
-                cur = sl;
+        for (int task = threadIdx.x; task < ns * C; task += kTilePix) {
+            const int sl = int((float(task) + 0.5f) * invC);
+            const int c = task - sl * C;
+            const int b = sof[sl], e = sof[sl + 1];
+            T acc0 = T(0), acc1 = T(0);
+            int j = b;
+            for (; j + 2 <= e; j += 2) {
+                acc0 += sw[j] * ys[spx[j] * LS + c];
+                acc1 += sw[j + 1] * ys[spx[j + 1] * LS + c];
             }
-            axpy_row<LMAX>(acc, L.sr_w[r], ys + L.sr_pix[r] * ld, C);
-        }
-        if (cur >= 0) {
-#pragma unroll
-            for (int c = 0; c < LMAX; ++c)
-                if (c < C) atomicAdd(&pl[cur * ld + c], acc[c]);
+            if (j < e) acc0 += sw[j] * ys[spx[j] * LS + c];
+            const T acc = acc0 + acc1;
+            if (acc != T(0)) atomic_add(&L.V0[(size_t)L.ts_vid[s0 + sl] * L.ld + c], acc);
         }
         __syncthreads();
-        T *Pm = P + (size_t)(ls.soff[m] + s0) * ld;
-        for (int k = threadIdx.x; k < ns * ld; k += kTilePix) Pm[k] = pl[k];
-        __syncthreads();
     }
-    (void)cap;
 }
 
-// Splat, second pass: V0[v] = sum of the partial rows of v's slots, one
-// thread per 16-byte vector of the vertex rows of every lattice.
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_vertex_gather(LatSet<T> ls, const T *__restrict__ P, long long total) {
-    using V = typename Vec16<T>::type;
-    constexpr int vw = Vec16<T>::n;
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= total) return;
-    int m = 0;
-    while (m + 1 < ls.nk && e >= ls.off[m + 1] / vw) ++m;
-    const LatView<T> &L = ls.l[m];
-    const unsigned G = unsigned(L.ld / vw);
-    const unsigned r = unsigned(e - ls.off[m] / vw);
-    const int v = int(r / G);
-    const int g = int(r - unsigned(v) * G);
-    const V *Pm = reinterpret_cast<const V *>(P + (size_t)ls.soff[m] * L.ld);
-    T acc[vw];
-#pragma unroll
-    for (int i = 0; i < vw; ++i) acc[i] = T(0);
-    const int b = L.vs_off[v], en = L.vs_off[v + 1];
-    for (int i = b; i < en; ++i) {
-        const V x = Pm[(size_t)L.vs_slot[i] * G + g];
-#pragma unroll
-        for (int k = 0; k < vw; ++k) acc[k] += reinterpret_cast<const T *>(&x)[k];
-    }
-    V o;
-#pragma unroll
-    for (int k = 0; k < vw; ++k) reinterpret_cast<T *>(&o)[k] = acc[k];
-    reinterpret_cast<V *>(L.V0)[r] = o;
-}
-
-// One-hot splat: one block per tile. The tile's labels are staged in LDS;
-// per lattice the tile's pairs, grouped by slot, are cut into equal runs of
-// consecutive pairs, one per thread. A thread sums the weights of its pairs
-// per (slot, label) in registers (up to four labels per slot; further ones
-// go straight to the vertex row) and adds each sum to V0[v][label].
+// One-hot input: the tile's labels are staged instead of rows, and lane task
+// (slot, c) adds up the weights of its slot's pairs whose pixel has label c.
 template <typename T>
 __global__ void __launch_bounds__(kTilePix)
 k_tile_labels(int C, const int32_t *__restrict__ labels, LatSet<T> ls,
               const int4 *__restrict__ tiles) {
-    __shared__ int labs[kTilePix];
+    extern __shared__ __align__(16) unsigned char tile_smem[];
+    int *labs = reinterpret_cast<int *>(tile_smem);
+    T *sw = reinterpret_cast<T *>(tile_smem + kTilePix * 8);
+    int *sof = reinterpret_cast<int *>(sw + kTilePairs);
+    uint8_t *spx = reinterpret_cast<uint8_t *>(sof + kTilePairs + 1);
     const int t = xcd_block(blockIdx.x, gridDim.x);
     const int4 td = tiles[t];
-    const int i = threadIdx.x / kTileW, px = threadIdx.x % kTileW;
-    labs[threadIdx.x] = (i < td.z && px < td.w)
-                            ? labels[(size_t)td.x + (size_t)i * td.y + px] : -1;
-    __syncthreads();
+    {
+        const int i = threadIdx.x / kTileW, px = threadIdx.x % kTileW;
+        labs[threadIdx.x] = (i < td.z && px < td.w)
+                                ? labels[(size_t)td.x + (size_t)i * td.y + px] : -1;
+    }
+    const float invC = 1.0f / float(C);
     for (int m = 0; m < ls.nk; ++m) {
         const LatView<T> &L = ls.l[m];
         const int s0 = L.ts_off[t], ns = L.ts_off[t + 1] - s0;
         const int e0 = L.sr_off[s0], ne = L.sr_off[s0 + ns] - e0;
-        const int per = (ne + kTilePix - 1) / kTilePix;
-        const int rb = e0 + threadIdx.x * per, re = min(rb + per, e0 + ne);
-        int cur = -1;
-        int l0 = -1, l1 = -1, l2 = -1, l3 = -1;
-        T w0 = T(0), w1 = T(0), w2 = T(0), w3 = T(0);
-        T *row = nullptr;
-        for (int r = rb; r <= re; ++r) {
-            const int sl = (r < re) ? int(L.sr_slot[r]) : -2;
-            if (sl != cur) {
-                if (cur >= 0) {
-                    if (l0 >= 0) atomic_add(&row[l0], w0);
-                    if (l1 >= 0) atomic_add(&row[l1], w1);
-                    if (l2 >= 0) atomic_add(&row[l2], w2);
-                    if (l3 >= 0) atomic_add(&row[l3], w3);
-                }
-                if (sl < 0) break;
-                cur = sl;
-                row = L.V0 + (size_t)L.ts_vid[s0 + sl] * L.ld;
-                l0 = l1 = l2 = l3 = -1;
+        tile_stage_pairs<T>(L, s0, ns, e0, ne, spx, sw, sof);
+        __syncthreads();
+        for (int task = threadIdx.x; task < ns * C; task += kTilePix) {
+            const int sl = int((float(task) + 0.5f) * invC);
+            const int c = task - sl * C;
+            const int b = sof[sl], e = sof[sl + 1];
+            T acc0 = T(0), acc1 = T(0);
+            int j = b;
+            for (; j + 2 <= e; j += 2) {
+                acc0 += labs[spx[j]] == c ? sw[j] : T(0);
+                acc1 += labs[spx[j + 1]] == c ? sw[j + 1] : T(0);
             }
-            const int lb = labs[L.sr_pix[r]];
-            if (lb < 0 || lb >= C) continue;
-            const T w = L.sr_w[r];
-            if (lb == l0) w0 += w;
-            else if (lb == l1) w1 += w;
-            else if (lb == l2) w2 += w;
-            else if (lb == l3) w3 += w;
-            else if (l0 < 0) { l0 = lb; w0 = w; }
-            else if (l1 < 0) { l1 = lb; w1 = w; }
-            else if (l2 < 0) { l2 = lb; w2 = w; }
-            else if (l3 < 0) { l3 = lb; w3 = w; }
-            else atomic_add(&row[lb], w);
+            if (j < e) acc0 += labs[spx[j]] == c ? sw[j] : T(0);
+            const T acc = acc0 + acc1;
+            if (acc != T(0)) atomic_add(&L.V0[(size_t)L.ts_vid[s0 + sl] * L.ld + c], acc);
         }
+        __syncthreads();
     }
 }
 
@@ -835,31 +825,15 @@ void exact_t(dcrf_ctx *ctx, const T *in, T *out, int C) {
 
 constexpr size_t kTileLds = 56 * 1024;   // dynamic LDS of the tile slices
 
-// LDS of k_tile_splat: the tile's values (kTilePix rows of ld), then the
-// partial rows of one lattice's slots (cap rows of ld)
-constexpr size_t kSplatLds = 60 * 1024;
-template <typename T>
-int tile_splat_cap(int C) {
-    const size_t row = (size_t)row_stride(C, sizeof(T)) * sizeof(T);
-    return int(kSplatLds / row) - kTilePix;
-}
-template <typename T>
-size_t tile_splat_lds(int C) {
-    return (size_t)(kTilePix + tile_splat_cap<T>(C)) * row_stride(C, sizeof(T)) * sizeof(T);
-}
-
 // whether the per-tile kernels serve C channels: each lattice's slots of a
 // tile must fit the splat's LDS partial rows
 template <typename T>
 bool use_tiles(const dcrf_ctx *ctx, int C) {
     if (!(ctx->tile_mode && ctx->ntiles > 0 && C <= kRowMaxC)) return false;
-    const int cap = tile_splat_cap<T>(C);
-    for (int m = 0; m < ctx->nk; ++m)
-        if (ctx->lat[m].max_tile_slots > cap) return false;
     // the slice stages the tile's pixel rows and at least one slot row
     const size_t slice = (size_t)kTilePix * (C | 1) * sizeof(T) + 16 +
                          (size_t)row_stride(C, sizeof(T)) * sizeof(T);
-    return cap > 0 && slice <= kTileLds;
+    return tile_splat_lds<T>(C) <= kTileLds && slice <= kTileLds;
 }
 
 // splat of the dense N x C input into V0 of every lattice of ls
@@ -868,19 +842,8 @@ void splat_set(dcrf_ctx *ctx, const LatSet<T> &ls, const T *in, int C) {
     const hipStream_t s = ctx->stream;
     ProfScope ps(ctx, PROF_SPLAT);
     if (use_tiles<T>(ctx, C)) {
-        const int ld = row_stride(C, sizeof(T));
-        ctx->splatP.ensure((size_t)std::max<long long>(ls.soff[ls.nk], 1) * ld * sizeof(T),
-                           s);
-        const int cap = tile_splat_cap<T>(C);
-        DCRF_DISPATCH_ROWS(C, DCRF_PLAUNCH(ps, (k_tile_splat<T, LMAX>),
-                                                 dim3(ctx->ntiles), dim3(kTilePix),
-                                                 tile_splat_lds<T>(C), s, C, ld, in, ls,
-                                                 ctx->tiles.as<int4>(),
-                                                 ctx->splatP.as<T>(), cap));
-        const long long total = ls.off[ls.nk] / Vec16<T>::n;
-        if (total > 0)
-            DCRF_PLAUNCH(ps, (k_vertex_gather<T>), dim3(ceil_div(total, 256)), dim3(256),
-                               0, s, ls, ctx->splatP.as<T>(), total);
+        DCRF_PLAUNCH(ps, (k_tile_splat<T>), dim3(ctx->ntiles), dim3(kTilePix),
+                     tile_splat_lds<T>(C), s, C, in, ls, ctx->tiles.as<int4>());
         DCRF_CHECK_LAUNCH();
         return;
     }
@@ -911,8 +874,9 @@ void splat_labels_t(dcrf_ctx *ctx, const int32_t *labels, int L) {
     LatSet<T> ls = make_lat_set<T>(ctx, L);
     ProfScope ps(ctx, PROF_SPLAT_LABELS);
     if (use_tiles<T>(ctx, 1)) {
-        DCRF_PLAUNCH(ps, (k_tile_labels<T>), dim3(ctx->ntiles), dim3(kTilePix), 0,
-                           ctx->stream, L, labels, ls, ctx->tiles.as<int4>());
+        DCRF_PLAUNCH(ps, (k_tile_labels<T>), dim3(ctx->ntiles), dim3(kTilePix),
+                     (size_t)kTilePix * 8 + tile_splat_lds<T>(1) - (size_t)kTilePix * sizeof(T),
+                     ctx->stream, L, labels, ls, ctx->tiles.as<int4>());
         DCRF_CHECK_LAUNCH();
         return;
     }

@@ -13,12 +13,11 @@
 //                              (row * kTileW + col) and weight sr_w
 //   vs_off[v] .. vs_off[v+1]   the slots of vertex v (vs_slot)
 // With it,
-//  - the splat becomes a gather inside each tile, from the tile's values
-//    staged once in LDS, into one partial row per slot, followed by a short
-//    per-vertex sum of its slots' partial rows: the pixel values are read
-//    once and coalesced, and no atomics are needed;
-//  - the one-hot (label) splat sums each slot's weights per label in
-//    registers and adds the few non-zero sums to the vertex rows;
+//  - the splat becomes a gather inside each tile: the tile's values and its
+//    pairs are staged once in LDS, each (slot, channel) sum is formed there
+//    and added to the vertex row with one atomic, so the pixel values are
+//    read once and coalesced;
+//  - the one-hot (label) splat does the same with the tile's labels;
 //  - the slices stage each tile's slot rows in LDS once instead of gathering
 //    d+1 rows per pixel from L2.
 
