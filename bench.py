@@ -128,6 +128,138 @@ def cpu_baseline(im, kernels, mu, iters):
                        f"500x375 L=21 image, {dt:.1f} s")
 
 
+# ---- profiler summaries ----------------------------------------------------
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fw_step_500x375_L21_hbm_traffic.txt")
+CALIB_BYTES = 256 << 20   # the --calib-copy kernel reads and writes 256 MiB
+
+
+def source_digest():
+    """sha256 over the library's kernel sources (file names and contents)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1608_06192_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        h.update(name.encode())
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _short(name):
+    """kernel name without namespaces and parameter list (template arguments
+    kept, so that instantiations stay apart)"""
+    n = name[5:] if name.startswith("void ") else name
+    n = n.replace("dcrf::(anonymous namespace)::", "").replace("dcrf::", "")
+    depth, out = 0, []
+    for ch in n:           # cut at the parameter list: the first '(' outside <>
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            break
+        out.append(ch)
+    return "".join(out).strip()
+
+
+def summarize_pmc(fetch_csv, write_csv, command):
+    """Write TRAFFIC_FILE from the counter CSVs of two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of `bench.py
+    --calib-copy`. The calibration dispatches are the non-library kernels that
+    read (write) at least 64 MiB by the counter: the plain copy of CALIB_BYTES
+    (the counter of its 256 MiB read shows half of it on this part)."""
+    import csv
+    per = {}
+    calib = {}
+    for ctr, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != ctr:
+                continue
+            v = float(r["Counter_Value"])
+            k = _short(r["Kernel_Name"])
+            if not k.startswith("k_") and v * 1024 >= 64 * (1 << 20):
+                calib.setdefault(ctr, []).append(v)
+            elif k.startswith("k_"):
+                per.setdefault(k, {}).setdefault(ctr, []).append(v)
+    lines = ["# HBM traffic per dispatch of the library's kernels, from the L2-to-memory",
+             "# byte counters of rocprofv3 (KiB per dispatch, averaged over dispatches),",
+             "# with a plain 256 MiB copy kernel in the same run as calibration.",
+             "# Workload: bench.py (voronoi 500x375, L=21, FP32, both kernels).",
+             "# Commands (repository root on the GPU host, TMPDIR=/tmp):"]
+    lines += ["#   " + c for c in command]
+    lines += ["# Summary written by: python bench.py --summarize-pmc <fetch csv> <write csv>",
+              f"source_sha256 {source_digest()}"]
+    kib = CALIB_BYTES / 1024
+    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+        vals = calib.get(ctr, [])
+        avg = sum(vals) / len(vals) if vals else float("nan")
+        lines.append(f"calib {ctr} measured_kib {avg:.1f} expected_kib {kib:.1f} "
+                     f"dispatches {len(vals)}")
+    for k in sorted(per):
+        f = per[k].get("FETCH_SIZE", [])
+        w = per[k].get("WRITE_SIZE", [])
+        if not f or not w:
+            continue
+        lines.append(f"kernel {k.replace(' ', '')} fetch_kib {sum(f) / len(f):.1f} "
+                     f"write_kib {sum(w) / len(w):.1f} dispatches {len(f)}")
+    with open(TRAFFIC_FILE, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def traffic_bytes(kernel):
+    """HBM bytes per launch of `kernel` from TRAFFIC_FILE, each counter scaled
+    by expected / measured of the calibration copy; None when the file is
+    missing, lacks the kernel, or was taken on other kernel sources."""
+    try:
+        lines = open(TRAFFIC_FILE).read().split("\n")
+    except OSError:
+        return None
+    rec, calib = {}, {}
+    sha = None
+    for ln in lines:
+        t = ln.split()
+        if not t or t[0].startswith("#"):
+            continue
+        if t[0] == "source_sha256":
+            sha = t[1]
+        elif t[0] == "calib":
+            calib[t[1]] = float(t[5]) / float(t[3])
+        elif t[0] == "kernel" and t[1].split("<")[0] == kernel:
+            n = int(t[-1])   # the instantiation with the most dispatches
+            if not rec or n > rec["n"]:
+                rec = dict(fetch=float(t[-5]), write=float(t[-3]), n=n)
+    if sha != source_digest() or not rec or len(calib) != 2:
+        return None
+    return (rec["fetch"] * calib["FETCH_SIZE"] + rec["write"] * calib["WRITE_SIZE"]) * 1024
+
+
+def summarize_trace(stats_csv, out_path, command, note):
+    """Write a kernel-statistics summary (calls, average/min/max microseconds,
+    total ms) of a rocprofv3 --kernel-trace --stats run."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# {note}", "#", "# Command (repository root on the GPU host):"]
+    lines += ["#   " + c for c in command]
+    lines += [f"# Summary written by: python bench.py --summarize-trace <stats csv> "
+              f"{os.path.relpath(out_path, ROOT)}", "#",
+              f"{'kernel':48s} {'calls':>7s} {'avg us':>9s} {'min us':>9s} "
+              f"{'max us':>9s} {'total ms':>9s}"]
+    for r in rows[:40]:
+        k = _short(r["Name"])
+        if "rocprim" in r["Name"]:
+            k = "rocprim " + r["Name"].split("::")[-1][:32]
+        lines.append(f"{k[:48]:48s} {int(r['Calls']):7d} "
+                     f"{float(r['AverageNs']) / 1e3:9.2f} {float(r['MinNs']) / 1e3:9.2f} "
+                     f"{float(r['MaxNs']) / 1e3:9.2f} "
+                     f"{float(r['TotalDurationNs']) / 1e6:9.3f}")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def _timed(torch, fn, reps=1):
     """milliseconds per call of fn on the current stream (HIP events)"""
     fn()
@@ -286,7 +418,23 @@ def main():
                          "the HBM byte counters of a profiler run)")
     ap.add_argument("--no-ext", action="store_true",
                     help="skip the diff, batch and lattice-error measurements")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM traffic summary under profiles/ from two "
+                         "rocprofv3 --pmc counter CSVs and exit")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("STATS_CSV", "OUT"),
+                    help="write a kernel statistics summary from a rocprofv3 "
+                         "--stats CSV and exit")
+    ap.add_argument("--command", action="append", default=[],
+                    help="profiler command line to record in a summary")
+    ap.add_argument("--note", default="Kernel statistics",
+                    help="first line of a trace summary")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc, args.command)
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace, args.command, args.note)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "a multi-GPU run is not built",
@@ -393,7 +541,7 @@ def main():
     achieved = dom_bytes / dom_ms / 1e6
     roofline = dict(bound="hbm", kernel=dom, achieved=achieved,
                     peak=HBM_PEAK_GBPS, unit="GB/s", frac=achieved / HBM_PEAK_GBPS,
-                    traffic=None, bytes_per_launch=dom_bytes,
+                    traffic=traffic_bytes(dom), bytes_per_launch=dom_bytes,
                     avg_launch_us=dom_ms * 1e3)
 
     res = dict(metric=METRIC, value=args.steps / dt, unit="FW iters/s",
