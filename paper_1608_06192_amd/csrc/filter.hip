@@ -34,6 +34,12 @@ namespace {
 
 // ------------------------------------------------------------------ splat
 
+// (pixel or label, weight) of one inverse-index entry, one LDS word
+template <typename T> struct alignas(2 * sizeof(T) > 8 ? 16 : 8) PairLds {
+    int i;
+    T w;
+};
+
 // lane (chunk, c): V0[v][c] += sum w * Y[pix][c]; block b of a lattice takes
 // its chunks b q .. b q + q - 1 (q = dense_splat_q: chunks of C lanes)
 template <typename T>
@@ -69,8 +75,7 @@ k_splat_gather(int C, int q, const T *__restrict__ Y, LatSet<T> ls) {
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_splat_gather_lds(int C, int q, int U, const T *__restrict__ Y, LatSet<T> ls) {
-    __shared__ int spix[kSplatStage];
-    __shared__ T sw[kSplatStage];
+    __shared__ PairLds<T> sp[kSplatStage];
     __shared__ int4 scd[256];
     const long long b0 = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x;
     int m = 0;   // uniform: each lattice's blocks start at a multiple of 256 lanes
@@ -84,27 +89,24 @@ k_splat_gather_lds(int C, int q, int U, const T *__restrict__ Y, LatSet<T> ls) {
     for (int i = t; i < nq * U; i += 256) {
         const int k = i / U, j = i - (i / U) * U;
         const int4 cd = scd[k];
-        if (cd.y + j < cd.z) {
-            spix[i] = L.ent_pix[cd.y + j];
-            sw[i] = L.ent_w[cd.y + j];
-        }
+        if (cd.y + j < cd.z) sp[i] = PairLds<T>{L.ent_pix[cd.y + j], L.ent_w[cd.y + j]};
     }
     __syncthreads();
     const int k = t / C, c = t - (t / C) * C;
     if (k >= nq) return;
     const int4 cd = scd[k];
     const int n = cd.z - cd.y;
-    const int *pk = spix + k * U;
-    const T *wk = sw + k * U;
+    const PairLds<T> *pk = sp + k * U;
     T acc0 = T(0), acc1 = T(0), acc2 = T(0), acc3 = T(0);
     int j = 0;
     for (; j + 4 <= n; j += 4) {
-        acc0 += wk[j + 0] * Y[(size_t)pk[j + 0] * C + c];
-        acc1 += wk[j + 1] * Y[(size_t)pk[j + 1] * C + c];
-        acc2 += wk[j + 2] * Y[(size_t)pk[j + 2] * C + c];
-        acc3 += wk[j + 3] * Y[(size_t)pk[j + 3] * C + c];
+        const PairLds<T> e0 = pk[j], e1 = pk[j + 1], e2 = pk[j + 2], e3 = pk[j + 3];
+        acc0 += e0.w * Y[(size_t)e0.i * C + c];
+        acc1 += e1.w * Y[(size_t)e1.i * C + c];
+        acc2 += e2.w * Y[(size_t)e2.i * C + c];
+        acc3 += e3.w * Y[(size_t)e3.i * C + c];
     }
-    for (; j < n; ++j) acc0 += wk[j] * Y[(size_t)pk[j] * C + c];
+    for (; j < n; ++j) acc0 += pk[j].w * Y[(size_t)pk[j].i * C + c];
     const T acc = (acc0 + acc1) + (acc2 + acc3);
     if (acc != T(0)) atomic_add(&L.V0[(size_t)cd.x * L.ld + c], acc);
 }
@@ -118,8 +120,7 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 k_splat_labels_lds(int C, int q, int U, const int32_t *__restrict__ labels,
                    LatSet<T> ls) {
-    __shared__ int slab[kSplatStage];
-    __shared__ T sw[kSplatStage];
+    __shared__ PairLds<T> sp[kSplatStage];
     __shared__ int4 scd[256];
     const long long b0 = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x;
     int m = 0;
@@ -133,26 +134,25 @@ k_splat_labels_lds(int C, int q, int U, const int32_t *__restrict__ labels,
     for (int i = t; i < nq * U; i += 256) {
         const int k = i / U, j = i - (i / U) * U;
         const int4 cd = scd[k];
-        if (cd.y + j < cd.z) {
-            slab[i] = labels[L.ent_pix[cd.y + j]];
-            sw[i] = L.ent_w[cd.y + j];
-        }
+        if (cd.y + j < cd.z) sp[i] = PairLds<T>{labels[L.ent_pix[cd.y + j]], L.ent_w[cd.y + j]};
     }
     __syncthreads();
     const int k = t / C, c = t - (t / C) * C;
     if (k >= nq) return;
     const int4 cd = scd[k];
     const int n = cd.z - cd.y;
-    const int *lk = slab + k * U;
-    const T *wk = sw + k * U;
-    T acc0 = T(0), acc1 = T(0);
+    const PairLds<T> *pk = sp + k * U;
+    T acc0 = T(0), acc1 = T(0), acc2 = T(0), acc3 = T(0);
     int j = 0;
-    for (; j + 2 <= n; j += 2) {
-        acc0 += lk[j + 0] == c ? wk[j + 0] : T(0);
-        acc1 += lk[j + 1] == c ? wk[j + 1] : T(0);
+    for (; j + 4 <= n; j += 4) {
+        const PairLds<T> e0 = pk[j], e1 = pk[j + 1], e2 = pk[j + 2], e3 = pk[j + 3];
+        acc0 += e0.i == c ? e0.w : T(0);
+        acc1 += e1.i == c ? e1.w : T(0);
+        acc2 += e2.i == c ? e2.w : T(0);
+        acc3 += e3.i == c ? e3.w : T(0);
     }
-    if (j < n) acc0 += lk[j] == c ? wk[j] : T(0);
-    const T acc = acc0 + acc1;
+    for (; j < n; ++j) acc0 += pk[j].i == c ? pk[j].w : T(0);
+    const T acc = (acc0 + acc1) + (acc2 + acc3);
     if (acc != T(0)) atomic_add(&L.V0[(size_t)cd.x * L.ld + c], acc);
 }
 
