@@ -376,13 +376,15 @@ enum { kSliceRaw = 0, kSliceQP = 1 };
 //   qp:  out = (Psi + D) Y    = (K'Y) mu^T + d * Y, d_a(i) = mabs_i r_a
 // `pre` (optional) holds K'Y already (exact mode): then no lattice is read.
 template <typename T, int LMAX, int MODE>
-__global__ void __launch_bounds__(RowTile<T>::kPix, 4)
+__global__ void __launch_bounds__(RowTile<T>::kPix, 2)
 k_slice_rows(int N, int C, const T *__restrict__ Y, const T *__restrict__ pre,
              LatSet<T> ls, T wsum, const T *__restrict__ mu,
              const T *__restrict__ mabs, const T *__restrict__ r,
              T *__restrict__ out) {
     constexpr int TP = RowTile<T>::kPix;
     __shared__ __align__(16) T lds[TP * (LMAX | 1)];
+    __shared__ int32_t sid[TP * kCorners52];
+    __shared__ T swc[TP * kCorners52];
     __shared__ T smu[MODE == kSliceQP ? LMAX * LMAX : 1];
     if (MODE == kSliceQP) {
         for (int i = threadIdx.x; i < C * C; i += TP)
@@ -403,8 +405,14 @@ k_slice_rows(int N, int C, const T *__restrict__ Y, const T *__restrict__ pre,
         } else {
             // the tile of Y goes to LDS first, while few registers are live,
             // and its loads overlap the gathers of the slice
+            if (ls.shape52) stage_corners52<T, TP>(ls, p0, np, sid, swc);
             tile_copy_in<T, TP, LMAX>(Y + p0 * C, np * C, C, lds);
-            if (act) slice_pixel<T, LMAX>(ls, a, C, q);
+            if (ls.shape52) {
+                __syncthreads();
+                if (act) slice_pixel52_staged<T, LMAX, TP>(ls, threadIdx.x, C, sid, swc, q);
+            } else if (act) {
+                slice_pixel<T, LMAX>(ls, a, C, q);
+            }
             __syncthreads();
             tile_read_own<T, LMAX>(np, C, lds, y);   // each thread its own row
         }

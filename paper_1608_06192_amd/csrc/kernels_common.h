@@ -442,6 +442,81 @@ __device__ __forceinline__ void slice_pixel_fixed(const LatSet<T> &ls,
         axpy_row<LMAX>(acc, wb[k], B.Vf + (size_t)ib[k] * B.ld, C);
 }
 
+// The per-pixel vertex ids and weights of the two lattices of a 5-D + 2-D
+// set (ls.shape52) for the pixels [p0, p0 + np) of a row tile, moved to LDS
+// with contiguous loads (all issued before the first store): lattice 0 at
+// sid/sw[0, 6 TP), lattice 1 at [6 TP, 9 TP). Every thread of the block calls
+// this; the caller synchronises before reading. np >= 1.
+constexpr int kCorners52 = 9;
+template <typename T, int TP>
+__device__ __forceinline__ void stage_corners52(const LatSet<T> &ls, long long p0,
+                                                int np, int32_t *sid, T *sw) {
+    const LatView<T> &A = ls.l[0];
+    const LatView<T> &B = ls.l[1];
+    const int na = np * 6, nb = np * 3;
+    const int32_t *va = A.vid + p0 * 6, *vb = B.vid + p0 * 3;
+    const T *wa = A.w + p0 * 6, *wb = B.w + p0 * 3;
+    int ia[6], ib[3];
+    T fa[6], fb[3];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int i = min((int)threadIdx.x + k * TP, na - 1);
+        ia[k] = va[i];
+        fa[k] = wa[i];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int i = min((int)threadIdx.x + k * TP, nb - 1);
+        ib[k] = vb[i];
+        fb[k] = wb[i];
+    }
+    // every loaded value is live here, so all the loads are issued first
+#pragma unroll
+    for (int k = 0; k < 6; ++k) __asm__ __volatile__("" ::"v"(ia[k]), "v"(fa[k]));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) __asm__ __volatile__("" ::"v"(ib[k]), "v"(fb[k]));
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int i = min((int)threadIdx.x + k * TP, na - 1);
+        sid[i] = ia[k];
+        sw[i] = fa[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int i = min((int)threadIdx.x + k * TP, nb - 1);
+        sid[6 * TP + i] = ib[k];
+        sw[6 * TP + i] = fb[k];
+    }
+}
+
+// The slice of the tile's pixel t (ls.shape52) from the corners staged by
+// stage_corners52; as slice_pixel_fixed otherwise.
+template <typename T, int LMAX, int TP>
+__device__ __forceinline__ void slice_pixel52_staged(const LatSet<T> &ls, int t, int C,
+                                                     const int32_t *sid, const T *sw,
+                                                     T (&acc)[LMAX]) {
+    const LatView<T> &A = ls.l[0];
+    const LatView<T> &B = ls.l[1];
+    int ia[6], ib[3];
+    T wa[6], wb[3];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int id = sid[t * 6 + k];
+        wa[k] = id >= 0 ? A.wg * sw[t * 6 + k] : T(0);
+        ia[k] = id >= 0 ? id : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int id = sid[6 * TP + t * 3 + k];
+        wb[k] = id >= 0 ? B.wg * sw[6 * TP + t * 3 + k] : T(0);
+        ib[k] = id >= 0 ? id : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) axpy_row<LMAX>(acc, wa[k], A.Vf + (size_t)ia[k] * A.ld, C);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) axpy_row<LMAX>(acc, wb[k], B.Vf + (size_t)ib[k] * B.ld, C);
+}
+
 // sum over the lattices of w_m gamma_m sum_k b_k V_m[v_k]  (the slice of
 // pixel a into acc, which the caller has zeroed)
 template <typename T, int LMAX>

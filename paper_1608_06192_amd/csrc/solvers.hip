@@ -270,6 +270,8 @@ __global__ void __launch_bounds__(RowTile<T>::kPix, 4)
 k_fw_slice_rows(FWSliceArgs<T> A, LatSet<T> ls) {
     constexpr int TP = RowTile<T>::kPix;
     __shared__ __align__(16) T lds[TP * (LMAX | 1)];
+    __shared__ int32_t sid[TP * kCorners52];
+    __shared__ T swc[TP * kCorners52];
     __shared__ T smu[POTTS ? 1 : LMAX * LMAX];
     __shared__ double red[kP2 * TP];
     const int L = A.L;
@@ -294,14 +296,22 @@ k_fw_slice_rows(FWSliceArgs<T> A, LatSet<T> ls) {
         // with Potts and no precomputed K'S the tile of y goes to LDS first,
         // so that its loads overlap the gathers of the slice
         const bool early = POTTS && !A.pre;
+        const bool staged = !A.pre && ls.shape52 && np > 0;   // uniform over the block
+        if (staged) stage_corners52<T, TP>(ls, p0, np, sid, swc);
         if (early) tile_copy_in<T, TP, LMAX>(A.y + p0 * L, np * L, L, lds);
         if (A.pre) {
             tile_load<T, LMAX, TP>(A.pre, p0, np, L, lds, q);
-        } else if (act) {
-            slice_pixel<T, LMAX>(ls, a, L, q);
+        } else {
+            if (staged) __syncthreads();
+            if (act) {
+                if (staged)
+                    slice_pixel52_staged<T, LMAX, TP>(ls, threadIdx.x, L, sid, swc, q);
+                else
+                    slice_pixel<T, LMAX>(ls, a, L, q);
 #pragma unroll
-            for (int j = 0; j < LMAX; ++j)
-                if (j == sa) q[j] -= A.wsum;
+                for (int j = 0; j < LMAX; ++j)
+                    if (j == sa) q[j] -= A.wsum;
+            }
         }
         T P[LMAX];
         const T dself = act ? A.mabs[sa] * A.r[a] : T(0);
