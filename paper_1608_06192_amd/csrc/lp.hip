@@ -14,8 +14,9 @@
 // channel read at right points adds to Lo. "Over the node's points only"
 // means a permutohedral lattice built on those points: its vertices are the
 // (node, global vertex) pairs touched by the node's points, found with a
-// device hash keyed by node * M + v, and its blur follows the global
-// neighbour table, keeping neighbours present in the same node.
+// device hash keyed by node * M + v (a sub-vertex is numbered by the thread
+// that inserts it), and its blur follows the global neighbour table, keeping
+// neighbours present in the same node.
 // All nodes of a level are filtered in one pass; labels are processed one at
 // a time (their hash tables then stay cache-resident).
 //
@@ -143,39 +144,65 @@ __device__ __forceinline__ bool dnc_node(long long p, int l, long long N,
     return lo < mid && mid < hi;
 }
 
-// insert the (node, vertex) keys of every entry (position p, vertex k)
+// insert the (node, vertex) keys of every entry (position p, vertex k); the
+// thread that claims an empty slot numbers the new sub-vertex (one counter
+// update per wave) and records its key
 __global__ void k_lp_insert(int N, int l, int D1, int M,
                             const int *__restrict__ perm,
                             const int *__restrict__ pix_vid,
                             uint64_t *__restrict__ hkeys, uint64_t capmask,
-                            int *__restrict__ ent_slot, int *__restrict__ flags) {
+                            int *__restrict__ ent_slot, int *__restrict__ flags,
+                            int *__restrict__ count, int *__restrict__ slot_vid,
+                            uint64_t *__restrict__ subkeys) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (long long)N * D1) return;
-    const int p = int(e / D1);
-    const int k = int(e - (long long)p * D1);
-    long long node;
-    int side;
+    const bool in = e < (long long)N * D1;
     int slot = -1;
-    if (dnc_node(p, l, N, node, side)) {
-        const int v = pix_vid[(size_t)perm[p] * D1 + k];
-        if (v >= 0) {
-            const uint64_t key = (uint64_t)node * (uint64_t)M + (uint64_t)v;
-            uint64_t h = mix64(key) & capmask;
-            uint64_t probe = 0;
-            for (; probe <= capmask; ++probe) {
-                const unsigned long long prev = atomicCAS(
-                    (unsigned long long *)&hkeys[h], (unsigned long long)kEmpty,
-                    (unsigned long long)key);
-                if (prev == kEmpty || prev == key) break;
-                h = (h + 1) & capmask;
+    bool claimed = false;
+    uint64_t key = 0;
+    if (in) {
+        const int p = int(e / D1);
+        const int k = int(e - (long long)p * D1);
+        long long node;
+        int side;
+        if (dnc_node(p, l, N, node, side)) {
+            const int v = pix_vid[(size_t)perm[p] * D1 + k];
+            if (v >= 0) {
+                key = (uint64_t)node * (uint64_t)M + (uint64_t)v;
+                uint64_t h = mix64(key) & capmask;
+                uint64_t probe = 0;
+                for (; probe <= capmask; ++probe) {
+                    const unsigned long long prev = atomicCAS(
+                        (unsigned long long *)&hkeys[h], (unsigned long long)kEmpty,
+                        (unsigned long long)key);
+                    if (prev == kEmpty || prev == key) {
+                        claimed = prev == kEmpty;
+                        break;
+                    }
+                    h = (h + 1) & capmask;
+                }
+                if (probe > capmask)
+                    atomicOr(flags, 2);
+                else
+                    slot = int(h);
             }
-            if (probe > capmask)
-                atomicOr(flags, 2);
-            else
-                slot = int(h);
         }
     }
-    ent_slot[e] = slot;
+    // one counter update per wave: the claiming lanes number their new
+    // sub-vertices from the wave's base in lane order
+    const unsigned long long mask = __ballot(claimed);
+    if (mask) {
+        const int lane = threadIdx.x & 63;
+        const int leader = __ffsll((long long)mask) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(count, __popcll(mask));
+        base = __shfl(base, leader);
+        if (claimed) {
+            const int id = base + __popcll(mask & ((1ull << lane) - 1));
+            slot_vid[slot] = id;
+            subkeys[id] = key;
+        }
+    }
+    if (in) ent_slot[e] = slot;
 }
 
 // splat the two half indicators: V0[id][side] += b; records the entry's
@@ -234,6 +261,10 @@ __global__ void k_lp_neighbours(const int *__restrict__ count, int M, int D1,
             }
             nbr_sub[((size_t)j * cap_sub + id) * 2 + sg] = nid;
         }
+}
+
+__global__ void k_fill_i32_lp(int *p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
 
 // one blur pass over the sub-lattice, 2 channels; the second pass clears V0
@@ -517,19 +548,11 @@ void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l, const int *perm) {
     int *count = W.cnt.as<int>() + 4 * m;
     int *flags = ctx->scratch.as<int>();
     DCRF_TRY_HIP(hipMemsetAsync(P.hkeys.p, 0xff, P.cap * 8, s));
+    hipLaunchKernelGGL(k_fill_i32_lp, dim3(1), dim3(64), 0, s, count);
     hipLaunchKernelGGL(k_lp_insert, dim3(ceil_div(E, 256)), dim3(256), 0, s, N, l,
                        D1, M, perm, Lt.pix_vid.as<int>(), P.hkeys.as<uint64_t>(),
-                       uint64_t(P.cap - 1), P.ent_slot.as<int>(), flags);
-    const int ntiles = ceil_div((long long)P.cap, kScanTile);
-    int *tiles = reinterpret_cast<int *>(ctx->scratch.as<char>() + 64);
-    hipLaunchKernelGGL(k_count_occupied, dim3(ntiles), dim3(kScanThreads), 0, s,
-                       P.hkeys.as<uint64_t>(), P.cap, tiles);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, tiles,
-                       ntiles);
-    hipLaunchKernelGGL(k_assign_ids, dim3(ntiles), dim3(kScanThreads), 0, s,
-                       P.hkeys.as<uint64_t>(), P.cap, tiles, P.slot_vid.as<int>(),
-                       P.subkeys.as<uint64_t>());
-    DCRF_TRY_HIP(hipMemcpyAsync(count, tiles + ntiles, 4, hipMemcpyDeviceToDevice, s));
+                       uint64_t(P.cap - 1), P.ent_slot.as<int>(), flags, count,
+                       P.slot_vid.as<int>(), P.subkeys.as<uint64_t>());
     hipLaunchKernelGGL((k_lp_splat<T>), dim3(ceil_div(E, 256)), dim3(256), 0, s,
                        N, l, D1, perm, Lt.pix_w.as<T>(), P.ent_slot.as<int>(),
                        P.slot_vid.as<int>(), P.ent_id.as<int>(), P.V[0].as<T>());
