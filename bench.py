@@ -18,6 +18,9 @@ Beside it the JSON line reports:
   on the library's stream), against the 8 TB/s HBM peak;
 * cpu_baseline: the FP64 oracle's Frank-Wolfe iterations on the host, one
   thread, over a bounded sample of iterations of the same workload;
+* qp_dc: 50 Frank-Wolfe iterations and the DC relaxation (5 concave-convex
+  steps of 10 inner iterations) at 320x213, L=21, FP32, with the energy of
+  the rounded labelling;
 * diff: 10 unrolled Frank-Wolfe iterations at 500x375, L=21, FP32 (seed 3):
   forward with checkpoints, reverse sweep, and the plain forward beside them;
 * batch: 16 Voronoi images of sizes U{240..500}^2, L=21, FP32, 10 Frank-
@@ -277,6 +280,32 @@ def _timed(torch, fn, reps=1):
 def extensions(torch, dcrf, synth, dev, kernels):
     f32, f64 = torch.float32, torch.float64
     out = {}
+
+    # -- QP + DC relaxation at 320x213: 50 Frank-Wolfe iterations, then the
+    #    concave-convex procedure with 5 outer steps of 10 inner iterations --
+    im = synth.make("voronoi_320x213_L21")
+    wl = synth.WORKLOADS["voronoi_320x213_L21"]
+    ctx = dcrf.Context(0)
+    ctx.set_image(im.H, im.W, torch.from_numpy(im.rgb).to(dev), kernels, dtype=f32)
+    phi = torch.from_numpy(im.unary).to(dev, f32)
+    mu = torch.from_numpy(synth.potts(im.L)).to(dev, f32)
+    y0 = torch.softmax(-phi, dim=1)
+    res_dc = {}
+
+    def qp_dc():
+        y = y0.clone()
+        ctx.qp_frank_wolfe(phi, mu, y, wl["iters"], trace=False)
+        res_dc["hist"] = ctx.dc_gen(phi, mu, y, wl["dc_outer"], wl["dc_inner"])
+        res_dc["y"] = y
+
+    t_qd = _timed(torch, qp_dc, 3)
+    labels = ctx.round(res_dc["y"])
+    energy = ctx.energy(phi, mu, labels)
+    out["qp_dc"] = dict(workload="voronoi 320x213 L=21 FP32: 50 FW iterations, then "
+                                 "DC_gen 5 x 10", ms=t_qd,
+                        S_after_dc=res_dc["hist"][-1], energy=energy)
+    log(f"[bench] QP 50 + DC_gen 5x10 at 320x213: {t_qd:.2f} ms, S = "
+        f"{res_dc['hist'][-1]:.6g}, E(argmax) = {energy:.6g}")
 
     # -- differentiation: 10 unrolled iterations at 500x375 ------------------
     im = synth.make("voronoi_500x375_L21_diff")
