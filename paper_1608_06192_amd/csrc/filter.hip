@@ -10,19 +10,27 @@
 //        group of C lanes per chunk sums w * Y[pixel] and adds the sum to the
 //        vertex row with one atomic per channel. Vertices shared by thousands
 //        of pixels (flat colour regions of the bilateral lattice) cost one
-//        atomic per chunk instead of one per pixel.
+//        atomic per chunk instead of one per pixel. A block stages its
+//        chunks' pairs in LDS first, so the only scattered global loads left
+//        are those of the input values (or, for a one-hot input, of the
+//        labels).
 //      blur: d+1 out-of-place passes V'[v] = V[v]/2 + (V[v+u_j] + V[v-u_j])/4
-//        (missing neighbours read as 0) over all lattices in one launch per
-//        pass; the transpose runs the directions in reverse order.
+//        (missing neighbours read as 0) over all lattices, one or a group of
+//        up to three directions per launch (through per-vertex path tables,
+//        the same values as the sequential passes); the transpose runs the
+//        directions in reverse order.
 //      slice: one thread per pixel gathers its d+1 vertex rows with 16-byte
-//        loads into registers; rows move to and from global memory through
-//        LDS so the pixel-major arrays are read and written coalesced.
+//        loads into registers; the tile's input rows and per-pixel vertex ids
+//        and weights are staged in LDS with contiguous loads, and the output
+//        rows leave through LDS, so the pixel-major arrays move coalesced.
+//    Optional launch shape: the same splats and slices by 16x16 pixel tiles
+//    (tiles.hip), with each tile's distinct vertices staged in LDS.
 //  - exact: the O(N^2) sum on the vector ALU, tiled through LDS (reference
 //    mode for small images and for measuring the lattice's error).
 //
 // Vertex values are M x ld (ld = C rounded up to 16 bytes, zero padding).
 // V[0] is the splat target and is kept all-zero between calls: the second
-// blur pass clears it while the passes ping-pong between V[1] and V[2].
+// blur launch clears it while the launches ping-pong between V[1] and V[2].
 
 #include <algorithm>
 
