@@ -163,7 +163,8 @@ int dcrf_set_image(dcrf_ctx *ctx, int H, int W, const float *rgb,
         ctx->img_W.assign(1, W);
         dcrf::build_lattices(ctx, rgb);
         dcrf::set_segments(ctx, {0, ctx->N});
-        dcrf::build_tiles(ctx);
+        ctx->ntiles = 0;   // the tile map is built when tiles are asked for
+        if (ctx->tile_mode) dcrf::build_tiles(ctx);
         ctx->has_image = true;
         dcrf::compute_row_sums(ctx);
     });
@@ -194,7 +195,8 @@ int dcrf_set_images(dcrf_ctx *ctx, int B, const int *H, const int *W,
         } else {
             dcrf::build_batch(ctx, B, H, W, rgb);
         }
-        dcrf::build_tiles(ctx);
+        ctx->ntiles = 0;   // the tile map is built when tiles are asked for
+        if (ctx->tile_mode) dcrf::build_tiles(ctx);
         ctx->has_image = true;
         dcrf::compute_row_sums(ctx);
     });
@@ -253,6 +255,7 @@ int dcrf_set_tune(dcrf_ctx *ctx, const dcrf_tune *t) {
         ctx->blur_block = t->blur_block;
         ctx->blur_group = t->blur_group;
         ctx->tile_mode = t->tiles;
+        if (t->tiles && ctx->has_image) dcrf::ensure_tiles(ctx);
     });
 }
 

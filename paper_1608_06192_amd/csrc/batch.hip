@@ -252,6 +252,7 @@ void autotune(dcrf_ctx *ctx, int L, int reps, double *best_ms) {
         ctx->blur_block = c.block;
         ctx->blur_group = c.group;
         ctx->tile_mode = c.tiles;
+        if (c.tiles) ensure_tiles(ctx);
     };
     Cand best = {ctx->splat_chunk, ctx->dense_chunk, ctx->splat_lds, ctx->blur_vpt,
                  ctx->blur_block, ctx->blur_group, ctx->tile_mode};

@@ -96,6 +96,8 @@ struct Lattice {
     DevBuf dchunks;      // the same with at most dchunk entries (dense splat)
     int ndchunks = 0;
     int dchunk = 32;
+    DevBuf dpix, dw;     // the dense chunks' entries, chunk c at [c dchunk, +dchunk)
+                         // (pixel, weight; padded with pixel 0, weight 0)
     // grouped blur: for blur directions taken G at a time, per group and
     // vertex the 3^G vertices reached by the paths of the group (-1 where a
     // path leaves the lattice); [0] forward order, [1] the transpose's order
@@ -117,6 +119,7 @@ struct Lattice {
         for (DevBuf *b : {&hkeys, &slot_vid, &pix_slot, &pix_vid, &pix_w,
                           &vkeys, &nbr, &V[0], &V[1], &V[2], &feat, &csr_off,
                           &csr_tmp, &ent_pix, &ent_w, &ent_v, &chunk_off, &chunks, &dchunks,
+                          &dpix, &dw,
                           &gtab[0], &gtab[1], &ts_off, &ts_vid, &tr_slot, &sr_off,
                           &sr_pix, &sr_w, &sr_slot, &vs_off, &vs_slot})
             b->release();
@@ -207,7 +210,7 @@ struct dcrf_ctx {
     int blur_group = 2;      // blur directions applied per launch (1..3)
     int tile_mode = 0;       // splats and slices through the per-tile slots
     // 2-D pixel tiles of every image (tiles.hip)
-    int ntiles = 0;
+    int ntiles = 0;          // 0 until the tile map is built (only when tiles are asked for)
     dcrf::DevBuf tiles;              // ntiles x int4: first row, row stride, rows, cols
     dcrf::DevBuf tile_img_off;       // nimg + 1 i32: first tile of each image
     std::vector<int> tile_img_off_h;
@@ -330,6 +333,8 @@ constexpr int kTileH = 16, kTileW = 16, kTilePix = kTileH * kTileW;
 // and lattice: at most kTilePix * (d + 1))
 constexpr int kMaxD1 = 6;
 void build_tiles(dcrf_ctx *ctx);
+// the tile map of the current image(s), built on first use
+void ensure_tiles(dcrf_ctx *ctx);
 
 // Segments of the pixel range (see dcrf_ctx): set on the host and uploaded.
 void set_segments(dcrf_ctx *ctx, const std::vector<int> &seg);

@@ -93,12 +93,8 @@ k_splat_gather_lds(int C, int q, int U, const T *__restrict__ Y, LatSet<T> ls) {
     const int nq = min(q, L.ndchunks - ch0);
     const int t = threadIdx.x;
     if (t < nq) scd[t] = L.dchunks[ch0 + t];
-    __syncthreads();
-    for (int i = t; i < nq * U; i += 256) {
-        const int k = i / U, j = i - (i / U) * U;
-        const int4 cd = scd[k];
-        if (cd.y + j < cd.z) sp[i] = PairLds<T>{L.ent_pix[cd.y + j], L.ent_w[cd.y + j]};
-    }
+    const size_t base = (size_t)ch0 * U;   // the block's entries: one contiguous range
+    for (int i = t; i < nq * U; i += 256) sp[i] = PairLds<T>{L.dpix[base + i], L.dw[base + i]};
     __syncthreads();
     const int k = t / C, c = t - (t / C) * C;
     if (k >= nq) return;
@@ -138,12 +134,9 @@ k_splat_labels_lds(int C, int q, int U, const int32_t *__restrict__ labels,
     const int nq = min(q, L.ndchunks - ch0);
     const int t = threadIdx.x;
     if (t < nq) scd[t] = L.dchunks[ch0 + t];
-    __syncthreads();
-    for (int i = t; i < nq * U; i += 256) {
-        const int k = i / U, j = i - (i / U) * U;
-        const int4 cd = scd[k];
-        if (cd.y + j < cd.z) sp[i] = PairLds<T>{labels[L.ent_pix[cd.y + j]], L.ent_w[cd.y + j]};
-    }
+    const size_t base = (size_t)ch0 * U;   // the block's entries: one contiguous range
+    for (int i = t; i < nq * U; i += 256)
+        sp[i] = PairLds<T>{labels[L.dpix[base + i]], L.dw[base + i]};
     __syncthreads();
     const int k = t / C, c = t - (t / C) * C;
     if (k >= nq) return;

@@ -15,6 +15,8 @@ struct LatView {
     const T *Vf;         // the buffer that holds the blurred values
     const int4 *chunks;  // inverse-index chunks (vertex, begin, end, 0)
     const int4 *dchunks; // the chunks of the dense splat
+    const int32_t *dpix; // their entries at a stride of the chunk length
+    const T *dw;
     const int32_t *ent_pix;
     const T *ent_w;
     const int32_t *ent_v;
@@ -99,6 +101,8 @@ inline LatSet<T> make_lat_set(dcrf_ctx *ctx, int C) {
         v.nslots = L.nslots;
         v.chunks = L.chunks.as<int4>();
         v.dchunks = L.dchunks.as<int4>();
+        v.dpix = L.dpix.as<int32_t>();
+        v.dw = L.dw.as<T>();
         v.ent_pix = L.ent_pix.as<int32_t>();
         v.ent_w = L.ent_w.as<T>();
         v.ent_v = L.ent_v.as<int32_t>();

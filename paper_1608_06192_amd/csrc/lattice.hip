@@ -513,12 +513,44 @@ void chunk_list(dcrf_ctx *ctx, int m, int len, DevBuf &out, int &count) {
     DCRF_TRY_HIP(hipStreamSynchronize(s));
 }
 
+// the entries of each dense chunk at a stride of U (the staged splats then
+// load a block's entries as one contiguous range, without waiting for the
+// chunk descriptors)
+template <typename T>
+__global__ void k_dense_pad(long long n, int U, const int4 *__restrict__ chunks,
+                            const int *__restrict__ ent_pix, const T *__restrict__ ent_w,
+                            int32_t *__restrict__ dpix, T *__restrict__ dw) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const long long c = i / U;
+    const int j = int(i - c * U);
+    const int4 cd = chunks[c];
+    const int e = cd.y + j;
+    dpix[i] = e < cd.z ? ent_pix[e] : 0;
+    dw[i] = e < cd.z ? ent_w[e] : T(0);
+}
+
 // both chunk lists of lattice m: for the one-hot splat (L.chunk entries) and
-// for the dense splat (L.dchunk entries)
+// for the dense splat (L.dchunk entries), and the dense chunks' entries
 void chunk_index(dcrf_ctx *ctx, int m) {
     Lattice &L = ctx->lat[m];
     chunk_list(ctx, m, L.chunk, L.chunks, L.nchunks);
     chunk_list(ctx, m, L.dchunk, L.dchunks, L.ndchunks);
+    const long long n = (long long)L.ndchunks * L.dchunk;
+    const hipStream_t s = ctx->stream;
+    L.dpix.ensure((size_t)std::max(n, 1ll) * 4, s);
+    L.dw.ensure((size_t)std::max(n, 1ll) * ctx->elt(), s);
+    if (n > 0) {
+        if (ctx->dtype == DCRF_F64)
+            hipLaunchKernelGGL((k_dense_pad<double>), dim3(ceil_div(n, 256ll)), dim3(256), 0,
+                               s, n, L.dchunk, L.dchunks.as<int4>(), L.ent_pix.as<int>(),
+                               L.ent_w.as<double>(), L.dpix.as<int32_t>(), L.dw.as<double>());
+        else
+            hipLaunchKernelGGL((k_dense_pad<float>), dim3(ceil_div(n, 256ll)), dim3(256), 0,
+                               s, n, L.dchunk, L.dchunks.as<int4>(), L.ent_pix.as<int>(),
+                               L.ent_w.as<float>(), L.dpix.as<int32_t>(), L.dw.as<float>());
+        DCRF_CHECK_LAUNCH();
+    }
 }
 
 template <int D, typename T>

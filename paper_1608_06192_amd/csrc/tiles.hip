@@ -242,6 +242,10 @@ void build_tile_map(dcrf_ctx *ctx, int m, const int32_t *pix_tile,
 
 }  // namespace
 
+void ensure_tiles(dcrf_ctx *ctx) {
+    if (ctx->ntiles == 0) build_tiles(ctx);
+}
+
 void build_tiles(dcrf_ctx *ctx) {
     const hipStream_t s = ctx->stream;
     std::vector<int4> td;
