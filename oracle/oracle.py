@@ -494,7 +494,8 @@ def dnc_nodes(N: int):
                 yield lo, mid, hi
 
 
-def lp_pair_sums_dnc(model: Model, order: np.ndarray, inner: str):
+def lp_pair_sums_dnc(model: Model, order: np.ndarray, inner: str,
+                     at: np.ndarray | None = None):
     """U and Lo of eq. grad_lp by the divide-and-conquer of App. E.
 
     For each node, the block between its halves is one filter call: the
@@ -502,11 +503,25 @@ def lp_pair_sums_dnc(model: Model, order: np.ndarray, inner: str):
     the left half adds to U; the indicator of the left half read at the right
     half adds to Lo. ``inner`` = "exact" uses the O(n^2) Gaussian sum,
     "lattice" a permutohedral lattice built on the node's points only.
+
+    ``at`` (optional pixel indices) evaluates the sums at those pixels only:
+    a pixel receives contributions only from the nodes whose range holds its
+    position, one per level, so every other node is skipped, and U and Lo are
+    then valid at the pixels of ``at`` alone.
     """
     N = order.shape[0]
     U = np.zeros(N)
     Lo = np.zeros(N)
+    want = None
+    if at is not None:
+        rank = np.empty(N, dtype=np.int64)
+        rank[order] = np.arange(N)
+        want = np.sort(rank[np.asarray(at, dtype=np.int64)])
     for lo, mid, hi in dnc_nodes(N):
+        if want is not None:
+            k = np.searchsorted(want, lo)
+            if k == want.shape[0] or want[k] >= hi:
+                continue
         left = order[lo:mid]
         right = order[mid:hi]
         if inner == "exact":

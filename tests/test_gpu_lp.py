@@ -129,3 +129,31 @@ def test_lp_objective_equals_energy_at_integral_point():
     E = ctx.energy(T(im.unary, torch.float64), T(synth.potts(3), torch.float64),
                    torch.from_numpy(x).to(dev()))
     assert abs(S - E) <= 1e-9 * abs(E)
+
+
+def test_lp_subgradient_fp32_500x375_sampled_entries():
+    # 500x375, L = 21, FP32: the size and precision the LP descent is timed
+    # at. The whole N x L subgradient comes from one GPU call; the oracle
+    # evaluates it at sampled pixels of three labels, walking only the nodes
+    # of the divide and conquer that hold a sampled pixel (one per level).
+    # Sampled pixels include both ends and the middle of each label's order.
+    im = synth.make("voronoi_500x375_L21")
+    N = im.N
+    y = synth.random_simplex_points(N, im.L, seed=11, sparsity=0.6)
+    y = y.astype(np.float32).astype(np.float64)
+    ctx = ctx_for(im, torch.float32)
+    g, _ = ctx.lp_subgradient(T(im.unary, torch.float32), T(y, torch.float32))
+    g = g.cpu().numpy().astype(np.float64)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    phi32 = im.unary.astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(5)
+    for i in (0, 10, 20):
+        order = O.sorted_order(y[:, i])
+        ends = order[[0, 1, N // 2 - 1, N // 2, N - 2, N - 1]]
+        at = np.unique(np.concatenate([rng.choice(N, 192, replace=False), ends]))
+        U, Lo = O.lp_pair_sums_dnc(model, order, "lattice", at=at)
+        go = phi32[at, i] + U[at] - Lo[at]
+        mag = np.abs(phi32[at, i]) + U[at] + Lo[at]
+        rel = np.abs(g[at, i] - go) / mag
+        print(f"[lp 500x375] label {i}: max rel err {rel.max():.3g}", flush=True)
+        assert (rel <= 1e-5).all()

@@ -191,6 +191,29 @@ def test_lp_dnc_exact_equals_brute_force():
         assert abs(S1 - S2) < 1e-11
 
 
+def test_lp_dnc_sampled_pixels():
+    # the sampled evaluation (only the nodes holding a wanted position) gives
+    # the brute-force sums at the wanted pixels (exact inner filter), and the
+    # full divide and conquer's values there (lattice inner filter)
+    model, _ = tiny_problem(N=40, L=3, seed=12)
+    K = model.dense_K()
+    rng = np.random.default_rng(4)
+    for _ in range(3):
+        order = rng.permutation(40)
+        at = rng.choice(40, size=7, replace=False)
+        Ub, Lb = O.lp_pair_sums_brute(K, order)
+        Us, Ls = O.lp_pair_sums_dnc(model, order, "exact", at=at)
+        assert np.abs(Us[at] - Ub[at]).max() < 1e-12
+        assert np.abs(Ls[at] - Lb[at]).max() < 1e-12
+    im = synth.voronoi_image(15, 20, 3, seed=5, regions=4)
+    lat = O.Model(im.H, im.W, im.rgb, [synth.BILATERAL, synth.SPATIAL])
+    order = O.sorted_order(synth.random_simplex_points(im.N, 3, 6, 0.5)[:, 1])
+    at = np.array([order[0], order[-1], order[im.N // 2], 17, 123])
+    Uf, Lf = O.lp_pair_sums_dnc(lat, order, "lattice")
+    Us, Ls = O.lp_pair_sums_dnc(lat, order, "lattice", at=at)
+    assert np.array_equal(Us[at], Uf[at]) and np.array_equal(Ls[at], Lf[at])
+
+
 def test_lp_reformulation_and_integral_energy():
     # eq. simple_S: <g(y), y> equals eq. potts-lp's |.| form; at integral y
     # S_LP = E (Sec. 6)
