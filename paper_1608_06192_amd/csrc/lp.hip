@@ -16,7 +16,9 @@
 // (node, global vertex) pairs touched by the node's points, found with a
 // device hash keyed by node * M + v (a sub-vertex is numbered by the thread
 // that inserts it), and its blur follows the global neighbour table, keeping
-// neighbours present in the same node.
+// neighbours present in the same node. Each node probes only its own region
+// of the table (twice its entries), so the probes of neighbouring positions
+// stay in a few cache lines.
 // All nodes of a level are filtered in one pass; labels are processed one at
 // a time (their hash tables then stay cache-resident).
 //
@@ -144,65 +146,82 @@ __device__ __forceinline__ bool dnc_node(long long p, int l, long long N,
     return lo < mid && mid < hi;
 }
 
-// insert the (node, vertex) keys of every entry (position p, vertex k); the
-// thread that claims an empty slot numbers the new sub-vertex (one counter
-// update per wave) and records its key
+// Hash region of a node: slots [2 lo D1, 2 hi D1) of the level's table, twice
+// the node's (position, vertex) entries, so linear probing inside it always
+// ends. Consecutive positions share a node, so a wave's probes, lookups and
+// claims stay inside one small region instead of spreading over the table.
+__device__ __forceinline__ void node_region(long long node, int l, long long N,
+                                            int D1, long long &base,
+                                            long long &size) {
+    const long long lo = (node * N) >> l;
+    const long long hi = ((node + 1) * N) >> l;
+    base = 2 * lo * D1;
+    size = 2 * (hi - lo) * D1;
+}
+
+// first probe of global vertex v in a region of `size` (< 2^32) slots
+__device__ __forceinline__ long long region_slot(int v, long long size) {
+    return (long long)(((mix64((uint64_t)v) >> 32) * (uint64_t)size) >> 32);
+}
+
+// insert the (node, vertex) keys of every entry e = (position p, vertex k)
+// into the node's region. A new sub-vertex takes the number of the entry that
+// claims its slot: unique, below N D1, and found without a shared counter
+// (a single counter taken by every wave serialises across the chip). Entry e
+// writes subkeys[e] = its key if it claimed a slot, else empty, so the
+// sub-vertex numbers of a level are the e with a non-empty subkeys[e].
 __global__ void k_lp_insert(int N, int l, int D1, int M,
                             const int *__restrict__ perm,
                             const int *__restrict__ pix_vid,
-                            uint64_t *__restrict__ hkeys, uint64_t capmask,
+                            uint64_t *__restrict__ hkeys,
                             int *__restrict__ ent_slot, int *__restrict__ flags,
-                            int *__restrict__ count, int *__restrict__ slot_vid,
+                            int *__restrict__ slot_vid,
                             uint64_t *__restrict__ subkeys) {
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool in = e < (long long)N * D1;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;   // N D1 < 2^31
+    const bool in = e < N * D1;
     int slot = -1;
     bool claimed = false;
     uint64_t key = 0;
     if (in) {
-        const int p = int(e / D1);
-        const int k = int(e - (long long)p * D1);
+        const int p = e / D1;
+        const int k = e - p * D1;
         long long node;
         int side;
         if (dnc_node(p, l, N, node, side)) {
             const int v = pix_vid[(size_t)perm[p] * D1 + k];
             if (v >= 0) {
                 key = (uint64_t)node * (uint64_t)M + (uint64_t)v;
-                uint64_t h = mix64(key) & capmask;
-                uint64_t probe = 0;
-                for (; probe <= capmask; ++probe) {
-                    const unsigned long long prev = atomicCAS(
-                        (unsigned long long *)&hkeys[h], (unsigned long long)kEmpty,
-                        (unsigned long long)key);
+                long long base, size;
+                node_region(node, l, N, D1, base, size);
+                long long h = region_slot(v, size);
+                long long probe = 0;
+                for (; probe < size; ++probe) {
+                    // a slot changes once, from empty to its key: a plain
+                    // load that sees a key is final, and only an empty slot
+                    // needs the compare-and-swap
+                    unsigned long long prev = hkeys[base + h];
+                    if (prev == kEmpty)
+                        prev = atomicCAS((unsigned long long *)&hkeys[base + h],
+                                         (unsigned long long)kEmpty,
+                                         (unsigned long long)key);
                     if (prev == kEmpty || prev == key) {
                         claimed = prev == kEmpty;
                         break;
                     }
-                    h = (h + 1) & capmask;
+                    if (++h == size) h = 0;
                 }
-                if (probe > capmask)
+                if (probe == size)
                     atomicOr(flags, 2);
                 else
-                    slot = int(h);
+                    slot = int(base + h);
             }
         }
     }
-    // one counter update per wave: the claiming lanes number their new
-    // sub-vertices from the wave's base in lane order
-    const unsigned long long mask = __ballot(claimed);
-    if (mask) {
-        const int lane = threadIdx.x & 63;
-        const int leader = __ffsll((long long)mask) - 1;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(count, __popcll(mask));
-        base = __shfl(base, leader);
-        if (claimed) {
-            const int id = base + __popcll(mask & ((1ull << lane) - 1));
-            slot_vid[slot] = id;
-            subkeys[id] = key;
-        }
+    if (claimed) slot_vid[slot] = e;
+    if (in) {
+        ent_slot[e] = slot;
+        subkeys[e] = claimed ? key : kEmpty;
     }
-    if (in) ent_slot[e] = slot;
 }
 
 // splat the two half indicators: V0[id][side] += b; records the entry's
@@ -213,13 +232,13 @@ __global__ void k_lp_splat(int N, int l, int D1, const int *__restrict__ perm,
                            const int *__restrict__ ent_slot,
                            const int *__restrict__ slot_vid,
                            int *__restrict__ ent_id, T *__restrict__ V0) {
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (long long)N * D1) return;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;   // N D1 < 2^31
+    if (e >= N * D1) return;
     const int s = ent_slot[e];
     int id = -1;
     if (s >= 0) {
-        const int p = int(e / D1);
-        const int k = int(e - (long long)p * D1);
+        const int p = e / D1;
+        const int k = e - p * D1;
         long long node;
         int side;
         dnc_node(p, l, N, node, side);
@@ -229,51 +248,56 @@ __global__ void k_lp_splat(int N, int l, int D1, const int *__restrict__ perm,
     ent_id[e] = id;
 }
 
-// neighbours of every sub-vertex: (node, v +- u_j) when present in the node
-__global__ void k_lp_neighbours(const int *__restrict__ count, int M, int D1,
+// neighbours of every sub-vertex: (node, v +- u_j) when present in the node,
+// looked up in the node's region. Numbers that are no sub-vertex this level
+// get no neighbours, so the blur keeps them at zero.
+__global__ void k_lp_neighbours(int S, int N, int l, int M, int D1,
                                 const uint64_t *__restrict__ subkeys,
                                 const int *__restrict__ nbr_global,
                                 const uint64_t *__restrict__ hkeys,
-                                uint64_t capmask, const int *__restrict__ slot_vid,
+                                const int *__restrict__ slot_vid,
                                 int *__restrict__ nbr_sub, int cap_sub) {
-    const int S = *count;
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= S) return;
     const uint64_t key = subkeys[id];
+    if (key == kEmpty) {
+        for (int j = 0; j < D1; ++j)
+            for (int sg = 0; sg < 2; ++sg)
+                nbr_sub[((size_t)j * cap_sub + id) * 2 + sg] = -1;
+        return;
+    }
     const uint64_t node = key / (uint64_t)M;
     const int v = int(key - node * (uint64_t)M);
+    long long base, size;
+    node_region((long long)node, l, N, D1, base, size);
     for (int j = 0; j < D1; ++j)
         for (int sg = 0; sg < 2; ++sg) {
             const int vn = nbr_global[((size_t)j * M + v) * 2 + sg];
             int nid = -1;
             if (vn >= 0) {
                 const uint64_t nk = node * (uint64_t)M + (uint64_t)vn;
-                uint64_t h = mix64(nk) & capmask;
-                for (uint64_t probe = 0; probe <= capmask; ++probe) {
-                    const uint64_t kk = hkeys[h];
+                long long h = region_slot(vn, size);
+                for (long long probe = 0; probe < size; ++probe) {
+                    const uint64_t kk = hkeys[base + h];
                     if (kk == nk) {
-                        nid = slot_vid[h];
+                        nid = slot_vid[base + h];
                         break;
                     }
                     if (kk == kEmpty) break;
-                    h = (h + 1) & capmask;
+                    if (++h == size) h = 0;
                 }
             }
             nbr_sub[((size_t)j * cap_sub + id) * 2 + sg] = nid;
         }
 }
 
-__global__ void k_fill_i32_lp(int *p) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
-}
-
-// one blur pass over the sub-lattice, 2 channels; the second pass clears V0
+// one blur pass over the sub-lattice (all S = N D1 numbers; those that are no
+// sub-vertex hold zeros and have no neighbours), 2 channels; the second pass
+// clears V0
 template <typename T>
-__global__ void k_lp_blur(const int *__restrict__ count, int j, int pass,
-                          int cap_sub, const int *__restrict__ nbr_sub,
-                          T *__restrict__ V0, T *__restrict__ V1,
-                          T *__restrict__ V2) {
-    const int S = *count;
+__global__ void k_lp_blur(int S, int j, int pass, int cap_sub,
+                          const int *__restrict__ nbr_sub, T *__restrict__ V0,
+                          T *__restrict__ V1, T *__restrict__ V2) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= S * 2) return;
     const int id = e >> 1;
@@ -499,7 +523,7 @@ struct LPWork {
         size_t cap = 0;
         int cap_sub = 0;
     } lat[DCRF_MAXK];
-    DevBuf g, part, cnt;
+    DevBuf g, part;
 };
 
 LPWork &lp_work(dcrf_ctx *ctx) {
@@ -545,25 +569,22 @@ void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l, const int *perm) {
     const hipStream_t s = ctx->stream;
     const int N = ctx->N, D1 = Lt.d + 1, M = Lt.M;
     const long long E = (long long)N * D1;
-    int *count = W.cnt.as<int>() + 4 * m;
     int *flags = ctx->scratch.as<int>();
     DCRF_TRY_HIP(hipMemsetAsync(P.hkeys.p, 0xff, P.cap * 8, s));
-    hipLaunchKernelGGL(k_fill_i32_lp, dim3(1), dim3(64), 0, s, count);
     hipLaunchKernelGGL(k_lp_insert, dim3(ceil_div(E, 256)), dim3(256), 0, s, N, l,
                        D1, M, perm, Lt.pix_vid.as<int>(), P.hkeys.as<uint64_t>(),
-                       uint64_t(P.cap - 1), P.ent_slot.as<int>(), flags, count,
-                       P.slot_vid.as<int>(), P.subkeys.as<uint64_t>());
+                       P.ent_slot.as<int>(), flags, P.slot_vid.as<int>(),
+                       P.subkeys.as<uint64_t>());
     hipLaunchKernelGGL((k_lp_splat<T>), dim3(ceil_div(E, 256)), dim3(256), 0, s,
                        N, l, D1, perm, Lt.pix_w.as<T>(), P.ent_slot.as<int>(),
                        P.slot_vid.as<int>(), P.ent_id.as<int>(), P.V[0].as<T>());
     hipLaunchKernelGGL(k_lp_neighbours, dim3(ceil_div(P.cap_sub, 256)), dim3(256),
-                       0, s, count, M, D1, P.subkeys.as<uint64_t>(),
-                       Lt.nbr.as<int>(), P.hkeys.as<uint64_t>(),
-                       uint64_t(P.cap - 1), P.slot_vid.as<int>(),
+                       0, s, P.cap_sub, N, l, M, D1, P.subkeys.as<uint64_t>(),
+                       Lt.nbr.as<int>(), P.hkeys.as<uint64_t>(), P.slot_vid.as<int>(),
                        P.nbr_sub.as<int>(), P.cap_sub);
     for (int pass = 0; pass < D1; ++pass)
         hipLaunchKernelGGL((k_lp_blur<T>), dim3(ceil_div(2ll * P.cap_sub, 256)),
-                           dim3(256), 0, s, count, pass, pass, P.cap_sub,
+                           dim3(256), 0, s, P.cap_sub, pass, pass, P.cap_sub,
                            P.nbr_sub.as<int>(), P.V[0].as<T>(), P.V[1].as<T>(),
                            P.V[2].as<T>());
     DCRF_CHECK_LAUNCH();
@@ -575,14 +596,15 @@ void lp_prepare(dcrf_ctx *ctx, LPWork &W, int L) {
     const int N = ctx->N;
     W.g.ensure((size_t)N * L * sizeof(T), s);
     W.part.ensure(1024 * 8, s);
-    W.cnt.ensure(64, s);
     if (ctx->mode == DCRF_FILTER_EXACT) return;
     for (int m = 0; m < ctx->nk; ++m) {
         auto &P = W.lat[m];
         const int D1 = ctx->lat[m].d + 1;
         const size_t E = (size_t)N * D1;
-        size_t cap = 1024;
-        while (cap < 2 * E) cap <<= 1;
+        // one region of twice its entries per node; slots are int32
+        if (2 * E > (size_t)INT32_MAX)
+            fail(DCRF_ERANGE, "image too large for the LP's sub-lattice tables");
+        const size_t cap = 2 * E;
         P.cap = cap;
         P.cap_sub = int(E);
         P.hkeys.ensure(cap * 8, s);
@@ -689,7 +711,7 @@ void lp_release(dcrf_ctx *ctx) {
     if (!ctx->lp) return;
     LPWork *W = static_cast<LPWork *>(ctx->lp);
     for (DevBuf *b : {&W->keys, &W->keys2, &W->vals, &W->vals2, &W->hist, &W->g,
-                      &W->part, &W->cnt})
+                      &W->part})
         b->release();
     for (auto &P : W->lat)
         for (DevBuf *b : {&P.hkeys, &P.slot_vid, &P.ent_slot, &P.ent_id,
