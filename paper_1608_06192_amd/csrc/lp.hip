@@ -134,11 +134,26 @@ k_rs_scatter(const K *__restrict__ keys, const int *__restrict__ vals, int n,
 
 // ---------------------------------------------------- divide and conquer
 
+// floor(a / b) for a >= 0, b > 0: below 2^52 the double quotient is within
+// one of the answer and one integer step corrects it (no 64-bit divide loop)
+__device__ __forceinline__ long long floor_div(long long a, long long b) {
+    if (a < (1ll << 52)) {
+        long long q = (long long)((double)a / (double)b);
+        const long long r = a - q * b;
+        if (r < 0)
+            --q;
+        else if (r >= b)
+            ++q;
+        return q;
+    }
+    return a / b;
+}
+
 // node of sorted position p at level l and whether both of its halves are
 // non-empty; side 0 = left half, 1 = right half
 __device__ __forceinline__ bool dnc_node(long long p, int l, long long N,
                                          long long &node, int &side) {
-    node = (((p + 1) << l) - 1) / N;
+    node = floor_div(((p + 1) << l) - 1, N);
     const long long lo = (node * N) >> l;
     const long long hi = ((node + 1) * N) >> l;
     const long long mid = ((2 * node + 1) * N) >> (l + 1);
@@ -168,20 +183,21 @@ __device__ __forceinline__ long long region_slot(int v, long long size) {
 // into the node's region. A new sub-vertex takes the number of the entry that
 // claims its slot: unique, below N D1, and found without a shared counter
 // (a single counter taken by every wave serialises across the chip). Entry e
-// writes subkeys[e] = its key if it claimed a slot, else empty, so the
-// sub-vertex numbers of a level are the e with a non-empty subkeys[e].
+// writes sub_nv[e] = (node, vertex) if it claimed a slot, else (-1, -1), so
+// the sub-vertex numbers of a level are the e with sub_nv[e].y >= 0.
 __global__ void k_lp_insert(int N, int l, int D1, int M,
                             const int *__restrict__ perm,
                             const int *__restrict__ pix_vid,
                             uint64_t *__restrict__ hkeys,
                             int *__restrict__ ent_slot, int *__restrict__ flags,
                             int *__restrict__ slot_vid,
-                            uint64_t *__restrict__ subkeys) {
+                            int2 *__restrict__ sub_nv, int *__restrict__ nbr_sub) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;   // N D1 < 2^31
     const bool in = e < N * D1;
     int slot = -1;
     bool claimed = false;
     uint64_t key = 0;
+    int2 nv = make_int2(-1, -1);
     if (in) {
         const int p = e / D1;
         const int k = e - p * D1;
@@ -191,6 +207,7 @@ __global__ void k_lp_insert(int N, int l, int D1, int M,
             const int v = pix_vid[(size_t)perm[p] * D1 + k];
             if (v >= 0) {
                 key = (uint64_t)node * (uint64_t)M + (uint64_t)v;
+                nv = make_int2(int(node), v);
                 long long base, size;
                 node_region(node, l, N, D1, base, size);
                 long long h = region_slot(v, size);
@@ -220,75 +237,148 @@ __global__ void k_lp_insert(int N, int l, int D1, int M,
     if (claimed) slot_vid[slot] = e;
     if (in) {
         ent_slot[e] = slot;
-        subkeys[e] = claimed ? key : kEmpty;
+        sub_nv[e] = claimed ? nv : make_int2(-1, -1);
+        // minus links start absent; the neighbour pass sets those present
+        for (int j = 0; j < D1; ++j) nbr_sub[((size_t)j * N * D1 + e) * 2 + 1] = -1;
     }
 }
 
 // splat the two half indicators: V0[id][side] += b; records the entry's
-// sub-vertex id for the slice
-template <typename T>
-__global__ void k_lp_splat(int N, int l, int D1, const int *__restrict__ perm,
-                           const T *__restrict__ pix_w,
-                           const int *__restrict__ ent_slot,
-                           const int *__restrict__ slot_vid,
-                           int *__restrict__ ent_id, T *__restrict__ V0) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;   // N D1 < 2^31
-    if (e >= N * D1) return;
-    const int s = ent_slot[e];
-    int id = -1;
-    if (s >= 0) {
-        const int p = e / D1;
-        const int k = e - p * D1;
-        long long node;
-        int side;
-        dnc_node(p, l, N, node, side);
-        id = slot_vid[s];
-        atomic_add(&V0[(size_t)id * 2 + side], pix_w[(size_t)perm[p] * D1 + k]);
+// sub-vertex id for the slice. Neighbouring positions share sub-vertices, so
+// a block first sums its entries per (id, side) in an LDS table (twice the
+// block's entries, so probing ends) and then adds each sum with one atomic.
+constexpr int kLpSplatThreads = 256;
+constexpr int kLpSplatSlots = 2 * kLpSplatThreads;
+
+// Small nodes share few sub-vertices within a block, and there each entry
+// adds directly (AGG = false).
+constexpr int kLpAggPixels = 64;   // node size from which the LDS sums pay
+
+template <typename T, bool AGG>
+__global__ void __launch_bounds__(kLpSplatThreads)
+k_lp_splat(int N, int l, int D1, const int *__restrict__ perm,
+           const T *__restrict__ pix_w, const int *__restrict__ ent_slot,
+           const int *__restrict__ slot_vid, int *__restrict__ ent_id,
+           T *__restrict__ V0) {
+    if (!AGG) {
+        const int e = blockIdx.x * kLpSplatThreads + threadIdx.x;
+        if (e >= N * D1) return;
+        const int s = ent_slot[e];
+        int id = -1;
+        if (s >= 0) {
+            const int p = e / D1;
+            const int k = e - p * D1;
+            long long node;
+            int side;
+            dnc_node(p, l, N, node, side);
+            id = slot_vid[s];
+            atomic_add(&V0[(size_t)id * 2 + side], pix_w[(size_t)perm[p] * D1 + k]);
+        }
+        ent_id[e] = id;
+        return;
     }
-    ent_id[e] = id;
+    __shared__ int skey[kLpSplatSlots];
+    __shared__ T sval[kLpSplatSlots];
+    for (int i = threadIdx.x; i < kLpSplatSlots; i += kLpSplatThreads) {
+        skey[i] = -1;
+        sval[i] = T(0);
+    }
+    __syncthreads();
+    const int e = blockIdx.x * kLpSplatThreads + threadIdx.x;   // N D1 < 2^31
+    if (e < N * D1) {
+        const int s = ent_slot[e];
+        int id = -1;
+        if (s >= 0) {
+            const int p = e / D1;
+            const int k = e - p * D1;
+            long long node;
+            int side;
+            dnc_node(p, l, N, node, side);
+            id = slot_vid[s];
+            const int key = id * 2 + side;   // < 2 N D1 < 2^31
+            const T w = pix_w[(size_t)perm[p] * D1 + k];
+            int h = int(mix64((uint64_t)key) & (kLpSplatSlots - 1));
+            for (int probe = 0; probe < kLpSplatSlots; ++probe) {
+                const int prev = atomicCAS(&skey[h], -1, key);
+                if (prev == -1 || prev == key) {
+                    atomicAdd(&sval[h], w);
+                    break;
+                }
+                h = (h + 1) & (kLpSplatSlots - 1);
+            }
+        }
+        ent_id[e] = id;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kLpSplatSlots; i += kLpSplatThreads) {
+        const int key = skey[i];
+        if (key >= 0) atomic_add(&V0[key], sval[i]);
+    }
 }
 
 // neighbours of every sub-vertex: (node, v +- u_j) when present in the node,
 // looked up in the node's region. Numbers that are no sub-vertex this level
 // get no neighbours, so the blur keeps them at zero.
-__global__ void k_lp_neighbours(int S, int N, int l, int M, int D1,
-                                const uint64_t *__restrict__ subkeys,
-                                const int *__restrict__ nbr_global,
-                                const uint64_t *__restrict__ hkeys,
-                                const int *__restrict__ slot_vid,
-                                int *__restrict__ nbr_sub, int cap_sub) {
+//
+// Only the d + 1 "plus" neighbours are looked up: (node, v + u_j) present
+// means its minus neighbour along j is (node, v), so a hit also writes that
+// reverse link (the insert pass set every minus link absent beforehand). The
+// lookups of a sub-vertex are independent: global neighbours, first probes
+// and sub-vertex numbers are each loaded for all directions before any is
+// used, so the loads overlap.
+constexpr int kLpMaxNb = 6;   // d + 1 for d <= 5
+
+__global__ void __launch_bounds__(256)
+k_lp_neighbours(int S, int N, int l, int M, int D1,
+                const int2 *__restrict__ sub_nv, const int *__restrict__ nbr_global,
+                const uint64_t *__restrict__ hkeys, const int *__restrict__ slot_vid,
+                int *__restrict__ nbr_sub, int cap_sub) {
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= S) return;
-    const uint64_t key = subkeys[id];
-    if (key == kEmpty) {
-        for (int j = 0; j < D1; ++j)
-            for (int sg = 0; sg < 2; ++sg)
-                nbr_sub[((size_t)j * cap_sub + id) * 2 + sg] = -1;
+    const int2 nv = sub_nv[id];
+    const int nq = D1;
+    if (nv.y < 0) {
+        for (int q = 0; q < nq; ++q) nbr_sub[((size_t)q * cap_sub + id) * 2] = -1;
         return;
     }
-    const uint64_t node = key / (uint64_t)M;
-    const int v = int(key - node * (uint64_t)M);
+    const long long node = nv.x;
     long long base, size;
-    node_region((long long)node, l, N, D1, base, size);
-    for (int j = 0; j < D1; ++j)
-        for (int sg = 0; sg < 2; ++sg) {
-            const int vn = nbr_global[((size_t)j * M + v) * 2 + sg];
-            int nid = -1;
-            if (vn >= 0) {
-                const uint64_t nk = node * (uint64_t)M + (uint64_t)vn;
-                long long h = region_slot(vn, size);
-                for (long long probe = 0; probe < size; ++probe) {
-                    const uint64_t kk = hkeys[base + h];
-                    if (kk == nk) {
-                        nid = slot_vid[base + h];
-                        break;
-                    }
-                    if (kk == kEmpty) break;
-                    if (++h == size) h = 0;
-                }
-            }
-            nbr_sub[((size_t)j * cap_sub + id) * 2 + sg] = nid;
+    node_region(node, l, N, D1, base, size);
+    int vn[kLpMaxNb];
+#pragma unroll
+    for (int q = 0; q < kLpMaxNb; ++q)
+        vn[q] = q < nq ? nbr_global[((size_t)q * M + nv.y) * 2] : -1;
+    long long h[kLpMaxNb];
+    uint64_t kk[kLpMaxNb];
+#pragma unroll
+    for (int q = 0; q < kLpMaxNb; ++q) {
+        h[q] = vn[q] >= 0 ? region_slot(vn[q], size) : 0;
+        kk[q] = vn[q] >= 0 ? hkeys[base + h[q]] : kEmpty;
+    }
+#pragma unroll
+    for (int q = 0; q < kLpMaxNb; ++q) {
+        if (vn[q] < 0) continue;
+        const uint64_t nk = (uint64_t)node * (uint64_t)M + (uint64_t)vn[q];
+        // a present key is rarely displaced: continue the probe only then
+        for (long long probe = 1; kk[q] != nk && kk[q] != kEmpty && probe < size;
+             ++probe) {
+            if (++h[q] == size) h[q] = 0;
+            kk[q] = hkeys[base + h[q]];
         }
+    }
+    int nid[kLpMaxNb];
+#pragma unroll
+    for (int q = 0; q < kLpMaxNb; ++q) {
+        const bool hit = vn[q] >= 0 &&
+                         kk[q] == (uint64_t)node * (uint64_t)M + (uint64_t)vn[q];
+        nid[q] = hit ? slot_vid[base + h[q]] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kLpMaxNb; ++q) {
+        if (q >= nq) continue;
+        nbr_sub[((size_t)q * cap_sub + id) * 2] = nid[q];
+        if (nid[q] >= 0) nbr_sub[((size_t)q * cap_sub + nid[q]) * 2 + 1] = id;
+    }
 }
 
 // one blur pass over the sub-lattice (all S = N D1 numbers; those that are no
@@ -519,7 +609,7 @@ k_dot(size_t n, const T *__restrict__ a, const T *__restrict__ b,
 struct LPWork {
     DevBuf keys, keys2, vals, vals2, hist;
     struct PerLat {
-        DevBuf hkeys, slot_vid, ent_slot, ent_id, subkeys, nbr_sub, V[3];
+        DevBuf hkeys, slot_vid, ent_slot, ent_id, sub_nv, nbr_sub, V[3];
         size_t cap = 0;
         int cap_sub = 0;
     } lat[DCRF_MAXK];
@@ -574,12 +664,19 @@ void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l, const int *perm) {
     hipLaunchKernelGGL(k_lp_insert, dim3(ceil_div(E, 256)), dim3(256), 0, s, N, l,
                        D1, M, perm, Lt.pix_vid.as<int>(), P.hkeys.as<uint64_t>(),
                        P.ent_slot.as<int>(), flags, P.slot_vid.as<int>(),
-                       P.subkeys.as<uint64_t>());
-    hipLaunchKernelGGL((k_lp_splat<T>), dim3(ceil_div(E, 256)), dim3(256), 0, s,
-                       N, l, D1, perm, Lt.pix_w.as<T>(), P.ent_slot.as<int>(),
-                       P.slot_vid.as<int>(), P.ent_id.as<int>(), P.V[0].as<T>());
+                       P.sub_nv.as<int2>(), P.nbr_sub.as<int>());
+    if ((N >> l) >= kLpAggPixels)
+        hipLaunchKernelGGL((k_lp_splat<T, true>), dim3(ceil_div(E, kLpSplatThreads)),
+                           dim3(kLpSplatThreads), 0, s, N, l, D1, perm,
+                           Lt.pix_w.as<T>(), P.ent_slot.as<int>(),
+                           P.slot_vid.as<int>(), P.ent_id.as<int>(), P.V[0].as<T>());
+    else
+        hipLaunchKernelGGL((k_lp_splat<T, false>), dim3(ceil_div(E, kLpSplatThreads)),
+                           dim3(kLpSplatThreads), 0, s, N, l, D1, perm,
+                           Lt.pix_w.as<T>(), P.ent_slot.as<int>(),
+                           P.slot_vid.as<int>(), P.ent_id.as<int>(), P.V[0].as<T>());
     hipLaunchKernelGGL(k_lp_neighbours, dim3(ceil_div(P.cap_sub, 256)), dim3(256),
-                       0, s, P.cap_sub, N, l, M, D1, P.subkeys.as<uint64_t>(),
+                       0, s, P.cap_sub, N, l, M, D1, P.sub_nv.as<int2>(),
                        Lt.nbr.as<int>(), P.hkeys.as<uint64_t>(), P.slot_vid.as<int>(),
                        P.nbr_sub.as<int>(), P.cap_sub);
     for (int pass = 0; pass < D1; ++pass)
@@ -600,6 +697,8 @@ void lp_prepare(dcrf_ctx *ctx, LPWork &W, int L) {
     for (int m = 0; m < ctx->nk; ++m) {
         auto &P = W.lat[m];
         const int D1 = ctx->lat[m].d + 1;
+        if (D1 > kLpMaxNb)
+            fail(DCRF_EUNSUPPORTED, "the LP takes lattices of dimension <= 5");
         const size_t E = (size_t)N * D1;
         // one region of twice its entries per node; slots are int32
         if (2 * E > (size_t)INT32_MAX)
@@ -611,7 +710,7 @@ void lp_prepare(dcrf_ctx *ctx, LPWork &W, int L) {
         P.slot_vid.ensure(cap * 4, s);
         P.ent_slot.ensure(E * 4, s);
         P.ent_id.ensure(E * 4, s);
-        P.subkeys.ensure(E * 8, s);
+        P.sub_nv.ensure(E * sizeof(int2), s);
         P.nbr_sub.ensure(E * D1 * 2 * 4, s);
         for (int b = 0; b < 3; ++b) P.V[b].ensure(E * 2 * sizeof(T), s);
     }
@@ -715,7 +814,7 @@ void lp_release(dcrf_ctx *ctx) {
         b->release();
     for (auto &P : W->lat)
         for (DevBuf *b : {&P.hkeys, &P.slot_vid, &P.ent_slot, &P.ent_id,
-                          &P.subkeys, &P.nbr_sub, &P.V[0], &P.V[1], &P.V[2]})
+                          &P.sub_nv, &P.nbr_sub, &P.V[0], &P.V[1], &P.V[2]})
             b->release();
     delete W;
     ctx->lp = nullptr;
