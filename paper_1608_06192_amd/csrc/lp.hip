@@ -186,8 +186,7 @@ __device__ __forceinline__ long long region_slot(int v, long long size) {
 // writes sub_nv[e] = (node, vertex) if it claimed a slot, else (-1, -1), so
 // the sub-vertex numbers of a level are the e with sub_nv[e].y >= 0.
 __global__ void k_lp_insert(int N, int l, int D1, int M,
-                            const int *__restrict__ perm,
-                            const int *__restrict__ pix_vid,
+                            const int *__restrict__ pos_vid,
                             uint64_t *__restrict__ hkeys,
                             int *__restrict__ ent_slot, int *__restrict__ flags,
                             int *__restrict__ slot_vid,
@@ -204,7 +203,7 @@ __global__ void k_lp_insert(int N, int l, int D1, int M,
         long long node;
         int side;
         if (dnc_node(p, l, N, node, side)) {
-            const int v = pix_vid[(size_t)perm[p] * D1 + k];
+            const int v = pos_vid[e];
             if (v >= 0) {
                 key = (uint64_t)node * (uint64_t)M + (uint64_t)v;
                 nv = make_int2(int(node), v);
@@ -239,7 +238,7 @@ __global__ void k_lp_insert(int N, int l, int D1, int M,
         ent_slot[e] = slot;
         sub_nv[e] = claimed ? nv : make_int2(-1, -1);
         // minus links start absent; the neighbour pass sets those present
-        for (int j = 0; j < D1; ++j) nbr_sub[((size_t)j * N * D1 + e) * 2 + 1] = -1;
+        for (int j = 0; j < D1; ++j) nbr_sub[(size_t)(2 * j + 1) * N * D1 + e] = -1;
     }
 }
 
@@ -256,8 +255,8 @@ constexpr int kLpAggPixels = 64;   // node size from which the LDS sums pay
 
 template <typename T, bool AGG>
 __global__ void __launch_bounds__(kLpSplatThreads)
-k_lp_splat(int N, int l, int D1, const int *__restrict__ perm,
-           const T *__restrict__ pix_w, const int *__restrict__ ent_slot,
+k_lp_splat(int N, int l, int D1, const T *__restrict__ pos_w,
+           const int *__restrict__ ent_slot,
            const int *__restrict__ slot_vid, int *__restrict__ ent_id,
            T *__restrict__ V0) {
     if (!AGG) {
@@ -272,7 +271,7 @@ k_lp_splat(int N, int l, int D1, const int *__restrict__ perm,
             int side;
             dnc_node(p, l, N, node, side);
             id = slot_vid[s];
-            atomic_add(&V0[(size_t)id * 2 + side], pix_w[(size_t)perm[p] * D1 + k]);
+            atomic_add(&V0[(size_t)id * 2 + side], pos_w[e]);
         }
         ent_id[e] = id;
         return;
@@ -296,7 +295,7 @@ k_lp_splat(int N, int l, int D1, const int *__restrict__ perm,
             dnc_node(p, l, N, node, side);
             id = slot_vid[s];
             const int key = id * 2 + side;   // < 2 N D1 < 2^31
-            const T w = pix_w[(size_t)perm[p] * D1 + k];
+            const T w = pos_w[e];
             int h = int(mix64((uint64_t)key) & (kLpSplatSlots - 1));
             for (int probe = 0; probe < kLpSplatSlots; ++probe) {
                 const int prev = atomicCAS(&skey[h], -1, key);
@@ -338,7 +337,7 @@ k_lp_neighbours(int S, int N, int l, int M, int D1,
     const int2 nv = sub_nv[id];
     const int nq = D1;
     if (nv.y < 0) {
-        for (int q = 0; q < nq; ++q) nbr_sub[((size_t)q * cap_sub + id) * 2] = -1;
+        for (int q = 0; q < nq; ++q) nbr_sub[(size_t)(2 * q) * cap_sub + id] = -1;
         return;
     }
     const long long node = nv.x;
@@ -376,35 +375,41 @@ k_lp_neighbours(int S, int N, int l, int M, int D1,
 #pragma unroll
     for (int q = 0; q < kLpMaxNb; ++q) {
         if (q >= nq) continue;
-        nbr_sub[((size_t)q * cap_sub + id) * 2] = nid[q];
-        if (nid[q] >= 0) nbr_sub[((size_t)q * cap_sub + nid[q]) * 2 + 1] = id;
+        nbr_sub[(size_t)(2 * q) * cap_sub + id] = nid[q];
+        if (nid[q] >= 0) nbr_sub[(size_t)(2 * q + 1) * cap_sub + nid[q]] = id;
     }
 }
 
 // one blur pass over the sub-lattice (all S = N D1 numbers; those that are no
-// sub-vertex hold zeros and have no neighbours), 2 channels; the second pass
-// clears V0
+// sub-vertex hold zeros and have no neighbours): one thread per sub-vertex
+// moves both channels as one 2-vector; the second pass clears V0
+template <typename T>
+struct alignas(2 * sizeof(T)) LpPair {
+    T c0, c1;
+};
+
 template <typename T>
 __global__ void k_lp_blur(int S, int j, int pass, int cap_sub,
-                          const int *__restrict__ nbr_sub, T *__restrict__ V0,
-                          T *__restrict__ V1, T *__restrict__ V2) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= S * 2) return;
-    const int id = e >> 1;
-    const int c = e & 1;
-    const T *src = (pass == 0) ? V0 : ((pass & 1) ? V1 : V2);
-    T *dst = (pass & 1) ? V2 : V1;
-    const int np = nbr_sub[((size_t)j * cap_sub + id) * 2 + 0];
-    const int nm = nbr_sub[((size_t)j * cap_sub + id) * 2 + 1];
-    const T vp = np >= 0 ? src[(size_t)np * 2 + c] : T(0);
-    const T vm = nm >= 0 ? src[(size_t)nm * 2 + c] : T(0);
-    dst[e] = T(0.5) * src[e] + T(0.25) * (vp + vm);
-    if (pass == 1) V0[e] = T(0);
+                          const int *__restrict__ nbr_sub, LpPair<T> *__restrict__ V0,
+                          LpPair<T> *__restrict__ V1, LpPair<T> *__restrict__ V2) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= S) return;
+    const LpPair<T> *src = (pass == 0) ? V0 : ((pass & 1) ? V1 : V2);
+    LpPair<T> *dst = (pass & 1) ? V2 : V1;
+    const int np = nbr_sub[(size_t)(2 * j) * cap_sub + id];
+    const int nm = nbr_sub[(size_t)(2 * j + 1) * cap_sub + id];
+    const LpPair<T> zero{T(0), T(0)};
+    const LpPair<T> x = src[id];
+    const LpPair<T> vp = np >= 0 ? src[np] : zero;
+    const LpPair<T> vm = nm >= 0 ? src[nm] : zero;
+    dst[id] = LpPair<T>{T(0.5) * x.c0 + T(0.25) * (vp.c0 + vm.c0),
+                        T(0.5) * x.c1 + T(0.25) * (vp.c1 + vm.c1)};
+    if (pass == 1) V0[id] = zero;
 }
 
 template <typename T>
 struct LPLat {
-    const T *pix_w;
+    const T *pos_w;
     const int *ent_id;
     const T *Vf;
     int D1;
@@ -418,30 +423,53 @@ struct LPLats {
 };
 
 // slice: the right channel at left points adds to U, the left channel at
-// right points adds to Lo; g[a][col] += U - Lo
+// right points adds to Lo; acc[p] += U - Lo for sorted position p (added to
+// g once the label's levels are done)
 template <typename T>
-__global__ void k_lp_slice(int N, int l, int L, int col,
-                           const int *__restrict__ perm, LPLats<T> lats,
-                           T *__restrict__ g) {
+__global__ void k_lp_slice(int N, int l, LPLats<T> lats, T *__restrict__ acc) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     long long node;
     int side;
     if (!dnc_node(p, l, N, node, side)) return;
-    const int a = perm[p];
     const int ch = 1 - side;
-    T acc = T(0);
+    T t = T(0);
     for (int m = 0; m < lats.nk; ++m) {
         const LPLat<T> &X = lats.l[m];
         T s = T(0);
         for (int k = 0; k < X.D1; ++k) {
             const int id = X.ent_id[(size_t)p * X.D1 + k];
             if (id >= 0)
-                s += X.pix_w[(size_t)a * X.D1 + k] * X.Vf[(size_t)id * 2 + ch];
+                s += X.pos_w[(size_t)p * X.D1 + k] * X.Vf[(size_t)id * 2 + ch];
         }
-        acc += X.wg * s;
+        t += X.wg * s;
     }
-    g[(size_t)a * L + col] += side == 0 ? acc : -acc;
+    acc[p] += side == 0 ? t : -t;
+}
+
+// the label's vertex ids and weights in sorted-position order, gathered once
+// for all its levels: pos_vid[p D1 + k] = vid[perm[p] D1 + k]
+template <typename T>
+__global__ void k_lp_gather(int N, int D1, const int *__restrict__ perm,
+                            const int *__restrict__ pix_vid,
+                            const T *__restrict__ pix_w, int *__restrict__ pos_vid,
+                            T *__restrict__ pos_w) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;   // N D1 < 2^31
+    if (e >= N * D1) return;
+    const int p = e / D1;
+    const size_t src = (size_t)perm[p] * D1 + (e - p * D1);
+    pos_vid[e] = pix_vid[src];
+    pos_w[e] = pix_w[src];
+}
+
+// g[perm[p]][col] += acc[p], and acc returns to zero for the next label
+template <typename T>
+__global__ void k_lp_add_col(int N, int L, int col, const int *__restrict__ perm,
+                             T *__restrict__ acc, T *__restrict__ g) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    g[(size_t)perm[p] * L + col] += acc[p];
+    acc[p] = T(0);
 }
 
 // exact mode: for the point at sorted position p,
@@ -610,10 +638,11 @@ struct LPWork {
     DevBuf keys, keys2, vals, vals2, hist;
     struct PerLat {
         DevBuf hkeys, slot_vid, ent_slot, ent_id, sub_nv, nbr_sub, V[3];
+        DevBuf pos_vid, pos_w;   // the label's vertex ids and weights by position
         size_t cap = 0;
         int cap_sub = 0;
     } lat[DCRF_MAXK];
-    DevBuf g, part;
+    DevBuf g, part, acc;
 };
 
 LPWork &lp_work(dcrf_ctx *ctx) {
@@ -653,7 +682,7 @@ void sort_column(dcrf_ctx *ctx, LPWork &W, const T *y, int L, int col,
 }
 
 template <typename T>
-void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l, const int *perm) {
+void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l) {
     Lattice &Lt = ctx->lat[m];
     auto &P = W.lat[m];
     const hipStream_t s = ctx->stream;
@@ -662,28 +691,28 @@ void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l, const int *perm) {
     int *flags = ctx->scratch.as<int>();
     DCRF_TRY_HIP(hipMemsetAsync(P.hkeys.p, 0xff, P.cap * 8, s));
     hipLaunchKernelGGL(k_lp_insert, dim3(ceil_div(E, 256)), dim3(256), 0, s, N, l,
-                       D1, M, perm, Lt.pix_vid.as<int>(), P.hkeys.as<uint64_t>(),
+                       D1, M, P.pos_vid.as<int>(), P.hkeys.as<uint64_t>(),
                        P.ent_slot.as<int>(), flags, P.slot_vid.as<int>(),
                        P.sub_nv.as<int2>(), P.nbr_sub.as<int>());
     if ((N >> l) >= kLpAggPixels)
         hipLaunchKernelGGL((k_lp_splat<T, true>), dim3(ceil_div(E, kLpSplatThreads)),
-                           dim3(kLpSplatThreads), 0, s, N, l, D1, perm,
-                           Lt.pix_w.as<T>(), P.ent_slot.as<int>(),
+                           dim3(kLpSplatThreads), 0, s, N, l, D1,
+                           P.pos_w.as<T>(), P.ent_slot.as<int>(),
                            P.slot_vid.as<int>(), P.ent_id.as<int>(), P.V[0].as<T>());
     else
         hipLaunchKernelGGL((k_lp_splat<T, false>), dim3(ceil_div(E, kLpSplatThreads)),
-                           dim3(kLpSplatThreads), 0, s, N, l, D1, perm,
-                           Lt.pix_w.as<T>(), P.ent_slot.as<int>(),
+                           dim3(kLpSplatThreads), 0, s, N, l, D1,
+                           P.pos_w.as<T>(), P.ent_slot.as<int>(),
                            P.slot_vid.as<int>(), P.ent_id.as<int>(), P.V[0].as<T>());
     hipLaunchKernelGGL(k_lp_neighbours, dim3(ceil_div(P.cap_sub, 256)), dim3(256),
                        0, s, P.cap_sub, N, l, M, D1, P.sub_nv.as<int2>(),
                        Lt.nbr.as<int>(), P.hkeys.as<uint64_t>(), P.slot_vid.as<int>(),
                        P.nbr_sub.as<int>(), P.cap_sub);
     for (int pass = 0; pass < D1; ++pass)
-        hipLaunchKernelGGL((k_lp_blur<T>), dim3(ceil_div(2ll * P.cap_sub, 256)),
+        hipLaunchKernelGGL((k_lp_blur<T>), dim3(ceil_div(P.cap_sub, 256)),
                            dim3(256), 0, s, P.cap_sub, pass, pass, P.cap_sub,
-                           P.nbr_sub.as<int>(), P.V[0].as<T>(), P.V[1].as<T>(),
-                           P.V[2].as<T>());
+                           P.nbr_sub.as<int>(), P.V[0].as<LpPair<T>>(),
+                           P.V[1].as<LpPair<T>>(), P.V[2].as<LpPair<T>>());
     DCRF_CHECK_LAUNCH();
 }
 
@@ -694,6 +723,7 @@ void lp_prepare(dcrf_ctx *ctx, LPWork &W, int L) {
     W.g.ensure((size_t)N * L * sizeof(T), s);
     W.part.ensure(1024 * 8, s);
     if (ctx->mode == DCRF_FILTER_EXACT) return;
+    W.acc.ensure((size_t)N * sizeof(T), s);   // zero between labels
     for (int m = 0; m < ctx->nk; ++m) {
         auto &P = W.lat[m];
         const int D1 = ctx->lat[m].d + 1;
@@ -713,6 +743,8 @@ void lp_prepare(dcrf_ctx *ctx, LPWork &W, int L) {
         P.sub_nv.ensure(E * sizeof(int2), s);
         P.nbr_sub.ensure(E * D1 * 2 * 4, s);
         for (int b = 0; b < 3; ++b) P.V[b].ensure(E * 2 * sizeof(T), s);
+        P.pos_vid.ensure(E * 4, s);
+        P.pos_w.ensure(E * sizeof(T), s);
     }
 }
 
@@ -738,20 +770,31 @@ double lp_subgradient_t(dcrf_ctx *ctx, const T *phi, int L, const T *y, T *g) {
             DCRF_CHECK_LAUNCH();
             continue;
         }
+        for (int m = 0; m < ctx->nk; ++m) {
+            Lattice &Lt = ctx->lat[m];
+            const int D1 = Lt.d + 1;
+            hipLaunchKernelGGL((k_lp_gather<T>), dim3(ceil_div((long long)N * D1, 256)),
+                               dim3(256), 0, s, N, D1, perm, Lt.pix_vid.as<int>(),
+                               Lt.pix_w.as<T>(), W.lat[m].pos_vid.as<int>(),
+                               W.lat[m].pos_w.as<T>());
+        }
         for (int l = 0; l < levels; ++l) {
-            for (int m = 0; m < ctx->nk; ++m) lp_level<T>(ctx, W, m, l, perm);
+            for (int m = 0; m < ctx->nk; ++m) lp_level<T>(ctx, W, m, l);
             LPLats<T> lats{};
             lats.nk = ctx->nk;
             for (int m = 0; m < ctx->nk; ++m) {
                 Lattice &Lt = ctx->lat[m];
-                lats.l[m] = LPLat<T>{Lt.pix_w.as<T>(), W.lat[m].ent_id.as<int>(),
+                lats.l[m] = LPLat<T>{W.lat[m].pos_w.as<T>(), W.lat[m].ent_id.as<int>(),
                                      W.lat[m].V[final_buffer(Lt.d)].as<T>(), Lt.d + 1,
                                      T(ctx->kern[m].weight * Lt.gamma)};
             }
             hipLaunchKernelGGL((k_lp_slice<T>), dim3(ceil_div(N, 256)), dim3(256),
-                               0, s, N, l, L, col, perm, lats, g);
+                               0, s, N, l, lats, W.acc.as<T>());
             DCRF_CHECK_LAUNCH();
         }
+        hipLaunchKernelGGL((k_lp_add_col<T>), dim3(ceil_div(N, 256)), dim3(256), 0, s,
+                           N, L, col, perm, W.acc.as<T>(), g);
+        DCRF_CHECK_LAUNCH();
     }
     int hflags = 0;
     DCRF_TRY_HIP(hipMemcpyAsync(&hflags, ctx->scratch.p, 4, hipMemcpyDeviceToHost, s));
@@ -810,11 +853,12 @@ void lp_release(dcrf_ctx *ctx) {
     if (!ctx->lp) return;
     LPWork *W = static_cast<LPWork *>(ctx->lp);
     for (DevBuf *b : {&W->keys, &W->keys2, &W->vals, &W->vals2, &W->hist, &W->g,
-                      &W->part})
+                      &W->part, &W->acc})
         b->release();
     for (auto &P : W->lat)
         for (DevBuf *b : {&P.hkeys, &P.slot_vid, &P.ent_slot, &P.ent_id,
-                          &P.sub_nv, &P.nbr_sub, &P.V[0], &P.V[1], &P.V[2]})
+                          &P.sub_nv, &P.nbr_sub, &P.V[0], &P.V[1], &P.V[2],
+                          &P.pos_vid, &P.pos_w})
             b->release();
     delete W;
     ctx->lp = nullptr;
