@@ -388,24 +388,46 @@ struct alignas(2 * sizeof(T)) LpPair {
     T c0, c1;
 };
 
-template <typename T>
-__global__ void k_lp_blur(int S, int j, int pass, int cap_sub,
-                          const int *__restrict__ nbr_sub, LpPair<T> *__restrict__ V0,
-                          LpPair<T> *__restrict__ V1, LpPair<T> *__restrict__ V2) {
+// G = 1: pass j; G = 2: passes j then j + 1 in one launch. Per sub-vertex the
+// second pass combines the first pass's values at the vertex and its two
+// neighbours along j + 1, each computed as the single pass computes it, so
+// the result is the same as two launches. `clr` (may be null) is set to zero.
+template <typename T, int G>
+__global__ void k_lp_blur(int S, int j, int cap_sub, const int *__restrict__ nbr_sub,
+                          const LpPair<T> *__restrict__ src,
+                          LpPair<T> *__restrict__ dst, LpPair<T> *__restrict__ clr) {
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= S) return;
-    const LpPair<T> *src = (pass == 0) ? V0 : ((pass & 1) ? V1 : V2);
-    LpPair<T> *dst = (pass & 1) ? V2 : V1;
-    const int np = nbr_sub[(size_t)(2 * j) * cap_sub + id];
-    const int nm = nbr_sub[(size_t)(2 * j + 1) * cap_sub + id];
     const LpPair<T> zero{T(0), T(0)};
-    const LpPair<T> x = src[id];
-    const LpPair<T> vp = np >= 0 ? src[np] : zero;
-    const LpPair<T> vm = nm >= 0 ? src[nm] : zero;
-    dst[id] = LpPair<T>{T(0.5) * x.c0 + T(0.25) * (vp.c0 + vm.c0),
+    auto pass = [&](int y) {
+        const int np = nbr_sub[(size_t)(2 * j) * cap_sub + y];
+        const int nm = nbr_sub[(size_t)(2 * j + 1) * cap_sub + y];
+        const LpPair<T> x = src[y];
+        const LpPair<T> vp = np >= 0 ? src[np] : zero;
+        const LpPair<T> vm = nm >= 0 ? src[nm] : zero;
+        return LpPair<T>{T(0.5) * x.c0 + T(0.25) * (vp.c0 + vm.c0),
+                         T(0.5) * x.c1 + T(0.25) * (vp.c1 + vm.c1)};
+    };
+    LpPair<T> out;
+    if (G == 1) {
+        out = pass(id);
+    } else {
+        const int np = nbr_sub[(size_t)(2 * j + 2) * cap_sub + id];
+        const int nm = nbr_sub[(size_t)(2 * j + 3) * cap_sub + id];
+        const LpPair<T> x = pass(id);
+        const LpPair<T> vp = np >= 0 ? pass(np) : zero;
+        const LpPair<T> vm = nm >= 0 ? pass(nm) : zero;
+        out = LpPair<T>{T(0.5) * x.c0 + T(0.25) * (vp.c0 + vm.c0),
                         T(0.5) * x.c1 + T(0.25) * (vp.c1 + vm.c1)};
-    if (pass == 1) V0[id] = zero;
+    }
+    dst[id] = out;
+    if (clr) clr[id] = zero;
 }
+
+// blur launches of a sub-lattice with D1 directions: two directions per
+// launch; the first launch reads V0, later ones alternate V1 -> V2 -> V1, and
+// the second clears V0 for the next level (D1 >= 3, so there is a second)
+inline int lp_blur_launches(int D1) { return (D1 + 1) / 2; }
 
 template <typename T>
 struct LPLat {
@@ -708,11 +730,22 @@ void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l) {
                        0, s, P.cap_sub, N, l, M, D1, P.sub_nv.as<int2>(),
                        Lt.nbr.as<int>(), P.hkeys.as<uint64_t>(), P.slot_vid.as<int>(),
                        P.nbr_sub.as<int>(), P.cap_sub);
-    for (int pass = 0; pass < D1; ++pass)
-        hipLaunchKernelGGL((k_lp_blur<T>), dim3(ceil_div(P.cap_sub, 256)),
-                           dim3(256), 0, s, P.cap_sub, pass, pass, P.cap_sub,
-                           P.nbr_sub.as<int>(), P.V[0].as<LpPair<T>>(),
-                           P.V[1].as<LpPair<T>>(), P.V[2].as<LpPair<T>>());
+    LpPair<T> *V0 = P.V[0].as<LpPair<T>>(), *V1 = P.V[1].as<LpPair<T>>(),
+              *V2 = P.V[2].as<LpPair<T>>();
+    const int nl = lp_blur_launches(D1);
+    for (int t = 0; t < nl; ++t) {
+        const LpPair<T> *src = t == 0 ? V0 : ((t & 1) ? V1 : V2);
+        LpPair<T> *dst = (t & 1) ? V2 : V1;
+        LpPair<T> *clr = t == 1 ? V0 : nullptr;
+        if (2 * t + 1 < D1)
+            hipLaunchKernelGGL((k_lp_blur<T, 2>), dim3(ceil_div(P.cap_sub, 256)),
+                               dim3(256), 0, s, P.cap_sub, 2 * t, P.cap_sub,
+                               P.nbr_sub.as<int>(), src, dst, clr);
+        else
+            hipLaunchKernelGGL((k_lp_blur<T, 1>), dim3(ceil_div(P.cap_sub, 256)),
+                               dim3(256), 0, s, P.cap_sub, 2 * t, P.cap_sub,
+                               P.nbr_sub.as<int>(), src, dst, clr);
+    }
     DCRF_CHECK_LAUNCH();
 }
 
@@ -727,8 +760,8 @@ void lp_prepare(dcrf_ctx *ctx, LPWork &W, int L) {
     for (int m = 0; m < ctx->nk; ++m) {
         auto &P = W.lat[m];
         const int D1 = ctx->lat[m].d + 1;
-        if (D1 > kLpMaxNb)
-            fail(DCRF_EUNSUPPORTED, "the LP takes lattices of dimension <= 5");
+        if (D1 > kLpMaxNb || D1 < 3)
+            fail(DCRF_EUNSUPPORTED, "the LP takes lattices of dimension 2 to 5");
         const size_t E = (size_t)N * D1;
         // one region of twice its entries per node; slots are int32
         if (2 * E > (size_t)INT32_MAX)
@@ -785,7 +818,7 @@ double lp_subgradient_t(dcrf_ctx *ctx, const T *phi, int L, const T *y, T *g) {
             for (int m = 0; m < ctx->nk; ++m) {
                 Lattice &Lt = ctx->lat[m];
                 lats.l[m] = LPLat<T>{W.lat[m].pos_w.as<T>(), W.lat[m].ent_id.as<int>(),
-                                     W.lat[m].V[final_buffer(Lt.d)].as<T>(), Lt.d + 1,
+                                     W.lat[m].V[final_buffer_after(lp_blur_launches(Lt.d + 1))].as<T>(), Lt.d + 1,
                                      T(ctx->kern[m].weight * Lt.gamma)};
             }
             hipLaunchKernelGGL((k_lp_slice<T>), dim3(ceil_div(N, 256)), dim3(256),
