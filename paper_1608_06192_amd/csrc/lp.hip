@@ -18,7 +18,9 @@
 // that inserts it), and its blur follows the global neighbour table, keeping
 // neighbours present in the same node. Each node probes only its own region
 // of the table (twice its entries), so the probes of neighbouring positions
-// stay in a few cache lines.
+// stay in a few cache lines; blocks map to XCDs in contiguous ranges of
+// positions (xcd_block), so from the third level on a node's region and its
+// sub-vertex rows are used by one XCD's L2.
 // All nodes of a level are filtered in one pass; labels are processed one at
 // a time (their hash tables then stay cache-resident).
 //
@@ -191,7 +193,7 @@ __global__ void k_lp_insert(int N, int l, int D1, int M,
                             int *__restrict__ ent_slot, int *__restrict__ flags,
                             int *__restrict__ slot_vid,
                             int2 *__restrict__ sub_nv, int *__restrict__ nbr_sub) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;   // N D1 < 2^31
+    const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;   // N D1 < 2^31
     const bool in = e < N * D1;
     int slot = -1;
     bool claimed = false;
@@ -260,7 +262,7 @@ k_lp_splat(int N, int l, int D1, const T *__restrict__ pos_w,
            const int *__restrict__ slot_vid, int *__restrict__ ent_id,
            T *__restrict__ V0) {
     if (!AGG) {
-        const int e = blockIdx.x * kLpSplatThreads + threadIdx.x;
+        const int e = xcd_block(blockIdx.x, gridDim.x) * kLpSplatThreads + threadIdx.x;
         if (e >= N * D1) return;
         const int s = ent_slot[e];
         int id = -1;
@@ -283,7 +285,7 @@ k_lp_splat(int N, int l, int D1, const T *__restrict__ pos_w,
         sval[i] = T(0);
     }
     __syncthreads();
-    const int e = blockIdx.x * kLpSplatThreads + threadIdx.x;   // N D1 < 2^31
+    const int e = xcd_block(blockIdx.x, gridDim.x) * kLpSplatThreads + threadIdx.x;   // N D1 < 2^31
     if (e < N * D1) {
         const int s = ent_slot[e];
         int id = -1;
@@ -332,7 +334,7 @@ k_lp_neighbours(int S, int N, int l, int M, int D1,
                 const int2 *__restrict__ sub_nv, const int *__restrict__ nbr_global,
                 const uint64_t *__restrict__ hkeys, const int *__restrict__ slot_vid,
                 int *__restrict__ nbr_sub, int cap_sub) {
-    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    const int id = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (id >= S) return;
     const int2 nv = sub_nv[id];
     const int nq = D1;
@@ -396,7 +398,7 @@ template <typename T, int G>
 __global__ void k_lp_blur(int S, int j, int cap_sub, const int *__restrict__ nbr_sub,
                           const LpPair<T> *__restrict__ src,
                           LpPair<T> *__restrict__ dst, LpPair<T> *__restrict__ clr) {
-    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    const int id = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (id >= S) return;
     const LpPair<T> zero{T(0), T(0)};
     auto pass = [&](int y) {
@@ -449,7 +451,7 @@ struct LPLats {
 // g once the label's levels are done)
 template <typename T>
 __global__ void k_lp_slice(int N, int l, LPLats<T> lats, T *__restrict__ acc) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (p >= N) return;
     long long node;
     int side;
@@ -476,7 +478,7 @@ __global__ void k_lp_gather(int N, int D1, const int *__restrict__ perm,
                             const int *__restrict__ pix_vid,
                             const T *__restrict__ pix_w, int *__restrict__ pos_vid,
                             T *__restrict__ pos_w) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;   // N D1 < 2^31
+    const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;   // N D1 < 2^31
     if (e >= N * D1) return;
     const int p = e / D1;
     const size_t src = (size_t)perm[p] * D1 + (e - p * D1);
