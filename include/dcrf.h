@@ -242,7 +242,10 @@ int dcrf_energy(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
  * node's points; with DCRF_FILTER_EXACT they are summed exactly, O(N^2) per
  * label. unary, y: (dev) N x L (y in the feasible set); g: (dev) N x L out;
  * *S_lp (host) = <g, y>, the LP objective at y. Waits for the stream. The
- * label compatibility is Potts; no mu argument is taken. */
+ * label compatibility is Potts; no mu argument is taken. Lattice mode keeps
+ * one sub-lattice table per kernel of 2 N (d+1) slots: DCRF_ERANGE if that
+ * exceeds 2^31 - 1 (about 179 M pixels with the bilateral kernel); a batch
+ * context gives DCRF_EUNSUPPORTED. */
 int dcrf_lp_subgradient(dcrf_ctx *ctx, const void *unary, int L, const void *y,
                         void *g, double *S_lp);
 
