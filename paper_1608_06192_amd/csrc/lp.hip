@@ -201,7 +201,6 @@ __global__ void k_lp_insert(int N, int l, int D1, int M,
     int2 nv = make_int2(-1, -1);
     if (in) {
         const int p = e / D1;
-        const int k = e - p * D1;
         long long node;
         int side;
         if (dnc_node(p, l, N, node, side)) {
@@ -268,7 +267,6 @@ k_lp_splat(int N, int l, int D1, const T *__restrict__ pos_w,
         int id = -1;
         if (s >= 0) {
             const int p = e / D1;
-            const int k = e - p * D1;
             long long node;
             int side;
             dnc_node(p, l, N, node, side);
@@ -291,7 +289,6 @@ k_lp_splat(int N, int l, int D1, const T *__restrict__ pos_w,
         int id = -1;
         if (s >= 0) {
             const int p = e / D1;
-            const int k = e - p * D1;
             long long node;
             int side;
             dnc_node(p, l, N, node, side);

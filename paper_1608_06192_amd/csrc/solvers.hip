@@ -14,12 +14,15 @@
 //   2. the gather splat of the one-hot s into the lattices;
 //   3. the blur passes;
 //   4. k_fw_slice: slice, apply mu and the diagonal, P_s = (Psi + D) s,
-//      reduce <y,P_s> and <s,P_s> per block;
-//   5. k_fw_alpha: one block per image reduces that image's partial sums in
-//      a fixed order and solves its step size on the device (App. B,
-//      eq. alpha-opt, written with the four products so that it is exact for
-//      a non-symmetric approximate Psi; endpoints when the quadratic is not
-//      convex).
+//      reduce <y,P_s> and <s,P_s> per block.
+// The blocks of steps 1 and 4 add their sums to per-image accumulators, one
+// set per XCD (device atomics), and every block of the next iteration's step
+// 1 (or k_fw_final after the last) adds the sets up in a fixed order and
+// solves the step size itself (App. B, eq. alpha-opt, written with the four
+// products so that it is exact for a non-symmetric approximate Psi;
+// endpoints when the quadratic is not convex): no launch of its own and no
+// host synchronisation. The accumulators alternate by iteration parity; the
+// first block of step 4 clears the parity that is no longer read.
 // The per-pixel kernels run one block per tile of one image, so a context
 // that holds a batch of images (concatenated lattices, see batch.hip) solves
 // every image's QP, each with its own step size, in the same launches.
@@ -50,6 +53,75 @@ constexpr int kP2 = 2;   // partial sums written by k_fw_slice
 // fw_scal holds one double per image: the step size of its last iteration
 // doubles per iteration in a forward checkpoint: alpha, a2, b1, interior
 constexpr int kStats = 4;
+constexpr int kPT = kP1 + kP2;   // sums per image and iteration
+constexpr int kSets = 8;         // accumulator sets, one per XCD
+
+// acc[parity][set][image][kPT], parity = iteration & 1
+__device__ __forceinline__ size_t acc_off(int par, int set, int nimg, int img) {
+    return (((size_t)par * kSets + set) * nimg + img) * kPT;
+}
+
+// sum i of image img of the iteration with parity par, sets in a fixed order
+__device__ __forceinline__ double acc_total(const double *acc, int par, int nimg,
+                                            int img, int i) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kSets; ++k) s += acc[acc_off(par, k, nimg, img) + i];
+    return s;
+}
+
+// exact line search from the sums (App. B): f(y + alpha D) = f(y) + alpha b1
+// + alpha^2 a2 over [0, 1]
+__device__ __forceinline__ double fw_line_search(const double *tot, double &a2,
+                                                 double &b1) {
+    const double Ayy = tot[0], Csy = tot[1], cy = tot[2], cs = tot[3];
+    const double Bys = tot[kP1 + 0], Dss = tot[kP1 + 1];
+    b1 = cs - cy + Bys + Csy - 2.0 * Ayy;
+    a2 = Dss - Bys - Csy + Ayy;
+    if (a2 > 0.0) return fmin(fmax(-b1 / (2.0 * a2), 0.0), 1.0);
+    return (a2 + b1 < 0.0) ? 1.0 : 0.0;
+}
+
+// trace entry (f(y_t), gap, alpha, labels changed) and checkpoint entry of
+// iteration it of image img
+__device__ __forceinline__ void fw_record(const double *tot, double alpha, double a2,
+                                          double b1, double *trace, double *stats,
+                                          int it, int nimg, int img) {
+    double *tr = trace + ((size_t)it * nimg + img) * 4;
+    tr[0] = tot[2] + tot[0];   // <c, y> + <y, P_y>
+    tr[1] = tot[4] - tot[5];   // <g, y - s>
+    tr[2] = alpha;
+    tr[3] = tot[6];
+    if (stats) {   // checkpoint for the reverse sweep
+        double *st = stats + ((size_t)it * nimg + img) * kStats;
+        st[0] = alpha;
+        st[1] = a2;
+        st[2] = b1;
+        st[3] = (a2 > 0.0 && -b1 / (2.0 * a2) > 0.0 && -b1 / (2.0 * a2) < 1.0) ? 1.0 : 0.0;
+    }
+}
+
+// Step size of iteration it of image img (< 0: none) for every thread of the
+// block; all threads call it. `mine` is this thread's sum when below kPT
+// (loaded earlier, so that its latency overlaps other loads); the sums meet in
+// LDS `stot`. If `record`, thread 0 writes the trace and checkpoint entries.
+__device__ __forceinline__ double fw_block_step(double mine, int it, int nimg, int img,
+                                                bool record, double *trace,
+                                                double *stats, double *stot) {
+    if ((int)threadIdx.x < kPT) stot[threadIdx.x] = mine;
+    __syncthreads();
+    if (img < 0) return 0.0;
+    double a2, b1;
+    const double alpha = fw_line_search(stot, a2, b1);
+    if (record && threadIdx.x == 0) fw_record(stot, alpha, a2, b1, trace, stats, it, nimg, img);
+    return alpha;
+}
+
+__device__ __forceinline__ double fw_load_sum(const double *acc, int it, int nimg,
+                                              int img) {
+    return (img >= 0 && (int)threadIdx.x < kPT)
+               ? acc_total(acc, it & 1, nimg, img, threadIdx.x) : 0.0;
+}
 
 template <typename T>
 __global__ void k_fill(T *p, size_t n, T v) {
@@ -92,8 +164,9 @@ struct FWArgs {
     const T *Ps, *c;
     int32_t *s;
     const int32_t *sprev;
-    double *scal, *part;
-    int first;
+    double *acc;              // accumulated sums, see acc_off
+    double *trace, *stats;    // entries of the previous iteration (stats may be null)
+    int it, first;
     const int *seg;   // image segments, one block per tile of an image
     int nimg;
     T *ysave, *Psave;   // checkpoint slots of y_t and P_t, or null
@@ -108,9 +181,7 @@ struct FWSliceArgs {
     T *Ps;
     const T *mu, *mabs, *r, *pre;
     T wsum;
-    double *scal, *part1, *part2;
-    int G1;
-    double *trace;   // 4 doubles per iteration
+    double *acc;   // accumulated sums, see acc_off
     int it;
     const int *seg;
     int nimg;
@@ -135,7 +206,9 @@ k_fw_lmo_rows(FWArgs<T> A) {
     const int tile = xcd_block(blockIdx.x, gridDim.x);
     int lo, hi;
     const int img = tile_range(A.seg, A.nimg, TP, tile, lo, hi);
-    const T al = (A.first || img < 0) ? T(0) : T(A.scal[img]);
+    __shared__ double stot[kPT];
+    // the previous step's sums, loaded now so that they arrive with the tiles
+    const double mine = A.first ? 0.0 : fw_load_sum(A.acc, A.it - 1, A.nimg, img);
     double acc[kP1];
 #pragma unroll
     for (int i = 0; i < kP1; ++i) acc[i] = 0.0;
@@ -151,6 +224,9 @@ k_fw_lmo_rows(FWArgs<T> A) {
         tile_load<T, LMAX, TP>(A.Py, p0, np, L, lds, py);
         const int sp = act ? A.sprev[a] : -1;
         if (!A.first) {
+            const T al = T(fw_block_step(mine, A.it - 1, A.nimg, img,
+                                         img >= 0 && lo == A.seg[2 * img], A.trace,
+                                         A.stats, stot));
             T ps[LMAX];
 #pragma unroll
             for (int j = 0; j < LMAX; ++j) ps[j] = T(0);
@@ -200,67 +276,9 @@ k_fw_lmo_rows(FWArgs<T> A) {
         }
     }
     block_sum<kP1, TP>(acc, red);
-    if (threadIdx.x < kP1) A.part[(size_t)tile * kP1 + threadIdx.x] = acc[threadIdx.x];
-}
-
-// One block: fixed-order reduction of every block's partial sums, the exact
-// line search (App. B) and the trace entry. A launch of its own, so that the
-// partial sums of all blocks are visible without device-wide fences.
-// One block per image: its tiles are [t1a, t1b) of the k_fw_lmo tiling (TP1
-// pixels) and [t2a, t2b) of the k_fw_slice tiling (TP2 pixels).
-template <int NT>
-__global__ void __launch_bounds__(NT)
-k_fw_alpha(const double *__restrict__ part1, const double *__restrict__ part2,
-           const int *__restrict__ seg, int nimg, int TP1, int TP2,
-           double *__restrict__ scal, double *__restrict__ trace, int it,
-           double *__restrict__ stats) {
-    __shared__ double red[(kP1 + kP2) * NT];
-    const int t = threadIdx.x;
-    const int img = blockIdx.x;
-    int t1a = 0, t2a = 0;
-    for (int k = 0; k < img; ++k) {
-        const int n = seg[2 * k + 1] - seg[2 * k];
-        t1a += (n + TP1 - 1) / TP1;
-        t2a += (n + TP2 - 1) / TP2;
-    }
-    const int n = seg[2 * img + 1] - seg[2 * img];
-    const int t1b = t1a + (n + TP1 - 1) / TP1, t2b = t2a + (n + TP2 - 1) / TP2;
-    double tot[kP1 + kP2];
-#pragma unroll
-    for (int i = 0; i < kP1 + kP2; ++i) tot[i] = 0.0;
-    for (int b = t1a + t; b < t1b; b += NT)
-#pragma unroll
-        for (int i = 0; i < kP1; ++i) tot[i] += part1[(size_t)b * kP1 + i];
-    for (int b = t2a + t; b < t2b; b += NT)
-#pragma unroll
-        for (int i = 0; i < kP2; ++i) tot[kP1 + i] += part2[(size_t)b * kP2 + i];
-    block_sum<kP1 + kP2, NT>(tot, red);
-    if (t == 0) {
-        const double Ayy = tot[0], Csy = tot[1], cy = tot[2], cs = tot[3];
-        const double gy = tot[4], gs = tot[5], changed = tot[6];
-        const double Bys = tot[kP1 + 0], Dss = tot[kP1 + 1];
-        const double b1 = cs - cy + Bys + Csy - 2.0 * Ayy;
-        const double a2 = Dss - Bys - Csy + Ayy;
-        double alpha;
-        if (a2 > 0.0)
-            alpha = fmin(fmax(-b1 / (2.0 * a2), 0.0), 1.0);
-        else
-            alpha = (a2 + b1 < 0.0) ? 1.0 : 0.0;
-        scal[img] = alpha;
-        double *tr = trace + ((size_t)it * nimg + img) * 4;
-        tr[0] = cy + Ayy;        // f(y_t)
-        tr[1] = gy - gs;         // <g, y_t - s_t>
-        tr[2] = alpha;
-        tr[3] = changed;
-        if (stats) {   // checkpoint for the reverse sweep
-            double *st = stats + ((size_t)it * nimg + img) * kStats;
-            st[0] = alpha;
-            st[1] = a2;
-            st[2] = b1;
-            st[3] = (a2 > 0.0 && -b1 / (2.0 * a2) > 0.0 && -b1 / (2.0 * a2) < 1.0)
-                        ? 1.0 : 0.0;
-        }
-    }
+    if (img >= 0 && threadIdx.x < kP1)
+        unsafeAtomicAdd(&A.acc[acc_off(A.it & 1, blockIdx.x & (kSets - 1), A.nimg, img) +
+                               threadIdx.x], acc[threadIdx.x]);
 }
 
 // Step 4, one thread per pixel (see the file comment). POTTS: mu = 1 - I,
@@ -283,7 +301,7 @@ k_fw_slice_rows(FWSliceArgs<T> A, LatSet<T> ls) {
     double acc[kP2] = {0.0, 0.0};
     const int tile = xcd_block(blockIdx.x, gridDim.x);
     int lo, hi;
-    tile_range(A.seg, A.nimg, TP, tile, lo, hi);
+    const int img = tile_range(A.seg, A.nimg, TP, tile, lo, hi);
     {
         const long long p0 = lo;
         const int np = hi - lo;
@@ -364,7 +382,12 @@ k_fw_slice_rows(FWSliceArgs<T> A, LatSet<T> ls) {
     }
     double v[kP2] = {acc[0], acc[1]};
     block_sum<kP2, TP>(v, red);
-    if (threadIdx.x < kP2) A.part2[(size_t)tile * kP2 + threadIdx.x] = v[threadIdx.x];
+    if (img >= 0 && threadIdx.x < kP2)
+        unsafeAtomicAdd(&A.acc[acc_off(A.it & 1, blockIdx.x & (kSets - 1), A.nimg, img) +
+                               kP1 + threadIdx.x], v[threadIdx.x]);
+    if (blockIdx.x == 0)   // the other parity: read by this iteration's step 1 only
+        for (int i = threadIdx.x; i < kSets * A.nimg * kPT; i += TP)
+            A.acc[acc_off((A.it + 1) & 1, 0, A.nimg, 0) + i] = 0.0;
 }
 
 // ------------------------------------------------- flat kernels (L > 32)
@@ -430,7 +453,12 @@ k_fw_lmo_flat(FWArgs<T> A) {
     const int l = t - lp * L;
     int lo, hi;
     const int img = tile_range(A.seg, A.nimg, ppb * kFlatGroups, blockIdx.x, lo, hi);
-    const T al = (A.first || img < 0) ? T(0) : T(A.scal[img]);
+    __shared__ double stot[kPT];
+    const T al = A.first ? T(0)
+                         : T(fw_block_step(fw_load_sum(A.acc, A.it - 1, A.nimg, img),
+                                           A.it - 1, A.nimg, img,
+                                           img >= 0 && lo == A.seg[2 * img], A.trace,
+                                           A.stats, stot));
     double acc[kP1];
 #pragma unroll
     for (int i = 0; i < kP1; ++i) acc[i] = 0.0;
@@ -484,7 +512,9 @@ k_fw_lmo_flat(FWArgs<T> A) {
         __syncthreads();
     }
     block_sum<kP1, kThreads>(acc, red);
-    if (t < kP1) A.part[(size_t)blockIdx.x * kP1 + t] = acc[t];
+    if (img >= 0 && t < kP1)
+        unsafeAtomicAdd(&A.acc[acc_off(A.it & 1, blockIdx.x & (kSets - 1), A.nimg, img) + t],
+                        acc[t]);
 }
 
 template <typename T>
@@ -499,7 +529,7 @@ k_fw_slice_flat(FWSliceArgs<T> A, LatSet<T> ls) {
     const int l = t - lp * L;
     double acc[kP2] = {0.0, 0.0};
     int lo, hi;
-    tile_range(A.seg, A.nimg, ppb * kFlatGroups, blockIdx.x, lo, hi);
+    const int img = tile_range(A.seg, A.nimg, ppb * kFlatGroups, blockIdx.x, lo, hi);
     for (int g0 = lo; g0 < hi; g0 += ppb) {
         const long long a = (long long)g0 + lp;
         const bool act = lp < ppb && a < hi;
@@ -539,21 +569,30 @@ k_fw_slice_flat(FWSliceArgs<T> A, LatSet<T> ls) {
     }
     double v[kP2] = {acc[0], acc[1]};
     block_sum<kP2, kThreads>(v, red);
-    if (t < kP2) A.part2[(size_t)blockIdx.x * kP2 + t] = v[t];
+    if (img >= 0 && t < kP2)
+        unsafeAtomicAdd(&A.acc[acc_off(A.it & 1, blockIdx.x & (kSets - 1), A.nimg, img) +
+                               kP1 + t], v[t]);
+    if (blockIdx.x == 0)
+        for (int i = t; i < kSets * A.nimg * kPT; i += kThreads)
+            A.acc[acc_off((A.it + 1) & 1, 0, A.nimg, 0) + i] = 0.0;
 }
 
 // ------------------------------------------------------------ the rest
 
-// y <- y + alpha (s - y), P_y <- (1 - alpha) P_y + alpha P_s with the step
-// of each image (blockIdx.y)
+// y <- y + alpha (s - y), P_y <- (1 - alpha) P_y + alpha P_s with the last
+// step of each image (blockIdx.y), solved here from the accumulated sums of
+// iteration `it`; block (0, img) records its trace and checkpoint entries
 template <typename T>
 __global__ void k_fw_final(int L, const int *__restrict__ seg, T *__restrict__ y,
                            T *__restrict__ Py, const T *__restrict__ Ps,
-                           const int32_t *__restrict__ s,
-                           const double *__restrict__ scal) {
+                           const int32_t *__restrict__ s, const double *__restrict__ acc,
+                           int it, int nimg, double *__restrict__ trace,
+                           double *__restrict__ stats) {
+    __shared__ double stot[kPT];
     const int img = blockIdx.y;
     const size_t lo = (size_t)seg[2 * img] * L, hi = (size_t)seg[2 * img + 1] * L;
-    const T al = T(scal[img]);
+    const T al = T(fw_block_step(fw_load_sum(acc, it, nimg, img), it, nimg, img,
+                                 blockIdx.x == 0, trace, stats, stot));
     for (size_t e = lo + (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < hi;
          e += (size_t)gridDim.x * blockDim.x) {
         const int a = int(e / L);
@@ -698,7 +737,7 @@ template <typename T>
 struct Work {
     T *c, *Py, *Ps, *mabs;
     int32_t *s, *sprev;
-    double *part1, *part2, *scal, *trace;
+    double *acc, *trace;
     int G1, G2;   // blocks (tiles) of k_fw_lmo and k_fw_slice
 };
 
@@ -717,7 +756,7 @@ Work<T> fw_workspace(dcrf_ctx *ctx, int L, int iters) {
     ctx->fw_s.ensure((size_t)ctx->N * 4, st);
     ctx->fw_sprev.ensure((size_t)ctx->N * 4, st);
     ctx->fw_part.ensure(np * 8, st);
-    ctx->fw_scal.ensure((size_t)ctx->nimg * 8, st);
+    ctx->fw_scal.ensure((size_t)2 * kSets * ctx->nimg * kPT * 8, st);   // accumulators
     ctx->fw_trace.ensure((size_t)std::max(iters, 1) * ctx->nimg * 4 * 8, st);
     ctx->fw_mu.ensure((size_t)L * sizeof(T), st);
     Work<T> w;
@@ -729,9 +768,7 @@ Work<T> fw_workspace(dcrf_ctx *ctx, int L, int iters) {
     w.mabs = ctx->fw_mu.as<T>();
     w.s = ctx->fw_s.as<int32_t>();
     w.sprev = ctx->fw_sprev.as<int32_t>();
-    w.part1 = ctx->fw_part.as<double>();
-    w.part2 = w.part1 + (size_t)G1 * kP1;
-    w.scal = ctx->fw_scal.as<double>();
+    w.acc = ctx->fw_scal.as<double>();
     w.trace = ctx->fw_trace.as<double>();
     return w;
 }
@@ -811,7 +848,7 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
     }
     hipLaunchKernelGGL(k_fill_i32, dim3(ceil_div(N, 256)), dim3(256), 0, st,
                        w.sprev, (size_t)N, -1);
-    DCRF_TRY_HIP(hipMemsetAsync(w.scal, 0, (size_t)ctx->nimg * 8, st));
+    DCRF_TRY_HIP(hipMemsetAsync(w.acc, 0, (size_t)2 * kSets * ctx->nimg * kPT * 8, st));
     DCRF_CHECK_LAUNCH();
 
     const bool exact = ctx->mode == DCRF_FILTER_EXACT;
@@ -821,9 +858,7 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
         ctx->tmpA.ensure(NL * sizeof(T), st);
         ctx->tmpB.ensure(NL * sizeof(T), st);
     }
-    // one block per tile of an image (k_fw_lmo: G1 tiles of TP1 pixels,
-    // k_fw_slice: G tiles of TP pixels)
-    const int TP1 = lmo_tile<T>(L), TP = slice_tile<T>(L);
+    // one block per tile of an image (k_fw_lmo: G1 tiles, k_fw_slice: G tiles)
     const int G1 = w.G1, G = w.G2;
     const int nimg = ctx->nimg;
     const int *seg = ctx->seg.as<int>();
@@ -835,8 +870,9 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
         T *ysv = save && rows ? static_cast<T *>(save->y) + (size_t)it * NL : nullptr;
         T *psv = save && rows ? static_cast<T *>(save->P) + (size_t)it * NL : nullptr;
         int32_t *ssv = save && rows ? save->s + (size_t)it * N : nullptr;
-        FWArgs<T> a{N, L, y, w.Py, w.Ps, w.c, w.s, w.sprev, w.scal, w.part1,
-                    it == 0 ? 1 : 0, seg, nimg, ysv, psv, ssv};
+        FWArgs<T> a{N, L, y, w.Py, w.Ps, w.c, w.s, w.sprev, w.acc, w.trace,
+                    save ? save->stats : nullptr, it, it == 0 ? 1 : 0, seg, nimg,
+                    ysv, psv, ssv};
         {
             ProfScope ps(ctx, PROF_FW_LMO);
             if (rows) {
@@ -868,8 +904,7 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
             if (save && vblock) save_vertices(it + 1);
         }
         FWSliceArgs<T> b{N, L, y, w.s, w.Ps, mu, w.mabs, ctx->r.as<T>(), pre,
-                         T(ctx->wsum), w.scal, w.part1, w.part2, G1, w.trace, it,
-                         seg, nimg};
+                         T(ctx->wsum), w.acc, it, seg, nimg};
         {
             ProfScope ps(ctx, PROF_FW_SLICE);
             if (rows) {
@@ -886,12 +921,6 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
                                    0, st, b, ls);
             }
         }
-        {
-            ProfScope ps(ctx, PROF_FW_ALPHA);
-            DCRF_PLAUNCH(ps, (k_fw_alpha<512>), dim3(nimg), dim3(512), 0,
-                               st, w.part1, w.part2, seg, nimg, TP1, TP, w.scal,
-                               w.trace, it, save ? save->stats : nullptr);
-        }
         DCRF_CHECK_LAUNCH();
         std::swap(w.s, w.sprev);
     }
@@ -902,7 +931,8 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
             maxn = std::max(maxn, ctx->seg_h[2 * j + 1] - ctx->seg_h[2 * j]);
         const int gx = std::min(4096, ceil_div((long long)maxn * L, 256));
         hipLaunchKernelGGL((k_fw_final<T>), dim3(gx, nimg), dim3(256), 0, st, L,
-                           seg, y, w.Py, w.Ps, w.sprev, w.scal);
+                           seg, y, w.Py, w.Ps, w.sprev, w.acc, iters - 1, nimg,
+                           w.trace, save ? save->stats : nullptr);
         DCRF_CHECK_LAUNCH();
     }
     if (trace && iters > 0) {   // record it * nimg + image
