@@ -92,8 +92,7 @@ def class_bytes(name, N, L, e, lattices, group=2):
       per lattice the per-pixel vertex ids and weights and the vertex rows
       read;
     * k_blur_group: per launch, over the lattices it covers, each vertex row
-      in and out (2 M L e) and the path table (M 3^G 4);
-    * k_fw_alpha: the per-tile partial sums it reduces."""
+      in and out (2 M L e) and the path table (M 3^G 4)."""
     if name == "k_fw_lmo_rows":
         return 6 * N * L * e + 2 * N * 4
     if name in ("k_splat_labels_lds", "k_splat_labels_chunks"):
@@ -107,8 +106,6 @@ def class_bytes(name, N, L, e, lattices, group=2):
         tot = sum(g * (2 * M * L * e + M * 3 ** group * 4)
                   for g, (d, M) in zip(groups, lattices))
         return tot / max(groups)
-    if name == "k_fw_alpha":
-        return (-(-N // 256) * 7 + -(-N // 128) * 2) * 8
     raise KeyError(name)
 
 
@@ -562,7 +559,7 @@ def main():
 
     # ---- roofline of the dominant kernel of the step ----------------------
     step_classes = ("k_fw_lmo_rows", "k_splat_labels_lds", "k_splat_labels_chunks",
-                    "k_blur_group", "k_blur_pass", "k_fw_slice_rows", "k_fw_alpha")
+                    "k_blur_group", "k_blur_pass", "k_fw_slice_rows")
     dom = max((k for k in per_iter if k in step_classes),
               key=lambda k: per_iter[k][0] * per_iter[k][1])
     dom_ms = per_iter[dom][0]

@@ -25,7 +25,7 @@ const char *prof_name(const dcrf_ctx *ctx, int c) {
     case PROF_SLICE_QP: return tiles ? "k_tile_slice_qp" : "k_slice_rows_qp";
     case PROF_SPLAT_LABELS:
         return tiles ? "k_tile_labels" : staged ? "k_splat_labels_lds" : "k_splat_labels_chunks";
-    case PROF_FW_ALPHA: return "k_fw_alpha";
+    case PROF_FW_FINAL: return "k_fw_final";
     default: return "?";
     }
 }

@@ -147,7 +147,7 @@ enum ProfClass {
     PROF_SLICE = 4,       // raw slice K'Y (k_slice_rows)
     PROF_SLICE_QP = 5,    // slice with mu and the diagonal
     PROF_SPLAT_LABELS = 6,  // one-hot splat (k_splat_labels_chunks)
-    PROF_FW_ALPHA = 7,    // reduction of the partial sums, step size
+    PROF_FW_FINAL = 7,    // k_fw_final: the last step size and update of a solve
     PROF_NCLASS = 8
 };
 

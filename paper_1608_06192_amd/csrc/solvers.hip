@@ -930,9 +930,10 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
         for (int j = 0; j < nimg; ++j)
             maxn = std::max(maxn, ctx->seg_h[2 * j + 1] - ctx->seg_h[2 * j]);
         const int gx = std::min(4096, ceil_div((long long)maxn * L, 256));
-        hipLaunchKernelGGL((k_fw_final<T>), dim3(gx, nimg), dim3(256), 0, st, L,
-                           seg, y, w.Py, w.Ps, w.sprev, w.acc, iters - 1, nimg,
-                           w.trace, save ? save->stats : nullptr);
+        ProfScope ps(ctx, PROF_FW_FINAL);
+        DCRF_PLAUNCH(ps, (k_fw_final<T>), dim3(gx, nimg), dim3(256), 0, st, L, seg, y,
+                     w.Py, w.Ps, w.sprev, w.acc, iters - 1, nimg, w.trace,
+                     save ? save->stats : nullptr);
         DCRF_CHECK_LAUNCH();
     }
     if (trace && iters > 0) {   // record it * nimg + image
