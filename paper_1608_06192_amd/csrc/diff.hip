@@ -29,10 +29,12 @@
 // from the saved vertex values, forms S_t = Q s_t, and reduces per tile the
 // pieces of abar and of the weight gradient; since Sbar is linear in
 // (alpha, Bbar, Dbar), <Sbar mu, (K~_m - I) s> and the rho terms split into
-// three scalar products each. k_step_adjoint (one block per image) turns
-// them into the step's adjoints and accumulates the weight gradient, on the
-// device; k_sweep_b updates ybar and Pbar. No host synchronisation happens
-// inside the sweep. cbar is not carried per iteration: with the recurrence
+// three scalar products each; the blocks add their sums to per-image
+// accumulators (one set per XCD, device atomics, alternating by iteration
+// parity). Every block of k_sweep_b adds the sets up in a fixed order, turns
+// the sums into the step's adjoints and updates ybar and Pbar; the image's
+// first tile also accumulates the weight gradient. No host synchronisation
+// and no launch of its own for the step happen inside the sweep. cbar is not carried per iteration: with the recurrence
 // y_t = (1 - alpha_{t-1}) y_{t-1} + alpha_{t-1} s_{t-1},
 //   sum_t cybar_t y_t = a_0 y_0 + sum_k b_k s_k,
 //   a_0 = sum_t cybar_t prod_{u<t} (1 - alpha_u),
@@ -54,7 +56,13 @@ namespace dcrf {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kNP = 1 + 3 * DCRF_MAXK;   // partial sums per tile of k_sweep_a
+constexpr int kNP = 1 + 3 * DCRF_MAXK;   // sums per image of k_sweep_a
+constexpr int kSets = 8;                 // accumulator sets, one per XCD
+
+// acc[parity][set][image][kNP], parity = iteration & 1
+__device__ __forceinline__ size_t sweep_acc_off(int par, int set, int nimg, int img) {
+    return (((size_t)par * kSets + set) * nimg + img) * kNP;
+}
 
 // y = softmax(-phi) row by row; rows move through LDS tiles (coalesced)
 template <typename T, int LMAX>
@@ -212,7 +220,7 @@ struct SweepA {
     const T *kappa1[DCRF_MAXK];   // K~_m 1
     T w[DCRF_MAXK], gam[DCRF_MAXK], wsum;
     T *S;
-    double *part;   // per tile: abar, then per kernel U, V, W
+    double *acc;    // per image: abar, then per kernel U, V, W (see sweep_acc_off)
 };
 
 // Per pixel of one tile: S = Q s from the saved vertex values of the
@@ -348,66 +356,68 @@ k_sweep_a(SweepA<T> A, LatSet<T> ls) {
     __syncthreads();
     tile_copy_out<T, TP, LMAX>(A.S + (size_t)lo * L, np * L, L, tq);
     const double tot = block_sum_waves<kNP, TP>(acc, red);
-    if ((int)threadIdx.x < kNP) A.part[(size_t)tile * kNP + threadIdx.x] = tot;
+    if (img >= 0 && (int)threadIdx.x < kNP)
+        unsafeAtomicAdd(&A.acc[sweep_acc_off(A.t & 1, blockIdx.x & (kSets - 1), A.nimg, img) +
+                               threadIdx.x], tot);
 }
 
 struct StepBar {
     double al, Abar, Bbar, Cbar, Dbar, cybar, csbar;
 };
 
-// One block per image: reduce the image's tiles of k_sweep_a, form the step
-// adjoints from the checkpointed step quadratic, accumulate the weight
-// gradient and record (cybar, csbar) of the iteration.
-template <int NT>
-__global__ void __launch_bounds__(NT)
-k_step_adjoint(const double *__restrict__ part, const int *__restrict__ seg, int nimg,
-               int TP, int nk, const double *__restrict__ stats, int t,
-               StepBar *__restrict__ sb, double *__restrict__ gw,
-               double *__restrict__ coef) {
-    __shared__ double red[kNP * NT];
-    const int img = blockIdx.x;
-    int ta = 0;
-    for (int k = 0; k < img; ++k) ta += (seg[2 * k + 1] - seg[2 * k] + TP - 1) / TP;
-    const int tb = ta + (seg[2 * img + 1] - seg[2 * img] + TP - 1) / TP;
-    double tot[kNP];
-#pragma unroll
-    for (int i = 0; i < kNP; ++i) tot[i] = 0.0;
-    for (int b = ta + (int)threadIdx.x; b < tb; b += NT)
-#pragma unroll
-        for (int i = 0; i < kNP; ++i) tot[i] += part[(size_t)b * kNP + i];
-    block_sum<kNP, NT>(tot, red);
-    if (threadIdx.x != 0) return;
-    const double *st = stats + ((size_t)t * nimg + img) * kFWStats;
+// The step's adjoints from the image's sums tot (k_sweep_a) and the
+// checkpointed step quadratic: abar, then for an interior step
+// b1bar = -abar / (2 a2), a2bar = -abar alpha / a2 (a clipped step passes no
+// gradient), and the adjoints of A, B, C, D, cy, cs through b1 and a2.
+__device__ __forceinline__ StepBar step_bar(const double *tot, const double *st) {
     const double abar = tot[0], al = st[0], a2 = st[1];
     double b1bar = 0.0, a2bar = 0.0;
     if (st[3] != 0.0) {
         b1bar = -abar / (2.0 * a2);
         a2bar = -abar * al / a2;
     }
-    const StepBar b{al, -2.0 * b1bar + a2bar, b1bar - a2bar, b1bar - a2bar, a2bar,
-                    -b1bar, b1bar};
-    sb[img] = b;
-    for (int m = 0; m < nk; ++m) {
-        const double *x = tot + 1 + 3 * m;
-        gw[(size_t)img * nk + m] += x[0] + b.Bbar * x[1] + b.Dbar * x[2];
-    }
-    coef[((size_t)t * nimg + img) * 2 + 0] = b.cybar;
-    coef[((size_t)t * nimg + img) * 2 + 1] = b.csbar;
+    return StepBar{al, -2.0 * b1bar + a2bar, b1bar - a2bar, b1bar - a2bar, a2bar,
+                   -b1bar, b1bar};
 }
 
+// Per block: the step adjoints of iteration t of its image from the
+// accumulated sums (sets added in a fixed order); the image's first tile adds
+// the step's weight gradient to gw and records (cybar, csbar); block 0 clears
+// the other parity, which k_sweep_a of iteration t - 1 fills next. Then
 // ybar <- (1 - alpha) ybar + Abar P + Bbar S + cybar c,
-// Pbar <- (1 - alpha) Pbar + Abar y + Cbar s, with c = phi - |mu| r
+// Pbar <- (1 - alpha) Pbar + Abar y + Cbar s, with c = phi - |mu| r.
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_sweep_b(const int *__restrict__ seg, int nimg, int L, int TPB,
-          const StepBar *__restrict__ sb, const int32_t *__restrict__ s,
+          double *__restrict__ acc, const double *__restrict__ stats, int t, int nk,
+          double *__restrict__ gw, double *__restrict__ coef,
+          const int32_t *__restrict__ s,
           const T *__restrict__ y, const T *__restrict__ P, const T *__restrict__ S,
           const T *__restrict__ phi, const T *__restrict__ r, const T *__restrict__ mabs,
           T *__restrict__ ybar, T *__restrict__ Pbar) {
+    __shared__ double stot[kNP];
     int lo, hi;
     const int img = tile_range(seg, nimg, TPB, xcd_block(blockIdx.x, gridDim.x), lo, hi);
+    if (img >= 0 && (int)threadIdx.x < kNP) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < kSets; ++k) v += acc[sweep_acc_off(t & 1, k, nimg, img) + threadIdx.x];
+        stot[threadIdx.x] = v;
+    }
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < kSets * nimg * kNP; i += kThreads)
+            acc[sweep_acc_off((t + 1) & 1, 0, nimg, 0) + i] = 0.0;
+    __syncthreads();
     if (img < 0) return;
-    const StepBar b = sb[img];
+    const StepBar b = step_bar(stot, stats + ((size_t)t * nimg + img) * kFWStats);
+    if (threadIdx.x == 0 && lo == seg[2 * img]) {
+        for (int m = 0; m < nk; ++m) {
+            const double *x = stot + 1 + 3 * m;
+            gw[(size_t)img * nk + m] += x[0] + b.Bbar * x[1] + b.Dbar * x[2];
+        }
+        coef[((size_t)t * nimg + img) * 2 + 0] = b.cybar;
+        coef[((size_t)t * nimg + img) * 2 + 1] = b.csbar;
+    }
     const T om = T(1.0 - b.al), Ab = T(b.Abar), Bb = T(b.Bbar), Cb = T(b.Cbar),
             cy = T(b.cybar);
     for (size_t e = (size_t)lo * L + threadIdx.x; e < (size_t)hi * L; e += kThreads) {
@@ -517,7 +527,7 @@ k_sweep_final(SweepF<T> A, LatSet<T> ls) {
 }
 
 struct DiffWork {
-    DevBuf ybar, Pbar, S, Z, KtZ, part, mabs, ones, sb, gw, coef, cb;
+    DevBuf ybar, Pbar, S, Z, KtZ, part, mabs, ones, acc, gw, coef, cb;
     DevBuf K1[DCRF_MAXK];
 };
 
@@ -593,7 +603,7 @@ void backward_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, int iters,
     W.part.ensure((size_t)GA * kNP * 8, st);
     W.mabs.ensure((size_t)L * sizeof(T), st);
     W.ones.ensure((size_t)N * sizeof(T), st);
-    W.sb.ensure((size_t)nimg * sizeof(StepBar), st);
+    W.acc.ensure((size_t)2 * kSets * nimg * kNP * 8, st);
     W.gw.ensure((size_t)nimg * nk * 8, st);
     W.coef.ensure((size_t)iters * nimg * 2 * 8, st);
     W.cb.ensure((size_t)nimg * (iters + 1) * 8, st);
@@ -634,8 +644,9 @@ void backward_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, int iters,
         A.gam[m] = T(ctx->lat[m].gamma);
     }
     A.S = W.S.as<T>();
-    A.part = W.part.as<double>();
+    A.acc = W.acc.as<double>();
     A.stats = stats;
+    DCRF_TRY_HIP(hipMemsetAsync(A.acc, 0, (size_t)2 * kSets * nimg * kNP * 8, st));
     for (int t = iters - 1; t >= 0; --t) {
         A.t = t;
         A.s = ss + (size_t)t * N;
@@ -648,11 +659,9 @@ void backward_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, int iters,
         else
             DCRF_DISPATCH_ROWS(L, hipLaunchKernelGGL((k_sweep_a<T, LMAX, false>), dim3(GA),
                                                      dim3(TP), 0, st, A, ls));
-        hipLaunchKernelGGL((k_step_adjoint<256>), dim3(nimg), dim3(256), 0, st,
-                           W.part.as<double>(), seg, nimg, TP, nk, stats, t,
-                           W.sb.as<StepBar>(), W.gw.as<double>(), W.coef.as<double>());
         hipLaunchKernelGGL((k_sweep_b<T>), dim3(GB), dim3(kThreads), 0, st, seg, nimg, L,
-                           TPB, W.sb.as<StepBar>(), A.s, A.y, A.P, W.S.as<T>(), phi,
+                           TPB, A.acc, stats, t, nk, W.gw.as<double>(),
+                           W.coef.as<double>(), A.s, A.y, A.P, W.S.as<T>(), phi,
                            ctx->r.as<T>(), W.mabs.as<T>(), ybar, Pbar);
         DCRF_CHECK_LAUNCH();
     }
@@ -784,7 +793,7 @@ void diff_release(dcrf_ctx *ctx) {
     if (!ctx->diff) return;
     DiffWork *W = static_cast<DiffWork *>(ctx->diff);
     for (DevBuf *b : {&W->ybar, &W->Pbar, &W->S, &W->Z, &W->KtZ, &W->part, &W->mabs,
-                      &W->ones, &W->sb, &W->gw, &W->coef, &W->cb})
+                      &W->ones, &W->acc, &W->gw, &W->coef, &W->cb})
         b->release();
     for (int m = 0; m < DCRF_MAXK; ++m) W->K1[m].release();
     delete W;
