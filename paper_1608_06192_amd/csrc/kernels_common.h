@@ -521,6 +521,65 @@ __device__ __forceinline__ void slice_pixel52_staged(const LatSet<T> &ls, int t,
     for (int k = 0; k < 3; ++k) axpy_row<LMAX>(acc, wb[k], B.Vf + (size_t)ib[k] * B.ld, C);
 }
 
+// The slice of a whole tile from the corners staged by stage_corners52, into
+// the LDS tile qt (row stride lds_stride(C)): one task per (pixel, 16-byte
+// chunk of its row), consecutive lanes taking consecutive chunks of one
+// pixel, so that a wave's loads of one corner cover a few rows instead of one
+// row per lane. All threads of the block call it; the caller synchronises
+// before reading qt.
+template <typename T, int LMAX, int TP>
+__device__ __forceinline__ void slice_tile52_coop(const LatSet<T> &ls, int np, int C,
+                                                  const int32_t *sid, const T *sw,
+                                                  T *qt) {
+    using V = typename Vec16<T>::type;
+    constexpr int w = Vec16<T>::n;
+    constexpr int KQ = (LMAX + w - 1) / w;   // tasks per thread
+    const LatView<T> &A = ls.l[0];
+    const LatView<T> &B = ls.l[1];
+    const int nq = (C + w - 1) / w;
+    const int Ls = lds_stride(C);
+    const int ntask = np * nq;
+#pragma unroll
+    for (int i = 0; i < KQ; ++i) {
+        const int task = (int)threadIdx.x + i * TP;
+        if (task >= ntask) break;
+        const int p = task / nq, qc = task - p * nq;
+        V acc;
+        T *ac = reinterpret_cast<T *>(&acc);
+#pragma unroll
+        for (int e = 0; e < w; ++e) ac[e] = T(0);
+        V va[6], vb[3];
+        T fa[6], fb[3];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int id = sid[p * 6 + k];
+            fa[k] = id >= 0 ? A.wg * sw[p * 6 + k] : T(0);
+            va[k] = *reinterpret_cast<const V *>(A.Vf + (size_t)(id >= 0 ? id : 0) * A.ld + qc * w);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int id = sid[6 * TP + p * 3 + k];
+            fb[k] = id >= 0 ? B.wg * sw[6 * TP + p * 3 + k] : T(0);
+            vb[k] = *reinterpret_cast<const V *>(B.Vf + (size_t)(id >= 0 ? id : 0) * B.ld + qc * w);
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const T *x = reinterpret_cast<const T *>(&va[k]);
+#pragma unroll
+            for (int e = 0; e < w; ++e) ac[e] += fa[k] * x[e];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const T *x = reinterpret_cast<const T *>(&vb[k]);
+#pragma unroll
+            for (int e = 0; e < w; ++e) ac[e] += fb[k] * x[e];
+        }
+#pragma unroll
+        for (int e = 0; e < w; ++e)
+            if (qc * w + e < C) qt[p * Ls + qc * w + e] = ac[e];
+    }
+}
+
 // sum over the lattices of w_m gamma_m sum_k b_k V_m[v_k]  (the slice of
 // pixel a into acc, which the caller has zeroed)
 template <typename T, int LMAX>

@@ -313,17 +313,21 @@ k_fw_slice_rows(FWSliceArgs<T> A, LatSet<T> ls) {
         const int sa = act ? A.s[a] : 0;
         // with Potts and no precomputed K'S the tile of y goes to LDS first,
         // so that its loads overlap the gathers of the slice
-        const bool early = POTTS && !A.pre;
         const bool staged = !A.pre && ls.shape52 && np > 0;   // uniform over the block
+        const bool early = POTTS && !A.pre && !staged;
         if (staged) stage_corners52<T, TP>(ls, p0, np, sid, swc);
         if (early) tile_copy_in<T, TP, LMAX>(A.y + p0 * L, np * L, L, lds);
         if (A.pre) {
             tile_load<T, LMAX, TP>(A.pre, p0, np, L, lds, q);
         } else {
-            if (staged) __syncthreads();
+            if (staged) {
+                __syncthreads();
+                slice_tile52_coop<T, LMAX, TP>(ls, np, L, sid, swc, lds);
+                __syncthreads();
+            }
             if (act) {
                 if (staged)
-                    slice_pixel52_staged<T, LMAX, TP>(ls, threadIdx.x, L, sid, swc, q);
+                    tile_read_own<T, LMAX>(np, L, lds, q);
                 else
                     slice_pixel<T, LMAX>(ls, a, L, q);
 #pragma unroll
@@ -331,6 +335,7 @@ k_fw_slice_rows(FWSliceArgs<T> A, LatSet<T> ls) {
                     if (j == sa) q[j] -= A.wsum;
             }
         }
+        if (staged) __syncthreads();   // every row of the slice read: lds is reused
         T P[LMAX];
         const T dself = act ? A.mabs[sa] * A.r[a] : T(0);
         if (POTTS) {
