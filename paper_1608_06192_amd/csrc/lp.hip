@@ -664,6 +664,10 @@ struct LPWork {
         int cap_sub = 0;
     } lat[DCRF_MAXK];
     DevBuf g, part, acc;
+    // the second and later lattices of a level run on a stream of their own
+    // (default priority), joined to the context's stream by two events
+    hipStream_t side = nullptr;
+    hipEvent_t ev_start = nullptr, ev_done = nullptr;
 };
 
 LPWork &lp_work(dcrf_ctx *ctx) {
@@ -703,10 +707,9 @@ void sort_column(dcrf_ctx *ctx, LPWork &W, const T *y, int L, int col,
 }
 
 template <typename T>
-void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l) {
+void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l, hipStream_t s) {
     Lattice &Lt = ctx->lat[m];
     auto &P = W.lat[m];
-    const hipStream_t s = ctx->stream;
     const int N = ctx->N, D1 = Lt.d + 1, M = Lt.M;
     const long long E = (long long)N * D1;
     int *flags = ctx->scratch.as<int>();
@@ -755,6 +758,11 @@ void lp_prepare(dcrf_ctx *ctx, LPWork &W, int L) {
     W.g.ensure((size_t)N * L * sizeof(T), s);
     W.part.ensure(1024 * 8, s);
     if (ctx->mode == DCRF_FILTER_EXACT) return;
+    if (!W.side) {
+        DCRF_TRY_HIP(hipStreamCreateWithFlags(&W.side, hipStreamNonBlocking));
+        DCRF_TRY_HIP(hipEventCreateWithFlags(&W.ev_start, hipEventDisableTiming));
+        DCRF_TRY_HIP(hipEventCreateWithFlags(&W.ev_done, hipEventDisableTiming));
+    }
     W.acc.ensure((size_t)N * sizeof(T), s);   // zero between labels
     for (int m = 0; m < ctx->nk; ++m) {
         auto &P = W.lat[m];
@@ -811,7 +819,17 @@ double lp_subgradient_t(dcrf_ctx *ctx, const T *phi, int L, const T *y, T *g) {
                                W.lat[m].pos_w.as<T>());
         }
         for (int l = 0; l < levels; ++l) {
-            for (int m = 0; m < ctx->nk; ++m) lp_level<T>(ctx, W, m, l);
+            // the lattices' chains are independent until the slice: the
+            // first runs on the context's stream, the others on the side
+            // stream, which starts after the previous level's slice
+            if (ctx->nk > 1) {
+                DCRF_TRY_HIP(hipEventRecord(W.ev_start, s));
+                DCRF_TRY_HIP(hipStreamWaitEvent(W.side, W.ev_start, 0));
+                for (int m = 1; m < ctx->nk; ++m) lp_level<T>(ctx, W, m, l, W.side);
+                DCRF_TRY_HIP(hipEventRecord(W.ev_done, W.side));
+            }
+            lp_level<T>(ctx, W, 0, l, s);
+            if (ctx->nk > 1) DCRF_TRY_HIP(hipStreamWaitEvent(s, W.ev_done, 0));
             LPLats<T> lats{};
             lats.nk = ctx->nk;
             for (int m = 0; m < ctx->nk; ++m) {
@@ -884,6 +902,12 @@ void lp_descent_t(dcrf_ctx *ctx, const T *phi, int L, T *y, int steps,
 void lp_release(dcrf_ctx *ctx) {
     if (!ctx->lp) return;
     LPWork *W = static_cast<LPWork *>(ctx->lp);
+    if (W->side) {
+        (void)hipStreamSynchronize(W->side);
+        (void)hipStreamDestroy(W->side);
+        (void)hipEventDestroy(W->ev_start);
+        (void)hipEventDestroy(W->ev_done);
+    }
     for (DevBuf *b : {&W->keys, &W->keys2, &W->vals, &W->vals2, &W->hist, &W->g,
                       &W->part, &W->acc})
         b->release();
