@@ -14,15 +14,17 @@
 // channel read at right points adds to Lo. "Over the node's points only"
 // means a permutohedral lattice built on those points: its vertices are the
 // (node, global vertex) pairs touched by the node's points, found with a
-// device hash keyed by node * M + v (a sub-vertex is numbered by the thread
-// that inserts it), and its blur follows the global neighbour table, keeping
-// neighbours present in the same node. Each node probes only its own region
+// device hash keyed by node * M + v (a sub-vertex takes the number of the
+// (position, vertex) entry that claims its slot), and its blur follows the
+// global neighbour table, keeping neighbours present in the same node. Each node probes only its own region
 // of the table (twice its entries), so the probes of neighbouring positions
 // stay in a few cache lines; blocks map to XCDs in contiguous ranges of
 // positions (xcd_block), so from the third level on a node's region and its
 // sub-vertex rows are used by one XCD's L2.
-// All nodes of a level are filtered in one pass; labels are processed one at
-// a time (their hash tables then stay cache-resident).
+// All nodes of a level are filtered in one pass, the first lattice on the
+// context's stream and the others on a second stream joined before the
+// slice; labels are processed one at a time (their hash tables then stay
+// cache-resident).
 //
 // With the exact filter mode the two sums are computed directly, O(N^2) per
 // label (the definition that the divide and conquer reproduces).

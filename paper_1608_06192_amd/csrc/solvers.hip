@@ -50,7 +50,7 @@ constexpr int kFlatGroups = 8;
 constexpr int kP1 = 8;   // partial sums written by k_fw_lmo
 constexpr int kP2 = 2;   // partial sums written by k_fw_slice
 
-// fw_scal holds one double per image: the step size of its last iteration
+// fw_scal holds the step-size accumulators (acc_off below)
 // doubles per iteration in a forward checkpoint: alpha, a2, b1, interior
 constexpr int kStats = 4;
 constexpr int kPT = kP1 + kP2;   // sums per image and iteration
@@ -752,7 +752,7 @@ Work<T> fw_workspace(dcrf_ctx *ctx, int L, int iters) {
     const size_t NL = (size_t)ctx->N * L;
     const int G1 = seg_tiles(ctx, lmo_tile<T>(L));
     const int G2 = seg_tiles(ctx, slice_tile<T>(L));
-    // the partial sums of k_fw_lmo and k_fw_slice; also those of k_S_value
+    // the partial sums of k_S_value (the solver's own sums go to fw_scal)
     const size_t np = std::max<size_t>((size_t)G1 * kP1 + (size_t)G2 * kP2,
                                        (size_t)seg_tiles(ctx, kThreads));
     ctx->fw_c.ensure(NL * sizeof(T), st);
