@@ -334,6 +334,33 @@ def test_dc_gen_fp64_matches_oracle():
     assert np.allclose(hg, ho, rtol=1e-9, atol=0)
 
 
+def test_dc_gen_fp32_matches_oracle_320x213():
+    # the configuration bench.py times for DC_gen: 320x213, L = 21, FP32,
+    # 5 concave-convex steps of 10 Frank-Wolfe iterations from the oracle's
+    # 50-iteration QP solution (rounded to FP32, the same start on both
+    # sides). The S history follows the oracle's within 1e-4 relative, and
+    # the rounded labelling's energy within 1e-4 of the oracle's.
+    im = synth.make("voronoi_320x213_L21")
+    ctx = gpu_ctx(im, torch.float32)
+    mu = synth.potts(im.L)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    qp = O.QP(model, im.unary, mu)
+    y0 = O.frank_wolfe(qp, O.softmax_neg(im.unary), 50).y
+    y0 = y0.astype(np.float32).astype(np.float64)
+    yo, ho = O.dc_gen(qp, y0, outer=5, inner=10)
+    y = T(y0, torch.float32)
+    hg = ctx.dc_gen(T(im.unary, torch.float32), T(mu, torch.float32), y, 5, 10)
+    print("S gpu", hg, "oracle", ho)
+    for a, b in zip(hg, ho):
+        assert abs(a - b) <= 1e-4 * abs(b)
+    assert all(b2 <= b1 + 1e-4 * abs(b1) for b1, b2 in zip(hg, hg[1:]))   # CCCP decreases S
+    lab = ctx.round(y)
+    e = ctx.energy(T(im.unary, torch.float32), T(mu, torch.float32), lab)
+    eo = O.energy(model, im.unary, mu, O.round_argmax(yo))
+    print(f"energy gpu {e:.8g} oracle {eo:.8g}")
+    assert abs(e - eo) <= 1e-4 * abs(eo)
+
+
 def test_errors_are_reported_not_fatal():
     from paper_1608_06192_amd import dcrf
     im = synth.make("rect_32x24_L3")
