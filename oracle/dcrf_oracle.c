@@ -313,19 +313,22 @@ void or_lattice_neighbours(const or_lattice *L, int *nbr)
     memcpy(nbr, L->nbr, (size_t)L->nv * (L->d + 1) * 2 * sizeof(int));
 }
 
-/* V (nv x C) = sum over points of b * in (n x C) */
+/* V (nv x C) = sum over points of b * in (n x C). The channels are
+ * independent: threads take whole channels, and every V[v][c] receives its
+ * terms in the order of the points, as in a serial loop. */
 void or_lattice_splat(const or_lattice *L, int C, const double *in, double *V)
 {
     const int D1 = L->d + 1;
     memset(V, 0, (size_t)L->nv * C * sizeof(double));
-    for (int a = 0; a < L->n; ++a)
-        for (int k = 0; k < D1; ++k) {
-            int v = L->pix_vid[(size_t)a * D1 + k];
-            if (v < 0) continue;
-            double b = L->pix_w[(size_t)a * D1 + k];
-            for (int c = 0; c < C; ++c)
+#pragma omp parallel for schedule(static) if (C > 1 && (size_t)L->n * C > 4096)
+    for (int c = 0; c < C; ++c)
+        for (int a = 0; a < L->n; ++a)
+            for (int k = 0; k < D1; ++k) {
+                int v = L->pix_vid[(size_t)a * D1 + k];
+                if (v < 0) continue;
+                double b = L->pix_w[(size_t)a * D1 + k];
                 V[(size_t)v * C + c] += b * in[(size_t)a * C + c];
-        }
+            }
 }
 
 /* one blur pass along u_j, out of place */
@@ -333,6 +336,7 @@ static void blur_pass(const or_lattice *L, int j, int C, const double *V,
                       double *W)
 {
     const int D1 = L->d + 1;
+#pragma omp parallel for schedule(static) if ((size_t)L->nv * C > 16384)
     for (int v = 0; v < L->nv; ++v) {
         int np = L->nbr[((size_t)v * D1 + j) * 2 + 0];
         int nm = L->nbr[((size_t)v * D1 + j) * 2 + 1];
@@ -362,6 +366,7 @@ void or_lattice_blur(const or_lattice *L, int C, double *V, int reverse)
 void or_lattice_slice(const or_lattice *L, int C, const double *V, double *out)
 {
     const int D1 = L->d + 1;
+#pragma omp parallel for schedule(static) if ((size_t)L->n * C > 16384)
     for (int a = 0; a < L->n; ++a) {
         for (int c = 0; c < C; ++c) out[(size_t)a * C + c] = 0.0;
         for (int k = 0; k < D1; ++k) {
@@ -391,4 +396,63 @@ void or_lattice_filter(const or_lattice *L, int C, const double *in,
     double g = or_lattice_gamma(L->d);
     for (size_t i = 0; i < (size_t)L->n * C; ++i) out[i] *= g;
     free(V);
+}
+
+/* ------------------------------------------------------------------------- */
+/* 3. The two triangular sums of the LP subgradient by divide and conquer.   */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * For one order of the N pixels (order[p] = pixel at position p), the sums of
+ * eq. grad_lp
+ *     U[c]  = sum over pixels a after c  of Kbar_ac,
+ *     Lo[c] = sum over pixels a before c of Kbar_ac,
+ * with Kbar = sum_m w_m K_m, by the divide and conquer of App. E: every node
+ * [lo, hi) of level l (lo = floor(n N / 2^l), split at
+ * mid = floor((2n+1) N / 2^(l+1))) filters the indicator of its left half and
+ * of its right half over the node's own points, with one reference lattice
+ * per kernel built on those points; the right indicator read at the left half
+ * adds to U, the left indicator read at the right half adds to Lo. Levels
+ * l = 0 .. ceil(log2 N) - 1. The nodes of a level hold disjoint pixels, so they
+ * are independent; within a node the kernels are added in the order m = 0..nk-1
+ * (acc = acc + w_m * filter_m), and the levels in increasing order.
+ * feats[m]: N x dims[m] features of kernel m (pixel-indexed).
+ */
+void or_lp_dnc_lattice(int N, int nk, const int *dims, const double *const *feats,
+                       const double *w, const int *order, double *U, double *Lo)
+{
+    for (int a = 0; a < N; ++a) U[a] = Lo[a] = 0.0;
+    int levels = 0;
+    while ((1LL << levels) < (long long)N) ++levels;
+    for (int l = 0; l < levels; ++l) {
+        const long long nn = 1LL << l;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (long long n = 0; n < nn; ++n) {
+            const long long lo = (n * N) >> l, hi = ((n + 1) * N) >> l;
+            const long long mid = ((2 * n + 1) * N) >> (l + 1);
+            if (!(lo < mid && mid < hi)) continue;
+            const int np = (int)(hi - lo), nl = (int)(mid - lo);
+            double *ind = (double *)calloc((size_t)np * 2, sizeof(double));
+            double *acc = (double *)calloc((size_t)np * 2, sizeof(double));
+            double *out = (double *)malloc((size_t)np * 2 * sizeof(double));
+            for (int i = 0; i < np; ++i) ind[(size_t)i * 2 + (i < nl ? 0 : 1)] = 1.0;
+            for (int m = 0; m < nk; ++m) {
+                const int d = dims[m];
+                double *f = (double *)malloc((size_t)np * d * sizeof(double));
+                for (int i = 0; i < np; ++i)
+                    memcpy(f + (size_t)i * d, feats[m] + (size_t)order[lo + i] * d,
+                           (size_t)d * sizeof(double));
+                or_lattice *Lt = or_lattice_build(np, d, f);
+                or_lattice_filter(Lt, 2, ind, out, 0);
+                for (int i = 0; i < np * 2; ++i) acc[i] += w[m] * out[i];
+                or_lattice_free(Lt);
+                free(f);
+            }
+            for (int i = 0; i < nl; ++i) U[order[lo + i]] += acc[(size_t)i * 2 + 1];
+            for (int i = nl; i < np; ++i) Lo[order[lo + i]] += acc[(size_t)i * 2 + 0];
+            free(ind);
+            free(acc);
+            free(out);
+        }
+    }
 }

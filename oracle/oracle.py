@@ -68,6 +68,8 @@ def _lib():
         lib.or_lattice_filter.argtypes = [P, I, P, P, I]
         lib.or_lattice_gamma.argtypes = [I]
         lib.or_lattice_gamma.restype = ctypes.c_double
+        lib.or_lp_dnc_lattice.argtypes = [I, I, P, P, P, P, P, P]
+        lib.or_lp_dnc_lattice.restype = None
         _LIB = lib
     return _LIB
 
@@ -542,6 +544,24 @@ def lp_pair_sums_dnc(model: Model, order: np.ndarray, inner: str,
                 acc += model.w[m] * Lattice(f[pts]).filter(ind)
             U[left] += acc[: mid - lo, 1]
             Lo[right] += acc[mid - lo:, 0]
+    return U, Lo
+
+
+def lp_pair_sums_dnc_c(model: Model, order: np.ndarray):
+    """The same sums as ``lp_pair_sums_dnc(model, order, "lattice")``, node
+    for node and in the same order of additions, walked in C (the nodes of a
+    level in parallel): a faster copy of that walk for larger images."""
+    N = order.shape[0]
+    nk = len(model.feats)
+    dims = np.array([f.shape[1] for f in model.feats], dtype=np.int32)
+    feats = [_f64(f) for f in model.feats]
+    fptr = (ctypes.c_void_p * nk)(*[f.ctypes.data for f in feats])
+    w = _f64(model.w)
+    o = np.ascontiguousarray(order, dtype=np.int32)
+    U = np.empty(N)
+    Lo = np.empty(N)
+    _lib().or_lp_dnc_lattice(N, nk, _p(dims), ctypes.cast(fptr, ctypes.c_void_p),
+                             _p(w), _p(o), _p(U), _p(Lo))
     return U, Lo
 
 

@@ -214,6 +214,22 @@ def test_lp_dnc_sampled_pixels():
     assert np.array_equal(Us[at], Uf[at]) and np.array_equal(Ls[at], Lf[at])
 
 
+def test_lp_dnc_c_walk_equals_python_walk():
+    # the C walk of the divide and conquer (lattice inner filter, nodes of a
+    # level in parallel) is the Python walk node for node: bit-identical
+    # sums, for odd and even N, one and two pixels, and ties in the order
+    for H, W, L, seed in [(24, 32, 3, 5), (17, 13, 4, 6), (1, 2, 2, 7),
+                          (1, 1, 2, 8), (9, 7, 3, 9)]:
+        im = synth.voronoi_image(H, W, L, seed=seed, regions=4)
+        model = O.Model(im.H, im.W, im.rgb, [synth.BILATERAL, synth.SPATIAL])
+        y = synth.random_simplex_points(im.N, L, seed=seed, sparsity=0.5)
+        for i in range(L):
+            order = O.sorted_order(y[:, i])
+            U, Lo = O.lp_pair_sums_dnc(model, order, "lattice")
+            U2, Lo2 = O.lp_pair_sums_dnc_c(model, order)
+            assert np.array_equal(U, U2) and np.array_equal(Lo, Lo2), (H, W, i)
+
+
 def test_lp_reformulation_and_integral_energy():
     # eq. simple_S: <g(y), y> equals eq. potts-lp's |.| form; at integral y
     # S_LP = E (Sec. 6)
