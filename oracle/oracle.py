@@ -452,6 +452,75 @@ def dc_gen(qp: QP, y0: np.ndarray, outer: int, inner: int):
     return y, hist
 
 
+def dcneg_pixel_step(c: np.ndarray, y: np.ndarray, mu: np.ndarray, wsum: float,
+                     inner: int, potts: bool) -> np.ndarray:
+    """The N independent convex problems of one DC_neg step (App. C,
+    eq. convexpb-onevar), one per pixel a:
+        min_{y_a in simplex}  c_a^T y_a - wsum y_a^T mu y_a,
+    with c = phi - g. wsum = sum_m w_m is the weight of the identity term
+    that eq. QP-concave-CCCP writes as mu (x) I_N (reading: each kernel
+    carries its weight, so removing the self-pair takes wsum I).
+
+    Potts, mu = [i != j]: on the simplex y_a^T mu y_a = 1 - |y_a|^2, so the
+    problem is min c_a^T y_a + wsum |y_a|^2, whose minimiser is the Euclidean
+    projection of -c_a / (2 wsum) onto the simplex; with wsum = 0 it is
+    linear and its minimiser is the vertex of the smallest c_a(i) (lowest
+    label on ties).
+    Other mu: App. C's Frank-Wolfe, per pixel, ``inner`` iterations from y_a
+    with the exact step of the per-pixel quadratic (each pixel its own step).
+    """
+    N, L = c.shape
+    if potts:
+        if wsum > 0:
+            return project_simplex(-c / (2.0 * wsum))
+        return onehot(np.argmin(c, axis=1), L)
+    y = _f64(y).copy()
+    for _ in range(inner):
+        grad = c - 2.0 * wsum * (y @ mu.T)
+        s = onehot(np.argmin(grad, axis=1), L)
+        d = s - y
+        # h(y + a d) = h(y) + a b1 + a^2 a2 per pixel (mu symmetric)
+        b1 = (c * d).sum(axis=1) - 2.0 * wsum * ((y @ mu.T) * d).sum(axis=1)
+        a2 = -wsum * ((d @ mu.T) * d).sum(axis=1)
+        alpha = np.where(a2 > 0, np.clip(-b1 / np.where(a2 > 0, 2.0 * a2, 1.0), 0.0, 1.0),
+                         np.where(a2 + b1 < 0, 1.0, 0.0))
+        y = y + alpha[:, None] * d
+    return y
+
+
+def dc_neg(qp: QP, y0: np.ndarray, outer: int, inner: int = 20):
+    """CCCP on the decomposition for negative semi-definite label
+    compatibilities (Sec. 5.2, eq. QP-concave-CCCP; App. C,
+    eq. convexpb-concavecccp and eq. convexpb-onevar).
+
+    With Kbar = sum_m w_m K_m and K' = Kbar - wsum I,
+        S(y) = phi^T y + y^T Psi y
+             = [phi^T y - wsum y^T (mu (x) I_N) y] + y^T (mu (x) Kbar) y,
+    a convex part and, for mu negative semi-definite on the directions that
+    keep each pixel on its simplex (Potts is: there mu acts as -I), a concave
+    part y^T (mu (x) Kbar) y. Step k (Alg. cccp) replaces the concave part by
+    its tangent at y^k; its gradient 2 (Kbar Y^k) mu^T is the one filter call
+    of the step (Kbar Y = K'Y + wsum Y). What remains to minimise over M is
+        c^T y - wsum y^T (mu (x) I_N) y,   c = phi + 2 (Kbar Y^k) mu^T,
+    eq. convexpb-concavecccp (the paper's g is -2 (Kbar Y^k) mu^T, the
+    gradient of the convex function that is subtracted), which splits into N
+    per-pixel problems (``dcneg_pixel_step``). Returns y and S(y^k) before
+    the first and after every step.
+    """
+    model, mu = qp.model, qp.mu
+    wsum = float(model.w.sum())
+    L = qp.L
+    potts = bool(np.array_equal(mu, np.ones((L, L)) - np.eye(L)))
+    y = _f64(y0).copy()
+    hist = [qp.S(y)]
+    for _ in range(outer):
+        KbarY = model.Kp(y) + wsum * y
+        c = qp.phi + 2.0 * KbarY @ mu.T
+        y = dcneg_pixel_step(c, y, mu, wsum, inner, potts)
+        hist.append(qp.S(y))
+    return y, hist
+
+
 # ---------------------------------------------------------------------------
 # LP relaxation (Sec. 6; App. D, E) -- Potts model
 # ---------------------------------------------------------------------------

@@ -160,6 +160,107 @@ def test_dc_gen_monotone_and_above_minimum():
     assert np.allclose(qp.phi - 2 * qp.d * 0.5, qp.phi - qp.d)
 
 
+def nsd_mu(L, seed):
+    """A symmetric compatibility that is negative semi-definite on the
+    directions with zero sum (the condition of the DC_neg decomposition):
+    J - B B^T with a zero-sum-blind constant part J."""
+    rng = np.random.default_rng(seed)
+    B = rng.normal(0, 0.6, size=(L, 2))
+    return np.ones((L, L)) - B @ B.T
+
+
+def _dcneg_parts(model, phi, mu, y, yk):
+    """S's convex part p, concave part q and the CCCP surrogate at y^k
+    (tangent of q), evaluated from a dense Kbar (independent of dc_neg)."""
+    K = model.dense_K()
+    wsum = model.w.sum()
+    Kbar = K + wsum * np.eye(K.shape[0])     # dense_K has no self-pairs
+    quad = lambda Kx, z: float((z * (Kx @ z @ mu.T)).sum())
+    p = float((phi * y).sum()) - wsum * float((y * (y @ mu.T)).sum())
+    q = quad(Kbar, y)
+    grad = 2.0 * (Kbar @ yk) @ mu.T
+    sur = p + quad(Kbar, yk) + float((grad * (y - yk)).sum())
+    return p, q, sur
+
+
+@pytest.mark.parametrize("general", [False, True])
+def test_dc_neg_decomposition_and_surrogate(general):
+    # eq. QP-concave-CCCP: S = p + q with p convex and q concave on M;
+    # the CCCP surrogate (q replaced by its tangent at y^k) equals S at y^k
+    # and lies above S on M (the tangent of a concave function)
+    model, phi = tiny_problem(N=8, L=3, seed=21)
+    L = 3
+    mu = nsd_mu(L, 3) if general else synth.potts(L)
+    assert np.array_equal(model.dense_K(), model.dense_K().T)
+    assert np.abs(np.diag(model.dense_K())).max() == 0.0
+    qp = O.QP(model, phi, mu)
+    rng = np.random.default_rng(5)
+    for _ in range(10):
+        y = synth.random_simplex_points(8, L, int(rng.integers(1 << 30)), 0.3)
+        yk = synth.random_simplex_points(8, L, int(rng.integers(1 << 30)), 0.3)
+        p, q, sur = _dcneg_parts(model, phi, mu, y, yk)
+        assert abs(p + q - qp.S(y)) <= 1e-10 * max(1.0, abs(qp.S(y)))
+        _, _, tight = _dcneg_parts(model, phi, mu, yk, yk)
+        assert abs(tight - qp.S(yk)) <= 1e-10 * max(1.0, abs(qp.S(yk)))
+        assert sur >= qp.S(y) - 1e-9
+
+
+@pytest.mark.parametrize("general", [False, True])
+def test_dc_neg_monotone_and_above_minimum(general):
+    # Alg. cccp on the DC_neg decomposition (exact filter): S(y^{k+1}) <=
+    # S(y^k) and S >= E_min on M (brute force); the surrogate is minimised
+    # exactly for Potts and by per-pixel Frank-Wolfe otherwise
+    model, phi = tiny_problem(N=8, L=3, seed=22)
+    mu = nsd_mu(3, 4) if general else synth.potts(3)
+    qp = O.QP(model, phi, mu)
+    y0 = O.softmax_neg(phi)
+    y, hist = O.dc_neg(qp, y0, outer=12, inner=50)
+    assert (np.diff(hist) <= 1e-9).all(), hist
+    assert hist[-1] < hist[0]
+    Emin, _ = O.brute_force_min(model.dense_K(), phi, mu)
+    assert min(hist) >= Emin - 1e-9
+    assert np.abs(y.sum(axis=1) - 1).max() < 1e-12 and y.min() >= 0
+
+
+@pytest.mark.parametrize("general", [False, True])
+def test_dc_neg_pixel_problem_matches_slsqp(general):
+    # eq. convexpb-onevar solved by an independent method (scipy's SLSQP with
+    # the simplex constraints) at random linear terms
+    from scipy.optimize import minimize
+    L, N = 5, 12
+    rng = np.random.default_rng(8)
+    mu = nsd_mu(L, 9) if general else synth.potts(L)
+    wsum = 2.5
+    c = rng.normal(0, 4.0, size=(N, L))
+    y0 = synth.random_simplex_points(N, L, 3, 0.0)
+    got = O.dcneg_pixel_step(c, y0, mu, wsum, 3000, not general)
+    h = lambda z, a: float(c[a] @ z - wsum * z @ mu @ z)
+    for a in range(N):
+        r = minimize(lambda z: h(z, a), y0[a], method="SLSQP",
+                     bounds=[(0, 1)] * L,
+                     constraints=[{"type": "eq", "fun": lambda z: z.sum() - 1}],
+                     options={"ftol": 1e-14, "maxiter": 500})
+        assert abs(got[a].sum() - 1) < 1e-12 and got[a].min() >= 0
+        if not general:   # closed form: the exact minimiser
+            assert h(got[a], a) <= r.fun + 1e-9, a
+            continue
+        # Frank-Wolfe: its duality gap brackets the optimum, and after 3000
+        # iterations the value is close to it
+        grad = c[a] - 2.0 * wsum * mu @ got[a]
+        gap = float(grad @ got[a] - grad.min())
+        assert r.fun >= h(got[a], a) - gap - 1e-9, a
+        assert h(got[a], a) - r.fun <= 1e-4 * max(1.0, abs(r.fun)), a
+        assert h(got[a], a) <= h(y0[a], a) + 1e-12, a
+
+
+def test_dc_neg_zero_weights_is_unary_argmin():
+    # w = 0: the per-pixel problems are linear; one step gives argmin phi
+    model, phi = tiny_problem(seed=23, w=(0.0, 0.0))
+    qp = O.QP(model, phi, synth.potts(3))
+    y, _ = O.dc_neg(qp, O.softmax_neg(phi), outer=1)
+    assert np.array_equal(y, O.onehot(np.argmin(phi, axis=1), 3))
+
+
 # ----------------------------------------------------------------------- LP
 
 def test_dnc_nodes_golden_example():
