@@ -16,11 +16,18 @@ Beside it the JSON line reports:
 * roofline: the dominant kernel of the step, its algorithmic bytes per launch
   over its average launch time (HIP events carried by the kernel dispatches
   on the library's stream), against the 8 TB/s HBM peak;
-* cpu_baseline: the FP64 oracle's Frank-Wolfe iterations on the host, one
-  thread, over a bounded sample of iterations of the same workload;
-* qp_dc: 50 Frank-Wolfe iterations and the DC relaxation (5 concave-convex
-  steps of 10 inner iterations) at 320x213, L=21, FP32, with the energy of
-  the rounded labelling;
+* cpu_baseline: the FP64 oracle's Frank-Wolfe iterations on the host's
+  cores (and on one thread beside it), over a bounded sample of iterations
+  of the same workload;
+* dc_neg: microseconds per step of the DC relaxation for negative
+  semi-definite compatibilities at the same shape (one filter call and the
+  per-pixel closed form per step);
+* lp: the LP relaxation's projected subgradient descent (divide and conquer,
+  100 steps from the timed QP solution): milliseconds per step and the
+  first, best and last S_LP;
+* qp_dc / qp_dcneg: 50 Frank-Wolfe iterations and then the generic DC
+  relaxation (5 concave-convex steps of 10 inner iterations) or DC_neg (5
+  steps) at 320x213, L=21, FP32, with the energy of the rounded labelling;
 * diff: 10 unrolled Frank-Wolfe iterations at 500x375, L=21, FP32 (seed 3):
   forward with checkpoints, reverse sweep, and the plain forward beside them;
 * batch: 16 Voronoi images of sizes U{240..500}^2, L=21, FP32, 10 Frank-
@@ -110,22 +117,31 @@ def class_bytes(name, N, L, e, lattices, group=2):
 
 
 def cpu_baseline(im, kernels, mu, iters):
-    """The FP64 oracle's Frank-Wolfe on the same image, one host thread."""
-    from threadpoolctl import threadpool_limits
+    """The FP64 oracle's Frank-Wolfe on the same image on the host's cores:
+    its lattice filter runs OpenMP threads (over output elements in the blur
+    and slice, over channels in the splat), its other steps are NumPy. Timed
+    with every thread the OpenMP runtime offers, then with one thread for
+    comparison."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import oracle as O
+    model = O.Model(im.H, im.W, im.rgb, kernels)
+    qp = O.QP(model, im.unary, mu)
+    y0 = O.softmax_neg(im.unary)
+    O.frank_wolfe(qp, y0, 1)                    # warm the code paths
+    omp = [p["num_threads"] for p in threadpool_info() if p.get("user_api") == "openmp"]
+    cores = max(omp) if omp else 1
+    t0 = time.perf_counter()
+    O.frank_wolfe(qp, y0, iters)
+    dt = time.perf_counter() - t0
     with threadpool_limits(limits=1):
-        os.environ["OMP_NUM_THREADS"] = "1"
-        model = O.Model(im.H, im.W, im.rgb, kernels)
-        qp = O.QP(model, im.unary, mu)
-        y0 = O.softmax_neg(im.unary)
-        O.frank_wolfe(qp, y0, 1)                    # warm the code paths
-        t0 = time.perf_counter()
+        t1 = time.perf_counter()
         O.frank_wolfe(qp, y0, iters)
-        dt = time.perf_counter() - t0
-    return dict(value=iters / dt, unit="FW iters/s", cores=1, kind="oracle",
+        dt1 = time.perf_counter() - t1
+    return dict(value=iters / dt, unit="FW iters/s", cores=cores, kind="oracle",
                 sample=f"{iters} Frank-Wolfe iterations (plus the solve's "
                        f"first filter of y0) of the FP64 oracle on the same "
-                       f"500x375 L=21 image, {dt:.1f} s")
+                       f"500x375 L=21 image, {dt:.1f} s on {cores} threads",
+                one_thread=dict(value=iters / dt1, seconds=dt1))
 
 
 # ---- profiler summaries ----------------------------------------------------
@@ -285,7 +301,7 @@ def extensions(torch, dcrf, synth, dev, kernels):
     ctx = dcrf.Context(0)
     ctx.set_image(im.H, im.W, torch.from_numpy(im.rgb).to(dev), kernels, dtype=f32)
     phi = torch.from_numpy(im.unary).to(dev, f32)
-    mu = torch.from_numpy(synth.potts(im.L)).to(dev, f32)
+    mu = None   # the Potts compatibility (a null mu: no host read of it)
     y0 = torch.softmax(-phi, dim=1)
     res_dc = {}
 
@@ -304,13 +320,34 @@ def extensions(torch, dcrf, synth, dev, kernels):
     log(f"[bench] QP 50 + DC_gen 5x10 at 320x213: {t_qd:.2f} ms, S = "
         f"{res_dc['hist'][-1]:.6g}, E(argmax) = {energy:.6g}")
 
+    # -- DC_neg: 50 Frank-Wolfe iterations, then 5 CCCP steps of the
+    #    negative semi-definite decomposition (one filter call each) --------
+    res_dn = {}
+
+    def qp_dcneg():
+        y = y0.clone()
+        ctx.qp_frank_wolfe(phi, mu, y, wl["iters"], trace=False)
+        ctx.dc_neg(phi, mu, y, 5, hist=False)
+        res_dn["y"] = y
+
+    t_qn = _timed(torch, qp_dcneg, 3)
+    yq = y0.clone()
+    ctx.qp_frank_wolfe(phi, mu, yq, wl["iters"], trace=False)
+    hist_dn = ctx.dc_neg(phi, mu, yq.clone(), 5)
+    e_dn = ctx.energy(phi, mu, ctx.round(res_dn["y"]))
+    out["qp_dcneg"] = dict(workload="voronoi 320x213 L=21 FP32: 50 FW iterations, then "
+                                    "DC_neg 5 steps", ms=t_qn, S_hist=hist_dn,
+                           energy=e_dn)
+    log(f"[bench] QP 50 + DC_neg 5 at 320x213: {t_qn:.2f} ms, S {hist_dn[0]:.6g} -> "
+        f"{hist_dn[-1]:.6g}, E(argmax) = {e_dn:.6g}")
+
     # -- differentiation: 10 unrolled iterations at 500x375 ------------------
     im = synth.make("voronoi_500x375_L21_diff")
     iters = synth.WORKLOADS["voronoi_500x375_L21_diff"]["iters"]
     ctx = dcrf.Context(0)
     ctx.set_image(im.H, im.W, torch.from_numpy(im.rgb).to(dev), kernels, dtype=f32)
     phi = torch.from_numpy(im.unary).to(dev, f32)
-    mu = torch.from_numpy(synth.potts(im.L)).to(dev, f32)
+    mu = None   # the Potts compatibility (a null mu: no host read of it)
     gt = torch.from_numpy(im.gt.astype(np.int64)).to(dev)
     holder = {}
 
@@ -347,7 +384,7 @@ def extensions(torch, dcrf, synth, dev, kernels):
     ims = synth.make_batch()
     iters = synth.WORKLOADS["voronoi_batch16_L21"]["iters"]
     L = ims[0].L
-    mu = torch.from_numpy(synth.potts(L)).to(dev, f32)
+    mu = None   # the Potts compatibility (a null mu: no host read of it)
     bctx = dcrf.Context(0)
     bctx.set_images([(x.H, x.W) for x in ims],
                     [torch.from_numpy(x.rgb).to(dev) for x in ims], kernels,
@@ -437,8 +474,8 @@ def main():
     ap.add_argument("--filter-reps", type=int, default=200)
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--lp-steps", type=int, default=3)
-    ap.add_argument("--lp-beta0", type=float, default=1e-4)
+    ap.add_argument("--lp-steps", type=int, default=100)
+    ap.add_argument("--lp-beta0", type=float, default=1e-6)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB copy kernel (reference for "
                          "the HBM byte counters of a profiler run)")
@@ -485,7 +522,7 @@ def main():
     log(f"[bench] {name}: N={N} L={L} lattices (d, M) = {lat}")
 
     phi = torch.from_numpy(im.unary).to(dev, f32)
-    mu = torch.from_numpy(mu_np).to(dev, f32)
+    mu = None   # the Potts compatibility (a null mu: no host read of it)
     e = np.exp(-(im.unary - im.unary.min(axis=1, keepdims=True)))
     y0 = torch.from_numpy(e / e.sum(axis=1, keepdims=True)).to(dev, f32)
 
@@ -534,6 +571,18 @@ def main():
     log(f"[bench] dense filter L=21: {f_ms * 1e3:.1f} us, "
         f"{filt['GBps']:.0f} GB/s algorithmic")
 
+    # ---- DC_neg steps at the same size (one filter call per step) ---------
+    yd = y.clone()
+    ctx.dc_neg(phi, mu, yd, 2, hist=False)
+    torch.cuda.synchronize()
+    dn_steps = 20
+    ev0.record()
+    ctx.dc_neg(phi, mu, yd, dn_steps, hist=False)
+    ev1.record()
+    torch.cuda.synchronize()
+    dn_ms = ev0.elapsed_time(ev1) / dn_steps
+    log(f"[bench] DC_neg step at 500x375: {dn_ms * 1e3:.1f} us")
+
     # ---- LP subgradient steps from the QP solution -------------------------
     lp = None
     if args.lp_steps > 0:
@@ -544,7 +593,8 @@ def main():
         torch.cuda.synchronize()
         lp_ms = (time.perf_counter() - t0) * 1e3 / args.lp_steps
         lp = dict(ms_per_step=lp_ms, steps=args.lp_steps, beta0=args.lp_beta0,
-                  S_LP_first=hist[0], S_LP_best=best)
+                  S_LP_first=hist[0], S_LP_best=best, S_LP_last=hist[-1],
+                  best_step=int(np.argmin(hist)))
         log(f"[bench] LP subgradient step (divide and conquer, 21 labels, "
             f"{int(np.ceil(np.log2(N)))} levels): {lp_ms:.1f} ms")
 
@@ -580,6 +630,9 @@ def main():
                            step="one Frank-Wolfe QP iteration",
                            lattice_vertices=[M for d, M in lat]),
                lattice_filter=filt, step_bytes=fw_step_bytes(N, L, 4, lat),
+               dc_neg=dict(workload="voronoi 500x375 L=21 FP32, DC_neg steps from "
+                                    "the timed QP solution", us_per_step=dn_ms * 1e3,
+                           steps=dn_steps),
                per_kernel_us={k: v[0] * 1e3 for k, v in per_iter.items()},
                lp=lp, roofline=roofline, **ext)
     if not args.no_cpu:

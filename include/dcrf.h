@@ -19,14 +19,26 @@
  *  - Memory: every array argument marked (dev) is DEVICE memory on the
  *    context's device, owned by the caller, contiguous, in the context's
  *    floating type (float for DCRF_F32, double for DCRF_F64) unless stated.
- *    Arguments marked (host) are host memory. The library keeps its own
- *    device workspace (lattice tables, solver state) inside the context and
- *    never frees caller memory.
+ *    Arguments marked (host) are host memory. The context's own device
+ *    memory (lattice tables, solver state) is either allocated by the
+ *    library as calls need it, or carved from a workspace the caller hands
+ *    to dcrf_set_image / dcrf_set_images (see dcrf_workspace_size); with a
+ *    workspace the library calls neither hipMalloc nor hipFree. It never
+ *    frees caller memory.
+ *  - Device-detected errors: the solvers check their unaries and marginals
+ *    for non-finite values on the device; a raised flag is reported as
+ *    DCRF_EINVAL by the next call that waits for the stream (dcrf_sync
+ *    waits and reports), and is then cleared.
  *  - Streams: all device work is enqueued on the context's stream. Calls
  *    that return host values (energies, traces, objective values) wait for
  *    the stream; the others are asynchronous.
  *  - Errors: every call returns a dcrf_status. It never aborts or exits. On
  *    failure dcrf_last_error() returns a message; the context stays usable.
+ *  - Label compatibility: every mu argument may be NULL, which stands for
+ *    the Potts compatibility mu(i, j) = [i != j] of Sec. 3. The library then
+ *    uses its own device copy and knows the closed form without reading mu
+ *    back; a non-NULL mu that happens to be Potts is recognised by one
+ *    device-to-host copy per call.
  */
 #ifndef DCRF_H
 #define DCRF_H
@@ -108,16 +120,58 @@ const char *dcrf_version(void);
 
 /* ---- image and lattices ------------------------------------------------ */
 
+/* An upper bound of the device memory a context needs for one H x W image
+ * with these kernels, for every call of this header on it with at most L
+ * labels or channels (the reverse sweep's workspace included, its
+ * checkpoint buffer not: that is the caller's). The bound takes the largest
+ * lattices the image size allows (N (d+1) vertices per kernel), so it holds
+ * for any colours. It assumes dense splat chunks of at most 64 entries
+ * (dcrf_set_tune refuses more while a workspace is attached), traces and S
+ * histories of at most 4096 steps and at most 4096 unrolled iterations.
+ * *bytes (host). No device is touched. */
+int dcrf_workspace_size(int H, int W, int L, const dcrf_kernel *kernels,
+                        int nk, int dtype, size_t *bytes);
+
+/* The same for a batch of B images of sizes H[j] x W[j] (dcrf_set_images). */
+int dcrf_workspace_size_images(int B, const int *H, const int *W, int L,
+                               const dcrf_kernel *kernels, int nk, int dtype,
+                               size_t *bytes);
+
 /* Set the image and kernels (1 <= nk <= 4) and build one permutohedral
  * lattice per kernel on the device: lattice coordinates in FP64, a device
  * hash table of vertices, per-pixel vertex ids and barycentric weights and a
  * neighbour table along the d+1 blur directions. Also computes the row sums
  * r = K'1 used by d (eq. RL-diagonal). rgb: (dev) float32 N x 3.
  * dtype: DCRF_F32 or DCRF_F64 for every later floating argument.
- * Errors: DCRF_EINVAL (sizes, thetas), DCRF_ERANGE (coordinates too large
- * for the 64-bit vertex key: theta too small for the image), DCRF_ENOMEM. */
+ * workspace: (dev, caller-owned, 256-byte aligned, >= 4096 bytes) or NULL.
+ * With a workspace of ws_bytes (dcrf_workspace_size gives enough) every
+ * device buffer of the context is taken from it until the next
+ * dcrf_set_image / dcrf_set_images or dcrf_destroy, which hand it back; the
+ * caller keeps it alive until then. A call that would need more returns
+ * DCRF_ENOMEM and leaves the context usable. NULL: the library allocates.
+ * Errors: DCRF_EINVAL (sizes, thetas, a non-finite colour), DCRF_ERANGE
+ * (coordinates too large for the 64-bit vertex key: theta too small for the
+ * image), DCRF_ECAPACITY (a lattice has more vertices than hash slots: only
+ * with dcrf_set_hash_capacity), DCRF_ENOMEM. */
 int dcrf_set_image(dcrf_ctx *ctx, int H, int W, const float *rgb,
-                   const dcrf_kernel *kernels, int nk, int dtype);
+                   const dcrf_kernel *kernels, int nk, int dtype, void *workspace,
+                   size_t ws_bytes);
+
+/* Bytes of the context's workspace in use now and at most since it was
+ * attached (DCRF_EINVAL without a workspace). Either pointer may be NULL. */
+int dcrf_workspace_used(dcrf_ctx *ctx, size_t *in_use, size_t *peak);
+
+/* Force the hash table of every lattice built by later dcrf_set_image /
+ * dcrf_set_images calls to `slots` slots (a power of two in [16, 2^32]);
+ * 0 restores the default (a power of two of at least 2 N (d+1), which never
+ * overflows). A lattice with more vertices than slots fails its build with
+ * DCRF_ECAPACITY. For testing the capacity path and for bounding the
+ * table's memory. */
+int dcrf_set_hash_capacity(dcrf_ctx *ctx, size_t slots);
+
+/* Wait for the context's stream and report device-detected errors raised
+ * since the last report (DCRF_EINVAL for a non-finite unary or marginal). */
+int dcrf_sync(dcrf_ctx *ctx);
 
 /* A batch of B images of their own sizes in one context (the batched
  * extension of the QP solver; the model of Sec. 3 per image). Image j has
@@ -135,10 +189,11 @@ int dcrf_set_image(dcrf_ctx *ctx, int H, int W, const float *rgb,
  * step checkpoints are per image; dcrf_fw_backward writes B x nk weight
  * gradients (image-major); dcrf_energy returns the sum over the images.
  * Not available on a batch (DCRF_EUNSUPPORTED): the exact filter mode and
- * the LP calls. B = 1 is the same as dcrf_set_image. */
+ * the LP calls. B = 1 is the same as dcrf_set_image. workspace, ws_bytes: as
+ * for dcrf_set_image, sized by dcrf_workspace_size_images. */
 int dcrf_set_images(dcrf_ctx *ctx, int B, const int *H, const int *W,
                     const float *const *rgb, const dcrf_kernel *kernels, int nk,
-                    int dtype);
+                    int dtype, void *workspace, size_t ws_bytes);
 
 /* *nimg = images held (1 after dcrf_set_image), *rows = N, the rows of every
  * N x C argument; seg (host, 2 nimg ints, may be NULL) = first and one past
@@ -217,8 +272,32 @@ int dcrf_qp_frank_wolfe(dcrf_ctx *ctx, const void *unary, const void *mu,
  * steps, each minimising phi^T y - 2 (d * y^k)^T y + y^T (Psi + D) y with
  * `inner` warm-started Frank-Wolfe iterations. S_hist: (host) outer+1 values
  * of S(y) = phi^T y + y^T Psi y (before the first and after each step) or
- * NULL. */
+ * NULL. The history stays on the device until the end of the call, which
+ * then waits for the stream once; without S_hist (and with mu NULL) the
+ * call is asynchronous. */
 int dcrf_dc_gen(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
+                void *y_inout, int outer, int inner, double *S_hist);
+
+/* DC relaxation for negative semi-definite label compatibilities by CCCP
+ * (Sec. 5.2, eq. QP-concave-CCCP; App. C, eq. convexpb-concavecccp and
+ * eq. convexpb-onevar). S(y) = phi^T y + y^T Psi y is split into
+ * phi^T y - wsum y^T (mu (x) I) y (convex) and y^T (mu (x) Kbar) y (concave),
+ * Kbar = sum_m w_m K_m, wsum = sum_m w_m. Each of the `outer` steps makes one
+ * filter call for the concave part's gradient 2 (Kbar Y) mu^T and then
+ * solves N independent L-variable problems
+ *     min over the simplex of c_a^T y_a - wsum y_a^T mu y_a,
+ *     c_a = phi_a + 2 (Kbar Y)_a mu^T.
+ * mu NULL or Potts: the exact minimiser, the projection of -c_a / (2 wsum)
+ * onto the simplex (the vertex of the smallest c_a(i) when wsum = 0);
+ * `inner` is then unused. Another mu (dev L x L, symmetric, negative
+ * semi-definite on the vectors that sum to zero; not checked): `inner` >= 1
+ * per-pixel Frank-Wolfe iterations with exact steps from y_a (App. C).
+ * unary: (dev) N x L; y_inout: (dev) N x L, start (in the feasible set) and
+ * result. S_hist: (host) outer + 1 values of S(y) (before the first and
+ * after each step; for a batch, the sum over its images) or NULL; asking
+ * for it costs one more filter call and one wait for the stream at the end.
+ * L <= 32 (DCRF_EUNSUPPORTED otherwise). */
+int dcrf_dc_neg(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
                 void *y_inout, int outer, int inner, double *S_hist);
 
 /* argmax labelling of marginals y (dev, N x L) into labels (dev int32 N),
@@ -281,22 +360,26 @@ int dcrf_project_simplex(dcrf_ctx *ctx, const void *v, int L, void *y);
  * part 256-byte aligned. L <= 32. */
 int dcrf_fw_saved_size(dcrf_ctx *ctx, int L, int iters, size_t *bytes);
 
-/* Forward: unary (dev N x L), mu (dev L x L); y_out (dev N x L) = y_T;
- * saved (dev, dcrf_fw_saved_size bytes, caller-owned) receives the
- * checkpoints that dcrf_fw_backward reads. */
+/* Forward: unary (dev N x L), mu (dev L x L or NULL); w (host, nk doubles,
+ * >= 0, or NULL to keep the context's weights): the kernel weights w_m of
+ * eq. pairwise, which stay set on the context afterwards (changing them
+ * recomputes K'1, one filter call; the lattices do not depend on them);
+ * y_out (dev N x L) = y_T; saved (dev, dcrf_fw_saved_size bytes,
+ * caller-owned) receives the checkpoints that dcrf_fw_backward reads. */
 int dcrf_fw_forward(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
-                    int iters, void *y_out, void *saved);
+                    const double *w, int iters, void *y_out, void *saved);
 
 /* Backward: given dl/dy_T in grad_y (dev N x L), writes dl/dphi to
- * grad_unary (dev N x L) and, if grad_w (host, nk doubles; B x nk for a
- * batch, image-major) is not NULL,
- * dl/dw_m for every kernel. unary, mu, L, iters and saved must be those of
- * the forward call, and neither the image nor the weights may have changed
- * in between. The step adjoints are formed on the device; the call waits
- * for the stream once, at its end. */
+ * grad_unary (dev N x L); grad_w (host, nk doubles; B x nk for a batch,
+ * image-major; may be NULL) receives each image's dl/dw_m, and grad_w_total
+ * (host, nk doubles, may be NULL) their sum over the images, the gradient of
+ * weights that the images share (equal to grad_w for one image). unary, mu,
+ * L, iters and saved must be those of the forward call, and neither the
+ * image nor the weights may have changed in between. The step adjoints are
+ * formed on the device; the call waits for the stream once, at its end. */
 int dcrf_fw_backward(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
                      int iters, const void *saved, const void *grad_y,
-                     void *grad_unary, double *grad_w);
+                     void *grad_unary, double *grad_w, double *grad_w_total);
 
 /* ---- benchmarking support ---------------------------------------------- */
 
@@ -306,7 +389,7 @@ int dcrf_fw_backward(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
  * kernel's own execution time. */
 int dcrf_set_profiling(dcrf_ctx *ctx, int enable);
 
-/* Totals of kernel class k (0 <= k < 8): *name (static string, the kernel's
+/* Totals of kernel class k (0 <= k < 9): *name (static string, the kernel's
  * name), *total_ms (summed event time) and *launches. Waits for the stream.
  * Any output pointer may be NULL. */
 int dcrf_get_profile(dcrf_ctx *ctx, int k, const char **name, double *total_ms,

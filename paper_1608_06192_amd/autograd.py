@@ -5,16 +5,20 @@ App. B), differentiable in the unaries phi and the kernel weights w_m. The
 forward and the reverse sweep both run in the HIP library (dcrf_fw_forward /
 dcrf_fw_backward); this module only marshals tensors.
 
-Memory: the forward keeps, per iteration, y_t (N x L), the conditional
-gradient's labels s_t (N int32) and four scalars; Q y_t and Q s_t are
-recomputed during the reverse sweep. With ``recompute=True`` the checkpoints
-are dropped after the forward and rebuilt by a second forward at backward
-time, so that nothing of size T x N x L stays alive between the two passes.
+Memory: the forward keeps, per iteration t, the iterate y_t and
+P_t = (Psi + D) y_t (N x L each), the conditional gradient's labels s_t
+(N int32), each lattice's blurred vertex values of the one-hot s_t (and of
+y_0), and four scalars: about 2 T N L values, 363 MB at 500x375, L = 21,
+T = 10 in FP32 (Context.fw_saved_size gives the exact figure). The reverse
+sweep reads them and runs no filter inside its loop. With
+``recompute=True`` the checkpoint is dropped after the forward and rebuilt
+by a second forward at backward time, so that nothing of size T x N x L
+stays alive between the two passes (the peak during backward is the same).
 
 On a context that holds a batch of images (``Context.set_images``) the
 unaries and marginals are the packed arrays of the batch, every image takes
 its own steps, and the shared weights receive the sum of the images'
-gradients.
+gradients (summed in the library).
 """
 
 from __future__ import annotations
@@ -29,9 +33,8 @@ class UnrolledFrankWolfe(torch.autograd.Function):
     def forward(fctx, ctx: Context, unary: torch.Tensor, weights: torch.Tensor,
                 mu: torch.Tensor, iters: int, recompute: bool = False):
         w = [float(v) for v in weights.detach().cpu().tolist()]
-        ctx.set_weights(w)
-        y, saved = ctx.fw_forward(unary.detach().contiguous(), mu.contiguous(),
-                                  iters)
+        mu = None if mu is None else mu.contiguous()
+        y, saved = ctx.fw_forward(unary.detach().contiguous(), mu, iters, w=w)
         fctx.dcrf = ctx
         fctx.iters = iters
         fctx.recompute = recompute
@@ -39,7 +42,7 @@ class UnrolledFrankWolfe(torch.autograd.Function):
         fctx.wdtype, fctx.wdevice = weights.dtype, weights.device
         if recompute:
             saved = None
-        fctx.save_for_backward(unary.detach().contiguous(), mu.contiguous())
+        fctx.save_for_backward(unary.detach().contiguous(), mu)
         fctx.saved_ckpt = saved
         return y
 
@@ -51,12 +54,10 @@ class UnrolledFrankWolfe(torch.autograd.Function):
         ctx.set_weights(fctx.w)
         saved = fctx.saved_ckpt
         if saved is None:
-            _, saved = ctx.fw_forward(unary, mu, fctx.iters)
+            _, saved = ctx.fw_forward(unary, mu, fctx.iters, w=fctx.w)
         gphi, gw = ctx.fw_backward(unary, mu, fctx.iters, saved,
-                                   grad_y.contiguous())
+                                   grad_y.contiguous(), summed=True)
         fctx.saved_ckpt = None
-        if ctx.nimg > 1:   # a batch shares the weights: sum over its images
-            gw = [sum(g[m] for g in gw) for m in range(ctx.nk)]
         gw_t = torch.tensor(gw, dtype=fctx.wdtype, device=fctx.wdevice)
         return None, gphi, gw_t, None, None, None
 

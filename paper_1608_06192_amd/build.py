@@ -42,7 +42,9 @@ SOURCES = {
     "diff.hip": [],
     "batch.hip": [],
     "tiles.hip": [],
+    "dcneg.hip": [],
     "abi.cpp": ["-x", "hip"],
+    "workspace.cpp": ["-x", "hip"],
 }
 
 

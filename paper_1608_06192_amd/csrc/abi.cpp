@@ -6,12 +6,15 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "dcrf_internal.h"
 
 using dcrf::Error;
 
 namespace dcrf {
+thread_local Arena *tl_arena = nullptr;
+
 // name of the kernel that class c launches under the context's launch shapes
 const char *prof_name(const dcrf_ctx *ctx, int c) {
     const bool tiles = ctx->tile_mode != 0, staged = ctx->splat_lds != 0;
@@ -26,6 +29,7 @@ const char *prof_name(const dcrf_ctx *ctx, int c) {
     case PROF_SPLAT_LABELS:
         return tiles ? "k_tile_labels" : staged ? "k_splat_labels_lds" : "k_splat_labels_chunks";
     case PROF_FW_FINAL: return "k_fw_final";
+    case PROF_DCNEG: return "k_dcneg_rows";
     default: return "?";
     }
 }
@@ -40,11 +44,23 @@ int set_err(dcrf_ctx *ctx, int code, const std::string &msg) {
     return code;
 }
 
+// the context's workspace (when it has one) serves every allocation made
+// during a call
+struct ArenaScope {
+    dcrf::Arena *prev;
+    explicit ArenaScope(dcrf_ctx *ctx) : prev(dcrf::tl_arena) {
+        ctx->arena.stream = ctx->stream;
+        dcrf::tl_arena = ctx->arena.active() ? &ctx->arena : nullptr;
+    }
+    ~ArenaScope() { dcrf::tl_arena = prev; }
+};
+
 template <typename F>
 int guarded(dcrf_ctx *ctx, F &&f) {
     if (!ctx) return DCRF_EINVAL;
     try {
         DCRF_TRY_HIP(hipSetDevice(ctx->device));
+        ArenaScope scope(ctx);
         f();
         ctx->err.clear();
         return DCRF_OK;
@@ -98,19 +114,29 @@ int dcrf_create(dcrf_ctx **out, int device, void *hip_stream) {
     return DCRF_OK;
 }
 
-int dcrf_destroy(dcrf_ctx *ctx) {
-    if (!ctx) return DCRF_EINVAL;
-    (void)hipSetDevice(ctx->device);
+// every device buffer of the context, back to hipFree or to its workspace
+static void release_all(dcrf_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     for (auto &L : ctx->lat) L.release();
     dcrf::lp_release(ctx);
     dcrf::diff_release(ctx);
-    ctx->prof.release();
     for (dcrf::DevBuf *b :
          {&ctx->r, &ctx->scratch, &ctx->tmpA, &ctx->tmpB, &ctx->fw_c,
           &ctx->fw_Py, &ctx->fw_Ps, &ctx->fw_s, &ctx->fw_sprev, &ctx->fw_part,
-          &ctx->fw_scal, &ctx->fw_trace, &ctx->fw_mu})
+          &ctx->fw_scal, &ctx->fw_trace, &ctx->fw_mu, &ctx->potts, &ctx->hist,
+          &ctx->errflag, &ctx->seg, &ctx->tiles, &ctx->tile_img_off})
         b->release();
+    ctx->potts_L = 0;
+    ctx->potts_dtype = -1;
+    ctx->ntiles = 0;
+    ctx->has_image = false;
+}
+
+int dcrf_destroy(dcrf_ctx *ctx) {
+    if (!ctx) return DCRF_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    release_all(ctx);
+    ctx->prof.release();
     delete ctx;
     return DCRF_OK;
 }
@@ -149,13 +175,29 @@ static void set_kernels(dcrf_ctx *ctx, const dcrf_kernel *kernels, int nk,
     }
 }
 
+// Attach the caller's workspace (or none) before an image is built. Buffers
+// move only when a workspace is involved on either side; without one the
+// context keeps its grow-only allocations from image to image.
+static void attach_workspace(dcrf_ctx *ctx, void *ws, size_t bytes) {
+    REQUIRE(ws == nullptr || bytes >= 4096, "workspace smaller than 4096 bytes");
+    REQUIRE(((uintptr_t)ws & 255) == 0, "workspace must be 256-byte aligned");
+    if (ws || ctx->arena.active()) {
+        release_all(ctx);
+        ctx->arena.reset(ws, ws ? bytes : 0);
+    }
+    ctx->arena.stream = ctx->stream;
+    dcrf::tl_arena = ctx->arena.active() ? &ctx->arena : nullptr;
+}
+
 int dcrf_set_image(dcrf_ctx *ctx, int H, int W, const float *rgb,
-                   const dcrf_kernel *kernels, int nk, int dtype) {
+                   const dcrf_kernel *kernels, int nk, int dtype, void *workspace,
+                   size_t ws_bytes) {
     return guarded(ctx, [&] {
         REQUIRE(H >= 1 && W >= 1 && (long long)H * W <= (1ll << 28),
                 "H and W must be >= 1 with H*W <= 2^28");
         REQUIRE(rgb != nullptr, "rgb is null");
         set_kernels(ctx, kernels, nk, dtype);
+        attach_workspace(ctx, workspace, ws_bytes);
         ctx->H = H;
         ctx->W = W;
         ctx->N = H * W;
@@ -172,7 +214,7 @@ int dcrf_set_image(dcrf_ctx *ctx, int H, int W, const float *rgb,
 
 int dcrf_set_images(dcrf_ctx *ctx, int B, const int *H, const int *W,
                     const float *const *rgb, const dcrf_kernel *kernels, int nk,
-                    int dtype) {
+                    int dtype, void *workspace, size_t ws_bytes) {
     return guarded(ctx, [&] {
         REQUIRE(B >= 1 && B <= 4096, "B must be in [1, 4096]");
         REQUIRE(H && W && rgb, "null argument");
@@ -182,6 +224,7 @@ int dcrf_set_images(dcrf_ctx *ctx, int B, const int *H, const int *W,
             REQUIRE(rgb[j] != nullptr, "rgb pointer is null");
         }
         set_kernels(ctx, kernels, nk, dtype);
+        attach_workspace(ctx, workspace, ws_bytes);
         if (ctx->mode == DCRF_FILTER_EXACT && B > 1)
             throw Error{DCRF_EUNSUPPORTED, "a batch needs the lattice filter mode"};
         if (B == 1) {
@@ -241,6 +284,8 @@ int dcrf_set_tune(dcrf_ctx *ctx, const dcrf_tune *t) {
         auto chunk_ok = [](int c) { return c == 16 || c == 32 || c == 64 || c == 128 || c == 256; };
         REQUIRE(chunk_ok(t->splat_chunk) && chunk_ok(t->dense_chunk),
                 "splat_chunk and dense_chunk must be 16, 32, 64, 128 or 256");
+        REQUIRE(!ctx->arena.active() || t->dense_chunk <= 64,
+                "with a caller workspace dense_chunk must be at most 64");
         REQUIRE(t->blur_vectors_per_thread >= 1 && t->blur_vectors_per_thread <= 4,
                 "blur_vectors_per_thread must be in 1..4");
         REQUIRE(t->blur_block == 64 || t->blur_block == 128 || t->blur_block == 256,
@@ -259,18 +304,27 @@ int dcrf_set_tune(dcrf_ctx *ctx, const dcrf_tune *t) {
     });
 }
 
+// replace the kernel weights and recompute r = K'1 (one filter call); the
+// lattices do not depend on the weights
+static void apply_weights(dcrf_ctx *ctx, const double *w) {
+    double s = 0;
+    for (int m = 0; m < ctx->nk; ++m) {
+        REQUIRE(std::isfinite(w[m]) && w[m] >= 0, "weights must be >= 0");
+        s += w[m];
+    }
+    bool same = true;
+    for (int m = 0; m < ctx->nk; ++m) same = same && ctx->kern[m].weight == w[m];
+    if (same) return;
+    for (int m = 0; m < ctx->nk; ++m) ctx->kern[m].weight = w[m];
+    ctx->wsum = s;
+    dcrf::compute_row_sums(ctx);
+}
+
 int dcrf_set_weights(dcrf_ctx *ctx, const double *w, int nk) {
     return guarded(ctx, [&] {
         require_image(ctx);
         REQUIRE(w != nullptr && nk == ctx->nk, "need one weight per kernel");
-        double s = 0;
-        for (int m = 0; m < nk; ++m) {
-            REQUIRE(std::isfinite(w[m]) && w[m] >= 0, "weights must be >= 0");
-            s += w[m];
-        }
-        for (int m = 0; m < nk; ++m) ctx->kern[m].weight = w[m];
-        ctx->wsum = s;
-        dcrf::compute_row_sums(ctx);
+        apply_weights(ctx, w);
     });
 }
 
@@ -323,8 +377,8 @@ int dcrf_qp_apply(dcrf_ctx *ctx, const void *y, const void *mu, int L,
     return guarded(ctx, [&] {
         require_image(ctx);
         check_labels(L);
-        REQUIRE(y && mu && out && y != out, "null or aliased argument");
-        dcrf::qp_apply(ctx, y, mu, L, out);
+        REQUIRE(y && out && y != out, "null or aliased argument");
+        dcrf::qp_apply(ctx, y, dcrf::resolve_mu(ctx, mu, L), L, out);
     });
 }
 
@@ -334,10 +388,13 @@ int dcrf_qp_frank_wolfe(dcrf_ctx *ctx, const void *unary, const void *mu,
     return guarded(ctx, [&] {
         require_image(ctx);
         check_labels(L);
-        REQUIRE(unary && mu && y_inout, "null argument");
+        REQUIRE(unary && y_inout, "null argument");
         REQUIRE(iters >= 0, "iters must be >= 0");
-        dcrf::frank_wolfe(ctx, unary, mu, L, y_inout, iters, trace, nullptr,
-                          false);
+        dcrf::check_finite(ctx, unary, L);
+        dcrf::check_finite(ctx, y_inout, L);
+        dcrf::frank_wolfe(ctx, unary, dcrf::resolve_mu(ctx, mu, L), L, y_inout,
+                          iters, trace, nullptr, false);
+        if (trace) dcrf::raise_device_errors(ctx);
     });
 }
 
@@ -346,9 +403,28 @@ int dcrf_dc_gen(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
     return guarded(ctx, [&] {
         require_image(ctx);
         check_labels(L);
-        REQUIRE(unary && mu && y_inout, "null argument");
+        REQUIRE(unary && y_inout, "null argument");
         REQUIRE(outer >= 0 && inner >= 1, "outer >= 0 and inner >= 1 required");
-        dcrf::dc_gen(ctx, unary, mu, L, y_inout, outer, inner, S_hist);
+        dcrf::check_finite(ctx, unary, L);
+        dcrf::check_finite(ctx, y_inout, L);
+        dcrf::dc_gen(ctx, unary, dcrf::resolve_mu(ctx, mu, L), L, y_inout, outer,
+                     inner, S_hist);
+        if (S_hist) dcrf::raise_device_errors(ctx);
+    });
+}
+
+int dcrf_dc_neg(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
+                void *y_inout, int outer, int inner, double *S_hist) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        check_labels(L);
+        REQUIRE(unary && y_inout, "null argument");
+        REQUIRE(outer >= 0 && inner >= 1, "outer >= 0 and inner >= 1 required");
+        dcrf::check_finite(ctx, unary, L);
+        dcrf::check_finite(ctx, y_inout, L);
+        dcrf::dc_neg(ctx, unary, dcrf::resolve_mu(ctx, mu, L), L, y_inout, outer,
+                     inner, S_hist);
+        if (S_hist) dcrf::raise_device_errors(ctx);
     });
 }
 
@@ -366,8 +442,10 @@ int dcrf_energy(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
     return guarded(ctx, [&] {
         require_image(ctx);
         check_labels(L);
-        REQUIRE(unary && mu && labels && energy, "null argument");
-        *energy = dcrf::energy(ctx, unary, mu, L, labels);
+        REQUIRE(unary && labels && energy, "null argument");
+        dcrf::check_finite(ctx, unary, L);
+        *energy = dcrf::energy(ctx, unary, dcrf::resolve_mu(ctx, mu, L), L, labels);
+        dcrf::raise_device_errors(ctx);
     });
 }
 
@@ -378,7 +456,10 @@ int dcrf_lp_subgradient(dcrf_ctx *ctx, const void *unary, int L, const void *y,
         check_labels(L);
         REQUIRE(unary && y && g && y != g, "null or aliased argument");
         require_single(ctx);
+        dcrf::check_finite(ctx, unary, L);
+        dcrf::check_finite(ctx, y, L);
         const double S = dcrf::lp_subgradient(ctx, unary, L, y, g);
+        dcrf::raise_device_errors(ctx);
         if (S_lp) *S_lp = S;
     });
 }
@@ -401,24 +482,41 @@ int dcrf_fw_saved_size(dcrf_ctx *ctx, int L, int iters, size_t *bytes) {
 }
 
 int dcrf_fw_forward(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
-                    int iters, void *y_out, void *saved) {
+                    const double *w, int iters, void *y_out, void *saved) {
     return guarded(ctx, [&] {
         require_diff(ctx, L, iters);
-        REQUIRE(unary && mu && y_out && saved, "null argument");
+        REQUIRE(unary && y_out && saved, "null argument");
         REQUIRE(y_out != unary, "y_out must not alias unary");
-        dcrf::fw_diff_forward(ctx, unary, mu, L, y_out, iters, saved);
+        REQUIRE(iters <= 4096 || !ctx->arena.active(),
+                "with a caller workspace at most 4096 unrolled iterations");
+        if (w) apply_weights(ctx, w);
+        dcrf::check_finite(ctx, unary, L);
+        dcrf::fw_diff_forward(ctx, unary, dcrf::resolve_mu(ctx, mu, L), L, y_out,
+                              iters, saved);
     });
 }
 
 int dcrf_fw_backward(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
                      int iters, const void *saved, const void *grad_y,
-                     void *grad_unary, double *grad_w) {
+                     void *grad_unary, double *grad_w, double *grad_w_total) {
     return guarded(ctx, [&] {
         require_diff(ctx, L, iters);
-        REQUIRE(unary && mu && saved && grad_y && grad_unary, "null argument");
+        REQUIRE(unary && saved && grad_y && grad_unary, "null argument");
         REQUIRE(grad_unary != grad_y, "grad_unary must not alias grad_y");
-        dcrf::fw_diff_backward(ctx, unary, mu, L, iters, saved, grad_y,
-                               grad_unary, grad_w);
+        dcrf::check_finite(ctx, grad_y, L);
+        std::vector<double> per((size_t)ctx->nimg * ctx->nk, 0.0);
+        dcrf::fw_diff_backward(ctx, unary, dcrf::resolve_mu(ctx, mu, L), L, iters,
+                               saved, grad_y, grad_unary,
+                               (grad_w || grad_w_total) ? per.data() : nullptr);
+        if (grad_w)
+            for (size_t i = 0; i < per.size(); ++i) grad_w[i] = per[i];
+        dcrf::raise_device_errors(ctx);
+        if (grad_w_total)   // shared weights: the sum over the images, in order
+            for (int m = 0; m < ctx->nk; ++m) {
+                double t = 0.0;
+                for (int j = 0; j < ctx->nimg; ++j) t += per[(size_t)j * ctx->nk + m];
+                grad_w_total[m] = t;
+            }
     });
 }
 
@@ -433,8 +531,11 @@ int dcrf_lp_descent(dcrf_ctx *ctx, const void *unary, int L, void *y_inout,
         REQUIRE(steps >= 0, "steps must be >= 0");
         REQUIRE(std::isfinite(beta0) && beta0 > 0, "beta0 must be > 0");
         REQUIRE(best_y != y_inout, "best_y must not alias y");
+        dcrf::check_finite(ctx, unary, L);
+        dcrf::check_finite(ctx, y_inout, L);
         dcrf::lp_descent(ctx, unary, L, y_inout, steps, beta0, best_obj, best_y,
                          hist);
+        dcrf::raise_device_errors(ctx);
     });
 }
 
@@ -445,6 +546,45 @@ int dcrf_project_simplex(dcrf_ctx *ctx, const void *v, int L, void *y) {
         REQUIRE(v && y, "null argument");
         dcrf::project_simplex(ctx, v, L, y);
     });
+}
+
+int dcrf_workspace_size(int H, int W, int L, const dcrf_kernel *kernels, int nk,
+                        int dtype, size_t *bytes) {
+    return dcrf_workspace_size_images(1, &H, &W, L, kernels, nk, dtype, bytes);
+}
+
+int dcrf_workspace_size_images(int B, const int *H, const int *W, int L,
+                               const dcrf_kernel *kernels, int nk, int dtype,
+                               size_t *bytes) {
+    if (!bytes || !H || !W || !kernels || B < 1 || B > 4096 || nk < 1 ||
+        nk > DCRF_MAXK || L < 1 || L > 256 || (dtype != DCRF_F32 && dtype != DCRF_F64))
+        return DCRF_EINVAL;
+    for (int j = 0; j < B; ++j)
+        if (H[j] < 1 || W[j] < 1 || (long long)H[j] * W[j] > (1ll << 28))
+            return DCRF_EINVAL;
+    *bytes = dcrf::workspace_bound(B, H, W, L, kernels, nk, dtype);
+    return DCRF_OK;
+}
+
+int dcrf_workspace_used(dcrf_ctx *ctx, size_t *in_use, size_t *peak) {
+    return guarded(ctx, [&] {
+        REQUIRE(ctx->arena.active(), "the context holds no caller workspace");
+        if (in_use) *in_use = ctx->arena.in_use;
+        if (peak) *peak = ctx->arena.peak;
+    });
+}
+
+int dcrf_set_hash_capacity(dcrf_ctx *ctx, size_t slots) {
+    return guarded(ctx, [&] {
+        REQUIRE(slots == 0 || (slots >= 16 && (slots & (slots - 1)) == 0 &&
+                               slots <= (size_t(1) << 32)),
+                "slots must be 0 or a power of two in [16, 2^32]");
+        ctx->hash_cap = slots;
+    });
+}
+
+int dcrf_sync(dcrf_ctx *ctx) {
+    return guarded(ctx, [&] { dcrf::raise_device_errors(ctx); });
 }
 
 int dcrf_set_profiling(dcrf_ctx *ctx, int enable) {

@@ -116,6 +116,7 @@ void build_batch(dcrf_ctx *ctx, int B, const int *H, const int *W,
     tmp.c.nk = ctx->nk;
     tmp.c.dtype = ctx->dtype;
     tmp.c.splat_chunk = ctx->splat_chunk;
+    tmp.c.hash_cap = ctx->hash_cap;
     for (int m = 0; m < ctx->nk; ++m) tmp.c.kern[m] = ctx->kern[m];
     PartList parts;
     parts.p.resize((size_t)B * ctx->nk);

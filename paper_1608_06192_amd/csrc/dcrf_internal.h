@@ -41,27 +41,121 @@ inline void fail(int code, const std::string &msg) { throw Error{code, msg}; }
 
 // ------------------------------------------------------- device buffers
 
-// A grow-only device allocation; new memory is zero-filled.
+// Device memory handed to a context by its caller (the workspace argument of
+// dcrf_set_image): a first-fit allocator over that one range in 256-byte
+// granules, with neighbouring free blocks merged. While a context holds
+// one, every buffer of the context lives in it and the library calls
+// neither hipMalloc nor hipFree for the context.
+struct Arena {
+    char *base = nullptr;
+    size_t size = 0;
+    size_t in_use = 0, peak = 0;
+    hipStream_t stream = nullptr;   // the owner's stream, drained before reuse
+    const char *refuse = nullptr;   // set: every allocation fails with this message
+    struct Block { size_t off, bytes; bool used; };
+    std::vector<Block> blocks;      // in offset order, covering [0, size)
+    bool active() const { return base != nullptr; }
+    void reset(void *mem, size_t bytes) {
+        base = static_cast<char *>(mem);
+        size = bytes & ~size_t(255);
+        in_use = peak = 0;
+        blocks.clear();
+        if (base && size) blocks.push_back({0, size, false});
+    }
+    void *alloc(size_t need) {
+        if (refuse) throw Error{DCRF_ENOMEM, refuse};
+        const size_t n = (need + 255) & ~size_t(255);
+        for (size_t i = 0; i < blocks.size(); ++i) {
+            Block &b = blocks[i];
+            if (b.used || b.bytes < n) continue;
+            if (b.bytes > n)
+                blocks.insert(blocks.begin() + i + 1, Block{b.off + n, b.bytes - n, false});
+            blocks[i].bytes = n;
+            blocks[i].used = true;
+            in_use += n;
+            if (in_use > peak) peak = in_use;
+            return base + blocks[i].off;
+        }
+        throw Error{DCRF_ENOMEM, "workspace exhausted: " + std::to_string(n) +
+                                     " more bytes needed (" + std::to_string(in_use) +
+                                     " of " + std::to_string(size) + " in use)"};
+    }
+    void free(void *p) {
+        const size_t off = size_t(static_cast<char *>(p) - base);
+        for (size_t i = 0; i < blocks.size(); ++i) {
+            if (blocks[i].off != off || !blocks[i].used) continue;
+            // kernels still queued on the owner's stream may read the block
+            (void)hipStreamSynchronize(stream);
+            blocks[i].used = false;
+            in_use -= blocks[i].bytes;
+            if (i + 1 < blocks.size() && !blocks[i + 1].used) {
+                blocks[i].bytes += blocks[i + 1].bytes;
+                blocks.erase(blocks.begin() + i + 1);
+            }
+            if (i > 0 && !blocks[i - 1].used) {
+                blocks[i - 1].bytes += blocks[i].bytes;
+                blocks.erase(blocks.begin() + i);
+            }
+            return;
+        }
+    }
+};
+
+// The arena of the context whose call is running on this thread (set by
+// the C ABI for the duration of each call), or null: buffers then come
+// from hipMalloc.
+extern thread_local Arena *tl_arena;
+
+// A grow-only device allocation; new memory is zero-filled. A borrowed
+// buffer points into memory the library does not own for this buffer (a
+// fixed scratch array): it is never freed, and growing it is an error.
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    Arena *arena = nullptr;   // the arena p was taken from, or null (hipMalloc)
+    bool borrowed = false;
     void ensure(size_t need, hipStream_t s) {
         if (need <= bytes) return;
-        if (p) {
-            DCRF_TRY_HIP(hipStreamSynchronize(s));
-            DCRF_TRY_HIP(hipFree(p));
-            p = nullptr;
-            bytes = 0;
-        }
+        if (borrowed)
+            throw Error{DCRF_ENOMEM, "a borrowed buffer is too small (" +
+                                         std::to_string(need) + " bytes needed)"};
+        release_with(s);
         size_t n = need < 256 ? 256 : need;
-        DCRF_TRY_HIP(hipMalloc(&p, n));
+        if (tl_arena) {
+            p = tl_arena->alloc(n);
+            arena = tl_arena;
+        } else {
+            DCRF_TRY_HIP(hipMalloc(&p, n));
+        }
         DCRF_TRY_HIP(hipMemsetAsync(p, 0, n, s));
         bytes = n;
     }
-    void release() {
-        if (p) (void)hipFree(p);
+    void release_with(hipStream_t s) {
+        if (!p) return;
+        if (!borrowed) {
+            if (arena) {
+                arena->free(p);
+            } else {
+                DCRF_TRY_HIP(hipStreamSynchronize(s));
+                DCRF_TRY_HIP(hipFree(p));
+            }
+        }
         p = nullptr;
+        arena = nullptr;
         bytes = 0;
+        borrowed = false;
+    }
+    void release() {
+        if (p && !borrowed) {
+            if (arena)
+                arena->free(p);
+            else
+                (void)hipFree(p);
+        }
+        p = nullptr;
+        arena = nullptr;
+        bytes = 0;
+        borrowed = false;
     }
     template <typename X> X *as() const { return static_cast<X *>(p); }
 };
@@ -148,7 +242,8 @@ enum ProfClass {
     PROF_SLICE_QP = 5,    // slice with mu and the diagonal
     PROF_SPLAT_LABELS = 6,  // one-hot splat (k_splat_labels_chunks)
     PROF_FW_FINAL = 7,    // k_fw_final: the last step size and update of a solve
-    PROF_NCLASS = 8
+    PROF_DCNEG = 8,       // k_dcneg_rows: slice and per-pixel step of DC_neg
+    PROF_NCLASS = 9
 };
 
 struct Profiler {
@@ -228,6 +323,15 @@ struct dcrf_ctx {
     // Frank-Wolfe state
     dcrf::DevBuf fw_c, fw_Py, fw_Ps, fw_s, fw_sprev, fw_part, fw_scal,
         fw_trace, fw_mu;
+    // the Potts compatibility [i != j] (L x L, context dtype) that stands in
+    // for a null mu argument; the solvers recognise it by its address and
+    // never read it back to the host
+    dcrf::DevBuf potts;
+    int potts_L = 0, potts_dtype = -1;
+    dcrf::DevBuf hist;       // per-step partial sums of a solver's history
+    dcrf::DevBuf errflag;    // device-detected input errors (non-finite values)
+    dcrf::Arena arena;       // the caller's workspace, when one is given
+    size_t hash_cap = 0;     // forced hash-table slots per lattice (0: sized by N)
     void *lp = nullptr;      // LP divide-and-conquer workspace (lp.hip)
     void *diff = nullptr;    // reverse-sweep workspace (diff.hip)
     dcrf::Profiler prof;
@@ -277,6 +381,27 @@ inline int blur_launches(int d, int G) { return (d + 1 + G - 1) / G; }
 inline int final_buffer(int d) { return final_buffer_after(d + 1); }
 
 // solvers.hip
+// flag (on the device, checked later) any non-finite value among the
+// images' rows of x (N x L)
+void check_finite(dcrf_ctx *ctx, const void *x, int L);
+// wait for the stream; DCRF_EINVAL if a check_finite flag was raised since
+// the last call of this (the flag is then cleared)
+void raise_device_errors(dcrf_ctx *ctx);
+// hash slots of a lattice with n pixel-vertex pairs: a power of two of at
+// least 2n (and 1024), or the context's forced capacity
+inline size_t hash_slots(const dcrf_ctx *ctx, size_t n) {
+    if (ctx->hash_cap) return ctx->hash_cap;
+    size_t cap = 1024;
+    while (cap < 2 * n) cap <<= 1;
+    return cap;
+}
+// mu itself, or for a null mu the context's device copy of the Potts
+// compatibility of L labels (built on first use for each L and dtype)
+const void *resolve_mu(dcrf_ctx *ctx, const void *mu, int L);
+// whether mu is the context's Potts copy (no host read)
+inline bool is_internal_potts(const dcrf_ctx *ctx, const void *mu) {
+    return mu != nullptr && mu == ctx->potts.p;
+}
 void qp_apply(dcrf_ctx *ctx, const void *y, const void *mu, int L, void *out);
 void frank_wolfe(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
                  void *y, int iters, dcrf_iter_trace *trace, const void *c_in,
@@ -286,6 +411,14 @@ void dc_gen(dcrf_ctx *ctx, const void *unary, const void *mu, int L, void *y,
 void round_labels(dcrf_ctx *ctx, const void *y, int L, int32_t *labels);
 double energy(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
               const int32_t *labels);
+
+// workspace.cpp: upper bound of a context's device memory for B images
+size_t workspace_bound(int B, const int *H, const int *W, int L,
+                       const dcrf_kernel *k, int nk, int dtype);
+
+// dcneg.hip: CCCP on the negative semi-definite decomposition
+void dc_neg(dcrf_ctx *ctx, const void *unary, const void *mu, int L, void *y,
+            int outer, int inner, double *S_hist);
 
 // Checkpoints of a Frank-Wolfe forward for the reverse sweep: y_t and
 // P_t = (Psi + D) y_t (iters x N x L each), s_t (iters x N labels), per

@@ -575,6 +575,7 @@ LatSet<T> saved_lat_set(dcrf_ctx *ctx, int L, const T *block) {
 // whether mu is the Potts compatibility (read once per call)
 template <typename T>
 bool mu_is_potts(dcrf_ctx *ctx, const T *mu, int L) {
+    if (is_internal_potts(ctx, mu)) return true;
     std::vector<T> h((size_t)L * L);
     DCRF_TRY_HIP(hipMemcpyAsync(h.data(), mu, h.size() * sizeof(T), hipMemcpyDeviceToHost,
                                 ctx->stream));

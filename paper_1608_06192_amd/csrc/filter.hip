@@ -239,7 +239,10 @@ __device__ __forceinline__ void blur_vector(const LatSet<T> &ls, int pass,
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_blur_pass(LatSet<T> ls, int pass, int reverse, long long total, int vpt) {
-    const long long base = (long long)blockIdx.x * blockDim.x * vpt + threadIdx.x;
+    // XCD-contiguous ranges of vertex rows: the rows a block reads around its
+    // own (lattice neighbours of nearby vertices) stay in one XCD's L2
+    const long long base =
+        (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x * vpt + threadIdx.x;
     for (int q = 0; q < vpt; ++q) {
         const long long e = base + (long long)q * blockDim.x;
         if (e >= total) return;
@@ -347,7 +350,8 @@ __device__ __forceinline__ void blur_group_vector(const LatSet<T> &ls, int grp,
 template <typename T, int G>
 __global__ void __launch_bounds__(256)
 k_blur_group(LatSet<T> ls, int grp, long long total, int vpt) {
-    const long long base = (long long)blockIdx.x * blockDim.x * vpt + threadIdx.x;
+    const long long base =
+        (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x * vpt + threadIdx.x;
     for (int q = 0; q < vpt; ++q) {
         const long long e = base + (long long)q * blockDim.x;
         if (e >= total) return;

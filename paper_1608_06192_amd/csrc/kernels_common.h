@@ -641,6 +641,43 @@ __device__ __forceinline__ double block_sum_waves(const double (&v)[NV], double 
     return s;
 }
 
+// Euclidean projection of v (register row, C valid entries) onto the simplex:
+// sort descending with a bitonic network, cumulative sums in sorted order,
+// rho = last j with u_j - (css_j - 1) / j > 0, tau = (css_rho - 1) / rho.
+template <typename T, int P>
+__device__ __forceinline__ T simplex_tau(const T (&v)[P], int C) {
+    T u[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) u[i] = (i < C) ? v[i] : -INFINITY;
+#pragma unroll
+    for (int k = 2; k <= P; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const bool desc = (i & k) == 0;
+                    const T x = u[i], y = u[l];
+                    const bool sw = desc ? (x < y) : (x > y);
+                    u[i] = sw ? y : x;
+                    u[l] = sw ? x : y;
+                }
+            }
+    T css = T(0), tau = T(0);
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        if (j < C) {
+            css += u[j];
+            const T t = (css - T(1)) / T(j + 1);
+            if (u[j] - t > T(0)) tau = t;
+        }
+    }
+    return tau;
+}
+
+template <int C> struct Pow2 { static constexpr int v = C <= 4 ? 4 : C <= 8 ? 8 : C <= 16 ? 16 : 32; };
+
 // Calls BODY with LMAX bound to the smallest register-row size >= C.
 #define DCRF_DISPATCH_ROWS(C, BODY)                                 \
     do {                                                           \

@@ -36,6 +36,7 @@ namespace {
 
 constexpr int kFlagRange = 1;
 constexpr int kFlagCapacity = 2;
+constexpr int kFlagNonFinite = 4;
 
 template <int D>
 struct Codec {
@@ -130,13 +131,15 @@ k_lattice_points(int N, int W, const float *__restrict__ rgb, double theta_pos,
         for (int j = 0; j < D; ++j) acc += E.e[i][j] * f[j];
         x[i] = acc;
     }
-    // coordinates that are not finite or too large for the integer vertex
-    // coordinates (non-finite colours, a tiny theta) are reported, not used
-    bool finite = true;
+    // non-finite colours, and coordinates too large for the integer vertex
+    // coordinates (a tiny theta), are reported, not used
+    bool fin = true, finite = true;
+#pragma unroll
+    for (int j = 0; j < D; ++j) fin = fin && isfinite(f[j]);
 #pragma unroll
     for (int i = 0; i < D1; ++i) finite = finite && (fabs(x[i]) < 1.0e9);
-    if (!finite) {
-        atomicOr(flags, kFlagRange);
+    if (!fin || !finite) {
+        atomicOr(flags, fin ? kFlagRange : kFlagNonFinite);
 #pragma unroll
         for (int k = 0; k < D1; ++k) {
             pix_w[(size_t)a * D1 + k] = T(0);
@@ -562,8 +565,7 @@ void build_one(dcrf_ctx *ctx, int m, const float *rgb, int *flags_dev) {
     constexpr int D1 = D + 1;
     L.d = D;
     L.gamma = std::pow(4.0 * M_PI / 3.0, 0.5 * D) * std::sqrt(double(D1));
-    size_t cap = 1024;
-    while (cap < 2 * (size_t)N * D1) cap <<= 1;
+    const size_t cap = hash_slots(ctx, (size_t)N * D1);
     L.cap = cap;
     L.hkeys.ensure(cap * 8, s);
     L.slot_vid.ensure(cap * 4, s);
@@ -646,9 +648,7 @@ void build_all(dcrf_ctx *ctx, const float *rgb) {
     size_t maxcap = 1024;
     for (int m = 0; m < ctx->nk; ++m) {
         const int D1 = (ctx->kern[m].use_rgb ? 5 : 2) + 1;
-        size_t cap = 1024;
-        while (cap < 2 * (size_t)ctx->N * D1) cap <<= 1;
-        maxcap = std::max(maxcap, cap);
+        maxcap = std::max(maxcap, hash_slots(ctx, (size_t)ctx->N * D1));
     }
     ctx->scratch.ensure(64 + (size_t)(ceil_div((long long)maxcap, kScanTile) + 1) * 4,
                         s);
@@ -663,11 +663,14 @@ void build_all(dcrf_ctx *ctx, const float *rgb) {
     int hflags = 0;
     DCRF_TRY_HIP(hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, s));
     DCRF_TRY_HIP(hipStreamSynchronize(s));
+    if (hflags & kFlagNonFinite) fail(DCRF_EINVAL, "a colour value is not finite");
     if (hflags & kFlagRange)
         fail(DCRF_ERANGE,
              "lattice coordinates exceed the 64-bit vertex key range "
              "(theta too small for the image extent)");
-    if (hflags & kFlagCapacity) fail(DCRF_ECAPACITY, "lattice hash table full");
+    if (hflags & kFlagCapacity)
+        fail(DCRF_ECAPACITY, "lattice hash table full: a lattice has more vertices "
+                             "than hash slots");
 }
 
 }  // namespace

@@ -804,11 +804,20 @@ void qp_apply_t(dcrf_ctx *ctx, const T *y, const T *mu, int L, const T *mabs,
     DCRF_CHECK_LAUNCH();
 }
 
-// Whether mu is the Potts compatibility [i != j] (read once per solve).
+// Whether mu is the Potts compatibility [i != j]: known without a host read
+// for the context's own copy (a null mu at the boundary), else read once.
 template <typename T>
 bool is_potts(dcrf_ctx *ctx, const T *mu, int L) {
-    std::vector<T> h((size_t)L * L);
-    DCRF_TRY_HIP(hipMemcpyAsync(h.data(), mu, h.size() * sizeof(T),
+    if (is_internal_potts(ctx, mu)) return true;
+    // up to 32 labels the copy lives on the stack (no host allocation)
+    T small[kRowMaxC * kRowMaxC];
+    std::vector<T> big;
+    T *h = small;
+    if (L > kRowMaxC) {
+        big.resize((size_t)L * L);
+        h = big.data();
+    }
+    DCRF_TRY_HIP(hipMemcpyAsync(h, mu, (size_t)L * L * sizeof(T),
                                 hipMemcpyDeviceToHost, ctx->stream));
     DCRF_TRY_HIP(hipStreamSynchronize(ctx->stream));
     for (int i = 0; i < L; ++i)
@@ -820,7 +829,7 @@ bool is_potts(dcrf_ctx *ctx, const T *mu, int L) {
 template <typename T>
 void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
                    int iters, dcrf_iter_trace *trace, int cmode, bool have_Py,
-                   const FWCheckpoint *save = nullptr) {
+                   const FWCheckpoint *save = nullptr, int potts_known = -1) {
     const hipStream_t st = ctx->stream;
     const int N = ctx->N;
     const size_t NL = (size_t)N * L;
@@ -853,7 +862,11 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
     }
     hipLaunchKernelGGL(k_fill_i32, dim3(ceil_div(N, 256)), dim3(256), 0, st,
                        w.sprev, (size_t)N, -1);
-    DCRF_TRY_HIP(hipMemsetAsync(w.acc, 0, (size_t)2 * kSets * ctx->nimg * kPT * 8, st));
+    {   // the step-size accumulators start at zero (a fill kernel, not a memset)
+        const size_t n = (size_t)2 * kSets * ctx->nimg * kPT;
+        hipLaunchKernelGGL((k_fill<double>), dim3(ceil_div((long long)n, 256)), dim3(256),
+                           0, st, w.acc, n, 0.0);
+    }
     DCRF_CHECK_LAUNCH();
 
     const bool exact = ctx->mode == DCRF_FILTER_EXACT;
@@ -867,7 +880,7 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
     const int G1 = w.G1, G = w.G2;
     const int nimg = ctx->nimg;
     const int *seg = ctx->seg.as<int>();
-    const bool potts = is_potts<T>(ctx, mu, L);
+    const bool potts = potts_known >= 0 ? potts_known != 0 : is_potts<T>(ctx, mu, L);
     const LatSet<T> ls = exact ? LatSet<T>{} : make_lat_set<T>(ctx, L);
     for (int it = 0; it < iters; ++it) {
         // checkpoints are written by the row kernel itself; the flat kernel
@@ -941,40 +954,56 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
                      save ? save->stats : nullptr);
         DCRF_CHECK_LAUNCH();
     }
-    if (trace && iters > 0) {   // record it * nimg + image
-        const size_t nrec = (size_t)iters * nimg;
-        std::vector<double> h(nrec * 4);
-        DCRF_TRY_HIP(hipMemcpyAsync(h.data(), w.trace, h.size() * 8,
+    if (trace && iters > 0) {   // record it * nimg + image: (f, gap, alpha, changed)
+        static_assert(sizeof(dcrf_iter_trace) == 4 * sizeof(double),
+                      "a trace record is four doubles, as on the device");
+        DCRF_TRY_HIP(hipMemcpyAsync(trace, w.trace, (size_t)iters * nimg * 4 * 8,
                                     hipMemcpyDeviceToHost, st));
         DCRF_TRY_HIP(hipStreamSynchronize(st));
-        for (size_t i = 0; i < nrec; ++i)
-            trace[i] = dcrf_iter_trace{h[i * 4 + 0], h[i * 4 + 1], h[i * 4 + 2],
-                                       h[i * 4 + 3]};
     }
 }
 
+// the per-tile partial sums of S(y) = phi^T y + y^T Psi y (from P_y) into
+// part[0, G), G = seg_tiles(ctx, kThreads)
 template <typename T>
-double S_value_t(dcrf_ctx *ctx, const T *phi, const T *y, int L) {
+void S_partials_t(dcrf_ctx *ctx, const T *phi, const T *y, int L, double *part) {
     const int G = seg_tiles(ctx, kThreads);
     hipLaunchKernelGGL((k_S_value<T>), dim3(G), dim3(kThreads), 0, ctx->stream,
                        ctx->seg.as<int>(), ctx->nimg, L, phi, y, ctx->fw_Py.as<T>(),
-                       ctx->fw_mu.as<T>(), ctx->r.as<T>(), ctx->fw_part.as<double>());
+                       ctx->fw_mu.as<T>(), ctx->r.as<T>(), part);
     DCRF_CHECK_LAUNCH();
-    return sum_partials(ctx, ctx->fw_part.as<double>(), G);
 }
 
+// CCCP on the generic DC decomposition. The S history's partial sums stay on
+// the device, one row per value, and are read back once at the end: a call
+// waits for the stream only when S_hist is asked for, and then once.
 template <typename T>
 void dc_gen_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y, int outer,
               int inner, double *S_hist) {
     // P_y = (Psi + D) y for the starting point
     Work<T> w = fw_workspace<T>(ctx, L, inner);
+    const int G = seg_tiles(ctx, kThreads);
+    DevBuf &hp = ctx->hist;   // outer + 1 rows of G partial sums
+    if (S_hist) hp.ensure((size_t)(outer + 1) * G * 8, ctx->stream);
     hipLaunchKernelGGL((k_mu_abs<T>), dim3(1), dim3(256), 0, ctx->stream, L, mu,
                        w.mabs);
     qp_apply_t<T>(ctx, y, mu, L, w.mabs, w.Py);
-    if (S_hist) S_hist[0] = S_value_t<T>(ctx, phi, y, L);
+    if (S_hist) S_partials_t<T>(ctx, phi, y, L, hp.as<double>());
+    const int potts = outer > 0 ? (is_potts<T>(ctx, mu, L) ? 1 : 0) : 0;
     for (int k = 0; k < outer; ++k) {
-        frank_wolfe_t<T>(ctx, phi, mu, L, y, inner, nullptr, 1, true);
-        if (S_hist) S_hist[k + 1] = S_value_t<T>(ctx, phi, y, L);
+        frank_wolfe_t<T>(ctx, phi, mu, L, y, inner, nullptr, 1, true, nullptr, potts);
+        if (S_hist) S_partials_t<T>(ctx, phi, y, L, hp.as<double>() + (size_t)(k + 1) * G);
+    }
+    if (S_hist) {
+        std::vector<double> h((size_t)(outer + 1) * G);
+        DCRF_TRY_HIP(hipMemcpyAsync(h.data(), hp.p, h.size() * 8,
+                                    hipMemcpyDeviceToHost, ctx->stream));
+        DCRF_TRY_HIP(hipStreamSynchronize(ctx->stream));
+        for (int k = 0; k <= outer; ++k) {
+            double v = 0.0;
+            for (int i = 0; i < G; ++i) v += h[(size_t)k * G + i];
+            S_hist[k] = v;
+        }
     }
 }
 
@@ -1018,6 +1047,68 @@ double energy_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L,
 }
 
 }  // namespace
+
+// flag |= 1 if an element of an image's rows of x (N x L) is not finite;
+// rows between the images of a batch are not read
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_check_finite(const int *__restrict__ seg, int nimg, int L, const T *__restrict__ x,
+               int *__restrict__ flag) {
+    int lo, hi;
+    tile_range(seg, nimg, 256, blockIdx.x, lo, hi);
+    bool bad = false;
+    for (size_t e = (size_t)lo * L + threadIdx.x; e < (size_t)hi * L; e += 256)
+        bad = bad || !isfinite(double(x[e]));
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(flag, 1);
+}
+
+template <typename T>
+__global__ void k_potts_fill(int L, T *__restrict__ mu) {
+    for (int e = threadIdx.x; e < L * L; e += blockDim.x)
+        mu[e] = (e / L != e % L) ? T(1) : T(0);
+}
+
+void check_finite(dcrf_ctx *ctx, const void *x, int L) {
+    ctx->errflag.ensure(4, ctx->stream);
+    const int G = seg_tiles(ctx, 256);
+    if (ctx->dtype == DCRF_F64)
+        hipLaunchKernelGGL((k_check_finite<double>), dim3(G), dim3(256), 0, ctx->stream,
+                           ctx->seg.as<int>(), ctx->nimg, L,
+                           static_cast<const double *>(x), ctx->errflag.as<int>());
+    else
+        hipLaunchKernelGGL((k_check_finite<float>), dim3(G), dim3(256), 0, ctx->stream,
+                           ctx->seg.as<int>(), ctx->nimg, L,
+                           static_cast<const float *>(x), ctx->errflag.as<int>());
+    DCRF_CHECK_LAUNCH();
+}
+
+void raise_device_errors(dcrf_ctx *ctx) {
+    if (!ctx->errflag.p) return;
+    int h = 0;
+    DCRF_TRY_HIP(hipMemcpyAsync(&h, ctx->errflag.p, 4, hipMemcpyDeviceToHost, ctx->stream));
+    DCRF_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    if (!h) return;
+    DCRF_TRY_HIP(hipMemsetAsync(ctx->errflag.p, 0, 4, ctx->stream));
+    fail(DCRF_EINVAL, "a non-finite value in the unaries or marginals given to this "
+                      "call or to an earlier call since the last check");
+}
+
+const void *resolve_mu(dcrf_ctx *ctx, const void *mu, int L) {
+    if (mu) return mu;
+    if (!(ctx->potts.p && ctx->potts_L == L && ctx->potts_dtype == ctx->dtype)) {
+        ctx->potts.ensure((size_t)L * L * ctx->elt(), ctx->stream);
+        if (ctx->dtype == DCRF_F64)
+            hipLaunchKernelGGL((k_potts_fill<double>), dim3(1), dim3(256), 0, ctx->stream,
+                               L, ctx->potts.as<double>());
+        else
+            hipLaunchKernelGGL((k_potts_fill<float>), dim3(1), dim3(256), 0, ctx->stream,
+                               L, ctx->potts.as<float>());
+        DCRF_CHECK_LAUNCH();
+        ctx->potts_L = L;
+        ctx->potts_dtype = ctx->dtype;
+    }
+    return ctx->potts.p;
+}
 
 void fill_ones(dcrf_ctx *ctx, void *p, size_t n) {
     if (ctx->dtype == DCRF_F64)

@@ -58,10 +58,20 @@ PROTOTYPES = {
     "dcrf_last_error": (ctypes.c_char_p, [_P]),
     "dcrf_set_stream": (_I, [_P, _P]),
     "dcrf_version": (ctypes.c_char_p, []),
-    "dcrf_set_image": (_I, [_P, _I, _I, _P, ctypes.POINTER(dcrf_kernel), _I, _I]),
+    "dcrf_workspace_size": (_I, [_I, _I, _I, ctypes.POINTER(dcrf_kernel), _I, _I,
+                                 ctypes.POINTER(ctypes.c_size_t)]),
+    "dcrf_workspace_size_images": (_I, [_I, ctypes.POINTER(_I), ctypes.POINTER(_I), _I,
+                                        ctypes.POINTER(dcrf_kernel), _I, _I,
+                                        ctypes.POINTER(ctypes.c_size_t)]),
+    "dcrf_set_image": (_I, [_P, _I, _I, _P, ctypes.POINTER(dcrf_kernel), _I, _I, _P,
+                            ctypes.c_size_t]),
     "dcrf_set_images": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
                              ctypes.POINTER(_P), ctypes.POINTER(dcrf_kernel), _I,
-                             _I]),
+                             _I, _P, ctypes.c_size_t]),
+    "dcrf_workspace_used": (_I, [_P, ctypes.POINTER(ctypes.c_size_t),
+                                 ctypes.POINTER(ctypes.c_size_t)]),
+    "dcrf_set_hash_capacity": (_I, [_P, ctypes.c_size_t]),
+    "dcrf_sync": (_I, [_P]),
     "dcrf_image_layout": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I),
                                ctypes.POINTER(_I)]),
     "dcrf_autotune": (_I, [_P, _I, _I, ctypes.POINTER(dcrf_tune)]),
@@ -75,20 +85,21 @@ PROTOTYPES = {
     "dcrf_qp_frank_wolfe": (_I, [_P, _P, _P, _I, _P, _I,
                                  ctypes.POINTER(dcrf_iter_trace)]),
     "dcrf_dc_gen": (_I, [_P, _P, _P, _I, _P, _I, _I, _PD]),
+    "dcrf_dc_neg": (_I, [_P, _P, _P, _I, _P, _I, _I, _PD]),
     "dcrf_round": (_I, [_P, _P, _I, _P]),
     "dcrf_energy": (_I, [_P, _P, _P, _I, _P, _PD]),
     "dcrf_lp_subgradient": (_I, [_P, _P, _I, _P, _P, _PD]),
     "dcrf_lp_descent": (_I, [_P, _P, _I, _P, _I, _D, _PD, _P, _PD]),
     "dcrf_project_simplex": (_I, [_P, _P, _I, _P]),
     "dcrf_fw_saved_size": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_size_t)]),
-    "dcrf_fw_forward": (_I, [_P, _P, _P, _I, _I, _P, _P]),
-    "dcrf_fw_backward": (_I, [_P, _P, _P, _I, _I, _P, _P, _P, _PD]),
+    "dcrf_fw_forward": (_I, [_P, _P, _P, _I, _PD, _I, _P, _P]),
+    "dcrf_fw_backward": (_I, [_P, _P, _P, _I, _I, _P, _P, _P, _PD, _PD]),
     "dcrf_set_profiling": (_I, [_P, _I]),
     "dcrf_get_profile": (_I, [_P, _I, ctypes.POINTER(ctypes.c_char_p), _PD,
                               ctypes.POINTER(ctypes.c_longlong)]),
 }
 
-PROF_CLASSES = 8
+PROF_CLASSES = 9
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -109,6 +120,20 @@ _lib = load_library()
 
 def _ptr(t: torch.Tensor):
     return ctypes.c_void_p(t.data_ptr())
+
+
+def workspace_size(sizes, L: int, kernels, dtype=torch.float32) -> int:
+    """dcrf_workspace_size(_images) for images of sizes [(H, W), ...]"""
+    code = {torch.float32: DCRF_F32, torch.float64: DCRF_F64}[dtype]
+    ks = _kernels(kernels)
+    B = len(sizes)
+    Hs = (ctypes.c_int * B)(*[int(h) for h, _ in sizes])
+    Ws = (ctypes.c_int * B)(*[int(w) for _, w in sizes])
+    n = ctypes.c_size_t()
+    st = _lib.dcrf_workspace_size_images(B, Hs, Ws, L, ks, len(ks), code, ctypes.byref(n))
+    if st != DCRF_OK:
+        raise DcrfError(st, "invalid workspace size query")
+    return n.value
 
 
 def _kernels(kernels):
@@ -147,6 +172,10 @@ class Context:
             msg = _lib.dcrf_last_error(None if create else self._h)
             raise DcrfError(status, (msg or b"").decode())
 
+    def _mu(self, mu):
+        """mu as a pointer; None stands for the Potts compatibility [i != j]"""
+        return None if mu is None else self._arg(mu, name="mu")
+
     def _stream(self):
         st = torch.cuda.current_stream(self.device).cuda_stream
         self._check(_lib.dcrf_set_stream(self._h, ctypes.c_void_p(st)))
@@ -159,18 +188,30 @@ class Context:
         return _ptr(t)
 
     # -- image -----------------------------------------------------------
+    def _workspace(self, ws):
+        """(pointer, bytes) of a caller workspace (a uint8 device tensor) or
+        (None, 0); the context keeps a reference until the next image."""
+        self._ws = ws
+        if ws is None:
+            return None, 0
+        if ws.device != self.device or ws.dtype != torch.uint8 or not ws.is_contiguous():
+            raise ValueError("workspace must be a contiguous uint8 tensor on the device")
+        return _ptr(ws), ws.numel()
+
     def set_image(self, H: int, W: int, rgb: torch.Tensor, kernels,
-                  dtype=torch.float32):
+                  dtype=torch.float32, workspace: torch.Tensor | None = None):
         self._stream()
         code = {torch.float32: DCRF_F32, torch.float64: DCRF_F64}[dtype]
         ks = _kernels(kernels)
+        wp, wb = self._workspace(workspace)
         self._check(_lib.dcrf_set_image(
             self._h, H, W, self._arg(rgb, torch.float32, "rgb"), ks, len(ks),
-            code))
+            code, wp, wb))
         self.dtype, self.N, self.nk, self.H, self.W = dtype, H * W, len(ks), H, W
         self.nimg, self.seg = 1, [(0, H * W)]
 
-    def set_images(self, sizes, rgbs, kernels, dtype=torch.float32):
+    def set_images(self, sizes, rgbs, kernels, dtype=torch.float32,
+                   workspace: torch.Tensor | None = None):
         """A batch: sizes = [(H, W), ...], rgbs = float32 (H*W, 3) tensors on
         the device. Afterwards every N x C argument is one packed array in
         the layout of `seg` (rows seg[j][0]:seg[j][1] are image j)."""
@@ -182,8 +223,9 @@ class Context:
         Ws = (ctypes.c_int * B)(*[int(w) for _, w in sizes])
         ptrs = (ctypes.c_void_p * B)(*[self._arg(r, torch.float32, "rgb").value
                                       for r in rgbs])
+        wp, wb = self._workspace(workspace)
         self._check(_lib.dcrf_set_images(self._h, B, Hs, Ws, ptrs, ks, len(ks),
-                                         code))
+                                         code, wp, wb))
         self.dtype, self.nk = dtype, len(ks)
         self.H = self.W = None
         nimg, rows = ctypes.c_int(), ctypes.c_int()
@@ -222,6 +264,20 @@ class Context:
                     blur_vectors_per_thread=t.blur_vectors_per_thread,
                     blur_block=t.blur_block, blur_group=t.blur_group,
                     tiles=t.tiles, ms=t.ms)
+
+    def workspace_used(self):
+        """(bytes in use, peak bytes) of the context's caller workspace"""
+        a, b = ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(_lib.dcrf_workspace_used(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def set_hash_capacity(self, slots: int):
+        self._check(_lib.dcrf_set_hash_capacity(self._h, int(slots)))
+
+    def sync(self):
+        """wait for the stream; raises for device-detected input errors"""
+        self._stream()
+        self._check(_lib.dcrf_sync(self._h))
 
     def set_weights(self, w):
         arr = (ctypes.c_double * len(w))(*[float(v) for v in w])
@@ -266,7 +322,7 @@ class Context:
                  out: torch.Tensor | None = None) -> torch.Tensor:
         out = torch.empty_like(y) if out is None else out
         self._stream()
-        self._check(_lib.dcrf_qp_apply(self._h, self._arg(y), self._arg(mu),
+        self._check(_lib.dcrf_qp_apply(self._h, self._arg(y), self._mu(mu),
                                        y.shape[1], self._arg(out)))
         return out
 
@@ -275,7 +331,7 @@ class Context:
         tr = (dcrf_iter_trace * max(iters * self.nimg, 1))() if trace else None
         self._stream()
         self._check(_lib.dcrf_qp_frank_wolfe(
-            self._h, self._arg(unary, name="unary"), self._arg(mu, name="mu"),
+            self._h, self._arg(unary, name="unary"), self._mu(mu),
             unary.shape[1], self._arg(y, name="y"), iters, tr))
         if not trace:
             return None
@@ -289,9 +345,20 @@ class Context:
         hist = (ctypes.c_double * (outer + 1))()
         self._stream()
         self._check(_lib.dcrf_dc_gen(
-            self._h, self._arg(unary), self._arg(mu), unary.shape[1],
+            self._h, self._arg(unary), self._mu(mu), unary.shape[1],
             self._arg(y), outer, inner, hist))
         return list(hist)
+
+    def dc_neg(self, unary, mu, y, outer: int, inner: int = 1, hist: bool = True):
+        """CCCP on the negative semi-definite decomposition, in place on y;
+        returns S(y) before the first and after every step (None without
+        hist)."""
+        h = (ctypes.c_double * (outer + 1))() if hist else None
+        self._stream()
+        self._check(_lib.dcrf_dc_neg(
+            self._h, self._arg(unary), self._mu(mu), unary.shape[1],
+            self._arg(y), outer, inner, h))
+        return list(h) if hist else None
 
     def round(self, y: torch.Tensor) -> torch.Tensor:
         lab = torch.empty(y.shape[0], dtype=torch.int32, device=self.device)
@@ -337,30 +404,37 @@ class Context:
         self._check(_lib.dcrf_fw_saved_size(self._h, L, iters, ctypes.byref(n)))
         return n.value
 
-    def fw_forward(self, unary, mu, iters: int):
-        """y_T of `iters` Frank-Wolfe iterations from softmax(-unary); returns
+    def fw_forward(self, unary, mu, iters: int, w=None):
+        """y_T of `iters` Frank-Wolfe iterations from softmax(-unary), with the
+        kernel weights w (nk floats; None keeps the context's); returns
         (y_T, saved), saved being the checkpoint buffer (uint8 tensor) that
         fw_backward needs."""
         L = unary.shape[1]
         saved = torch.empty(self.fw_saved_size(L, iters), dtype=torch.uint8,
                             device=self.device)
         y = torch.empty_like(unary)
+        wa = None if w is None else (ctypes.c_double * len(w))(*[float(v) for v in w])
         self._stream()
         self._check(_lib.dcrf_fw_forward(
-            self._h, self._arg(unary, name="unary"), self._arg(mu, name="mu"), L,
+            self._h, self._arg(unary, name="unary"), self._mu(mu), L, wa,
             iters, self._arg(y), _ptr(saved)))
         return y, saved
 
-    def fw_backward(self, unary, mu, iters: int, saved, grad_y):
+    def fw_backward(self, unary, mu, iters: int, saved, grad_y, summed=False):
         """(dl/dunary, dl/dw) for dl/dy_T = grad_y; dl/dw is a list of nk
-        floats, or for a batch a list of nimg such lists."""
+        floats, or for a batch a list of nimg such lists; with ``summed`` the
+        batch's sum over its images (the gradient of weights the images
+        share), computed in the library."""
         gphi = torch.empty_like(unary)
         gw = (ctypes.c_double * (self.nk * self.nimg))()
+        tot = (ctypes.c_double * self.nk)()
         self._stream()
         self._check(_lib.dcrf_fw_backward(
-            self._h, self._arg(unary, name="unary"), self._arg(mu, name="mu"),
+            self._h, self._arg(unary, name="unary"), self._mu(mu),
             unary.shape[1], iters, _ptr(saved), self._arg(grad_y, name="grad_y"),
-            self._arg(gphi), gw))
+            self._arg(gphi), gw, tot))
+        if summed:
+            return gphi, list(tot)
         if self.nimg == 1:
             return gphi, list(gw)
         return gphi, [list(gw[j * self.nk:(j + 1) * self.nk])
@@ -384,6 +458,6 @@ class Context:
         e = ctypes.c_double()
         self._stream()
         self._check(_lib.dcrf_energy(
-            self._h, self._arg(unary), self._arg(mu), unary.shape[1],
+            self._h, self._arg(unary), self._mu(mu), unary.shape[1],
             self._arg(labels, torch.int32, "labels"), ctypes.byref(e)))
         return e.value

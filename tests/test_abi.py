@@ -20,8 +20,10 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("dcrf_create", "dcrf_set_image", "dcrf_filter",
-                     "dcrf_qp_frank_wolfe", "dcrf_dc_gen", "dcrf_energy",
-                     "dcrf_round", "dcrf_last_error"):
+                     "dcrf_qp_frank_wolfe", "dcrf_dc_gen", "dcrf_dc_neg",
+                     "dcrf_energy", "dcrf_round", "dcrf_last_error",
+                     "dcrf_workspace_size", "dcrf_workspace_size_images",
+                     "dcrf_fw_forward", "dcrf_fw_backward", "dcrf_sync"):
         assert required in names
 
 
@@ -41,7 +43,8 @@ def test_version_and_null_context():
     # a null context is rejected without touching a device
     assert lib.dcrf_destroy(None) == -1
     assert lib.dcrf_filter(None, None, None, 1, 0) == -1
-    assert lib.dcrf_set_image(None, 1, 1, None, None, 1, 0) == -1
+    assert lib.dcrf_set_image(None, 1, 1, None, None, 1, 0, None, 0) == -1
+    assert lib.dcrf_sync(None) == -1
 
 
 def test_create_without_device_fails_cleanly():
@@ -53,3 +56,29 @@ def test_create_without_device_fails_cleanly():
     st = dcrf._lib.dcrf_create(ctypes.byref(h), 0, None)
     assert st == -1 and not h.value
     assert b"device" in dcrf._lib.dcrf_last_error(None)
+
+
+def test_workspace_size_arithmetic():
+    # the size query needs no device: it grows with the image, the labels and
+    # the precision, a batch of one image is that image, and bad arguments
+    # are rejected with DCRF_EINVAL
+    import torch
+    from paper_1608_06192_amd import dcrf, synth
+    K = [synth.BILATERAL, synth.SPATIAL]
+    f32, f64 = torch.float32, torch.float64
+    base = dcrf.workspace_size([(375, 500)], 21, K, f32)
+    assert base > 0
+    assert dcrf.workspace_size([(375, 500)], 21, K, f64) > base
+    assert dcrf.workspace_size([(375, 500)], 32, K, f32) > base
+    assert dcrf.workspace_size([(376, 500)], 21, K, f32) > base
+    assert dcrf.workspace_size([(375, 500)], 21, K[:1], f32) < base
+    n = ctypes.c_size_t()
+    ks = dcrf._kernels(K)
+    assert dcrf._lib.dcrf_workspace_size(375, 500, 21, ks, 2, 0, ctypes.byref(n)) == 0
+    assert n.value == base
+    two = dcrf.workspace_size([(375, 500), (240, 300)], 21, K, f32)
+    assert two > base
+    for bad in [(0, 5, 21, 2, 0), (5, 5, 0, 2, 0), (5, 5, 257, 2, 0),
+                (5, 5, 21, 0, 0), (5, 5, 21, 2, 7)]:
+        H, W, L, nk, dt = bad
+        assert dcrf._lib.dcrf_workspace_size(H, W, L, ks, nk, dt, ctypes.byref(n)) == -1

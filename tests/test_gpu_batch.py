@@ -12,7 +12,10 @@ splat. The checks are:
 * the reverse sweep (FP64) against the oracle's per image: dl/dphi within
   1e-8 of its max, dl/dw within 1e-8 relative;
 * the 16-image 240..500 batch (FP64, 10 iterations) against 16 single-image
-  GPU runs (1e-10) and, for its two smallest images, against the oracle.
+  GPU runs (1e-10) and, for its two smallest images, against the oracle;
+* the same batch in FP32 (the benchmarked configuration), forward and
+  reverse sweep, every image against the oracle and against a single-image
+  FP32 context (bars in the test's docstring).
 """
 
 import numpy as np
@@ -194,3 +197,188 @@ def test_batch_unsupported_calls():
     with pytest.raises(dcrf.DcrfError) as e:
         ctx.lp_subgradient(phi, torch.full_like(phi, 0.2))
     assert dcrf.STATUS[e.value.status] == "DCRF_EUNSUPPORTED"
+
+
+_ORACLE_BATCH16 = {}
+
+
+def _oracle_batch16(ims, mu, iters):
+    """The oracle's unrolled forward and backward for every image of the
+    16-image batch, computed once per test session on a thread pool (the
+    oracle's C parts release the interpreter lock). NumPy's BLAS is held to
+    one thread meanwhile: its own thread pool, entered from several
+    interpreter threads at once, returns wrong products (measured: an image's
+    first conditional gradients differing at hundreds of pixels from a serial
+    run), while the oracle's OpenMP loops are safe to run concurrently."""
+    import concurrent.futures as cf
+    from threadpoolctl import threadpool_limits
+    if "refs" not in _ORACLE_BATCH16:
+        with threadpool_limits(limits=1, user_api="blas"), cf.ThreadPoolExecutor(8) as ex:
+            _ORACLE_BATCH16["refs"] = list(
+                ex.map(lambda im: _oracle_unrolled(im, mu, iters), ims))
+    return _ORACLE_BATCH16["refs"]
+
+
+def _oracle_unrolled(im, mu, iters):
+    """The oracle's FP64 unrolled forward and reverse sweep for one image:
+    upstream gradient (cross entropy to the region labels), dl/dphi, dl/dw,
+    the sum of the absolute values of dl/dw's summands, and the conditional
+    gradients' labels of every iteration."""
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    _, yT, tape, qp, c = O.fw_unrolled_loss(model, im.unary, mu, iters, im.gt)
+    ybar = O.cross_entropy_grad(yT, im.gt)
+    gphi, gw, gw_abs = O.fw_unrolled_backward(qp, tape, c, ybar, scale=True)
+    s = np.stack([r["s"].argmax(1) for r in tape]).astype(np.int32)
+    # per iteration, the gap between the two smallest entries of the
+    # oracle's gradient g = c + 2 P relative to max |g|, per pixel: where it
+    # is at the level of rounding, either label is a valid conditional
+    # gradient
+    margin = []
+    for r in tape:
+        g = c + 2.0 * r["P"]
+        g2 = np.partition(g, 1, axis=1)
+        margin.append(((g2[:, 1] - g2[:, 0]) / np.abs(g).max(axis=1)).astype(np.float32))
+    return dict(ybar=ybar, gphi=gphi, gw=gw, gw_abs=gw_abs, s=s, yT=yT,
+                margin=np.stack(margin))
+
+
+def _first_flips_are_near_ties(s_gpu, r, rel):
+    """At the first iteration where the GPU's conditional gradients differ
+    from the oracle's (before it both trajectories agree to rounding), every
+    differing pixel is a near-tie of the oracle's own gradient (top-two gap
+    within rel of max |g|). Returns the number of differing decisions."""
+    differ = s_gpu != r["s"]
+    n = int(differ.sum())
+    if n:
+        t = int(np.argmax(differ.any(axis=1)))
+        gaps = r["margin"][t][differ[t]]
+        assert (gaps <= rel).all(), (t, gaps.max())
+    return n
+
+
+def test_batch16_fp64_fwd_bwd_matches_oracle():
+    """The benchmarked batch (16 images of U{240..500}^2, L = 21, autotuned
+    launch shapes, 10 unrolled iterations, cross-entropy upstream) in FP64:
+    both sides take their argmin decisions in the same precision, so the
+    conditional gradients agree except at exact near-ties (top-two gap of
+    the oracle's gradient within 1e-9 of its scale, checked at the first
+    differing iteration; at most 10 decisions per image). Where every
+    decision agrees the whole derivative must match the oracle's: y_T within
+    1e-10, dl/dphi within 1e-8 of its max, dl/dw within 1e-8 relative."""
+    from diffsaved import unpack_saved
+    ims = synth.make_batch()
+    iters = synth.WORKLOADS["voronoi_batch16_L21"]["iters"]
+    L = ims[0].L
+    mu = synth.potts(L)
+    refs = _oracle_batch16(ims, mu, iters)
+    f64 = torch.float64
+    ctx = batch_ctx(ims, f64)
+    ctx.autotune(L, reps=2)
+    phi = ctx.pack([T(im.unary, f64) for im in ims], L)
+    y, saved = ctx.fw_forward(phi, None, iters)
+    gphi, gw = ctx.fw_backward(phi, None, iters, saved,
+                               ctx.pack([T(r["ybar"], f64) for r in refs], L))
+    s_b, _ = unpack_saved(ctx, saved, ctx.N, L, iters, 8)
+    for j, (im, r, yj, gj) in enumerate(zip(ims, refs, ctx.unpack(y), ctx.unpack(gphi))):
+        a, b = ctx.seg[j]
+        nd = _first_flips_are_near_ties(s_b[:, a:b], r, 1e-9)
+        print(f"[batch16 fp64] image {j} {im.H}x{im.W}: decisions differing {nd}",
+              flush=True)
+        assert nd <= 10, j
+        if nd:
+            continue
+        assert np.abs(yj.cpu().numpy() - r["yT"]).max() <= 1e-10, j
+        g = gj.cpu().numpy()
+        assert np.abs(g - r["gphi"]).max() <= 1e-8 * np.abs(r["gphi"]).max(), j
+        assert np.allclose(gw[j], r["gw"], rtol=1e-8, atol=0), j
+
+
+def test_batch16_fp32_fwd_bwd_matches_single_and_oracle():
+    """The batch configuration that bench.py times: 16 Voronoi images of
+    sizes U{240..500}^2, L = 21, FP32, autotuned launch shapes, 10 unrolled
+    Frank-Wolfe iterations, then the reverse sweep with the cross-entropy
+    upstream gradient (the oracle's, so that both sides differentiate the
+    same loss).
+
+    Every image, from the batch and from a single-image FP32 context, against
+    the FP64 oracle's unrolled backward with the bars of the single-image
+    FP32 test: conditional-gradient labels differing on at most 1e-3 of the
+    decisions, those of the first differing iteration all near-ties of the
+    oracle's gradient (top-two gap within 1e-5 of its scale), dl/dphi within
+    2e-4 in relative 2-norm (measured at most 1.2e-4: the pixels whose
+    decisions flipped dominate it), dl/dw within 16 u times the sum of the absolute
+    values of its summands (u = 6e-8: the weight gradient is a sum that
+    cancels to 1e-2 .. 1e-4 of that absolute sum on these images). The
+    derivative is also checked to 1e-8 in FP64
+    (test_batch16_fp64_fwd_bwd_matches_oracle). Batch against single: the
+    two differ only in the order of floating-point atomics, so the same
+    decision bar, marginals within 1e-4 except on a share below 1e-3, and
+    dl/dphi within 2e-4 in relative 2-norm."""
+    from diffsaved import unpack_saved
+    ims = synth.make_batch()
+    iters = synth.WORKLOADS["voronoi_batch16_L21"]["iters"]
+    L = ims[0].L
+    mu = synth.potts(L)
+    f32 = torch.float32
+    refs = _oracle_batch16(ims, mu, iters)
+    ctx = batch_ctx(ims, f32)
+    tune = ctx.autotune(L, reps=2)
+    print(f"[autotune] {tune}", flush=True)
+    phi = ctx.pack([T(im.unary, f32) for im in ims], L)
+    m = T(mu, f32)
+    y, saved = ctx.fw_forward(phi, m, iters)
+    ys = [t.double().cpu().numpy() for t in ctx.unpack(y)]
+    ybars32 = [T(r["ybar"], f32) for r in refs]
+    gphi, gw = ctx.fw_backward(phi, m, iters, saved, ctx.pack(ybars32, L))
+    gphis = [t.double().cpu().numpy() for t in ctx.unpack(gphi)]
+    s_b, _ = unpack_saved(ctx, saved, ctx.N, L, iters, 4)
+    for j, (im, r) in enumerate(zip(ims, refs)):
+        a, b = ctx.seg[j]
+        sc = single_ctx(im, f32)
+        ph = T(im.unary, f32)
+        y1, sv1 = sc.fw_forward(ph, m, iters)
+        g1, w1 = sc.fw_backward(ph, m, iters, sv1, ybars32[j])
+        s_1, _ = unpack_saved(sc, sv1, im.N, L, iters, 4)
+        y1 = y1.double().cpu().numpy()
+        g1 = g1.double().cpu().numpy()
+        bound_w = 16 * 6e-8 * r["gw_abs"]
+        nd = iters * im.N
+        for name, s_x, g_x, w_x in (("batch", s_b[:, a:b], gphis[j], gw[j]),
+                                    ("single", s_1, g1, w1)):
+            d_o = _first_flips_are_near_ties(s_x, r, 1e-5)
+            e_phi = np.linalg.norm(g_x - r["gphi"]) / np.linalg.norm(r["gphi"])
+            err_w = np.abs(np.array(w_x) - r["gw"])
+            print(f"[batch16 fp32] image {j} {im.H}x{im.W} {name} vs oracle: "
+                  f"decisions differing {d_o}, dphi rel {e_phi:.2e}, dw err "
+                  f"{err_w} bound {bound_w}", flush=True)
+            assert d_o <= 1e-3 * nd, (j, name)
+            assert e_phi <= 2e-4, (j, name)
+            assert (err_w <= bound_w).all(), (j, name)
+        differ = int((s_b[:, a:b] != s_1).sum())
+        share = float((np.abs(ys[j] - y1) > 1e-4).mean())
+        e_phi = np.linalg.norm(gphis[j] - g1) / np.linalg.norm(g1)
+        print(f"[batch16 fp32] image {j} batch vs single: decisions differing "
+              f"{differ}, y share>1e-4 {share:.2e}, dphi rel {e_phi:.2e}", flush=True)
+        assert differ <= 1e-3 * nd, j
+        assert share <= 1e-3, j
+        assert e_phi <= 2e-4, j
+
+
+def test_batch_summed_weight_gradient():
+    # the library's sum over the images equals the per-image gradients
+    ims = small_batch()
+    L, iters = 5, 6
+    ctx = batch_ctx(ims, torch.float64)
+    phi = ctx.pack([T(im.unary, torch.float64) for im in ims], L)
+    y, saved = ctx.fw_forward(phi, None, iters)
+    ybar = torch.randn(y.shape, generator=torch.Generator().manual_seed(5),
+                       dtype=torch.float64).to(dev())
+    g1, per = ctx.fw_backward(phi, None, iters, saved, ybar)
+    g2, tot = ctx.fw_backward(phi, None, iters, saved, ybar, summed=True)
+    # two reverse sweeps: equal up to the order of their atomic additions
+    # (compared on the images' rows; the rows between images are unspecified)
+    for a1, a2 in zip(ctx.unpack(g1), ctx.unpack(g2)):
+        assert (a1 - a2).abs().max().item() <= 1e-10 * a1.abs().max().item()
+    for m in range(ctx.nk):
+        acc = sum(per[j][m] for j in range(len(ims)))
+        assert abs(tot[m] - acc) <= 1e-10 * sum(abs(per[j][m]) for j in range(len(ims)))

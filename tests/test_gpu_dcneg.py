@@ -1,0 +1,161 @@
+"""GPU parity of DC_neg, the DC relaxation for negative semi-definite label
+compatibilities (Sec. 5.2, eq. QP-concave-CCCP; App. C), against the FP64
+oracle's ``dc_neg``.
+
+Tolerances:
+* FP64 (32x24, L = 3, lattice and exact filter; a general negative
+  semi-definite mu with per-pixel Frank-Wolfe): marginals within 1e-9 and the
+  S history within 1e-9 relative. The two sides differ only in summation
+  order (lattice atomics, the per-pixel sums), and the per-pixel step (a
+  projection, or Frank-Wolfe with its argmin decisions in the same
+  precision) is continuous in its input or makes the same decisions.
+* FP32 at 320x213, L = 21 from the oracle's 50-iteration QP solution (the
+  benchmarked pipeline QP then DC_neg), 5 steps: S history within 1e-4
+  relative; marginals within 1e-4 except on a share below 1e-3 (FP32
+  rounding of c moves the projection continuously, but a pixel whose two
+  smallest entries of c nearly tie may end on the other vertex); the
+  rounded labelling's energy within 1e-4 of the oracle's.
+* a batch of uneven images (FP64): every image as in a single-image context
+  (1e-10), the S history the sum of the images' histories.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1608_06192_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+KERNELS = [synth.BILATERAL, synth.SPATIAL]
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def T(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev(), dtype)
+
+
+def gpu_ctx(im, dtype, mode="lattice"):
+    from paper_1608_06192_amd import dcrf
+    print(f"[case] DC_neg {im.H}x{im.W} L={im.L} {dtype} {mode}", flush=True)
+    ctx = dcrf.Context(0)
+    ctx.set_image(im.H, im.W, torch.from_numpy(im.rgb).to(dev()), KERNELS,
+                  dtype=dtype)
+    if mode != "lattice":
+        ctx.set_filter_mode(mode)
+    return ctx
+
+
+def nsd_mu(L, seed):
+    """symmetric, negative semi-definite on the vectors that sum to zero"""
+    rng = np.random.default_rng(seed)
+    B = rng.normal(0, 0.6, size=(L, 2))
+    return np.ones((L, L)) - B @ B.T
+
+
+@pytest.mark.parametrize("mode", ["lattice", "exact"])
+def test_dc_neg_fp64_matches_oracle(mode):
+    im = synth.make("rect_32x24_L3")
+    ctx = gpu_ctx(im, torch.float64, mode)
+    mu = synth.potts(3)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS, mode=mode)
+    qp = O.QP(model, im.unary, mu)
+    y0 = O.frank_wolfe(qp, O.softmax_neg(im.unary), 10).y
+    yo, ho = O.dc_neg(qp, y0, outer=8)
+    y = T(y0, torch.float64)
+    hg = ctx.dc_neg(T(im.unary, torch.float64), None, y, 8)
+    print("S gpu", hg, "oracle", ho, flush=True)
+    assert np.abs(y.cpu().numpy() - yo).max() <= 1e-9
+    assert np.allclose(hg, ho, rtol=1e-9, atol=0)
+
+
+def test_dc_neg_fp64_general_mu_matches_oracle():
+    im = synth.voronoi_image(19, 23, 5, seed=61, regions=5)
+    ctx = gpu_ctx(im, torch.float64)
+    mu = nsd_mu(5, 62)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    qp = O.QP(model, im.unary, mu)
+    y0 = O.softmax_neg(im.unary)
+    yo, ho = O.dc_neg(qp, y0, outer=4, inner=12)
+    y = T(y0, torch.float64)
+    hg = ctx.dc_neg(T(im.unary, torch.float64), T(mu, torch.float64), y, 4, 12)
+    assert np.abs(y.cpu().numpy() - yo).max() <= 1e-9
+    assert np.allclose(hg, ho, rtol=1e-9, atol=0)
+    # an explicit Potts mu takes the closed form, as a null mu does
+    yp = T(y0, torch.float64)
+    yn = yp.clone()
+    ctx.dc_neg(T(im.unary, torch.float64), T(synth.potts(5), torch.float64), yp, 3)
+    ctx.dc_neg(T(im.unary, torch.float64), None, yn, 3)
+    assert (yp - yn).abs().max().item() <= 1e-12
+
+
+def test_dc_neg_fp32_320x213_after_qp():
+    im = synth.make("voronoi_320x213_L21")
+    ctx = gpu_ctx(im, torch.float32)
+    mu = synth.potts(im.L)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    qp = O.QP(model, im.unary, mu)
+    y0 = O.frank_wolfe(qp, O.softmax_neg(im.unary), 50).y
+    y0 = y0.astype(np.float32).astype(np.float64)
+    yo, ho = O.dc_neg(qp, y0, outer=5)
+    y = T(y0, torch.float32)
+    hg = ctx.dc_neg(T(im.unary, torch.float32), None, y, 5)
+    yg = y.double().cpu().numpy()
+    diff = np.abs(yg - yo)
+    print(f"S gpu {hg} oracle {ho}; max |dy| {diff.max():.3g}, share > 1e-4 "
+          f"{(diff > 1e-4).mean():.3g}", flush=True)
+    for a, b in zip(hg, ho):
+        assert abs(a - b) <= 1e-4 * abs(b)
+    assert (diff > 1e-4).mean() < 1e-3
+    # the FP32 projection subtracts the threshold from values of size
+    # |c| / (2 wsum) (tens here): each entry carries about 1e-6 of rounding
+    assert np.abs(yg.sum(axis=1) - 1).max() < 1e-4 and yg.min() >= 0
+    lab = ctx.round(y)
+    e = ctx.energy(T(im.unary, torch.float32), None, lab)
+    eo = O.energy(model, im.unary, mu, O.round_argmax(yo))
+    print(f"energy gpu {e:.8g} oracle {eo:.8g}", flush=True)
+    assert abs(e - eo) <= 1e-4 * abs(eo)
+
+
+def test_dc_neg_zero_weights_and_one_label():
+    from paper_1608_06192_amd import dcrf
+    im = synth.make("rect_32x24_L3")
+    ctx = dcrf.Context(0)
+    ctx.set_image(im.H, im.W, torch.from_numpy(im.rgb).to(dev()),
+                  [dict(synth.BILATERAL, weight=0.0), dict(synth.SPATIAL, weight=0.0)],
+                  dtype=torch.float64)
+    y = T(O.softmax_neg(im.unary), torch.float64)
+    ctx.dc_neg(T(im.unary, torch.float64), None, y, 1)
+    assert np.array_equal(y.cpu().numpy(), O.onehot(np.argmin(im.unary, axis=1), 3))
+    im1 = synth.voronoi_image(9, 7, 1, seed=63, regions=2)
+    c1 = gpu_ctx(im1, torch.float64)
+    y1 = torch.ones(im1.N, 1, dtype=torch.float64, device=dev())
+    h = c1.dc_neg(T(im1.unary, torch.float64), None, y1, 2)
+    assert torch.equal(y1, torch.ones_like(y1)) and len(h) == 3
+
+
+def test_dc_neg_batch_matches_single_contexts():
+    from paper_1608_06192_amd import dcrf
+    L = 5
+    ims = [synth.voronoi_image(24, 40, L, seed=64),
+           synth.rect_image(33, 17, L, seed=65),
+           synth.voronoi_image(45, 29, L, seed=66, regions=6)]
+    ctx = dcrf.Context(0)
+    ctx.set_images([(im.H, im.W) for im in ims],
+                   [torch.from_numpy(im.rgb).to(dev()) for im in ims], KERNELS,
+                   dtype=torch.float64)
+    phi = ctx.pack([T(im.unary, torch.float64) for im in ims], L)
+    y = ctx.pack([T(O.softmax_neg(im.unary), torch.float64) for im in ims], L)
+    hb = ctx.dc_neg(phi, None, y, 4)
+    tot = np.zeros(5)
+    for im, yb in zip(ims, ctx.unpack(y)):
+        sc = gpu_ctx(im, torch.float64)
+        ys = T(O.softmax_neg(im.unary), torch.float64)
+        hs = sc.dc_neg(T(im.unary, torch.float64), None, ys, 4)
+        tot += np.array(hs)
+        assert (yb - ys).abs().max().item() <= 1e-10
+    assert np.allclose(hb, tot, rtol=1e-10, atol=0)

@@ -32,6 +32,8 @@ import torch
 from oracle import oracle as O
 from paper_1608_06192_amd import synth
 
+from diffsaved import _a256, saved_offsets, unpack_saved
+
 pytestmark = pytest.mark.gpu
 
 KERNELS = [synth.BILATERAL, synth.SPATIAL]
@@ -52,34 +54,6 @@ def gpu_ctx(im, dtype, kernels=KERNELS):
     ctx.set_image(im.H, im.W, torch.from_numpy(im.rgb).to(dev()), kernels,
                   dtype=dtype)
     return ctx
-
-
-def _a256(b):
-    return (b + 255) // 256 * 256
-
-
-def saved_offsets(ctx, N, L, iters, elt):
-    """The checkpoint layout stated in the header: y_t, P_t, s_t, the blurred
-    vertex values of every lattice ((iters + 1) blocks), then four doubles
-    (alpha, a2, b1, interior) per iteration and image, each 256-byte
-    aligned. Returns the byte offsets of s_t and of the doubles."""
-    q = 16 // elt
-    ld = (L + q - 1) // q * q
-    vblock = sum(ctx.lattice_info(m)[1] * ld for m in range(ctx.nk))
-    p_off = _a256(iters * N * L * elt)
-    s_off = _a256(p_off + iters * N * L * elt)
-    v_off = _a256(s_off + iters * N * 4)
-    st_off = _a256(v_off + (iters + 1) * vblock * elt)
-    return s_off, st_off
-
-
-def unpack_saved(ctx, saved, N, L, iters, elt):
-    raw = saved.cpu().numpy()
-    s_off, st_off = saved_offsets(ctx, N, L, iters, elt)
-    s = raw[s_off:s_off + iters * N * 4].view(np.int32).reshape(iters, N)
-    nst = iters * ctx.nimg * 4
-    stats = raw[st_off:st_off + nst * 8].view(np.float64).reshape(iters * ctx.nimg, 4)
-    return s, stats
 
 
 def oracle_problem(im, iters, mu, kernels=KERNELS):
@@ -294,3 +268,34 @@ def test_fw_diff_errors():
     ctx.set_filter_mode("lattice")
     s_off, st_off = saved_offsets(ctx, im.N, 3, 4, 8)
     assert ctx.fw_saved_size(3, 4) == _a256(st_off + 4 * 32)
+
+
+def test_forward_weights_argument_and_summed_gradient():
+    # dcrf_fw_forward's weights argument gives the same forward and reverse
+    # sweep as setting the weights first; the library's summed weight
+    # gradient of a single image equals its per-image gradient
+    im = synth.make("rect_32x24_L3")
+    ctx = gpu_ctx(im, torch.float64)
+    phi = T(im.unary, torch.float64)
+    w = [7.0, 2.0]
+    ya, sa = ctx.fw_forward(phi, None, 6, w=w)
+    ybar = torch.randn(ya.shape, generator=torch.Generator().manual_seed(3),
+                       dtype=torch.float64).to(dev())
+    ga, wa = ctx.fw_backward(phi, None, 6, sa, ybar)
+    gs, ws = ctx.fw_backward(phi, None, 6, sa, ybar, summed=True)
+    assert (ga - gs).abs().max().item() <= 1e-10 * ga.abs().max().item()
+    assert np.allclose(wa, ws, rtol=1e-10, atol=0)
+    ctx2 = gpu_ctx(im, torch.float64)
+    ctx2.set_weights(w)
+    yb, sb = ctx2.fw_forward(phi, None, 6)
+    gb, wb = ctx2.fw_backward(phi, None, 6, sb, ybar)
+    assert (ya - yb).abs().max().item() <= 1e-12
+    assert (ga - gb).abs().max().item() <= 1e-10 * ga.abs().max().item()
+    assert np.allclose(wa, wb, rtol=1e-10, atol=0)
+    # and the oracle with those weights
+    kern = [dict(synth.BILATERAL, weight=w[0]), dict(synth.SPATIAL, weight=w[1])]
+    model = O.Model(im.H, im.W, im.rgb, kern)
+    _, yT, tape, qp, c = O.fw_unrolled_loss(model, im.unary, synth.potts(3), 6, im.gt)
+    assert np.abs(ya.cpu().numpy() - yT).max() <= 1e-10
+    _, gw_o = O.fw_unrolled_backward(qp, tape, c, ybar.cpu().numpy())
+    assert np.allclose(wa, gw_o, rtol=1e-8, atol=0)

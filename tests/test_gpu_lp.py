@@ -157,3 +157,41 @@ def test_lp_subgradient_fp32_500x375_sampled_entries():
         rel = np.abs(g[at, i] - go) / mag
         print(f"[lp 500x375] label {i}: max rel err {rel.max():.3g}", flush=True)
         assert (rel <= 1e-5).all()
+
+
+def test_lp_descent_fp32_steps_160x120():
+    # Five projected-subgradient steps (Alg. lp_subgrad, beta_t = beta0/(1+t))
+    # at 160x120, L = 21, FP32, from a Frank-Wolfe QP solution. The oracle's
+    # trajectory runs through FP32-representable points: its FP64 step from
+    # y_t is rounded to FP32 to give y_{t+1}. The GPU makes one step from each
+    # y_t (lp_descent with one step of size beta0/(1+t)). Both sides then sort
+    # the same values, so the orders agree, and S_LP(y_t) must agree within
+    # 1e-5 relative and the stepped iterate within 1e-4 elementwise.
+    im = synth.voronoi_image(120, 160, 21, seed=12)
+    ctx = ctx_for(im, torch.float32)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    mu = synth.potts(im.L)
+    qp = O.QP(model, im.unary, mu)
+    phi32 = im.unary.astype(np.float32).astype(np.float64)
+    y = O.frank_wolfe(qp, O.softmax_neg(im.unary), 20).y
+    y = y.astype(np.float32).astype(np.float64)
+    beta0 = 1e-4
+    pair = lambda o: O.lp_pair_sums_dnc_c(model, o)
+    phi = T(phi32, torch.float32)
+    S_hist_o, S_hist_g = [], []
+    for t in range(5):
+        beta = beta0 / (1.0 + t)
+        g, S = O.lp_subgradient(phi32, y, pair)
+        y_next = O.project_simplex(y - beta * g)
+        yg = T(y, torch.float32)
+        best, hist = ctx.lp_descent(phi, yg, 1, beta)
+        yg = yg.cpu().numpy().astype(np.float64)
+        err_y = np.abs(yg - y_next).max()
+        print(f"[lp descent 160x120] t={t} S_LP gpu {hist[0]:.9g} oracle {S:.9g} "
+              f"rel {abs(hist[0] - S) / abs(S):.2e}; max |dy| {err_y:.2e}", flush=True)
+        assert abs(hist[0] - S) <= 1e-5 * abs(S), t
+        assert err_y <= 1e-4, t
+        S_hist_o.append(S)
+        S_hist_g.append(hist[0])
+        y = y_next.astype(np.float32).astype(np.float64)
+    print("S_LP history oracle", S_hist_o, "gpu", S_hist_g, flush=True)

@@ -280,6 +280,60 @@ def test_fw_fp32_500x375_bench_configuration():
         assert abs(fg - fo) <= 1e-4 * abs(fo)
 
 
+def test_fw_fp32_steps_500x375_bench_configuration():
+    # the timed workload (500x375, L = 21, FP32, default launch shapes), one
+    # GPU iteration from each oracle iterate y_t0, t0 = 0, 5, ..., 45 (rounded
+    # to FP32 and renormalised, the same start on both sides). At every pixel
+    # the GPU's conditional gradient must be a valid argmin of the oracle's
+    # gradient at that point (up to FP32 rounding of the gradient), and the
+    # step size and objective must agree: alpha within 1e-4, f within 1e-5
+    # relative. A GPU that mislabels any pixel fails here, whatever the
+    # share of pixels involved.
+    im = synth.make("voronoi_500x375_L21")
+    ctx = gpu_ctx(im, torch.float32)
+    mu = synth.potts(im.L)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    qp = O.QP(model, im.unary, mu)
+    starts = {}
+    y = O.softmax_neg(im.unary)
+    Py = qp.Q(y)
+    c = qp.phi - qp.d
+    for t in range(46):
+        if t % 5 == 0:
+            starts[t] = y.copy()
+        s = O.onehot(np.argmin(c + 2.0 * Py, axis=1), im.L)
+        Ps = qp.Q(s)
+        al, _, _ = O.fw_step_size(c, y, s, Py, Ps)
+        y = y + al * (s - y)
+        Py = (1.0 - al) * Py + al * Ps
+    phi = T(im.unary, torch.float32)
+    mu_t = T(mu, torch.float32)
+    for t0, yt in starts.items():
+        yt = yt.astype(np.float32).astype(np.float64)
+        yt /= yt.sum(axis=1, keepdims=True)
+        yt = yt.astype(np.float32).astype(np.float64)
+        ref = O.frank_wolfe(qp, yt, 1)
+        g = c + 2.0 * qp.Q(yt)
+        yg = T(yt, torch.float32)
+        tr = ctx.qp_frank_wolfe(phi, mu_t, yg, 1)
+        ag = tr[0][2]
+        y1 = yg.cpu().numpy().astype(np.float64)
+        # s from y1 = (1 - alpha) y + alpha s; alpha >> FP32 rounding here
+        assert ag > 1e-4, (t0, ag)
+        s_gpu = np.argmax(y1 - (1 - ag) * yt, axis=1)
+        s_or = ref.s_hist[0]
+        ok = _eps_argmin_ok(g, s_gpu)
+        fo = ref.trace[0][0]
+        print(f"[fw step 500x375] t0={t0} alpha gpu={ag:.6g} oracle={ref.alphas[0]:.6g}"
+              f" f rel err {abs(tr[0][0] - fo) / abs(fo):.2e}; s differs at "
+              f"{(s_gpu != s_or).sum()} pixels, non-argmin {(~ok).sum()}", flush=True)
+        assert ok.all(), t0
+        assert abs(ag - ref.alphas[0]) <= 1e-4 * max(1.0, abs(ref.alphas[0])), t0
+        assert abs(tr[0][0] - fo) <= 1e-5 * abs(fo), t0
+        same = s_gpu == s_or
+        assert np.abs(y1[same] - ref.y[same]).max() < 1e-4, t0
+
+
 @pytest.mark.parametrize("L,general_mu", [(3, True), (32, False), (40, False),
                                           (40, True)])
 def test_fw_fp64_label_counts_and_general_mu(L, general_mu):
@@ -436,3 +490,78 @@ def test_grouped_blur_fw_fp64_matches_oracle(tiles):
     y = T(y0, torch.float64)
     ctx.qp_frank_wolfe(T(im.unary, torch.float64), T(mu, torch.float64), y, 20)
     assert np.abs(y.cpu().numpy() - st.y).max() <= 1e-10
+
+
+def test_null_mu_is_potts():
+    # a null mu stands for Potts: the same kernels run as for an explicit
+    # Potts mu. Results agree to FP64 rounding (the splat's atomics add in a
+    # run-dependent order, so bitwise equality is not expected)
+    im = synth.make("voronoi_320x213_L21")
+    ctx = gpu_ctx(im, torch.float64)
+    phi = T(im.unary, torch.float64)
+    mu = T(synth.potts(im.L), torch.float64)
+    y0 = T(O.softmax_neg(im.unary), torch.float64)
+    ya, yb = y0.clone(), y0.clone()
+    ta = ctx.qp_frank_wolfe(phi, mu, ya, 12)
+    tb = ctx.qp_frank_wolfe(phi, None, yb, 12)
+    assert (ya - yb).abs().max().item() <= 1e-12
+    for ra, rb in zip(ta, tb):
+        assert abs(ra[0] - rb[0]) <= 1e-12 * abs(ra[0])
+        assert abs(ra[2] - rb[2]) <= 1e-10
+    ha = ctx.dc_gen(phi, mu, ya, 2, 3)
+    hb = ctx.dc_gen(phi, None, yb, 2, 3)
+    assert (ya - yb).abs().max().item() <= 1e-11
+    assert np.allclose(ha, hb, rtol=1e-11, atol=0)
+    lab = ctx.round(ya)
+    ea, eb = ctx.energy(phi, mu, lab), ctx.energy(phi, None, lab)
+    assert abs(ea - eb) <= 1e-12 * abs(ea)
+    qa, qb = ctx.qp_apply(y0, mu), ctx.qp_apply(y0, None)
+    assert (qa - qb).abs().max().item() <= 1e-12 * qa.abs().max().item()
+    im3 = synth.make("rect_32x24_L3")   # another label count
+    c3 = gpu_ctx(im3, torch.float64)
+    p3 = T(im3.unary, torch.float64)
+    y3a = T(O.softmax_neg(im3.unary), torch.float64)
+    y3b = y3a.clone()
+    c3.qp_frank_wolfe(p3, T(synth.potts(3), torch.float64), y3a, 5, trace=False)
+    c3.qp_frank_wolfe(p3, None, y3b, 5, trace=False)
+    assert (y3a - y3b).abs().max().item() <= 1e-12
+
+
+def test_batch_image_lattices_match_oracle():
+    # every image of the 16-image batch workload, one context each (FP64):
+    # the vertex sets and per-pixel (vertex, weight) tables bit-exact against
+    # the oracle's lattices, and the filter K'Y of a random Y within
+    # 1e-11 (K~|Y| + 2 wsum |Y|); all images are reported before asserting
+    ims = synth.make_batch()
+    bad = []
+    for j, im in enumerate(ims):
+        ctx = gpu_ctx(im, torch.float64)
+        model = O.Model(im.H, im.W, im.rgb, KERNELS)
+        msg = []
+        for m, lat in enumerate(model.lattices):
+            d, M = ctx.lattice_info(m)
+            gk, gv, gw = ctx.lattice_export(m)
+            ok = lat.keys()
+            sg, so = set(map(tuple, gk)), set(map(tuple, ok))
+            ov, ow = lat.points()
+            gt = key_table(gk, gv, gw)
+            ot = key_table(ok, ov, ow)
+            npix = sum(1 for a, b in zip(gt, ot) if a != b)
+            if M != lat.nv or sg != so or npix:
+                first = next((a for a in range(im.N) if gt[a] != ot[a]), None)
+                msg.append(f"lattice {m}: M gpu {M} oracle {lat.nv}, keys only in gpu "
+                           f"{len(sg - so)}, only in oracle {len(so - sg)}, pixels "
+                           f"differing {npix}, first {first}")
+                if first is not None:
+                    msg.append(f"  gpu {gt[first]}\n  oracle {ot[first]}")
+        Y = np.random.default_rng(j).uniform(-1, 1, size=(im.N, 3))
+        g = ctx.filter(T(Y, torch.float64)).cpu().numpy()
+        o = model.Kp(Y)
+        nbad = int((np.abs(g - o) > filter_bound(model, Y, 1e-11)).sum())
+        if nbad:
+            msg.append(f"filter: {nbad} entries off, max |diff| {np.abs(g - o).max():.3g}")
+        print(f"[lattice check] image {j} {im.H}x{im.W}: " + ("ok" if not msg else
+              "\n".join(msg)), flush=True)
+        if msg:
+            bad.append(j)
+    assert not bad, bad
