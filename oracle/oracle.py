@@ -684,6 +684,62 @@ def lp_descent(phi: np.ndarray, y0: np.ndarray, steps: int, beta0: float,
     return y, best, best_y, hist
 
 
+def kt_round(y: np.ndarray, round_label: np.ndarray, round_theta: np.ndarray):
+    """Kleinberg and Tardos's rounding of an LP point for the uniform metric,
+    which is the Potts model. Sec. 6 cites it for the factor-2 bound of the
+    LP relaxation without restating it.
+
+    Rounds r = 0, 1, ... draw a label i_r and a threshold theta_r uniform in
+    [0, 1) (here given, so that both sides use the same draws). Every pixel
+    still without a label takes i_r if y_a(i_r) > theta_r, so P(x_a = i) =
+    y_a(i) and a pair is separated with probability at most
+    sum_i |y_a(i) - y_b(i)|: the expected energy is at most phi^T y plus twice
+    the LP's pairwise term. Reading: the comparison is strict (a label of
+    marginal 0 is never taken) and made in y's precision; pixels left after
+    the last round take the argmax of y (lowest label on ties), and their
+    count is returned.
+    """
+    y = np.asarray(y)
+    N = y.shape[0]
+    th = np.asarray(round_theta).astype(y.dtype)
+    x = np.full(N, -1, dtype=np.int32)
+    for i, t in zip(np.asarray(round_label), th):
+        free = x < 0
+        if not free.any():
+            break
+        x[free & (y[:, i] > t)] = i
+    left = x < 0
+    x[left] = np.argmax(y[left], axis=1)
+    return x, int(left.sum())
+
+
+def present_labels(y: np.ndarray, tau: float) -> np.ndarray:
+    """The labels whose marginal exceeds tau at some pixel: the "labels
+    present in the solutions provided by other methods" to which Sec. 7
+    suggests restricting the LP (App. I discards labels of very small
+    probability the same way)."""
+    return np.nonzero(np.asarray(y).max(axis=0) > tau)[0].astype(np.int32)
+
+
+def lp_descent_subset(phi: np.ndarray, y0: np.ndarray, subset, steps: int,
+                      beta0: float, pair_sums):
+    """Alg. lp_subgrad restricted to the labels of ``subset`` (Sec. 7): the
+    other labels are fixed at 0, which leaves their terms of eq. potts-lp at
+    0, so the restricted objective is the full one at the scattered point.
+    Reading: the start is the projection of y0's columns of the subset onto
+    the simplex. Returns the scattered last y, the best S_LP, the scattered
+    best y and the S_LP history."""
+    S = np.asarray(subset)
+    ys0 = project_simplex(_f64(y0)[:, S])
+    ys, best, best_ys, hist = lp_descent(_f64(phi)[:, S], ys0, steps, beta0,
+                                         pair_sums)
+    y = np.zeros(np.shape(y0))
+    y[:, S] = ys
+    by = np.zeros(np.shape(y0))
+    by[:, S] = best_ys
+    return y, best, by, hist
+
+
 # ---------------------------------------------------------------------------
 # Differentiation of unrolled Frank-Wolfe (reverse mode, hand derived)
 # ---------------------------------------------------------------------------

@@ -408,6 +408,78 @@ def test_lp_descent_approaches_lp_optimum_and_two_label_tightness():
         assert best - opt < 2e-2 * max(1.0, abs(opt))
 
 
+def _kt_draws(R, L, seed):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, L, size=R).astype(np.int32), rng.random(R)
+
+
+def test_kt_round_integral_points_and_fallback():
+    # an integral y is returned as its labelling; without rounds every pixel
+    # takes the argmax and is counted as left over
+    rng = np.random.default_rng(0)
+    x = rng.integers(0, 4, size=50)
+    lab, th = _kt_draws(400, 4, 1)
+    got, left = O.kt_round(O.onehot(x, 4), lab, th)
+    assert left == 0 and np.array_equal(got, x)
+    y = synth.random_simplex_points(50, 4, 2, 0.3)
+    got, left = O.kt_round(y, lab[:0], th[:0])
+    assert left == 50 and np.array_equal(got, O.round_argmax(y))
+
+
+def test_kt_round_marginals_and_pairwise_bound():
+    # Monte Carlo over independent draws: P(x_a = i) = y_a(i) (labels of
+    # marginal 0 never taken), and the expected energy is at most
+    # phi^T y + 2 (the LP's pairwise term), the bound behind the factor 2
+    model, phi = tiny_problem(N=6, L=3, seed=31)
+    K = model.dense_K()
+    mu = synth.potts(3)
+    y = synth.random_simplex_points(6, 3, 5, 0.4)
+    n = 20000
+    counts = np.zeros((6, 3))
+    E = np.empty(n)
+    for k in range(n):
+        lab, th = _kt_draws(120, 3, 1000 + k)
+        x, left = O.kt_round(y, lab, th)
+        assert left == 0
+        counts[np.arange(6), x] += 1
+        E[k] = O.energy_dense(K, phi, mu, x)
+    freq = counts / n
+    sigma = np.sqrt(np.maximum(y * (1 - y), 1e-12) / n)
+    assert (np.abs(freq - y) <= 5 * sigma + 1e-12).all()
+    assert (freq[y == 0] == 0).all()
+    unary = float((phi * y).sum())
+    pair = O.S_LP_dense(K, phi, y) - unary
+    assert E.mean() <= unary + 2 * pair + 5 * E.std() / np.sqrt(n)
+
+
+def test_present_labels_and_subset_lp():
+    # the labels present in a labelling; the LP restricted to all labels is
+    # the plain LP; a proper subset keeps the other labels at 0 and its S_LP
+    # history is the full problem's S_LP at the scattered points
+    rng = np.random.default_rng(3)
+    x = rng.choice([0, 2, 3], size=12)
+    assert np.array_equal(O.present_labels(O.onehot(x, 5), 0.5), np.unique(x))
+    model, phi = tiny_problem(N=12, L=4, seed=33)
+    K = model.dense_K()
+    pair = lambda o: O.lp_pair_sums_brute(K, o)
+    y0 = synth.random_simplex_points(12, 4, 7, 0.0)
+    ya, ba, _, ha = O.lp_descent(phi, y0, 4, 0.05, pair)
+    yb, bb, _, hb = O.lp_descent_subset(phi, y0, [0, 1, 2, 3], 4, 0.05, pair)
+    assert np.allclose(ya, yb, rtol=0, atol=1e-14) and np.allclose(ha, hb, rtol=1e-14)
+    S = [1, 3]
+    ys, best, by, hs = O.lp_descent_subset(phi, y0, S, 5, 0.05, pair)
+    assert (ys[:, [0, 2]] == 0).all() and (by[:, [0, 2]] == 0).all()
+    assert np.abs(ys.sum(axis=1) - 1).max() < 1e-12
+    y = O.project_simplex(y0[:, S])
+    for t in range(5):
+        full = np.zeros_like(y0)
+        full[:, S] = y
+        _, S_full = O.lp_subgradient(phi, full, pair)
+        assert abs(S_full - hs[t]) <= 1e-12 * abs(S_full)
+        g, _ = O.lp_subgradient(phi[:, S], y, pair)
+        y = O.project_simplex(y - 0.05 / (1 + t) * g)
+
+
 def test_simplex_projection_kkt_and_bisection():
     rng = np.random.default_rng(14)
     V = rng.normal(0, 2, size=(200, 21))
