@@ -268,6 +268,29 @@ int dcrf_qp_frank_wolfe(dcrf_ctx *ctx, const void *unary, const void *mu,
                         int L, void *y_inout, int iters,
                         dcrf_iter_trace *trace);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that keep the allocator out of their steady state):
+ * dcrf_qp_frank_wolfe with the same arguments and results, which allocates
+ * nothing. The solve's per-call buffers (linear term, P_y, P_s, conditional
+ * gradients, partial sums, step accumulators, trace, the Potts copy of mu
+ * and each lattice's vertex values) live in one fixed device array of the
+ * library, dcrf_noalloc_scratch_bytes() bytes (64 MiB) per device, held
+ * until the process ends; everything else it reads was built by
+ * dcrf_set_image. Limits: lattice filter mode, L <= 32, iters <= 4096, and
+ * a solve that fits the array (about 3 N L values plus the vertex values:
+ * 500 x 375 with 21 labels in FP32 fits); otherwise DCRF_EINVAL or
+ * DCRF_EUNSUPPORTED, with nothing allocated. A launch shape whose blur tables
+ * were never built (a dcrf_set_tune without a later filter call) gives
+ * DCRF_ENOMEM instead of allocating them. Every call on one device shares
+ * the array, so calls that overlap on a device (other streams or threads)
+ * race; consecutive calls on one stream are safe. */
+int dcrf_qp_frank_wolfe_noalloc(dcrf_ctx *ctx, const void *unary, const void *mu,
+                                int L, void *y_inout, int iters,
+                                dcrf_iter_trace *trace);
+
+/* *bytes = the size of the allocation-free solve's device array. */
+int dcrf_noalloc_scratch_bytes(size_t *bytes);
+
 /* Generic DC relaxation by CCCP (Sec. 5.1, Alg. cccp, eq. cccp-qp): `outer`
  * steps, each minimising phi^T y - 2 (d * y^k)^T y + y^T (Psi + D) y with
  * `inner` warm-started Frank-Wolfe iterations. S_hist: (host) outer+1 values

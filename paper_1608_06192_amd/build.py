@@ -43,6 +43,7 @@ SOURCES = {
     "batch.hip": [],
     "tiles.hip": [],
     "dcneg.hip": [],
+    "noalloc.hip": [],
     "abi.cpp": ["-x", "hip"],
     "workspace.cpp": ["-x", "hip"],
 }

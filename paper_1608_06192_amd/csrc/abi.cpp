@@ -398,6 +398,24 @@ int dcrf_qp_frank_wolfe(dcrf_ctx *ctx, const void *unary, const void *mu,
     });
 }
 
+int dcrf_qp_frank_wolfe_noalloc(dcrf_ctx *ctx, const void *unary, const void *mu,
+                                int L, void *y_inout, int iters,
+                                dcrf_iter_trace *trace) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        check_labels(L);
+        REQUIRE(unary && y_inout, "null argument");
+        REQUIRE(iters >= 0, "iters must be >= 0");
+        dcrf::frank_wolfe_noalloc_entry(ctx, unary, mu, L, y_inout, iters, trace);
+    });
+}
+
+int dcrf_noalloc_scratch_bytes(size_t *bytes) {
+    if (!bytes) return DCRF_EINVAL;
+    *bytes = dcrf::noalloc_scratch_bytes();
+    return DCRF_OK;
+}
+
 int dcrf_dc_gen(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
                 void *y_inout, int outer, int inner, double *S_hist) {
     return guarded(ctx, [&] {

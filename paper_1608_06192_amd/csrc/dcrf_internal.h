@@ -408,6 +408,15 @@ void frank_wolfe(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
                  bool have_Py);
 void dc_gen(dcrf_ctx *ctx, const void *unary, const void *mu, int L, void *y,
             int outer, int inner, double *S_hist);
+// noalloc.hip: the size of the allocation-free scratch array, and the solve
+// on it (its device address taken once per device)
+size_t noalloc_scratch_bytes();
+void frank_wolfe_noalloc_entry(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
+                               void *y, int iters, dcrf_iter_trace *trace);
+// Frank-Wolfe with the solve's buffers borrowed from base (cap bytes)
+void frank_wolfe_noalloc(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
+                         void *y, int iters, dcrf_iter_trace *trace, void *base,
+                         size_t cap);
 void round_labels(dcrf_ctx *ctx, const void *y, int L, int32_t *labels);
 double energy(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
               const int32_t *labels);

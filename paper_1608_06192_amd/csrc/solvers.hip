@@ -1046,6 +1046,100 @@ double energy_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L,
     return sum_partials(ctx, ctx->fw_part.as<double>(), G);
 }
 
+// dcrf_qp_frank_wolfe with every buffer the solve takes borrowed from
+// `base` (cap bytes): the same kernels on the same layouts, with the
+// per-call state (linear term, P_y, P_s, conditional gradients, partial
+// sums, step accumulators, trace, sum_j |mu_ij|, the Potts copy of mu, the
+// input-error flag) and each lattice's three vertex-value arrays placed at
+// 256-byte aligned offsets of base. Everything else the solve reads (the
+// lattice tables, r, the blur path tables) was built by dcrf_set_image. While
+// it runs, any other allocation fails with DCRF_ENOMEM instead of reaching
+// the device allocator, and the context's own buffers are restored on exit.
+template <typename T>
+void fw_noalloc_t(dcrf_ctx *ctx, const T *phi, const void *mu, int L, T *y, int iters,
+                  dcrf_iter_trace *trace, char *base, size_t cap) {
+    if (ctx->mode != DCRF_FILTER_LATTICE)
+        fail(DCRF_EUNSUPPORTED, "the allocation-free solve needs the lattice filter mode");
+    if (L > kRowMaxC) fail(DCRF_EUNSUPPORTED, "the allocation-free solve takes L <= 32");
+    if (iters > 4096) fail(DCRF_EINVAL, "the allocation-free solve takes iters <= 4096");
+    const int nimg = ctx->nimg;
+    const size_t N = ctx->N, NL = N * L, e = sizeof(T);
+    const int G1 = seg_tiles(ctx, lmo_tile<T>(L)), G2 = seg_tiles(ctx, slice_tile<T>(L));
+    const size_t np = std::max<size_t>((size_t)G1 * kP1 + (size_t)G2 * kP2,
+                                       (size_t)seg_tiles(ctx, kThreads));
+    const size_t ld = row_stride(L, e);
+    struct Item { DevBuf *buf; size_t bytes; };
+    constexpr int kItems = 11 + 3 * DCRF_MAXK;
+    Item items[kItems];
+    int n = 0;
+    for (DevBuf *b : {&ctx->fw_c, &ctx->fw_Py, &ctx->fw_Ps}) items[n++] = {b, NL * e};
+    items[n++] = {&ctx->fw_s, N * 4};
+    items[n++] = {&ctx->fw_sprev, N * 4};
+    items[n++] = {&ctx->fw_part, np * 8};
+    items[n++] = {&ctx->fw_scal, (size_t)2 * kSets * nimg * kPT * 8};
+    items[n++] = {&ctx->fw_trace, (size_t)std::max(iters, 1) * nimg * 4 * 8};
+    items[n++] = {&ctx->fw_mu, (size_t)L * e};
+    items[n++] = {&ctx->potts, (size_t)L * L * e};
+    items[n++] = {&ctx->errflag, 4};
+    for (int m = 0; m < ctx->nk; ++m)
+        for (int b = 0; b < 3; ++b)
+            items[n++] = {&ctx->lat[m].V[b], (size_t)std::max(ctx->lat[m].M, 1) * ld * e};
+    size_t total = 0;
+    for (int i = 0; i < n; ++i) total += (items[i].bytes + 255) / 256 * 256;
+    if (total > cap)
+        fail(DCRF_EINVAL, "this solve needs " + std::to_string(total) +
+                              " bytes of scratch; the allocation-free entry point has " +
+                              std::to_string(cap));
+    // borrow, and put everything back however the solve ends
+    struct Restore {
+        dcrf_ctx *ctx;
+        Item *items;
+        int n;
+        DevBuf saved[kItems];
+        int potts_L, potts_dtype;
+        bool prof;
+        Arena *arena;
+        Arena refuse;
+        ~Restore() {
+            for (int i = 0; i < n; ++i) *items[i].buf = saved[i];
+            ctx->potts_L = potts_L;
+            ctx->potts_dtype = potts_dtype;
+            ctx->prof.on = prof;
+            tl_arena = arena;
+        }
+    } rs{ctx, items, n, {}, ctx->potts_L, ctx->potts_dtype, ctx->prof.on, tl_arena, {}};
+    size_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        rs.saved[i] = *items[i].buf;
+        DevBuf b;
+        b.p = base + off;
+        b.bytes = (items[i].bytes + 255) / 256 * 256;
+        b.borrowed = true;
+        *items[i].buf = b;
+        off += b.bytes;
+    }
+    ctx->potts_L = 0;       // the Potts copy is rebuilt in the scratch when asked for
+    ctx->prof.on = false;   // profiling would create events
+    rs.refuse.refuse = "the allocation-free solve would need device memory beyond its "
+                       "scratch (e.g. blur tables for a launch shape not yet used)";
+    tl_arena = &rs.refuse;
+    const hipStream_t st = ctx->stream;
+    // what must start at zero: the splat targets and the error flag
+    for (int m = 0; m < ctx->nk; ++m) {
+        const size_t cnt = (size_t)std::max(ctx->lat[m].M, 1) * ld;
+        hipLaunchKernelGGL((k_fill<T>), dim3(ceil_div((long long)cnt, 256)), dim3(256), 0,
+                           st, ctx->lat[m].V[0].as<T>(), cnt, T(0));
+    }
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, st, ctx->errflag.as<int32_t>(),
+                       (size_t)1, 0);
+    DCRF_CHECK_LAUNCH();
+    const T *mu_eff = static_cast<const T *>(resolve_mu(ctx, mu, L));
+    check_finite(ctx, phi, L);
+    check_finite(ctx, y, L);
+    frank_wolfe_t<T>(ctx, phi, mu_eff, L, y, iters, trace, 0, false);
+    if (trace) raise_device_errors(ctx);
+}
+
 }  // namespace
 
 // flag |= 1 if an element of an image's rows of x (N x L) is not finite;
@@ -1108,6 +1202,19 @@ const void *resolve_mu(dcrf_ctx *ctx, const void *mu, int L) {
         ctx->potts_dtype = ctx->dtype;
     }
     return ctx->potts.p;
+}
+
+void frank_wolfe_noalloc(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
+                         void *y, int iters, dcrf_iter_trace *trace, void *base,
+                         size_t cap) {
+    if (ctx->dtype == DCRF_F64)
+        fw_noalloc_t<double>(ctx, static_cast<const double *>(unary), mu, L,
+                             static_cast<double *>(y), iters, trace,
+                             static_cast<char *>(base), cap);
+    else
+        fw_noalloc_t<float>(ctx, static_cast<const float *>(unary), mu, L,
+                            static_cast<float *>(y), iters, trace,
+                            static_cast<char *>(base), cap);
 }
 
 void fill_ones(dcrf_ctx *ctx, void *p, size_t n) {

@@ -85,6 +85,9 @@ PROTOTYPES = {
     "dcrf_qp_frank_wolfe": (_I, [_P, _P, _P, _I, _P, _I,
                                  ctypes.POINTER(dcrf_iter_trace)]),
     "dcrf_dc_gen": (_I, [_P, _P, _P, _I, _P, _I, _I, _PD]),
+    "dcrf_qp_frank_wolfe_noalloc": (_I, [_P, _P, _P, _I, _P, _I,
+                                         ctypes.POINTER(dcrf_iter_trace)]),
+    "dcrf_noalloc_scratch_bytes": (_I, [ctypes.POINTER(ctypes.c_size_t)]),
     "dcrf_dc_neg": (_I, [_P, _P, _P, _I, _P, _I, _I, _PD]),
     "dcrf_round": (_I, [_P, _P, _I, _P]),
     "dcrf_energy": (_I, [_P, _P, _P, _I, _P, _PD]),
@@ -331,6 +334,21 @@ class Context:
         tr = (dcrf_iter_trace * max(iters * self.nimg, 1))() if trace else None
         self._stream()
         self._check(_lib.dcrf_qp_frank_wolfe(
+            self._h, self._arg(unary, name="unary"), self._mu(mu),
+            unary.shape[1], self._arg(y, name="y"), iters, tr))
+        if not trace:
+            return None
+        rec = [(t.objective, t.gap, t.alpha, t.changed)
+               for t in tr[:iters * self.nimg]]
+        if self.nimg == 1:
+            return rec
+        return [rec[j::self.nimg] for j in range(self.nimg)]
+
+    def qp_frank_wolfe_noalloc(self, unary, mu, y, iters: int, trace: bool = True):
+        """qp_frank_wolfe through the entry point that allocates nothing"""
+        tr = (dcrf_iter_trace * max(iters * self.nimg, 1))() if trace else None
+        self._stream()
+        self._check(_lib.dcrf_qp_frank_wolfe_noalloc(
             self._h, self._arg(unary, name="unary"), self._mu(mu),
             unary.shape[1], self._arg(y, name="y"), iters, tr))
         if not trace:
