@@ -24,7 +24,11 @@ Beside it the JSON line reports:
   per-pixel closed form per step);
 * lp: the LP relaxation's projected subgradient descent (divide and conquer,
   100 steps from the timed QP solution): milliseconds per step and the
-  first, best and last S_LP;
+  first, best and last S_LP; the same descent restricted to the labels whose
+  marginal exceeds 0.5 somewhere in the QP solution (for a near-integral
+  solution, the labels its argmax uses); and Kleinberg-Tardos
+  rounding of the best LP point (8 L seeded rounds) with its energy beside
+  the argmax's;
 * qp_dc / qp_dcneg: 50 Frank-Wolfe iterations and then the generic DC
   relaxation (5 concave-convex steps of 10 inner iterations) or DC_neg (5
   steps) at 320x213, L=21, FP32, with the energy of the rounded labelling;
@@ -476,6 +480,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--lp-steps", type=int, default=100)
     ap.add_argument("--lp-beta0", type=float, default=1e-6)
+    ap.add_argument("--lp-tau", type=float, default=0.5,
+                    help="marginal above which a label counts as present")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB copy kernel (reference for "
                          "the HBM byte counters of a profiler run)")
@@ -587,9 +593,10 @@ def main():
     lp = None
     if args.lp_steps > 0:
         ylp = y.clone()                       # the timed QP solve's result
+        ybest = torch.empty_like(y)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        best, hist = ctx.lp_descent(phi, ylp, args.lp_steps, args.lp_beta0)
+        best, hist = ctx.lp_descent(phi, ylp, args.lp_steps, args.lp_beta0, best_y=ybest)
         torch.cuda.synchronize()
         lp_ms = (time.perf_counter() - t0) * 1e3 / args.lp_steps
         lp = dict(ms_per_step=lp_ms, steps=args.lp_steps, beta0=args.lp_beta0,
@@ -597,6 +604,38 @@ def main():
                   best_step=int(np.argmin(hist)))
         log(f"[bench] LP subgradient step (divide and conquer, 21 labels, "
             f"{int(np.ceil(np.log2(N)))} levels): {lp_ms:.1f} ms")
+
+        # the LP on the labels present in the QP solution (marginal > tau)
+        sub = ctx.present_labels(y, args.lp_tau)
+        ysub = y.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bsub, hsub = ctx.lp_descent_subset(phi, ysub, sub, args.lp_steps, args.lp_beta0)
+        torch.cuda.synchronize()
+        sub_ms = (time.perf_counter() - t0) * 1e3 / args.lp_steps
+        lp["subset"] = dict(tau=args.lp_tau, labels=len(sub), ms_per_step=sub_ms,
+                            S_LP_first=hsub[0], S_LP_best=bsub, S_LP_last=hsub[-1])
+        log(f"[bench] LP on the {len(sub)} labels present (tau {args.lp_tau}): "
+            f"{sub_ms:.1f} ms/step, S_LP {hsub[0]:.6g} -> {bsub:.6g}")
+
+        # Kleinberg-Tardos rounding of the best LP point, 8 L rounds drawn
+        # from a seeded generator, against the argmax of the same point
+        g = torch.Generator().manual_seed(7)
+        R = 8 * L
+        rl = torch.randint(0, L, (R,), generator=g, dtype=torch.int32).to(dev)
+        rt = torch.rand(R, generator=g, dtype=torch.float64).to(dev, f32)
+        kt_reps = 20
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(kt_reps):
+            xk, left = ctx.round_kt(ybest, rl, rt)
+        kt_ms = (time.perf_counter() - t0) * 1e3 / kt_reps
+        lp["kt_round"] = dict(rounds=R, ms=kt_ms, pixels_left=left,
+                              energy=ctx.energy(phi, mu, xk),
+                              energy_argmax=ctx.energy(phi, mu, ctx.round(ybest)))
+        log(f"[bench] KT rounding ({R} rounds): {kt_ms * 1e3:.0f} us per call incl. "
+            f"readback, E {lp['kt_round']['energy']:.6g} vs argmax "
+            f"{lp['kt_round']['energy_argmax']:.6g}, {left} pixels left")
 
     ext = {} if args.no_ext else extensions(torch, dcrf, synth, dev, kernels)
     if args.calib_copy:

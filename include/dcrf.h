@@ -361,6 +361,40 @@ int dcrf_lp_descent(dcrf_ctx *ctx, const void *unary, int L, void *y_inout,
                     int steps, double beta0, double *best_obj, void *best_y,
                     double *hist);
 
+/* Kleinberg and Tardos's rounding of marginals y (dev N x L) for the
+ * uniform metric, the Potts model (Sec. 6 cites it for the LP relaxation's
+ * factor-2 bound): round r = 0..R-1 carries a label round_label[r] (dev int32
+ * R, in [0, L)) and a threshold round_theta[r] (dev R, context dtype),
+ * which the caller draws uniform in [0, 1); each pixel takes the label of
+ * the first round with y_a(label) > theta (compared in the context's
+ * precision). So P(x_a = i) = y_a(i), and the expected energy is at most
+ * phi^T y plus twice the LP's pairwise term. Pixels that no round reaches
+ * take the argmax of y (lowest label on ties); *left (host, may be NULL)
+ * receives their number (about N (1 - 1/L)^R). labels: (dev int32 N) out.
+ * Waits for the stream. DCRF_EINVAL for a round label outside [0, L). */
+int dcrf_round_kt(dcrf_ctx *ctx, const void *y, int L, const int32_t *round_label,
+                  const void *round_theta, int R, int32_t *labels, int *left);
+
+/* The labels with y_a(i) > tau at some pixel (y dev N x L), in increasing
+ * order, into labels (host, L ints); *count (host) their number. The labels
+ * "present in the solutions provided by other methods" of Sec. 7, to which
+ * the LP can be restricted (App. I drops labels of small probability the
+ * same way). Waits for the stream. */
+int dcrf_present_labels(dcrf_ctx *ctx, const void *y, int L, double tau,
+                        int32_t *labels, int *count);
+
+/* dcrf_lp_descent restricted to the labels subset[0..nsub-1] (host, distinct,
+ * in [0, L)) (Sec. 7): the other labels are held at 0, which leaves their
+ * terms of eq. potts-lp at 0, so the objective is the full S_LP of the
+ * scattered point. The start is the Euclidean projection of y_inout's subset
+ * columns onto the simplex; y_inout (dev N x L) receives the result with 0 in
+ * the other columns; best_obj, best_y, hist as for dcrf_lp_descent. Each
+ * step sorts and runs the divide and conquer for nsub labels instead of L.
+ * A batch context gives DCRF_EUNSUPPORTED. */
+int dcrf_lp_descent_subset(dcrf_ctx *ctx, const void *unary, int L, void *y_inout,
+                           const int32_t *subset, int nsub, int steps, double beta0,
+                           double *best_obj, void *best_y, double *hist);
+
 /* y = Euclidean projection of each row of v onto the simplex (sort-based
  * rule). v, y: (dev) N x L; may be the same array. */
 int dcrf_project_simplex(dcrf_ctx *ctx, const void *v, int L, void *y);

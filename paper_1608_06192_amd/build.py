@@ -43,6 +43,7 @@ SOURCES = {
     "batch.hip": [],
     "tiles.hip": [],
     "dcneg.hip": [],
+    "rounding.hip": [],
     "noalloc.hip": [],
     "abi.cpp": ["-x", "hip"],
     "workspace.cpp": ["-x", "hip"],

@@ -124,7 +124,8 @@ static void release_all(dcrf_ctx *ctx) {
          {&ctx->r, &ctx->scratch, &ctx->tmpA, &ctx->tmpB, &ctx->fw_c,
           &ctx->fw_Py, &ctx->fw_Ps, &ctx->fw_s, &ctx->fw_sprev, &ctx->fw_part,
           &ctx->fw_scal, &ctx->fw_trace, &ctx->fw_mu, &ctx->potts, &ctx->hist,
-          &ctx->errflag, &ctx->seg, &ctx->tiles, &ctx->tile_img_off})
+          &ctx->errflag, &ctx->seg, &ctx->tiles, &ctx->tile_img_off, &ctx->small,
+          &ctx->sub_phi, &ctx->sub_y, &ctx->sub_best})
         b->release();
     ctx->potts_L = 0;
     ctx->potts_dtype = -1;
@@ -553,6 +554,55 @@ int dcrf_lp_descent(dcrf_ctx *ctx, const void *unary, int L, void *y_inout,
         dcrf::check_finite(ctx, y_inout, L);
         dcrf::lp_descent(ctx, unary, L, y_inout, steps, beta0, best_obj, best_y,
                          hist);
+        dcrf::raise_device_errors(ctx);
+    });
+}
+
+int dcrf_round_kt(dcrf_ctx *ctx, const void *y, int L, const int32_t *round_label,
+                  const void *round_theta, int R, int32_t *labels, int *left) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        check_labels(L);
+        REQUIRE(y && labels && (R == 0 || (round_label && round_theta)), "null argument");
+        REQUIRE(R >= 0, "R must be >= 0");
+        const int n = dcrf::round_kt(ctx, y, L, round_label, round_theta, R, labels);
+        if (left) *left = n;
+    });
+}
+
+int dcrf_present_labels(dcrf_ctx *ctx, const void *y, int L, double tau,
+                        int32_t *labels, int *count) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        check_labels(L);
+        REQUIRE(y && labels && count, "null argument");
+        REQUIRE(std::isfinite(tau), "tau must be finite");
+        *count = dcrf::present_labels(ctx, y, L, tau, labels);
+    });
+}
+
+int dcrf_lp_descent_subset(dcrf_ctx *ctx, const void *unary, int L, void *y_inout,
+                           const int32_t *subset, int nsub, int steps, double beta0,
+                           double *best_obj, void *best_y, double *hist) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        check_labels(L);
+        REQUIRE(unary && y_inout && subset, "null argument");
+        require_single(ctx);
+        REQUIRE(nsub >= 1 && nsub <= L, "nsub must be in [1, L]");
+        bool seen[256] = {};
+        for (int k = 0; k < nsub; ++k) {
+            REQUIRE(subset[k] >= 0 && subset[k] < L && !seen[subset[k]],
+                    "subset entries must be distinct labels in [0, L)");
+            seen[subset[k]] = true;
+        }
+        REQUIRE(steps >= 0, "steps must be >= 0");
+        REQUIRE(std::isfinite(beta0) && beta0 > 0, "beta0 must be > 0");
+        REQUIRE(best_y != y_inout, "best_y must not alias y");
+        dcrf::check_finite(ctx, unary, L);
+        dcrf::check_finite(ctx, y_inout, L);
+        dcrf::lp_descent_subset(ctx, unary, L, y_inout, subset, nsub, steps, beta0,
+                                best_obj, best_y, hist);
         dcrf::raise_device_errors(ctx);
     });
 }

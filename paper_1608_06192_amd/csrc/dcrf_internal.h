@@ -329,6 +329,8 @@ struct dcrf_ctx {
     dcrf::DevBuf potts;
     int potts_L = 0, potts_dtype = -1;
     dcrf::DevBuf hist;       // per-step partial sums of a solver's history
+    dcrf::DevBuf small;      // 4 KB of per-call flags, counters and index tables
+    dcrf::DevBuf sub_phi, sub_y, sub_best;   // the LP on a label subset
     dcrf::DevBuf errflag;    // device-detected input errors (non-finite values)
     dcrf::Arena arena;       // the caller's workspace, when one is given
     size_t hash_cap = 0;     // forced hash-table slots per lattice (0: sized by N)
@@ -420,6 +422,15 @@ void frank_wolfe_noalloc(dcrf_ctx *ctx, const void *unary, const void *mu, int L
 void round_labels(dcrf_ctx *ctx, const void *y, int L, int32_t *labels);
 double energy(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
               const int32_t *labels);
+
+// rounding.hip: Kleinberg-Tardos rounding (returns the pixels left to the
+// argmax), the labels present in y, the LP restricted to a label subset
+int round_kt(dcrf_ctx *ctx, const void *y, int L, const int32_t *rlab, const void *rth,
+             int R, int32_t *labels);
+int present_labels(dcrf_ctx *ctx, const void *y, int L, double tau, int32_t *out);
+void lp_descent_subset(dcrf_ctx *ctx, const void *unary, int L, void *y,
+                       const int32_t *subset, int S, int steps, double beta0,
+                       double *best, void *best_y, double *hist);
 
 // workspace.cpp: upper bound of a context's device memory for B images
 size_t workspace_bound(int B, const int *H, const int *W, int L,

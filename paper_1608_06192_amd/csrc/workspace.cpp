@@ -149,6 +149,8 @@ size_t workspace_bound(int B, const int *H, const int *W, int L,
     s.add(size_t(B + 1) * 4);
     s.add(4);                                          // input error flag
     s.add(size_t(L) * L * e);                          // Potts copy of mu
+    s.add(4096);                                       // per-call flags and tables
+    for (int i = 0; i < 3; ++i) s.add(NL * e);         // the LP on a label subset
     // Frank-Wolfe, DC_gen, DC_neg, energy
     for (int i = 0; i < 3; ++i) s.add(NL * e);         // c, P_y, P_s
     s.add(N * 4);                                      // s

@@ -94,6 +94,9 @@ PROTOTYPES = {
     "dcrf_lp_subgradient": (_I, [_P, _P, _I, _P, _P, _PD]),
     "dcrf_lp_descent": (_I, [_P, _P, _I, _P, _I, _D, _PD, _P, _PD]),
     "dcrf_project_simplex": (_I, [_P, _P, _I, _P]),
+    "dcrf_round_kt": (_I, [_P, _P, _I, _P, _P, _I, _P, ctypes.POINTER(_I)]),
+    "dcrf_present_labels": (_I, [_P, _P, _I, _D, _P, ctypes.POINTER(_I)]),
+    "dcrf_lp_descent_subset": (_I, [_P, _P, _I, _P, _P, _I, _I, _D, _PD, _P, _PD]),
     "dcrf_fw_saved_size": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_size_t)]),
     "dcrf_fw_forward": (_I, [_P, _P, _P, _I, _PD, _I, _P, _P]),
     "dcrf_fw_backward": (_I, [_P, _P, _P, _I, _I, _P, _P, _P, _PD, _PD]),
@@ -406,6 +409,44 @@ class Context:
         self._check(_lib.dcrf_lp_descent(
             self._h, self._arg(unary), unary.shape[1], self._arg(y), steps,
             float(beta0), ctypes.byref(best),
+            None if best_y is None else self._arg(best_y), hist))
+        return best.value, list(hist[:steps])
+
+    def round_kt(self, y, round_label: torch.Tensor, round_theta: torch.Tensor):
+        """(labels, pixels left to the argmax): Kleinberg-Tardos rounding with
+        the given draws (device tensors: int32 labels, thresholds in the
+        context dtype)"""
+        lab = torch.empty(y.shape[0], dtype=torch.int32, device=self.device)
+        left = ctypes.c_int()
+        R = round_label.numel()
+        self._stream()
+        self._check(_lib.dcrf_round_kt(
+            self._h, self._arg(y), y.shape[1],
+            self._arg(round_label, torch.int32, "round_label") if R else None,
+            self._arg(round_theta, name="round_theta") if R else None, R, _ptr(lab),
+            ctypes.byref(left)))
+        return lab, left.value
+
+    def present_labels(self, y, tau: float):
+        L = y.shape[1]
+        out = (ctypes.c_int32 * L)()
+        n = ctypes.c_int()
+        self._stream()
+        self._check(_lib.dcrf_present_labels(self._h, self._arg(y), L, float(tau), out,
+                                             ctypes.byref(n)))
+        return list(out[:n.value])
+
+    def lp_descent_subset(self, unary, y, subset, steps: int, beta0: float,
+                          best_y: torch.Tensor | None = None):
+        """the LP descent on the labels of `subset` only, in place on y;
+        returns (best S_LP, history)"""
+        sub = (ctypes.c_int32 * len(subset))(*[int(i) for i in subset])
+        hist = (ctypes.c_double * max(steps, 1))()
+        best = ctypes.c_double()
+        self._stream()
+        self._check(_lib.dcrf_lp_descent_subset(
+            self._h, self._arg(unary), unary.shape[1], self._arg(y), sub, len(subset),
+            steps, float(beta0), ctypes.byref(best),
             None if best_y is None else self._arg(best_y), hist))
         return best.value, list(hist[:steps])
 
