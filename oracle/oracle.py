@@ -21,6 +21,8 @@ the paper's order and notation, with no blocking or fusion:
 * the LP relaxation (Sec. 6, eq. potts-lp, eq. simple_S, eq. grad_lp), its
   subgradient by brute force and by divide and conquer (App. E), projected
   subgradient descent (Alg. lp_subgrad) with a simplex projection;
+* the LP for an r-HST metric (App. F, eq. rHST-LP, Alg. rHST), Kleinberg and
+  Tardos's rounding for the uniform metric, and the LP on a label subset;
 * the reverse-mode derivative of unrolled Frank-Wolfe.
 
 Where the paper is silent or ambiguous, the reading taken is stated next to
@@ -738,6 +740,112 @@ def lp_descent_subset(phi: np.ndarray, y0: np.ndarray, subset, steps: int,
     by = np.zeros(np.shape(y0))
     by[:, S] = best_ys
     return y, best, by, hist
+
+
+# ---------------------------------------------------------------------------
+# The LP for an r-HST metric (App. F, eq. rHST-LP, Alg. rHST)
+# ---------------------------------------------------------------------------
+
+def tree_label_sets(parent, L: int) -> np.ndarray:
+    """L(T) for every subtree T of a rooted tree: nodes 0..L-1 are the
+    leaves, node k standing for label k, and parent[root] = -1. Returns an
+    (n_nodes, L) 0/1 matrix whose row T marks the labels under T."""
+    parent = np.asarray(parent)
+    n = parent.shape[0]
+    M = np.zeros((n, L), dtype=np.int8)
+    for k in range(L):
+        t, hops = k, 0
+        while t >= 0:
+            M[t, k] = 1
+            t = int(parent[t])
+            hops += 1
+            if hops > n:
+                raise ValueError("parent[] has a cycle")
+    return M
+
+
+def tree_metric(parent, length, L: int) -> np.ndarray:
+    """d^t(i, j): the sum of the edge lengths on the path between leaves i
+    and j, length[T] being the edge from T up to its parent (App. F)."""
+    parent = np.asarray(parent)
+
+    def up(k):                       # ancestors of k with the distance from k
+        out, d, t = {}, 0.0, k
+        while t >= 0:
+            out[t] = d
+            d += float(length[t])
+            t = int(parent[t])
+        return out
+
+    D = np.zeros((L, L))
+    for i in range(L):
+        ai = up(i)
+        for j in range(L):
+            t, d = j, 0.0
+            while t not in ai:       # climb from j to the lowest common ancestor
+                d += float(length[t])
+                t = int(parent[t])
+            D[i, j] = d + ai[t]
+    return D
+
+
+def tree_columns(y: np.ndarray, M: np.ndarray) -> np.ndarray:
+    """y_a(T) = sum_{i in L(T)} y_a(i) for every subtree (Alg. rHST, the
+    precomputation loop). Reading: the labels are added in increasing order
+    starting from 0."""
+    y = np.asarray(y, dtype=np.float64)
+    Y = np.zeros((y.shape[0], M.shape[0]))
+    for T in range(M.shape[0]):
+        for i in np.nonzero(M[T])[0]:
+            Y[:, T] += y[:, i]
+    return Y
+
+
+def rhst_lp_subgradient(phi: np.ndarray, y: np.ndarray, M: np.ndarray, c,
+                        pair_sums):
+    """Subgradient of eq. rHST-LP (Alg. rHST): g starts at phi; for every
+    subtree T with c_T != 0, the pixels are ordered by y_a(T) (descending,
+    ties by pixel index) and gt = c_T (U - Lo) with the two triangular sums
+    of that order is added to the column of every label in L(T). Subtrees
+    with c_T = 0 add nothing. S = <g, y> is the objective, since every term
+    of eq. rHST-LP is linear in y for a fixed order of each y(T)."""
+    g = np.array(phi, dtype=np.float64, copy=True)
+    Y = tree_columns(y, M)
+    for T in range(M.shape[0]):
+        if c[T] == 0:
+            continue
+        U, Lo = pair_sums(sorted_order(Y[:, T]))
+        gt = float(c[T]) * (U - Lo)
+        for k in np.nonzero(M[T])[0]:
+            g[:, k] += gt
+    return g, float((g * y).sum())
+
+
+def S_rhst_dense(K: np.ndarray, phi: np.ndarray, y: np.ndarray, M: np.ndarray,
+                 c) -> float:
+    """eq. rHST-LP evaluated directly from a dense Kbar (tiny N):
+    phi^T y + sum_T c_T sum_{a != b} Kbar_ab |y_a(T) - y_b(T)| / 2."""
+    Y = tree_columns(y, M)
+    pair = 0.0
+    for T in range(M.shape[0]):
+        pair += float(c[T]) * (K * np.abs(Y[:, None, T] - Y[None, :, T])).sum() / 2.0
+    return float((phi * y).sum() + pair)
+
+
+def rhst_lp_descent(phi: np.ndarray, y0: np.ndarray, M: np.ndarray, c, steps: int,
+                    beta0: float, pair_sums):
+    """Projected subgradient descent on eq. rHST-LP (Alg. rHST's loop) with
+    beta_t = beta0 / (1 + t), as for the Potts LP. Returns the last y, the
+    best (S, y) seen and the S history."""
+    y = _f64(y0).copy()
+    best, best_y, hist = math.inf, y.copy(), []
+    for t in range(steps):
+        g, S = rhst_lp_subgradient(phi, y, M, c, pair_sums)
+        hist.append(S)
+        if S < best:
+            best, best_y = S, y.copy()
+        y = project_simplex(y - beta0 / (1.0 + t) * g)
+    return y, best, best_y, hist
 
 
 # ---------------------------------------------------------------------------

@@ -126,6 +126,43 @@ def potts(L: int) -> np.ndarray:
     return 1.0 - np.eye(L)
 
 
+def random_hst(L: int, seed: int, r: float = 2.0, top: float = 1.0,
+               max_children: int = 3):
+    """A random r-hierarchically well-separated tree over L labels: the
+    labels are split recursively into 2..max_children random groups down
+    to single labels; the edges from a node to its children all have one
+    length, top / r^depth (so lengths fall by the factor r from the root
+    down). Nodes 0..L-1 are the leaves (node k is label k), internal nodes
+    follow in creation order, the root first among them.
+
+    Returns (parent, length): int32 parent of every node (-1 for the root)
+    and float64 length of the edge from every node to its parent (0 for the
+    root)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    parent = list(range(L))            # placeholders for the leaves
+    length = [0.0] * L
+    parent_int, length_int = [], []
+
+    def build(labels, par, depth, edge):
+        if len(labels) == 1:
+            parent[labels[0]] = par
+            length[labels[0]] = edge
+            return
+        node = L + len(parent_int)
+        parent_int.append(par)
+        length_int.append(edge)
+        k = int(g.integers(2, min(max_children, len(labels)) + 1))
+        perm = g.permutation(labels)
+        cuts = np.sort(g.choice(np.arange(1, len(labels)), size=k - 1, replace=False))
+        child_edge = top / r ** depth
+        for part in np.split(perm, cuts):
+            build(sorted(int(v) for v in part), node, depth + 1, child_edge)
+
+    build(list(range(L)), -1, 0, 0.0)
+    return (np.array(parent + parent_int, dtype=np.int32),
+            np.array(length + length_int, dtype=np.float64))
+
+
 # The workloads used throughout (image sizes, label counts, seeds, iterations).
 WORKLOADS = {
     "rect_32x24_L3": dict(kind="rect", H=24, W=32, L=3, seed=0, iters=20),
