@@ -546,7 +546,7 @@ def lp_pair_sums_brute(K: np.ndarray, order: np.ndarray):
     return U, Lo
 
 
-def dnc_nodes(N: int):
+def dnc_nodes(N: int, levels: int | None = None):
     """Nodes of the divide and conquer of App. E, level by level.
 
     App. E splits a range of N positions at h = N/2 and recurses on both
@@ -555,9 +555,11 @@ def dnc_nodes(N: int):
     splits at floor((2n+1) N / 2^(l+1)); the top split is N/2 for even N (the
     3|3 blocks of the N = 6 example of Sec. 6) and after ceil(log2 N) levels
     every node holds at most one position. Yields (lo, mid, hi) for every node
-    whose two halves are both non-empty.
+    whose two halves are both non-empty, over the first ``levels`` levels
+    (all of them by default).
     """
-    levels = int(math.ceil(math.log2(N))) if N > 1 else 0
+    if levels is None:
+        levels = int(math.ceil(math.log2(N))) if N > 1 else 0
     for l in range(levels):
         for n in range(1 << l):
             lo = (n * N) >> l
@@ -567,8 +569,17 @@ def dnc_nodes(N: int):
                 yield lo, mid, hi
 
 
+def leaf_level(N: int, leaf: int) -> int:
+    """The first level of the divide and conquer whose nodes all hold at
+    most ``leaf`` positions (node sizes at level l are at most ceil(N/2^l))."""
+    l = 0
+    while -(-N // (1 << l)) > leaf:
+        l += 1
+    return l
+
+
 def lp_pair_sums_dnc(model: Model, order: np.ndarray, inner: str,
-                     at: np.ndarray | None = None):
+                     at: np.ndarray | None = None, leaf: int = 0):
     """U and Lo of eq. grad_lp by the divide-and-conquer of App. E.
 
     For each node, the block between its halves is one filter call: the
@@ -581,6 +592,11 @@ def lp_pair_sums_dnc(model: Model, order: np.ndarray, inner: str,
     a pixel receives contributions only from the nodes whose range holds its
     position, one per level, so every other node is skipped, and U and Lo are
     then valid at the pixels of ``at`` alone.
+
+    ``leaf`` > 0 stops the recursion at the first level whose nodes hold at
+    most ``leaf`` positions and sums every pair inside those nodes exactly
+    (the Gaussian sum of eq. fb, as the brute force does) instead of
+    filtering their halves level by level further down.
     """
     N = order.shape[0]
     U = np.zeros(N)
@@ -590,7 +606,8 @@ def lp_pair_sums_dnc(model: Model, order: np.ndarray, inner: str,
         rank = np.empty(N, dtype=np.int64)
         rank[order] = np.arange(N)
         want = np.sort(rank[np.asarray(at, dtype=np.int64)])
-    for lo, mid, hi in dnc_nodes(N):
+    cut = leaf_level(N, leaf) if leaf > 0 else None
+    for lo, mid, hi in dnc_nodes(N, cut):
         if want is not None:
             k = np.searchsorted(want, lo)
             if k == want.shape[0] or want[k] >= hi:
@@ -615,6 +632,23 @@ def lp_pair_sums_dnc(model: Model, order: np.ndarray, inner: str,
                 acc += model.w[m] * Lattice(f[pts]).filter(ind)
             U[left] += acc[: mid - lo, 1]
             Lo[right] += acc[mid - lo:, 0]
+    if cut is not None:
+        for n in range(1 << cut):
+            lo, hi = (n * N) >> cut, ((n + 1) * N) >> cut
+            if hi - lo < 2:
+                continue
+            if want is not None:
+                k = np.searchsorted(want, lo)
+                if k == want.shape[0] or want[k] >= hi:
+                    continue
+            pts = order[lo:hi]
+            Kn = np.zeros((hi - lo, hi - lo))
+            for m, f in enumerate(model.feats):
+                d = f[pts][:, None, :] - f[pts][None, :, :]
+                Kn += model.w[m] * np.exp(-0.5 * (d * d).sum(axis=2))
+            np.fill_diagonal(Kn, 0.0)
+            U[pts] += np.triu(Kn, 1).sum(axis=1)     # later positions of the node
+            Lo[pts] += np.tril(Kn, -1).sum(axis=1)   # earlier positions
     return U, Lo
 
 

@@ -499,3 +499,59 @@ def test_simplex_projection_kkt_and_bisection():
         for _ in range(10):
             z = rng.dirichlet(np.ones(21))
             assert np.linalg.norm(v - p) <= np.linalg.norm(v - z) + 1e-12
+
+
+def _pair_model(H, W, seed, mode="exact"):
+    rng = np.random.default_rng(seed)
+    rgb = rng.uniform(0, 255, size=(H * W, 3)).astype(np.float32)
+    kern = [O.Kernel(1, 2.0, 40.0, 4.0), O.Kernel(0, 1.5, 0.0, 1.5)]
+    return O.Model(H, W, rgb, kern, mode=mode), rng
+
+
+@pytest.mark.parametrize("leaf", [1, 2, 3, 5, 16, 61, 200])
+def test_leaf_exact_dnc_with_exact_inner_is_the_brute_force(leaf):
+    # exact filters above the cut plus exact pairs inside the leaves count
+    # every pair once: the brute-force sums for any cutoff (here N = 60, so
+    # 61 and 200 make the whole range one leaf)
+    model, rng = _pair_model(6, 10, 1)
+    K = model.dense_K()
+    order = rng.permutation(60)
+    Ub, Lb = O.lp_pair_sums_brute(K, order)
+    U, Lo = O.lp_pair_sums_dnc(model, order, "exact", leaf=leaf)
+    assert np.allclose(U, Ub, rtol=1e-12, atol=1e-12)
+    assert np.allclose(Lo, Lb, rtol=1e-12, atol=1e-12)
+    assert O.leaf_level(60, leaf) == (0 if leaf >= 60 else int(np.ceil(np.log2(60 / leaf))))
+
+
+def test_leaf_exact_dnc_lattice_whole_leaf_and_sampling():
+    model, rng = _pair_model(9, 13, 2, mode="lattice")
+    N = 117
+    order = rng.permutation(N)
+    K = _pair_model(9, 13, 2)[0].dense_K()
+    Ub, Lb = O.lp_pair_sums_brute(K, order)
+    U, Lo = O.lp_pair_sums_dnc(model, order, "lattice", leaf=N)
+    assert np.allclose(U, Ub, rtol=1e-12, atol=1e-12)
+    assert np.allclose(Lo, Lb, rtol=1e-12, atol=1e-12)
+    # sampled evaluation equals the full one at the sampled pixels
+    U, Lo = O.lp_pair_sums_dnc(model, order, "lattice", leaf=8)
+    at = rng.choice(N, 20, replace=False)
+    Us, Ls = O.lp_pair_sums_dnc(model, order, "lattice", at=at, leaf=8)
+    assert np.array_equal(Us[at], U[at]) and np.array_equal(Ls[at], Lo[at])
+
+
+def test_leaf_exact_dnc_is_closer_to_the_exact_sums():
+    # the lattice is least accurate on the few points of small nodes; summing
+    # those exactly brings U - Lo closer to the brute force
+    errs = {}
+    for leaf in (0, 16, 64):
+        e = []
+        for seed in (3, 4, 5):
+            model, rng = _pair_model(20, 24, seed, mode="lattice")
+            K = _pair_model(20, 24, seed)[0].dense_K()
+            order = rng.permutation(480)
+            Ub, Lb = O.lp_pair_sums_brute(K, order)
+            U, Lo = O.lp_pair_sums_dnc(model, order, "lattice", leaf=leaf)
+            e.append(np.linalg.norm((U - Lo) - (Ub - Lb)) / np.linalg.norm(Ub - Lb))
+        errs[leaf] = float(np.mean(e))
+    print("relative error of U - Lo by leaf cutoff", errs)
+    assert errs[64] < errs[16] < errs[0]
