@@ -24,11 +24,12 @@ Beside it the JSON line reports:
   per-pixel closed form per step);
 * lp: the LP relaxation's projected subgradient descent (divide and conquer,
   100 steps from the timed QP solution): milliseconds per step and the
-  first, best and last S_LP; the same descent restricted to the labels whose
-  marginal exceeds 0.5 somewhere in the QP solution (for a near-integral
-  solution, the labels its argmax uses); and Kleinberg-Tardos
+  first, best and last S_LP; 20 steps of it with leaf-exact nodes of at
+  most 256 positions; the same descent restricted to the labels that
+  the QP solution's argmax uses; and Kleinberg-Tardos
   rounding of the best LP point (8 L seeded rounds) with its energy beside
-  the argmax's;
+  the argmax's; and the LP for a tree metric (a seeded 2-HST over the 21
+  labels, 10 steps): milliseconds per step;
 * qp_dc / qp_dcneg: 50 Frank-Wolfe iterations and then the generic DC
   relaxation (5 concave-convex steps of 10 inner iterations) or DC_neg (5
   steps) at 320x213, L=21, FP32, with the energy of the rounded labelling;
@@ -480,8 +481,6 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--lp-steps", type=int, default=100)
     ap.add_argument("--lp-beta0", type=float, default=1e-6)
-    ap.add_argument("--lp-tau", type=float, default=0.5,
-                    help="marginal above which a label counts as present")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB copy kernel (reference for "
                          "the HBM byte counters of a profiler run)")
@@ -605,17 +604,35 @@ def main():
         log(f"[bench] LP subgradient step (divide and conquer, 21 labels, "
             f"{int(np.ceil(np.log2(N)))} levels): {lp_ms:.1f} ms")
 
-        # the LP on the labels present in the QP solution (marginal > tau)
-        sub = ctx.present_labels(y, args.lp_tau)
+        # the same descent with leaf-exact nodes of at most 256 positions
+        yleaf = y.clone()
+        leaf_steps = max(1, args.lp_steps // 5)
+        ctx.set_lp_leaf(256)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bleaf, hleaf = ctx.lp_descent(phi, yleaf, leaf_steps, args.lp_beta0)
+        torch.cuda.synchronize()
+        leaf_ms = (time.perf_counter() - t0) * 1e3 / leaf_steps
+        ctx.set_lp_leaf(0)
+        lp["leaf_exact"] = dict(leaf=256, steps=leaf_steps, ms_per_step=leaf_ms,
+                                S_LP_first=hleaf[0], S_LP_best=bleaf,
+                                plain_S_LP_at_same_step=hist[leaf_steps - 1],
+                                leaf_S_LP_at_same_step=hleaf[-1])
+        log(f"[bench] LP step with leaf-exact nodes (<= 256 positions): {leaf_ms:.1f} ms, "
+            f"S_LP after {leaf_steps} steps {hleaf[-1]:.6g} (plain {hist[leaf_steps - 1]:.6g})")
+
+        # the LP on the labels that the QP solution's argmax uses (Sec. 7
+        # restricts the LP to the labels present in another method's result)
+        sub = ctx.labels_used(ctx.round(y), L)
         ysub = y.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         bsub, hsub = ctx.lp_descent_subset(phi, ysub, sub, args.lp_steps, args.lp_beta0)
         torch.cuda.synchronize()
         sub_ms = (time.perf_counter() - t0) * 1e3 / args.lp_steps
-        lp["subset"] = dict(tau=args.lp_tau, labels=len(sub), ms_per_step=sub_ms,
+        lp["subset"] = dict(labels=len(sub), ms_per_step=sub_ms,
                             S_LP_first=hsub[0], S_LP_best=bsub, S_LP_last=hsub[-1])
-        log(f"[bench] LP on the {len(sub)} labels present (tau {args.lp_tau}): "
+        log(f"[bench] LP on the {len(sub)} labels the argmax uses: "
             f"{sub_ms:.1f} ms/step, S_LP {hsub[0]:.6g} -> {bsub:.6g}")
 
         # Kleinberg-Tardos rounding of the best LP point, 8 L rounds drawn
@@ -636,6 +653,23 @@ def main():
         log(f"[bench] KT rounding ({R} rounds): {kt_ms * 1e3:.0f} us per call incl. "
             f"readback, E {lp['kt_round']['energy']:.6g} vs argmax "
             f"{lp['kt_round']['energy_argmax']:.6g}, {left} pixels left")
+
+        # the LP for a tree metric: a seeded 2-HST over the labels, c_T twice
+        # the edge length above T, descent from the QP solution
+        parent, length = synth.random_hst(L, seed=21)
+        c = [2.0 * v for v in length]
+        yt = y.clone()
+        tree_steps = max(1, args.lp_steps // 10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        btree, htree = ctx.lp_descent_tree(phi, yt, parent, c, tree_steps, args.lp_beta0)
+        torch.cuda.synchronize()
+        tree_ms = (time.perf_counter() - t0) * 1e3 / tree_steps
+        lp["tree"] = dict(nodes=len(parent), weighted_subtrees=int(sum(v > 0 for v in c)),
+                          steps=tree_steps, ms_per_step=tree_ms, S_first=htree[0],
+                          S_best=btree)
+        log(f"[bench] r-HST LP ({len(parent)} nodes): {tree_ms:.1f} ms/step, "
+            f"S {htree[0]:.6g} -> {btree:.6g} in {tree_steps} steps")
 
     ext = {} if args.no_ext else extensions(torch, dcrf, synth, dev, kernels)
     if args.calib_copy:

@@ -335,6 +335,15 @@ int dcrf_energy(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
 
 /* ---- LP relaxation (Potts) --------------------------------------------- */
 
+/* Leaf-exact divide and conquer for the LP calls below (App. E): from the
+ * first level whose nodes all hold at most `leaf` sorted positions
+ * (ceil(N / 2^l) <= leaf), the pairs inside each node are summed exactly
+ * (the Gaussian sum, one block per node) instead of being filtered level by
+ * level further down: ceil(log2(N / leaf)) lattice levels instead of
+ * ceil(log2 N). leaf in [0, 256]; 0 or 1 (the default 0) keeps the plain
+ * recursion. The exact filter mode ignores it. */
+int dcrf_set_lp_leaf(dcrf_ctx *ctx, int leaf);
+
 /* One subgradient of the LP relaxation of the Potts model (Sec. 6,
  * eq. potts-lp) at y: g_c(i) = phi_c(i) + sum_{a after c} Kbar_ac
  * - sum_{a before c} Kbar_ac, the order being y(:, i) descending with ties by
@@ -361,6 +370,34 @@ int dcrf_lp_descent(dcrf_ctx *ctx, const void *unary, int L, void *y_inout,
                     int steps, double beta0, double *best_obj, void *best_y,
                     double *hist);
 
+/* ---- LP relaxation for an r-HST metric (App. F) ----------------------- */
+
+/* One subgradient of the LP for a tree metric (App. F, eq. rHST-LP,
+ * Alg. rHST). The tree has n_nodes nodes: node k < L is label k's leaf,
+ * parent[t] (host int32) is t's parent or -1 for the root (one root, no
+ * cycles, labels are leaves), c[t] (host, >= 0) the weight c_T of subtree t.
+ * With y_a(T) the sum of y_a(i) over the labels under T (added in increasing
+ * label order), g = phi plus, for every subtree with c_T > 0,
+ * c_T (sum_{a after c} Kbar_ac - sum_{a before c} Kbar_ac) in the order of
+ * y(T) (descending, ties by pixel index) on the column of every label under
+ * T; *S_lp (host) = <g, y>, the objective of eq. rHST-LP. The pair sums are
+ * those of dcrf_lp_subgradient (divide and conquer, or exact), one pass per
+ * weighted subtree. For an r-HST with edge length l_T above subtree T,
+ * c_T = 2 l_T makes the objective at integral y the energy with
+ * mu(i, j) = the tree's path length between i and j. n_nodes <= 1024.
+ * DCRF_EINVAL for a malformed tree or a negative or non-finite weight; a
+ * batch context gives DCRF_EUNSUPPORTED. Waits for the stream. */
+int dcrf_lp_subgradient_tree(dcrf_ctx *ctx, const void *unary, int L, const void *y,
+                             int n_nodes, const int32_t *parent, const double *c, void *g,
+                             double *S_lp);
+
+/* Projected subgradient descent on eq. rHST-LP (Alg. rHST's loop), with the
+ * tree as for dcrf_lp_subgradient_tree and the steps, outputs and limits of
+ * dcrf_lp_descent. */
+int dcrf_lp_descent_tree(dcrf_ctx *ctx, const void *unary, int L, void *y_inout,
+                         int n_nodes, const int32_t *parent, const double *c, int steps,
+                         double beta0, double *best_obj, void *best_y, double *hist);
+
 /* Kleinberg and Tardos's rounding of marginals y (dev N x L) for the
  * uniform metric, the Potts model (Sec. 6 cites it for the LP relaxation's
  * factor-2 bound): round r = 0..R-1 carries a label round_label[r] (dev int32
@@ -382,6 +419,14 @@ int dcrf_round_kt(dcrf_ctx *ctx, const void *y, int L, const int32_t *round_labe
  * same way). Waits for the stream. */
 int dcrf_present_labels(dcrf_ctx *ctx, const void *y, int L, double tau,
                         int32_t *labels, int *count);
+
+/* The labels that a labelling uses (labels: dev int32 N, values in [0, L)),
+ * in increasing order, into used (host, L ints); *count (host) their number:
+ * the labels present in another method's solution, to which Sec. 7
+ * restricts the LP. Waits for the stream. DCRF_EINVAL for a label outside
+ * [0, L). */
+int dcrf_labels_used(dcrf_ctx *ctx, const int32_t *labels, int L, int32_t *used,
+                     int *count);
 
 /* dcrf_lp_descent restricted to the labels subset[0..nsub-1] (host, distinct,
  * in [0, L)) (Sec. 7): the other labels are held at 0, which leaves their

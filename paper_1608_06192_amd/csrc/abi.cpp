@@ -558,6 +558,43 @@ int dcrf_lp_descent(dcrf_ctx *ctx, const void *unary, int L, void *y_inout,
     });
 }
 
+int dcrf_lp_subgradient_tree(dcrf_ctx *ctx, const void *unary, int L, const void *y,
+                             int n_nodes, const int32_t *parent, const double *c, void *g,
+                             double *S_lp) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        check_labels(L);
+        REQUIRE(unary && y && g && y != g && parent && c, "null or aliased argument");
+        require_single(ctx);
+        const dcrf::TreeSpec tr = dcrf::tree_spec(parent, c, n_nodes, L);
+        dcrf::check_finite(ctx, unary, L);
+        dcrf::check_finite(ctx, y, L);
+        const double S = dcrf::lp_subgradient_tree(ctx, unary, L, y, tr, g);
+        dcrf::raise_device_errors(ctx);
+        if (S_lp) *S_lp = S;
+    });
+}
+
+int dcrf_lp_descent_tree(dcrf_ctx *ctx, const void *unary, int L, void *y_inout,
+                         int n_nodes, const int32_t *parent, const double *c, int steps,
+                         double beta0, double *best_obj, void *best_y, double *hist) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        check_labels(L);
+        REQUIRE(unary && y_inout && parent && c, "null argument");
+        require_single(ctx);
+        REQUIRE(steps >= 0, "steps must be >= 0");
+        REQUIRE(std::isfinite(beta0) && beta0 > 0, "beta0 must be > 0");
+        REQUIRE(best_y != y_inout, "best_y must not alias y");
+        const dcrf::TreeSpec tr = dcrf::tree_spec(parent, c, n_nodes, L);
+        dcrf::check_finite(ctx, unary, L);
+        dcrf::check_finite(ctx, y_inout, L);
+        dcrf::lp_descent_tree(ctx, unary, L, y_inout, tr, steps, beta0, best_obj, best_y,
+                              hist);
+        dcrf::raise_device_errors(ctx);
+    });
+}
+
 int dcrf_round_kt(dcrf_ctx *ctx, const void *y, int L, const int32_t *round_label,
                   const void *round_theta, int R, int32_t *labels, int *left) {
     return guarded(ctx, [&] {
@@ -578,6 +615,16 @@ int dcrf_present_labels(dcrf_ctx *ctx, const void *y, int L, double tau,
         REQUIRE(y && labels && count, "null argument");
         REQUIRE(std::isfinite(tau), "tau must be finite");
         *count = dcrf::present_labels(ctx, y, L, tau, labels);
+    });
+}
+
+int dcrf_labels_used(dcrf_ctx *ctx, const int32_t *labels, int L, int32_t *used,
+                     int *count) {
+    return guarded(ctx, [&] {
+        require_image(ctx);
+        check_labels(L);
+        REQUIRE(labels && used && count, "null argument");
+        *count = dcrf::labels_used(ctx, labels, L, used);
     });
 }
 
@@ -648,6 +695,13 @@ int dcrf_set_hash_capacity(dcrf_ctx *ctx, size_t slots) {
                                slots <= (size_t(1) << 32)),
                 "slots must be 0 or a power of two in [16, 2^32]");
         ctx->hash_cap = slots;
+    });
+}
+
+int dcrf_set_lp_leaf(dcrf_ctx *ctx, int leaf) {
+    return guarded(ctx, [&] {
+        REQUIRE(leaf >= 0 && leaf <= 256, "leaf must be in [0, 256]");
+        ctx->lp_leaf = leaf;
     });
 }
 

@@ -334,6 +334,7 @@ struct dcrf_ctx {
     dcrf::DevBuf errflag;    // device-detected input errors (non-finite values)
     dcrf::Arena arena;       // the caller's workspace, when one is given
     size_t hash_cap = 0;     // forced hash-table slots per lattice (0: sized by N)
+    int lp_leaf = 0;         // LP divide and conquer: exact pairs in nodes of <= this many
     void *lp = nullptr;      // LP divide-and-conquer workspace (lp.hip)
     void *diff = nullptr;    // reverse-sweep workspace (diff.hip)
     dcrf::Profiler prof;
@@ -428,6 +429,7 @@ double energy(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
 int round_kt(dcrf_ctx *ctx, const void *y, int L, const int32_t *rlab, const void *rth,
              int R, int32_t *labels);
 int present_labels(dcrf_ctx *ctx, const void *y, int L, double tau, int32_t *out);
+int labels_used(dcrf_ctx *ctx, const int32_t *labels, int L, int32_t *out);
 void lp_descent_subset(dcrf_ctx *ctx, const void *unary, int L, void *y,
                        const int32_t *subset, int S, int steps, double beta0,
                        double *best, void *best_y, double *hist);
@@ -477,6 +479,19 @@ void lp_descent(dcrf_ctx *ctx, const void *unary, int L, void *y, int steps,
                 double beta0, double *best, void *best_y, double *hist);
 void project_simplex(dcrf_ctx *ctx, const void *v, int L, void *y);
 void lp_release(dcrf_ctx *ctx);
+// the LP for an r-HST metric: the tree's subtrees with their weights c_T and
+// label lists (increasing label order), checked and built from parent[]
+constexpr int kMaxTreeNodes = 1024;
+struct TreeSpec {
+    int n = 0;
+    std::vector<double> c;
+    std::vector<int> off, lab;   // labels of subtree t: lab[off[t] .. off[t+1])
+};
+TreeSpec tree_spec(const int32_t *parent, const double *c, int n, int L);
+double lp_subgradient_tree(dcrf_ctx *ctx, const void *unary, int L, const void *y,
+                           const TreeSpec &tr, void *g);
+void lp_descent_tree(dcrf_ctx *ctx, const void *unary, int L, void *y, const TreeSpec &tr,
+                     int steps, double beta0, double *best, void *best_y, double *hist);
 
 inline int ceil_div(long long a, long long b) { return int((a + b - 1) / b); }
 

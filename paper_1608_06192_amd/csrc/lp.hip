@@ -36,6 +36,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <string>
 #include <vector>
 
 #include "dcrf_internal.h"
@@ -495,14 +496,81 @@ __global__ void k_lp_add_col(int N, int L, int col, const int *__restrict__ perm
     acc[p] = T(0);
 }
 
+// leaf-exact divide and conquer: node n of level lcut holds the sorted
+// positions [n N >> lcut, (n+1) N >> lcut), at most kLpLeafMax of them; the
+// pixel at position p receives sum over the node's other positions q of
+// Kbar(pi(q), pi(p)) (q > p ? 1 : -1), the exact Gaussian sum, with the
+// node's features staged in LDS (one block per node, one lane per position)
+constexpr int kLpLeafMax = 256;
+constexpr int kLpLeafMaxF = 16;   // feature dimensions over all kernels
+
+template <typename T>
+__global__ void __launch_bounds__(kLpLeafMax)
+k_lp_leaf(int N, int lcut, const int *__restrict__ perm, ExactSet<T> ex,
+          T *__restrict__ acc) {
+    __shared__ T sf[kLpLeafMax][kLpLeafMaxF];
+    const long long n = blockIdx.x;
+    const int lo = int((n * N) >> lcut), hi = int(((n + 1) * N) >> lcut);
+    const int p = lo + (int)threadIdx.x;
+    if (p < hi) {
+        const int a = perm[p];
+        for (int m = 0; m < ex.nk; ++m)
+            for (int j = 0; j < ex.d[m]; ++j)
+                sf[threadIdx.x][ex.off[m] + j] = ex.f[m][(size_t)a * ex.d[m] + j];
+    }
+    __syncthreads();
+    if (p >= hi) return;
+    const int me = (int)threadIdx.x;
+    T s = T(0);
+    for (int t = 0; t < hi - lo; ++t) {
+        if (t == me) continue;
+        T kab = T(0);
+        for (int m = 0; m < ex.nk; ++m) {
+            T r2 = T(0);
+            for (int j = ex.off[m]; j < ex.off[m + 1]; ++j) {
+                const T df = sf[me][j] - sf[t][j];
+                r2 += df * df;
+            }
+            kab += ex.w[m] * exp(T(-0.5) * r2);
+        }
+        s += t > me ? kab : -kab;
+    }
+    acc[p] += s;
+}
+
+// y_a(T) = sum of y_a(i) over the subtree's labels, in increasing label order
+template <typename T>
+__global__ void k_tree_col(int N, int L, const T *__restrict__ y,
+                           const int *__restrict__ labs, int nlab, T *__restrict__ col) {
+    const int a = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (a >= N) return;
+    const T *row = y + (size_t)a * L;
+    T s = T(0);
+    for (int j = 0; j < nlab; ++j) s += row[labs[j]];
+    col[a] = s;
+}
+
+// g[perm[p]][k] += c acc[p] for every label k of the subtree; acc returns
+// to zero
+template <typename T>
+__global__ void k_lp_add_tree(int N, int L, const int *__restrict__ perm,
+                              T *__restrict__ acc, T c, const int *__restrict__ labs,
+                              int nlab, T *__restrict__ g) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const T v = c * acc[p];
+    T *row = g + (size_t)perm[p] * L;
+    for (int j = 0; j < nlab; ++j) row[labs[j]] += v;
+    acc[p] = T(0);
+}
+
 // exact mode: for the point at sorted position p,
-// sum_{q != p} Kbar(pi(q), pi(p)) (q > p ? 1 : -1), tiled through LDS
+// acc[p] = sum_{q != p} Kbar(pi(q), pi(p)) (q > p ? 1 : -1), tiled through LDS
 constexpr int kLpExTile = 128;
 
 template <typename T>
 __global__ void __launch_bounds__(kLpExTile)
-k_lp_exact(int N, int L, int col, const int *__restrict__ perm,
-           ExactSet<T> ex, T *__restrict__ g) {
+k_lp_exact(int N, const int *__restrict__ perm, ExactSet<T> ex, T *__restrict__ acc_out) {
     __shared__ T sf[kLpExTile][16];
     const int p = blockIdx.x * kLpExTile + threadIdx.x;
     T fa[16];
@@ -541,7 +609,7 @@ k_lp_exact(int N, int L, int col, const int *__restrict__ perm,
         }
         __syncthreads();
     }
-    if (p < N) g[(size_t)a * L + col] += acc;
+    if (p < N) acc_out[p] = acc;
 }
 
 // ------------------------------------------------- projection and step
@@ -630,6 +698,7 @@ struct LPWork {
         int cap_sub = 0;
     } lat[DCRF_MAXK];
     DevBuf g, part, acc;
+    DevBuf col, tree_lab;    // a subtree's column y(T) and the subtrees' label lists
     // the second and later lattices of a level run on a stream of their own
     // (default priority), joined to the context's stream by two events
     hipStream_t side = nullptr;
@@ -723,13 +792,13 @@ void lp_prepare(dcrf_ctx *ctx, LPWork &W, int L) {
     const int N = ctx->N;
     W.g.ensure((size_t)N * L * sizeof(T), s);
     W.part.ensure(1024 * 8, s);
+    W.acc.ensure((size_t)N * sizeof(T), s);   // zero between columns
     if (ctx->mode == DCRF_FILTER_EXACT) return;
     if (!W.side) {
         DCRF_TRY_HIP(hipStreamCreateWithFlags(&W.side, hipStreamNonBlocking));
         DCRF_TRY_HIP(hipEventCreateWithFlags(&W.ev_start, hipEventDisableTiming));
         DCRF_TRY_HIP(hipEventCreateWithFlags(&W.ev_done, hipEventDisableTiming));
     }
-    W.acc.ensure((size_t)N * sizeof(T), s);   // zero between labels
     for (int m = 0; m < ctx->nk; ++m) {
         auto &P = W.lat[m];
         const int D1 = ctx->lat[m].d + 1;
@@ -754,6 +823,96 @@ void lp_prepare(dcrf_ctx *ctx, LPWork &W, int L) {
     }
 }
 
+// The two triangular sums of column `col` of y (leading dimension ld) in the
+// order of its values: on return acc[p] = U - Lo of the pixel at sorted
+// position p, and the order itself is returned.
+template <typename T>
+int *column_pair_sums(dcrf_ctx *ctx, LPWork &W, const T *y, int ld, int col, int levels) {
+    const hipStream_t s = ctx->stream;
+    const int N = ctx->N;
+    int *perm = nullptr;
+    sort_column<T>(ctx, W, y, ld, col, &perm);
+    if (ctx->mode == DCRF_FILTER_EXACT) {
+        ExactSet<T> ex = make_exact_set<T>(ctx);
+        hipLaunchKernelGGL((k_lp_exact<T>), dim3(ceil_div(N, kLpExTile)), dim3(kLpExTile),
+                           0, s, N, perm, ex, W.acc.as<T>());
+        DCRF_CHECK_LAUNCH();
+        return perm;
+    }
+    for (int m = 0; m < ctx->nk; ++m) {
+        Lattice &Lt = ctx->lat[m];
+        const int D1 = Lt.d + 1;
+        hipLaunchKernelGGL((k_lp_gather<T>), dim3(ceil_div((long long)N * D1, 256)),
+                           dim3(256), 0, s, N, D1, perm, Lt.pix_vid.as<int>(),
+                           Lt.pix_w.as<T>(), W.lat[m].pos_vid.as<int>(),
+                           W.lat[m].pos_w.as<T>());
+    }
+    // leaf-exact: lattice levels down to the first whose nodes hold at most
+    // ctx->lp_leaf positions, then the exact pairs inside those nodes
+    int lcut = levels;
+    if (ctx->lp_leaf > 1) {
+        lcut = 0;
+        while (((long long)N + (1ll << lcut) - 1) >> lcut > ctx->lp_leaf) ++lcut;
+    }
+    for (int l = 0; l < lcut; ++l) {
+        // the lattices' chains are independent until the slice: the first
+        // runs on the context's stream, the others on the side stream, which
+        // starts after the previous level's slice
+        if (ctx->nk > 1) {
+            DCRF_TRY_HIP(hipEventRecord(W.ev_start, s));
+            DCRF_TRY_HIP(hipStreamWaitEvent(W.side, W.ev_start, 0));
+            for (int m = 1; m < ctx->nk; ++m) lp_level<T>(ctx, W, m, l, W.side);
+            DCRF_TRY_HIP(hipEventRecord(W.ev_done, W.side));
+        }
+        lp_level<T>(ctx, W, 0, l, s);
+        if (ctx->nk > 1) DCRF_TRY_HIP(hipStreamWaitEvent(s, W.ev_done, 0));
+        LPLats<T> lats{};
+        lats.nk = ctx->nk;
+        for (int m = 0; m < ctx->nk; ++m) {
+            Lattice &Lt = ctx->lat[m];
+            lats.l[m] = LPLat<T>{W.lat[m].pos_w.as<T>(), W.lat[m].ent_id.as<int>(),
+                                 W.lat[m].V[final_buffer_after(lp_blur_launches(Lt.d + 1))].as<T>(), Lt.d + 1,
+                                 T(ctx->kern[m].weight * Lt.gamma)};
+        }
+        hipLaunchKernelGGL((k_lp_slice<T>), dim3(ceil_div(N, 256)), dim3(256), 0, s, N, l,
+                           lats, W.acc.as<T>());
+        DCRF_CHECK_LAUNCH();
+    }
+    if (lcut < levels) {
+        ExactSet<T> ex = make_exact_set<T>(ctx);
+        if (ex.off[ex.nk] > kLpLeafMaxF)
+            fail(DCRF_EUNSUPPORTED, "leaf-exact sums take at most 16 feature dimensions");
+        hipLaunchKernelGGL((k_lp_leaf<T>), dim3(1u << lcut), dim3(kLpLeafMax), 0, s, N, lcut,
+                           perm, ex, W.acc.as<T>());
+        DCRF_CHECK_LAUNCH();
+    }
+    return perm;
+}
+
+int dnc_levels(int N) {
+    int levels = 0;
+    while ((1ll << levels) < N) ++levels;
+    return levels;
+}
+
+// S = <g, y> (the objective, eq. simple_S), after checking the sub-lattice
+// hash tables' overflow flag; waits for the stream
+template <typename T>
+double finish_subgradient(dcrf_ctx *ctx, LPWork &W, const T *g, const T *y, size_t NL) {
+    const hipStream_t s = ctx->stream;
+    int hflags = 0;
+    DCRF_TRY_HIP(hipMemcpyAsync(&hflags, ctx->scratch.p, 4, hipMemcpyDeviceToHost, s));
+    const int G = std::min(1024, ceil_div((long long)NL, 256));
+    hipLaunchKernelGGL((k_dot<T>), dim3(G), dim3(256), 0, s, NL, g, y, W.part.as<double>());
+    std::vector<double> h(G);
+    DCRF_TRY_HIP(hipMemcpyAsync(h.data(), W.part.p, G * 8, hipMemcpyDeviceToHost, s));
+    DCRF_TRY_HIP(hipStreamSynchronize(s));
+    if (hflags & 2) fail(DCRF_ECAPACITY, "LP sub-lattice hash table full");
+    double S = 0.0;
+    for (double v : h) S += v;
+    return S;
+}
+
 template <typename T>
 double lp_subgradient_t(dcrf_ctx *ctx, const T *phi, int L, const T *y, T *g) {
     LPWork &W = lp_work(ctx);
@@ -763,67 +922,48 @@ double lp_subgradient_t(dcrf_ctx *ctx, const T *phi, int L, const T *y, T *g) {
     const size_t NL = (size_t)N * L;
     hipLaunchKernelGGL((k_copy<T>), dim3(ceil_div((long long)NL, 256)), dim3(256),
                        0, s, NL, phi, g);
-    int levels = 0;
-    while ((1ll << levels) < N) ++levels;
+    const int levels = dnc_levels(N);
     DCRF_TRY_HIP(hipMemsetAsync(ctx->scratch.p, 0, 4, s));
     for (int col = 0; col < L; ++col) {
-        int *perm = nullptr;
-        sort_column<T>(ctx, W, y, L, col, &perm);
-        if (ctx->mode == DCRF_FILTER_EXACT) {
-            ExactSet<T> ex = make_exact_set<T>(ctx);
-            hipLaunchKernelGGL((k_lp_exact<T>), dim3(ceil_div(N, kLpExTile)),
-                               dim3(kLpExTile), 0, s, N, L, col, perm, ex, g);
-            DCRF_CHECK_LAUNCH();
-            continue;
-        }
-        for (int m = 0; m < ctx->nk; ++m) {
-            Lattice &Lt = ctx->lat[m];
-            const int D1 = Lt.d + 1;
-            hipLaunchKernelGGL((k_lp_gather<T>), dim3(ceil_div((long long)N * D1, 256)),
-                               dim3(256), 0, s, N, D1, perm, Lt.pix_vid.as<int>(),
-                               Lt.pix_w.as<T>(), W.lat[m].pos_vid.as<int>(),
-                               W.lat[m].pos_w.as<T>());
-        }
-        for (int l = 0; l < levels; ++l) {
-            // the lattices' chains are independent until the slice: the
-            // first runs on the context's stream, the others on the side
-            // stream, which starts after the previous level's slice
-            if (ctx->nk > 1) {
-                DCRF_TRY_HIP(hipEventRecord(W.ev_start, s));
-                DCRF_TRY_HIP(hipStreamWaitEvent(W.side, W.ev_start, 0));
-                for (int m = 1; m < ctx->nk; ++m) lp_level<T>(ctx, W, m, l, W.side);
-                DCRF_TRY_HIP(hipEventRecord(W.ev_done, W.side));
-            }
-            lp_level<T>(ctx, W, 0, l, s);
-            if (ctx->nk > 1) DCRF_TRY_HIP(hipStreamWaitEvent(s, W.ev_done, 0));
-            LPLats<T> lats{};
-            lats.nk = ctx->nk;
-            for (int m = 0; m < ctx->nk; ++m) {
-                Lattice &Lt = ctx->lat[m];
-                lats.l[m] = LPLat<T>{W.lat[m].pos_w.as<T>(), W.lat[m].ent_id.as<int>(),
-                                     W.lat[m].V[final_buffer_after(lp_blur_launches(Lt.d + 1))].as<T>(), Lt.d + 1,
-                                     T(ctx->kern[m].weight * Lt.gamma)};
-            }
-            hipLaunchKernelGGL((k_lp_slice<T>), dim3(ceil_div(N, 256)), dim3(256),
-                               0, s, N, l, lats, W.acc.as<T>());
-            DCRF_CHECK_LAUNCH();
-        }
+        int *perm = column_pair_sums<T>(ctx, W, y, L, col, levels);
         hipLaunchKernelGGL((k_lp_add_col<T>), dim3(ceil_div(N, 256)), dim3(256), 0, s,
                            N, L, col, perm, W.acc.as<T>(), g);
         DCRF_CHECK_LAUNCH();
     }
-    int hflags = 0;
-    DCRF_TRY_HIP(hipMemcpyAsync(&hflags, ctx->scratch.p, 4, hipMemcpyDeviceToHost, s));
-    const int G = std::min(1024, ceil_div((long long)NL, 256));
-    hipLaunchKernelGGL((k_dot<T>), dim3(G), dim3(256), 0, s, NL, g, y,
-                       W.part.as<double>());
-    std::vector<double> h(G);
-    DCRF_TRY_HIP(hipMemcpyAsync(h.data(), W.part.p, G * 8, hipMemcpyDeviceToHost, s));
-    DCRF_TRY_HIP(hipStreamSynchronize(s));
-    if (hflags & 2) fail(DCRF_ECAPACITY, "LP sub-lattice hash table full");
-    double S = 0.0;
-    for (double v : h) S += v;
-    return S;
+    return finish_subgradient<T>(ctx, W, g, y, NL);
+}
+
+// eq. rHST-LP's subgradient (Alg. rHST): g = phi, then for every subtree
+// with c_T != 0 the column y(T), its order and pair sums, and
+// g(., k) += c_T (U - Lo) for the subtree's labels k
+template <typename T>
+double lp_subgradient_tree_t(dcrf_ctx *ctx, const T *phi, int L, const T *y, T *g,
+                             const TreeSpec &tr) {
+    LPWork &W = lp_work(ctx);
+    const hipStream_t s = ctx->stream;
+    const int N = ctx->N;
+    lp_prepare<T>(ctx, W, L);
+    const size_t NL = (size_t)N * L;
+    W.col.ensure((size_t)N * sizeof(T), s);
+    W.tree_lab.ensure(tr.lab.size() * 4, s);
+    DCRF_TRY_HIP(hipMemcpyAsync(W.tree_lab.p, tr.lab.data(), tr.lab.size() * 4,
+                                hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL((k_copy<T>), dim3(ceil_div((long long)NL, 256)), dim3(256),
+                       0, s, NL, phi, g);
+    const int levels = dnc_levels(N);
+    DCRF_TRY_HIP(hipMemsetAsync(ctx->scratch.p, 0, 4, s));
+    const int *labs = W.tree_lab.as<int>();
+    for (int t = 0; t < tr.n; ++t) {
+        const int nlab = tr.off[t + 1] - tr.off[t];
+        if (tr.c[t] == 0.0 || nlab == 0) continue;
+        hipLaunchKernelGGL((k_tree_col<T>), dim3(ceil_div(N, 256)), dim3(256), 0, s, N, L, y,
+                           labs + tr.off[t], nlab, W.col.as<T>());
+        int *perm = column_pair_sums<T>(ctx, W, W.col.as<T>(), 1, 0, levels);
+        hipLaunchKernelGGL((k_lp_add_tree<T>), dim3(ceil_div(N, 256)), dim3(256), 0, s, N,
+                           L, perm, W.acc.as<T>(), T(tr.c[t]), labs + tr.off[t], nlab, g);
+        DCRF_CHECK_LAUNCH();
+    }
+    return finish_subgradient<T>(ctx, W, g, y, NL);
 }
 
 template <typename T>
@@ -841,16 +981,16 @@ void project_t(dcrf_ctx *ctx, const T *src, const T *g, T beta, int L, T *dst) {
     DCRF_CHECK_LAUNCH();
 }
 
-template <typename T>
-void lp_descent_t(dcrf_ctx *ctx, const T *phi, int L, T *y, int steps,
-                  double beta0, double *best, T *best_y, double *hist) {
-    LPWork &W = lp_work(ctx);
-    lp_prepare<T>(ctx, W, L);
+// projected subgradient descent (Alg. lp_subgrad, Alg. rHST):
+// y <- Pi(y - beta0 / (1 + t) g(y)), keeping the best objective seen
+template <typename T, typename Subgradient>
+void descent_t(dcrf_ctx *ctx, LPWork &W, int L, T *y, int steps, double beta0,
+               double *best, T *best_y, double *hist, Subgradient subgradient) {
     const size_t NL = (size_t)ctx->N * L;
     double b = INFINITY;
     for (int t = 0; t < steps; ++t) {
         T *g = W.g.as<T>();
-        const double S = lp_subgradient_t<T>(ctx, phi, L, y, g);
+        const double S = subgradient(g);
         if (hist) hist[t] = S;
         if (S < b) {
             b = S;
@@ -861,6 +1001,24 @@ void lp_descent_t(dcrf_ctx *ctx, const T *phi, int L, T *y, int steps,
         project_t<T>(ctx, y, g, T(beta0 / (1.0 + t)), L, y);
     }
     if (best) *best = b;
+}
+
+template <typename T>
+void lp_descent_t(dcrf_ctx *ctx, const T *phi, int L, T *y, int steps,
+                  double beta0, double *best, T *best_y, double *hist) {
+    LPWork &W = lp_work(ctx);
+    lp_prepare<T>(ctx, W, L);
+    descent_t<T>(ctx, W, L, y, steps, beta0, best, best_y, hist,
+                 [&](T *g) { return lp_subgradient_t<T>(ctx, phi, L, y, g); });
+}
+
+template <typename T>
+void lp_descent_tree_t(dcrf_ctx *ctx, const T *phi, int L, T *y, const TreeSpec &tr,
+                       int steps, double beta0, double *best, T *best_y, double *hist) {
+    LPWork &W = lp_work(ctx);
+    lp_prepare<T>(ctx, W, L);
+    descent_t<T>(ctx, W, L, y, steps, beta0, best, best_y, hist,
+                 [&](T *g) { return lp_subgradient_tree_t<T>(ctx, phi, L, y, g, tr); });
 }
 
 }  // namespace
@@ -875,7 +1033,7 @@ void lp_release(dcrf_ctx *ctx) {
         (void)hipEventDestroy(W->ev_done);
     }
     for (DevBuf *b : {&W->keys, &W->keys2, &W->vals, &W->vals2, &W->hist, &W->g,
-                      &W->part, &W->acc})
+                      &W->part, &W->acc, &W->col, &W->tree_lab})
         b->release();
     for (auto &P : W->lat)
         for (DevBuf *b : {&P.hkeys, &P.slot_vid, &P.ent_slot, &P.ent_id,
@@ -907,6 +1065,63 @@ void lp_descent(dcrf_ctx *ctx, const void *unary, int L, void *y, int steps,
         lp_descent_t<float>(ctx, static_cast<const float *>(unary), L,
                             static_cast<float *>(y), steps, beta0, best,
                             static_cast<float *>(best_y), hist);
+}
+
+TreeSpec tree_spec(const int32_t *parent, const double *c, int n, int L) {
+    if (n < L || n > kMaxTreeNodes)
+        fail(DCRF_EINVAL, "n_nodes must be in [L, " + std::to_string(kMaxTreeNodes) + "]");
+    int roots = 0;
+    for (int t = 0; t < n; ++t) {
+        if (parent[t] < -1 || parent[t] >= n || parent[t] == t)
+            fail(DCRF_EINVAL, "parent[" + std::to_string(t) + "] is not a node index or -1");
+        if (parent[t] >= 0 && parent[t] < L)
+            fail(DCRF_EINVAL, "a label's node (0..L-1) cannot be a parent");
+        if (parent[t] == -1) ++roots;
+        if (!std::isfinite(c[t]) || c[t] < 0.0)
+            fail(DCRF_EINVAL, "the subtree weights c must be finite and >= 0");
+    }
+    if (roots != 1) fail(DCRF_EINVAL, "the tree must have exactly one root (parent -1)");
+    std::vector<std::vector<int>> labs(n);
+    for (int k = 0; k < L; ++k) {
+        int t = k, hops = 0;
+        while (t >= 0) {
+            if (++hops > n) fail(DCRF_EINVAL, "parent[] has a cycle");
+            labs[t].push_back(k);
+            t = parent[t];
+        }
+    }
+    TreeSpec tr;
+    tr.n = n;
+    tr.c.assign(c, c + n);
+    tr.off.push_back(0);
+    for (int t = 0; t < n; ++t) {
+        tr.lab.insert(tr.lab.end(), labs[t].begin(), labs[t].end());
+        tr.off.push_back(int(tr.lab.size()));
+    }
+    return tr;
+}
+
+double lp_subgradient_tree(dcrf_ctx *ctx, const void *unary, int L, const void *y,
+                           const TreeSpec &tr, void *g) {
+    if (ctx->dtype == DCRF_F64)
+        return lp_subgradient_tree_t<double>(ctx, static_cast<const double *>(unary), L,
+                                             static_cast<const double *>(y),
+                                             static_cast<double *>(g), tr);
+    return lp_subgradient_tree_t<float>(ctx, static_cast<const float *>(unary), L,
+                                        static_cast<const float *>(y),
+                                        static_cast<float *>(g), tr);
+}
+
+void lp_descent_tree(dcrf_ctx *ctx, const void *unary, int L, void *y, const TreeSpec &tr,
+                     int steps, double beta0, double *best, void *best_y, double *hist) {
+    if (ctx->dtype == DCRF_F64)
+        lp_descent_tree_t<double>(ctx, static_cast<const double *>(unary), L,
+                                  static_cast<double *>(y), tr, steps, beta0, best,
+                                  static_cast<double *>(best_y), hist);
+    else
+        lp_descent_tree_t<float>(ctx, static_cast<const float *>(unary), L,
+                                 static_cast<float *>(y), tr, steps, beta0, best,
+                                 static_cast<float *>(best_y), hist);
 }
 
 void project_simplex(dcrf_ctx *ctx, const void *v, int L, void *y) {

@@ -81,6 +81,22 @@ k_label_present(const int *__restrict__ seg, int nimg, int L, const T *__restric
     }
 }
 
+// flags[x_a] = 1 for every pixel; counters[0] = 1 for a label outside [0, L)
+__global__ void __launch_bounds__(kTP)
+k_labels_used(const int *__restrict__ seg, int nimg, int L, const int32_t *__restrict__ x,
+              int *__restrict__ flags, int *__restrict__ bad) {
+    int lo, hi;
+    tile_range(seg, nimg, kTP, blockIdx.x, lo, hi);
+    const int a = lo + (int)threadIdx.x;
+    if (a >= hi) return;
+    const int k = x[a];
+    if (k < 0 || k >= L) {
+        atomicOr(bad, 1);
+        return;
+    }
+    if (flags[k] == 0) atomicOr(&flags[k], 1);
+}
+
 // dst[a][k] = src[a][idx[k]] (N x L -> N x S)
 template <typename T>
 __global__ void k_gather_cols(int N, int L, int S, const int32_t *__restrict__ idx,
@@ -138,6 +154,24 @@ int present_labels_t(dcrf_ctx *ctx, const T *y, int L, double tau, int32_t *out)
     return n;
 }
 
+int labels_used_t(dcrf_ctx *ctx, const int32_t *x, int L, int32_t *out) {
+    const hipStream_t st = ctx->stream;
+    ctx->small.ensure(4096, st);
+    int *flags = ctx->small.as<int>();
+    hipLaunchKernelGGL((k_fill_ints), dim3(1), dim3(256), 0, st, flags, L + 1, 0);
+    hipLaunchKernelGGL((k_labels_used), dim3(seg_tiles(ctx, kTP)), dim3(kTP), 0, st,
+                       ctx->seg.as<int>(), ctx->nimg, L, x, flags, flags + L);
+    DCRF_CHECK_LAUNCH();
+    int h[257];
+    DCRF_TRY_HIP(hipMemcpyAsync(h, flags, (size_t)(L + 1) * 4, hipMemcpyDeviceToHost, st));
+    DCRF_TRY_HIP(hipStreamSynchronize(st));
+    if (h[L]) fail(DCRF_EINVAL, "a label lies outside [0, L)");
+    int n = 0;
+    for (int i = 0; i < L; ++i)
+        if (h[i]) out[n++] = i;
+    return n;
+}
+
 template <typename T>
 void lp_descent_subset_t(dcrf_ctx *ctx, const T *phi, int L, T *y, const int32_t *subset,
                          int S, int steps, double beta0, double *best, T *best_y,
@@ -184,6 +218,10 @@ int present_labels(dcrf_ctx *ctx, const void *y, int L, double tau, int32_t *out
     if (ctx->dtype == DCRF_F64)
         return present_labels_t<double>(ctx, static_cast<const double *>(y), L, tau, out);
     return present_labels_t<float>(ctx, static_cast<const float *>(y), L, tau, out);
+}
+
+int labels_used(dcrf_ctx *ctx, const int32_t *labels, int L, int32_t *out) {
+    return labels_used_t(ctx, labels, L, out);
 }
 
 void lp_descent_subset(dcrf_ctx *ctx, const void *unary, int L, void *y,

@@ -175,6 +175,8 @@ size_t workspace_bound(int B, const int *H, const int *W, int L,
         s.add(NL * e);
         s.add(1024 * 8);
         s.add(N * e);
+        s.add(N * e);                                  // a subtree's column y(T)
+        s.add(size_t(kMaxTreeNodes) * size_t(L) * 4);  // the subtrees' label lists
         for (int m = 0; m < nk; ++m) {
             const size_t D1 = k[m].use_rgb ? 6 : 3, E = N * D1;
             s.add(2 * E * 8);

@@ -94,8 +94,12 @@ PROTOTYPES = {
     "dcrf_lp_subgradient": (_I, [_P, _P, _I, _P, _P, _PD]),
     "dcrf_lp_descent": (_I, [_P, _P, _I, _P, _I, _D, _PD, _P, _PD]),
     "dcrf_project_simplex": (_I, [_P, _P, _I, _P]),
+    "dcrf_lp_subgradient_tree": (_I, [_P, _P, _I, _P, _I, _P, _P, _P, _PD]),
+    "dcrf_lp_descent_tree": (_I, [_P, _P, _I, _P, _I, _P, _P, _I, _D, _PD, _P, _PD]),
     "dcrf_round_kt": (_I, [_P, _P, _I, _P, _P, _I, _P, ctypes.POINTER(_I)]),
+    "dcrf_set_lp_leaf": (_I, [_P, _I]),
     "dcrf_present_labels": (_I, [_P, _P, _I, _D, _P, ctypes.POINTER(_I)]),
+    "dcrf_labels_used": (_I, [_P, _P, _I, _P, ctypes.POINTER(_I)]),
     "dcrf_lp_descent_subset": (_I, [_P, _P, _I, _P, _P, _I, _I, _D, _PD, _P, _PD]),
     "dcrf_fw_saved_size": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_size_t)]),
     "dcrf_fw_forward": (_I, [_P, _P, _P, _I, _PD, _I, _P, _P]),
@@ -399,6 +403,11 @@ class Context:
             self._arg(g), ctypes.byref(S)))
         return g, S.value
 
+    def set_lp_leaf(self, leaf: int):
+        """exact pair sums inside divide-and-conquer nodes of at most `leaf`
+        positions (0: the plain recursion)"""
+        self._check(_lib.dcrf_set_lp_leaf(self._h, int(leaf)))
+
     def lp_descent(self, unary, y, steps: int, beta0: float,
                    best_y: torch.Tensor | None = None):
         """Projected subgradient descent in place on y; returns (best S_LP,
@@ -410,6 +419,40 @@ class Context:
             self._h, self._arg(unary), unary.shape[1], self._arg(y), steps,
             float(beta0), ctypes.byref(best),
             None if best_y is None else self._arg(best_y), hist))
+        return best.value, list(hist[:steps])
+
+    @staticmethod
+    def _tree(parent, c):
+        n = len(parent)
+        if len(c) != n:
+            raise ValueError("parent and c must have one entry per node")
+        return (n, (ctypes.c_int32 * n)(*[int(v) for v in parent]),
+                (ctypes.c_double * n)(*[float(v) for v in c]))
+
+    def lp_subgradient_tree(self, unary, y, parent, c, g: torch.Tensor | None = None):
+        """(g, S) of the LP for the tree metric given by parent[] (node k < L
+        is label k) and the subtree weights c"""
+        g = torch.empty_like(y) if g is None else g
+        n, pa, ca = self._tree(parent, c)
+        S = ctypes.c_double()
+        self._stream()
+        self._check(_lib.dcrf_lp_subgradient_tree(
+            self._h, self._arg(unary), unary.shape[1], self._arg(y), n, pa, ca,
+            self._arg(g), ctypes.byref(S)))
+        return g, S.value
+
+    def lp_descent_tree(self, unary, y, parent, c, steps: int, beta0: float,
+                        best_y: torch.Tensor | None = None):
+        """projected subgradient descent on the tree LP, in place on y;
+        returns (best objective, history)"""
+        n, pa, ca = self._tree(parent, c)
+        hist = (ctypes.c_double * max(steps, 1))()
+        best = ctypes.c_double()
+        self._stream()
+        self._check(_lib.dcrf_lp_descent_tree(
+            self._h, self._arg(unary), unary.shape[1], self._arg(y), n, pa, ca, steps,
+            float(beta0), ctypes.byref(best), None if best_y is None else self._arg(best_y),
+            hist))
         return best.value, list(hist[:steps])
 
     def round_kt(self, y, round_label: torch.Tensor, round_theta: torch.Tensor):
@@ -434,6 +477,14 @@ class Context:
         self._stream()
         self._check(_lib.dcrf_present_labels(self._h, self._arg(y), L, float(tau), out,
                                              ctypes.byref(n)))
+        return list(out[:n.value])
+
+    def labels_used(self, labels: torch.Tensor, L: int):
+        out = (ctypes.c_int32 * L)()
+        n = ctypes.c_int()
+        self._stream()
+        self._check(_lib.dcrf_labels_used(self._h, self._arg(labels, torch.int32, "labels"),
+                                          L, out, ctypes.byref(n)))
         return list(out[:n.value])
 
     def lp_descent_subset(self, unary, y, subset, steps: int, beta0: float,

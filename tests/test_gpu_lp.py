@@ -195,3 +195,64 @@ def test_lp_descent_fp32_steps_160x120():
         S_hist_g.append(hist[0])
         y = y_next.astype(np.float32).astype(np.float64)
     print("S_LP history oracle", S_hist_o, "gpu", S_hist_g, flush=True)
+
+
+@pytest.mark.parametrize("H,W,L,leaf,dtype,rtol", [
+    (24, 32, 3, 16, torch.float64, 1e-10),
+    (13, 11, 4, 256, torch.float64, 1e-10),   # N = 143: one leaf, all exact
+    (48, 64, 5, 200, torch.float32, 1e-5),
+])
+def test_lp_leaf_exact_matches_oracle(H, W, L, leaf, dtype, rtol):
+    # the leaf-exact divide and conquer (App. E with exact pairs inside the
+    # nodes of at most `leaf` positions) against the oracle's, same bar as
+    # the plain recursion
+    im = synth.voronoi_image(H, W, L, seed=H * W + L + 1, regions=6)
+    y = synth.random_simplex_points(im.N, L, seed=9, sparsity=0.5)
+    ctx = ctx_for(im, dtype)
+    ctx.set_lp_leaf(leaf)
+    g, S = ctx.lp_subgradient(T(im.unary, dtype), T(y, dtype))
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    mag = np.abs(im.unary).copy()
+
+    def pair(order):
+        U, Lo = O.lp_pair_sums_dnc(model, order, "lattice", leaf=leaf)
+        pair.rec.append((U, Lo))
+        return U, Lo
+    pair.rec = []
+    go, So = O.lp_subgradient(im.unary, y, pair)
+    for i, (U, Lo) in enumerate(pair.rec):
+        mag[:, i] += np.abs(U) + np.abs(Lo)
+    err = np.abs(g.cpu().numpy().astype(np.float64) - go)
+    print(f"[lp leaf {leaf}] {H}x{W}: max rel err {(err / mag).max():.3g}", flush=True)
+    assert (err <= rtol * mag).all()
+    assert abs(S - So) <= rtol * (np.abs(mag) * y).sum()
+    if leaf >= im.N:
+        # one leaf holds every position: the exact filter mode's sums
+        ctx.set_filter_mode("exact")
+        ge, Se = ctx.lp_subgradient(T(im.unary, dtype), T(y, dtype))
+        assert (g - ge).abs().max().item() <= 1e-12 * float(mag.max())
+
+
+def test_lp_leaf_exact_fp32_500x375_sampled_entries():
+    # the leaf cutoff the LP bench reports (256: 10 lattice levels instead of
+    # 18, then 1024 exact leaves of at most 184 positions) at the timed size
+    im = synth.make("voronoi_500x375_L21")
+    N = im.N
+    y = synth.random_simplex_points(N, im.L, seed=12, sparsity=0.6)
+    ctx = ctx_for(im, torch.float32)
+    ctx.set_lp_leaf(256)
+    g, _ = ctx.lp_subgradient(T(im.unary, torch.float32), T(y, torch.float32))
+    g = g.cpu().numpy().astype(np.float64)
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    phi32 = im.unary.astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(6)
+    for i in (3, 17):
+        order = O.sorted_order(y[:, i])
+        ends = order[[0, 1, N // 2 - 1, N // 2, N - 2, N - 1]]
+        at = np.unique(np.concatenate([rng.choice(N, 160, replace=False), ends]))
+        U, Lo = O.lp_pair_sums_dnc(model, order, "lattice", at=at, leaf=256)
+        go = phi32[at, i] + U[at] - Lo[at]
+        mag = np.abs(phi32[at, i]) + U[at] + Lo[at]
+        rel = np.abs(g[at, i] - go) / mag
+        print(f"[lp leaf 500x375] label {i}: max rel err {rel.max():.3g}", flush=True)
+        assert (rel <= 1e-5).all()

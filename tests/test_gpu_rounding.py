@@ -204,3 +204,15 @@ def test_lp_descent_subset_rejects_bad_subsets():
         with pytest.raises(dcrf.DcrfError) as e:
             ctx.lp_descent_subset(phi, y, bad, 1, 1e-3)
         assert dcrf.STATUS[e.value.status] == "DCRF_EINVAL", bad
+
+
+def test_labels_used_matches_unique():
+    from paper_1608_06192_amd import dcrf
+    im = synth.voronoi_image(33, 41, 9, seed=6, regions=5)
+    ctx = ctx_for(im, torch.float32)
+    x = np.random.default_rng(4).choice([0, 2, 3, 7], size=im.N).astype(np.int32)
+    assert ctx.labels_used(torch.from_numpy(x).to(dev()), 9) == [0, 2, 3, 7]
+    x[5] = 9
+    with pytest.raises(dcrf.DcrfError) as e:
+        ctx.labels_used(torch.from_numpy(x).to(dev()), 9)
+    assert dcrf.STATUS[e.value.status] == "DCRF_EINVAL"
