@@ -229,6 +229,52 @@ def summarize_pmc(fetch_csv, write_csv, command):
     print("\n".join(lines))
 
 
+def summarize_busy(csv_path, out_path, command):
+    """Write a summary of the texture-address (TA) and texture-data (TD) unit
+    busy fractions per kernel from one rocprofv3 --pmc run of TA_BUSY_avr,
+    TD_TD_BUSY_sum, TCC_BUSY_avr and GRBM_GUI_ACTIVE: busy cycles over the
+    active cycles of the dispatch. GRBM_GUI_ACTIVE reads the sum over the 8
+    XCDs (a 17.9 us dispatch reads about 472 000, eight windows of about 59 000
+    cycles), so the per-XCD cycle count is an eighth of it; TD is summed over
+    its 256 instances (one per CU) and averaged here."""
+    import csv
+    per = {}
+    for r in csv.DictReader(open(csv_path)):
+        k = _short(r["Kernel_Name"])
+        d = per.setdefault(k, {}).setdefault(r.get("Dispatch_Id", r.get("Correlation_Id")), {})
+        d[r["Counter_Name"]] = float(r["Counter_Value"])
+    lines = ["# Vector-memory pipeline busy fractions per dispatch: TA (address",
+             "# unit) and TD (data return) busy cycles, and L2 (TCC) busy, over",
+             "# the per-XCD active cycles (GRBM_GUI_ACTIVE / 8); averaged over the",
+             "# kernel's dispatches. at::native::vectorized_elementwise is the plain",
+             "# 256 MiB copy (torch.mul) run beside the library as a reference.",
+             "# Workload: bench.py (voronoi 500x375, L=21, FP32, both kernels).",
+             "# Command (repository root on the GPU host, TMPDIR=/tmp):"]
+    lines += ["#   " + c for c in command]
+    lines += ["# Summary written by: python bench.py --summarize-busy <csv> <out>",
+              f"{'kernel':40s} {'dispatches':>10s} {'TA busy':>8s} {'TD busy':>8s} "
+              f"{'L2 busy':>8s}"]
+    rows = []
+    for k, ds in per.items():
+        ta, td, tcc = [], [], []
+        for c in ds.values():
+            g = c.get("GRBM_GUI_ACTIVE", 0.0) / 8.0
+            if g <= 0:
+                continue
+            ta.append(c.get("TA_BUSY_avr", 0.0) / g)
+            td.append(c.get("TD_TD_BUSY_sum", 0.0) / 256.0 / g)
+            tcc.append(c.get("TCC_BUSY_avr", 0.0) / g)
+        if ta:
+            rows.append((k, len(ta), sum(ta) / len(ta), sum(td) / len(td),
+                         sum(tcc) / len(tcc)))
+    rows.sort(key=lambda r: -r[1])
+    for k, n, a, b, c in rows[:40]:
+        lines.append(f"{k[:40]:40s} {n:10d} {100 * a:7.1f}% {100 * b:7.1f}% {100 * c:7.1f}%")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def traffic_bytes(kernel):
     """HBM bytes per launch of `kernel` from TRAFFIC_FILE, each counter scaled
     by expected / measured of the calibration copy; None when the file is
@@ -434,20 +480,38 @@ def extensions(torch, dcrf, synth, dev, kernels):
             g[idx, g_t] = -1.0 / (n * y[idx, g_t].clamp_min(1e-12))
             c.fw_backward(p, mu, iters, saved, g)
 
+    # steady-state batched Frank-Wolfe iterations (one launch per stage over
+    # all 16 images): the time of 60 iterations minus that of 10, per
+    # iteration, against the algorithmic bytes of one iteration
+    blat = [bctx.lattice_info(m) for m in range(len(kernels))]
+    yb = torch.empty_like(bphi)
+
+    def bsolve(k):
+        yb.copy_(torch.softmax(-bphi, dim=1))
+        bctx.qp_frank_wolfe(bphi, mu, yb, k, trace=False)
+    t10 = _timed(torch, lambda: bsolve(10), 3)
+    t60 = _timed(torch, lambda: bsolve(60), 3)
+    it_ms = (t60 - t10) / 50
+    npx = sum(x.N for x in ims)
+    it_bytes = fw_step_bytes(npx, L, 4, blat)
     t_bf = _timed(torch, bfwd, 3)
     t_bfb = _timed(torch, bfwdbwd, 2)
     t_sf = _timed(torch, seq_fwd, 2)
     t_sfb = _timed(torch, seq_fwdbwd, 1)
-    npx = sum(x.N for x in ims)
     out["batch"] = dict(workload="16 Voronoi images, H and W ~ U{240..500}, "
                                  "L=21, FP32, 10 FW iterations each",
-                        pixels=npx, autotune=tune,
+                        pixels=npx, autotune=tune, lattice_vertices=[M for d, M in blat],
+                        fw_iteration_ms=it_ms, fw_iteration_bytes=it_bytes,
+                        fw_iteration_GBps=it_bytes / it_ms / 1e6,
+                        fw_iteration_frac_of_hbm_peak=it_bytes / it_ms / 1e6 / HBM_PEAK_GBPS,
                         batched_forward_ms=t_bf, batched_fwd_bwd_ms=t_bfb,
                         sequential_plain_forward_ms=t_sf,
                         sequential_fwd_bwd_ms=t_sfb,
                         batched_fwd_bwd_over_sequential_forward=t_bfb / t_sf,
                         forward_speedup=t_sf / t_bf,
                         fwd_bwd_speedup=t_sfb / t_bfb)
+    log(f"[bench] batch of 16: steady FW iteration {it_ms * 1e3:.1f} us, "
+        f"{it_bytes / 1e6:.1f} MB algorithmic = {it_bytes / it_ms / 1e6:.0f} GB/s")
     log(f"[bench] batch of 16 ({npx} px): batched fwd {t_bf:.2f} ms, fwd+bwd "
         f"{t_bfb:.2f} ms; sequential fwd {t_sf:.2f} ms, fwd+bwd {t_sfb:.2f} ms; "
         f"tune {tune}")
@@ -492,6 +556,9 @@ def main():
     ap.add_argument("--summarize-trace", nargs=2, metavar=("STATS_CSV", "OUT"),
                     help="write a kernel statistics summary from a rocprofv3 "
                          "--stats CSV and exit")
+    ap.add_argument("--summarize-busy", nargs=2, metavar=("CSV", "OUT"),
+                    help="write a TA/TD busy summary from a rocprofv3 --pmc CSV "
+                         "and exit")
     ap.add_argument("--command", action="append", default=[],
                     help="profiler command line to record in a summary")
     ap.add_argument("--note", default="Kernel statistics",
@@ -502,6 +569,9 @@ def main():
         return
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace, args.command, args.note)
+        return
+    if args.summarize_busy:
+        summarize_busy(*args.summarize_busy, args.command)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -571,10 +641,26 @@ def main():
     torch.cuda.synchronize()
     f_ms = ev0.elapsed_time(ev1) / args.filter_reps
     f_bytes = lattice_bytes(N, L, 4, lat)
+    # cold: each call after a 512 MB write that evicts the L2s and the
+    # 256 MB Infinity Cache (median of 5)
+    flush = torch.empty(128 << 20, device=dev, dtype=f32)
+    cold = []
+    for _ in range(5):
+        flush.fill_(1.0)
+        ev0.record()
+        ctx.filter(Y, out=out)
+        ev1.record()
+        torch.cuda.synchronize()
+        cold.append(ev0.elapsed_time(ev1))
+    del flush
+    c_ms = sorted(cold)[2]
     filt = dict(ms=f_ms, GBps=f_bytes / f_ms / 1e6, bytes=f_bytes,
-                frac_of_hbm_peak=f_bytes / f_ms / 1e6 / HBM_PEAK_GBPS)
+                frac_of_hbm_peak=f_bytes / f_ms / 1e6 / HBM_PEAK_GBPS,
+                cold_ms=c_ms, cold_GBps=f_bytes / c_ms / 1e6,
+                cold_frac_of_hbm_peak=f_bytes / c_ms / 1e6 / HBM_PEAK_GBPS)
     log(f"[bench] dense filter L=21: {f_ms * 1e3:.1f} us, "
-        f"{filt['GBps']:.0f} GB/s algorithmic")
+        f"{filt['GBps']:.0f} GB/s algorithmic; after a 512 MB flush "
+        f"{c_ms * 1e3:.1f} us, {filt['cold_GBps']:.0f} GB/s")
 
     # ---- DC_neg steps at the same size (one filter call per step) ---------
     yd = y.clone()
