@@ -221,7 +221,8 @@ class Model:
 
     mode "exact": the O(N^2) sum. mode "lattice": each K_m replaced by its
     permutohedral approximation; the self term subtracted is still the exact
-    (sum_m w_m) Y_a.
+    (sum_m w_m) Y_a. mode "separable": the kernels on position alone (no
+    colour) by the exact O(N^2) sum, the others by the lattice.
     """
 
     def __init__(self, H: int, W: int, rgb: np.ndarray, kernels, mode="lattice"):
@@ -231,8 +232,10 @@ class Model:
         self.feats = [features(H, W, rgb, k) for k in self.kernels]
         self.w = np.array([k.weight for k in self.kernels], dtype=np.float64)
         self.mode = mode
-        self.lattices = ([Lattice(f) for f in self.feats]
-                         if mode == "lattice" else None)
+        self.exact_m = [mode == "exact" or (mode == "separable" and not k.use_rgb)
+                        for k in self.kernels]
+        self.lattices = (None if mode == "exact" else
+                         [None if e else Lattice(f) for f, e in zip(self.feats, self.exact_m)])
 
     def with_weights(self, w) -> "Model":
         m = object.__new__(Model)
@@ -242,7 +245,7 @@ class Model:
 
     def Km(self, m: int, Y: np.ndarray, reverse: bool = False) -> np.ndarray:
         """K_m Y including the diagonal term (exact or lattice)."""
-        if self.mode == "exact":
+        if self.exact_m[m]:
             f = self.feats[m]
             return gauss_exact(f, f, Y, exclude_same_index=False)
         return self.lattices[m].filter(Y, reverse=reverse)
@@ -256,7 +259,7 @@ class Model:
             return out
         out = -self.w.sum() * Y
         for m in range(len(self.feats)):
-            out = out + self.w[m] * self.lattices[m].filter(Y, reverse=reverse)
+            out = out + self.w[m] * self.Km(m, Y, reverse=reverse)
         return out
 
     def dense_K(self) -> np.ndarray:

@@ -267,3 +267,51 @@ def test_lattice_collinear_with_exact_on_image():
     cos = a @ b / np.linalg.norm(a) / np.linalg.norm(b)
     assert cos > 0.99
     assert 0.7 < (b / a).mean() < 1.5
+
+
+def test_spatial_gaussian_factorises_into_two_one_dimensional_passes():
+    # the spatial kernel exp(-((x_a-x_b)^2 + (y_a-y_b)^2) / (2 theta^2))
+    # (features p / theta, eq. gaussiankernel with App. G's scaling) is the
+    # product of a Gaussian in x and one in y, so K Y is a convolution along
+    # the rows followed by one along the columns, each with the taps
+    # g(t) = exp(-t^2 / (2 theta^2)); the taps below 2^-60 of the centre
+    # (|t| > theta sqrt(120 ln 2)) change no FP64 result
+    H, W, theta = 11, 17, 3.0
+    rng = np.random.default_rng(0)
+    Y = rng.normal(size=(H * W, 3))
+    k = O.Kernel(0, theta, 0.0, 1.0)
+    f = O.features(H, W, np.zeros((H * W, 3), np.float32), k)
+    ref = O.gauss_exact(f, f, Y, exclude_same_index=False)
+    R = int(math.ceil(theta * math.sqrt(120 * math.log(2))))
+    g = np.exp(-np.arange(-R, R + 1) ** 2 / (2 * theta ** 2))
+    img = Y.reshape(H, W, 3)
+    rows = np.zeros_like(img)
+    for x in range(W):
+        for t in range(-R, R + 1):
+            if 0 <= x + t < W:
+                rows[:, x] += g[t + R] * img[:, x + t]
+    both = np.zeros_like(img)
+    for yy in range(H):
+        for t in range(-R, R + 1):
+            if 0 <= yy + t < H:
+                both[yy] += g[t + R] * rows[yy + t]
+    assert np.allclose(both.reshape(-1, 3), ref, rtol=1e-13, atol=1e-13)
+
+
+def test_separable_mode_is_exact_spatial_plus_lattice_bilateral():
+    # mode "separable": spatial kernels by the exact sum, the others by the
+    # lattice; with one kind of kernel it is the exact or the lattice model
+    H, W = 9, 12
+    rng = np.random.default_rng(1)
+    rgb = rng.uniform(0, 255, size=(H * W, 3)).astype(np.float32)
+    Y = rng.random((H * W, 4))
+    bil = O.Kernel(1, 5.0, 30.0, 2.0)
+    spa = O.Kernel(0, 2.0, 0.0, 1.5)
+    both = O.Model(H, W, rgb, [bil, spa], mode="separable").Kp(Y)
+    lat = O.Model(H, W, rgb, [bil], mode="lattice")
+    ex = O.Model(H, W, rgb, [spa], mode="exact")
+    assert np.allclose(both, lat.Kp(Y) + ex.Kp(Y), rtol=1e-13, atol=1e-13)
+    assert np.allclose(O.Model(H, W, rgb, [spa], mode="separable").Kp(Y), ex.Kp(Y),
+                       rtol=1e-14, atol=1e-14)
+    assert np.allclose(O.Model(H, W, rgb, [bil], mode="separable").Kp(Y), lat.Kp(Y),
+                       rtol=1e-14, atol=1e-14)
