@@ -40,7 +40,11 @@ Beside it the JSON line reports:
   per stage over the concatenated lattices, autotuned launch shapes) against
   16 sequential single-image forwards and forward+backwards;
 * lattice_error: the lattice filter against the exact O(N^2) sum at 320x213
-  (ratio of means, cosine and relative 2-norm error of K'Y for a random Y).
+  (ratio of means, cosine and relative 2-norm error of K'Y for a random Y),
+  and the same for the separable mode (spatial kernel exact, bilateral on
+  the lattice);
+* lattice_filter.separable_ms / separable_fw_iteration_us: the dense filter
+  and a Frank-Wolfe iteration in the separable mode at 500x375.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -527,10 +531,14 @@ def extensions(torch, dcrf, synth, dev, kernels):
     exact = ctx.filter(Y, exact=True)
     num = float((lat * exact).sum())
     cos = num / float(lat.norm() * exact.norm())
+    sep = ctx.filter(Y, separable=True)
     out["lattice_error"] = dict(
         workload="voronoi 320x213, both kernels, K'Y for Y ~ U[0,1]^(N x 4), FP64",
         ratio_of_means=float(lat.mean() / exact.mean()), cosine=cos,
-        rel_l2_error=float((lat - exact).norm() / exact.norm()))
+        rel_l2_error=float((lat - exact).norm() / exact.norm()),
+        separable_ratio_of_means=float(sep.mean() / exact.mean()),
+        separable_cosine=float((sep * exact).sum() / (sep.norm() * exact.norm())),
+        separable_rel_l2_error=float((sep - exact).norm() / exact.norm()))
     log(f"[bench] lattice vs exact: {out['lattice_error']}")
     return out
 
@@ -661,6 +669,28 @@ def main():
     log(f"[bench] dense filter L=21: {f_ms * 1e3:.1f} us, "
         f"{filt['GBps']:.0f} GB/s algorithmic; after a 512 MB flush "
         f"{c_ms * 1e3:.1f} us, {filt['cold_GBps']:.0f} GB/s")
+
+    # ---- the separable mode: the spatial kernel exact by two 1-D passes --
+    ev0.record()
+    for _ in range(20):
+        ctx.filter(Y, out=out, separable=True)
+    ev1.record()
+    torch.cuda.synchronize()
+    sep_ms = ev0.elapsed_time(ev1) / 20
+    ctx.set_filter_mode("separable")
+    ysep = y0.clone()
+    ctx.qp_frank_wolfe(phi, mu, ysep, 5, trace=False)
+    ysep = y0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.qp_frank_wolfe(phi, mu, ysep, 50, trace=False)
+    torch.cuda.synchronize()
+    sep_fw_us = (time.perf_counter() - t0) * 1e6 / 50
+    ctx.set_filter_mode("lattice")
+    filt["separable_ms"] = sep_ms
+    filt["separable_fw_iteration_us"] = sep_fw_us
+    log(f"[bench] separable mode: dense filter {sep_ms * 1e3:.1f} us, FW iteration "
+        f"{sep_fw_us:.1f} us (50 iterations)")
 
     # ---- DC_neg steps at the same size (one filter call per step) ---------
     yd = y.clone()

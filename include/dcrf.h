@@ -68,12 +68,15 @@ typedef enum { DCRF_F32 = 0, DCRF_F64 = 1 } dcrf_dtype;
 /* How the solvers apply the pixel compatibility. */
 typedef enum {
     DCRF_FILTER_LATTICE = 0, /* permutohedral lattice, O(N) (Sec. 3, App. A) */
-    DCRF_FILTER_EXACT = 1    /* exact O(N^2) Gaussian sum (eq. fb)           */
+    DCRF_FILTER_EXACT = 1,   /* exact O(N^2) Gaussian sum (eq. fb)           */
+    DCRF_FILTER_SEPARABLE = 2 /* position-only kernels exact by two 1-D
+                                 convolutions, the others by the lattice */
 } dcrf_filter_mode;
 
 /* Flags of dcrf_filter. */
 #define DCRF_ADJOINT 1u      /* apply the transpose (blur directions reversed) */
 #define DCRF_EXACT 2u        /* use the exact O(N^2) sum for this call        */
+#define DCRF_SEPARABLE 4u    /* the separable filter mode for this call       */
 
 /* One Gaussian kernel of the pixel compatibility (eq. pairwise, App. G). */
 typedef struct {
@@ -224,7 +227,18 @@ int dcrf_set_tune(dcrf_ctx *ctx, const dcrf_tune *tune);
  * lattices; recomputes r. */
 int dcrf_set_weights(dcrf_ctx *ctx, const double *w, int nk);
 
-/* Choose lattice or exact filtering for the solvers (default lattice). */
+/* Choose how the solvers filter (default DCRF_FILTER_LATTICE).
+ * DCRF_FILTER_SEPARABLE applies every kernel on position alone (no colour
+ * features) exactly: its Gaussian factors into one along x and one along y
+ * (eq. gaussiankernel with App. G's scaling), so K Y is a convolution of
+ * each channel along the rows and then along the columns with taps
+ * exp(-t^2 / (2 theta^2)), |t| <= min(ceil(theta sqrt(120 ln 2)), max(H, W) - 1)
+ * (the dropped taps lie below 2^-60 of the centre); the other kernels stay on
+ * the lattice. The QP apply, Frank-Wolfe, DC_gen, DC_neg and the energy then
+ * take a dense K'Y per filter (as in the exact mode). The LP, the
+ * differentiation, the allocation-free solve, the autotuner and batch
+ * contexts give DCRF_EUNSUPPORTED in the exact and separable modes (the LP
+ * accepts the exact mode). */
 int dcrf_set_filter_mode(dcrf_ctx *ctx, int mode);
 
 /* Lattice of kernel m: feature dimension d and number of vertices. */
@@ -244,8 +258,9 @@ int dcrf_lattice_export(dcrf_ctx *ctx, int m, int32_t *keys, int32_t *vid,
  * out_a = sum_{b != a} sum_m w_m k_m(a, b) in_b  (eq. fb summed over the
  * kernels without the b = a term of eq. labelling-energy). By default each
  * K_m is its permutohedral approximation gamma_d * slice . blur . splat;
- * DCRF_EXACT uses the O(N^2) sum, DCRF_ADJOINT the transpose.
- * in, out: (dev) N x C, 1 <= C <= 256, not aliased. */
+ * DCRF_EXACT uses the O(N^2) sum, DCRF_SEPARABLE the separable mode of
+ * dcrf_set_filter_mode (the two exclude each other), DCRF_ADJOINT the
+ * transpose. in, out: (dev) N x C, 1 <= C <= 256, not aliased. */
 int dcrf_filter(dcrf_ctx *ctx, const void *in, void *out, int C,
                 unsigned flags);
 

@@ -44,6 +44,7 @@ SOURCES = {
     "tiles.hip": [],
     "dcneg.hip": [],
     "rounding.hip": [],
+    "separable.hip": [],
     "noalloc.hip": [],
     "abi.cpp": ["-x", "hip"],
     "workspace.cpp": ["-x", "hip"],

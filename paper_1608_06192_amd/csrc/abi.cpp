@@ -92,6 +92,13 @@ void check_labels(int L) {
     REQUIRE(L >= 1 && L <= 256, "L must be in [1, 256]");
 }
 
+// the LP's pair sums are built for the lattice and exact filter modes only
+void require_lp_mode(dcrf_ctx *ctx) {
+    if (ctx->mode == DCRF_FILTER_SEPARABLE)
+        throw Error{DCRF_EUNSUPPORTED,
+                    "the LP needs the lattice or the exact filter mode"};
+}
+
 }  // namespace
 
 extern "C" {
@@ -125,7 +132,8 @@ static void release_all(dcrf_ctx *ctx) {
           &ctx->fw_Py, &ctx->fw_Ps, &ctx->fw_s, &ctx->fw_sprev, &ctx->fw_part,
           &ctx->fw_scal, &ctx->fw_trace, &ctx->fw_mu, &ctx->potts, &ctx->hist,
           &ctx->errflag, &ctx->seg, &ctx->tiles, &ctx->tile_img_off, &ctx->small,
-          &ctx->sub_phi, &ctx->sub_y, &ctx->sub_best})
+          &ctx->sub_phi, &ctx->sub_y, &ctx->sub_best, &ctx->sep_taps, &ctx->sep_tmp,
+          &ctx->sep_acc})
         b->release();
     ctx->potts_L = 0;
     ctx->potts_dtype = -1;
@@ -226,7 +234,7 @@ int dcrf_set_images(dcrf_ctx *ctx, int B, const int *H, const int *W,
         }
         set_kernels(ctx, kernels, nk, dtype);
         attach_workspace(ctx, workspace, ws_bytes);
-        if (ctx->mode == DCRF_FILTER_EXACT && B > 1)
+        if (ctx->mode != DCRF_FILTER_LATTICE && B > 1)
             throw Error{DCRF_EUNSUPPORTED, "a batch needs the lattice filter mode"};
         if (B == 1) {
             ctx->H = H[0];
@@ -331,9 +339,11 @@ int dcrf_set_weights(dcrf_ctx *ctx, const double *w, int nk) {
 
 int dcrf_set_filter_mode(dcrf_ctx *ctx, int mode) {
     return guarded(ctx, [&] {
-        REQUIRE(mode == DCRF_FILTER_LATTICE || mode == DCRF_FILTER_EXACT,
-                "mode must be DCRF_FILTER_LATTICE or DCRF_FILTER_EXACT");
-        if (mode == DCRF_FILTER_EXACT && ctx->has_image && ctx->nimg > 1)
+        REQUIRE(mode == DCRF_FILTER_LATTICE || mode == DCRF_FILTER_EXACT ||
+                    mode == DCRF_FILTER_SEPARABLE,
+                "mode must be DCRF_FILTER_LATTICE, DCRF_FILTER_EXACT or "
+                "DCRF_FILTER_SEPARABLE");
+        if (mode != DCRF_FILTER_LATTICE && ctx->has_image && ctx->nimg > 1)
             throw Error{DCRF_EUNSUPPORTED, "a batch needs the lattice filter mode"};
         const bool changed = ctx->mode != mode;
         ctx->mode = mode;
@@ -365,11 +375,16 @@ int dcrf_filter(dcrf_ctx *ctx, const void *in, void *out, int C,
         require_image(ctx);
         REQUIRE(in && out && in != out, "in and out must be distinct, non-null");
         REQUIRE(C >= 1 && C <= 256, "C must be in [1, 256]");
-        REQUIRE((flags & ~(DCRF_ADJOINT | DCRF_EXACT)) == 0, "unknown flags");
-        if ((flags & DCRF_EXACT) && ctx->nimg > 1)
-            throw Error{DCRF_EUNSUPPORTED, "the exact filter of a batch is not built"};
-        dcrf::filter_apply(ctx, in, out, C, (flags & DCRF_ADJOINT) != 0,
-                           (flags & DCRF_EXACT) != 0);
+        REQUIRE((flags & ~(DCRF_ADJOINT | DCRF_EXACT | DCRF_SEPARABLE)) == 0,
+                "unknown flags");
+        REQUIRE(!((flags & DCRF_EXACT) && (flags & DCRF_SEPARABLE)),
+                "DCRF_EXACT and DCRF_SEPARABLE exclude each other");
+        if ((flags & (DCRF_EXACT | DCRF_SEPARABLE)) && ctx->nimg > 1)
+            throw Error{DCRF_EUNSUPPORTED, "the exact and separable filters of a batch are not built"};
+        const int kind = (flags & DCRF_EXACT)       ? DCRF_FILTER_EXACT
+                         : (flags & DCRF_SEPARABLE) ? DCRF_FILTER_SEPARABLE
+                                                    : DCRF_FILTER_LATTICE;
+        dcrf::filter_apply(ctx, in, out, C, (flags & DCRF_ADJOINT) != 0, kind);
     });
 }
 
@@ -475,6 +490,7 @@ int dcrf_lp_subgradient(dcrf_ctx *ctx, const void *unary, int L, const void *y,
         check_labels(L);
         REQUIRE(unary && y && g && y != g, "null or aliased argument");
         require_single(ctx);
+        require_lp_mode(ctx);
         dcrf::check_finite(ctx, unary, L);
         dcrf::check_finite(ctx, y, L);
         const double S = dcrf::lp_subgradient(ctx, unary, L, y, g);
@@ -547,6 +563,7 @@ int dcrf_lp_descent(dcrf_ctx *ctx, const void *unary, int L, void *y_inout,
         check_labels(L);
         REQUIRE(unary && y_inout, "null argument");
         require_single(ctx);
+        require_lp_mode(ctx);
         REQUIRE(steps >= 0, "steps must be >= 0");
         REQUIRE(std::isfinite(beta0) && beta0 > 0, "beta0 must be > 0");
         REQUIRE(best_y != y_inout, "best_y must not alias y");
@@ -566,6 +583,7 @@ int dcrf_lp_subgradient_tree(dcrf_ctx *ctx, const void *unary, int L, const void
         check_labels(L);
         REQUIRE(unary && y && g && y != g && parent && c, "null or aliased argument");
         require_single(ctx);
+        require_lp_mode(ctx);
         const dcrf::TreeSpec tr = dcrf::tree_spec(parent, c, n_nodes, L);
         dcrf::check_finite(ctx, unary, L);
         dcrf::check_finite(ctx, y, L);
@@ -583,6 +601,7 @@ int dcrf_lp_descent_tree(dcrf_ctx *ctx, const void *unary, int L, void *y_inout,
         check_labels(L);
         REQUIRE(unary && y_inout && parent && c, "null argument");
         require_single(ctx);
+        require_lp_mode(ctx);
         REQUIRE(steps >= 0, "steps must be >= 0");
         REQUIRE(std::isfinite(beta0) && beta0 > 0, "beta0 must be > 0");
         REQUIRE(best_y != y_inout, "best_y must not alias y");
@@ -636,6 +655,7 @@ int dcrf_lp_descent_subset(dcrf_ctx *ctx, const void *unary, int L, void *y_inou
         check_labels(L);
         REQUIRE(unary && y_inout && subset, "null argument");
         require_single(ctx);
+        require_lp_mode(ctx);
         REQUIRE(nsub >= 1 && nsub <= L, "nsub must be in [1, L]");
         bool seen[256] = {};
         for (int k = 0; k < nsub; ++k) {

@@ -260,7 +260,7 @@ void autotune(dcrf_ctx *ctx, int L, int reps, double *best_ms) {
     double best_t = 1e300;
     auto run = [&] {
         // the dense filter and the one-hot path of a Frank-Wolfe iteration
-        filter_apply(ctx, ctx->tmpA.p, ctx->tmpB.p, L, false, false);
+        filter_apply(ctx, ctx->tmpA.p, ctx->tmpB.p, L, false, DCRF_FILTER_LATTICE);
         splat_labels(ctx, ctx->fw_s.as<int32_t>(), L);
         blur_all(ctx, L, false);
         slice_into(ctx, ctx->tmpA.p, nullptr, L, nullptr, nullptr, ctx->tmpB.p,

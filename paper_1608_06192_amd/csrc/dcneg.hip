@@ -236,7 +236,7 @@ void dc_neg_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y, int outer,
     const int N = ctx->N;
     constexpr int TP = RowTile<T>::kPix;
     const int G = seg_tiles(ctx, TP);
-    const bool exact = ctx->mode == DCRF_FILTER_EXACT;
+    const bool exact = ctx->mode != DCRF_FILTER_LATTICE;   // a dense K'Y first
     const bool potts = potts_mu<T>(ctx, mu, L);
     // rows of partial sums: S(y^k) for k = 0..outer when asked, else one
     // scratch row that each step overwrites
@@ -249,7 +249,7 @@ void dc_neg_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y, int outer,
     auto pass = [&](int k, int update) {
         LatSet<T> ls{};
         if (exact) {
-            filter_apply(ctx, y, ctx->tmpA.p, L, false, true);
+            filter_apply(ctx, y, ctx->tmpA.p, L, false, ctx->mode);
             a.pre = ctx->tmpA.as<T>();
         } else {
             splat_dense(ctx, y, L);

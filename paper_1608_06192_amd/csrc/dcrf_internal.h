@@ -320,6 +320,7 @@ struct dcrf_ctx {
     dcrf::DevBuf r;          // N x T: K'1
     dcrf::DevBuf scratch;    // small device scratch (flags, counters)
     dcrf::DevBuf tmpA, tmpB; // N x C scratch arrays
+    dcrf::DevBuf sep_taps, sep_tmp, sep_acc;   // the separable filter mode
     // Frank-Wolfe state
     dcrf::DevBuf fw_c, fw_Py, fw_Ps, fw_s, fw_sprev, fw_part, fw_scal,
         fw_trace, fw_mu;
@@ -359,8 +360,12 @@ void rechunk(dcrf_ctx *ctx, int chunk, int dense_chunk);
 
 // filter.hip
 // out = K' in (N x C), lattice or exact, optionally the transpose
+// separable.hip: K'Y with the position-only kernels exact (two 1-D passes)
+// and the others by the lattice
+void filter_separable(dcrf_ctx *ctx, const void *in, void *out, int C, bool adjoint);
+// kind: DCRF_FILTER_LATTICE, DCRF_FILTER_EXACT or DCRF_FILTER_SEPARABLE
 void filter_apply(dcrf_ctx *ctx, const void *in, void *out, int C,
-                  bool adjoint, bool exact);
+                  bool adjoint, int kind);
 // r = K'1
 void compute_row_sums(dcrf_ctx *ctx);
 // make sure every lattice has vertex buffers for C channels

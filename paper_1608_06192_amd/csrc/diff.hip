@@ -690,7 +690,7 @@ void backward_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, int iters,
     // the end of the sweep: ybar += K'^T (Pbar mu) + d Pbar and the rest
     hipLaunchKernelGGL((k_rowmat<T>), dim3(std::min(4096, ceil_div(N, kThreads / L))),
                        dim3(kThreads), 0, st, N, L, Pbar, mu, W.Z.as<T>());
-    filter_apply(ctx, W.Z.p, W.KtZ.p, L, true, false);
+    filter_apply(ctx, W.Z.p, W.KtZ.p, L, true, DCRF_FILTER_LATTICE);
     SweepF<T> F{};
     F.seg = seg;
     F.nimg = nimg;

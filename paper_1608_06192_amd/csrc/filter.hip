@@ -1054,9 +1054,13 @@ void slice_t(dcrf_ctx *ctx, const T *Y, const T *pre, int C, const T *mu,
 
 template <typename T>
 void filter_t(dcrf_ctx *ctx, const T *in, T *out, int C, bool adjoint,
-              bool exact) {
-    if (exact) {
+              int kind) {
+    if (kind == DCRF_FILTER_EXACT) {
         exact_t<T>(ctx, in, out, C);
+        return;
+    }
+    if (kind == DCRF_FILTER_SEPARABLE) {
+        filter_separable(ctx, in, out, C, adjoint);
         return;
     }
     splat_dense_t<T>(ctx, in, C);
@@ -1146,13 +1150,13 @@ void slice_into(dcrf_ctx *ctx, const void *Y, const void *pre, int C,
 }
 
 void filter_apply(dcrf_ctx *ctx, const void *in, void *out, int C,
-                  bool adjoint, bool exact) {
+                  bool adjoint, int kind) {
     if (ctx->dtype == DCRF_F64)
         filter_t<double>(ctx, static_cast<const double *>(in),
-                         static_cast<double *>(out), C, adjoint, exact);
+                         static_cast<double *>(out), C, adjoint, kind);
     else
         filter_t<float>(ctx, static_cast<const float *>(in),
-                        static_cast<float *>(out), C, adjoint, exact);
+                        static_cast<float *>(out), C, adjoint, kind);
 }
 
 void compute_row_sums(dcrf_ctx *ctx) {
@@ -1160,8 +1164,7 @@ void compute_row_sums(dcrf_ctx *ctx) {
     ctx->r.ensure((size_t)ctx->N * e, ctx->stream);
     ctx->tmpA.ensure((size_t)ctx->N * e, ctx->stream);
     fill_ones(ctx, ctx->tmpA.p, ctx->N);
-    filter_apply(ctx, ctx->tmpA.p, ctx->r.p, 1, false,
-                 ctx->mode == DCRF_FILTER_EXACT);
+    filter_apply(ctx, ctx->tmpA.p, ctx->r.p, 1, false, ctx->mode);
 }
 
 }  // namespace dcrf

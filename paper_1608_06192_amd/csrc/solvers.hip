@@ -784,9 +784,9 @@ void qp_apply_t(dcrf_ctx *ctx, const T *y, const T *mu, int L, const T *mabs,
     const hipStream_t st = ctx->stream;
     const int N = ctx->N;
     const T *pre = nullptr;
-    if (ctx->mode == DCRF_FILTER_EXACT) {
+    if (ctx->mode != DCRF_FILTER_LATTICE) {
         ctx->tmpA.ensure((size_t)N * L * sizeof(T), st);
-        filter_apply(ctx, y, ctx->tmpA.p, L, false, true);
+        filter_apply(ctx, y, ctx->tmpA.p, L, false, ctx->mode);
         pre = ctx->tmpA.as<T>();
     } else {
         splat_dense(ctx, y, L);
@@ -843,7 +843,7 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
     if (!have_Py) qp_apply_t<T>(ctx, y, mu, L, w.mabs, w.Py);
     // blurred vertex values of every lattice, one block per checkpoint
     size_t vblock = 0;
-    if (save && ctx->mode != DCRF_FILTER_EXACT)
+    if (save && ctx->mode == DCRF_FILTER_LATTICE)
         for (int m = 0; m < ctx->nk; ++m)
             vblock += (size_t)ctx->lat[m].M * row_stride(L, sizeof(T));
     auto save_vertices = [&](int slot) {
@@ -869,7 +869,7 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
     }
     DCRF_CHECK_LAUNCH();
 
-    const bool exact = ctx->mode == DCRF_FILTER_EXACT;
+    const bool exact = ctx->mode != DCRF_FILTER_LATTICE;   // K'S of a dense one-hot
     const bool rows = L <= kRowMaxC;
     if (!exact) ensure_vertex_buffers(ctx, L);
     if (exact) {
@@ -914,7 +914,7 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
         if (exact) {
             hipLaunchKernelGGL((k_onehot<T>), dim3(gE), dim3(256), 0, st, N, L,
                                w.s, ctx->tmpB.as<T>());
-            filter_apply(ctx, ctx->tmpB.p, ctx->tmpA.p, L, false, true);
+            filter_apply(ctx, ctx->tmpB.p, ctx->tmpA.p, L, false, ctx->mode);
             pre = ctx->tmpA.as<T>();
         } else {
             splat_labels(ctx, w.s, L);
@@ -1025,12 +1025,12 @@ double energy_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L,
     }
     const T *pre = nullptr;
     LatSet<T> ls{};
-    if (ctx->mode == DCRF_FILTER_EXACT) {
+    if (ctx->mode != DCRF_FILTER_LATTICE) {
         ctx->tmpA.ensure((size_t)N * L * sizeof(T), st);
         ctx->tmpB.ensure((size_t)N * L * sizeof(T), st);
         hipLaunchKernelGGL((k_onehot<T>), dim3(ceil_div((long long)N * L, 256)),
                            dim3(256), 0, st, N, L, x, ctx->tmpB.as<T>());
-        filter_apply(ctx, ctx->tmpB.p, ctx->tmpA.p, L, false, true);
+        filter_apply(ctx, ctx->tmpB.p, ctx->tmpA.p, L, false, ctx->mode);
         pre = ctx->tmpA.as<T>();
     } else {
         splat_labels(ctx, x, L);

@@ -17,8 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libdcrf.so")
 
 DCRF_OK = 0
 DCRF_F32, DCRF_F64 = 0, 1
-DCRF_FILTER_LATTICE, DCRF_FILTER_EXACT = 0, 1
-DCRF_ADJOINT, DCRF_EXACT = 1, 2
+DCRF_FILTER_LATTICE, DCRF_FILTER_EXACT, DCRF_FILTER_SEPARABLE = 0, 1, 2
+DCRF_ADJOINT, DCRF_EXACT, DCRF_SEPARABLE = 1, 2, 4
 
 STATUS = {0: "DCRF_OK", -1: "DCRF_EINVAL", -2: "DCRF_ENOMEM", -3: "DCRF_ERANGE",
           -4: "DCRF_ECAPACITY", -5: "DCRF_EHIP", -6: "DCRF_EUNSUPPORTED",
@@ -296,7 +296,8 @@ class Context:
 
     def set_filter_mode(self, mode: str):
         self._stream()
-        m = {"lattice": DCRF_FILTER_LATTICE, "exact": DCRF_FILTER_EXACT}[mode]
+        m = {"lattice": DCRF_FILTER_LATTICE, "exact": DCRF_FILTER_EXACT,
+             "separable": DCRF_FILTER_SEPARABLE}[mode]
         self._check(_lib.dcrf_set_filter_mode(self._h, m))
 
     def lattice_info(self, m: int):
@@ -318,11 +319,12 @@ class Context:
 
     # -- filter ----------------------------------------------------------
     def filter(self, x: torch.Tensor, adjoint=False, exact=False,
-               out: torch.Tensor | None = None) -> torch.Tensor:
+               out: torch.Tensor | None = None, separable=False) -> torch.Tensor:
         C = x.shape[1] if x.dim() == 2 else 1
         if out is None:
             out = torch.empty_like(x)
-        flags = (DCRF_ADJOINT if adjoint else 0) | (DCRF_EXACT if exact else 0)
+        flags = ((DCRF_ADJOINT if adjoint else 0) | (DCRF_EXACT if exact else 0)
+                 | (DCRF_SEPARABLE if separable else 0))
         self._stream()
         self._check(_lib.dcrf_filter(self._h, self._arg(x, name="in"),
                                      self._arg(out, name="out"), C, flags))

@@ -57,7 +57,7 @@ def nsd_mu(L, seed):
     return np.ones((L, L)) - B @ B.T
 
 
-@pytest.mark.parametrize("mode", ["lattice", "exact"])
+@pytest.mark.parametrize("mode", ["lattice", "exact", "separable"])
 def test_dc_neg_fp64_matches_oracle(mode):
     im = synth.make("rect_32x24_L3")
     ctx = gpu_ctx(im, torch.float64, mode)

@@ -134,7 +134,7 @@ def test_qp_apply_matches_oracle(name, dtype, rtol):
     assert (np.abs(g - o) <= rtol * (scale + 1e-30)).all()
 
 
-@pytest.mark.parametrize("mode", ["lattice", "exact"])
+@pytest.mark.parametrize("mode", ["lattice", "exact", "separable"])
 def test_fw_fp64_matches_oracle(mode):
     # 32x24, L = 3, FP64, 20 iterations, seed 0
     im = synth.make("rect_32x24_L3")
