@@ -133,7 +133,7 @@ static void release_all(dcrf_ctx *ctx) {
           &ctx->fw_scal, &ctx->fw_trace, &ctx->fw_mu, &ctx->potts, &ctx->hist,
           &ctx->errflag, &ctx->seg, &ctx->tiles, &ctx->tile_img_off, &ctx->small,
           &ctx->sub_phi, &ctx->sub_y, &ctx->sub_best, &ctx->sep_taps, &ctx->sep_tmp,
-          &ctx->sep_acc})
+          &ctx->sep_acc, &ctx->sep_part})
         b->release();
     ctx->potts_L = 0;
     ctx->potts_dtype = -1;

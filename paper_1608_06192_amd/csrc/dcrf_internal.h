@@ -320,7 +320,7 @@ struct dcrf_ctx {
     dcrf::DevBuf r;          // N x T: K'1
     dcrf::DevBuf scratch;    // small device scratch (flags, counters)
     dcrf::DevBuf tmpA, tmpB; // N x C scratch arrays
-    dcrf::DevBuf sep_taps, sep_tmp, sep_acc;   // the separable filter mode
+    dcrf::DevBuf sep_taps, sep_tmp, sep_acc, sep_part;   // the separable filter mode
     // Frank-Wolfe state
     dcrf::DevBuf fw_c, fw_Py, fw_Ps, fw_s, fw_sprev, fw_part, fw_scal,
         fw_trace, fw_mu;

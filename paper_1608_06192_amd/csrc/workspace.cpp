@@ -150,11 +150,11 @@ size_t workspace_bound(int B, const int *H, const int *W, int L,
     s.add(4);                                          // input error flag
     s.add(size_t(L) * L * e);                          // Potts copy of mu
     s.add(4096);                                       // per-call flags and tables
-    // separable mode: taps (at most the larger image side) and two N x L arrays
+    // separable mode: taps (at most the larger image side) and three N x L arrays
     size_t side = 1;
     for (int j = 0; j < B; ++j) side = std::max<size_t>(side, std::max(H[j], W[j]));
     s.add(side * e);
-    for (int i = 0; i < 2; ++i) s.add(NL * e);
+    for (int i = 0; i < 3; ++i) s.add(NL * e);
     for (int i = 0; i < 3; ++i) s.add(NL * e);         // the LP on a label subset
     // Frank-Wolfe, DC_gen, DC_neg, energy
     for (int i = 0; i < 3; ++i) s.add(NL * e);         // c, P_y, P_s

@@ -152,3 +152,18 @@ def test_separable_filter_fp32_500x375_sampled_pixels():
     err = np.abs(g[at] - o)
     print(f"[separable 500x375] max err / bound {(err / b).max():.3g}", flush=True)
     assert (err <= b).all()
+
+
+def test_separable_with_two_kernels_of_each_kind():
+    # two lattice kernels and two position-only ones: the lattice sum is
+    # formed first (scaled once the second arrives), the first exact kernel
+    # accumulates into it and the second writes the result
+    im = synth.voronoi_image(30, 40, 3, seed=12, regions=5)
+    ks = [synth.BILATERAL, dict(use_rgb=1, theta_pos=20.0, theta_rgb=30.0, weight=2.0),
+          synth.SPATIAL, dict(use_rgb=0, theta_pos=1.5, theta_rgb=0.0, weight=0.7)]
+    ctx = ctx_for(im, torch.float64, kernels=ks)
+    model = O.Model(im.H, im.W, im.rgb, ks, mode="separable")
+    Y = np.random.default_rng(13).uniform(-1, 1, size=(im.N, 5))
+    for adjoint in (False, True):
+        g = ctx.filter(T(Y, torch.float64), adjoint=adjoint, separable=True).cpu().numpy()
+        assert (np.abs(g - model.Kp(Y, reverse=adjoint)) <= bound(model, Y, 1e-11)).all()
