@@ -191,9 +191,9 @@ def _short(name):
 def summarize_pmc(fetch_csv, write_csv, command):
     """Write TRAFFIC_FILE from the counter CSVs of two rocprofv3 --pmc runs
     (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of `bench.py
-    --calib-copy`. The calibration dispatches are the non-library kernels that
-    read (write) at least 64 MiB by the counter: the plain copy of CALIB_BYTES
-    (the counter of its 256 MiB read shows half of it on this part)."""
+    --calib-copy`. The calibration dispatches are those of the plain copy of
+    CALIB_BYTES (torch.mul; the counter of its 256 MiB read shows half of it on
+    this part), told apart from the cache-flush fill by the kernel's name."""
     import csv
     per = {}
     calib = {}
@@ -203,8 +203,8 @@ def summarize_pmc(fetch_csv, write_csv, command):
                 continue
             v = float(r["Counter_Value"])
             k = _short(r["Kernel_Name"])
-            if not k.startswith("k_") and v * 1024 >= 64 * (1 << 20):
-                calib.setdefault(ctr, []).append(v)
+            if "MulFunctor" in r["Kernel_Name"] and v * 1024 >= 64 * (1 << 20):
+                calib.setdefault(ctr, []).append(v)   # the 256 MiB copy (torch.mul)
             elif k.startswith("k_"):
                 per.setdefault(k, {}).setdefault(ctr, []).append(v)
     lines = ["# HBM traffic per dispatch of the library's kernels, from the L2-to-memory",
@@ -557,7 +557,8 @@ def main():
                     help="also run a plain 256 MiB copy kernel (reference for "
                          "the HBM byte counters of a profiler run)")
     ap.add_argument("--no-ext", action="store_true",
-                    help="skip the diff, batch and lattice-error measurements")
+                    help="skip the separable-mode, diff, batch and lattice-error "
+                         "measurements")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic summary under profiles/ from two "
                          "rocprofv3 --pmc counter CSVs and exit")
@@ -670,28 +671,6 @@ def main():
         f"{filt['GBps']:.0f} GB/s algorithmic; after a 512 MB flush "
         f"{c_ms * 1e3:.1f} us, {filt['cold_GBps']:.0f} GB/s")
 
-    # ---- the separable mode: the spatial kernel exact by two 1-D passes --
-    ev0.record()
-    for _ in range(20):
-        ctx.filter(Y, out=out, separable=True)
-    ev1.record()
-    torch.cuda.synchronize()
-    sep_ms = ev0.elapsed_time(ev1) / 20
-    ctx.set_filter_mode("separable")
-    ysep = y0.clone()
-    ctx.qp_frank_wolfe(phi, mu, ysep, 5, trace=False)
-    ysep = y0.clone()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.qp_frank_wolfe(phi, mu, ysep, 50, trace=False)
-    torch.cuda.synchronize()
-    sep_fw_us = (time.perf_counter() - t0) * 1e6 / 50
-    ctx.set_filter_mode("lattice")
-    filt["separable_ms"] = sep_ms
-    filt["separable_fw_iteration_us"] = sep_fw_us
-    log(f"[bench] separable mode: dense filter {sep_ms * 1e3:.1f} us, FW iteration "
-        f"{sep_fw_us:.1f} us (50 iterations)")
-
     # ---- DC_neg steps at the same size (one filter call per step) ---------
     yd = y.clone()
     ctx.dc_neg(phi, mu, yd, 2, hist=False)
@@ -787,6 +766,28 @@ def main():
         log(f"[bench] r-HST LP ({len(parent)} nodes): {tree_ms:.1f} ms/step, "
             f"S {htree[0]:.6g} -> {btree:.6g} in {tree_steps} steps")
 
+    if not args.no_ext:
+        # the separable mode: the spatial kernel exact by two 1-D passes
+        ev0.record()
+        for _ in range(20):
+            ctx.filter(Y, out=out, separable=True)
+        ev1.record()
+        torch.cuda.synchronize()
+        sep_ms = ev0.elapsed_time(ev1) / 20
+        ctx.set_filter_mode("separable")
+        ysep = y0.clone()
+        ctx.qp_frank_wolfe(phi, mu, ysep, 5, trace=False)
+        ysep = y0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.qp_frank_wolfe(phi, mu, ysep, 50, trace=False)
+        torch.cuda.synchronize()
+        sep_fw_us = (time.perf_counter() - t0) * 1e6 / 50
+        ctx.set_filter_mode("lattice")
+        filt["separable_ms"] = sep_ms
+        filt["separable_fw_iteration_us"] = sep_fw_us
+        log(f"[bench] separable mode: dense filter {sep_ms * 1e3:.1f} us, FW iteration "
+            f"{sep_fw_us:.1f} us (50 iterations)")
     ext = {} if args.no_ext else extensions(torch, dcrf, synth, dev, kernels)
     if args.calib_copy:
         a = torch.ones(64 << 20, device=dev, dtype=f32)

@@ -128,6 +128,9 @@ def test_fw_diff_fp32_matches_oracle_500x375():
     assert frac <= 1e-3
     assert err_phi <= 1e-4
     assert (err_w <= bound_w).all()
+    # marginals: FP32 decisions may flip at near-ties, so a share of entries
+    # may differ; measured 8.6e-6 of them beyond 1e-4
+    assert (dy > 1e-4).mean() <= 1e-3
 
 
 def _gpu_loss(ctx, phi, mu, iters, gt):

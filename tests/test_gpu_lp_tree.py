@@ -213,3 +213,20 @@ def test_malformed_trees_are_rejected():
         with pytest.raises(dcrf.DcrfError) as e:
             ctx.lp_subgradient_tree(phi, y, parent, c)
         assert dcrf.STATUS[e.value.status] == "DCRF_EINVAL", parent
+
+
+def test_tree_with_a_chain_of_single_child_nodes():
+    # internal nodes with one child repeat their child's column: the oracle
+    # and the GPU must both count every weighted node; labels 0, 1 under node
+    # 4, node 4 alone under node 5, node 5 and label 2 and label 3 under the
+    # root 6
+    im = synth.voronoi_image(18, 22, 4, seed=16, regions=4)
+    parent = [4, 4, 6, 6, 5, 6, -1]
+    c = [1.0, 1.0, 2.0, 2.0, 0.5, 0.25, 0.0]
+    y = dyadic_points(im.N, 4, seed=17)
+    ctx = ctx_for(im, torch.float64)
+    g, S = ctx.lp_subgradient_tree(T(im.unary, torch.float64), T(y, torch.float64),
+                                   parent, c)
+    go, So, mag = oracle_tree(im, y, np.array(parent), np.array(c), im.unary)
+    assert (np.abs(g.cpu().numpy() - go) <= 1e-10 * mag).all()
+    assert abs(S - So) <= 1e-10 * (mag * y).sum()

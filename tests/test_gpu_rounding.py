@@ -216,3 +216,27 @@ def test_labels_used_matches_unique():
     with pytest.raises(dcrf.DcrfError) as e:
         ctx.labels_used(torch.from_numpy(x).to(dev()), 9)
     assert dcrf.STATUS[e.value.status] == "DCRF_EINVAL"
+
+
+def test_rounding_and_subset_edge_cases():
+    # one label: KT rounding and the argmax give label 0 everywhere; a subset
+    # of one label is the integral point of that label, whose S_LP is its
+    # unary sum (every pair agrees, so the pairwise term is 0; the exact
+    # filter makes the two triangular sums cancel to rounding); a threshold
+    # of 1 leaves no label present
+    im = synth.voronoi_image(20, 25, 5, seed=14, regions=4)
+    ctx = ctx_for(im, torch.float64)
+    y1 = torch.ones(im.N, 1, dtype=torch.float64, device=dev())
+    lab, th = draws(1, 6, seed=15)
+    x, left = ctx.round_kt(y1, torch.from_numpy(lab).to(dev()), T(th, torch.float64))
+    assert left == 0 and (x.cpu().numpy() == 0).all()
+    phi = T(im.unary, torch.float64)
+    y = T(O.softmax_neg(im.unary), torch.float64)
+    assert ctx.present_labels(y, 1.0) == []
+    ys = y.clone()
+    ctx.set_filter_mode("exact")
+    best, hist = ctx.lp_descent_subset(phi, ys, [3], 2, 1e-3)
+    want = float(im.unary[:, 3].sum())
+    assert abs(hist[0] - want) <= 1e-10 * abs(want) and abs(best - want) <= 1e-10 * abs(want)
+    ys = ys.cpu().numpy()
+    assert (ys[:, 3] == 1).all() and (np.delete(ys, 3, axis=1) == 0).all()
