@@ -77,6 +77,8 @@ typedef enum {
 #define DCRF_ADJOINT 1u      /* apply the transpose (blur directions reversed) */
 #define DCRF_EXACT 2u        /* use the exact O(N^2) sum for this call        */
 #define DCRF_SEPARABLE 4u    /* the separable filter mode for this call       */
+#define DCRF_KEEP_SELF 8u    /* keep the b = a term: out = Kbar in            */
+#define DCRF_PER_KERNEL 16u  /* one output block per kernel (see dcrf_filter)  */
 
 /* One Gaussian kernel of the pixel compatibility (eq. pairwise, App. G). */
 typedef struct {
@@ -198,6 +200,24 @@ int dcrf_set_images(dcrf_ctx *ctx, int B, const int *H, const int *W,
                     const float *const *rgb, const dcrf_kernel *kernels, int nk,
                     int dtype, void *workspace, size_t ws_bytes);
 
+/* dcrf_set_images under the name of the batch calls below. */
+int dcrf_batch_set_images(dcrf_ctx *ctx, int B, const int *H, const int *W,
+                          const float *const *rgb, const dcrf_kernel *kernels, int nk,
+                          int dtype, void *workspace, size_t ws_bytes);
+
+/* dcrf_fw_forward and dcrf_fw_backward with one array per image instead of
+ * the packed layout: unary[j], y_out[j], grad_y[j] and grad_unary[j] (host
+ * arrays of B device pointers) each hold image j's H[j] W[j] x L values,
+ * row-major. The library copies them to and from packed arrays of its own
+ * (device-to-device copies on the context's stream), so the results are
+ * those of the packed calls; saved, grad_w (B x nk, image-major) and
+ * grad_w_total (nk) as there. One launch per stage covers every image. */
+int dcrf_batch_fw_forward(dcrf_ctx *ctx, const void *const *unary, const void *mu, int L,
+                          const double *w, int iters, void *const *y_out, void *saved);
+int dcrf_batch_fw_backward(dcrf_ctx *ctx, const void *const *unary, const void *mu, int L,
+                           int iters, const void *saved, const void *const *grad_y,
+                           void *const *grad_unary, double *grad_w, double *grad_w_total);
+
 /* *nimg = images held (1 after dcrf_set_image), *rows = N, the rows of every
  * N x C argument; seg (host, 2 nimg ints, may be NULL) = first and one past
  * the last row of each image. Any pointer may be NULL. */
@@ -260,7 +280,13 @@ int dcrf_lattice_export(dcrf_ctx *ctx, int m, int32_t *keys, int32_t *vid,
  * K_m is its permutohedral approximation gamma_d * slice . blur . splat;
  * DCRF_EXACT uses the O(N^2) sum, DCRF_SEPARABLE the separable mode of
  * dcrf_set_filter_mode (the two exclude each other), DCRF_ADJOINT the
- * transpose. in, out: (dev) N x C, 1 <= C <= 256, not aliased. */
+ * transpose. DCRF_KEEP_SELF keeps the b = a term: out = Kbar in =
+ * K' in + (sum w) in (with the lattice, each kernel's own approximate self
+ * response). DCRF_PER_KERNEL writes nk blocks of N x C to out (out holds
+ * nk N C values): block m = w_m K_m in - w_m in, kernel m's share of K' in
+ * (the blocks add up to it), or w_m K_m in with DCRF_KEEP_SELF; the
+ * per-kernel pieces of the weight gradient of eq. pairwise.
+ * in, out: (dev) N x C, 1 <= C <= 256, not aliased. */
 int dcrf_filter(dcrf_ctx *ctx, const void *in, void *out, int C,
                 unsigned flags);
 

@@ -133,7 +133,7 @@ static void release_all(dcrf_ctx *ctx) {
           &ctx->fw_scal, &ctx->fw_trace, &ctx->fw_mu, &ctx->potts, &ctx->hist,
           &ctx->errflag, &ctx->seg, &ctx->tiles, &ctx->tile_img_off, &ctx->small,
           &ctx->sub_phi, &ctx->sub_y, &ctx->sub_best, &ctx->sep_taps, &ctx->sep_tmp,
-          &ctx->sep_acc, &ctx->sep_part})
+          &ctx->sep_acc, &ctx->sep_part, &ctx->pack_a, &ctx->pack_b, &ctx->pack_c})
         b->release();
     ctx->potts_L = 0;
     ctx->potts_dtype = -1;
@@ -252,6 +252,12 @@ int dcrf_set_images(dcrf_ctx *ctx, int B, const int *H, const int *W,
         ctx->has_image = true;
         dcrf::compute_row_sums(ctx);
     });
+}
+
+int dcrf_batch_set_images(dcrf_ctx *ctx, int B, const int *H, const int *W,
+                          const float *const *rgb, const dcrf_kernel *kernels, int nk,
+                          int dtype, void *workspace, size_t ws_bytes) {
+    return dcrf_set_images(ctx, B, H, W, rgb, kernels, nk, dtype, workspace, ws_bytes);
 }
 
 int dcrf_image_layout(dcrf_ctx *ctx, int *nimg, int *rows, int *seg) {
@@ -375,7 +381,8 @@ int dcrf_filter(dcrf_ctx *ctx, const void *in, void *out, int C,
         require_image(ctx);
         REQUIRE(in && out && in != out, "in and out must be distinct, non-null");
         REQUIRE(C >= 1 && C <= 256, "C must be in [1, 256]");
-        REQUIRE((flags & ~(DCRF_ADJOINT | DCRF_EXACT | DCRF_SEPARABLE)) == 0,
+        REQUIRE((flags & ~(DCRF_ADJOINT | DCRF_EXACT | DCRF_SEPARABLE | DCRF_KEEP_SELF |
+                           DCRF_PER_KERNEL)) == 0,
                 "unknown flags");
         REQUIRE(!((flags & DCRF_EXACT) && (flags & DCRF_SEPARABLE)),
                 "DCRF_EXACT and DCRF_SEPARABLE exclude each other");
@@ -384,7 +391,11 @@ int dcrf_filter(dcrf_ctx *ctx, const void *in, void *out, int C,
         const int kind = (flags & DCRF_EXACT)       ? DCRF_FILTER_EXACT
                          : (flags & DCRF_SEPARABLE) ? DCRF_FILTER_SEPARABLE
                                                     : DCRF_FILTER_LATTICE;
-        dcrf::filter_apply(ctx, in, out, C, (flags & DCRF_ADJOINT) != 0, kind);
+        if (flags & (DCRF_KEEP_SELF | DCRF_PER_KERNEL))
+            dcrf::filter_parts(ctx, in, out, C, (flags & DCRF_ADJOINT) != 0, kind,
+                               (flags & DCRF_KEEP_SELF) != 0, (flags & DCRF_PER_KERNEL) != 0);
+        else
+            dcrf::filter_apply(ctx, in, out, C, (flags & DCRF_ADJOINT) != 0, kind);
     });
 }
 
@@ -547,6 +558,82 @@ int dcrf_fw_backward(dcrf_ctx *ctx, const void *unary, const void *mu, int L,
             for (size_t i = 0; i < per.size(); ++i) grad_w[i] = per[i];
         dcrf::raise_device_errors(ctx);
         if (grad_w_total)   // shared weights: the sum over the images, in order
+            for (int m = 0; m < ctx->nk; ++m) {
+                double t = 0.0;
+                for (int j = 0; j < ctx->nimg; ++j) t += per[(size_t)j * ctx->nk + m];
+                grad_w_total[m] = t;
+            }
+    });
+}
+
+// copies between each image's own N_j x L array and the packed layout (rows
+// [seg[2j], seg[2j+1]) of `packed`); the rows between images are left alone
+static void pack_rows(dcrf_ctx *ctx, const void *const *per_image, void *packed, int L,
+                      bool to_packed) {
+    const size_t e = ctx->elt(), row = (size_t)L * e;
+    for (int j = 0; j < ctx->nimg; ++j) {
+        const size_t r0 = ctx->seg_h[2 * j], n = ctx->seg_h[2 * j + 1] - r0;
+        char *pk = static_cast<char *>(packed) + r0 * row;
+        if (to_packed)
+            DCRF_TRY_HIP(hipMemcpyAsync(pk, per_image[j], n * row, hipMemcpyDeviceToDevice,
+                                        ctx->stream));
+        else
+            DCRF_TRY_HIP(hipMemcpyAsync(const_cast<void *>(per_image[j]), pk, n * row,
+                                        hipMemcpyDeviceToDevice, ctx->stream));
+    }
+}
+
+static void require_per_image(dcrf_ctx *ctx, const void *const *a, const char *what) {
+    REQUIRE(a != nullptr, std::string(what) + " is null");
+    for (int j = 0; j < ctx->nimg; ++j)
+        REQUIRE(a[j] != nullptr, std::string(what) + "[" + std::to_string(j) + "] is null");
+}
+
+int dcrf_batch_fw_forward(dcrf_ctx *ctx, const void *const *unary, const void *mu, int L,
+                          const double *w, int iters, void *const *y_out, void *saved) {
+    return guarded(ctx, [&] {
+        require_diff(ctx, L, iters);
+        require_per_image(ctx, unary, "unary");
+        require_per_image(ctx, (const void *const *)y_out, "y_out");
+        REQUIRE(saved != nullptr, "null argument");
+        REQUIRE(iters <= 4096 || !ctx->arena.active(),
+                "with a caller workspace at most 4096 unrolled iterations");
+        if (w) apply_weights(ctx, w);
+        const size_t bytes = (size_t)ctx->N * L * ctx->elt();
+        ctx->pack_a.ensure(bytes, ctx->stream);
+        ctx->pack_b.ensure(bytes, ctx->stream);
+        pack_rows(ctx, unary, ctx->pack_a.p, L, true);
+        dcrf::check_finite(ctx, ctx->pack_a.p, L);
+        dcrf::fw_diff_forward(ctx, ctx->pack_a.p, dcrf::resolve_mu(ctx, mu, L), L,
+                              ctx->pack_b.p, iters, saved);
+        pack_rows(ctx, (const void *const *)y_out, ctx->pack_b.p, L, false);
+    });
+}
+
+int dcrf_batch_fw_backward(dcrf_ctx *ctx, const void *const *unary, const void *mu, int L,
+                           int iters, const void *saved, const void *const *grad_y,
+                           void *const *grad_unary, double *grad_w, double *grad_w_total) {
+    return guarded(ctx, [&] {
+        require_diff(ctx, L, iters);
+        require_per_image(ctx, unary, "unary");
+        require_per_image(ctx, grad_y, "grad_y");
+        require_per_image(ctx, (const void *const *)grad_unary, "grad_unary");
+        REQUIRE(saved != nullptr, "null argument");
+        const size_t bytes = (size_t)ctx->N * L * ctx->elt();
+        for (dcrf::DevBuf *b : {&ctx->pack_a, &ctx->pack_b, &ctx->pack_c})
+            b->ensure(bytes, ctx->stream);
+        pack_rows(ctx, unary, ctx->pack_a.p, L, true);
+        pack_rows(ctx, grad_y, ctx->pack_b.p, L, true);
+        dcrf::check_finite(ctx, ctx->pack_b.p, L);
+        std::vector<double> per((size_t)ctx->nimg * ctx->nk, 0.0);
+        dcrf::fw_diff_backward(ctx, ctx->pack_a.p, dcrf::resolve_mu(ctx, mu, L), L, iters,
+                               saved, ctx->pack_b.p, ctx->pack_c.p,
+                               (grad_w || grad_w_total) ? per.data() : nullptr);
+        pack_rows(ctx, (const void *const *)grad_unary, ctx->pack_c.p, L, false);
+        if (grad_w)
+            for (size_t i = 0; i < per.size(); ++i) grad_w[i] = per[i];
+        dcrf::raise_device_errors(ctx);
+        if (grad_w_total)
             for (int m = 0; m < ctx->nk; ++m) {
                 double t = 0.0;
                 for (int j = 0; j < ctx->nimg; ++j) t += per[(size_t)j * ctx->nk + m];

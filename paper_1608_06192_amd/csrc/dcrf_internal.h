@@ -321,6 +321,7 @@ struct dcrf_ctx {
     dcrf::DevBuf scratch;    // small device scratch (flags, counters)
     dcrf::DevBuf tmpA, tmpB; // N x C scratch arrays
     dcrf::DevBuf sep_taps, sep_tmp, sep_acc, sep_part;   // the separable filter mode
+    dcrf::DevBuf pack_a, pack_b, pack_c;   // packed copies for the per-image batch calls
     // Frank-Wolfe state
     dcrf::DevBuf fw_c, fw_Py, fw_Ps, fw_s, fw_sprev, fw_part, fw_scal,
         fw_trace, fw_mu;
@@ -476,6 +477,13 @@ void diff_release(dcrf_ctx *ctx);
 // own response at a), or its transpose
 void filter_kernel(dcrf_ctx *ctx, int m, const void *in, void *out, int C,
                    bool adjoint);
+// sum over b != a of k_m(a, b) in_b, exactly, for kernel m alone (weight 1)
+void exact_kernel(dcrf_ctx *ctx, int m, const void *in, void *out, int C);
+// dcrf_filter's variants: keep_self adds (sum w) in back (K-bar Y);
+// per_kernel writes nk blocks of N x C, block m = w_m K_m in without (or,
+// with keep_self, with) its self term, for the filter kind given
+void filter_parts(dcrf_ctx *ctx, const void *in, void *out, int C, bool adjoint,
+                  int kind, bool keep_self, bool per_kernel);
 
 // lp.hip
 double lp_subgradient(dcrf_ctx *ctx, const void *unary, int L, const void *y,

@@ -836,6 +836,24 @@ void exact_t(dcrf_ctx *ctx, const T *in, T *out, int C) {
     DCRF_CHECK_LAUNCH();
 }
 
+// sum over b != a of k_m(a, b) in_b for kernel m alone (weight 1)
+template <typename T>
+void exact_kernel_t(dcrf_ctx *ctx, int m, const T *in, T *out, int C) {
+    const ExactSet<T> all = make_exact_set<T>(ctx);
+    ExactSet<T> ex{};
+    ex.nk = 1;
+    ex.f[0] = all.f[m];
+    ex.d[0] = all.d[m];
+    ex.off[0] = 0;
+    ex.off[1] = all.d[m];
+    ex.w[0] = T(1);
+    for (int c0 = 0; c0 < C; c0 += kExactCB)
+        hipLaunchKernelGGL((k_exact<T>), dim3(ceil_div(ctx->N, kExactTile)),
+                           dim3(kExactTile), 0, ctx->stream, ctx->N, C, c0, in,
+                           out, ex);
+    DCRF_CHECK_LAUNCH();
+}
+
 constexpr size_t kTileLds = 56 * 1024;   // dynamic LDS of the tile slices
 
 // whether the per-tile kernels serve C channels: each lattice's slots of a
@@ -1092,6 +1110,15 @@ void filter_kernel_t(dcrf_ctx *ctx, int m, const T *in, T *out, int C,
 }
 
 }  // namespace
+
+void exact_kernel(dcrf_ctx *ctx, int m, const void *in, void *out, int C) {
+    if (ctx->dtype == DCRF_F64)
+        exact_kernel_t<double>(ctx, m, static_cast<const double *>(in),
+                               static_cast<double *>(out), C);
+    else
+        exact_kernel_t<float>(ctx, m, static_cast<const float *>(in),
+                              static_cast<float *>(out), C);
+}
 
 void filter_kernel(dcrf_ctx *ctx, int m, const void *in, void *out, int C,
                    bool adjoint) {

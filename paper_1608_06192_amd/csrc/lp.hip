@@ -179,6 +179,19 @@ __device__ __forceinline__ void node_region(long long node, int l, long long N,
     size = 2 * (hi - lo) * D1;
 }
 
+// Level tags of the sub-lattice hash: a stored key carries the level's tag
+// ep (1..kMaxTag) in its top 16 bits, so a slot whose tag differs (an older
+// level's key, or a zero of a fresh table) counts as empty and no level
+// clears the table. ep = 0 marks the untagged form (node keys of 48 bits or
+// more): keys are stored as they are and the table is cleared to kEmpty
+// before each level.
+constexpr int kTagShift = 48;
+constexpr unsigned kMaxTag = 0xfffe;
+
+__device__ __forceinline__ bool slot_taken(uint64_t slot, unsigned ep) {
+    return ep ? unsigned(slot >> kTagShift) == ep : slot != kEmpty;
+}
+
 // first probe of global vertex v in a region of `size` (< 2^32) slots
 __device__ __forceinline__ long long region_slot(int v, long long size) {
     return (long long)(((mix64((uint64_t)v) >> 32) * (uint64_t)size) >> 32);
@@ -190,7 +203,7 @@ __device__ __forceinline__ long long region_slot(int v, long long size) {
 // (a single counter taken by every wave serialises across the chip). Entry e
 // writes sub_nv[e] = (node, vertex) if it claimed a slot, else (-1, -1), so
 // the sub-vertex numbers of a level are the e with sub_nv[e].y >= 0.
-__global__ void k_lp_insert(int N, int l, int D1, int M,
+__global__ void k_lp_insert(int N, int l, int D1, int M, unsigned ep,
                             const int *__restrict__ pos_vid,
                             uint64_t *__restrict__ hkeys,
                             int *__restrict__ ent_slot, int *__restrict__ flags,
@@ -210,24 +223,30 @@ __global__ void k_lp_insert(int N, int l, int D1, int M,
             const int v = pos_vid[e];
             if (v >= 0) {
                 key = (uint64_t)node * (uint64_t)M + (uint64_t)v;
+                if (ep) key |= (uint64_t)ep << kTagShift;
                 nv = make_int2(int(node), v);
                 long long base, size;
                 node_region(node, l, N, D1, base, size);
                 long long h = region_slot(v, size);
                 long long probe = 0;
                 for (; probe < size; ++probe) {
-                    // a slot changes once, from empty to its key: a plain
-                    // load that sees a key is final, and only an empty slot
-                    // needs the compare-and-swap
+                    // during a level a slot changes once, from free to a key
+                    // of the level: a plain load that sees such a key is
+                    // final, and only a free slot needs the compare-and-swap
+                    // (which fails, returning the key, if another entry took
+                    // it first)
                     unsigned long long prev = hkeys[base + h];
-                    if (prev == kEmpty)
-                        prev = atomicCAS((unsigned long long *)&hkeys[base + h],
-                                         (unsigned long long)kEmpty,
-                                         (unsigned long long)key);
-                    if (prev == kEmpty || prev == key) {
-                        claimed = prev == kEmpty;
-                        break;
+                    if (!slot_taken(prev, ep)) {
+                        const unsigned long long got =
+                            atomicCAS((unsigned long long *)&hkeys[base + h], prev,
+                                      (unsigned long long)key);
+                        if (got == prev) {
+                            claimed = true;
+                            break;
+                        }
+                        prev = got;
                     }
+                    if (prev == key) break;
                     if (++h == size) h = 0;
                 }
                 if (probe == size)
@@ -330,7 +349,7 @@ k_lp_splat(int N, int l, int D1, const T *__restrict__ pos_w,
 constexpr int kLpMaxNb = 6;   // d + 1 for d <= 5
 
 __global__ void __launch_bounds__(256)
-k_lp_neighbours(int S, int N, int l, int M, int D1,
+k_lp_neighbours(int S, int N, int l, int M, int D1, unsigned ep,
                 const int2 *__restrict__ sub_nv, const int *__restrict__ nbr_global,
                 const uint64_t *__restrict__ hkeys, const int *__restrict__ slot_vid,
                 int *__restrict__ nbr_sub, int cap_sub) {
@@ -356,12 +375,13 @@ k_lp_neighbours(int S, int N, int l, int M, int D1,
         h[q] = vn[q] >= 0 ? region_slot(vn[q], size) : 0;
         kk[q] = vn[q] >= 0 ? hkeys[base + h[q]] : kEmpty;
     }
+    const uint64_t tag = ep ? (uint64_t)ep << kTagShift : 0;
 #pragma unroll
     for (int q = 0; q < kLpMaxNb; ++q) {
         if (vn[q] < 0) continue;
-        const uint64_t nk = (uint64_t)node * (uint64_t)M + (uint64_t)vn[q];
+        const uint64_t nk = ((uint64_t)node * (uint64_t)M + (uint64_t)vn[q]) | tag;
         // a present key is rarely displaced: continue the probe only then
-        for (long long probe = 1; kk[q] != nk && kk[q] != kEmpty && probe < size;
+        for (long long probe = 1; kk[q] != nk && slot_taken(kk[q], ep) && probe < size;
              ++probe) {
             if (++h[q] == size) h[q] = 0;
             kk[q] = hkeys[base + h[q]];
@@ -371,7 +391,7 @@ k_lp_neighbours(int S, int N, int l, int M, int D1,
 #pragma unroll
     for (int q = 0; q < kLpMaxNb; ++q) {
         const bool hit = vn[q] >= 0 &&
-                         kk[q] == (uint64_t)node * (uint64_t)M + (uint64_t)vn[q];
+                         kk[q] == (((uint64_t)node * (uint64_t)M + (uint64_t)vn[q]) | tag);
         nid[q] = hit ? slot_vid[base + h[q]] : -1;
     }
 #pragma unroll
@@ -696,6 +716,8 @@ struct LPWork {
         DevBuf pos_vid, pos_w;   // the label's vertex ids and weights by position
         size_t cap = 0;
         int cap_sub = 0;
+        unsigned tag = 0;          // the last level's tag in hkeys (0: none yet)
+        const void *tag_buf = nullptr;   // the hkeys allocation the tag refers to
     } lat[DCRF_MAXK];
     DevBuf g, part, acc;
     DevBuf col, tree_lab;    // a subtree's column y(T) and the subtrees' label lists
@@ -748,9 +770,26 @@ void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l, hipStream_t s) {
     const int N = ctx->N, D1 = Lt.d + 1, M = Lt.M;
     const long long E = (long long)N * D1;
     int *flags = ctx->scratch.as<int>();
-    DCRF_TRY_HIP(hipMemsetAsync(P.hkeys.p, 0xff, P.cap * 8, s));
+    // a fresh tag per level (the table starts zeroed: tag 0 is free); after
+    // the last tag the table is cleared once and the tags start again. Node
+    // keys of 48 bits or more go untagged, with a clear per level.
+    unsigned ep = 0;
+    if ((long double)N * (long double)M < (long double)(1ull << kTagShift)) {
+        if (P.tag_buf != P.hkeys.p) {   // a new allocation: zeroed by ensure()
+            P.tag = 0;
+            P.tag_buf = P.hkeys.p;
+        }
+        if (P.tag >= kMaxTag) {
+            DCRF_TRY_HIP(hipMemsetAsync(P.hkeys.p, 0, P.cap * 8, s));
+            P.tag = 0;
+        }
+        ep = ++P.tag;
+    } else {
+        DCRF_TRY_HIP(hipMemsetAsync(P.hkeys.p, 0xff, P.cap * 8, s));
+        P.tag_buf = nullptr;
+    }
     hipLaunchKernelGGL(k_lp_insert, dim3(ceil_div(E, 256)), dim3(256), 0, s, N, l,
-                       D1, M, P.pos_vid.as<int>(), P.hkeys.as<uint64_t>(),
+                       D1, M, ep, P.pos_vid.as<int>(), P.hkeys.as<uint64_t>(),
                        P.ent_slot.as<int>(), flags, P.slot_vid.as<int>(),
                        P.sub_nv.as<int2>(), P.nbr_sub.as<int>());
     if ((N >> l) >= kLpAggPixels)
@@ -764,7 +803,7 @@ void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l, hipStream_t s) {
                            P.pos_w.as<T>(), P.ent_slot.as<int>(),
                            P.slot_vid.as<int>(), P.ent_id.as<int>(), P.V[0].as<T>());
     hipLaunchKernelGGL(k_lp_neighbours, dim3(ceil_div(P.cap_sub, 256)), dim3(256),
-                       0, s, P.cap_sub, N, l, M, D1, P.sub_nv.as<int2>(),
+                       0, s, P.cap_sub, N, l, M, D1, ep, P.sub_nv.as<int2>(),
                        Lt.nbr.as<int>(), P.hkeys.as<uint64_t>(), P.slot_vid.as<int>(),
                        P.nbr_sub.as<int>(), P.cap_sub);
     LpPair<T> *V0 = P.V[0].as<LpPair<T>>(), *V1 = P.V[1].as<LpPair<T>>(),

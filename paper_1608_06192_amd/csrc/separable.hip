@@ -1,6 +1,6 @@
 // The separable filter mode: kernels on position alone by the exact sum,
 // computed as two one-dimensional convolutions; the other kernels by the
-// lattice.
+// lattice. Also the filter's per-kernel and self-keeping variants.
 //
 // A kernel with features (x / theta, y / theta) (eq. gaussiankernel with
 // App. G's scaling) is exp(-(dx^2 + dy^2) / (2 theta^2)) =
@@ -307,7 +307,53 @@ void filter_separable_t(dcrf_ctx *ctx, const T *in, T *out, int C, bool adjoint)
     DCRF_CHECK_LAUNCH();
 }
 
+template <typename T>
+void filter_parts_t(dcrf_ctx *ctx, const T *in, T *out, int C, bool adjoint, int kind,
+                    bool keep_self, bool per_kernel) {
+    const hipStream_t st = ctx->stream;
+    const size_t NC = (size_t)ctx->N * C;
+    const int g = ceil_div((long long)NC, 256);
+    if (!per_kernel) {
+        filter_apply(ctx, in, out, C, adjoint, kind);
+        if (keep_self)
+            hipLaunchKernelGGL((k_axpy<T>), dim3(g), dim3(256), 0, st, NC, T(ctx->wsum), in,
+                               out);
+        DCRF_CHECK_LAUNCH();
+        return;
+    }
+    for (int m = 0; m < ctx->nk; ++m) {
+        T *blk = out + (size_t)m * NC;
+        const T w = T(ctx->kern[m].weight);
+        // blk = K_m in with its self term
+        if (kind == DCRF_FILTER_EXACT) {
+            exact_kernel(ctx, m, in, blk, C);   // the pairs b != a
+            hipLaunchKernelGGL((k_axpy<T>), dim3(g), dim3(256), 0, st, NC, T(1), in, blk);
+        } else if (kind == DCRF_FILTER_SEPARABLE && !ctx->kern[m].use_rgb) {
+            separable_kernel_t<T>(ctx, m, in, blk, C, T(1), nullptr, T(0), T(0));
+        } else {
+            filter_kernel(ctx, m, in, blk, C, adjoint);   // calibrated lattice
+        }
+        hipLaunchKernelGGL((k_scale<T>), dim3(g), dim3(256), 0, st, NC, w, blk, blk);
+        if (!keep_self)
+            hipLaunchKernelGGL((k_axpy<T>), dim3(g), dim3(256), 0, st, NC, -w, in, blk);
+    }
+    DCRF_CHECK_LAUNCH();
+}
+
 }  // namespace
+
+void filter_parts(dcrf_ctx *ctx, const void *in, void *out, int C, bool adjoint, int kind,
+                  bool keep_self, bool per_kernel) {
+    if (kind == DCRF_FILTER_SEPARABLE && ctx->nimg > 1)
+        fail(DCRF_EUNSUPPORTED, "the separable filter mode takes a single image");
+    if (ctx->dtype == DCRF_F64)
+        filter_parts_t<double>(ctx, static_cast<const double *>(in),
+                               static_cast<double *>(out), C, adjoint, kind, keep_self,
+                               per_kernel);
+    else
+        filter_parts_t<float>(ctx, static_cast<const float *>(in), static_cast<float *>(out),
+                              C, adjoint, kind, keep_self, per_kernel);
+}
 
 void filter_separable(dcrf_ctx *ctx, const void *in, void *out, int C, bool adjoint) {
     if (ctx->nimg > 1)

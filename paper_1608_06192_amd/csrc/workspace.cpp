@@ -156,6 +156,7 @@ size_t workspace_bound(int B, const int *H, const int *W, int L,
     s.add(side * e);
     for (int i = 0; i < 3; ++i) s.add(NL * e);
     for (int i = 0; i < 3; ++i) s.add(NL * e);         // the LP on a label subset
+    for (int i = 0; i < 3; ++i) s.add(NL * e);         // packed per-image arguments
     // Frank-Wolfe, DC_gen, DC_neg, energy
     for (int i = 0; i < 3; ++i) s.add(NL * e);         // c, P_y, P_s
     s.add(N * 4);                                      // s

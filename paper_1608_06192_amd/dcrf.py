@@ -19,6 +19,7 @@ DCRF_OK = 0
 DCRF_F32, DCRF_F64 = 0, 1
 DCRF_FILTER_LATTICE, DCRF_FILTER_EXACT, DCRF_FILTER_SEPARABLE = 0, 1, 2
 DCRF_ADJOINT, DCRF_EXACT, DCRF_SEPARABLE = 1, 2, 4
+DCRF_KEEP_SELF, DCRF_PER_KERNEL = 8, 16
 
 STATUS = {0: "DCRF_OK", -1: "DCRF_EINVAL", -2: "DCRF_ENOMEM", -3: "DCRF_ERANGE",
           -4: "DCRF_ECAPACITY", -5: "DCRF_EHIP", -6: "DCRF_EUNSUPPORTED",
@@ -68,6 +69,9 @@ PROTOTYPES = {
     "dcrf_set_images": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
                              ctypes.POINTER(_P), ctypes.POINTER(dcrf_kernel), _I,
                              _I, _P, ctypes.c_size_t]),
+    "dcrf_batch_set_images": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
+                                   ctypes.POINTER(_P), ctypes.POINTER(dcrf_kernel), _I,
+                                   _I, _P, ctypes.c_size_t]),
     "dcrf_workspace_used": (_I, [_P, ctypes.POINTER(ctypes.c_size_t),
                                  ctypes.POINTER(ctypes.c_size_t)]),
     "dcrf_set_hash_capacity": (_I, [_P, ctypes.c_size_t]),
@@ -104,6 +108,8 @@ PROTOTYPES = {
     "dcrf_fw_saved_size": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_size_t)]),
     "dcrf_fw_forward": (_I, [_P, _P, _P, _I, _PD, _I, _P, _P]),
     "dcrf_fw_backward": (_I, [_P, _P, _P, _I, _I, _P, _P, _P, _PD, _PD]),
+    "dcrf_batch_fw_forward": (_I, [_P, _P, _P, _I, _PD, _I, _P, _P]),
+    "dcrf_batch_fw_backward": (_I, [_P, _P, _P, _I, _I, _P, _P, _P, _PD, _PD]),
     "dcrf_set_profiling": (_I, [_P, _I]),
     "dcrf_get_profile": (_I, [_P, _I, ctypes.POINTER(ctypes.c_char_p), _PD,
                               ctypes.POINTER(ctypes.c_longlong)]),
@@ -319,12 +325,17 @@ class Context:
 
     # -- filter ----------------------------------------------------------
     def filter(self, x: torch.Tensor, adjoint=False, exact=False,
-               out: torch.Tensor | None = None, separable=False) -> torch.Tensor:
+               out: torch.Tensor | None = None, separable=False, keep_self=False,
+               per_kernel=False) -> torch.Tensor:
+        """K' x (or its variants; per_kernel: a (nk, N, C) tensor of the
+        kernels' shares)"""
         C = x.shape[1] if x.dim() == 2 else 1
         if out is None:
-            out = torch.empty_like(x)
+            shape = (self.nk,) + tuple(x.shape) if per_kernel else x.shape
+            out = torch.empty(shape, dtype=x.dtype, device=x.device)
         flags = ((DCRF_ADJOINT if adjoint else 0) | (DCRF_EXACT if exact else 0)
-                 | (DCRF_SEPARABLE if separable else 0))
+                 | (DCRF_SEPARABLE if separable else 0) | (DCRF_KEEP_SELF if keep_self else 0)
+                 | (DCRF_PER_KERNEL if per_kernel else 0))
         self._stream()
         self._check(_lib.dcrf_filter(self._h, self._arg(x, name="in"),
                                      self._arg(out, name="out"), C, flags))
@@ -551,6 +562,39 @@ class Context:
             return gphi, list(gw)
         return gphi, [list(gw[j * self.nk:(j + 1) * self.nk])
                       for j in range(self.nimg)]
+
+    # -- the batch calls with one array per image ------------------------
+    def _ptrs(self, ts, name):
+        if len(ts) != self.nimg:
+            raise ValueError(f"{name} needs one tensor per image ({self.nimg})")
+        return (ctypes.c_void_p * len(ts))(*[self._arg(t, name=name) for t in ts])
+
+    def batch_fw_forward(self, unaries, mu, iters: int, w=None):
+        """fw_forward with one (N_j, L) tensor per image; returns ([y_j], saved)"""
+        L = unaries[0].shape[1]
+        saved = torch.empty(self.fw_saved_size(L, iters), dtype=torch.uint8,
+                            device=self.device)
+        ys = [torch.empty_like(u) for u in unaries]
+        wa = None if w is None else (ctypes.c_double * len(w))(*[float(v) for v in w])
+        self._stream()
+        self._check(_lib.dcrf_batch_fw_forward(
+            self._h, self._ptrs(unaries, "unary"), self._mu(mu), L, wa, iters,
+            self._ptrs(ys, "y_out"), _ptr(saved)))
+        return ys, saved
+
+    def batch_fw_backward(self, unaries, mu, iters: int, saved, grad_ys):
+        """fw_backward with one tensor per image: ([dl/dunary_j], per-image
+        dl/dw lists, their sum)"""
+        L = unaries[0].shape[1]
+        gphis = [torch.empty_like(u) for u in unaries]
+        gw = (ctypes.c_double * (self.nk * self.nimg))()
+        tot = (ctypes.c_double * self.nk)()
+        self._stream()
+        self._check(_lib.dcrf_batch_fw_backward(
+            self._h, self._ptrs(unaries, "unary"), self._mu(mu), L, iters, _ptr(saved),
+            self._ptrs(grad_ys, "grad_y"), self._ptrs(gphis, "grad_unary"), gw, tot))
+        return gphis, [list(gw[j * self.nk:(j + 1) * self.nk])
+                       for j in range(self.nimg)], list(tot)
 
     # -- profiling -------------------------------------------------------
     def set_profiling(self, on: bool):

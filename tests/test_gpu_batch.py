@@ -382,3 +382,29 @@ def test_batch_summed_weight_gradient():
     for m in range(ctx.nk):
         acc = sum(per[j][m] for j in range(len(ims)))
         assert abs(tot[m] - acc) <= 1e-10 * sum(abs(per[j][m]) for j in range(len(ims)))
+
+
+def test_batch_per_image_calls_match_packed():
+    # dcrf_batch_fw_forward / _backward take one array per image and copy
+    # them to and from the packed layout: their results are the packed
+    # calls' (up to the rounding order of the step-size atomics)
+    from paper_1608_06192_amd import dcrf
+    ims = [synth.voronoi_image(h, w, 4, seed=40 + j, regions=5)
+           for j, (h, w) in enumerate([(20, 30), (17, 23), (25, 19)])]
+    ctx = dcrf.Context(0)
+    print("[case] per-image batch calls", flush=True)
+    ctx.set_images([(x.H, x.W) for x in ims], [torch.from_numpy(x.rgb).to(dev()) for x in ims],
+                   KERNELS, dtype=torch.float64)
+    phis = [torch.from_numpy(x.unary).to(dev()) for x in ims]
+    packed = ctx.pack(phis, 4)
+    y, saved = ctx.fw_forward(packed, None, 6)
+    ys, saved2 = ctx.batch_fw_forward(phis, None, 6)
+    rng = np.random.default_rng(41)
+    gys = [torch.from_numpy(rng.normal(size=(x.N, 4))).to(dev()) for x in ims]
+    gp, gw = ctx.fw_backward(packed, None, 6, saved, ctx.pack(gys, 4))
+    gps, gws, gtot = ctx.batch_fw_backward(phis, None, 6, saved2, gys)
+    for j, (a, b) in enumerate(ctx.seg):
+        assert (ys[j] - y[a:b]).abs().max().item() <= 1e-12, j
+        assert (gps[j] - gp[a:b]).abs().max().item() <= 1e-12 * gp[a:b].abs().max().item(), j
+        assert np.allclose(gws[j], gw[j], rtol=1e-12, atol=0), j
+    assert np.allclose(gtot, np.sum(gws, axis=0), rtol=1e-14, atol=0)
