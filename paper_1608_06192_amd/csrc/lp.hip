@@ -524,34 +524,67 @@ __global__ void k_lp_add_col(int N, int L, int col, const int *__restrict__ perm
 constexpr int kLpLeafMax = 256;
 constexpr int kLpLeafMaxF = 16;   // feature dimensions over all kernels
 
-template <typename T>
+// The features of the node's positions sit in LDS (every lane of a wave
+// reads the same position's row: a broadcast); each lane keeps its own in
+// registers. FA, FB: the feature dimensions of the first two kernels, fixed
+// at compile time for the usual layouts (0, 0: any layout, read at run time).
+template <typename T, int FA, int FB>
 __global__ void __launch_bounds__(kLpLeafMax)
 k_lp_leaf(int N, int lcut, const int *__restrict__ perm, ExactSet<T> ex,
           T *__restrict__ acc) {
-    __shared__ T sf[kLpLeafMax][kLpLeafMaxF];
+    constexpr bool fixed = FA > 0;
+    constexpr int FS = fixed ? FA + FB : kLpLeafMaxF;   // LDS row stride
+    __shared__ T sf[kLpLeafMax * FS];
     const long long n = blockIdx.x;
     const int lo = int((n * N) >> lcut), hi = int(((n + 1) * N) >> lcut);
     const int p = lo + (int)threadIdx.x;
+    const int F = fixed ? FA + FB : ex.off[ex.nk];
+    T fa[FS];
+#pragma unroll
+    for (int j = 0; j < FS; ++j) fa[j] = T(0);
     if (p < hi) {
         const int a = perm[p];
         for (int m = 0; m < ex.nk; ++m)
             for (int j = 0; j < ex.d[m]; ++j)
-                sf[threadIdx.x][ex.off[m] + j] = ex.f[m][(size_t)a * ex.d[m] + j];
+                sf[threadIdx.x * FS + ex.off[m] + j] = ex.f[m][(size_t)a * ex.d[m] + j];
     }
     __syncthreads();
     if (p >= hi) return;
     const int me = (int)threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < FS; ++j)
+        if (j < F) fa[j] = sf[me * FS + j];
     T s = T(0);
     for (int t = 0; t < hi - lo; ++t) {
         if (t == me) continue;
-        T kab = T(0);
-        for (int m = 0; m < ex.nk; ++m) {
-            T r2 = T(0);
-            for (int j = ex.off[m]; j < ex.off[m + 1]; ++j) {
-                const T df = sf[me][j] - sf[t][j];
-                r2 += df * df;
+        const T *ft = sf + t * FS;
+        T kab;
+        if constexpr (fixed) {
+            T ra = T(0), rb = T(0);
+#pragma unroll
+            for (int j = 0; j < FA; ++j) {
+                const T df = fa[j] - ft[j];
+                ra += df * df;
             }
-            kab += ex.w[m] * exp(T(-0.5) * r2);
+#pragma unroll
+            for (int j = FA; j < FA + FB; ++j) {
+                const T df = fa[j] - ft[j];
+                rb += df * df;
+            }
+            kab = ex.w[0] * exp(T(-0.5) * ra);
+            if (FB > 0) kab += ex.w[1] * exp(T(-0.5) * rb);
+        } else {
+            kab = T(0);
+            for (int m = 0; m < ex.nk; ++m) {
+                T r2 = T(0);
+#pragma unroll
+                for (int j = 0; j < FS; ++j) {
+                    if (j < ex.off[m] || j >= ex.off[m + 1]) continue;
+                    const T df = fa[j] - ft[j];
+                    r2 += df * df;
+                }
+                kab += ex.w[m] * exp(T(-0.5) * r2);
+            }
         }
         s += t > me ? kab : -kab;
     }
@@ -921,8 +954,19 @@ int *column_pair_sums(dcrf_ctx *ctx, LPWork &W, const T *y, int ld, int col, int
         ExactSet<T> ex = make_exact_set<T>(ctx);
         if (ex.off[ex.nk] > kLpLeafMaxF)
             fail(DCRF_EUNSUPPORTED, "leaf-exact sums take at most 16 feature dimensions");
-        hipLaunchKernelGGL((k_lp_leaf<T>), dim3(1u << lcut), dim3(kLpLeafMax), 0, s, N, lcut,
-                           perm, ex, W.acc.as<T>());
+        const dim3 grid(1u << lcut), block(kLpLeafMax);
+        T *acc = W.acc.as<T>();
+        const int d0 = ex.d[0], d1 = ex.nk > 1 ? ex.d[1] : 0;
+        if (ex.nk == 2 && d0 == 5 && d1 == 2)
+            hipLaunchKernelGGL((k_lp_leaf<T, 5, 2>), grid, block, 0, s, N, lcut, perm, ex, acc);
+        else if (ex.nk == 2 && d0 == 2 && d1 == 5)
+            hipLaunchKernelGGL((k_lp_leaf<T, 2, 5>), grid, block, 0, s, N, lcut, perm, ex, acc);
+        else if (ex.nk == 1 && d0 == 5)
+            hipLaunchKernelGGL((k_lp_leaf<T, 5, 0>), grid, block, 0, s, N, lcut, perm, ex, acc);
+        else if (ex.nk == 1 && d0 == 2)
+            hipLaunchKernelGGL((k_lp_leaf<T, 2, 0>), grid, block, 0, s, N, lcut, perm, ex, acc);
+        else
+            hipLaunchKernelGGL((k_lp_leaf<T, 0, 0>), grid, block, 0, s, N, lcut, perm, ex, acc);
         DCRF_CHECK_LAUNCH();
     }
     return perm;
