@@ -44,7 +44,10 @@ Beside it the JSON line reports:
   and the same for the separable mode (spatial kernel exact, bilateral on
   the lattice);
 * lattice_filter.separable_ms / separable_fw_iteration_us: the dense filter
-  and a Frank-Wolfe iteration in the separable mode at 500x375.
+  and a Frank-Wolfe iteration in the separable mode at 500x375;
+* lattice_filter.fused_splat_fw_iteration_us: a Frank-Wolfe iteration with
+  the one-hot splat done pixel by pixel inside the conditional-gradient
+  kernel instead of its own vertex-major launch.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -786,6 +789,20 @@ def main():
         ctx.set_filter_mode("lattice")
         filt["separable_ms"] = sep_ms
         filt["separable_fw_iteration_us"] = sep_fw_us
+        # the one-hot splat inside the conditional-gradient kernel
+        # (pixel-major, runs of equal vertex and label summed per wave)
+        ctx.set_tune(fw_splat=1)
+        yfu = y0.clone()
+        ctx.qp_frank_wolfe(phi, mu, yfu, 5, trace=False)
+        yfu = y0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.qp_frank_wolfe(phi, mu, yfu, 100, trace=False)
+        torch.cuda.synchronize()
+        filt["fused_splat_fw_iteration_us"] = (time.perf_counter() - t0) * 1e6 / 100
+        ctx.set_tune(fw_splat=0)
+        log(f"[bench] FW iteration with the splat in the LMO kernel: "
+            f"{filt['fused_splat_fw_iteration_us']:.1f} us (100 iterations)")
         log(f"[bench] separable mode: dense filter {sep_ms * 1e3:.1f} us, FW iteration "
             f"{sep_fw_us:.1f} us (50 iterations)")
     ext = {} if args.no_ext else extensions(torch, dcrf, synth, dev, kernels)

@@ -107,6 +107,13 @@ typedef struct {
     int blur_block;               /* threads per block of the blur            */
     int blur_group;               /* blur directions applied per launch       */
     int tiles;                    /* 1: splats and slices by 16x16 pixel tiles */
+    int fw_splat;                 /* 0 (default): the Frank-Wolfe step splats
+                                     its one-hot s in a launch of its own
+                                     (vertex by vertex, over the inverse
+                                     index); 1: from the kernel that picks s,
+                                     pixel by pixel (runs of lanes with the
+                                     same vertex and label summed in the wave
+                                     first, one atomic per run) */
     double ms;                    /* time of the tuned filter paths, ms       */
 } dcrf_tune;
 
@@ -238,7 +245,7 @@ int dcrf_autotune(dcrf_ctx *ctx, int L, int reps, dcrf_tune *out);
 /* Set the launch shapes directly (the `ms` field is ignored): splat_chunk and
  * dense_chunk in {16, 32, 64, 128, 256}, splat_stage 0 or 1,
  * blur_vectors_per_thread in 1..4, blur_block in {64, 128, 256}, blur_group
- * in 1..3, tiles 0 or 1; DCRF_EINVAL otherwise.
+ * in 1..3, tiles 0 or 1, fw_splat 0 or 1; DCRF_EINVAL otherwise.
  * Results are the same for every choice up to floating-point summation
  * order. */
 int dcrf_set_tune(dcrf_ctx *ctx, const dcrf_tune *tune);

@@ -287,6 +287,7 @@ int dcrf_autotune(dcrf_ctx *ctx, int L, int reps, dcrf_tune *out) {
             out->blur_block = ctx->blur_block;
             out->blur_group = ctx->blur_group;
             out->tiles = ctx->tile_mode;
+            out->fw_splat = ctx->fw_splat;
             out->ms = ms;
         }
     });
@@ -308,6 +309,7 @@ int dcrf_set_tune(dcrf_ctx *ctx, const dcrf_tune *t) {
         REQUIRE(t->blur_group >= 1 && t->blur_group <= 3, "blur_group must be in 1..3");
         REQUIRE(t->tiles == 0 || t->tiles == 1, "tiles must be 0 or 1");
         REQUIRE(t->splat_stage == 0 || t->splat_stage == 1, "splat_stage must be 0 or 1");
+        REQUIRE(t->fw_splat == 0 || t->fw_splat == 1, "fw_splat must be 0 or 1");
         if (t->splat_chunk != ctx->splat_chunk || t->dense_chunk != ctx->dense_chunk)
             dcrf::rechunk(ctx, t->splat_chunk, t->dense_chunk);
         ctx->splat_lds = t->splat_stage;
@@ -315,6 +317,7 @@ int dcrf_set_tune(dcrf_ctx *ctx, const dcrf_tune *t) {
         ctx->blur_block = t->blur_block;
         ctx->blur_group = t->blur_group;
         ctx->tile_mode = t->tiles;
+        ctx->fw_splat = t->fw_splat;
         if (t->tiles && ctx->has_image) dcrf::ensure_tiles(ctx);
     });
 }

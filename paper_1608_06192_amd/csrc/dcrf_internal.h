@@ -304,6 +304,7 @@ struct dcrf_ctx {
     int blur_block = 256;    // threads per block in the blur
     int blur_group = 2;      // blur directions applied per launch (1..3)
     int tile_mode = 0;       // splats and slices through the per-tile slots
+    int fw_splat = 0;        // Frank-Wolfe: one-hot splat inside the LMO kernel
     // 2-D pixel tiles of every image (tiles.hip)
     int ntiles = 0;          // 0 until the tile map is built (only when tiles are asked for)
     dcrf::DevBuf tiles;              // ntiles x int4: first row, row stride, rows, cols

@@ -340,6 +340,70 @@ __device__ __forceinline__ void tile_copy_out(T *__restrict__ dst, int n, int C,
     }
 }
 
+// tile_copy_in in two halves, so that the loads of several tiles (or of a
+// tile and other data) are in flight together: tile_fetch issues a thread's
+// loads into a TileRegs, tile_put stores them into the LDS tile in
+// tile_copy_in's layout. Every thread calls both; neither synchronises.
+// Odd C: v[k] is the tile's 16-byte vector threadIdx.x + k TP (clamped to the
+// last whole one), `tail` element nv w + threadIdx.x; even C: element k of v
+// (viewed as K w values of T) is the tile's element threadIdx.x + k TP.
+template <typename T, int TP, int CMAX>
+struct TileRegs {
+    using V = typename Vec16<T>::type;
+    static constexpr int w = Vec16<T>::n;
+    static constexpr int K = (CMAX + w - 1) / w;
+    V v[K];
+    T tail;
+    __device__ __forceinline__ T &el(int k) { return reinterpret_cast<T *>(v)[k]; }
+    __device__ __forceinline__ const T &el(int k) const {
+        return reinterpret_cast<const T *>(v)[k];
+    }
+};
+
+template <typename T, int TP, int CMAX>
+__device__ __forceinline__ void tile_fetch(const T *__restrict__ src, int n, int C,
+                                           TileRegs<T, TP, CMAX> &r) {
+    using R = TileRegs<T, TP, CMAX>;
+    if (C & 1) {
+        const int nv = n / R::w;
+        const auto *s = reinterpret_cast<const typename R::V *>(src);
+        if (nv > 0) {
+#pragma unroll
+            for (int k = 0; k < R::K; ++k) r.v[k] = s[min((int)threadIdx.x + k * TP, nv - 1)];
+        }
+        const int i = nv * R::w + (int)threadIdx.x;
+        r.tail = i < n ? src[i] : T(0);
+    } else if (n > 0) {
+#pragma unroll
+        for (int k = 0; k < CMAX; ++k) r.el(k) = src[min((int)threadIdx.x + k * TP, n - 1)];
+    }
+}
+
+template <typename T, int TP, int CMAX>
+__device__ __forceinline__ void tile_put(int n, int C, const TileRegs<T, TP, CMAX> &r,
+                                         T *lds) {
+    using R = TileRegs<T, TP, CMAX>;
+    if (C & 1) {
+        const int nv = n / R::w;
+        auto *l = reinterpret_cast<typename R::V *>(lds);
+        if (nv > 0) {
+#pragma unroll
+            for (int k = 0; k < R::K; ++k) l[min((int)threadIdx.x + k * TP, nv - 1)] = r.v[k];
+        }
+        const int i = nv * R::w + (int)threadIdx.x;
+        if (i < n) lds[i] = r.tail;
+    } else if (n > 0) {
+        const int Ls = C | 1;
+        const float inv = 1.0f / float(C);
+#pragma unroll
+        for (int k = 0; k < CMAX; ++k) {
+            const int i = min((int)threadIdx.x + k * TP, n - 1);
+            const int p = int((float(i) + 0.5f) * inv);
+            lds[p * Ls + (i - p * C)] = r.el(k);
+        }
+    }
+}
+
 // Row threadIdx.x of a tile staged by tile_copy_in, into registers (no
 // synchronisation: the caller has synchronised after the copy, and a thread
 // that later overwrites only its own row needs none either).
@@ -364,6 +428,16 @@ __device__ __forceinline__ void tile_load(const T *__restrict__ g, long long p0,
         for (int j = 0; j < LMAX; ++j)
             if (j < C) r[j] = lds[threadIdx.x * Ls + j];
     }
+    __syncthreads();
+}
+
+// tile_load's second half for a tile fetched by tile_fetch (np rows of C)
+template <typename T, int LMAX, int TP>
+__device__ __forceinline__ void tile_rows(int np, int C, const TileRegs<T, TP, LMAX> &f,
+                                          T *lds, T (&r)[LMAX]) {
+    tile_put<T, TP, LMAX>(np * C, C, f, lds);
+    __syncthreads();
+    tile_read_own<T, LMAX>(np, C, lds, r);
     __syncthreads();
 }
 
@@ -525,9 +599,11 @@ __device__ __forceinline__ void slice_pixel52_staged(const LatSet<T> &ls, int t,
 // the LDS tile qt (row stride lds_stride(C)): one task per (pixel, 16-byte
 // chunk of its row), consecutive lanes taking consecutive chunks of one
 // pixel, so that a wave's loads of one corner cover a few rows instead of one
-// row per lane. All threads of the block call it; the caller synchronises
-// before reading qt.
-template <typename T, int LMAX, int TP>
+// row per lane. A thread takes its tasks U at a time with the loads of all U
+// issued together (a task past the end repeats the last one and stores
+// nothing), so that 9 U rows are in flight per lane. All threads of the block
+// call it; the caller synchronises before reading qt.
+template <typename T, int LMAX, int TP, int U = 2>
 __device__ __forceinline__ void slice_tile52_coop(const LatSet<T> &ls, int np, int C,
                                                   const int32_t *sid, const T *sw,
                                                   T *qt) {
@@ -540,43 +616,135 @@ __device__ __forceinline__ void slice_tile52_coop(const LatSet<T> &ls, int np, i
     const int Ls = lds_stride(C);
     const int ntask = np * nq;
 #pragma unroll
-    for (int i = 0; i < KQ; ++i) {
-        const int task = (int)threadIdx.x + i * TP;
-        if (task >= ntask) break;
-        const int p = task / nq, qc = task - p * nq;
-        V acc;
-        T *ac = reinterpret_cast<T *>(&acc);
+    for (int i0 = 0; i0 < KQ; i0 += U) {
+        if ((int)threadIdx.x + i0 * TP >= ntask) break;
+        int p[U], qc[U];
+        V va[U][6], vb[U][3];
+        T fa[U][6], fb[U][3];
 #pragma unroll
-        for (int e = 0; e < w; ++e) ac[e] = T(0);
-        V va[6], vb[3];
-        T fa[6], fb[3];
+        for (int u = 0; u < U; ++u) {
+            const int task = min((int)threadIdx.x + (i0 + u) * TP, ntask - 1);
+            p[u] = task / nq;
+            qc[u] = task - p[u] * nq;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const int id = sid[p * 6 + k];
-            fa[k] = id >= 0 ? A.wg * sw[p * 6 + k] : T(0);
-            va[k] = *reinterpret_cast<const V *>(A.Vf + (size_t)(id >= 0 ? id : 0) * A.ld + qc * w);
+            for (int k = 0; k < 6; ++k) {
+                const int id = sid[p[u] * 6 + k];
+                fa[u][k] = id >= 0 ? A.wg * sw[p[u] * 6 + k] : T(0);
+                va[u][k] = *reinterpret_cast<const V *>(
+                    A.Vf + (size_t)(unsigned)(id >= 0 ? id : 0) * (unsigned)A.ld + qc[u] * w);
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int id = sid[6 * TP + p[u] * 3 + k];
+                fb[u][k] = id >= 0 ? B.wg * sw[6 * TP + p[u] * 3 + k] : T(0);
+                vb[u][k] = *reinterpret_cast<const V *>(
+                    B.Vf + (size_t)(unsigned)(id >= 0 ? id : 0) * (unsigned)B.ld + qc[u] * w);
+            }
         }
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int id = sid[6 * TP + p * 3 + k];
-            fb[k] = id >= 0 ? B.wg * sw[6 * TP + p * 3 + k] : T(0);
-            vb[k] = *reinterpret_cast<const V *>(B.Vf + (size_t)(id >= 0 ? id : 0) * B.ld + qc * w);
+        for (int u = 0; u < U; ++u) {
+            T ac[w];
+#pragma unroll
+            for (int e = 0; e < w; ++e) ac[e] = T(0);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const T *x = reinterpret_cast<const T *>(&va[u][k]);
+#pragma unroll
+                for (int e = 0; e < w; ++e) ac[e] += fa[u][k] * x[e];
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const T *x = reinterpret_cast<const T *>(&vb[u][k]);
+#pragma unroll
+                for (int e = 0; e < w; ++e) ac[e] += fb[u][k] * x[e];
+            }
+            if ((int)threadIdx.x + (i0 + u) * TP < ntask) {
+#pragma unroll
+                for (int e = 0; e < w; ++e)
+                    if (qc[u] * w + e < C) qt[p[u] * Ls + qc[u] * w + e] = ac[e];
+            }
         }
+    }
+}
+
+// ------------------------------------------- one-hot splat, pixel-major
+
+// Every lane of the wave holds one term: v to be added at row `id` (< 0: no
+// term), column `lab` of V (row stride ld). Consecutive lanes hold
+// consecutive pixels, whose terms often share their (row, column): such runs
+// are summed inside the wave first (a segmented scan over lanes), and the
+// last lane of each run adds the run's sum to V with one atomic. All lanes of
+// the wave call it together.
+template <typename T>
+__device__ __forceinline__ void wave_run_add(T *V, int ld, int id, int lab, T v) {
+    const int lane = (int)(threadIdx.x & 63);
+    const int pid = __shfl_up(id, 1), plab = __shfl_up(lab, 1);
+    const bool head = lane == 0 || pid != id || plab != lab;
+    const unsigned long long hm = __ballot(head);
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+    const int start = 63 - __clzll(hm & upto);   // the first lane of this run
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const T *x = reinterpret_cast<const T *>(&va[k]);
+    for (int d = 1; d < 64; d <<= 1) {
+        const T up = __shfl_up(v, d);
+        if (lane - d >= start) v += up;
+    }
+    const bool last = lane == 63 || ((hm >> (lane + 1)) & 1ull);
+    if (last && id >= 0 && lab >= 0) atomic_add(V + (size_t)(unsigned)id * (unsigned)ld + lab, v);
+}
+
+// The corners of one pixel in a 5-D + 2-D lattice pair (ls.shape52), loaded
+// ahead of their use; id -1 for a missing vertex or an inactive lane.
+template <typename T>
+struct Corners52 {
+    int id[kCorners52];
+    T w[kCorners52];
+};
+
+template <typename T>
+__device__ __forceinline__ void load_corners52(const LatSet<T> &ls, long long a, bool act,
+                                               Corners52<T> &c) {
+    const long long i = act ? a : 0;
 #pragma unroll
-            for (int e = 0; e < w; ++e) ac[e] += fa[k] * x[e];
+    for (int k = 0; k < 6; ++k) {
+        c.id[k] = ls.l[0].vid[i * 6 + k];
+        c.w[k] = ls.l[0].w[i * 6 + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        c.id[6 + k] = ls.l[1].vid[i * 3 + k];
+        c.w[6 + k] = ls.l[1].w[i * 3 + k];
+    }
+    if (!act)
+#pragma unroll
+        for (int k = 0; k < kCorners52; ++k) c.id[k] = -1;
+}
+
+// The splat of the one-hot rows of the wave's pixels: pixel a (label lab,
+// < 0 or an inactive lane: nothing) adds w_m(a, k) to V0_m[v_m(a, k)][lab]
+// for every corner k of every lattice, the terms of a run of lanes with the
+// same vertex and label summed first (wave_run_add). The caller's targets
+// V0 hold zeros before the first wave adds to them.
+template <typename T>
+__device__ __forceinline__ void splat_onehot52(const LatSet<T> &ls, const Corners52<T> &c,
+                                               int lab) {
+#pragma unroll
+    for (int k = 0; k < kCorners52; ++k) {
+        const LatView<T> &L = ls.l[k < 6 ? 0 : 1];
+        wave_run_add<T>(L.V0, L.ld, c.id[k], lab, c.w[k]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void splat_onehot(const LatSet<T> &ls, long long a, bool act,
+                                             int lab) {
+    for (int m = 0; m < ls.nk; ++m) {
+        const LatView<T> &L = ls.l[m];
+        const int D1 = L.d + 1;
+        for (int k = 0; k < D1; ++k) {
+            const int id = act ? L.vid[a * D1 + k] : -1;
+            const T wv = act ? L.w[a * D1 + k] : T(0);
+            wave_run_add<T>(L.V0, L.ld, id, lab, wv);
         }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const T *x = reinterpret_cast<const T *>(&vb[k]);
-#pragma unroll
-            for (int e = 0; e < w; ++e) ac[e] += fb[k] * x[e];
-        }
-#pragma unroll
-        for (int e = 0; e < w; ++e)
-            if (qc * w + e < C) qt[p * Ls + qc * w + e] = ac[e];
     }
 }
 

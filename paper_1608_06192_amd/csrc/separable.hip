@@ -246,11 +246,9 @@ void filter_separable_t(dcrf_ctx *ctx, const T *in, T *out, int C, bool adjoint)
     const hipStream_t st = ctx->stream;
     const size_t NC = (size_t)ctx->N * C;
     const int g = ceil_div((long long)NC, 256);
-    int last_sep = -1, nlat = 0;
-    for (int m = 0; m < ctx->nk; ++m) {
-        if (ctx->kern[m].use_rgb) ++nlat;
-        else last_sep = m;
-    }
+    int last_sep = -1;
+    for (int m = 0; m < ctx->nk; ++m)
+        if (!ctx->kern[m].use_rgb) last_sep = m;
     // acc * acc_w holds the sum of w_m K_m Y so far (acc_w: the weight of a
     // single lattice kernel, applied in the last pass's epilogue)
     T *acc = nullptr, *part = nullptr;

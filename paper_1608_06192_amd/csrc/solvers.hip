@@ -196,9 +196,12 @@ template <typename T> struct LmoTile;
 template <> struct LmoTile<float> { static constexpr int kPix = 256; };
 template <> struct LmoTile<double> { static constexpr int kPix = 128; };
 
-template <typename T, int LMAX>
+// SPLAT: the kernel also splats the one-hot s into the lattices (step 2),
+// pixel-major: 1 for any lattice set, 2 for a 5-D + 2-D pair (corners loaded
+// at the start, so that their latency overlaps the tiles').
+template <typename T, int LMAX, int SPLAT>
 __global__ void __launch_bounds__(LmoTile<T>::kPix)
-k_fw_lmo_rows(FWArgs<T> A) {
+k_fw_lmo_rows(FWArgs<T> A, LatSet<T> ls) {
     constexpr int TP = LmoTile<T>::kPix;
     __shared__ __align__(16) T lds[TP * (LMAX | 1)];
     __shared__ double red[kP1 * TP];
@@ -217,6 +220,8 @@ k_fw_lmo_rows(FWArgs<T> A) {
         const int np = hi - lo;
         const long long a = p0 + threadIdx.x;
         const bool act = (int)threadIdx.x < np;
+        Corners52<T> cn;
+        if (SPLAT == 2) load_corners52<T>(ls, a, act, cn);
         T y[LMAX], py[LMAX], c[LMAX];
 #pragma unroll
         for (int j = 0; j < LMAX; ++j) y[j] = py[j] = c[j] = T(0);
@@ -244,6 +249,7 @@ k_fw_lmo_rows(FWArgs<T> A) {
             tile_store<T, LMAX, TP>(A.Psave, p0, np, L, lds, py);
         }
         tile_load<T, LMAX, TP>(A.c, p0, np, L, lds, c);
+        int lab = -1;
         if (act) {
             int best = 0;
             T bv = c[0] + T(2) * py[0];
@@ -256,6 +262,7 @@ k_fw_lmo_rows(FWArgs<T> A) {
                 }
             }
             A.s[a] = best;
+            lab = best;
             if (A.ssave) A.ssave[a] = best;
             acc[6] += (best != sp) ? 1.0 : 0.0;
 #pragma unroll
@@ -274,6 +281,8 @@ k_fw_lmo_rows(FWArgs<T> A) {
                 }
             }
         }
+        if (SPLAT == 2) splat_onehot52<T>(ls, cn, lab);
+        if (SPLAT == 1) splat_onehot<T>(ls, a, act, lab);
     }
     block_sum<kP1, TP>(acc, red);
     if (img >= 0 && threadIdx.x < kP1)
@@ -315,7 +324,13 @@ k_fw_slice_rows(FWSliceArgs<T> A, LatSet<T> ls) {
         // so that its loads overlap the gathers of the slice
         const bool staged = !A.pre && ls.shape52 && np > 0;   // uniform over the block
         const bool early = POTTS && !A.pre && !staged;
-        if (staged) stage_corners52<T, TP>(ls, p0, np, sid, swc);
+        // staged: the tile of y is fetched into registers with the corners,
+        // so that its loads overlap theirs and the gathers of the slice
+        TileRegs<T, TP, LMAX> fy;
+        if (staged) {
+            tile_fetch<T, TP, LMAX>(A.y + p0 * L, np * L, L, fy);
+            stage_corners52<T, TP>(ls, p0, np, sid, swc);
+        }
         if (early) tile_copy_in<T, TP, LMAX>(A.y + p0 * L, np * L, L, lds);
         if (A.pre) {
             tile_load<T, LMAX, TP>(A.pre, p0, np, L, lds, q);
@@ -368,7 +383,9 @@ k_fw_slice_rows(FWSliceArgs<T> A, LatSet<T> ls) {
         T y[LMAX];
 #pragma unroll
         for (int j = 0; j < LMAX; ++j) y[j] = T(0);
-        if (early) {
+        if (staged) {
+            tile_rows<T, LMAX, TP>(np, L, fy, lds, y);
+        } else if (early) {
             __syncthreads();
             tile_read_own<T, LMAX>(np, L, lds, y);
         } else {
@@ -882,6 +899,8 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
     const int *seg = ctx->seg.as<int>();
     const bool potts = potts_known >= 0 ? potts_known != 0 : is_potts<T>(ctx, mu, L);
     const LatSet<T> ls = exact ? LatSet<T>{} : make_lat_set<T>(ctx, L);
+    // the one-hot splat inside the LMO kernel (the row kernels only)
+    const int fuse = (!exact && rows && ctx->fw_splat) ? (ls.shape52 ? 2 : 1) : 0;
     for (int it = 0; it < iters; ++it) {
         // checkpoints are written by the row kernel itself; the flat kernel
         // (more than 32 labels) leaves them to copies below
@@ -893,10 +912,18 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
                     ysv, psv, ssv};
         {
             ProfScope ps(ctx, PROF_FW_LMO);
-            if (rows) {
-                DCRF_DISPATCH_ROWS(L, DCRF_PLAUNCH(ps, (k_fw_lmo_rows<T, LMAX>),
+            if (rows && fuse == 2) {
+                DCRF_DISPATCH_ROWS(L, DCRF_PLAUNCH(ps, (k_fw_lmo_rows<T, LMAX, 2>),
                                                          dim3(G1), dim3(LmoTile<T>::kPix),
-                                                         0, st, a));
+                                                         0, st, a, ls));
+            } else if (rows && fuse == 1) {
+                DCRF_DISPATCH_ROWS(L, DCRF_PLAUNCH(ps, (k_fw_lmo_rows<T, LMAX, 1>),
+                                                         dim3(G1), dim3(LmoTile<T>::kPix),
+                                                         0, st, a, ls));
+            } else if (rows) {
+                DCRF_DISPATCH_ROWS(L, DCRF_PLAUNCH(ps, (k_fw_lmo_rows<T, LMAX, 0>),
+                                                         dim3(G1), dim3(LmoTile<T>::kPix),
+                                                         0, st, a, ls));
             } else {
                 DCRF_PLAUNCH(ps, (k_fw_lmo_flat<T>), dim3(G1), dim3(kThreads), 0,
                                    st, a);
@@ -917,7 +944,7 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
             filter_apply(ctx, ctx->tmpB.p, ctx->tmpA.p, L, false, ctx->mode);
             pre = ctx->tmpA.as<T>();
         } else {
-            splat_labels(ctx, w.s, L);
+            if (!fuse) splat_labels(ctx, w.s, L);
             blur_all(ctx, L, false);
             if (save && vblock) save_vertices(it + 1);
         }

@@ -160,6 +160,56 @@ def test_fw_fp64_matches_oracle(mode):
     assert abs(e - eo) <= 1e-10 * abs(eo)
 
 
+WIDE = dict(use_rgb=1, theta_pos=20.0, theta_rgb=30.0, weight=2.0)
+
+
+@pytest.mark.parametrize("kernels", [[synth.BILATERAL], [synth.SPATIAL, synth.BILATERAL],
+                                     [synth.BILATERAL, synth.SPATIAL, WIDE]])
+@pytest.mark.parametrize("fw_splat", [0, 1])
+def test_fw_fp64_kernel_layouts_and_splat_paths(kernels, fw_splat):
+    # the one-hot splat inside the conditional-gradient kernel for lattice
+    # sets other than (5-D, 2-D) (one lattice, the pair in the other order,
+    # three lattices) and the splat launch of its own: 37x29 (a ragged last
+    # tile), L = 5, 20 iterations in FP64 against the oracle
+    im = synth.voronoi_image(37, 29, 5, seed=11, regions=6)
+    ctx = gpu_ctx(im, torch.float64, kernels=kernels)
+    ctx.set_tune(fw_splat=fw_splat)
+    mu = synth.potts(im.L)
+    model = O.Model(im.H, im.W, im.rgb, [O.Kernel(**k) for k in kernels])
+    qp = O.QP(model, im.unary, mu)
+    y0 = O.softmax_neg(im.unary)
+    st = O.frank_wolfe(qp, y0, 20)
+    y = T(y0, torch.float64)
+    tr = ctx.qp_frank_wolfe(T(im.unary, torch.float64), T(mu, torch.float64), y, 20)
+    assert np.abs(y.cpu().numpy() - st.y).max() < 1e-9
+    for (fo, _, ao), (fg, _, ag, _) in zip(st.trace, tr):
+        assert abs(fg - fo) <= 1e-9 * abs(fo)
+        assert abs(ag - ao) <= 1e-8
+
+
+def test_fw_fused_and_separate_splat_agree_500x375():
+    # the bench workload (500x375, L = 21, 5-D + 2-D lattices) in FP64, 30
+    # iterations with the splat inside the conditional-gradient kernel and
+    # with a splat launch of its own (the default): the same arithmetic up
+    # to the order of the splat's sums, so the trajectories agree to 1e-9
+    im = synth.make("voronoi_500x375_L21")
+    phi = T(im.unary, torch.float64)
+    mu = T(synth.potts(im.L), torch.float64)
+    y0 = O.softmax_neg(im.unary)
+    out = []
+    for fw_splat in (1, 0):
+        ctx = gpu_ctx(im, torch.float64)
+        ctx.set_tune(fw_splat=fw_splat)
+        y = T(y0, torch.float64)
+        tr = ctx.qp_frank_wolfe(phi, mu, y, 30)
+        out.append((y.cpu().numpy(), tr))
+    (ya, ta), (yb, tb) = out
+    print(f"[fw splat paths] max |dy| {np.abs(ya - yb).max():.3g}", flush=True)
+    assert np.abs(ya - yb).max() < 1e-9
+    for ra, rb in zip(ta, tb):
+        assert abs(ra[0] - rb[0]) <= 1e-9 * abs(rb[0])
+
+
 def test_fw_fp64_matches_oracle_320x213():
     # 320x213, L = 21, 50 iterations in FP64 on both sides: every argmin is
     # decided in the same precision, so the whole trajectory must agree
