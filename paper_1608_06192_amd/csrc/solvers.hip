@@ -204,7 +204,7 @@ __global__ void __launch_bounds__(LmoTile<T>::kPix)
 k_fw_lmo_rows(FWArgs<T> A, LatSet<T> ls) {
     constexpr int TP = LmoTile<T>::kPix;
     __shared__ __align__(16) T lds[TP * (LMAX | 1)];
-    __shared__ double red[kP1 * TP];
+    __shared__ double red[kP1 * (TP / 64)];
     const int L = A.L;
     const int tile = xcd_block(blockIdx.x, gridDim.x);
     int lo, hi;
@@ -284,23 +284,23 @@ k_fw_lmo_rows(FWArgs<T> A, LatSet<T> ls) {
         if (SPLAT == 2) splat_onehot52<T>(ls, cn, lab);
         if (SPLAT == 1) splat_onehot<T>(ls, a, act, lab);
     }
-    block_sum<kP1, TP>(acc, red);
+    const double tot = block_sum_waves<kP1, TP>(acc, red);
     if (img >= 0 && threadIdx.x < kP1)
         unsafeAtomicAdd(&A.acc[acc_off(A.it & 1, blockIdx.x & (kSets - 1), A.nimg, img) +
-                               threadIdx.x], acc[threadIdx.x]);
+                               threadIdx.x], tot);
 }
 
 // Step 4, one thread per pixel (see the file comment). POTTS: mu = 1 - I,
 // so (Q mu^T)_i = sum_j Q_j - Q_i.
 template <typename T, int LMAX, bool POTTS>
-__global__ void __launch_bounds__(RowTile<T>::kPix, 4)
+__global__ void __launch_bounds__(RowTile<T>::kPix, 3)
 k_fw_slice_rows(FWSliceArgs<T> A, LatSet<T> ls) {
     constexpr int TP = RowTile<T>::kPix;
     __shared__ __align__(16) T lds[TP * (LMAX | 1)];
     __shared__ int32_t sid[TP * kCorners52];
     __shared__ T swc[TP * kCorners52];
     __shared__ T smu[POTTS ? 1 : LMAX * LMAX];
-    __shared__ double red[kP2 * TP];
+    __shared__ double red[kP2 * (TP / 64)];
     const int L = A.L;
     if (!POTTS) {
         for (int i = threadIdx.x; i < L * L; i += TP)
@@ -402,11 +402,10 @@ k_fw_slice_rows(FWSliceArgs<T> A, LatSet<T> ls) {
         }
         tile_store<T, LMAX, TP>(A.Ps, p0, np, L, lds, P);
     }
-    double v[kP2] = {acc[0], acc[1]};
-    block_sum<kP2, TP>(v, red);
+    const double tot = block_sum_waves<kP2, TP>(acc, red);
     if (img >= 0 && threadIdx.x < kP2)
         unsafeAtomicAdd(&A.acc[acc_off(A.it & 1, blockIdx.x & (kSets - 1), A.nimg, img) +
-                               kP1 + threadIdx.x], v[threadIdx.x]);
+                               kP1 + threadIdx.x], tot);
     if (blockIdx.x == 0)   // the other parity: read by this iteration's step 1 only
         for (int i = threadIdx.x; i < kSets * A.nimg * kPT; i += TP)
             A.acc[acc_off((A.it + 1) & 1, 0, A.nimg, 0) + i] = 0.0;
