@@ -402,6 +402,84 @@ k_lp_neighbours(int S, int N, int l, int M, int D1, unsigned ep,
     }
 }
 
+// Dense numbering for the first levels, where a level's nodes times the
+// lattice's vertices fit the sub-vertex arrays (2^l M <= N (d + 1)): the
+// sub-vertex (node n, global vertex v) is number n M + v, so no hash is
+// built. mark[n M + v] = the level's mark when some entry of node n has
+// vertex v; the other numbers are no sub-vertex, hold zeros and have no
+// neighbours. Neighbours come straight from the global table: (n, v +- u_j)
+// is (n, nbr_j(v)) when that number is marked.
+template <typename T, bool AGG>
+__global__ void __launch_bounds__(kLpSplatThreads)
+k_lp_dense_splat(int N, int l, int D1, int M, int mk, const int *__restrict__ pos_vid,
+                 const T *__restrict__ pos_w, int *__restrict__ mark,
+                 int *__restrict__ ent_id, T *__restrict__ V0) {
+    __shared__ int skey[AGG ? kLpSplatSlots : 1];
+    __shared__ T sval[AGG ? kLpSplatSlots : 1];
+    if (AGG) {
+        for (int i = threadIdx.x; i < kLpSplatSlots; i += kLpSplatThreads) {
+            skey[i] = -1;
+            sval[i] = T(0);
+        }
+        __syncthreads();
+    }
+    const int e = xcd_block(blockIdx.x, gridDim.x) * kLpSplatThreads + threadIdx.x;
+    if (e < N * D1) {
+        int id = -1;
+        const int p = e / D1;
+        long long node;
+        int side;
+        const int v = pos_vid[e];
+        if (dnc_node(p, l, N, node, side) && v >= 0) {
+            id = int(node) * M + v;   // < 2^l M <= N D1 < 2^31
+            mark[id] = mk;
+            const int key = id * 2 + side;
+            const T w = pos_w[e];
+            if (AGG) {
+                int h = int(mix64((uint64_t)key) & (kLpSplatSlots - 1));
+                for (int probe = 0; probe < kLpSplatSlots; ++probe) {
+                    const int prev = atomicCAS(&skey[h], -1, key);
+                    if (prev == -1 || prev == key) {
+                        atomicAdd(&sval[h], w);
+                        break;
+                    }
+                    h = (h + 1) & (kLpSplatSlots - 1);
+                }
+            } else {
+                atomic_add(&V0[key], w);
+            }
+        }
+        ent_id[e] = id;
+    }
+    if (AGG) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < kLpSplatSlots; i += kLpSplatThreads) {
+            const int key = skey[i];
+            if (key >= 0) atomic_add(&V0[key], sval[i]);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_lp_dense_nbrs(int S, int M, int D1, int mk, const int *__restrict__ mark,
+                const int *__restrict__ nbr_global, int *__restrict__ nbr_sub,
+                int cap_sub) {
+    const int id = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (id >= S) return;
+    const int n = id / M, v = id - n * M;
+    const bool here = mark[id] == mk;
+    int vn[2 * kLpMaxNb];
+#pragma unroll
+    for (int q = 0; q < 2 * kLpMaxNb; ++q)
+        vn[q] = here && q < 2 * D1 ? nbr_global[((size_t)(q >> 1) * M + v) * 2 + (q & 1)] : -1;
+    int ok[2 * kLpMaxNb];
+#pragma unroll
+    for (int q = 0; q < 2 * kLpMaxNb; ++q) ok[q] = vn[q] >= 0 ? mark[n * M + vn[q]] == mk : 0;
+#pragma unroll
+    for (int q = 0; q < 2 * kLpMaxNb; ++q)
+        if (q < 2 * D1) nbr_sub[(size_t)q * cap_sub + id] = ok[q] ? n * M + vn[q] : -1;
+}
+
 // one blur pass over the sub-lattice (all S = N D1 numbers; those that are no
 // sub-vertex hold zeros and have no neighbours): one thread per sub-vertex
 // moves both channels as one 2-vector; the second pass clears V0
@@ -745,11 +823,13 @@ k_dot(size_t n, const T *__restrict__ a, const T *__restrict__ b,
 struct LPWork {
     DevBuf keys, keys2, vals, vals2, hist;
     struct PerLat {
-        DevBuf hkeys, slot_vid, ent_slot, ent_id, sub_nv, nbr_sub, V[3];
+        DevBuf hkeys, slot_vid, ent_slot, ent_id, sub_nv, nbr_sub, V[3], mark;
         DevBuf pos_vid, pos_w;   // the label's vertex ids and weights by position
         size_t cap = 0;
         int cap_sub = 0;
         unsigned tag = 0;          // the last level's tag in hkeys (0: none yet)
+        int mk = 0;                // the last dense level's mark (0: none yet)
+        const void *mk_buf = nullptr;    // the mark allocation mk refers to
         const void *tag_buf = nullptr;   // the hkeys allocation the tag refers to
     } lat[DCRF_MAXK];
     DevBuf g, part, acc;
@@ -796,12 +876,61 @@ void sort_column(dcrf_ctx *ctx, LPWork &W, const T *y, int L, int col,
     *perm_out = v0;   // an even number of passes leaves the result in vals
 }
 
+// the blur launches of a level over sub-vertex numbers [0, S)
+template <typename T>
+void lp_blur(LPWork::PerLat &P, int D1, int S, hipStream_t s) {
+    LpPair<T> *V0 = P.V[0].as<LpPair<T>>(), *V1 = P.V[1].as<LpPair<T>>(),
+              *V2 = P.V[2].as<LpPair<T>>();
+    const int nl = lp_blur_launches(D1);
+    for (int t = 0; t < nl; ++t) {
+        const LpPair<T> *src = t == 0 ? V0 : ((t & 1) ? V1 : V2);
+        LpPair<T> *dst = (t & 1) ? V2 : V1;
+        LpPair<T> *clr = t == 1 ? V0 : nullptr;
+        if (2 * t + 1 < D1)
+            hipLaunchKernelGGL((k_lp_blur<T, 2>), dim3(ceil_div(S, 256)), dim3(256), 0, s,
+                               S, 2 * t, P.cap_sub, P.nbr_sub.as<int>(), src, dst, clr);
+        else
+            hipLaunchKernelGGL((k_lp_blur<T, 1>), dim3(ceil_div(S, 256)), dim3(256), 0, s,
+                               S, 2 * t, P.cap_sub, P.nbr_sub.as<int>(), src, dst, clr);
+    }
+}
+
 template <typename T>
 void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l, hipStream_t s) {
     Lattice &Lt = ctx->lat[m];
     auto &P = W.lat[m];
     const int N = ctx->N, D1 = Lt.d + 1, M = Lt.M;
     const long long E = (long long)N * D1;
+    if (l < 31 && ((long long)M << l) <= (long long)P.cap_sub) {
+        // dense numbering: every level's numbers are [0, 2^l M), all of them
+        // cleared by the previous level's blur (V0) or rewritten here
+        const int S = int((long long)M << l);
+        if (P.mk_buf != P.mark.p) {   // a new allocation: zeroed by ensure()
+            P.mk = 0;
+            P.mk_buf = P.mark.p;
+        }
+        if (P.mk == INT32_MAX) {
+            DCRF_TRY_HIP(hipMemsetAsync(P.mark.p, 0, (size_t)P.cap_sub * 4, s));
+            P.mk = 0;
+        }
+        const int mk = ++P.mk;
+        if ((N >> l) >= kLpAggPixels)
+            hipLaunchKernelGGL((k_lp_dense_splat<T, true>), dim3(ceil_div(E, kLpSplatThreads)),
+                               dim3(kLpSplatThreads), 0, s, N, l, D1, M, mk,
+                               P.pos_vid.as<int>(), P.pos_w.as<T>(), P.mark.as<int>(),
+                               P.ent_id.as<int>(), P.V[0].as<T>());
+        else
+            hipLaunchKernelGGL((k_lp_dense_splat<T, false>), dim3(ceil_div(E, kLpSplatThreads)),
+                               dim3(kLpSplatThreads), 0, s, N, l, D1, M, mk,
+                               P.pos_vid.as<int>(), P.pos_w.as<T>(), P.mark.as<int>(),
+                               P.ent_id.as<int>(), P.V[0].as<T>());
+        hipLaunchKernelGGL(k_lp_dense_nbrs, dim3(ceil_div(S, 256)), dim3(256), 0, s, S, M,
+                           D1, mk, P.mark.as<int>(), Lt.nbr.as<int>(), P.nbr_sub.as<int>(),
+                           P.cap_sub);
+        lp_blur<T>(P, D1, S, s);
+        DCRF_CHECK_LAUNCH();
+        return;
+    }
     int *flags = ctx->scratch.as<int>();
     // a fresh tag per level (the table starts zeroed: tag 0 is free); after
     // the last tag the table is cleared once and the tags start again. Node
@@ -839,22 +968,7 @@ void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l, hipStream_t s) {
                        0, s, P.cap_sub, N, l, M, D1, ep, P.sub_nv.as<int2>(),
                        Lt.nbr.as<int>(), P.hkeys.as<uint64_t>(), P.slot_vid.as<int>(),
                        P.nbr_sub.as<int>(), P.cap_sub);
-    LpPair<T> *V0 = P.V[0].as<LpPair<T>>(), *V1 = P.V[1].as<LpPair<T>>(),
-              *V2 = P.V[2].as<LpPair<T>>();
-    const int nl = lp_blur_launches(D1);
-    for (int t = 0; t < nl; ++t) {
-        const LpPair<T> *src = t == 0 ? V0 : ((t & 1) ? V1 : V2);
-        LpPair<T> *dst = (t & 1) ? V2 : V1;
-        LpPair<T> *clr = t == 1 ? V0 : nullptr;
-        if (2 * t + 1 < D1)
-            hipLaunchKernelGGL((k_lp_blur<T, 2>), dim3(ceil_div(P.cap_sub, 256)),
-                               dim3(256), 0, s, P.cap_sub, 2 * t, P.cap_sub,
-                               P.nbr_sub.as<int>(), src, dst, clr);
-        else
-            hipLaunchKernelGGL((k_lp_blur<T, 1>), dim3(ceil_div(P.cap_sub, 256)),
-                               dim3(256), 0, s, P.cap_sub, 2 * t, P.cap_sub,
-                               P.nbr_sub.as<int>(), src, dst, clr);
-    }
+    lp_blur<T>(P, D1, P.cap_sub, s);
     DCRF_CHECK_LAUNCH();
 }
 
@@ -889,6 +1003,7 @@ void lp_prepare(dcrf_ctx *ctx, LPWork &W, int L) {
         P.ent_id.ensure(E * 4, s);
         P.sub_nv.ensure(E * sizeof(int2), s);
         P.nbr_sub.ensure(E * D1 * 2 * 4, s);
+        P.mark.ensure(E * 4, s);
         for (int b = 0; b < 3; ++b) P.V[b].ensure(E * 2 * sizeof(T), s);
         P.pos_vid.ensure(E * 4, s);
         P.pos_w.ensure(E * sizeof(T), s);
@@ -1121,7 +1236,7 @@ void lp_release(dcrf_ctx *ctx) {
     for (auto &P : W->lat)
         for (DevBuf *b : {&P.hkeys, &P.slot_vid, &P.ent_slot, &P.ent_id,
                           &P.sub_nv, &P.nbr_sub, &P.V[0], &P.V[1], &P.V[2],
-                          &P.pos_vid, &P.pos_w})
+                          &P.mark, &P.pos_vid, &P.pos_w})
             b->release();
     delete W;
     ctx->lp = nullptr;

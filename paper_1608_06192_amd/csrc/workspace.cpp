@@ -191,6 +191,7 @@ size_t workspace_bound(int B, const int *H, const int *W, int L,
             s.add(E * 4);
             s.add(E * 8);
             s.add(E * D1 * 8);
+            s.add(E * 4);                              // dense levels' marks
             for (int i = 0; i < 3; ++i) s.add(E * 2 * e);
             s.add(E * 4);
             s.add(E * e);
