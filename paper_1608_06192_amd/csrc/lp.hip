@@ -208,7 +208,8 @@ __global__ void k_lp_insert(int N, int l, int D1, int M, unsigned ep,
                             uint64_t *__restrict__ hkeys,
                             int *__restrict__ ent_slot, int *__restrict__ flags,
                             int *__restrict__ slot_vid,
-                            int2 *__restrict__ sub_nv, int *__restrict__ nbr_sub) {
+                            int2 *__restrict__ sub_nv, int *__restrict__ nbr_sub,
+                            int ld_nb) {
     const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;   // N D1 < 2^31
     const bool in = e < N * D1;
     int slot = -1;
@@ -261,7 +262,7 @@ __global__ void k_lp_insert(int N, int l, int D1, int M, unsigned ep,
         ent_slot[e] = slot;
         sub_nv[e] = claimed ? nv : make_int2(-1, -1);
         // minus links start absent; the neighbour pass sets those present
-        for (int j = 0; j < D1; ++j) nbr_sub[(size_t)(2 * j + 1) * N * D1 + e] = -1;
+        for (int j = 0; j < D1; ++j) nbr_sub[(size_t)(2 * j + 1) * ld_nb + e] = -1;
     }
 }
 
@@ -403,7 +404,7 @@ k_lp_neighbours(int S, int N, int l, int M, int D1, unsigned ep,
 }
 
 // Dense numbering for the first levels, where a level's nodes times the
-// lattice's vertices fit the sub-vertex arrays (2^l M <= N (d + 1)): the
+// lattice's vertices fit the dense capacity (2^l M <= lp_dense_cap): the
 // sub-vertex (node n, global vertex v) is number n M + v, so no hash is
 // built. mark[n M + v] = the level's mark when some entry of node n has
 // vertex v; the other numbers are no sub-vertex, hold zeros and have no
@@ -826,7 +827,9 @@ struct LPWork {
         DevBuf hkeys, slot_vid, ent_slot, ent_id, sub_nv, nbr_sub, V[3], mark;
         DevBuf pos_vid, pos_w;   // the label's vertex ids and weights by position
         size_t cap = 0;
-        int cap_sub = 0;
+        int cap_sub = 0;           // sub-vertex numbers of a hashed level: N (d + 1)
+        int cap_dense = 0;         // numbers available to a dense level
+        int ld_nb = 0;             // row stride of nbr_sub and of the V buffers' numbers
         unsigned tag = 0;          // the last level's tag in hkeys (0: none yet)
         int mk = 0;                // the last dense level's mark (0: none yet)
         const void *mk_buf = nullptr;    // the mark allocation mk refers to
@@ -888,10 +891,10 @@ void lp_blur(LPWork::PerLat &P, int D1, int S, hipStream_t s) {
         LpPair<T> *clr = t == 1 ? V0 : nullptr;
         if (2 * t + 1 < D1)
             hipLaunchKernelGGL((k_lp_blur<T, 2>), dim3(ceil_div(S, 256)), dim3(256), 0, s,
-                               S, 2 * t, P.cap_sub, P.nbr_sub.as<int>(), src, dst, clr);
+                               S, 2 * t, P.ld_nb, P.nbr_sub.as<int>(), src, dst, clr);
         else
             hipLaunchKernelGGL((k_lp_blur<T, 1>), dim3(ceil_div(S, 256)), dim3(256), 0, s,
-                               S, 2 * t, P.cap_sub, P.nbr_sub.as<int>(), src, dst, clr);
+                               S, 2 * t, P.ld_nb, P.nbr_sub.as<int>(), src, dst, clr);
     }
 }
 
@@ -901,7 +904,7 @@ void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l, hipStream_t s) {
     auto &P = W.lat[m];
     const int N = ctx->N, D1 = Lt.d + 1, M = Lt.M;
     const long long E = (long long)N * D1;
-    if (l < 31 && ((long long)M << l) <= (long long)P.cap_sub) {
+    if (l < 31 && ((long long)M << l) <= (long long)P.cap_dense) {
         // dense numbering: every level's numbers are [0, 2^l M), all of them
         // cleared by the previous level's blur (V0) or rewritten here
         const int S = int((long long)M << l);
@@ -910,7 +913,7 @@ void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l, hipStream_t s) {
             P.mk_buf = P.mark.p;
         }
         if (P.mk == INT32_MAX) {
-            DCRF_TRY_HIP(hipMemsetAsync(P.mark.p, 0, (size_t)P.cap_sub * 4, s));
+            DCRF_TRY_HIP(hipMemsetAsync(P.mark.p, 0, (size_t)P.cap_dense * 4, s));
             P.mk = 0;
         }
         const int mk = ++P.mk;
@@ -926,7 +929,7 @@ void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l, hipStream_t s) {
                                P.ent_id.as<int>(), P.V[0].as<T>());
         hipLaunchKernelGGL(k_lp_dense_nbrs, dim3(ceil_div(S, 256)), dim3(256), 0, s, S, M,
                            D1, mk, P.mark.as<int>(), Lt.nbr.as<int>(), P.nbr_sub.as<int>(),
-                           P.cap_sub);
+                           P.ld_nb);
         lp_blur<T>(P, D1, S, s);
         DCRF_CHECK_LAUNCH();
         return;
@@ -953,7 +956,7 @@ void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l, hipStream_t s) {
     hipLaunchKernelGGL(k_lp_insert, dim3(ceil_div(E, 256)), dim3(256), 0, s, N, l,
                        D1, M, ep, P.pos_vid.as<int>(), P.hkeys.as<uint64_t>(),
                        P.ent_slot.as<int>(), flags, P.slot_vid.as<int>(),
-                       P.sub_nv.as<int2>(), P.nbr_sub.as<int>());
+                       P.sub_nv.as<int2>(), P.nbr_sub.as<int>(), P.ld_nb);
     if ((N >> l) >= kLpAggPixels)
         hipLaunchKernelGGL((k_lp_splat<T, true>), dim3(ceil_div(E, kLpSplatThreads)),
                            dim3(kLpSplatThreads), 0, s, N, l, D1,
@@ -967,7 +970,7 @@ void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l, hipStream_t s) {
     hipLaunchKernelGGL(k_lp_neighbours, dim3(ceil_div(P.cap_sub, 256)), dim3(256),
                        0, s, P.cap_sub, N, l, M, D1, ep, P.sub_nv.as<int2>(),
                        Lt.nbr.as<int>(), P.hkeys.as<uint64_t>(), P.slot_vid.as<int>(),
-                       P.nbr_sub.as<int>(), P.cap_sub);
+                       P.nbr_sub.as<int>(), P.ld_nb);
     lp_blur<T>(P, D1, P.cap_sub, s);
     DCRF_CHECK_LAUNCH();
 }
@@ -997,14 +1000,20 @@ void lp_prepare(dcrf_ctx *ctx, LPWork &W, int L) {
         const size_t cap = 2 * E;
         P.cap = cap;
         P.cap_sub = int(E);
+        // the dense levels may number up to kLpDenseFactor N (d + 1) (node,
+        // vertex) pairs, the hashed ones N (d + 1)
+        const size_t dense = lp_dense_cap(E);
+        P.cap_dense = int(dense);
+        P.ld_nb = int(std::max(E, dense));
+        const size_t ld = (size_t)P.ld_nb;
         P.hkeys.ensure(cap * 8, s);
         P.slot_vid.ensure(cap * 4, s);
         P.ent_slot.ensure(E * 4, s);
         P.ent_id.ensure(E * 4, s);
         P.sub_nv.ensure(E * sizeof(int2), s);
-        P.nbr_sub.ensure(E * D1 * 2 * 4, s);
-        P.mark.ensure(E * 4, s);
-        for (int b = 0; b < 3; ++b) P.V[b].ensure(E * 2 * sizeof(T), s);
+        P.nbr_sub.ensure(ld * D1 * 2 * 4, s);
+        P.mark.ensure(dense * 4, s);
+        for (int b = 0; b < 3; ++b) P.V[b].ensure(ld * 2 * sizeof(T), s);
         P.pos_vid.ensure(E * 4, s);
         P.pos_w.ensure(E * sizeof(T), s);
     }

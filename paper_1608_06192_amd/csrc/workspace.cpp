@@ -190,9 +190,10 @@ size_t workspace_bound(int B, const int *H, const int *W, int L,
             s.add(E * 4);
             s.add(E * 4);
             s.add(E * 8);
-            s.add(E * D1 * 8);
-            s.add(E * 4);                              // dense levels' marks
-            for (int i = 0; i < 3; ++i) s.add(E * 2 * e);
+            const size_t dense = lp_dense_cap(E), ld = std::max(E, dense);
+            s.add(ld * D1 * 8);
+            s.add(dense * 4);                          // dense levels' marks
+            for (int i = 0; i < 3; ++i) s.add(ld * 2 * e);
             s.add(E * 4);
             s.add(E * e);
         }
