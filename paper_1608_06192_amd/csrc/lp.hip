@@ -461,6 +461,57 @@ k_lp_dense_splat(int N, int l, int D1, int M, int mk, const int *__restrict__ po
     }
 }
 
+// The same splat gathered by vertex (the lattice's inverse index): wave w of
+// a block takes global vertex v, adds the weights of v's entries into LDS
+// bins (node, side) of the level, and stores each non-zero bin at its dense
+// number with a plain store (one wave owns every number n M + v), marking
+// it. Levels with more than kLpVertexBins / 2 nodes use k_lp_dense_splat.
+constexpr int kLpVertexBins = 512;
+
+__device__ __forceinline__ int dnc_node_side(int p, int l, int N) {
+    long long node;
+    int side;
+    return dnc_node(p, l, N, node, side) ? int(node) * 2 + side : -1;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_lp_vertex_splat(int N, int l, int M, int mk, const int *__restrict__ csr_off,
+                  const int *__restrict__ ent_pix, const T *__restrict__ ent_w,
+                  const int *__restrict__ rank, int *__restrict__ mark,
+                  T *__restrict__ V0) {
+    __shared__ T bins[4][kLpVertexBins];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int v = xcd_block(blockIdx.x, gridDim.x) * 4 + wv;
+    const int nb = 2 << l;   // bins of the level: 2^l nodes, two sides
+    T *b = bins[wv];
+    for (int i = lane; i < nb; i += 64) b[i] = T(0);
+    __syncthreads();
+    if (v < M) {
+        const int e1 = csr_off[v + 1];
+        for (int j = csr_off[v] + lane; j < e1; j += 64) {
+            const int ns = dnc_node_side(rank[ent_pix[j]], l, N);
+            if (ns >= 0) atomicAdd(&b[ns], ent_w[j]);
+        }
+    }
+    __syncthreads();
+    if (v < M)
+        for (int i = lane; i < nb; i += 64) {
+            const T x = b[i];
+            if (x != T(0)) {
+                const int id = (i >> 1) * M + v;
+                V0[(size_t)id * 2 + (i & 1)] = x;
+                mark[id] = mk;
+            }
+        }
+}
+
+// rank[perm[p]] = p: the sorted position of every pixel
+__global__ void k_lp_rank(int N, const int *__restrict__ perm, int *__restrict__ rank) {
+    const int p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (p < N) rank[perm[p]] = p;
+}
+
 __global__ void __launch_bounds__(256)
 k_lp_dense_nbrs(int S, int M, int D1, int mk, const int *__restrict__ mark,
                 const int *__restrict__ nbr_global, int *__restrict__ nbr_sub,
@@ -533,10 +584,12 @@ inline int lp_blur_launches(int D1) { return (D1 + 1) / 2; }
 template <typename T>
 struct LPLat {
     const T *pos_w;
-    const int *ent_id;
+    const int *ent_id;   // the entries' sub-vertex numbers (hashed levels)
     const T *Vf;
     int D1;
     T wg;
+    const int *pos_vid;  // dense levels: entry (p, k) is number node M + pos_vid
+    int M, dense;
 };
 
 template <typename T>
@@ -561,7 +614,13 @@ __global__ void k_lp_slice(int N, int l, LPLats<T> lats, T *__restrict__ acc) {
         const LPLat<T> &X = lats.l[m];
         T s = T(0);
         for (int k = 0; k < X.D1; ++k) {
-            const int id = X.ent_id[(size_t)p * X.D1 + k];
+            int id;
+            if (X.dense) {
+                const int v = X.pos_vid[(size_t)p * X.D1 + k];
+                id = v >= 0 ? int(node) * X.M + v : -1;
+            } else {
+                id = X.ent_id[(size_t)p * X.D1 + k];
+            }
             if (id >= 0)
                 s += X.pos_w[(size_t)p * X.D1 + k] * X.Vf[(size_t)id * 2 + ch];
         }
@@ -836,12 +895,18 @@ struct LPWork {
         const void *tag_buf = nullptr;   // the hkeys allocation the tag refers to
     } lat[DCRF_MAXK];
     DevBuf g, part, acc;
+    DevBuf rank;             // the sorted position of every pixel (dense levels)
     DevBuf col, tree_lab;    // a subtree's column y(T) and the subtrees' label lists
     // the second and later lattices of a level run on a stream of their own
     // (default priority), joined to the context's stream by two events
     hipStream_t side = nullptr;
     hipEvent_t ev_start = nullptr, ev_done = nullptr;
 };
+
+// level l of lattice m (M vertices) numbers its sub-vertices densely
+inline bool lp_dense_level(const LPWork::PerLat &P, int M, int l) {
+    return l < 31 && ((long long)M << l) <= (long long)P.cap_dense;
+}
 
 LPWork &lp_work(dcrf_ctx *ctx) {
     if (!ctx->lp) ctx->lp = new LPWork();
@@ -904,7 +969,7 @@ void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l, hipStream_t s) {
     auto &P = W.lat[m];
     const int N = ctx->N, D1 = Lt.d + 1, M = Lt.M;
     const long long E = (long long)N * D1;
-    if (l < 31 && ((long long)M << l) <= (long long)P.cap_dense) {
+    if (lp_dense_level(P, M, l)) {
         // dense numbering: every level's numbers are [0, 2^l M), all of them
         // cleared by the previous level's blur (V0) or rewritten here
         const int S = int((long long)M << l);
@@ -917,7 +982,12 @@ void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l, hipStream_t s) {
             P.mk = 0;
         }
         const int mk = ++P.mk;
-        if ((N >> l) >= kLpAggPixels)
+        if ((2 << l) <= kLpVertexBins)
+            hipLaunchKernelGGL((k_lp_vertex_splat<T>), dim3(ceil_div(M, 4)), dim3(256), 0, s,
+                               N, l, M, mk, Lt.csr_off.as<int>(), Lt.ent_pix.as<int>(),
+                               Lt.ent_w.as<T>(), W.rank.as<int>(), P.mark.as<int>(),
+                               P.V[0].as<T>());
+        else if ((N >> l) >= kLpAggPixels)
             hipLaunchKernelGGL((k_lp_dense_splat<T, true>), dim3(ceil_div(E, kLpSplatThreads)),
                                dim3(kLpSplatThreads), 0, s, N, l, D1, M, mk,
                                P.pos_vid.as<int>(), P.pos_w.as<T>(), P.mark.as<int>(),
@@ -982,6 +1052,7 @@ void lp_prepare(dcrf_ctx *ctx, LPWork &W, int L) {
     W.g.ensure((size_t)N * L * sizeof(T), s);
     W.part.ensure(1024 * 8, s);
     W.acc.ensure((size_t)N * sizeof(T), s);   // zero between columns
+    W.rank.ensure((size_t)N * 4, s);
     if (ctx->mode == DCRF_FILTER_EXACT) return;
     if (!W.side) {
         DCRF_TRY_HIP(hipStreamCreateWithFlags(&W.side, hipStreamNonBlocking));
@@ -1035,6 +1106,8 @@ int *column_pair_sums(dcrf_ctx *ctx, LPWork &W, const T *y, int ld, int col, int
         DCRF_CHECK_LAUNCH();
         return perm;
     }
+    hipLaunchKernelGGL(k_lp_rank, dim3(ceil_div(N, 256)), dim3(256), 0, s, N, perm,
+                       W.rank.as<int>());
     for (int m = 0; m < ctx->nk; ++m) {
         Lattice &Lt = ctx->lat[m];
         const int D1 = Lt.d + 1;
@@ -1068,7 +1141,8 @@ int *column_pair_sums(dcrf_ctx *ctx, LPWork &W, const T *y, int ld, int col, int
             Lattice &Lt = ctx->lat[m];
             lats.l[m] = LPLat<T>{W.lat[m].pos_w.as<T>(), W.lat[m].ent_id.as<int>(),
                                  W.lat[m].V[final_buffer_after(lp_blur_launches(Lt.d + 1))].as<T>(), Lt.d + 1,
-                                 T(ctx->kern[m].weight * Lt.gamma)};
+                                 T(ctx->kern[m].weight * Lt.gamma), W.lat[m].pos_vid.as<int>(),
+                                 Lt.M, lp_dense_level(W.lat[m], Lt.M, l) ? 1 : 0};
         }
         hipLaunchKernelGGL((k_lp_slice<T>), dim3(ceil_div(N, 256)), dim3(256), 0, s, N, l,
                            lats, W.acc.as<T>());
@@ -1240,7 +1314,7 @@ void lp_release(dcrf_ctx *ctx) {
         (void)hipEventDestroy(W->ev_done);
     }
     for (DevBuf *b : {&W->keys, &W->keys2, &W->vals, &W->vals2, &W->hist, &W->g,
-                      &W->part, &W->acc, &W->col, &W->tree_lab})
+                      &W->part, &W->acc, &W->rank, &W->col, &W->tree_lab})
         b->release();
     for (auto &P : W->lat)
         for (DevBuf *b : {&P.hkeys, &P.slot_vid, &P.ent_slot, &P.ent_id,

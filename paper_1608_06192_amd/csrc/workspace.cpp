@@ -181,6 +181,7 @@ size_t workspace_bound(int B, const int *H, const int *W, int L,
         s.add(NL * e);
         s.add(1024 * 8);
         s.add(N * e);
+        s.add(N * 4);                                  // sorted position of every pixel
         s.add(N * e);                                  // a subtree's column y(T)
         s.add(size_t(kMaxTreeNodes) * size_t(L) * 4);  // the subtrees' label lists
         for (int m = 0; m < nk; ++m) {
