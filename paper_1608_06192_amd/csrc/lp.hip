@@ -506,6 +506,122 @@ k_lp_vertex_splat(int N, int l, int M, int mk, const int *__restrict__ csr_off,
         }
 }
 
+// Node-local levels, where whole nodes fit a block: block b takes nodes
+// [b k, b k + k), whose entries are one contiguous range of at most
+// kLpNodeCap, and sorts their keys (node, vertex) in LDS (bitonic). Each run
+// of equal keys is one sub-vertex, numbered by the entry number of its first
+// element in sorted order; that element's thread sums the run's weights per
+// side (a plain store: the block owns its numbers), and finds the plus and
+// minus neighbours (node, nbr_j(v)) by binary search in the sorted keys.
+// Every number of the block that is no sub-vertex gets no links. One launch
+// replaces the hash insert, the splat and the neighbour lookups.
+constexpr int kLpNodeCap = 2048;
+constexpr int kLpNodeThreads = 512;
+
+__device__ __forceinline__ int lds_lower_bound(const unsigned long long *a, int n,
+                                               unsigned long long x) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kLpNodeThreads)
+k_lp_node_level(int N, int l, int D1, int M, int k, const int *__restrict__ pos_vid,
+                const T *__restrict__ pos_w, const int *__restrict__ nbr_global,
+                int *__restrict__ ent_id, T *__restrict__ V0, int *__restrict__ nbr_sub,
+                int ld_nb) {
+    __shared__ unsigned long long skey[kLpNodeCap];
+    __shared__ int sidx[kLpNodeCap];
+    // keys: valid (node, vertex) pairs < 2^43; an entry that is no term
+    // (a node with an empty half, a missing vertex) kNone; the padding up to
+    // a power of two kPad, so that the block's ne entries fill the sorted
+    // positions [0, ne) and every number written stays in the block's range
+    constexpr unsigned long long kPad = ~0ull, kNone = kPad - 1;
+    const long long n0 = (long long)blockIdx.x * k;
+    const long long n1 = min(n0 + k, 1ll << l);
+    const int lo = int((n0 * N) >> l), hi = int((n1 * N) >> l);
+    const int ne = (hi - lo) * D1;   // <= kLpNodeCap (k is chosen so)
+    int P2 = 1;
+    while (P2 < ne) P2 <<= 1;
+    const long long e0 = (long long)lo * D1;
+    for (int i = threadIdx.x; i < P2; i += kLpNodeThreads) {
+        unsigned long long key = i < ne ? kNone : kPad;
+        if (i < ne) {
+            const int p = lo + i / D1;
+            long long node;
+            int side;
+            const int v = pos_vid[e0 + i];
+            if (dnc_node(p, l, N, node, side) && v >= 0)
+                key = ((unsigned long long)(node - n0) << 32) | (unsigned)v;
+        }
+        skey[i] = key;
+        sidx[i] = i;
+    }
+    __syncthreads();
+    for (int size = 2; size <= P2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < (P2 >> 1); t += kLpNodeThreads) {
+                const int i = ((t & ~(stride - 1)) << 1) | (t & (stride - 1));
+                const int j = i + stride;
+                const bool up = (i & size) == 0;
+                const unsigned long long a = skey[i], b = skey[j];
+                if ((a > b) == up && a != b) {
+                    skey[i] = b;
+                    skey[j] = a;
+                    const int x = sidx[i];
+                    sidx[i] = sidx[j];
+                    sidx[j] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const int nvalid = lds_lower_bound(skey, P2, kNone);
+    for (int r = threadIdx.x; r < ne; r += kLpNodeThreads) {
+        const unsigned long long key = skey[r];
+        const long long e = e0 + sidx[r];
+        const int r0 = r < nvalid ? lds_lower_bound(skey, nvalid, key) : -1;
+        ent_id[e] = r0 >= 0 ? int(e0 + sidx[r0]) : -1;
+        if (r0 != r) {   // no sub-vertex is numbered e
+            for (int q = 0; q < 2 * D1; ++q) nbr_sub[(size_t)q * ld_nb + e] = -1;
+            continue;
+        }
+        T s0 = T(0), s1 = T(0);
+        for (int rr = r; rr < nvalid && skey[rr] == key; ++rr) {
+            const int ii = sidx[rr];
+            long long node;
+            int side;
+            dnc_node(lo + ii / D1, l, N, node, side);
+            const T w = pos_w[e0 + ii];
+            if (side)
+                s1 += w;
+            else
+                s0 += w;
+        }
+        V0[e * 2] = s0;
+        V0[e * 2 + 1] = s1;
+        const int v = int(key & 0xffffffffull);
+        const unsigned long long nb = key & ~0xffffffffull;
+        for (int q = 0; q < 2 * D1; ++q) {
+            const int vn = nbr_global[((size_t)(q >> 1) * M + v) * 2 + (q & 1)];
+            int nid = -1;
+            if (vn >= 0) {
+                const unsigned long long kk = nb | (unsigned)vn;
+                const int rn = lds_lower_bound(skey, nvalid, kk);
+                if (rn < nvalid && skey[rn] == kk) nid = int(e0 + sidx[rn]);
+            }
+            nbr_sub[(size_t)q * ld_nb + e] = nid;
+        }
+    }
+}
+
 // rank[perm[p]] = p: the sorted position of every pixel
 __global__ void k_lp_rank(int N, const int *__restrict__ perm, int *__restrict__ rank) {
     const int p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -1001,6 +1117,18 @@ void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l, hipStream_t s) {
                            D1, mk, P.mark.as<int>(), Lt.nbr.as<int>(), P.nbr_sub.as<int>(),
                            P.ld_nb);
         lp_blur<T>(P, D1, S, s);
+        DCRF_CHECK_LAUNCH();
+        return;
+    }
+    const long long smax = ((long long)N + (1ll << l) - 1) >> l;   // the largest node
+    if (l < 31 && smax * D1 <= kLpNodeCap) {
+        const int k = int(std::max(1ll, kLpNodeCap / (smax * D1)));
+        const long long nodes = 1ll << l;
+        hipLaunchKernelGGL((k_lp_node_level<T>), dim3(unsigned((nodes + k - 1) / k)),
+                           dim3(kLpNodeThreads), 0, s, N, l, D1, M, k, P.pos_vid.as<int>(),
+                           P.pos_w.as<T>(), Lt.nbr.as<int>(), P.ent_id.as<int>(),
+                           P.V[0].as<T>(), P.nbr_sub.as<int>(), P.ld_nb);
+        lp_blur<T>(P, D1, P.cap_sub, s);
         DCRF_CHECK_LAUNCH();
         return;
     }
