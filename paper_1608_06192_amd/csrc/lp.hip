@@ -507,16 +507,15 @@ k_lp_vertex_splat(int N, int l, int M, int mk, const int *__restrict__ csr_off,
 }
 
 // Node-local levels, where whole nodes fit a block: block b takes nodes
-// [b k, b k + k), whose entries are one contiguous range of at most
-// kLpNodeCap, and sorts their keys (node, vertex) in LDS (bitonic). Each run
+// [b k, b k + k), whose entries are one contiguous range of at most CAP
+// (2048, or 4096 where a node needs more), and sorts their keys (node, vertex) in LDS (bitonic). Each run
 // of equal keys is one sub-vertex, numbered by the entry number of its first
 // element in sorted order; that element's thread sums the run's weights per
 // side (a plain store: the block owns its numbers), and finds the plus and
 // minus neighbours (node, nbr_j(v)) by binary search in the sorted keys.
 // Every number of the block that is no sub-vertex gets no links. One launch
 // replaces the hash insert, the splat and the neighbour lookups.
-constexpr int kLpNodeCap = 2048;
-constexpr int kLpNodeThreads = 512;
+constexpr int kLpNodeCap = 4096;   // the larger block; 2048 where nodes fit it
 
 __device__ __forceinline__ int lds_lower_bound(const unsigned long long *a, int n,
                                                unsigned long long x) {
@@ -531,14 +530,15 @@ __device__ __forceinline__ int lds_lower_bound(const unsigned long long *a, int 
     return lo;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kLpNodeThreads)
+template <typename T, int CAP>
+__global__ void __launch_bounds__(CAP / 4)
 k_lp_node_level(int N, int l, int D1, int M, int k, const int *__restrict__ pos_vid,
                 const T *__restrict__ pos_w, const int *__restrict__ nbr_global,
                 int *__restrict__ ent_id, T *__restrict__ V0, int *__restrict__ nbr_sub,
                 int ld_nb) {
-    __shared__ unsigned long long skey[kLpNodeCap];
-    __shared__ int sidx[kLpNodeCap];
+    constexpr int kLpNodeThreads = CAP / 4;
+    __shared__ unsigned long long skey[CAP];
+    __shared__ int sidx[CAP];
     // keys: valid (node, vertex) pairs < 2^43; an entry that is no term
     // (a node with an empty half, a missing vertex) kNone; the padding up to
     // a power of two kPad, so that the block's ne entries fill the sorted
@@ -547,7 +547,7 @@ k_lp_node_level(int N, int l, int D1, int M, int k, const int *__restrict__ pos_
     const long long n0 = (long long)blockIdx.x * k;
     const long long n1 = min(n0 + k, 1ll << l);
     const int lo = int((n0 * N) >> l), hi = int((n1 * N) >> l);
-    const int ne = (hi - lo) * D1;   // <= kLpNodeCap (k is chosen so)
+    const int ne = (hi - lo) * D1;   // <= CAP (k is chosen so)
     int P2 = 1;
     while (P2 < ne) P2 <<= 1;
     const long long e0 = (long long)lo * D1;
@@ -1122,12 +1122,20 @@ void lp_level(dcrf_ctx *ctx, LPWork &W, int m, int l, hipStream_t s) {
     }
     const long long smax = ((long long)N + (1ll << l) - 1) >> l;   // the largest node
     if (l < 31 && smax * D1 <= kLpNodeCap) {
-        const int k = int(std::max(1ll, kLpNodeCap / (smax * D1)));
+        const int cap = smax * D1 <= 2048 ? 2048 : 4096;
+        const int k = int(std::max(1ll, cap / (smax * D1)));
         const long long nodes = 1ll << l;
-        hipLaunchKernelGGL((k_lp_node_level<T>), dim3(unsigned((nodes + k - 1) / k)),
-                           dim3(kLpNodeThreads), 0, s, N, l, D1, M, k, P.pos_vid.as<int>(),
-                           P.pos_w.as<T>(), Lt.nbr.as<int>(), P.ent_id.as<int>(),
-                           P.V[0].as<T>(), P.nbr_sub.as<int>(), P.ld_nb);
+        const dim3 grid(unsigned((nodes + k - 1) / k)), block(cap / 4);
+        if (cap == 2048)
+            hipLaunchKernelGGL((k_lp_node_level<T, 2048>), grid, block, 0, s, N, l, D1, M, k,
+                               P.pos_vid.as<int>(), P.pos_w.as<T>(), Lt.nbr.as<int>(),
+                               P.ent_id.as<int>(), P.V[0].as<T>(), P.nbr_sub.as<int>(),
+                               P.ld_nb);
+        else
+            hipLaunchKernelGGL((k_lp_node_level<T, 4096>), grid, block, 0, s, N, l, D1, M, k,
+                               P.pos_vid.as<int>(), P.pos_w.as<T>(), Lt.nbr.as<int>(),
+                               P.ent_id.as<int>(), P.V[0].as<T>(), P.nbr_sub.as<int>(),
+                               P.ld_nb);
         lp_blur<T>(P, D1, P.cap_sub, s);
         DCRF_CHECK_LAUNCH();
         return;
