@@ -826,6 +826,17 @@ def main():
                     peak=HBM_PEAK_GBPS, unit="GB/s", frac=achieved / HBM_PEAK_GBPS,
                     traffic=traffic_bytes(dom), bytes_per_launch=dom_bytes,
                     avg_launch_us=dom_ms * 1e3)
+    # the same for every kernel of the step (the LMO and the slice take
+    # nearly the same time, so which one is dominant varies between runs)
+    step_rooflines = []
+    for k in sorted((k for k in per_iter if k in step_classes),
+                    key=lambda k: -per_iter[k][0] * per_iter[k][1]):
+        b = class_bytes(k, N, L, 4, lat)
+        a = b / per_iter[k][0] / 1e6
+        step_rooflines.append(dict(kernel=k, avg_launch_us=per_iter[k][0] * 1e3,
+                                   launches_per_step=per_iter[k][1] / prof_iters,
+                                   bytes_per_launch=b, achieved=a,
+                                   frac=a / HBM_PEAK_GBPS, traffic=traffic_bytes(k)))
 
     res = dict(metric=METRIC, value=args.steps / dt, unit="FW iters/s",
                n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -841,7 +852,7 @@ def main():
                                     "the timed QP solution", us_per_step=dn_ms * 1e3,
                            steps=dn_steps),
                per_kernel_us={k: v[0] * 1e3 for k, v in per_iter.items()},
-               lp=lp, roofline=roofline, **ext)
+               lp=lp, roofline=roofline, step_rooflines=step_rooflines, **ext)
     if not args.no_cpu:
         log(f"[bench] CPU baseline: {args.cpu_iters} oracle FW iterations ...")
         res["cpu_baseline"] = cpu_baseline(im, kernels, mu_np, args.cpu_iters)
