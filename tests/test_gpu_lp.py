@@ -159,6 +159,69 @@ def test_lp_subgradient_fp32_500x375_sampled_entries():
         assert (rel <= 1e-5).all()
 
 
+def test_lp_subgradient_fp64_500x375_every_level_kind():
+    # 500x375, L = 21, FP64: at this size the divide and conquer builds its
+    # sub-lattices all three ways (dense numbering on the first levels, the
+    # node-local sort with blocks of 2048 and of 4096 entries on the deep
+    # ones, the per-node hash on the 2-D lattice's level 7). The oracle
+    # evaluates one label's column at sampled pixels (both ends and the
+    # middle of its order included); both sides sort the same FP64 values.
+    im = synth.make("voronoi_500x375_L21")
+    N = im.N
+    y = synth.random_simplex_points(N, im.L, seed=13, sparsity=0.6)
+    ctx = ctx_for(im, torch.float64)
+    g, _ = ctx.lp_subgradient(T(im.unary, torch.float64), T(y, torch.float64))
+    g = g.cpu().numpy()
+    model = O.Model(im.H, im.W, im.rgb, KERNELS)
+    rng = np.random.default_rng(9)
+    i = 7
+    order = O.sorted_order(y[:, i])
+    ends = order[[0, 1, N // 2 - 1, N // 2, N - 2, N - 1]]
+    at = np.unique(np.concatenate([rng.choice(N, 160, replace=False), ends]))
+    U, Lo = O.lp_pair_sums_dnc(model, order, "lattice", at=at)
+    go = im.unary[at, i] + U[at] - Lo[at]
+    mag = np.abs(im.unary[at, i]) + U[at] + Lo[at]
+    rel = np.abs(g[at, i] - go) / mag
+    print(f"[lp 500x375 fp64] label {i}: max rel err {rel.max():.3g}", flush=True)
+    assert (rel <= 1e-10).all()
+
+
+@pytest.mark.parametrize("theta", [400.0, 40.0])
+def test_lp_subgradient_few_vertices(theta):
+    # one colour and wide kernels: a handful of vertices, so the dense
+    # numbering (node times vertex count) reaches the deepest levels, past
+    # the 256 nodes of the by-vertex splat (there each entry adds its weight
+    # itself); 24x32, L = 3, FP64 against the oracle's whole subgradient
+    from paper_1608_06192_amd import dcrf
+    H, W, L = 24, 32, 3
+    rgb = np.tile(np.asarray((90.0, 140.0, 200.0), np.float32), (H * W, 1))
+    kernels = [dict(use_rgb=1, theta_pos=theta, theta_rgb=13.0, weight=10.0),
+               dict(use_rgb=0, theta_pos=theta / 2, theta_rgb=0.0, weight=3.0)]
+    rng = np.random.default_rng(int(theta))
+    phi = rng.uniform(0.0, 4.0, size=(H * W, L))
+    y = synth.random_simplex_points(H * W, L, seed=4, sparsity=0.3)
+    print(f"[case] LP one colour {H}x{W} theta {theta}", flush=True)
+    ctx = dcrf.Context(0)
+    ctx.set_image(H, W, torch.from_numpy(rgb).to(dev()), kernels, dtype=torch.float64)
+    g, S = ctx.lp_subgradient(T(phi, torch.float64), T(y, torch.float64))
+    model = O.Model(H, W, rgb, kernels)
+    mag = np.abs(phi).copy()
+
+    def sums(order):
+        U, Lo = O.lp_pair_sums_dnc(model, order, "lattice")
+        sums.cache.append((U, Lo))
+        return U, Lo
+    sums.cache = []
+    go, So = O.lp_subgradient(phi, y, sums)
+    for i, (U, Lo) in enumerate(sums.cache):
+        mag[:, i] += np.abs(U) + np.abs(Lo)
+    nv = [ctx.lattice_info(m)[1] for m in range(2)]
+    err = np.abs(g.cpu().numpy() - go)
+    print(f"[lp few vertices] vertices {nv}: max rel err {(err / mag).max():.3g}", flush=True)
+    assert (err <= 1e-10 * mag).all()
+    assert abs(S - So) <= 1e-10 * (mag * y).sum()
+
+
 def test_lp_descent_fp32_steps_160x120():
     # Five projected-subgradient steps (Alg. lp_subgrad, beta_t = beta0/(1+t))
     # at 160x120, L = 21, FP32, from a Frank-Wolfe QP solution. The oracle's
