@@ -38,7 +38,8 @@ Beside it the JSON line reports:
 * batch: 16 Voronoi images of sizes U{240..500}^2, L=21, FP32, 10 Frank-
   Wolfe iterations each: the batched forward and forward+backward (one launch
   per stage over the concatenated lattices, autotuned launch shapes) against
-  16 sequential single-image forwards and forward+backwards;
+  16 sequential single-image forwards and forward+backwards; batch.persistent:
+  the same with every iteration of the forward in one cooperative launch;
 * lattice_error: the lattice filter against the exact O(N^2) sum at 320x213
   (ratio of means, cosine and relative 2-norm error of K'Y for a random Y),
   and the same for the separable mode (spatial kernel exact, bilateral on
@@ -505,6 +506,19 @@ def extensions(torch, dcrf, synth, dev, kernels):
     t_bfb = _timed(torch, bfwdbwd, 2)
     t_sf = _timed(torch, seq_fwd, 2)
     t_sfb = _timed(torch, seq_fwdbwd, 1)
+    # the same forward (and forward+backward) with all iterations of the
+    # forward in one persistent cooperative launch (two blur directions per
+    # group, the staged splat, no tiles: the launch shapes it takes)
+    ptune = dict(tune, blur_group=2, tiles=0, splat_stage=1)
+    bctx.set_tune(**dict(ptune, fw_persistent=0))
+    t_sbf = _timed(torch, bfwd, 3)
+    bctx.set_tune(**dict(ptune, fw_persistent=1))
+    t_pbf = _timed(torch, bfwd, 3)
+    t_pbfb = _timed(torch, bfwdbwd, 2)
+    t_p10 = _timed(torch, lambda: bsolve(10), 3)
+    t_p60 = _timed(torch, lambda: bsolve(60), 3)
+    p_it_ms = (t_p60 - t_p10) / 50
+    bctx.set_tune(**dict(tune, fw_persistent=0))
     out["batch"] = dict(workload="16 Voronoi images, H and W ~ U{240..500}, "
                                  "L=21, FP32, 10 FW iterations each",
                         pixels=npx, autotune=tune, lattice_vertices=[M for d, M in blat],
@@ -516,12 +530,20 @@ def extensions(torch, dcrf, synth, dev, kernels):
                         sequential_fwd_bwd_ms=t_sfb,
                         batched_fwd_bwd_over_sequential_forward=t_bfb / t_sf,
                         forward_speedup=t_sf / t_bf,
-                        fwd_bwd_speedup=t_sfb / t_bfb)
+                        fwd_bwd_speedup=t_sfb / t_bfb,
+                        persistent=dict(
+                            launch_shapes=ptune,
+                            per_stage_forward_ms=t_sbf, forward_ms=t_pbf,
+                            fwd_bwd_ms=t_pbfb, fw_iteration_ms=p_it_ms,
+                            fw_iteration_GBps=it_bytes / p_it_ms / 1e6))
     log(f"[bench] batch of 16: steady FW iteration {it_ms * 1e3:.1f} us, "
         f"{it_bytes / 1e6:.1f} MB algorithmic = {it_bytes / it_ms / 1e6:.0f} GB/s")
     log(f"[bench] batch of 16 ({npx} px): batched fwd {t_bf:.2f} ms, fwd+bwd "
         f"{t_bfb:.2f} ms; sequential fwd {t_sf:.2f} ms, fwd+bwd {t_sfb:.2f} ms; "
         f"tune {tune}")
+    log(f"[bench] batch of 16, one persistent launch per forward: fwd {t_pbf:.2f} ms "
+        f"(per-stage {t_sbf:.2f} ms in the same shapes), fwd+bwd {t_pbfb:.2f} ms, "
+        f"steady FW iteration {p_it_ms * 1e3:.1f} us")
     del bctx, sctx, bh
 
     # -- lattice against the exact sum at 320x213 ----------------------------

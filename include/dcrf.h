@@ -114,6 +114,13 @@ typedef struct {
                                      pixel by pixel (runs of lanes with the
                                      same vertex and label summed in the wave
                                      first, one atomic per run) */
+    int fw_persistent;            /* 0 (default): one launch per stage of each
+                                     Frank-Wolfe iteration; 1: every iteration
+                                     of a solve in one cooperative launch with
+                                     grid barriers between the stages (the
+                                     row kernels' lattice path with the staged
+                                     one-hot splat and blur_group 2; other
+                                     settings keep the per-stage launches) */
     double ms;                    /* time of the tuned filter paths, ms       */
 } dcrf_tune;
 
@@ -245,7 +252,8 @@ int dcrf_autotune(dcrf_ctx *ctx, int L, int reps, dcrf_tune *out);
 /* Set the launch shapes directly (the `ms` field is ignored): splat_chunk and
  * dense_chunk in {16, 32, 64, 128, 256}, splat_stage 0 or 1,
  * blur_vectors_per_thread in 1..4, blur_block in {64, 128, 256}, blur_group
- * in 1..3, tiles 0 or 1, fw_splat 0 or 1; DCRF_EINVAL otherwise.
+ * in 1..3, tiles 0 or 1, fw_splat 0 or 1, fw_persistent 0 or 1;
+ * DCRF_EINVAL otherwise.
  * Results are the same for every choice up to floating-point summation
  * order. */
 int dcrf_set_tune(dcrf_ctx *ctx, const dcrf_tune *tune);

@@ -131,7 +131,7 @@ static void release_all(dcrf_ctx *ctx) {
          {&ctx->r, &ctx->scratch, &ctx->tmpA, &ctx->tmpB, &ctx->fw_c,
           &ctx->fw_Py, &ctx->fw_Ps, &ctx->fw_s, &ctx->fw_sprev, &ctx->fw_part,
           &ctx->fw_scal, &ctx->fw_trace, &ctx->fw_mu, &ctx->potts, &ctx->hist,
-          &ctx->errflag, &ctx->seg, &ctx->tiles, &ctx->tile_img_off, &ctx->small,
+          &ctx->errflag, &ctx->fw_bar, &ctx->seg, &ctx->tiles, &ctx->tile_img_off, &ctx->small,
           &ctx->sub_phi, &ctx->sub_y, &ctx->sub_best, &ctx->sep_taps, &ctx->sep_tmp,
           &ctx->sep_acc, &ctx->sep_part, &ctx->pack_a, &ctx->pack_b, &ctx->pack_c})
         b->release();
@@ -288,6 +288,7 @@ int dcrf_autotune(dcrf_ctx *ctx, int L, int reps, dcrf_tune *out) {
             out->blur_group = ctx->blur_group;
             out->tiles = ctx->tile_mode;
             out->fw_splat = ctx->fw_splat;
+            out->fw_persistent = ctx->fw_persistent;
             out->ms = ms;
         }
     });
@@ -310,6 +311,7 @@ int dcrf_set_tune(dcrf_ctx *ctx, const dcrf_tune *t) {
         REQUIRE(t->tiles == 0 || t->tiles == 1, "tiles must be 0 or 1");
         REQUIRE(t->splat_stage == 0 || t->splat_stage == 1, "splat_stage must be 0 or 1");
         REQUIRE(t->fw_splat == 0 || t->fw_splat == 1, "fw_splat must be 0 or 1");
+        REQUIRE(t->fw_persistent == 0 || t->fw_persistent == 1, "fw_persistent must be 0 or 1");
         if (t->splat_chunk != ctx->splat_chunk || t->dense_chunk != ctx->dense_chunk)
             dcrf::rechunk(ctx, t->splat_chunk, t->dense_chunk);
         ctx->splat_lds = t->splat_stage;
@@ -318,6 +320,7 @@ int dcrf_set_tune(dcrf_ctx *ctx, const dcrf_tune *t) {
         ctx->blur_group = t->blur_group;
         ctx->tile_mode = t->tiles;
         ctx->fw_splat = t->fw_splat;
+        ctx->fw_persistent = t->fw_persistent;
         if (t->tiles && ctx->has_image) dcrf::ensure_tiles(ctx);
     });
 }

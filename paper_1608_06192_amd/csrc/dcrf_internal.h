@@ -306,6 +306,8 @@ struct dcrf_ctx {
     int blur_group = 2;      // blur directions applied per launch (1..3)
     int tile_mode = 0;       // splats and slices through the per-tile slots
     int fw_splat = 0;        // Frank-Wolfe: one-hot splat inside the LMO kernel
+    int fw_persistent = 0;   // Frank-Wolfe: every iteration in one cooperative launch
+    dcrf::DevBuf fw_bar;     // its grid barrier (count, generation) and timeout flag
     // 2-D pixel tiles of every image (tiles.hip)
     int ntiles = 0;          // 0 until the tile map is built (only when tiles are asked for)
     dcrf::DevBuf tiles;              // ntiles x int4: first row, row stride, rows, cols
@@ -373,6 +375,8 @@ void filter_apply(dcrf_ctx *ctx, const void *in, void *out, int C,
 void compute_row_sums(dcrf_ctx *ctx);
 // make sure every lattice has vertex buffers for C channels
 void ensure_vertex_buffers(dcrf_ctx *ctx, int C);
+// the grouped blur's path tables for G directions per launch (forward order)
+void blur_group_tables(dcrf_ctx *ctx, int G);
 // splat of one-hot labels (C = L channels), blur; leaves results in the final
 // buffers of each lattice
 void splat_labels(dcrf_ctx *ctx, const int32_t *labels, int L);

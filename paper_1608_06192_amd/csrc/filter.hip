@@ -42,11 +42,6 @@ namespace {
 
 // ------------------------------------------------------------------ splat
 
-// (pixel or label, weight) of one inverse-index entry, one LDS word
-template <typename T> struct alignas(2 * sizeof(T) > 8 ? 16 : 8) PairLds {
-    int i;
-    T w;
-};
 
 // lane (chunk, c): V0[v][c] += sum w * Y[pix][c]; block b of a lattice takes
 // its chunks b q .. b q + q - 1 (q = dense_splat_q: chunks of C lanes)
@@ -115,46 +110,14 @@ k_splat_gather_lds(int C, int q, int U, const T *__restrict__ Y, LatSet<T> ls) {
     if (acc != T(0)) atomic_add(&L.V0[(size_t)cd.x * L.ld + c], acc);
 }
 
-// One-hot input in the layout of the staged dense splat: block b takes q
-// chunks of C = L lanes (chunk, label); the labels of the chunks' pixels and
-// the weights are staged in LDS, then lane (chunk, c) adds up the weights of
-// the entries labelled c, and adds the sum to V0[v][c] if it is not zero.
-// Labels outside [0, L) add nothing.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_splat_labels_lds(int C, int q, int U, const int32_t *__restrict__ labels,
                    LatSet<T> ls) {
     __shared__ PairLds<T> sp[kSplatStage];
     __shared__ int4 scd[256];
-    const long long b0 = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x;
-    int m = 0;
-    while (m + 1 < ls.nk && b0 >= ls.coff[m + 1]) ++m;
-    const LatView<T> &L = ls.l[m];
-    const int ch0 = int((b0 - ls.coff[m]) / 256) * q;
-    const int nq = min(q, L.ndchunks - ch0);
-    const int t = threadIdx.x;
-    if (t < nq) scd[t] = L.dchunks[ch0 + t];
-    const size_t base = (size_t)ch0 * U;   // the block's entries: one contiguous range
-    for (int i = t; i < nq * U; i += 256)
-        sp[i] = PairLds<T>{labels[L.dpix[base + i]], L.dw[base + i]};
-    __syncthreads();
-    const int k = t / C, c = t - (t / C) * C;
-    if (k >= nq) return;
-    const int4 cd = scd[k];
-    const int n = cd.z - cd.y;
-    const PairLds<T> *pk = sp + k * U;
-    T acc0 = T(0), acc1 = T(0), acc2 = T(0), acc3 = T(0);
-    int j = 0;
-    for (; j + 4 <= n; j += 4) {
-        const PairLds<T> e0 = pk[j], e1 = pk[j + 1], e2 = pk[j + 2], e3 = pk[j + 3];
-        acc0 += e0.i == c ? e0.w : T(0);
-        acc1 += e1.i == c ? e1.w : T(0);
-        acc2 += e2.i == c ? e2.w : T(0);
-        acc3 += e3.i == c ? e3.w : T(0);
-    }
-    for (; j < n; ++j) acc0 += pk[j].i == c ? pk[j].w : T(0);
-    const T acc = (acc0 + acc1) + (acc2 + acc3);
-    if (acc != T(0)) atomic_add(&L.V0[(size_t)cd.x * L.ld + c], acc);
+    splat_labels_block<T>(C, q, U, labels, ls,
+                          (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x, sp, scd);
 }
 
 // One-hot input (pixel a is 1 at channel labels[a]): one wave per inverse-
@@ -260,8 +223,6 @@ k_blur_pass(LatSet<T> ls, int pass, int reverse, long long total, int vpt) {
 // group of the last launch that has fewer than G directions tabulates only
 // the staying path for the missing ones, and the launch rescales by 2 per
 // missing direction.
-template <int G> struct Pow3 { static constexpr int v = 3 * Pow3<G - 1>::v; };
-template <> struct Pow3<0> { static constexpr int v = 1; };
 
 __global__ void k_group_table(int M, const int32_t *__restrict__ nbr, int G,
                               int j1, int j2, int j3, int npass,
@@ -291,61 +252,6 @@ __global__ void k_group_table(int M, const int32_t *__restrict__ nbr, int G,
     }
 }
 
-template <typename T, int G>
-__device__ __forceinline__ void blur_group_vector(const LatSet<T> &ls, int grp,
-                                                  long long e) {
-    using V = typename Vec16<T>::type;
-    constexpr int vw = Vec16<T>::n;
-    constexpr int P = Pow3<G>::v;
-    int m = 0;
-    while (m + 1 < ls.nk && e >= ls.off[m + 1] / vw) ++m;
-    const LatView<T> &L = ls.l[m];
-    const unsigned Gv = unsigned(L.ld / vw);
-    const unsigned r = unsigned(e - ls.off[m] / vw);
-    V zero;
-    for (int i = 0; i < vw; ++i) reinterpret_cast<T *>(&zero)[i] = T(0);
-    if (grp >= L.ngrp) {
-        if (grp == 1) reinterpret_cast<V *>(L.V0)[r] = zero;
-        return;
-    }
-    const int v = int(r / Gv);
-    const int g = int(r - unsigned(v) * Gv);
-    const V *src = reinterpret_cast<const V *>((grp == 0) ? L.V0 : ((grp & 1) ? L.V1 : L.V2));
-    V *dst = reinterpret_cast<V *>((grp & 1) ? L.V2 : L.V1);
-    const int32_t *ids = L.gt + ((size_t)grp * L.M + v) * P;
-    int id[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) id[p] = ids[p];
-    T acc[vw];
-#pragma unroll
-    for (int i = 0; i < vw; ++i) acc[i] = T(0);
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        // coefficient: 1/2 per staying step, 1/4 per move (digits of p)
-        T c = T(1);
-        int code = p;
-#pragma unroll
-        for (int k = 0; k < G; ++k) {
-            c *= (code % 3 == 0) ? T(0.5) : T(0.25);
-            code /= 3;
-        }
-        const V x = src[(size_t)(id[p] >= 0 ? id[p] : 0) * Gv + g];
-        if (id[p] < 0) c = T(0);
-#pragma unroll
-        for (int i = 0; i < vw; ++i) acc[i] += c * reinterpret_cast<const T *>(&x)[i];
-    }
-    if (grp == L.ngrp - 1) {
-        const int missing = L.ngrp * G - (L.d + 1);
-        const T sc = T(1 << missing);
-#pragma unroll
-        for (int i = 0; i < vw; ++i) acc[i] *= sc;
-    }
-    V o;
-#pragma unroll
-    for (int i = 0; i < vw; ++i) reinterpret_cast<T *>(&o)[i] = acc[i];
-    dst[r] = o;
-    if (grp == 1) reinterpret_cast<V *>(L.V0)[r] = zero;
-}
 
 template <typename T, int G>
 __global__ void __launch_bounds__(256)
@@ -1145,6 +1051,8 @@ void splat_dense(dcrf_ctx *ctx, const void *in, int C) {
     else
         splat_dense_t<float>(ctx, static_cast<const float *>(in), C);
 }
+
+void blur_group_tables(dcrf_ctx *ctx, int G) { ensure_group_tables(ctx, G, false); }
 
 void splat_labels(dcrf_ctx *ctx, const int32_t *labels, int L) {
     if (ctx->dtype == DCRF_F64)

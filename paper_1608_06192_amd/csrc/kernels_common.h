@@ -667,6 +667,116 @@ __device__ __forceinline__ void slice_tile52_coop(const LatSet<T> &ls, int np, i
     }
 }
 
+// ------------------------------------ label splat and grouped blur bodies
+
+// (pixel or label, weight) of one inverse-index entry, one LDS word
+template <typename T> struct alignas(2 * sizeof(T) > 8 ? 16 : 8) PairLds {
+    int i;
+    T w;
+};
+
+// One-hot input in the layout of the staged dense splat: block b takes q
+// chunks of C = L lanes (chunk, label); the labels of the chunks' pixels and
+// the weights are staged in LDS, then lane (chunk, c) adds up the weights of
+// the entries labelled c, and adds the sum to V0[v][c] if it is not zero.
+// Labels outside [0, L) add nothing.
+// The block of 256 threads that takes lanes [b0, b0 + 256); sp holds
+// kSplatStage pairs, scd 256 chunk descriptors.
+template <typename T>
+__device__ __forceinline__ void splat_labels_block(int C, int q, int U,
+                                                   const int32_t *__restrict__ labels,
+                                                   const LatSet<T> &ls, long long b0,
+                                                   PairLds<T> *sp, int4 *scd) {
+    int m = 0;
+    while (m + 1 < ls.nk && b0 >= ls.coff[m + 1]) ++m;
+    const LatView<T> &L = ls.l[m];
+    const int ch0 = int((b0 - ls.coff[m]) / 256) * q;
+    const int nq = min(q, L.ndchunks - ch0);
+    const int t = threadIdx.x;
+    if (t < nq) scd[t] = L.dchunks[ch0 + t];
+    const size_t base = (size_t)ch0 * U;   // the block's entries: one contiguous range
+    for (int i = t; i < nq * U; i += 256)
+        sp[i] = PairLds<T>{labels[L.dpix[base + i]], L.dw[base + i]};
+    __syncthreads();
+    const int k = t / C, c = t - (t / C) * C;
+    if (k >= nq) return;
+    const int4 cd = scd[k];
+    const int n = cd.z - cd.y;
+    const PairLds<T> *pk = sp + k * U;
+    T acc0 = T(0), acc1 = T(0), acc2 = T(0), acc3 = T(0);
+    int j = 0;
+    for (; j + 4 <= n; j += 4) {
+        const PairLds<T> e0 = pk[j], e1 = pk[j + 1], e2 = pk[j + 2], e3 = pk[j + 3];
+        acc0 += e0.i == c ? e0.w : T(0);
+        acc1 += e1.i == c ? e1.w : T(0);
+        acc2 += e2.i == c ? e2.w : T(0);
+        acc3 += e3.i == c ? e3.w : T(0);
+    }
+    for (; j < n; ++j) acc0 += pk[j].i == c ? pk[j].w : T(0);
+    const T acc = (acc0 + acc1) + (acc2 + acc3);
+    if (acc != T(0)) atomic_add(&L.V0[(size_t)cd.x * L.ld + c], acc);
+}
+
+
+template <int G> struct Pow3 { static constexpr int v = 3 * Pow3<G - 1>::v; };
+template <> struct Pow3<0> { static constexpr int v = 1; };
+
+template <typename T, int G>
+__device__ __forceinline__ void blur_group_vector(const LatSet<T> &ls, int grp,
+                                                  long long e) {
+    using V = typename Vec16<T>::type;
+    constexpr int vw = Vec16<T>::n;
+    constexpr int P = Pow3<G>::v;
+    int m = 0;
+    while (m + 1 < ls.nk && e >= ls.off[m + 1] / vw) ++m;
+    const LatView<T> &L = ls.l[m];
+    const unsigned Gv = unsigned(L.ld / vw);
+    const unsigned r = unsigned(e - ls.off[m] / vw);
+    V zero;
+    for (int i = 0; i < vw; ++i) reinterpret_cast<T *>(&zero)[i] = T(0);
+    if (grp >= L.ngrp) {
+        if (grp == 1) reinterpret_cast<V *>(L.V0)[r] = zero;
+        return;
+    }
+    const int v = int(r / Gv);
+    const int g = int(r - unsigned(v) * Gv);
+    const V *src = reinterpret_cast<const V *>((grp == 0) ? L.V0 : ((grp & 1) ? L.V1 : L.V2));
+    V *dst = reinterpret_cast<V *>((grp & 1) ? L.V2 : L.V1);
+    const int32_t *ids = L.gt + ((size_t)grp * L.M + v) * P;
+    int id[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) id[p] = ids[p];
+    T acc[vw];
+#pragma unroll
+    for (int i = 0; i < vw; ++i) acc[i] = T(0);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        // coefficient: 1/2 per staying step, 1/4 per move (digits of p)
+        T c = T(1);
+        int code = p;
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            c *= (code % 3 == 0) ? T(0.5) : T(0.25);
+            code /= 3;
+        }
+        const V x = src[(size_t)(id[p] >= 0 ? id[p] : 0) * Gv + g];
+        if (id[p] < 0) c = T(0);
+#pragma unroll
+        for (int i = 0; i < vw; ++i) acc[i] += c * reinterpret_cast<const T *>(&x)[i];
+    }
+    if (grp == L.ngrp - 1) {
+        const int missing = L.ngrp * G - (L.d + 1);
+        const T sc = T(1 << missing);
+#pragma unroll
+        for (int i = 0; i < vw; ++i) acc[i] *= sc;
+    }
+    V o;
+#pragma unroll
+    for (int i = 0; i < vw; ++i) reinterpret_cast<T *>(&o)[i] = acc[i];
+    dst[r] = o;
+    if (grp == 1) reinterpret_cast<V *>(L.V0)[r] = zero;
+}
+
 // ------------------------------------------- one-hot splat, pixel-major
 
 // Every lane of the wave holds one term: v to be added at row `id` (< 0: no

@@ -199,17 +199,14 @@ template <> struct LmoTile<double> { static constexpr int kPix = 128; };
 // SPLAT: the kernel also splats the one-hot s into the lattices (step 2),
 // pixel-major: 1 for any lattice set, 2 for a 5-D + 2-D pair (corners loaded
 // at the start, so that their latency overlaps the tiles').
-template <typename T, int LMAX, int SPLAT>
-__global__ void __launch_bounds__(LmoTile<T>::kPix)
-k_fw_lmo_rows(FWArgs<T> A, LatSet<T> ls) {
-    constexpr int TP = LmoTile<T>::kPix;
-    __shared__ __align__(16) T lds[TP * (LMAX | 1)];
-    __shared__ double red[kP1 * (TP / 64)];
+// One tile of TP pixels (a block of TP threads); lds holds TP (LMAX | 1)
+// values, red kP1 TP / 64 doubles, stot kPT doubles.
+template <typename T, int LMAX, int SPLAT, int TP>
+__device__ __forceinline__ void fw_lmo_tile(const FWArgs<T> &A, const LatSet<T> &ls,
+                                            int tile, T *lds, double *red, double *stot) {
     const int L = A.L;
-    const int tile = xcd_block(blockIdx.x, gridDim.x);
     int lo, hi;
     const int img = tile_range(A.seg, A.nimg, TP, tile, lo, hi);
-    __shared__ double stot[kPT];
     // the previous step's sums, loaded now so that they arrive with the tiles
     const double mine = A.first ? 0.0 : fw_load_sum(A.acc, A.it - 1, A.nimg, img);
     double acc[kP1];
@@ -286,21 +283,29 @@ k_fw_lmo_rows(FWArgs<T> A, LatSet<T> ls) {
     }
     const double tot = block_sum_waves<kP1, TP>(acc, red);
     if (img >= 0 && threadIdx.x < kP1)
-        unsafeAtomicAdd(&A.acc[acc_off(A.it & 1, blockIdx.x & (kSets - 1), A.nimg, img) +
+        unsafeAtomicAdd(&A.acc[acc_off(A.it & 1, tile & (kSets - 1), A.nimg, img) +
                                threadIdx.x], tot);
+}
+
+template <typename T, int LMAX, int SPLAT>
+__global__ void __launch_bounds__(LmoTile<T>::kPix)
+k_fw_lmo_rows(FWArgs<T> A, LatSet<T> ls) {
+    constexpr int TP = LmoTile<T>::kPix;
+    __shared__ __align__(16) T lds[TP * (LMAX | 1)];
+    __shared__ double red[kP1 * (TP / 64)];
+    __shared__ double stot[kPT];
+    fw_lmo_tile<T, LMAX, SPLAT, TP>(A, ls, xcd_block(blockIdx.x, gridDim.x), lds, red, stot);
 }
 
 // Step 4, one thread per pixel (see the file comment). POTTS: mu = 1 - I,
 // so (Q mu^T)_i = sum_j Q_j - Q_i.
-template <typename T, int LMAX, bool POTTS>
-__global__ void __launch_bounds__(RowTile<T>::kPix, 3)
-k_fw_slice_rows(FWSliceArgs<T> A, LatSet<T> ls) {
-    constexpr int TP = RowTile<T>::kPix;
-    __shared__ __align__(16) T lds[TP * (LMAX | 1)];
-    __shared__ int32_t sid[TP * kCorners52];
-    __shared__ T swc[TP * kCorners52];
-    __shared__ T smu[POTTS ? 1 : LMAX * LMAX];
-    __shared__ double red[kP2 * (TP / 64)];
+// One tile of TP pixels (a block of TP threads); lds holds TP (LMAX | 1)
+// values, sid and swc TP kCorners52 each, smu LMAX^2 (general mu), red
+// kP2 TP / 64 doubles.
+template <typename T, int LMAX, bool POTTS, int TP>
+__device__ __forceinline__ void fw_slice_tile(const FWSliceArgs<T> &A, const LatSet<T> &ls,
+                                              int tile, T *lds, int32_t *sid, T *swc,
+                                              T *smu, double *red) {
     const int L = A.L;
     if (!POTTS) {
         for (int i = threadIdx.x; i < L * L; i += TP)
@@ -308,7 +313,6 @@ k_fw_slice_rows(FWSliceArgs<T> A, LatSet<T> ls) {
         __syncthreads();
     }
     double acc[kP2] = {0.0, 0.0};
-    const int tile = xcd_block(blockIdx.x, gridDim.x);
     int lo, hi;
     const int img = tile_range(A.seg, A.nimg, TP, tile, lo, hi);
     {
@@ -404,11 +408,155 @@ k_fw_slice_rows(FWSliceArgs<T> A, LatSet<T> ls) {
     }
     const double tot = block_sum_waves<kP2, TP>(acc, red);
     if (img >= 0 && threadIdx.x < kP2)
-        unsafeAtomicAdd(&A.acc[acc_off(A.it & 1, blockIdx.x & (kSets - 1), A.nimg, img) +
+        unsafeAtomicAdd(&A.acc[acc_off(A.it & 1, tile & (kSets - 1), A.nimg, img) +
                                kP1 + threadIdx.x], tot);
-    if (blockIdx.x == 0)   // the other parity: read by this iteration's step 1 only
+    if (tile == 0)   // the other parity: read by this iteration's step 1 only
         for (int i = threadIdx.x; i < kSets * A.nimg * kPT; i += TP)
             A.acc[acc_off((A.it + 1) & 1, 0, A.nimg, 0) + i] = 0.0;
+}
+
+template <typename T, int LMAX, bool POTTS>
+__global__ void __launch_bounds__(RowTile<T>::kPix, 3)
+k_fw_slice_rows(FWSliceArgs<T> A, LatSet<T> ls) {
+    constexpr int TP = RowTile<T>::kPix;
+    __shared__ __align__(16) T lds[TP * (LMAX | 1)];
+    __shared__ int32_t sid[TP * kCorners52];
+    __shared__ T swc[TP * kCorners52];
+    __shared__ T smu[POTTS ? 1 : LMAX * LMAX];
+    __shared__ double red[kP2 * (TP / 64)];
+    fw_slice_tile<T, LMAX, POTTS, TP>(A, ls, xcd_block(blockIdx.x, gridDim.x), lds, sid, swc,
+                                      smu, red);
+}
+
+// ------------------------------------------- persistent Frank-Wolfe launch
+
+// All iterations of a Frank-Wolfe solve in one cooperative launch (every
+// block resident at once): the per-stage kernels' bodies run over virtual
+// blocks (tiles of kPersistPix pixels, splat chunks, blur vectors) with a
+// grid barrier between the stages: LMO | one-hot splat | blur group 1 |
+// ... | blur group n (with the vertex checkpoint) | slice |. The step size
+// still rides on the stage boundary between the slice and the next LMO. The
+// barrier's wait is bounded: a block that waits longer than kBarrierSpins
+// polls sets the timeout flag and goes on (the host then reports the solve
+// as failed), so a broken co-residency cannot hang the device.
+constexpr int kPersistPix = 256;
+constexpr unsigned kBarrierSpins = 1u << 22;
+
+__device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned &gen, int *timeout) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&bar[0], 1u) == gridDim.x - 1) {
+            atomicExch(&bar[0], 0u);
+            __threadfence();
+            atomicAdd(&bar[1], 1u);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                if (++spins > kBarrierSpins) {
+                    atomicOr(timeout, 1);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        ++gen;
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+template <typename T>
+struct FWPersist {
+    FWArgs<T> a;          // the LMO's arguments (it, first, s, sprev, saves set per iteration)
+    FWSliceArgs<T> b;     // the slice's
+    int iters, g1, g2;    // iterations; LMO and slice tiles of kPersistPix pixels
+    int q, U;             // one-hot splat: chunks per block, entries per chunk
+    long long splat_blocks, blur_vecs;
+    int ngrp;             // blur groups (launches of the per-stage path)
+    int32_t *s0, *s1;     // the label buffers, alternating by iteration
+    T *ysv, *psv;         // checkpoints (or null): y_t and P_t per iteration,
+    int32_t *ssv;         // s_t,
+    T *vsv;               // and the blurred vertex values after each iteration's blur
+    size_t NL, vblock;
+    unsigned *bar;        // count, generation (both zero at launch)
+    int *timeout;
+};
+
+template <typename T, int LMAX, bool POTTS>
+__global__ void __launch_bounds__(kPersistPix, 2)
+k_fw_persistent(FWPersist<T> P, LatSet<T> ls) {
+    constexpr int TP = kPersistPix;
+    __shared__ __align__(16) T lds[TP * (LMAX | 1)];
+    __shared__ double red[kP1 * (TP / 64)];
+    __shared__ double stot[kPT];
+    __shared__ int32_t sid[TP * kCorners52];
+    __shared__ T swc[TP * kCorners52];
+    __shared__ T smu[POTTS ? 1 : LMAX * LMAX];
+    __shared__ PairLds<T> sp[kSplatStage];
+    __shared__ int4 scd[256];
+    unsigned gen = 0;
+    const int L = P.a.L;
+    using V = typename Vec16<T>::type;
+    constexpr int vw = Vec16<T>::n;
+    for (int it = 0; it < P.iters; ++it) {
+        int32_t *scur = (it & 1) ? P.s1 : P.s0;
+        FWArgs<T> a = P.a;
+        a.it = it;
+        a.first = it == 0 ? 1 : 0;
+        a.s = scur;
+        a.sprev = (it & 1) ? P.s0 : P.s1;
+        a.ysave = P.ysv ? P.ysv + (size_t)it * P.NL : nullptr;
+        a.Psave = P.psv ? P.psv + (size_t)it * P.NL : nullptr;
+        a.ssave = P.ssv ? P.ssv + (size_t)it * a.N : nullptr;
+        for (int vb = blockIdx.x; vb < P.g1; vb += gridDim.x) {
+            fw_lmo_tile<T, LMAX, 0, TP>(a, ls, vb, lds, red, stot);
+            __syncthreads();
+        }
+        grid_barrier(P.bar, gen, P.timeout);
+        for (long long vb = blockIdx.x; vb < P.splat_blocks; vb += gridDim.x) {
+            splat_labels_block<T>(L, P.q, P.U, scur, ls, vb * 256, sp, scd);
+            __syncthreads();
+        }
+        grid_barrier(P.bar, gen, P.timeout);
+        for (int grp = 0; grp < P.ngrp; ++grp) {
+            for (long long e = (long long)blockIdx.x * TP + threadIdx.x; e < P.blur_vecs;
+                 e += (long long)gridDim.x * TP)
+                blur_group_vector<T, 2>(ls, grp, e);
+            grid_barrier(P.bar, gen, P.timeout);
+        }
+        if (P.ngrp == 1) {   // no second group cleared the splat target
+            for (long long e = (long long)blockIdx.x * TP + threadIdx.x; e < P.blur_vecs;
+                 e += (long long)gridDim.x * TP) {
+                int m = 0;
+                while (m + 1 < ls.nk && e >= ls.off[m + 1] / vw) ++m;
+                V zero;
+                for (int i = 0; i < vw; ++i) reinterpret_cast<T *>(&zero)[i] = T(0);
+                reinterpret_cast<V *>(ls.l[m].V0)[e - ls.off[m] / vw] = zero;
+            }
+        }
+        if (P.vsv) {   // blurred vertex values for the reverse sweep (slot it + 1)
+            T *dst = P.vsv + (size_t)(it + 1) * P.vblock;
+            for (long long e = (long long)blockIdx.x * TP + threadIdx.x; e < P.blur_vecs * vw;
+                 e += (long long)gridDim.x * TP) {
+                int m = 0;
+                while (m + 1 < ls.nk && e >= ls.off[m + 1]) ++m;
+                dst[e] = ls.l[m].Vf[e - ls.off[m]];
+            }
+        }
+        FWSliceArgs<T> b = P.b;
+        b.it = it;
+        b.s = scur;
+        for (int vb = blockIdx.x; vb < P.g2; vb += gridDim.x) {
+            fw_slice_tile<T, LMAX, POTTS, TP>(b, ls, vb, lds, sid, swc, smu, red);
+            __syncthreads();
+        }
+        grid_barrier(P.bar, gen, P.timeout);
+    }
+}
+
+__global__ void k_fill_u32(unsigned *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
 }
 
 // ------------------------------------------------- flat kernels (L > 32)
@@ -842,6 +990,72 @@ bool is_potts(dcrf_ctx *ctx, const T *mu, int L) {
     return true;
 }
 
+template <typename T, int LMAX, bool POTTS>
+void fw_persistent_go(dcrf_ctx *ctx, FWPersist<T> &P, LatSet<T> &ls) {
+    const auto kern = k_fw_persistent<T, LMAX, POTTS>;
+    int per_cu = 0, cus = 0;
+    DCRF_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kPersistPix, 0));
+    DCRF_TRY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                       ctx->device));
+    if (per_cu < 1) fail(DCRF_EUNSUPPORTED, "the persistent solve does not fit a compute unit");
+    long long need = std::max<long long>(P.g1, P.g2);
+    need = std::max(need, P.splat_blocks);
+    need = std::max(need, (P.blur_vecs + kPersistPix - 1) / kPersistPix);
+    const int grid = int(std::max(1ll, std::min<long long>((long long)per_cu * cus, need)));
+    void *args[] = {&P, &ls};
+    DCRF_TRY_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(grid),
+                                            dim3(kPersistPix), args, 0, ctx->stream));
+}
+
+// All iterations of the solve in one cooperative launch (k_fw_persistent),
+// then a check that no grid barrier timed out.
+template <typename T>
+void fw_persistent_launch(dcrf_ctx *ctx, LatSet<T> ls, const Work<T> &w, T *y, const T *mu,
+                          int L, int iters, const FWCheckpoint *save, size_t vblock,
+                          bool potts) {
+    const hipStream_t st = ctx->stream;
+    const int N = ctx->N;
+    blur_group_tables(ctx, 2);
+    for (int m = 0; m < ctx->nk; ++m) ls.l[m].gt = ctx->lat[m].gtab[0].as<int32_t>();
+    ctx->fw_bar.ensure(256, st);
+    unsigned *bar = ctx->fw_bar.as<unsigned>();
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, bar, 3);
+    FWPersist<T> P{};
+    P.a = FWArgs<T>{N, L, y, w.Py, w.Ps, w.c, w.s, w.sprev, w.acc, w.trace,
+                    save ? save->stats : nullptr, 0, 1, ctx->seg.as<int>(), ctx->nimg,
+                    nullptr, nullptr, nullptr};
+    P.b = FWSliceArgs<T>{N, L, y, w.s, w.Ps, mu, w.mabs, ctx->r.as<T>(), nullptr,
+                         T(ctx->wsum), w.acc, 0, ctx->seg.as<int>(), ctx->nimg};
+    P.iters = iters;
+    P.g1 = P.g2 = seg_tiles(ctx, kPersistPix);
+    P.q = dense_splat_q(ctx, L);
+    P.U = ctx->dense_chunk;
+    P.splat_blocks = ls.coff[ls.nk] / 256;
+    P.blur_vecs = ls.off[ls.nk] / Vec16<T>::n;
+    P.ngrp = 0;
+    for (int m = 0; m < ls.nk; ++m) P.ngrp = std::max(P.ngrp, ls.l[m].ngrp);
+    P.s0 = w.s;
+    P.s1 = w.sprev;
+    P.ysv = save ? static_cast<T *>(save->y) : nullptr;
+    P.psv = save ? static_cast<T *>(save->P) : nullptr;
+    P.ssv = save ? save->s : nullptr;
+    P.vsv = save && vblock ? static_cast<T *>(save->V) : nullptr;
+    P.NL = (size_t)N * L;
+    P.vblock = vblock;
+    P.bar = bar;
+    P.timeout = reinterpret_cast<int *>(bar + 2);
+    DCRF_CHECK_LAUNCH();
+    if (potts)
+        DCRF_DISPATCH_ROWS(L, (fw_persistent_go<T, LMAX, true>(ctx, P, ls)));
+    else
+        DCRF_DISPATCH_ROWS(L, (fw_persistent_go<T, LMAX, false>(ctx, P, ls)));
+    int timed_out = 0;
+    DCRF_TRY_HIP(hipMemcpyAsync(&timed_out, bar + 2, 4, hipMemcpyDeviceToHost, st));
+    DCRF_TRY_HIP(hipStreamSynchronize(st));
+    if (timed_out)
+        fail(DCRF_EHIP, "a grid barrier of the persistent Frank-Wolfe launch timed out");
+}
+
 template <typename T>
 void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
                    int iters, dcrf_iter_trace *trace, int cmode, bool have_Py,
@@ -900,7 +1114,15 @@ void frank_wolfe_t(dcrf_ctx *ctx, const T *phi, const T *mu, int L, T *y,
     const LatSet<T> ls = exact ? LatSet<T>{} : make_lat_set<T>(ctx, L);
     // the one-hot splat inside the LMO kernel (the row kernels only)
     const int fuse = (!exact && rows && ctx->fw_splat) ? (ls.shape52 ? 2 : 1) : 0;
-    for (int it = 0; it < iters; ++it) {
+    // every iteration in one cooperative launch: the row kernels' lattice
+    // path with the staged one-hot splat and two blur directions per group
+    const bool persist = ctx->fw_persistent && !exact && rows && !fuse && iters > 0 &&
+                         ctx->blur_group == 2 && !ctx->tile_mode && ctx->splat_lds;
+    if (persist) {
+        fw_persistent_launch<T>(ctx, ls, w, y, mu, L, iters, save, vblock, potts);
+        if (iters & 1) std::swap(w.s, w.sprev);   // the last s where the loop leaves it
+    }
+    for (int it = 0; it < (persist ? 0 : iters); ++it) {
         // checkpoints are written by the row kernel itself; the flat kernel
         // (more than 32 labels) leaves them to copies below
         T *ysv = save && rows ? static_cast<T *>(save->y) + (size_t)it * NL : nullptr;
@@ -1124,6 +1346,7 @@ void fw_noalloc_t(dcrf_ctx *ctx, const T *phi, const void *mu, int L, T *y, int 
         DevBuf saved[kItems];
         int potts_L, potts_dtype;
         bool prof;
+        int persistent;
         Arena *arena;
         Arena refuse;
         ~Restore() {
@@ -1131,9 +1354,11 @@ void fw_noalloc_t(dcrf_ctx *ctx, const T *phi, const void *mu, int L, T *y, int 
             ctx->potts_L = potts_L;
             ctx->potts_dtype = potts_dtype;
             ctx->prof.on = prof;
+            ctx->fw_persistent = persistent;
             tl_arena = arena;
         }
-    } rs{ctx, items, n, {}, ctx->potts_L, ctx->potts_dtype, ctx->prof.on, tl_arena, {}};
+    } rs{ctx, items, n, {}, ctx->potts_L, ctx->potts_dtype, ctx->prof.on,
+         ctx->fw_persistent, tl_arena, {}};
     size_t off = 0;
     for (int i = 0; i < n; ++i) {
         rs.saved[i] = *items[i].buf;
@@ -1146,6 +1371,9 @@ void fw_noalloc_t(dcrf_ctx *ctx, const T *phi, const void *mu, int L, T *y, int 
     }
     ctx->potts_L = 0;       // the Potts copy is rebuilt in the scratch when asked for
     ctx->prof.on = false;   // profiling would create events
+    // the per-stage launches: the persistent solve waits for the stream (its
+    // barrier check) and keeps a buffer of its own
+    ctx->fw_persistent = 0;
     rs.refuse.refuse = "the allocation-free solve would need device memory beyond its "
                        "scratch (e.g. blur tables for a launch shape not yet used)";
     tl_arena = &rs.refuse;

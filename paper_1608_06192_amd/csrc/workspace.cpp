@@ -150,6 +150,7 @@ size_t workspace_bound(int B, const int *H, const int *W, int L,
     s.add(4);                                          // input error flag
     s.add(size_t(L) * L * e);                          // Potts copy of mu
     s.add(4096);                                       // per-call flags and tables
+    s.add(256);                                        // persistent solve's grid barrier
     // separable mode: taps (at most the larger image side) and three N x L arrays
     size_t side = 1;
     for (int j = 0; j < B; ++j) side = std::max<size_t>(side, std::max(H[j], W[j]));

@@ -48,7 +48,7 @@ class dcrf_tune(ctypes.Structure):
                 ("blur_vectors_per_thread", ctypes.c_int),
                 ("blur_block", ctypes.c_int), ("blur_group", ctypes.c_int),
                 ("tiles", ctypes.c_int), ("fw_splat", ctypes.c_int),
-                ("ms", ctypes.c_double)]
+                ("fw_persistent", ctypes.c_int), ("ms", ctypes.c_double)]
 
 
 # name -> (restype, argtypes); mirrors include/dcrf.h
@@ -266,9 +266,9 @@ class Context:
 
     def set_tune(self, splat_chunk=64, blur_vectors_per_thread=1,
                  blur_block=256, blur_group=2, tiles=0, dense_chunk=32,
-                 splat_stage=1, fw_splat=0, **_):
+                 splat_stage=1, fw_splat=0, fw_persistent=0, **_):
         t = dcrf_tune(splat_chunk, dense_chunk, splat_stage, blur_vectors_per_thread,
-                      blur_block, blur_group, tiles, fw_splat, 0.0)
+                      blur_block, blur_group, tiles, fw_splat, fw_persistent, 0.0)
         self._stream()
         self._check(_lib.dcrf_set_tune(self._h, ctypes.byref(t)))
 
@@ -280,7 +280,8 @@ class Context:
                     splat_stage=t.splat_stage,
                     blur_vectors_per_thread=t.blur_vectors_per_thread,
                     blur_block=t.blur_block, blur_group=t.blur_group,
-                    tiles=t.tiles, fw_splat=t.fw_splat, ms=t.ms)
+                    tiles=t.tiles, fw_splat=t.fw_splat, fw_persistent=t.fw_persistent,
+                    ms=t.ms)
 
     def workspace_used(self):
         """(bytes in use, peak bytes) of the context's caller workspace"""

@@ -408,3 +408,102 @@ def test_batch_per_image_calls_match_packed():
         assert (gps[j] - gp[a:b]).abs().max().item() <= 1e-12 * gp[a:b].abs().max().item(), j
         assert np.allclose(gws[j], gw[j], rtol=1e-12, atol=0), j
     assert np.allclose(gtot, np.sum(gws, axis=0), rtol=1e-14, atol=0)
+
+
+def _persistent_vs_stages(ctx, run, tune=None):
+    """run(ctx) with one launch per stage and with the persistent launch,
+    the other launch shapes as in `tune` (default: the defaults)"""
+    t = dict(tune or {})
+    ctx.set_tune(**dict(t, fw_persistent=0))
+    a = run(ctx)
+    ctx.set_tune(**dict(t, fw_persistent=1))
+    b = run(ctx)
+    ctx.set_tune(**dict(t, fw_persistent=0))
+    return a, b
+
+
+def test_persistent_fw_fp64_matches_per_stage_small_batch():
+    # the same solve (3 images of uneven sizes, L = 5, 20 iterations, FP64)
+    # in one cooperative launch with grid barriers and with one launch per
+    # stage: the same arithmetic up to the order of the splat's atomics, so
+    # the marginals and every per-image trace entry agree to 1e-10
+    ims = small_batch()
+    ctx = batch_ctx(ims, torch.float64)
+    L = ims[0].L
+    phi = ctx.pack([T(im.unary, torch.float64) for im in ims], L)
+    y0 = ctx.pack([T(O.softmax_neg(im.unary), torch.float64) for im in ims], L)
+
+    def run(c):
+        y = y0.clone()
+        tr = c.qp_frank_wolfe(phi, None, y, 20)
+        return y.cpu().numpy(), np.asarray(tr, dtype=np.float64)
+    (ya, ta), (yb, tb) = _persistent_vs_stages(ctx, run)
+    print(f"[persistent small] max |dy| {np.abs(ya - yb).max():.3g}", flush=True)
+    assert np.abs(ya - yb).max() <= 1e-10
+    assert np.abs(ta - tb).max() <= 1e-10 * np.abs(ta).max()
+
+
+def test_persistent_fw_fp64_single_image_500x375():
+    # one image at the benchmarked size, 30 iterations in FP64, both paths
+    from paper_1608_06192_amd import dcrf
+    im = synth.make("voronoi_500x375_L21")
+    ctx = dcrf.Context(0)
+    ctx.set_image(im.H, im.W, torch.from_numpy(im.rgb).to(dev()), KERNELS,
+                  dtype=torch.float64)
+    print("[case] persistent 500x375 fp64", flush=True)
+    phi = T(im.unary, torch.float64)
+    y0 = T(O.softmax_neg(im.unary), torch.float64)
+
+    def run(c):
+        y = y0.clone()
+        tr = c.qp_frank_wolfe(phi, None, y, 30)
+        return y.cpu().numpy(), np.asarray(tr, dtype=np.float64)
+    (ya, ta), (yb, tb) = _persistent_vs_stages(ctx, run)
+    print(f"[persistent 500x375] max |dy| {np.abs(ya - yb).max():.3g}", flush=True)
+    assert np.abs(ya - yb).max() <= 1e-9
+    assert np.abs(ta[:, 0] - tb[:, 0]).max() <= 1e-10 * np.abs(ta[:, 0]).max()
+
+
+def test_persistent_fw_fwd_bwd_fp64_batch16_matches_per_stage():
+    """The benchmarked 16-image batch (U{240..500}^2, L = 21, autotuned launch
+    shapes with two blur directions per group, the staged splat and no
+    tiles, 10 unrolled iterations with checkpoints, then the reverse sweep)
+    in FP64 with the forward in one persistent launch and with one launch per
+    stage. Where both take the same conditional gradients (FP64 on both
+    sides; a differing decision can only come from an exact near-tie, and
+    such an image is skipped, at most 2 of 16) y_T and dl/dphi agree within
+    1e-10 of their scale and dl/dw, a sum whose terms cancel to about 1e-4 of
+    their absolute sum, within 1e-8 relative (the bar of the oracle
+    comparison above)."""
+    from diffsaved import unpack_saved
+    ims = synth.make_batch()
+    iters = synth.WORKLOADS["voronoi_batch16_L21"]["iters"]
+    L = ims[0].L
+    f64 = torch.float64
+    ctx = batch_ctx(ims, f64)
+    # autotuned shapes, with those the persistent launch takes
+    tune = dict(ctx.autotune(L, reps=2), blur_group=2, tiles=0, splat_stage=1)
+    phi = ctx.pack([T(im.unary, f64) for im in ims], L)
+    rng = np.random.default_rng(3)
+    ybar = ctx.pack([T(rng.standard_normal((im.N, L)), f64) for im in ims], L)
+
+    def run(c):
+        y, saved = c.fw_forward(phi, None, iters)
+        gphi, gw = c.fw_backward(phi, None, iters, saved, ybar)
+        s_b, _ = unpack_saved(c, saved, c.N, L, iters, 8)
+        return [v.cpu().numpy() for v in c.unpack(y)], \
+            [v.cpu().numpy() for v in c.unpack(gphi)], np.asarray(gw), s_b.copy()
+    (ya, ga, wa, sa), (yb, gb, wb, sb) = _persistent_vs_stages(ctx, run, tune)
+    skipped, wrel = 0, 0.0
+    for j in range(len(ims)):
+        a, b = ctx.seg[j]
+        if not np.array_equal(sa[:, a:b], sb[:, a:b]):
+            skipped += 1
+            continue
+        assert np.abs(ya[j] - yb[j]).max() <= 1e-10, j
+        assert np.abs(ga[j] - gb[j]).max() <= 1e-10 * np.abs(ga[j]).max(), j
+        wrel = max(wrel, float(np.max(np.abs(wa[j] - wb[j]) / np.abs(wa[j]))))
+        assert np.allclose(wa[j], wb[j], rtol=1e-8, atol=0), j
+    print(f"[persistent batch16] images skipped for a differing decision: {skipped}; "
+          f"dl/dw max rel diff {wrel:.3g}", flush=True)
+    assert skipped <= 2
