@@ -539,6 +539,10 @@ k_lp_node_level(int N, int l, int D1, int M, int k, const int *__restrict__ pos_
     constexpr int kLpNodeThreads = CAP / 4;
     __shared__ unsigned long long skey[CAP];
     __shared__ int sidx[CAP];
+    // weight and side of the block's entry i (by entry, not by sorted
+    // position): the run sums read them from LDS
+    __shared__ T sw[CAP];
+    __shared__ unsigned char sside[CAP];
     // keys: valid (node, vertex) pairs < 2^43; an entry that is no term
     // (a node with an empty half, a missing vertex) kNone; the padding up to
     // a power of two kPad, so that the block's ne entries fill the sorted
@@ -558,8 +562,11 @@ k_lp_node_level(int N, int l, int D1, int M, int k, const int *__restrict__ pos_
             long long node;
             int side;
             const int v = pos_vid[e0 + i];
+            const T w = pos_w[e0 + i];
             if (dnc_node(p, l, N, node, side) && v >= 0)
                 key = ((unsigned long long)(node - n0) << 32) | (unsigned)v;
+            sw[i] = w;
+            sside[i] = (unsigned char)side;
         }
         skey[i] = key;
         sidx[i] = i;
@@ -596,14 +603,10 @@ k_lp_node_level(int N, int l, int D1, int M, int k, const int *__restrict__ pos_
         T s0 = T(0), s1 = T(0);
         for (int rr = r; rr < nvalid && skey[rr] == key; ++rr) {
             const int ii = sidx[rr];
-            long long node;
-            int side;
-            dnc_node(lo + ii / D1, l, N, node, side);
-            const T w = pos_w[e0 + ii];
-            if (side)
-                s1 += w;
+            if (sside[ii])
+                s1 += sw[ii];
             else
-                s0 += w;
+                s0 += sw[ii];
         }
         V0[e * 2] = s0;
         V0[e * 2 + 1] = s1;
