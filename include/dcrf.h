@@ -17,8 +17,9 @@
  *    element (a, c) at [a*C + c]. mu is row-major L x L. rgb is float32
  *    N x 3 with values in [0, 255].
  *  - Memory: every array argument marked (dev) is DEVICE memory on the
- *    context's device, owned by the caller, contiguous, in the context's
- *    floating type (float for DCRF_F32, double for DCRF_F64) unless stated.
+ *    context's device, owned by the caller, contiguous, 16-byte aligned (as
+ *    device allocations are), in the context's floating type (float for
+ *    DCRF_F32, double for DCRF_F64) unless stated.
  *    Arguments marked (host) are host memory. The context's own device
  *    memory (lattice tables, solver state) is either allocated by the
  *    library as calls need it, or carved from a workspace the caller hands
