@@ -74,18 +74,29 @@ k_splat_gather(int C, int q, const T *__restrict__ Y, LatSet<T> ls) {
 // consecutive chunks (lane = chunk * C + channel, q U <= kSplatStage). Their (pixel, weight)
 // pairs are copied to LDS with contiguous loads first, so that the only
 // per-lane global loads left are those of the input values; the C lanes of a
-// chunk would otherwise each load the same pair.
+// chunk would otherwise each load the same pair. With two lattices
+// (pq0 + pq1 > 0) the blocks follow xcd_pair_block, 8 pq_m blocks for
+// lattice m (the chunks are in first-pixel order), so that each XCD gathers
+// one stretch of input rows for both lattices; blocks past a lattice's
+// chunks do nothing.
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_splat_gather_lds(int C, int q, int U, const T *__restrict__ Y, LatSet<T> ls) {
+k_splat_gather_lds(int C, int q, int U, const T *__restrict__ Y, LatSet<T> ls, int pq0,
+                   int pq1) {
     __shared__ PairLds<T> sp[kSplatStage];
     __shared__ int4 scd[256];
-    const long long b0 = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x;
-    int m = 0;   // uniform: each lattice's blocks start at a multiple of 256 lanes
-    while (m + 1 < ls.nk && b0 >= ls.coff[m + 1]) ++m;
+    int m = 0, lb = 0;
+    if (pq0 + pq1 > 0) {
+        m = xcd_pair_block(blockIdx.x, pq0, pq1, lb);
+    } else {
+        const long long b0 = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x;
+        while (m + 1 < ls.nk && b0 >= ls.coff[m + 1]) ++m;   // uniform
+        lb = int((b0 - ls.coff[m]) / 256);
+    }
     const LatView<T> &L = ls.l[m];
-    const int ch0 = int((b0 - ls.coff[m]) / 256) * q;
+    const int ch0 = lb * q;
     const int nq = min(q, L.ndchunks - ch0);
+    if (nq <= 0) return;   // uniform, before any barrier
     const int t = threadIdx.x;
     if (t < nq) scd[t] = L.dchunks[ch0 + t];
     const size_t base = (size_t)ch0 * U;   // the block's entries: one contiguous range
@@ -789,9 +800,15 @@ void splat_set(dcrf_ctx *ctx, const LatSet<T> &ls, const T *in, int C) {
     if (C > 256) fail(DCRF_EUNSUPPORTED, "the dense splat takes at most 256 channels");
     const dim3 grid(ceil_div(total, 256));
     const int q = dense_splat_q(ctx, C);
-    if (ctx->splat_lds)
+    if (ctx->splat_lds && ls.nk == 2) {
+        int pq[2];
+        for (int m = 0; m < 2; ++m)
+            pq[m] = (int)ceil_div(ceil_div((long long)ls.l[m].ndchunks, (long long)q), 8ll);
+        DCRF_PLAUNCH(ps, (k_splat_gather_lds<T>), dim3(8 * (pq[0] + pq[1])), dim3(256), 0,
+                     s, C, q, ctx->dense_chunk, in, ls, pq[0], pq[1]);
+    } else if (ctx->splat_lds)
         DCRF_PLAUNCH(ps, (k_splat_gather_lds<T>), grid, dim3(256), 0, s, C, q,
-                           ctx->dense_chunk, in, ls);
+                           ctx->dense_chunk, in, ls, 0, 0);
     else
         DCRF_PLAUNCH(ps, (k_splat_gather<T>), grid, dim3(256), 0, s, C, q, in, ls);
     DCRF_CHECK_LAUNCH();

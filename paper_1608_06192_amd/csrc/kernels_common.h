@@ -165,6 +165,23 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
 }
 
+// Block b of a launch over two lattices of 8 q0 and 8 q1 blocks, whose
+// blocks walk each lattice's work in pixel order: the hardware sends block b
+// to XCD b mod 8, and XCD x takes blocks [x q_m, (x + 1) q_m) of both
+// lattices, interleaved in proportion, so that it covers the same stretch of
+// pixels in both lattices at the same time and the rows they gather meet in
+// its L2. Returns the lattice and sets lb, the block within it.
+__device__ __forceinline__ int xcd_pair_block(int b, int q0, int q1, int &lb) {
+    const int x = b & 7, i = b >> 3, T = q0 + q1;
+    const int c = int((long long)(i + 1) * q0 / T);   // lattice-0 blocks among the first i + 1
+    if (c > int((long long)i * q0 / T)) {
+        lb = x * q0 + c - 1;
+        return 0;
+    }
+    lb = x * q1 + (i - c);
+    return 1;
+}
+
 // Tile `tile` of the per-image tilings of TP pixels, images taken in order
 // (see dcrf_ctx::seg): returns the image and sets [lo, hi), its pixel rows.
 // Images start at multiples of 64 pixels, so a tile's rows start 16-byte
